@@ -1,0 +1,157 @@
+"""Pins of the oracle's direct product and of its compressed (Alg. 1/3) and
+transposed (Alg. 2/4) methods, against closed forms and identities."""
+
+import numpy as np
+import pytest
+import scipy.fft
+
+from oracle import compressed, direct, matrix, params, transposed
+
+ALL_FAMS = [(matrix.CHEBYSHEV_T, {}), (matrix.LEGENDRE, {}),
+            (matrix.JACOBI, dict(alpha=-0.5, beta=-0.5)), (matrix.JACOBI, dict(alpha=2.0, beta=3.0)),
+            (matrix.LAGUERRE_FN, {}), (matrix.HERMITE_FN, {})]
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+# ------------------------------------------------------------------ direct product
+@pytest.mark.parametrize("N", [64, 4096])
+def test_chebyshev_direct_is_a_dct(N):
+    # sec. 2.1: at Chebyshev nodes A x is a fast DCT.  With theta_j = pi(j+1/2)/N,
+    # sum_k x_k cos(k theta_j) = (DCT-III(x)_j + x_0) / 2 (SciPy's unnormalised DCT-III)
+    x = np.random.default_rng(3).standard_normal(N)
+    y = direct.matvec(matrix.MatrixFamily(matrix.CHEBYSHEV_T, N), x[None, :])[0]
+    ref = (scipy.fft.dct(x, type=3) + x[0]) / 2.0
+    np.testing.assert_allclose(y, ref, atol=1e-12 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("fam_id,kw", ALL_FAMS)
+def test_direct_vs_naive_loop(fam_id, kw):
+    N = 24
+    fam = matrix.MatrixFamily(fam_id, N, **kw)
+    X = np.random.default_rng(5).standard_normal((2, N))
+    A = fam.block(np.arange(N), 0, N)
+    naive = np.array([[sum(A[j, m] * X[r, m] for m in range(N)) for j in range(N)]
+                      for r in range(2)])
+    np.testing.assert_allclose(direct.matvec(fam, X, panel=7), naive, rtol=1e-13, atol=1e-15)
+    rows = np.array([3, 0, 23])
+    np.testing.assert_allclose(direct.matvec(fam, X, rows=rows), naive[:, rows], rtol=1e-13,
+                               atol=1e-15)
+    # the transposed product is the same matrix read by columns
+    naiveT = np.array([[sum(A[j, m] * X[r, j] for j in range(N)) for m in range(N)]
+                       for r in range(2)])
+    np.testing.assert_allclose(direct.matvec_transposed(fam, X, panel=5), naiveT, rtol=1e-13,
+                               atol=1e-15)
+
+
+# ------------------------------------------------------------------ DFT convention
+@pytest.mark.parametrize("N,theta", [(16, 0.5), (128, 1.3), (1000, 2.9)])
+def test_row_dft_matches_geometric_series(N, theta):
+    # Appendix A: (1/sqrt N) sum_j e^{i j theta} w^{jk} = (1/sqrt N)(e^{iN theta}-1)/(e^{i theta} w^k - 1),
+    # w = exp(-2 pi i/N); and the cos row is the mean of the +theta and -theta series.
+    # This fixes the sign and normalisation of F in eq. (1).
+    k = np.arange(N)
+    w = np.exp(-2j * np.pi / N)
+
+    def yexp(t):
+        return (np.exp(1j * N * t) - 1) / (np.exp(1j * t) * w ** k - 1) / np.sqrt(N)
+
+    row = np.exp(1j * theta * np.arange(N))
+    np.testing.assert_allclose(np.fft.fft(row, norm="ortho"), yexp(theta), atol=1e-12)
+    ycos = (yexp(theta) + yexp(-theta)) / 2
+    # the oracle's compressed rows with zeta = 0 (rectangular window, W = I)
+    plan = compressed.Plan.__new__(compressed.Plan)
+    plan.fam, plan.zeta = matrix.MatrixFamily(matrix.CHEBYSHEV_T, 4), 0.0
+    blk = params.Block(N, 0, 0, N)
+    plan.fam.block = lambda rows, m0, m1: np.cos(theta * np.arange(m0, m1))[None, :]
+    np.testing.assert_allclose(compressed._spectrum(plan, blk, np.arange(1))[0], ycos,
+                               atol=1e-12)
+
+
+# ------------------------------------------------------------------ exact identity, eq. (comp1)
+@pytest.mark.parametrize("fam_id,kw", ALL_FAMS)
+@pytest.mark.parametrize("N", [8, 16, 64, 256])
+def test_unthresholded_method_is_exact(fam_id, kw, N):
+    # with every entry of Add kept, Add F* W^{-1} v = A_e v: the extension, window,
+    # DFT convention and block bookkeeping (sec. 3) must reproduce A x exactly
+    fam = matrix.MatrixFamily(fam_id, N, **kw)
+    plan = compressed.Plan(fam, 1e-10, 1e-2, min_block=4)
+    C = compressed.Compressed(plan, threshold=False)
+    X = np.random.default_rng(7).standard_normal((3, N))
+    Yd = direct.matvec(fam, X)
+    assert rel(C.execute(X), Yd) <= 1e-13
+    # and the transposed product of Alg. 2/4
+    Fv = np.random.default_rng(8).standard_normal((2, N))
+    assert rel(transposed.execute(C, Fv), direct.matvec_transposed(fam, Fv)) <= 1e-13
+
+
+def test_planted_sign_error_is_caught(monkeypatch):
+    # a wrong DFT sign in the execute step must break the identity above
+    fam = matrix.MatrixFamily(matrix.LEGENDRE, 64)
+    C = compressed.Compressed(compressed.Plan(fam, 1e-10, 1e-2, min_block=4), threshold=False)
+    X = np.random.default_rng(7).standard_normal((1, 64))
+    monkeypatch.setattr(compressed.np.fft, "ifft", np.fft.fft)
+    with pytest.raises(AssertionError):
+        assert rel(C.execute(X), direct.matvec(fam, X)) <= 1e-13
+
+
+def test_planted_block_offset_error_is_caught(monkeypatch):
+    # a retained range shifted by one column (reading A-5's off-by-one the other way)
+    fam = matrix.MatrixFamily(matrix.LEGENDRE, 64)
+    plan = compressed.Plan(fam, 1e-10, 1e-2, min_block=4)
+    for b in plan.blocks:
+        b.c_lo += 1
+    C = compressed.Compressed(plan, threshold=False)
+    X = np.random.default_rng(7).standard_normal((1, 64))
+    assert rel(C.execute(X), direct.matvec(fam, X)) > 1e-3
+
+
+# ------------------------------------------------------------------ threshold behaviour
+def test_error_falls_with_eps1_and_scales_with_eps1_over_eps2():
+    # sec. 2.2: accuracy proportional to eps1/eps2
+    N = 512
+    fam = matrix.MatrixFamily(matrix.LEGENDRE, N)
+    X = np.random.default_rng(9).standard_normal((4, N))
+    Yd = direct.matvec(fam, X)
+    errs = {}
+    for eps2 in (1e-3, 1e-2):
+        last = np.inf
+        for eps1 in (1e-5, 1e-7, 1e-9, 1e-11):
+            C = compressed.Compressed(compressed.Plan(fam, eps1, eps2, min_block=16))
+            e = rel(C.execute(X), Yd)
+            assert e < last
+            last = e
+            errs[eps1, eps2] = e
+            assert 1e-4 * eps1 / eps2 <= e <= 3.0 * eps1 / eps2, (eps1, eps2, e)
+
+
+def test_kept_pattern_is_hermitian_and_banded():
+    # real rows give conjugate-symmetric spectra (sec. 5.1), so the kept set is
+    # symmetric under k <-> L-k; for the Jacobi family row n is close to a tone of
+    # frequency theta_n, so its band sits near k = theta_n L / (2 pi)
+    N = 1024
+    fam = matrix.MatrixFamily(matrix.LEGENDRE, N)
+    plan = compressed.Plan(fam, 1e-8, 1e-2)
+    C = compressed.Compressed(plan)
+    theta = np.arccos(fam.nodes())
+    for blk, S in zip(plan.blocks, C.mats):
+        S = S.tocsr()
+        for n in range(0, N, 37):
+            cols = S.indices[S.indptr[n]:S.indptr[n + 1]]
+            mirrored = np.sort((blk.L - cols) % blk.L)
+            np.testing.assert_array_equal(np.sort(cols), mirrored)
+            half = cols[cols <= blk.L // 2]
+            centre = theta[n] * blk.L / (2 * np.pi)
+            assert half.min() - 2 <= centre <= half.max() + 2
+            assert half.max() - half.min() + 1 <= 16
+
+
+def test_transposed_thresholded_accuracy():
+    N = 512
+    fam = matrix.MatrixFamily(matrix.JACOBI, N, alpha=0.5, beta=1.5)
+    C = compressed.Compressed(compressed.Plan(fam, 1e-9, 1e-2))
+    Fv = np.random.default_rng(11).standard_normal((3, N))
+    e = rel(transposed.execute(C, Fv), direct.matvec_transposed(fam, Fv))
+    assert e <= 3e-7
