@@ -1,0 +1,218 @@
+/*
+ * spt.h -- fast special-function transforms by the extra-component method
+ * (A. V. Terekhov, "An extra-component method for evaluating fast
+ * matrix-vector multiplication with special functions", arXiv 2004.11610),
+ * on AMD Instinct MI355X (gfx950).
+ *
+ * The library computes y = A x for a fixed N x N matrix A of special-function
+ * values at quadrature nodes, for many right-hand sides x, in O(N log N) per
+ * right-hand side after an O(N^2 log N) precomputation:
+ *
+ *   precomputation (Alg. 1 steps 1.1-1.3; sec. 3 for the block version)
+ *     zeta(eps1) and the extra-component counts s_i (sec. 2.2), the block
+ *     partition (sec. 3, Table 1), the compressed blocks A_e W F (eq. A_comp)
+ *     thresholded at eps1 * max|A_e W F| and stored as banded tiles.
+ *   computation (Alg. 1 steps 2.1-2.2; sec. 3)
+ *     extend x with zero extra components and divide by the window (eq. Fe1),
+ *     real-to-half-complex FFT (F*, sec. 5.1), banded product with every block
+ *     and the direct tail, summed into y (eq. comp1).
+ *   transposed computation (Alg. 2 steps 2.1-2.2; sec. 3)
+ *     banded product with the transposed blocks, inverse FFT, divide by the
+ *     window and discard the extra components (eq. Fe2).
+ *
+ * Matrices (row j = node x_j, column m = degree):
+ *   SPT_CHEBYSHEV_T  A[j,m] = T_m(x_j) = cos(m theta_j), Chebyshev-Gauss nodes
+ *                    theta_j = pi (j+1/2)/N (eq. cheb_matrix); Algorithm 1 with
+ *                    extras on both sides.
+ *   SPT_LEGENDRE     A[j,m] = sqrt(lambda_j) p_m(x_j), orthonormal Legendre
+ *                    polynomials, Gauss-Legendre nodes (x descending) and
+ *                    Christoffel weights lambda_j, so A is orthogonal (sec. 5.2).
+ *   SPT_JACOBI       the same for Jacobi (alpha, beta), alpha, beta > -1.
+ *   SPT_LAGUERRE_FN  A[j,m] = exp(-x_j/2) L_m(x_j), Gauss-Laguerre nodes
+ *                    ascending (sec. 4).
+ *   SPT_HERMITE_FN   A[j,m] = psi_m(x_j), Hermite functions, Gauss-Hermite
+ *                    nodes ascending.
+ *   All but SPT_CHEBYSHEV_T use the block method (sec. 3): extras on the
+ *   right only, recursion on the first s_i columns, the last columns direct.
+ *
+ * Conventions for every call:
+ *   - Every function returns spt_status: SPT_OK (0) or a negative error code;
+ *     spt_last_error() then returns a message (thread-local, valid until the
+ *     next call on the same thread).
+ *   - A failed call leaves its plan valid (spt_plan_create leaves *out NULL).
+ *   - "stream" is a hipStream_t passed as void* (NULL = the null stream).
+ *     Calls that take a stream enqueue their work and return; device outputs
+ *     are ready when the stream is synchronised.
+ *   - Device pointers are HIP device memory of the device that was current
+ *     when the plan was created.  Matrices of right-hand sides are RHS-major:
+ *     X[r*N + m] is component m of right-hand side r (R x N, contiguous).
+ *   - A plan owns its device memory (compressed blocks, tables, workspace)
+ *     and frees it in spt_plan_destroy.  One plan must not execute on two
+ *     streams at once (its workspace is shared).
+ */
+#ifndef SPT_H
+#define SPT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t spt_status;
+enum {
+  SPT_OK = 0,
+  SPT_E_INVALID_ARG = -1,    /* a NULL, out-of-range or inconsistent argument */
+  SPT_E_NOT_PRECOMPUTED = -2,/* execute before a successful spt_precompute    */
+  SPT_E_HIP = -3,            /* a HIP runtime call failed (message has the text) */
+  SPT_E_OOM = -4,            /* device memory allocation failed               */
+  SPT_E_UNSUPPORTED = -5,    /* precision not prepared, size beyond a kernel  */
+  SPT_E_NUMERIC = -6         /* non-finite values met in the precomputation   */
+};
+
+typedef enum {
+  SPT_CHEBYSHEV_T = 1,
+  SPT_LEGENDRE = 2,
+  SPT_JACOBI = 3,
+  SPT_LAGUERRE_FN = 4,
+  SPT_HERMITE_FN = 5
+} spt_family;
+
+/* Arithmetic of the execute path.  The precomputation is always float64. */
+typedef enum {
+  SPT_F64 = 0,        /* X, Y float64; FFT and banded product in float64          */
+  SPT_F32 = 1,        /* X, Y float32; FFT and banded product in float32          */
+  SPT_SPLIT_BF16 = 2  /* X, Y float32; FFT float32; banded product on the matrix
+                         cores: both operands split into three bfloat16 pieces,
+                         the six products of total order <= 2 accumulated in
+                         float32                                               */
+} spt_precision;
+
+typedef enum {
+  SPT_MODE_AUTO = 0,   /* ROW unless the compressed form stores more than dense */
+  SPT_MODE_ROW = 1,    /* row compression (Alg. 1 / block Alg. 3)              */
+  SPT_MODE_DIRECT = 3  /* dense product with A (no compression)                */
+} spt_mode;
+
+/* Plan parameters.  A zero-filled struct selects every default. */
+typedef struct {
+  double alpha, beta;     /* SPT_JACOBI only; alpha, beta > -1                    */
+  double eps2;            /* extra-component level eps2 (sec. 2.2); 0 -> 1e-2;
+                             must satisfy eps < eps2 < 1                          */
+  int32_t mode;           /* spt_mode                                             */
+  int32_t unweighted;     /* LEGENDRE/JACOBI: 1 drops the sqrt(lambda_j) factor   */
+  uint32_t precisions;    /* bit (1 << spt_precision) per execute precision to
+                             prepare in spt_precompute; 0 -> all three            */
+  int32_t min_block;      /* block recursion stops at width <= min_block; 0 -> 32 */
+  int32_t exact_fft_len;  /* 0: L_i rounded up to the smallest even length whose
+                             half is 2^a 3^b 5^c; 1: L_i = W_i + s_i as computed
+                             (for geometry queries: spt_precompute then fails
+                             with SPT_E_UNSUPPORTED unless every L_i has that
+                             form)                                                 */
+  int64_t panel_rows;     /* rows per precompute panel; 0 -> automatic            */
+  const double* nodes;    /* optional host array of the N nodes, in the family's
+                             order (see above); NULL -> computed on the device.
+                             Copied during spt_plan_create.                       */
+} spt_params;
+
+typedef struct spt_plan* spt_plan_t;
+
+/* Plan summary (spt_plan_query). */
+typedef struct {
+  int32_t family, mode, n_blocks, tail;  /* tail = columns multiplied directly  */
+  int64_t N;
+  double eps1, eps2, zeta;
+  int32_t precomputed;
+  int32_t max_band;                      /* widest per-row band (half spectrum) */
+  int64_t nnz;                           /* kept half-spectrum entries, all blocks */
+  int64_t stored;                        /* stored (tile-padded) entries        */
+  int64_t matrix_bytes_f64;              /* device bytes read per execute (F64) */
+  int64_t matrix_bytes_f32;              /* same for F32 / SPLIT_BF16           */
+  double max_abs[16];                    /* max |A_e W F| per block (first 16)  */
+  double kappa;                          /* max over blocks of rms(w) rms(1/w on the
+                                            retained columns): the factor by which
+                                            rounding of the half spectra grows in
+                                            the product (sec. 2.2 error growth)  */
+} spt_plan_info;
+
+/* Create a plan for the N x N matrix of `family` with threshold eps (= eps1 of
+ * sec. 2.2: entries of A_e W F with |.| <= eps * max|.| are dropped, and
+ * 1/I0(zeta) = eps).  Host only: computes zeta, s_i and the block partition.
+ * N >= 2, 0 < eps < eps2 < 1.  p may be NULL (all defaults). */
+spt_status spt_plan_create(spt_plan_t* out, int32_t family, const spt_params* p,
+                           int64_t N, double eps);
+
+/* Block geometry (host, valid after create): for block i, its FFT length L[i],
+ * the degree of its column 0 (m_offset[i]) and its retained columns
+ * [c_lo[i], c_hi[i]).  Arrays hold `cap` entries; *n_blocks gets the count. */
+spt_status spt_plan_blocks(spt_plan_t plan, int32_t* L, int32_t* m_offset, int32_t* c_lo,
+                           int32_t* c_hi, int32_t cap, int32_t* n_blocks);
+
+/* Precomputation on `stream` (nodes, weights, A_e W F by panels, threshold,
+ * banded tiles).  Synchronises `stream` before returning.  May be called
+ * again (it rebuilds the compressed form). */
+spt_status spt_precompute(spt_plan_t plan, void* stream);
+
+/* Y = A X^T for nrhs right-hand sides: Y[r*N + j] = sum_m A[j,m] X[r*N + m].
+ * X, Y: device, nrhs x N, float64 for SPT_F64 and float32 otherwise, must not
+ * overlap.  nrhs >= 1.  The precision must have been prepared. */
+spt_status spt_execute(spt_plan_t plan, const void* X, void* Y, int64_t nrhs, int32_t prec,
+                       void* stream);
+
+/* Transposed product (Alg. 2 / block Alg. 4): Y[r*N + m] = sum_j A[j,m] X[r*N + j].
+ * Same arguments and rules as spt_execute. */
+spt_status spt_execute_transposed(spt_plan_t plan, const void* X, void* Y, int64_t nrhs,
+                                  int32_t prec, void* stream);
+
+/* Execute `count` plans (any families and sizes, each precomputed with `prec`)
+ * in one launch sequence on `stream`: Y[i] = A_i X[i]^T with nrhs[i]
+ * right-hand sides.  X, Y, nrhs are host arrays of `count` entries holding
+ * device pointers / counts.  The first call for a given set of plans and
+ * sizes records the launches in a HIP graph that later calls replay. */
+spt_status spt_execute_batched(const spt_plan_t* plans, const void* const* X, void* const* Y,
+                               const int64_t* nrhs, int32_t count, int32_t prec, void* stream);
+
+/* Plan summary; info is a host struct filled by the call. */
+spt_status spt_plan_query(spt_plan_t plan, spt_plan_info* info);
+
+/* Copy the N nodes (after spt_precompute) to the host array `out`. */
+spt_status spt_plan_nodes(spt_plan_t plan, double* out);
+
+/* Copy one dense row block of the compressed matrix of block `blk` (after
+ * spt_precompute) to the host: out[(row - row0) * (L/2+1) + k] for rows
+ * [row0, row0 + nrows) and k in [0, L/2], as interleaved (re, im) float64
+ * pairs, entries that are not stored read as zero.  The values are the stored
+ * ones, i.e. already multiplied by c_k (1 at k = 0 and k = L/2, else 2). */
+spt_status spt_plan_compressed_rows(spt_plan_t plan, int32_t blk, int64_t row0, int64_t nrows,
+                                    double* out);
+
+/* Kernel timing with HIP events (for measurement): between spt_profile_begin
+ * and spt_profile_end every execute records an event pair on its stream around
+ * each stage below; spt_profile_end synchronises those events and returns,
+ * per stage, the summed milliseconds and the number of timed launches
+ * (host arrays of SPT_NUM_STAGES entries).  Process-wide; not thread-safe. */
+enum {
+  SPT_STAGE_FFT = 0,        /* extend, divide by the window, F* (all blocks)     */
+  SPT_STAGE_SPMM = 1,       /* banded product of every block and the tail       */
+  SPT_STAGE_SPMM_T = 2,     /* transposed banded product (all blocks)           */
+  SPT_STAGE_INV_FFT = 3,    /* F*, divide by the window, discard the extras     */
+  SPT_STAGE_TAIL_T = 4,     /* transposed direct tail                           */
+  SPT_NUM_STAGES = 5
+};
+spt_status spt_profile_begin(void);
+spt_status spt_profile_end(double* ms, int64_t* launches);
+
+/* Destroy a plan (NULL is allowed).  Waits for the device to finish. */
+spt_status spt_plan_destroy(spt_plan_t plan);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* spt_last_error(void);
+
+/* Library version string. */
+const char* spt_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPT_H */

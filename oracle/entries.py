@@ -168,6 +168,75 @@ def laguerre_ln_dln(N, x):
     return L, d
 
 
+def _two_sum(a, b):
+    s = a + b
+    bb = s - a
+    return s, (a - (s - bb)) + (b - bb)
+
+
+def _two_prod(a, b):
+    p = a * b
+    ca, cb = 134217729.0 * a, 134217729.0 * b   # Veltkamp splitting, 2^27 + 1
+    ah = ca - (ca - a)
+    al = a - ah
+    bh = cb - (cb - b)
+    bl = b - bh
+    return p, ((ah * bh - p) + ah * bl + al * bh) + al * bl
+
+
+def _dd_norm(hi, lo):
+    s = hi + lo
+    return s, lo - (s - hi)
+
+
+def _dd_mul(ah, al, bh, bl):
+    p, e = _two_prod(ah, bh)
+    return _dd_norm(p, e + (ah * bl + al * bh))
+
+
+def _dd_sub(ah, al, bh, bl):
+    s, e = _two_sum(ah, -bh)
+    return _dd_norm(s, e + (al - bl))
+
+
+def _dd_div_int(ah, al, d):
+    q = ah / d
+    p, e = _two_prod(q, d)
+    return _dd_norm(q, ((ah - p) - e + al) / d)
+
+
+def laguerre_ln_dln_dd(N, x):
+    """(L_N(x), L_N'(x)) by the recurrence in double-double arithmetic, up to a
+    common positive factor.  Near x = 0 the recurrence has a double
+    characteristic root and float64 rounding grows like k^2 eps, which leaves
+    the smallest roots with ~1e-11 relative error; the double-double pass is
+    used for one final Newton correction."""
+    x = np.asarray(x, dtype=np.float64)
+    z = np.zeros_like(x)
+    L_prev = (z.copy(), z.copy())
+    L = (np.ones_like(x), z.copy())
+    d_prev = (z.copy(), z.copy())
+    d = (z.copy(), z.copy())
+    for m in range(N):
+        c = _two_sum(np.full_like(x, 2.0 * m + 1.0), -x)          # 2m+1-x, exact
+        t = _dd_mul(c[0], c[1], L[0], L[1])
+        mL = _dd_mul(np.full_like(x, float(m)), z, L_prev[0], L_prev[1])
+        t = _dd_sub(t[0], t[1], mL[0], mL[1])
+        L_next = _dd_div_int(t[0], t[1], m + 1.0)
+        u = _dd_mul(c[0], c[1], d[0], d[1])
+        u = _dd_sub(u[0], u[1], L[0], L[1])
+        md = _dd_mul(np.full_like(x, float(m)), z, d_prev[0], d_prev[1])
+        u = _dd_sub(u[0], u[1], md[0], md[1])
+        d_next = _dd_div_int(u[0], u[1], m + 1.0)
+        L_prev, L, d_prev, d = L, L_next, d, d_next
+        big = np.maximum(np.abs(L[0]), np.abs(d[0])) > _BIG
+        if np.any(big):
+            for pair in (L_prev, L, d_prev, d):
+                pair[0][big] *= _RESCALE
+                pair[1][big] *= _RESCALE
+    return L[0] + L[1], d[0] + d[1]
+
+
 # --------------------------------------------------------------------------- Hermite
 
 def hermite_fn(x, m0, m1):

@@ -85,7 +85,10 @@ def gauss_laguerre(N, idx=None):
     k = np.arange(N, dtype=np.float64)
     j = np.arange(N) if idx is None else np.asarray(idx)
     x0 = _eig_subset(2.0 * k + 1.0, k[1:], j)
-    return _newton(x0, lambda x: entries.laguerre_ln_dln(N, x))
+    x = _newton(x0, lambda x: entries.laguerre_ln_dln(N, x))
+    # one Newton correction with L_N evaluated in double-double (see entries)
+    p, dp = entries.laguerre_ln_dln_dd(N, x)
+    return x - p / dp
 
 
 def gauss_hermite(N, idx=None):

@@ -1,0 +1,977 @@
+// C ABI of the spt library: plans, the precomputation (Alg. 1 steps 1.1-1.3 and
+// the block version of sec. 3), the computation stage (Alg. 1 steps 2.1-2.2),
+// the transposed computation (Alg. 2) and batched execution.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+#include "planner.hpp"
+
+namespace spt {
+namespace {
+
+thread_local std::string g_last_error;
+
+// ---------------------------------------------------------------- device buffers
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { reset(); }
+  void reset() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  void alloc(size_t n) {
+    reset();
+    if (n == 0) return;
+    hipError_t e = hipMalloc(&p, n);
+    if (e != hipSuccess) {
+      p = nullptr;
+      (void)hipGetLastError();
+      throw Error(SPT_E_OOM, "hipMalloc(" + std::to_string(n) + " bytes) failed: " +
+                                 hipGetErrorString(e));
+    }
+    bytes = n;
+  }
+  void ensure(size_t n) {
+    if (n > bytes) alloc(n);
+  }
+  template <typename T> T* as() const { return static_cast<T*>(p); }
+};
+
+template <typename T>
+void upload(DevBuf& b, const std::vector<T>& h, hipStream_t s) {
+  b.alloc(h.size() * sizeof(T));
+  if (!h.empty()) {
+    SPT_HIP(hipMemcpyAsync(b.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    SPT_HIP(hipStreamSynchronize(s));
+  }
+}
+
+struct DevBlock {
+  BlockGeom g;
+  int P = 0;
+  FftPlan fft;
+  DevBuf winv64, winv32, tw64, tw32, post64, post32;
+  DevBuf k0, kw, off;   // per tile
+  DevBuf val64, val32;  // tile boxes
+  int64_t nnz = 0, stored = 0;
+  int max_band = 0;
+  double maxabs = 0.0;
+  double kappa = 0.0;
+  std::vector<int32_t> h_k0, h_kw;
+  std::vector<int64_t> h_off;
+};
+
+bool is_jacobi(int f) { return f == SPT_LEGENDRE || f == SPT_JACOBI; }
+
+}  // namespace
+}  // namespace spt
+
+struct spt_plan {
+  int family = 0;
+  spt_params p{};
+  int64_t N = 0;
+  double eps1 = 0, eps2 = 0, zeta = 0;
+  int mode = SPT_MODE_ROW;  // resolved mode
+  int requested_mode = 0;
+  std::vector<spt::BlockGeom> geom;
+  int64_t tail = 0;
+  std::vector<double> user_nodes;
+  int device = 0;
+  bool precomputed = false;
+  uint32_t prepared = 0;
+  int n_tiles = 0;
+  // device state
+  spt::DevBuf nodes, rowscale, ca, cb;
+  double p0 = 0.0;
+  std::vector<std::unique_ptr<spt::DevBlock>> blk;
+  spt::DevBuf tail64, tail32;
+  spt::DevBuf work;  // execute workspace (half spectra)
+  int64_t work_rhs = 0;
+};
+
+namespace spt {
+namespace {
+
+int64_t tiles_of(int64_t N) { return (N + TILE_ROWS - 1) / TILE_ROWS; }
+
+void check_plan(spt_plan_t plan) {
+  if (!plan) throw Error(SPT_E_INVALID_ARG, "plan is NULL");
+}
+
+void set_device(spt_plan_t plan) { SPT_HIP(hipSetDevice(plan->device)); }
+
+// recurrence tables for the family, degrees 0 .. K
+void family_tables(spt_plan_t plan, int64_t K, hipStream_t s) {
+  const int f = plan->family;
+  std::vector<double> a(K + 2, 0.0), b(K + 2, 0.0);
+  if (is_jacobi(f)) {
+    const double al = plan->p.alpha, be = plan->p.beta, ab = al + be;
+    // orthonormal Jacobi recurrence x p_k = a_{k+1} p_{k+1} + b_k p_k + a_k p_{k-1}
+    b[0] = (be - al) / (ab + 2.0);
+    for (int64_t k = 1; k <= K + 1; ++k) {
+      const double kk = (double)k;
+      b[k] = (be * be - al * al) / ((2 * kk + ab) * (2 * kk + ab + 2));
+    }
+    a[1] = std::sqrt(4.0 * (1 + al) * (1 + be) / ((2 + ab) * (2 + ab) * (3 + ab)));
+    for (int64_t k = 2; k <= K + 1; ++k) {
+      const double kk = (double)k;
+      const double num = 4.0 * kk * (kk + al) * (kk + be) * (kk + ab);
+      const double den = (2 * kk + ab) * (2 * kk + ab) * (2 * kk + ab + 1) * (2 * kk + ab - 1);
+      a[k] = std::sqrt(num / den);
+    }
+    const double log_mu0 = (ab + 1.0) * std::log(2.0) + std::lgamma(al + 1.0) +
+                           std::lgamma(be + 1.0) - std::lgamma(ab + 2.0);
+    plan->p0 = std::exp(-0.5 * log_mu0);
+  } else if (f == SPT_HERMITE_FN) {
+    for (int64_t k = 0; k <= K + 1; ++k) {
+      a[k] = std::sqrt(2.0 / (double)(k + 1));
+      b[k] = std::sqrt((double)k / (double)(k + 1));
+    }
+  }
+  upload(plan->ca, a, s);
+  upload(plan->cb, b, s);
+}
+
+FamilyArgs family_args(spt_plan_t plan, bool with_scale) {
+  FamilyArgs f{};
+  f.family = plan->family;
+  f.N = plan->N;
+  f.unweighted = plan->p.unweighted;
+  f.x = plan->nodes.as<double>();
+  f.rowscale = with_scale ? plan->rowscale.as<double>() : nullptr;
+  f.ca = plan->ca.as<double>();
+  f.cb = plan->cb.as<double>();
+  f.p0 = plan->p0;
+  return f;
+}
+
+void compute_nodes(spt_plan_t plan, hipStream_t s) {
+  const int64_t N = plan->N;
+  const int f = plan->family;
+  plan->nodes.alloc(N * sizeof(double));
+  if (!plan->user_nodes.empty()) {
+    SPT_HIP(hipMemcpyAsync(plan->nodes.p, plan->user_nodes.data(), N * sizeof(double),
+                           hipMemcpyHostToDevice, s));
+    return;
+  }
+  std::vector<double> d(N, 0.0), e2(N, 0.0);
+  if (is_jacobi(f)) {
+    const double al = plan->p.alpha, be = plan->p.beta, ab = al + be;
+    d[0] = (be - al) / (ab + 2.0);
+    for (int64_t k = 1; k < N; ++k) {
+      const double kk = (double)k;
+      d[k] = (be * be - al * al) / ((2 * kk + ab) * (2 * kk + ab + 2));
+    }
+    if (N > 1) e2[1] = 4.0 * (1 + al) * (1 + be) / ((2 + ab) * (2 + ab) * (3 + ab));
+    for (int64_t k = 2; k < N; ++k) {
+      const double kk = (double)k;
+      e2[k] = 4.0 * kk * (kk + al) * (kk + be) * (kk + ab) /
+              ((2 * kk + ab) * (2 * kk + ab) * (2 * kk + ab + 1) * (2 * kk + ab - 1));
+    }
+  } else if (f == SPT_LAGUERRE_FN) {
+    for (int64_t k = 0; k < N; ++k) {
+      d[k] = 2.0 * k + 1.0;
+      e2[k] = (double)k * (double)k;
+    }
+  } else if (f == SPT_HERMITE_FN) {
+    for (int64_t k = 0; k < N; ++k) e2[k] = 0.5 * (double)k;
+  }
+  double lo = 1e300, hi = -1e300;
+  for (int64_t k = 0; k < N; ++k) {
+    const double r = (k > 0 ? std::sqrt(e2[k]) : 0.0) + (k + 1 < N ? std::sqrt(e2[k + 1]) : 0.0);
+    lo = std::min(lo, d[k] - r);
+    hi = std::max(hi, d[k] + r);
+  }
+  const double pad = 1e-10 * std::max(1.0, std::max(std::fabs(lo), std::fabs(hi)));
+  lo -= pad;
+  hi += pad;
+  DevBuf dd, de;
+  upload(dd, d, s);
+  upload(de, e2, s);
+  launch_nodes(family_args(plan, false), dd.as<double>(), de.as<double>(), lo, hi,
+               plan->nodes.as<double>(), s);
+  SPT_HIP(hipStreamSynchronize(s));
+}
+
+template <typename C, typename T>
+std::vector<C> to_vec2(const std::vector<long double>& re, const std::vector<long double>& im) {
+  std::vector<C> out(re.size());
+  for (size_t i = 0; i < re.size(); ++i) out[i] = C{(T)re[i], (T)im[i]};
+  return out;
+}
+
+// exp(+2 pi i q / P), q < P, and exp(+i pi k / P), k <= P, in long double
+void twiddles(int P, std::vector<long double>& twr, std::vector<long double>& twi,
+              std::vector<long double>& por, std::vector<long double>& poi) {
+  const long double pi = 3.141592653589793238462643383279502884L;
+  twr.resize(P);
+  twi.resize(P);
+  for (int q = 0; q < P; ++q) {
+    const long double a = 2.0L * pi * (long double)q / (long double)P;
+    twr[q] = cosl(a);
+    twi[q] = sinl(a);
+  }
+  por.resize(P + 1);
+  poi.resize(P + 1);
+  for (int k = 0; k <= P; ++k) {
+    const long double a = pi * (long double)k / (long double)P;
+    por[k] = cosl(a);
+    poi[k] = sinl(a);
+  }
+}
+
+size_t max_lds_bytes(int device) {
+  int v = 0;
+  SPT_HIP(hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, device));
+  return (size_t)v;
+}
+
+// ---------------------------------------------------------------- precompute
+void build_block(spt_plan_t plan, DevBlock& B, hipStream_t s, size_t lds_max) {
+  const int L = B.g.L, P = L / 2;
+  if (L % 2) throw Error(SPT_E_UNSUPPORTED, "odd block length " + std::to_string(L));
+  B.P = P;
+  B.fft = make_fft_plan(P);
+  if ((size_t)P * sizeof(double2) > lds_max)
+    throw Error(SPT_E_UNSUPPORTED, "block FFT length " + std::to_string(L) +
+                                       " exceeds the LDS of one workgroup");
+  // window over the L columns and its reciprocal
+  std::vector<double> w(L), winv(L);
+  std::vector<float> winv32(L);
+  double sw = 0.0, swi = 0.0;
+  for (int c = 0; c < L; ++c) {
+    w[c] = kaiser((double)c, (double)(L - 1), plan->zeta);
+    winv[c] = 1.0 / w[c];
+    winv32[c] = (float)winv[c];
+    sw += w[c] * w[c];
+    if (c >= B.g.c_lo && c < B.g.c_hi) swi += winv[c] * winv[c];
+  }
+  B.kappa = std::sqrt(sw / L) * std::sqrt(swi / (B.g.c_hi - B.g.c_lo));
+  DevBuf dw;
+  upload(dw, w, s);
+  upload(B.winv64, winv, s);
+  upload(B.winv32, winv32, s);
+  std::vector<long double> twr, twi, por, poi;
+  twiddles(P, twr, twi, por, poi);
+  upload(B.tw64, to_vec2<double2, double>(twr, twi), s);
+  upload(B.tw32, to_vec2<float2, float>(twr, twi), s);
+  upload(B.post64, to_vec2<double2, double>(por, poi), s);
+  upload(B.post32, to_vec2<float2, float>(por, poi), s);
+
+  const int64_t N = plan->N;
+  const int64_t ntiles = plan->n_tiles;
+  // rows per panel: A_e W rows (8 L bytes) + their half spectra (16 (P+1) bytes)
+  int64_t budget = (int64_t)8 << 30;
+  int64_t rows = plan->p.panel_rows > 0 ? plan->p.panel_rows
+                                        : budget / (8 * (int64_t)L + 16 * (int64_t)(P + 1));
+  rows = std::max<int64_t>(TILE_ROWS, (rows / TILE_ROWS) * TILE_ROWS);
+  rows = std::min<int64_t>(rows, ntiles * TILE_ROWS);
+  const int64_t npanel = (N + rows - 1) / rows;
+  DevBuf rowbuf, spec, maxbits, klo, khi, kcnt;
+  rowbuf.alloc((size_t)rows * L * sizeof(double));
+  spec.alloc((size_t)rows * (P + 1) * sizeof(double2));
+  maxbits.alloc(sizeof(unsigned long long));
+  klo.alloc(rows * sizeof(int32_t));
+  khi.alloc(rows * sizeof(int32_t));
+  kcnt.alloc(rows * sizeof(int32_t));
+  SPT_HIP(hipMemsetAsync(maxbits.p, 0, sizeof(unsigned long long), s));
+  const FamilyArgs fa = family_args(plan, is_jacobi(plan->family) && !plan->p.unweighted);
+  RowFftArgs ra{};
+  ra.rows = rowbuf.as<double>();
+  ra.spec = spec.as<double2>();
+  ra.tw = B.tw64.as<double2>();
+  ra.post = B.post64.as<double2>();
+  ra.L = L;
+  ra.P = P;
+  ra.scale = 1.0 / std::sqrt((double)L);
+  auto spectrum = [&](int64_t row0, int nr) {
+    launch_rec_rows(fa, row0, nr, B.g.m_off, L, dw.as<double>(), rowbuf.as<double>(), s);
+    ra.nrows = nr;
+    launch_row_fft(ra, B.fft, s);
+  };
+  auto panel_rows = [&](int64_t p) { return (int)std::min<int64_t>(rows, N - p * rows); };
+
+  // pass 1: max |A_e W F| over the block (Alg. 1 step 1.3)
+  for (int64_t p = 0; p < npanel; ++p) {
+    const int nr = panel_rows(p);
+    spectrum(p * rows, nr);
+    launch_maxabs(spec.as<double2>(), (int64_t)nr * (P + 1), maxbits.as<unsigned long long>(), s);
+  }
+  unsigned long long bits = 0;
+  SPT_HIP(hipMemcpyAsync(&bits, maxbits.p, sizeof(bits), hipMemcpyDeviceToHost, s));
+  SPT_HIP(hipStreamSynchronize(s));
+  double m2;
+  std::memcpy(&m2, &bits, sizeof(m2));
+  if (!std::isfinite(m2))
+    throw Error(SPT_E_NUMERIC, "non-finite entries in the compressed block of length " +
+                                   std::to_string(L));
+  B.maxabs = std::sqrt(m2);
+  const double thr = plan->eps1 * B.maxabs;
+
+  // pass 2: band of every row, tile boxes on the host
+  std::vector<int32_t> hlo(N), hhi(N), hcnt(N);
+  for (int64_t p = 0; p < npanel; ++p) {
+    const int nr = panel_rows(p);
+    if (npanel > 1) spectrum(p * rows, nr);
+    launch_extents(spec.as<double2>(), nr, P, thr, klo.as<int32_t>(), khi.as<int32_t>(),
+                   kcnt.as<int32_t>(), s);
+    SPT_HIP(hipMemcpyAsync(hcnt.data() + p * rows, kcnt.p, nr * sizeof(int32_t),
+                           hipMemcpyDeviceToHost, s));
+    SPT_HIP(hipMemcpyAsync(hlo.data() + p * rows, klo.p, nr * sizeof(int32_t),
+                           hipMemcpyDeviceToHost, s));
+    SPT_HIP(hipMemcpyAsync(hhi.data() + p * rows, khi.p, nr * sizeof(int32_t),
+                           hipMemcpyDeviceToHost, s));
+    SPT_HIP(hipStreamSynchronize(s));
+  }
+  B.h_k0.assign(ntiles, 0);
+  B.h_kw.assign(ntiles, 0);
+  B.h_off.assign(ntiles, 0);
+  int64_t total = 0;
+  B.max_band = 0;
+  for (int64_t t = 0; t < ntiles; ++t) {
+    int lo = 0x7FFFFFFF, hi = -1;
+    for (int64_t q = 0; q < TILE_ROWS; ++q) {
+      const int64_t n = t * TILE_ROWS + q;
+      if (n >= N || hhi[n] < 0) continue;
+      lo = std::min(lo, hlo[n]);
+      hi = std::max(hi, hhi[n]);
+      B.max_band = std::max(B.max_band, hhi[n] - hlo[n] + 1);
+    }
+    B.h_k0[t] = hi < 0 ? 0 : lo;
+    B.h_kw[t] = hi < 0 ? 0 : hi - lo + 1;
+    B.h_off[t] = total;
+    total += (int64_t)B.h_kw[t] * TILE_ROWS;
+  }
+  B.stored = total;
+  upload(B.k0, B.h_k0, s);
+  upload(B.kw, B.h_kw, s);
+  upload(B.off, B.h_off, s);
+  const bool want64 = plan->prepared & (1u << SPT_F64);
+  const bool want32 = plan->prepared & ((1u << SPT_F32) | (1u << SPT_SPLIT_BF16));
+  B.val64.reset();
+  B.val32.reset();
+  if (want64) B.val64.alloc(std::max<int64_t>(total, 1) * sizeof(double2));
+  if (want32) B.val32.alloc(std::max<int64_t>(total, 1) * sizeof(float2));
+
+  // pass 3: pack the kept entries (times c_k) into the tiles
+  for (int64_t p = 0; p < npanel; ++p) {
+    const int nr = panel_rows(p);
+    if (npanel > 1) spectrum(p * rows, nr);
+    launch_pack(spec.as<double2>(), p * rows, nr, N, P, thr, B.k0.as<int32_t>(),
+                B.kw.as<int32_t>(), B.off.as<int64_t>(), (int)((p * rows) / TILE_ROWS),
+                want64 ? B.val64.as<double2>() : nullptr, want32 ? B.val32.as<float2>() : nullptr,
+                s);
+  }
+  SPT_HIP(hipStreamSynchronize(s));
+  int64_t nnz = 0;
+  for (int64_t n = 0; n < N; ++n) nnz += hcnt[n];
+  B.nnz = nnz;
+}
+
+void build_tail(spt_plan_t plan, hipStream_t s) {
+  plan->tail64.reset();
+  plan->tail32.reset();
+  const int64_t t = plan->tail;
+  if (t <= 0) return;
+  const int64_t ldt = (int64_t)plan->n_tiles * TILE_ROWS;
+  plan->tail64.alloc((size_t)t * ldt * sizeof(double));
+  launch_rec_tail(family_args(plan, is_jacobi(plan->family) && !plan->p.unweighted), (int)t,
+                  plan->tail64.as<double>(), s);
+  if (plan->prepared & ((1u << SPT_F32) | (1u << SPT_SPLIT_BF16))) {
+    plan->tail32.alloc((size_t)t * ldt * sizeof(float));
+    launch_to_f32(plan->tail64.as<double>(), plan->tail32.as<float>(), t * ldt, s);
+  }
+  SPT_HIP(hipStreamSynchronize(s));
+}
+
+void precompute(spt_plan_t plan, hipStream_t s) {
+  set_device(plan);
+  const size_t lds_max = max_lds_bytes(plan->device);
+  init_fft_kernels(lds_max);
+  plan->precomputed = false;
+  plan->prepared = plan->p.precisions ? plan->p.precisions : 7u;
+  plan->n_tiles = (int)tiles_of(plan->N);
+  int64_t K = plan->N;
+  for (auto& g : plan->geom) K = std::max<int64_t>(K, g.L + std::max(0, g.m_off));
+  family_tables(plan, K + 2, s);
+  compute_nodes(plan, s);
+  if (is_jacobi(plan->family) && !plan->p.unweighted) {
+    plan->rowscale.alloc(plan->N * sizeof(double));
+    launch_weights(family_args(plan, false), plan->rowscale.as<double>(), s);
+  }
+  SPT_HIP(hipStreamSynchronize(s));
+  plan->blk.clear();
+  plan->mode = plan->requested_mode == SPT_MODE_DIRECT ? SPT_MODE_DIRECT : SPT_MODE_ROW;
+  if (plan->mode == SPT_MODE_ROW) {
+    for (auto& g : plan->geom) {
+      auto B = std::make_unique<DevBlock>();
+      B->g = g;
+      build_block(plan, *B, s, lds_max);
+      plan->blk.push_back(std::move(B));
+    }
+    if (plan->requested_mode == SPT_MODE_AUTO) {
+      // fewest stored bytes: the compressed blocks against the dense matrix
+      int64_t stored = 0;
+      for (auto& B : plan->blk) stored += 2 * B->stored;  // complex = 2 reals
+      stored += plan->tail * plan->N;
+      if (stored > plan->N * plan->N) {
+        plan->blk.clear();
+        plan->mode = SPT_MODE_DIRECT;
+      }
+    }
+  }
+  if (plan->mode == SPT_MODE_DIRECT) plan->tail = plan->N;
+  build_tail(plan, s);
+  plan->precomputed = true;
+}
+
+// ---------------------------------------------------------------- execute
+void ensure_work(spt_plan_t plan, int64_t R) {
+  int64_t per = 0;
+  for (auto& B : plan->blk) per += B->P + 1;
+  const size_t bytes = (size_t)std::max<int64_t>(per, 1) * (size_t)R * sizeof(double2);
+  if (bytes > plan->work.bytes) {
+    plan->work.alloc(bytes);
+    plan->work_rhs = R;
+  }
+}
+
+void check_exec(spt_plan_t plan, const void* X, const void* Y, int64_t R, int prec) {
+  check_plan(plan);
+  if (!plan->precomputed) throw Error(SPT_E_NOT_PRECOMPUTED, "plan is not precomputed");
+  if (!X || !Y) throw Error(SPT_E_INVALID_ARG, "X or Y is NULL");
+  if (R < 1 || R > 65535 * 64) throw Error(SPT_E_INVALID_ARG, "nrhs out of range");
+  if (prec < 0 || prec > 2) throw Error(SPT_E_INVALID_ARG, "unknown precision");
+  if (!(plan->prepared & (1u << prec)))
+    throw Error(SPT_E_UNSUPPORTED, "precision " + std::to_string(prec) + " was not prepared");
+  const size_t es = prec == SPT_F64 ? 8 : 4;
+  const char* x0 = static_cast<const char*>(X);
+  const char* y0 = static_cast<const char*>(Y);
+  const size_t n = (size_t)R * plan->N * es;
+  if (x0 < y0 + n && y0 < x0 + n) throw Error(SPT_E_INVALID_ARG, "X and Y overlap");
+}
+
+template <typename T>
+void execute_t(spt_plan_t plan, const T* X, T* Y, int64_t R, int prec, hipStream_t s) {
+  using C = cplx_t<T>;
+  ensure_work(plan, R);
+  SpmmArgs<T> sa{};
+  sa.nblk = (int)plan->blk.size();
+  sa.n_tiles = plan->n_tiles;
+  C* z = plan->work.as<C>();
+  std::vector<ExecFftArgs<T>> ffts;
+  for (int i = 0; i < sa.nblk; ++i) {
+    DevBlock& B = *plan->blk[i];
+    ExecFftArgs<T> fa{};
+    fa.X = X;
+    fa.Z = z;
+    fa.winv = std::is_same<T, double>::value ? (const T*)B.winv64.p : (const T*)B.winv32.p;
+    fa.tw = std::is_same<T, double>::value ? (const C*)B.tw64.p : (const C*)B.tw32.p;
+    fa.post = std::is_same<T, double>::value ? (const C*)B.post64.p : (const C*)B.post32.p;
+    fa.N = plan->N;
+    fa.R = (int)R;
+    fa.L = B.g.L;
+    fa.P = B.P;
+    fa.ldz = B.P + 1;
+    fa.m_off = B.g.m_off;
+    fa.c_lo = B.g.c_lo;
+    fa.c_hi = B.g.c_hi;
+    fa.scale = (T)(1.0 / std::sqrt((double)B.g.L));
+    ffts.push_back(fa);
+    sa.k0[i] = B.k0.as<int32_t>();
+    sa.kw[i] = B.kw.as<int32_t>();
+    sa.off[i] = B.off.as<int64_t>();
+    sa.val[i] = std::is_same<T, double>::value ? (const C*)B.val64.p : (const C*)B.val32.p;
+    sa.z[i] = z;
+    sa.ldz[i] = B.P + 1;
+    z += (size_t)R * (B.P + 1);
+  }
+  sa.tail = (int)plan->tail;
+  sa.tailmat = std::is_same<T, double>::value ? (const T*)plan->tail64.p : (const T*)plan->tail32.p;
+  sa.X = X;
+  sa.Y = Y;
+  sa.R = (int)R;
+  sa.N = plan->N;
+  if (!ffts.empty())
+    staged(SPT_STAGE_FFT, s, [&] {
+      for (int i = 0; i < sa.nblk; ++i) launch_exec_fft<T>(ffts[i], plan->blk[i]->fft, s);
+    });
+  staged(SPT_STAGE_SPMM, s, [&] {
+    if constexpr (std::is_same<T, float>::value) {
+      if (prec == SPT_SPLIT_BF16) {
+        launch_spmm_split_bf16(sa, s);
+        return;
+      }
+    }
+    launch_spmm<T>(sa, s);
+  });
+}
+
+template <typename T>
+__global__ void zero_kernel(T* p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = T(0);
+}
+
+template <typename T>
+void execute_transposed_t(spt_plan_t plan, const T* F, T* Y, int64_t R, hipStream_t s) {
+  using C = cplx_t<T>;
+  ensure_work(plan, R);
+  int64_t per = 0;
+  for (auto& B : plan->blk) per += B->P + 1;
+  const int64_t nz = 2 * per * R;
+  if (nz > 0) {
+    const int nb = (int)std::min<int64_t>((nz + 255) / 256, 8192);
+    hipLaunchKernelGGL(zero_kernel<T>, dim3(nb), dim3(256), 0, s, (T*)plan->work.p, nz);
+    SPT_HIP(hipGetLastError());
+  }
+  C* u = plan->work.as<C>();
+  for (auto& Bp : plan->blk) {
+    DevBlock& B = *Bp;
+    SpmmTArgs<T> ta{};
+    ta.k0 = B.k0.as<int32_t>();
+    ta.kw = B.kw.as<int32_t>();
+    ta.off = B.off.as<int64_t>();
+    ta.val = std::is_same<T, double>::value ? (const C*)B.val64.p : (const C*)B.val32.p;
+    ta.u = u;
+    ta.ldu = B.P + 1;
+    ta.P = B.P;
+    ta.n_tiles = plan->n_tiles;
+    ta.F = F;
+    ta.R = (int)R;
+    ta.N = plan->N;
+    staged(SPT_STAGE_SPMM_T, s, [&] { launch_spmm_transposed<T>(ta, s); });
+    InvFftArgs<T> ia{};
+    ia.U = u;
+    ia.Y = Y;
+    ia.winv = std::is_same<T, double>::value ? (const T*)B.winv64.p : (const T*)B.winv32.p;
+    ia.tw = std::is_same<T, double>::value ? (const C*)B.tw64.p : (const C*)B.tw32.p;
+    ia.post = std::is_same<T, double>::value ? (const C*)B.post64.p : (const C*)B.post32.p;
+    ia.N = plan->N;
+    ia.R = (int)R;
+    ia.L = B.g.L;
+    ia.P = B.P;
+    ia.ldu = B.P + 1;
+    ia.m_off = B.g.m_off;
+    ia.c_lo = B.g.c_lo;
+    ia.c_hi = B.g.c_hi;
+    ia.scale = (T)(1.0 / std::sqrt((double)B.g.L));
+    staged(SPT_STAGE_INV_FFT, s, [&] { launch_inv_fft<T>(ia, B.fft, s); });
+    u += (size_t)R * (B.P + 1);
+  }
+  if (plan->tail > 0)
+    staged(SPT_STAGE_TAIL_T, s, [&] {
+      launch_tail_transposed<T>(std::is_same<T, double>::value ? (const T*)plan->tail64.p
+                                                               : (const T*)plan->tail32.p,
+                                (int)plan->tail, F, Y, (int)R, plan->N, s);
+    });
+}
+
+// ---------------------------------------------------------------- stage timing
+struct Profiler {
+  bool on = false;
+  struct Rec {
+    int stage;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+  hipEvent_t get() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e;
+    SPT_HIP(hipEventCreate(&e));
+    return e;
+  }
+};
+Profiler g_prof;
+
+// records an event pair around fn() on stream s when profiling is on
+template <typename F>
+void staged(int stage, hipStream_t s, F&& fn) {
+  if (!g_prof.on) {
+    fn();
+    return;
+  }
+  Profiler::Rec r{stage, g_prof.get(), g_prof.get()};
+  SPT_HIP(hipEventRecord(r.a, s));
+  fn();
+  SPT_HIP(hipEventRecord(r.b, s));
+  g_prof.recs.push_back(r);
+}
+
+// ---------------------------------------------------------------- batched graphs
+struct BatchCache {
+  std::vector<const void*> key;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t stream = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  int device = -1;
+  ~BatchCache() { clear(); }
+  void clear() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    exec = nullptr;
+    key.clear();
+  }
+};
+std::mutex g_batch_mu;
+BatchCache g_batch;
+
+template <typename F>
+spt_status guard(F&& fn) {
+  try {
+    fn();
+    g_last_error.clear();
+    return SPT_OK;
+  } catch (const Error& e) {
+    g_last_error = e.what();
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    g_last_error = "host allocation failed";
+    return SPT_E_OOM;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return SPT_E_HIP;
+  }
+}
+
+}  // namespace
+}  // namespace spt
+
+using namespace spt;
+
+extern "C" {
+
+const char* spt_last_error(void) { return g_last_error.c_str(); }
+
+const char* spt_version(void) { return "spt 0.1 (gfx950)"; }
+
+spt_status spt_plan_create(spt_plan_t* out, int32_t family, const spt_params* p, int64_t N,
+                           double eps) {
+  return guard([&] {
+    if (!out) throw Error(SPT_E_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (family < SPT_CHEBYSHEV_T || family > SPT_HERMITE_FN)
+      throw Error(SPT_E_INVALID_ARG, "unknown family " + std::to_string(family));
+    if (N < 2 || N > (int64_t)1 << 24) throw Error(SPT_E_INVALID_ARG, "N out of range");
+    spt_params prm{};
+    if (p) prm = *p;
+    const double eps2 = prm.eps2 == 0.0 ? 1e-2 : prm.eps2;
+    if (!(eps > 0.0 && eps < 1.0)) throw Error(SPT_E_INVALID_ARG, "eps must lie in (0, 1)");
+    if (!(eps2 > eps && eps2 < 1.0)) throw Error(SPT_E_INVALID_ARG, "need eps < eps2 < 1");
+    if (family == SPT_JACOBI && !(prm.alpha > -1.0 && prm.beta > -1.0))
+      throw Error(SPT_E_INVALID_ARG, "Jacobi needs alpha, beta > -1");
+    if (family == SPT_LEGENDRE) prm.alpha = prm.beta = 0.0;
+    if (prm.mode != SPT_MODE_AUTO && prm.mode != SPT_MODE_ROW && prm.mode != SPT_MODE_DIRECT)
+      throw Error(SPT_E_INVALID_ARG, "unknown mode");
+    if (prm.precisions & ~7u) throw Error(SPT_E_INVALID_ARG, "unknown precision bits");
+    if (prm.min_block < 0 || prm.panel_rows < 0) throw Error(SPT_E_INVALID_ARG, "negative size");
+    auto plan = std::make_unique<spt_plan>();
+    plan->family = family;
+    plan->N = N;
+    plan->eps1 = eps;
+    plan->eps2 = eps2;
+    plan->requested_mode = prm.mode;
+    if (prm.nodes) {
+      plan->user_nodes.assign(prm.nodes, prm.nodes + N);
+      for (double v : plan->user_nodes)
+        if (!std::isfinite(v)) throw Error(SPT_E_INVALID_ARG, "non-finite node");
+    }
+    prm.nodes = nullptr;
+    plan->p = prm;
+    plan->zeta = zeta_of_eps(eps);
+    const int64_t min_block = prm.min_block > 0 ? prm.min_block : 32;
+    const bool round_fft = prm.exact_fft_len == 0;
+    if (prm.mode == SPT_MODE_DIRECT) {
+      plan->geom.clear();
+      plan->tail = N;
+    } else if (family == SPT_CHEBYSHEV_T) {
+      partition_two_sided(N, plan->zeta, eps2, round_fft, plan->geom, plan->tail);
+    } else {
+      partition_one_sided(N, plan->zeta, eps2, min_block, round_fft, plan->geom, plan->tail);
+    }
+    if ((int)plan->geom.size() > MAX_BLOCKS) throw Error(SPT_E_UNSUPPORTED, "too many blocks");
+    plan->mode = prm.mode == SPT_MODE_DIRECT ? SPT_MODE_DIRECT : SPT_MODE_ROW;
+    // plan creation is host-only; the device is the current one (0 when HIP
+    // reports none, in which case the first device call fails with SPT_E_HIP)
+    if (hipGetDevice(&plan->device) != hipSuccess) {
+      (void)hipGetLastError();
+      plan->device = 0;
+    }
+    *out = plan.release();
+  });
+}
+
+spt_status spt_plan_blocks(spt_plan_t plan, int32_t* L, int32_t* m_offset, int32_t* c_lo,
+                           int32_t* c_hi, int32_t cap, int32_t* n_blocks) {
+  return guard([&] {
+    check_plan(plan);
+    const int n = plan->precomputed ? (int)plan->blk.size() : (int)plan->geom.size();
+    if (n_blocks) *n_blocks = n;
+    for (int i = 0; i < n && i < cap; ++i) {
+      const BlockGeom& g = plan->precomputed ? plan->blk[i]->g : plan->geom[i];
+      if (L) L[i] = g.L;
+      if (m_offset) m_offset[i] = g.m_off;
+      if (c_lo) c_lo[i] = g.c_lo;
+      if (c_hi) c_hi[i] = g.c_hi;
+    }
+  });
+}
+
+spt_status spt_precompute(spt_plan_t plan, void* stream) {
+  return guard([&] {
+    check_plan(plan);
+    try {
+      precompute(plan, static_cast<hipStream_t>(stream));
+    } catch (...) {
+      plan->precomputed = false;
+      plan->blk.clear();
+      throw;
+    }
+  });
+}
+
+spt_status spt_execute(spt_plan_t plan, const void* X, void* Y, int64_t nrhs, int32_t prec,
+                       void* stream) {
+  return guard([&] {
+    check_exec(plan, X, Y, nrhs, prec);
+    set_device(plan);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (prec == SPT_F64)
+      execute_t<double>(plan, (const double*)X, (double*)Y, nrhs, prec, s);
+    else
+      execute_t<float>(plan, (const float*)X, (float*)Y, nrhs, prec, s);
+  });
+}
+
+spt_status spt_execute_transposed(spt_plan_t plan, const void* X, void* Y, int64_t nrhs,
+                                  int32_t prec, void* stream) {
+  return guard([&] {
+    check_exec(plan, X, Y, nrhs, prec);
+    if (prec == SPT_SPLIT_BF16)
+      throw Error(SPT_E_UNSUPPORTED, "the transposed product runs in F64 or F32");
+    set_device(plan);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (prec == SPT_F64)
+      execute_transposed_t<double>(plan, (const double*)X, (double*)Y, nrhs, s);
+    else
+      execute_transposed_t<float>(plan, (const float*)X, (float*)Y, nrhs, s);
+  });
+}
+
+spt_status spt_execute_batched(const spt_plan_t* plans, const void* const* X, void* const* Y,
+                               const int64_t* nrhs, int32_t count, int32_t prec, void* stream) {
+  return guard([&] {
+    if (count < 0 || (count > 0 && (!plans || !X || !Y || !nrhs)))
+      throw Error(SPT_E_INVALID_ARG, "bad batch arrays");
+    if (count == 0) return;
+    for (int i = 0; i < count; ++i) {
+      check_exec(plans[i], X[i], Y[i], nrhs[i], prec);
+      if (plans[i]->device != plans[0]->device)
+        throw Error(SPT_E_INVALID_ARG, "batched plans live on different devices");
+    }
+    set_device(plans[0]);
+    for (int i = 0; i < count; ++i) ensure_work(plans[i], nrhs[i]);
+    std::vector<const void*> key;
+    key.push_back((const void*)(intptr_t)prec);
+    for (int i = 0; i < count; ++i) {
+      key.push_back(plans[i]);
+      key.push_back(X[i]);
+      key.push_back(Y[i]);
+      key.push_back((const void*)(intptr_t)nrhs[i]);
+      key.push_back(plans[i]->work.p);
+    }
+    std::lock_guard<std::mutex> lk(g_batch_mu);
+    BatchCache& bc = g_batch;
+    if (bc.device != plans[0]->device) {
+      bc.clear();
+      if (bc.stream) (void)hipStreamDestroy(bc.stream);
+      if (bc.ev_in) (void)hipEventDestroy(bc.ev_in);
+      if (bc.ev_out) (void)hipEventDestroy(bc.ev_out);
+      SPT_HIP(hipStreamCreateWithFlags(&bc.stream, hipStreamNonBlocking));
+      SPT_HIP(hipEventCreateWithFlags(&bc.ev_in, hipEventDisableTiming));
+      SPT_HIP(hipEventCreateWithFlags(&bc.ev_out, hipEventDisableTiming));
+      bc.device = plans[0]->device;
+    }
+    if (!bc.exec || bc.key != key) {
+      bc.clear();
+      hipGraph_t g = nullptr;
+      const bool prof = g_prof.on;
+      g_prof.on = false;  // no timing events inside a graph
+      struct Restore {
+        bool v;
+        ~Restore() { g_prof.on = v; }
+      } restore{prof};
+      SPT_HIP(hipStreamBeginCapture(bc.stream, hipStreamCaptureModeThreadLocal));
+      try {
+        for (int i = 0; i < count; ++i) {
+          if (prec == SPT_F64)
+            execute_t<double>(plans[i], (const double*)X[i], (double*)Y[i], nrhs[i], prec,
+                              bc.stream);
+          else
+            execute_t<float>(plans[i], (const float*)X[i], (float*)Y[i], nrhs[i], prec,
+                             bc.stream);
+        }
+      } catch (...) {
+        (void)hipStreamEndCapture(bc.stream, &g);
+        if (g) (void)hipGraphDestroy(g);
+        throw;
+      }
+      SPT_HIP(hipStreamEndCapture(bc.stream, &g));
+      hipError_t e = hipGraphInstantiate(&bc.exec, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (e != hipSuccess) {
+        bc.exec = nullptr;
+        throw Error(SPT_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+      }
+      bc.key = key;
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    SPT_HIP(hipEventRecord(bc.ev_in, s));
+    SPT_HIP(hipStreamWaitEvent(bc.stream, bc.ev_in, 0));
+    SPT_HIP(hipGraphLaunch(bc.exec, bc.stream));
+    SPT_HIP(hipEventRecord(bc.ev_out, bc.stream));
+    SPT_HIP(hipStreamWaitEvent(s, bc.ev_out, 0));
+  });
+}
+
+spt_status spt_plan_query(spt_plan_t plan, spt_plan_info* info) {
+  return guard([&] {
+    check_plan(plan);
+    if (!info) throw Error(SPT_E_INVALID_ARG, "info is NULL");
+    std::memset(info, 0, sizeof(*info));
+    info->family = plan->family;
+    info->mode = plan->mode;
+    info->N = plan->N;
+    info->eps1 = plan->eps1;
+    info->eps2 = plan->eps2;
+    info->zeta = plan->zeta;
+    info->tail = (int32_t)plan->tail;
+    info->precomputed = plan->precomputed;
+    info->n_blocks = plan->precomputed ? (int)plan->blk.size() : (int)plan->geom.size();
+    if (plan->precomputed) {
+      int64_t ldt = (int64_t)plan->n_tiles * TILE_ROWS;
+      int64_t tiles_bytes = 0;
+      for (size_t i = 0; i < plan->blk.size(); ++i) {
+        const DevBlock& B = *plan->blk[i];
+        info->nnz += B.nnz;
+        info->stored += B.stored;
+        info->max_band = std::max(info->max_band, B.max_band);
+        tiles_bytes += (int64_t)plan->n_tiles * 16;
+        if (i < 16) info->max_abs[i] = B.maxabs;
+        info->kappa = std::max(info->kappa, B.kappa);
+      }
+      info->matrix_bytes_f64 = info->stored * 16 + tiles_bytes + plan->tail * ldt * 8;
+      info->matrix_bytes_f32 = info->stored * 8 + tiles_bytes + plan->tail * ldt * 4;
+    }
+  });
+}
+
+spt_status spt_plan_nodes(spt_plan_t plan, double* out) {
+  return guard([&] {
+    check_plan(plan);
+    if (!out) throw Error(SPT_E_INVALID_ARG, "out is NULL");
+    if (!plan->precomputed) throw Error(SPT_E_NOT_PRECOMPUTED, "plan is not precomputed");
+    set_device(plan);
+    SPT_HIP(hipMemcpy(out, plan->nodes.p, plan->N * sizeof(double), hipMemcpyDeviceToHost));
+  });
+}
+
+spt_status spt_plan_compressed_rows(spt_plan_t plan, int32_t blk, int64_t row0, int64_t nrows,
+                                    double* out) {
+  return guard([&] {
+    check_plan(plan);
+    if (!plan->precomputed) throw Error(SPT_E_NOT_PRECOMPUTED, "plan is not precomputed");
+    if (blk < 0 || blk >= (int)plan->blk.size()) throw Error(SPT_E_INVALID_ARG, "bad block");
+    if (!out || row0 < 0 || nrows < 0 || row0 + nrows > plan->N)
+      throw Error(SPT_E_INVALID_ARG, "bad row range");
+    const DevBlock& B = *plan->blk[blk];
+    if (!B.val64.p) throw Error(SPT_E_UNSUPPORTED, "F64 values were not prepared");
+    set_device(plan);
+    const int64_t P1 = B.P + 1;
+    std::fill(out, out + 2 * nrows * P1, 0.0);
+    if (nrows == 0) return;
+    const int64_t t0 = row0 / TILE_ROWS, t1 = (row0 + nrows - 1) / TILE_ROWS;
+    for (int64_t t = t0; t <= t1; ++t) {
+      const int kw = B.h_kw[t];
+      if (kw == 0) continue;
+      std::vector<double2> box((size_t)kw * TILE_ROWS);
+      SPT_HIP(hipMemcpy(box.data(), B.val64.as<double2>() + B.h_off[t],
+                        box.size() * sizeof(double2), hipMemcpyDeviceToHost));
+      for (int kk = 0; kk < kw; ++kk)
+        for (int q = 0; q < TILE_ROWS; ++q) {
+          const int64_t n = t * TILE_ROWS + q;
+          if (n < row0 || n >= row0 + nrows) continue;
+          const int64_t k = B.h_k0[t] + kk;
+          out[2 * ((n - row0) * P1 + k)] = box[(size_t)kk * TILE_ROWS + q].x;
+          out[2 * ((n - row0) * P1 + k) + 1] = box[(size_t)kk * TILE_ROWS + q].y;
+        }
+    }
+  });
+}
+
+spt_status spt_profile_begin(void) {
+  return guard([&] {
+    for (auto& r : g_prof.recs) {
+      g_prof.pool.push_back(r.a);
+      g_prof.pool.push_back(r.b);
+    }
+    g_prof.recs.clear();
+    g_prof.on = true;
+  });
+}
+
+spt_status spt_profile_end(double* ms, int64_t* launches) {
+  return guard([&] {
+    g_prof.on = false;
+    if (ms) std::fill(ms, ms + SPT_NUM_STAGES, 0.0);
+    if (launches) std::fill(launches, launches + SPT_NUM_STAGES, (int64_t)0);
+    for (auto& r : g_prof.recs) {
+      SPT_HIP(hipEventSynchronize(r.b));
+      float t = 0.f;
+      SPT_HIP(hipEventElapsedTime(&t, r.a, r.b));
+      if (ms) ms[r.stage] += t;
+      if (launches) launches[r.stage] += 1;
+      g_prof.pool.push_back(r.a);
+      g_prof.pool.push_back(r.b);
+    }
+    g_prof.recs.clear();
+  });
+}
+
+spt_status spt_plan_destroy(spt_plan_t plan) {
+  return guard([&] {
+    if (!plan) return;
+    (void)hipSetDevice(plan->device);
+    (void)hipDeviceSynchronize();
+    {
+      std::lock_guard<std::mutex> lk(g_batch_mu);
+      for (const void* k : g_batch.key)
+        if (k == plan) {
+          g_batch.clear();
+          break;
+        }
+    }
+    delete plan;
+  });
+}
+
+}  // extern "C"

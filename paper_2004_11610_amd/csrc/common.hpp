@@ -1,0 +1,175 @@
+// Shared host/device definitions of the spt library (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <cstdio>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/spt.h"
+
+namespace spt {
+
+// Rows per compressed tile: every block of a plan is cut into the same row
+// tiles of TILE_ROWS consecutive nodes, so that one workgroup owns the same
+// output rows in every block and sums the blocks in registers.
+constexpr int TILE_ROWS = 16;
+// Largest number of blocks a plan may have (the recursion stops long before).
+constexpr int MAX_BLOCKS = 24;
+// Largest FFT radix pass count.
+constexpr int MAX_PASSES = 24;
+
+struct Error : std::runtime_error {
+  spt_status code;
+  Error(spt_status c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define SPT_HIP(call)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (call);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      throw ::spt::Error(e_ == hipErrorOutOfMemory ? SPT_E_OOM : SPT_E_HIP,             \
+                         std::string(#call) + ": " + hipGetErrorString(e_));            \
+  } while (0)
+
+template <typename T> struct cplx;
+template <> struct cplx<double> { using type = double2; };
+template <> struct cplx<float> { using type = float2; };
+template <typename T> using cplx_t = typename cplx<T>::type;
+
+// FFT radix schedule for one length P (complex points): P = prod(radix[i]).
+struct FftPlan {
+  int P = 1;
+  int npass = 0;
+  int radix[MAX_PASSES] = {};
+  int threads = 64;
+};
+
+FftPlan make_fft_plan(int P);
+
+// ---------------------------------------------------------------- kernel launch API
+// (implemented in the .hip files; all take device pointers and a stream)
+
+template <typename T>
+struct ExecFftArgs {
+  const T* X;         // R x N input (RHS-major)
+  cplx_t<T>* Z;       // R x ldz output half spectrum
+  const T* winv;      // 1/w over the block's L columns
+  const cplx_t<T>* tw;    // P twiddles e^{+2 pi i q/P}
+  const cplx_t<T>* post;  // P+1 twiddles e^{+i pi k/P}
+  int64_t N;
+  int R, L, P, ldz, m_off, c_lo, c_hi;
+  T scale;            // 1/sqrt(L)
+};
+
+template <typename T>
+void launch_exec_fft(const ExecFftArgs<T>& a, const FftPlan& fp, hipStream_t s);
+
+template <typename T>
+struct InvFftArgs {      // transposed execute: half spectrum -> real, /w, keep retained
+  const cplx_t<T>* U;   // R x ldu half spectrum
+  T* Y;                 // R x N output (accumulated: +=) at degrees c + m_off, c in [c_lo, c_hi)
+  const T* winv;
+  const cplx_t<T>* tw;
+  const cplx_t<T>* post;
+  int64_t N;
+  int R, L, P, ldu, m_off, c_lo, c_hi;
+  T scale;
+};
+
+template <typename T>
+void launch_inv_fft(const InvFftArgs<T>& a, const FftPlan& fp, hipStream_t s);
+
+struct RowFftArgs {      // precompute: forward F of windowed rows, float64
+  const double* rows;    // nrows x L
+  double2* spec;         // nrows x (P+1)
+  const double2* tw;
+  const double2* post;
+  int nrows, L, P;
+  double scale;
+};
+void launch_row_fft(const RowFftArgs& a, const FftPlan& fp, hipStream_t s);
+
+// banded product, all blocks + tail, y = sum_i Re(A_i z_i) + B_tail x_tail
+template <typename T>
+struct SpmmArgs {
+  int nblk;
+  int n_tiles;
+  const int32_t* k0[MAX_BLOCKS];
+  const int32_t* kw[MAX_BLOCKS];
+  const int64_t* off[MAX_BLOCKS];
+  const cplx_t<T>* val[MAX_BLOCKS];
+  const cplx_t<T>* z[MAX_BLOCKS];
+  int ldz[MAX_BLOCKS];
+  int tail;
+  const T* tailmat;   // tail x N (column m of the tail is contiguous over rows)
+  const T* X;
+  T* Y;
+  int R;
+  int64_t N;
+};
+
+template <typename T>
+void launch_spmm(const SpmmArgs<T>& a, hipStream_t s);
+void launch_spmm_split_bf16(const SpmmArgs<float>& a, hipStream_t s);
+
+// transposed banded product: u_i = A_i^T f (half spectrum), per block
+template <typename T>
+struct SpmmTArgs {
+  const int32_t* k0;
+  const int32_t* kw;
+  const int64_t* off;
+  const cplx_t<T>* val;
+  cplx_t<T>* u;       // R x ldu, zeroed then accumulated
+  int ldu, P, n_tiles;
+  const T* F;         // R x N
+  int R;
+  int64_t N;
+};
+template <typename T>
+void launch_spmm_transposed(const SpmmTArgs<T>& a, hipStream_t s);
+
+// tail of the transposed product: fhat[:, m] += sum_j A[j, m] f_j, m < tail
+template <typename T>
+void launch_tail_transposed(const T* tailmat, int tail, const T* F, T* Y, int R, int64_t N,
+                            hipStream_t s);
+
+// ---------------------------------------------------------------- precompute kernels
+struct FamilyArgs {
+  int family;
+  int64_t N;
+  int unweighted;
+  const double* x;        // nodes
+  const double* rowscale; // sqrt(lambda_j) (Jacobi family) or NULL
+  const double* ca;       // recurrence coefficient tables (family specific)
+  const double* cb;
+  const double* cc;
+  int ncoef;              // entries in the tables
+  double p0;              // p_0 for the Jacobi family
+};
+
+void launch_nodes(const FamilyArgs& f, const double* diag, const double* off2, double lo,
+                  double hi, double* x_out, hipStream_t s);
+void launch_weights(const FamilyArgs& f, double* rowscale, hipStream_t s);
+// rows [row0, row0+nrows) x degrees [m0, m0+L), times window w (NULL = 1),
+// row-major into out (ld = L)
+void launch_rec_rows(const FamilyArgs& f, int64_t row0, int nrows, int m0, int L,
+                     const double* w, double* out, hipStream_t s);
+// tail matrix: out[m * N + j] = A[j, m], m < t (float64)
+void launch_rec_tail(const FamilyArgs& f, int t, double* out, hipStream_t s);
+
+void launch_maxabs(const double2* spec, int64_t count, unsigned long long* max_bits,
+                   hipStream_t s);
+void launch_extents(const double2* spec, int nrows, int P, double thr, int32_t* klo,
+                    int32_t* khi, int32_t* cnt, hipStream_t s);
+void init_fft_kernels(size_t max_lds);
+void launch_pack(const double2* spec, int64_t row0, int nrows, int64_t N, int P, double thr,
+                 const int32_t* tile_k0, const int32_t* tile_kw, const int64_t* tile_off,
+                 int tile0, double2* val64, float2* val32, hipStream_t s);
+void launch_to_f32(const double* in, float* out, int64_t n, hipStream_t s);
+void launch_nonfinite(const double* p, int64_t n, int* flag, hipStream_t s);
+
+}  // namespace spt

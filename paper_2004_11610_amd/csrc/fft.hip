@@ -1,0 +1,340 @@
+// Batched real <-> half-complex FFTs in LDS for gfx950.
+//
+// A real vector of even length L = 2P is packed as P complex points
+// c_j = v_{2j} + i v_{2j+1}, transformed by a mixed-radix (2, 3, 4, 5, 8)
+// Stockham autosort FFT held entirely in LDS (one workgroup per vector, each
+// pass reads its radix-R butterfly inputs into registers, synchronises, and
+// writes the outputs in place), and unpacked into the half spectrum
+// Z_k, k = 0 .. P, of the length-L DFT (sec. 5.1: real rows and real inputs
+// only need half of the spectrum).
+//
+// Conventions: F of eq. (1) has the kernel exp(-2 pi i jk/L)/sqrt(L) (SIGN -1,
+// used by the precomputation A_e W F); the computation stage applies F*
+// (SIGN +1).  Twiddle tables hold exp(+2 pi i q/P) (q < P) and exp(+i pi k/P)
+// (k <= P); SIGN -1 uses their conjugates.
+
+#include "common.hpp"
+
+namespace spt {
+namespace {
+
+template <typename C>
+__device__ __forceinline__ C cadd(C a, C b) { return C{a.x + b.x, a.y + b.y}; }
+template <typename C>
+__device__ __forceinline__ C csub(C a, C b) { return C{a.x - b.x, a.y - b.y}; }
+template <typename C>
+__device__ __forceinline__ C cmul(C a, C b) {
+  return C{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+// multiply by SIGN * i
+template <int SIGN, typename C>
+__device__ __forceinline__ C mul_si(C a) {
+  return SIGN > 0 ? C{-a.y, a.x} : C{a.y, -a.x};
+}
+
+// In-register DFTs X_k = sum_n x_n exp(SIGN 2 pi i n k / R).
+template <int SIGN, int R, typename C>
+struct Dft;
+
+template <int SIGN, typename C>
+struct Dft<SIGN, 2, C> {
+  __device__ __forceinline__ static void run(C* v) {
+    C a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+  }
+};
+
+template <int SIGN, typename C>
+struct Dft<SIGN, 4, C> {
+  __device__ __forceinline__ static void run(C* v) {
+    C s02 = cadd(v[0], v[2]), d02 = csub(v[0], v[2]);
+    C s13 = cadd(v[1], v[3]), d13 = mul_si<SIGN>(csub(v[1], v[3]));
+    v[0] = cadd(s02, s13);
+    v[2] = csub(s02, s13);
+    v[1] = cadd(d02, d13);
+    v[3] = csub(d02, d13);
+  }
+};
+
+template <int SIGN, typename C>
+struct Dft<SIGN, 8, C> {
+  __device__ __forceinline__ static void run(C* v) {
+    using T = decltype(v[0].x);
+    const T h = T(0.70710678118654752440);  // 1/sqrt(2)
+    C e[4] = {v[0], v[2], v[4], v[6]};
+    C o[4] = {v[1], v[3], v[5], v[7]};
+    Dft<SIGN, 4, C>::run(e);
+    Dft<SIGN, 4, C>::run(o);
+    // o_k *= exp(SIGN i pi k / 4)
+    C o1 = C{h * (o[1].x - SIGN * o[1].y), h * (o[1].y + SIGN * o[1].x)};
+    C o2 = mul_si<SIGN>(o[2]);
+    C o3 = C{h * (-o[3].x - SIGN * o[3].y), h * (-o[3].y + SIGN * o[3].x)};
+    v[0] = cadd(e[0], o[0]);
+    v[4] = csub(e[0], o[0]);
+    v[1] = cadd(e[1], o1);
+    v[5] = csub(e[1], o1);
+    v[2] = cadd(e[2], o2);
+    v[6] = csub(e[2], o2);
+    v[3] = cadd(e[3], o3);
+    v[7] = csub(e[3], o3);
+  }
+};
+
+template <int SIGN, typename C>
+struct Dft<SIGN, 3, C> {
+  __device__ __forceinline__ static void run(C* v) {
+    using T = decltype(v[0].x);
+    const T s3 = T(0.86602540378443864676);  // sqrt(3)/2
+    C t = cadd(v[1], v[2]);
+    C d = csub(v[1], v[2]);
+    C m = C{v[0].x - T(0.5) * t.x, v[0].y - T(0.5) * t.y};
+    C r = mul_si<SIGN>(C{s3 * d.x, s3 * d.y});
+    v[0] = cadd(v[0], t);
+    v[1] = cadd(m, r);
+    v[2] = csub(m, r);
+  }
+};
+
+template <int SIGN, typename C>
+struct Dft<SIGN, 5, C> {
+  __device__ __forceinline__ static void run(C* v) {
+    using T = decltype(v[0].x);
+    const T c1 = T(0.30901699437494742410);   // cos(2 pi/5)
+    const T c2 = T(-0.80901699437494742410);  // cos(4 pi/5)
+    const T s1 = T(0.95105651629515357212);   // sin(2 pi/5)
+    const T s2 = T(0.58778525229247312917);   // sin(4 pi/5)
+    C t1 = cadd(v[1], v[4]), t2 = cadd(v[2], v[3]);
+    C d1 = csub(v[1], v[4]), d2 = csub(v[2], v[3]);
+    C a1 = C{v[0].x + c1 * t1.x + c2 * t2.x, v[0].y + c1 * t1.y + c2 * t2.y};
+    C a2 = C{v[0].x + c2 * t1.x + c1 * t2.x, v[0].y + c2 * t1.y + c1 * t2.y};
+    C b1 = mul_si<SIGN>(C{s1 * d1.x + s2 * d2.x, s1 * d1.y + s2 * d2.y});
+    C b2 = mul_si<SIGN>(C{s2 * d1.x - s1 * d2.x, s2 * d1.y - s1 * d2.y});
+    v[0] = cadd(v[0], cadd(t1, t2));
+    v[1] = cadd(a1, b1);
+    v[4] = csub(a1, b1);
+    v[2] = cadd(a2, b2);
+    v[3] = csub(a2, b2);
+  }
+};
+
+// One Stockham pass of radix R over P points in LDS (in place through
+// registers).  Requires nthreads >= P/16, so each thread owns at most
+// ceil(16/R) butterflies.
+template <int SIGN, int R, typename C>
+__device__ __forceinline__ void stockham_pass(C* lds, int P, int Ns, const C* __restrict__ tw,
+                                              int tid, int nt) {
+  constexpr int MAXB = (16 + R - 1) / R;
+  const int nb = P / R;
+  C v[MAXB][R];
+#pragma unroll
+  for (int b = 0; b < MAXB; ++b) {
+    const int j = tid + b * nt;
+    if (j < nb) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[b][r] = lds[j + r * nb];
+    }
+  }
+  __syncthreads();
+  const int stride = P / (Ns * R);
+#pragma unroll
+  for (int b = 0; b < MAXB; ++b) {
+    const int j = tid + b * nt;
+    if (j < nb) {
+      const int jm = j % Ns;
+      if (Ns > 1) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          C t = tw[jm * r * stride];
+          if (SIGN < 0) t.y = -t.y;
+          v[b][r] = cmul(v[b][r], t);
+        }
+      }
+      Dft<SIGN, R, C>::run(v[b]);
+      const int base = (j - jm) * R + jm;
+#pragma unroll
+      for (int r = 0; r < R; ++r) lds[base + r * Ns] = v[b][r];
+    }
+  }
+  __syncthreads();
+}
+
+template <int SIGN, typename C>
+__device__ void run_fft(C* lds, const FftPlan& fp, const C* __restrict__ tw, int tid, int nt) {
+  int Ns = 1;
+  for (int p = 0; p < fp.npass; ++p) {
+    const int R = fp.radix[p];
+    switch (R) {
+      case 8: stockham_pass<SIGN, 8>(lds, fp.P, Ns, tw, tid, nt); break;
+      case 4: stockham_pass<SIGN, 4>(lds, fp.P, Ns, tw, tid, nt); break;
+      case 2: stockham_pass<SIGN, 2>(lds, fp.P, Ns, tw, tid, nt); break;
+      case 5: stockham_pass<SIGN, 5>(lds, fp.P, Ns, tw, tid, nt); break;
+      default: stockham_pass<SIGN, 3>(lds, fp.P, Ns, tw, tid, nt); break;
+    }
+    Ns *= R;
+  }
+}
+
+// Unpack the packed length-P transform C into the half spectrum of the real
+// length-2P vector: Z_k = E_k + exp(SIGN i pi k/P) O_k, with
+// E_k = (C_k + conj C_{P-k})/2 and O_k = (C_k - conj C_{P-k})/(2i).
+template <int SIGN, typename C, typename T>
+__device__ __forceinline__ C unpack(const C* lds, int P, int k, const C* __restrict__ post,
+                                    T scale) {
+  C ck = lds[k == P ? 0 : k];
+  C cm = lds[k == 0 ? 0 : P - k];
+  cm.y = -cm.y;
+  C e = C{T(0.5) * (ck.x + cm.x), T(0.5) * (ck.y + cm.y)};
+  C d = C{T(0.5) * (ck.x - cm.x), T(0.5) * (ck.y - cm.y)};
+  C o = C{d.y, -d.x};  // d / i
+  C t = post[k];
+  if (SIGN < 0) t.y = -t.y;
+  C z = cadd(e, cmul(t, o));
+  return C{z.x * scale, z.y * scale};
+}
+
+// ---------------------------------------------------------------- execute: E1 + E2
+// One workgroup per right-hand side: v_c = x_{c + m_off} / w_c on the retained
+// columns [c_lo, c_hi), 0 on the extras (eq. Fe1), then Z = F* v (half).
+template <typename T>
+__global__ void exec_fft_kernel(ExecFftArgs<T> a, FftPlan fp) {
+  using C = cplx_t<T>;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C* lds = reinterpret_cast<C*>(smem_raw);
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int r = blockIdx.x;
+  const T* __restrict__ x = a.X + (int64_t)r * a.N;
+  for (int j = tid; j < a.P; j += nt) {
+    const int c0 = 2 * j, c1 = 2 * j + 1;
+    T v0 = (c0 >= a.c_lo && c0 < a.c_hi) ? x[c0 + a.m_off] * a.winv[c0] : T(0);
+    T v1 = (c1 >= a.c_lo && c1 < a.c_hi) ? x[c1 + a.m_off] * a.winv[c1] : T(0);
+    lds[j] = C{v0, v1};
+  }
+  __syncthreads();
+  run_fft<+1>(lds, fp, a.tw, tid, nt);
+  C* __restrict__ z = a.Z + (int64_t)r * a.ldz;
+  for (int k = tid; k <= a.P; k += nt) z[k] = unpack<+1>(lds, a.P, k, a.post, a.scale);
+}
+
+// ---------------------------------------------------------------- transposed: E4
+// One workgroup per right-hand side: half spectrum U (k = 0..P) -> real g of
+// length 2P by F*, then y_{c + m_off} = g_c / w_c on the retained columns only
+// (the extras are discarded, eq. Fe2).
+template <typename T>
+__global__ void inv_fft_kernel(InvFftArgs<T> a, FftPlan fp) {
+  using C = cplx_t<T>;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C* lds = reinterpret_cast<C*>(smem_raw);
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int r = blockIdx.x;
+  const C* __restrict__ u = a.U + (int64_t)r * a.ldu;
+  for (int k = tid; k < a.P; k += nt) {
+    C uk = u[k];
+    C um = u[a.P - k];
+    um.y = -um.y;  // conj U_{P-k}
+    C ge = cadd(uk, um);
+    C go = cmul(csub(uk, um), a.post[k]);
+    lds[k] = C{ge.x - go.y, ge.y + go.x};  // ge + i go
+  }
+  __syncthreads();
+  run_fft<+1>(lds, fp, a.tw, tid, nt);
+  T* __restrict__ y = a.Y + (int64_t)r * a.N;
+  for (int j = tid; j < a.P; j += nt) {
+    const C c = lds[j];
+    const int c0 = 2 * j, c1 = 2 * j + 1;
+    if (c0 >= a.c_lo && c0 < a.c_hi) y[c0 + a.m_off] = c.x * a.scale * a.winv[c0];
+    if (c1 >= a.c_lo && c1 < a.c_hi) y[c1 + a.m_off] = c.y * a.scale * a.winv[c1];
+  }
+}
+
+// ---------------------------------------------------------------- precompute: P5
+// One workgroup per row: F of a windowed row (float64), half spectrum out.
+__global__ void row_fft_kernel(RowFftArgs a, FftPlan fp) {
+  using C = double2;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C* lds = reinterpret_cast<C*>(smem_raw);
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int64_t row = blockIdx.x;
+  const double* __restrict__ v = a.rows + row * a.L;
+  for (int j = tid; j < a.P; j += nt) lds[j] = C{v[2 * j], v[2 * j + 1]};
+  __syncthreads();
+  run_fft<-1>(lds, fp, a.tw, tid, nt);
+  C* __restrict__ s = a.spec + row * (a.P + 1);
+  for (int k = tid; k <= a.P; k += nt) s[k] = unpack<-1>(lds, a.P, k, a.post, a.scale);
+}
+
+template <typename K>
+void set_lds(K kernel, size_t bytes) {
+  SPT_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+}
+
+}  // namespace
+
+// Allow every FFT kernel the whole LDS of a workgroup (once per device; kept
+// out of the launch path so that launches can be captured in graphs).
+void init_fft_kernels(size_t max_lds) {
+  static std::vector<int> done;
+  int dev = 0;
+  SPT_HIP(hipGetDevice(&dev));
+  for (int d : done)
+    if (d == dev) return;
+  set_lds(exec_fft_kernel<double>, max_lds);
+  set_lds(exec_fft_kernel<float>, max_lds);
+  set_lds(inv_fft_kernel<double>, max_lds);
+  set_lds(inv_fft_kernel<float>, max_lds);
+  set_lds(row_fft_kernel, max_lds);
+  done.push_back(dev);
+}
+
+FftPlan make_fft_plan(int P) {
+  FftPlan fp;
+  fp.P = P;
+  int n = P;
+  // radix 8 first (fewest passes), then 4 / 2, then 3 and 5
+  std::vector<int> rad;
+  while (n % 8 == 0) { rad.push_back(8); n /= 8; }
+  while (n % 4 == 0) { rad.push_back(4); n /= 4; }
+  while (n % 2 == 0) { rad.push_back(2); n /= 2; }
+  while (n % 3 == 0) { rad.push_back(3); n /= 3; }
+  while (n % 5 == 0) { rad.push_back(5); n /= 5; }
+  if (n != 1) throw Error(SPT_E_UNSUPPORTED, "FFT length half " + std::to_string(P) +
+                                                 " is not 2^a 3^b 5^c");
+  if ((int)rad.size() > MAX_PASSES) throw Error(SPT_E_UNSUPPORTED, "too many FFT passes");
+  fp.npass = (int)rad.size();
+  for (int i = 0; i < fp.npass; ++i) fp.radix[i] = rad[i];
+  int t = (P + 15) / 16;
+  t = ((t + 63) / 64) * 64;
+  if (t < 64) t = 64;
+  if (t > 1024) throw Error(SPT_E_UNSUPPORTED, "FFT length half " + std::to_string(P) +
+                                                   " exceeds the single-workgroup FFT");
+  fp.threads = t;
+  return fp;
+}
+
+template <typename T>
+void launch_exec_fft(const ExecFftArgs<T>& a, const FftPlan& fp, hipStream_t s) {
+  const size_t lds = sizeof(cplx_t<T>) * (size_t)a.P;
+  hipLaunchKernelGGL(exec_fft_kernel<T>, dim3(a.R), dim3(fp.threads), lds, s, a, fp);
+  SPT_HIP(hipGetLastError());
+}
+
+template <typename T>
+void launch_inv_fft(const InvFftArgs<T>& a, const FftPlan& fp, hipStream_t s) {
+  const size_t lds = sizeof(cplx_t<T>) * (size_t)a.P;
+  hipLaunchKernelGGL(inv_fft_kernel<T>, dim3(a.R), dim3(fp.threads), lds, s, a, fp);
+  SPT_HIP(hipGetLastError());
+}
+
+void launch_row_fft(const RowFftArgs& a, const FftPlan& fp, hipStream_t s) {
+  const size_t lds = sizeof(double2) * (size_t)a.P;
+  hipLaunchKernelGGL(row_fft_kernel, dim3(a.nrows), dim3(fp.threads), lds, s, a, fp);
+  SPT_HIP(hipGetLastError());
+}
+
+template void launch_exec_fft<double>(const ExecFftArgs<double>&, const FftPlan&, hipStream_t);
+template void launch_exec_fft<float>(const ExecFftArgs<float>&, const FftPlan&, hipStream_t);
+template void launch_inv_fft<double>(const InvFftArgs<double>&, const FftPlan&, hipStream_t);
+template void launch_inv_fft<float>(const InvFftArgs<float>&, const FftPlan&, hipStream_t);
+
+}  // namespace spt

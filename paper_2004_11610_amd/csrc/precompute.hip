@@ -1,0 +1,447 @@
+// Precomputation kernels (float64): quadrature nodes and weights, rows of the
+// extended matrix A_e times the window (Alg. 1 step 1.2, sec. 3), the maximum
+// of |A_e W F| and the threshold eps1 * max (Alg. 1 step 1.3), band extents and
+// packing of the kept entries into row tiles.
+
+#include "common.hpp"
+
+namespace spt {
+namespace {
+
+constexpr double LN2 = 0.69314718055994530942;
+// ln 2 = LN2_HI + LN2_LO: LN2_HI = round(2^32 ln 2) / 2^32 has 32 significant
+// bits, so n * LN2_HI is exact for |n| < 2^21; LN2_LO is the rounded remainder.
+constexpr double LN2_HI = 0x1.62e42ff000000p-1;
+constexpr double LN2_LO = -0x1.718432a1b0e26p-35;
+constexpr double BIG = 0x1p500;
+constexpr double RESCALE = 0x1p-500;
+
+// exp(-a) = mant * 2^E, a >= 0, with the Cody-Waite reduction a = E' ln 2 + r
+__device__ __forceinline__ void exp_neg_scaled(double a, double& mant, int& E) {
+  const double n = rint(a * (1.0 / LN2));
+  double r = fma(-n, LN2_HI, a);
+  r = fma(-n, LN2_LO, r);
+  mant = exp(-r);
+  E = -(int)n;
+}
+
+// Recurrence state of one row, advanced one degree at a time.
+struct RowRec {
+  int family;
+  double x, p_prev, p, scale;  // value = p * 2^E * scale
+  int E;
+  int m;                       // degree of p
+  int64_t j, N;                // node index (Chebyshev)
+
+  __device__ void init(const FamilyArgs& f, int64_t jj) {
+    family = f.family;
+    j = jj;
+    N = f.N;
+    x = f.x[jj];
+    m = 0;
+    E = 0;
+    p_prev = 0.0;
+    scale = 1.0;
+    if (family == SPT_LEGENDRE || family == SPT_JACOBI) {
+      p = f.p0;
+      if (f.rowscale) scale = f.rowscale[jj];
+    } else if (family == SPT_LAGUERRE_FN) {
+      exp_neg_scaled(0.5 * x, p, E);
+    } else if (family == SPT_HERMITE_FN) {
+      const double hi = x * x;
+      const double lo = fma(x, x, -hi);
+      exp_neg_scaled(0.5 * hi, p, E);
+      p *= (1.0 - 0.5 * lo) * 0.75112554446494248286;  // pi^{-1/4}
+    } else {
+      p = 1.0;
+    }
+  }
+  // value at degree mm (Chebyshev only: closed form with an exact angle)
+  __device__ double cheb(int64_t mm) const {
+    const int64_t fourN = 4 * N;
+    int64_t q = ((mm % fourN) * ((2 * j + 1) % fourN)) % fourN;
+    if (q < 0) q += fourN;
+    return cospi((double)q / (double)(2 * N));
+  }
+  __device__ double value() const { return ldexp(p, E) * scale; }
+  __device__ void advance(const FamilyArgs& f) {
+    double nxt;
+    if (family == SPT_LEGENDRE || family == SPT_JACOBI) {
+      nxt = ((x - f.cb[m]) * p - f.ca[m] * p_prev) / f.ca[m + 1];
+    } else if (family == SPT_LAGUERRE_FN) {
+      nxt = ((2.0 * m + 1.0 - x) * p - (double)m * p_prev) / (double)(m + 1);
+    } else {  // Hermite functions
+      nxt = f.ca[m] * x * p - f.cb[m] * p_prev;
+    }
+    p_prev = p;
+    p = nxt;
+    ++m;
+    if (fabs(p) > BIG) {
+      p *= RESCALE;
+      p_prev *= RESCALE;
+      E += 500;
+    }
+  }
+};
+
+// ---------------------------------------------------------------- nodes
+// Gauss nodes: bisection with Sturm counts on the symmetric tridiagonal Jacobi
+// matrix (diag d_i, squared off-diagonal e_i^2), then Newton on the degree-N
+// polynomial by its recurrence.  Chebyshev-Gauss nodes in closed form.
+__device__ int sturm_count(const double* __restrict__ d, const double* __restrict__ e2, int64_t n,
+                           double lam, double pivmin) {
+  int cnt = 0;
+  double q = d[0] - lam;
+  if (fabs(q) < pivmin) q = -pivmin;
+  cnt += q < 0.0;
+  for (int64_t i = 1; i < n; ++i) {
+    q = (d[i] - lam) - e2[i] / q;
+    if (fabs(q) < pivmin) q = -pivmin;
+    cnt += q < 0.0;
+  }
+  return cnt;
+}
+
+// (p_N, p_N') up to a common positive factor
+__device__ void poly_and_derivative(const FamilyArgs& f, double x, double& pn, double& dpn) {
+  double p_prev = 0.0, p = 1.0, d_prev = 0.0, d = 0.0;
+  const int64_t N = f.N;
+  if (f.family == SPT_LEGENDRE || f.family == SPT_JACOBI) p = f.p0;
+  for (int64_t m = 0; m < N; ++m) {
+    double pn1, dn1;
+    if (f.family == SPT_LEGENDRE || f.family == SPT_JACOBI) {
+      pn1 = ((x - f.cb[m]) * p - f.ca[m] * p_prev) / f.ca[m + 1];
+      dn1 = ((x - f.cb[m]) * d + p - f.ca[m] * d_prev) / f.ca[m + 1];
+    } else if (f.family == SPT_LAGUERRE_FN) {
+      pn1 = ((2.0 * m + 1.0 - x) * p - (double)m * p_prev) / (double)(m + 1);
+      dn1 = ((2.0 * m + 1.0 - x) * d - p - (double)m * d_prev) / (double)(m + 1);
+    } else {
+      pn1 = f.ca[m] * x * p - f.cb[m] * p_prev;
+      dn1 = f.ca[m] * (p + x * d) - f.cb[m] * d_prev;
+    }
+    p_prev = p;
+    p = pn1;
+    d_prev = d;
+    d = dn1;
+    if (fmax(fabs(p), fabs(d)) > BIG) {
+      p *= RESCALE;
+      p_prev *= RESCALE;
+      d *= RESCALE;
+      d_prev *= RESCALE;
+    }
+  }
+  pn = p;
+  dpn = d;
+}
+
+// double-double helpers (error-free transformations with fma)
+struct DD {
+  double hi, lo;
+};
+__device__ __forceinline__ DD dd_norm(double hi, double lo) {
+  const double s = hi + lo;
+  return DD{s, lo - (s - hi)};
+}
+__device__ __forceinline__ DD two_sum(double a, double b) {
+  const double s = a + b;
+  const double bb = s - a;
+  return DD{s, (a - (s - bb)) + (b - bb)};
+}
+__device__ __forceinline__ DD dd_mul(DD a, DD b) {
+  const double p = a.hi * b.hi;
+  const double e = fma(a.hi, b.hi, -p);
+  return dd_norm(p, e + (a.hi * b.lo + a.lo * b.hi));
+}
+__device__ __forceinline__ DD dd_sub(DD a, DD b) {
+  const DD s = two_sum(a.hi, -b.hi);
+  return dd_norm(s.hi, s.lo + (a.lo - b.lo));
+}
+__device__ __forceinline__ DD dd_div(DD a, double d) {
+  const double q = a.hi / d;
+  const double p = q * d;
+  const double e = fma(q, d, -p);
+  return dd_norm(q, ((a.hi - p) - e + a.lo) / d);
+}
+
+// One Newton correction for a Laguerre root with L_N, L_N' in double-double:
+// near x = 0 the float64 recurrence loses ~k^2 eps (double characteristic root).
+__device__ double laguerre_dd_newton(int64_t N, double x) {
+  DD Lp{0.0, 0.0}, L{1.0, 0.0}, dp{0.0, 0.0}, d{0.0, 0.0};
+  for (int64_t m = 0; m < N; ++m) {
+    const DD c = two_sum(2.0 * (double)m + 1.0, -x);
+    const DD mm{(double)m, 0.0};
+    const DD Ln = dd_div(dd_sub(dd_mul(c, L), dd_mul(mm, Lp)), (double)(m + 1));
+    const DD dn = dd_div(dd_sub(dd_sub(dd_mul(c, d), L), dd_mul(mm, dp)), (double)(m + 1));
+    Lp = L;
+    L = Ln;
+    dp = d;
+    d = dn;
+    if (fmax(fabs(L.hi), fabs(d.hi)) > BIG) {
+      Lp = DD{Lp.hi * RESCALE, Lp.lo * RESCALE};
+      L = DD{L.hi * RESCALE, L.lo * RESCALE};
+      dp = DD{dp.hi * RESCALE, dp.lo * RESCALE};
+      d = DD{d.hi * RESCALE, d.lo * RESCALE};
+    }
+  }
+  return x - (L.hi + L.lo) / (d.hi + d.lo);
+}
+
+__global__ void nodes_kernel(FamilyArgs f, const double* __restrict__ diag,
+                             const double* __restrict__ off2, double lo0, double hi0,
+                             double* __restrict__ x_out) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t N = f.N;
+  if (j >= N) return;
+  if (f.family == SPT_CHEBYSHEV_T) {
+    x_out[j] = cospi((double)(2 * j + 1) / (double)(2 * N));
+    return;
+  }
+  // the Jacobi family is stored with x descending, the others ascending
+  const int64_t k = (f.family == SPT_LEGENDRE || f.family == SPT_JACOBI) ? N - 1 - j : j;
+  const double eps = 2.220446049250313e-16;
+  const double pivmin = 1e-290;
+  double lo = lo0, hi = hi0;
+  for (int it = 0; it < 200; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (!(mid > lo && mid < hi)) break;
+    if (hi - lo <= 2.0 * eps * fmax(fabs(lo), fabs(hi))) break;
+    if (sturm_count(diag, off2, N, mid, pivmin) > k) hi = mid;
+    else lo = mid;
+  }
+  double x = 0.5 * (lo + hi);
+  for (int it = 0; it < 8; ++it) {
+    double pn, dpn;
+    poly_and_derivative(f, x, pn, dpn);
+    const double dx = pn / dpn;
+    x -= dx;
+    if (fabs(dx) <= 4.0 * eps * fabs(x)) break;
+  }
+  if (f.family == SPT_LAGUERRE_FN) x = laguerre_dd_newton(N, x);
+  x_out[j] = x;
+}
+
+// Christoffel weights of the orthonormal Jacobi system: scale_j = lambda_j^{1/2}
+// = (sum_{m<N} p_m(x_j)^2)^{-1/2}
+__global__ void weights_kernel(FamilyArgs f, double* __restrict__ rowscale) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= f.N) return;
+  FamilyArgs g = f;
+  g.rowscale = nullptr;
+  RowRec rec;
+  rec.init(g, j);
+  double s = 0.0;
+  for (int64_t m = 0; m < f.N; ++m) {
+    const double v = rec.value();
+    s += v * v;
+    if (m + 1 < f.N) rec.advance(g);
+  }
+  rowscale[j] = 1.0 / sqrt(s);
+}
+
+// ---------------------------------------------------------------- panels of A_e W
+// One wave per 64 rows, lane = row; 64-column chunks go through an LDS tile so
+// that each row's columns are written contiguously.
+__global__ __launch_bounds__(64) void rec_rows_kernel(FamilyArgs f, int64_t row0, int nrows,
+                                                      int m0, int L, const double* __restrict__ w,
+                                                      double* __restrict__ out) {
+  __shared__ double tile[64][65];
+  const int lane = threadIdx.x;
+  const int lr = blockIdx.x * 64 + lane;  // local row
+  const int64_t j = row0 + lr;
+  const bool active = lr < nrows && j < f.N;
+  RowRec rec;
+  rec.init(f, active ? j : 0);
+  const bool cheb = f.family == SPT_CHEBYSHEV_T;
+  // one-sided blocks start at degree 0 > m0 never happens; m0 < 0 only for Chebyshev
+  for (int c0 = 0; c0 < L; c0 += 64) {
+    for (int cc = 0; cc < 64; ++cc) {
+      const int c = c0 + cc;
+      double v = 0.0;
+      if (c < L) {
+        if (cheb) {
+          v = rec.cheb((int64_t)m0 + c);
+        } else {
+          v = rec.value();
+          if (c + 1 < L) rec.advance(f);
+        }
+        if (w) v *= w[c];
+      }
+      tile[lane][cc] = active ? v : 0.0;
+    }
+    __syncthreads();
+    const int ncols = min(64, L - c0);
+    for (int rr = 0; rr < 64; ++rr) {
+      const int lr2 = blockIdx.x * 64 + rr;
+      if (lr2 < nrows && lane < ncols) out[(int64_t)lr2 * L + c0 + lane] = tile[rr][lane];
+    }
+    __syncthreads();
+  }
+}
+
+// tail[m * ldt + j] = A[j, m] for m < t; rows j >= N are zero
+__global__ void rec_tail_kernel(FamilyArgs f, int t, int64_t ldt, double* __restrict__ out) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= ldt) return;
+  if (j >= f.N) {
+    for (int m = 0; m < t; ++m) out[(int64_t)m * ldt + j] = 0.0;
+    return;
+  }
+  RowRec rec;
+  rec.init(f, j);
+  for (int m = 0; m < t; ++m) {
+    out[(int64_t)m * ldt + j] = f.family == SPT_CHEBYSHEV_T ? rec.cheb(m) : rec.value();
+    if (f.family != SPT_CHEBYSHEV_T && m + 1 < t) rec.advance(f);
+  }
+}
+
+// ---------------------------------------------------------------- threshold
+__global__ void maxabs_kernel(const double2* __restrict__ s, int64_t n,
+                              unsigned long long* __restrict__ max_bits) {
+  double mx = 0.0;
+  bool bad = false;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const double2 v = s[i];
+    const double a = v.x * v.x + v.y * v.y;
+    bad |= !isfinite(a);
+    mx = fmax(mx, a);
+  }
+  for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o));
+  const unsigned long long anybad = __any(bad);
+  if ((threadIdx.x & 63) == 0) {
+    // non-negative doubles order like their bit patterns; a non-finite value
+    // is reported as +inf
+    const unsigned long long bits =
+        anybad ? 0x7FF0000000000000ull : (unsigned long long)__double_as_longlong(mx);
+    atomicMax(max_bits, bits);
+  }
+}
+
+// per row: first and last half-spectrum index with |a| > thr, and the count
+__global__ __launch_bounds__(256) void extents_kernel(const double2* __restrict__ s, int nrows,
+                                                      int P, double thr, int32_t* __restrict__ klo,
+                                                      int32_t* __restrict__ khi,
+                                                      int32_t* __restrict__ cnt) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int row = blockIdx.x * 4 + wave;
+  if (row >= nrows) return;
+  const double2* __restrict__ r = s + (int64_t)row * (P + 1);
+  int lo = 0x7FFFFFFF, hi = -1, n = 0;
+  for (int k = lane; k <= P; k += 64) {
+    const double2 v = r[k];
+    if (sqrt(v.x * v.x + v.y * v.y) > thr) {
+      lo = min(lo, k);
+      hi = max(hi, k);
+      ++n;
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    lo = min(lo, __shfl_xor(lo, o));
+    hi = max(hi, __shfl_xor(hi, o));
+    n += __shfl_xor(n, o);
+  }
+  if (lane == 0) {
+    klo[row] = hi < 0 ? -1 : lo;
+    khi[row] = hi;
+    cnt[row] = n;
+  }
+}
+
+// kept entries times c_k into the tile boxes; thread = (tile, kk, q)
+__global__ __launch_bounds__(256) void pack_kernel(const double2* __restrict__ s, int64_t row0,
+                                                   int nrows, int64_t N, int P, double thr,
+                                                   const int32_t* __restrict__ tk0,
+                                                   const int32_t* __restrict__ tkw,
+                                                   const int64_t* __restrict__ toff, int tile0,
+                                                   double2* __restrict__ v64,
+                                                   float2* __restrict__ v32) {
+  const int t = tile0 + blockIdx.x;  // global tile index
+  const int k0 = tk0[t], kw = tkw[t];
+  const int64_t off = toff[t];
+  for (int e = threadIdx.x; e < kw * TILE_ROWS; e += blockDim.x) {
+    const int kk = e / TILE_ROWS, q = e % TILE_ROWS;
+    const int64_t n = (int64_t)t * TILE_ROWS + q;
+    const int64_t lr = n - row0;
+    double2 v = double2{0.0, 0.0};
+    if (n < N && lr >= 0 && lr < nrows) {
+      const int k = k0 + kk;
+      const double2 a = s[lr * (P + 1) + k];
+      if (sqrt(a.x * a.x + a.y * a.y) > thr) {
+        const double ck = (k == 0 || k == P) ? 1.0 : 2.0;
+        v = double2{a.x * ck, a.y * ck};
+      }
+    }
+    if (v64) v64[off + e] = v;
+    if (v32) v32[off + e] = float2{(float)v.x, (float)v.y};
+  }
+}
+
+__global__ void to_f32_kernel(const double* __restrict__ in, float* __restrict__ out, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = (float)in[i];
+}
+
+int blocks_for(int64_t n, int threads) {
+  int64_t b = (n + threads - 1) / threads;
+  return (int)std::min<int64_t>(std::max<int64_t>(b, 1), 65535 * 16);
+}
+
+}  // namespace
+
+void launch_nodes(const FamilyArgs& f, const double* diag, const double* off2, double lo,
+                  double hi, double* x_out, hipStream_t s) {
+  hipLaunchKernelGGL(nodes_kernel, dim3(blocks_for(f.N, 64)), dim3(64), 0, s, f, diag, off2, lo,
+                     hi, x_out);
+  SPT_HIP(hipGetLastError());
+}
+
+void launch_weights(const FamilyArgs& f, double* rowscale, hipStream_t s) {
+  hipLaunchKernelGGL(weights_kernel, dim3(blocks_for(f.N, 64)), dim3(64), 0, s, f, rowscale);
+  SPT_HIP(hipGetLastError());
+}
+
+void launch_rec_rows(const FamilyArgs& f, int64_t row0, int nrows, int m0, int L,
+                     const double* w, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(rec_rows_kernel, dim3((nrows + 63) / 64), dim3(64), 0, s, f, row0, nrows,
+                     m0, L, w, out);
+  SPT_HIP(hipGetLastError());
+}
+
+void launch_rec_tail(const FamilyArgs& f, int t, double* out, hipStream_t s) {
+  const int64_t ldt = ((f.N + TILE_ROWS - 1) / TILE_ROWS) * TILE_ROWS;
+  hipLaunchKernelGGL(rec_tail_kernel, dim3(blocks_for(ldt, 64)), dim3(64), 0, s, f, t, ldt,
+                     out);
+  SPT_HIP(hipGetLastError());
+}
+
+void launch_maxabs(const double2* spec, int64_t count, unsigned long long* max_bits,
+                   hipStream_t s) {
+  const int blocks = (int)std::min<int64_t>((count + 255) / 256, 4096);
+  hipLaunchKernelGGL(maxabs_kernel, dim3(std::max(blocks, 1)), dim3(256), 0, s, spec, count,
+                     max_bits);
+  SPT_HIP(hipGetLastError());
+}
+
+void launch_extents(const double2* spec, int nrows, int P, double thr, int32_t* klo,
+                    int32_t* khi, int32_t* cnt, hipStream_t s) {
+  hipLaunchKernelGGL(extents_kernel, dim3((nrows + 3) / 4), dim3(256), 0, s, spec, nrows, P,
+                     thr, klo, khi, cnt);
+  SPT_HIP(hipGetLastError());
+}
+
+void launch_pack(const double2* spec, int64_t row0, int nrows, int64_t N, int P, double thr,
+                 const int32_t* tile_k0, const int32_t* tile_kw, const int64_t* tile_off,
+                 int tile0, double2* val64, float2* val32, hipStream_t s) {
+  const int ntile = (nrows + TILE_ROWS - 1) / TILE_ROWS;
+  hipLaunchKernelGGL(pack_kernel, dim3(ntile), dim3(256), 0, s, spec, row0, nrows, N, P, thr,
+                     tile_k0, tile_kw, tile_off, tile0, val64, val32);
+  SPT_HIP(hipGetLastError());
+}
+
+void launch_to_f32(const double* in, float* out, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(to_f32_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, in, out, n);
+  SPT_HIP(hipGetLastError());
+}
+
+}  // namespace spt
