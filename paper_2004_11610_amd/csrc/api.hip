@@ -64,7 +64,7 @@ struct DevBlock {
   BlockGeom g;
   int P = 0;
   FftPlan fft;
-  DevBuf winv64, winv32, tw64, tw32, post64, post32;
+  DevBuf winv64, winv32, tw64, post64, post32;
   DevBuf k0, kw, off;   // per tile
   DevBuf val64, val32;  // tile boxes
   int64_t nnz = 0, stored = 0;
@@ -100,6 +100,10 @@ struct spt_plan {
   std::vector<std::unique_ptr<spt::DevBlock>> blk;
   spt::DevBuf tail64, tail32;
   spt::DevBuf work;  // execute workspace (half spectra)
+  spt::DevBuf fftdesc64, fftdesc32;  // FftDesc per block for the fused FFT launch
+  spt::DevBuf tilemeta;              // TileMeta per (tile, block)
+  spt::DevBuf spmmblk64, spmmblk32;  // SpmmBlock per block
+  int fft_threads = 64, fft_maxP = 1;
   int64_t work_rhs = 0;
 };
 
@@ -214,16 +218,24 @@ std::vector<C> to_vec2(const std::vector<long double>& re, const std::vector<lon
   return out;
 }
 
-// exp(+2 pi i q / P), q < P, and exp(+i pi k / P), k <= P, in long double
+// Pass twiddles as two tables (exp(+2 pi i q/P), q < 128, then
+// exp(+2 pi i 128 q/P), q <= P/128) and the unpack twiddles exp(+i pi k/P),
+// k <= P, in long double
 void twiddles(int P, std::vector<long double>& twr, std::vector<long double>& twi,
               std::vector<long double>& por, std::vector<long double>& poi) {
   const long double pi = 3.141592653589793238462643383279502884L;
-  twr.resize(P);
-  twi.resize(P);
-  for (int q = 0; q < P; ++q) {
+  const int lo = 128, nhi = P / lo + 1;
+  twr.resize(lo + nhi);
+  twi.resize(lo + nhi);
+  for (int q = 0; q < lo; ++q) {
     const long double a = 2.0L * pi * (long double)q / (long double)P;
     twr[q] = cosl(a);
     twi[q] = sinl(a);
+  }
+  for (int q = 0; q < nhi; ++q) {
+    const long double a = 2.0L * pi * (long double)(q * lo) / (long double)P;
+    twr[lo + q] = cosl(a);
+    twi[lo + q] = sinl(a);
   }
   por.resize(P + 1);
   poi.resize(P + 1);
@@ -268,7 +280,6 @@ void build_block(spt_plan_t plan, DevBlock& B, hipStream_t s, size_t lds_max) {
   std::vector<long double> twr, twi, por, poi;
   twiddles(P, twr, twi, por, poi);
   upload(B.tw64, to_vec2<double2, double>(twr, twi), s);
-  upload(B.tw32, to_vec2<float2, float>(twr, twi), s);
   upload(B.post64, to_vec2<double2, double>(por, poi), s);
   upload(B.post32, to_vec2<float2, float>(por, poi), s);
 
@@ -398,6 +409,60 @@ void build_tail(spt_plan_t plan, hipStream_t s) {
   SPT_HIP(hipStreamSynchronize(s));
 }
 
+template <typename T>
+std::vector<FftDesc<T>> fft_descs(spt_plan_t plan) {
+  using C = cplx_t<T>;
+  const bool dbl = std::is_same<T, double>::value;
+  std::vector<FftDesc<T>> d;
+  int64_t zoff = 0;
+  for (auto& Bp : plan->blk) {
+    DevBlock& B = *Bp;
+    FftDesc<T> e{};
+    e.winv = (const T*)(dbl ? B.winv64.p : B.winv32.p);
+    e.tw = B.tw64.as<double2>();
+    e.post = (const C*)(dbl ? B.post64.p : B.post32.p);
+    e.zoff = zoff;
+    e.fp = B.fft;
+    e.L = B.g.L;
+    e.m_off = B.g.m_off;
+    e.c_lo = B.g.c_lo;
+    e.c_hi = B.g.c_hi;
+    e.ldz = B.P + 1;
+    e.scale = (T)(1.0 / std::sqrt((double)B.g.L));
+    d.push_back(e);
+    zoff += B.P + 1;
+  }
+  return d;
+}
+
+void build_fft_descs(spt_plan_t plan, hipStream_t s) {
+  plan->fft_threads = 64;
+  plan->fft_maxP = 1;
+  for (auto& B : plan->blk) {
+    plan->fft_threads = std::max(plan->fft_threads, B->fft.threads);
+    plan->fft_maxP = std::max(plan->fft_maxP, B->P);
+  }
+  upload(plan->fftdesc64, fft_descs<double>(plan), s);
+  upload(plan->fftdesc32, fft_descs<float>(plan), s);
+  // banded product tables: tile boxes of every block, tile-major
+  const int nblk = (int)plan->blk.size();
+  std::vector<TileMeta> meta((size_t)plan->n_tiles * std::max(nblk, 1));
+  std::vector<SpmmBlock<double>> b64;
+  std::vector<SpmmBlock<float>> b32;
+  int64_t zoff = 0;
+  for (int b = 0; b < nblk; ++b) {
+    const DevBlock& B = *plan->blk[b];
+    for (int t = 0; t < plan->n_tiles; ++t)
+      meta[(size_t)t * nblk + b] = TileMeta{B.h_k0[t], B.h_kw[t], B.h_off[t]};
+    b64.push_back(SpmmBlock<double>{B.val64.as<double2>(), zoff, B.P + 1, 0});
+    b32.push_back(SpmmBlock<float>{B.val32.as<float2>(), zoff, B.P + 1, 0});
+    zoff += B.P + 1;
+  }
+  upload(plan->tilemeta, meta, s);
+  upload(plan->spmmblk64, b64, s);
+  upload(plan->spmmblk32, b32, s);
+}
+
 void precompute(spt_plan_t plan, hipStream_t s) {
   set_device(plan);
   const size_t lds_max = max_lds_bytes(plan->device);
@@ -436,6 +501,7 @@ void precompute(spt_plan_t plan, hipStream_t s) {
   }
   if (plan->mode == SPT_MODE_DIRECT) plan->tail = plan->N;
   build_tail(plan, s);
+  build_fft_descs(plan, s);
   plan->precomputed = true;
 }
 
@@ -472,43 +538,24 @@ void execute_t(spt_plan_t plan, const T* X, T* Y, int64_t R, int prec, hipStream
   SpmmArgs<T> sa{};
   sa.nblk = (int)plan->blk.size();
   sa.n_tiles = plan->n_tiles;
-  C* z = plan->work.as<C>();
-  std::vector<ExecFftArgs<T>> ffts;
-  for (int i = 0; i < sa.nblk; ++i) {
-    DevBlock& B = *plan->blk[i];
-    ExecFftArgs<T> fa{};
-    fa.X = X;
-    fa.Z = z;
-    fa.winv = std::is_same<T, double>::value ? (const T*)B.winv64.p : (const T*)B.winv32.p;
-    fa.tw = std::is_same<T, double>::value ? (const C*)B.tw64.p : (const C*)B.tw32.p;
-    fa.post = std::is_same<T, double>::value ? (const C*)B.post64.p : (const C*)B.post32.p;
-    fa.N = plan->N;
-    fa.R = (int)R;
-    fa.L = B.g.L;
-    fa.P = B.P;
-    fa.ldz = B.P + 1;
-    fa.m_off = B.g.m_off;
-    fa.c_lo = B.g.c_lo;
-    fa.c_hi = B.g.c_hi;
-    fa.scale = (T)(1.0 / std::sqrt((double)B.g.L));
-    ffts.push_back(fa);
-    sa.k0[i] = B.k0.as<int32_t>();
-    sa.kw[i] = B.kw.as<int32_t>();
-    sa.off[i] = B.off.as<int64_t>();
-    sa.val[i] = std::is_same<T, double>::value ? (const C*)B.val64.p : (const C*)B.val32.p;
-    sa.z[i] = z;
-    sa.ldz[i] = B.P + 1;
-    z += (size_t)R * (B.P + 1);
-  }
+  sa.meta = plan->tilemeta.as<TileMeta>();
+  sa.blocks = std::is_same<T, double>::value ? (const SpmmBlock<T>*)plan->spmmblk64.p
+                                             : (const SpmmBlock<T>*)plan->spmmblk32.p;
+  C* const z0 = plan->work.as<C>();
+  sa.Z = z0;
   sa.tail = (int)plan->tail;
   sa.tailmat = std::is_same<T, double>::value ? (const T*)plan->tail64.p : (const T*)plan->tail32.p;
   sa.X = X;
   sa.Y = Y;
   sa.R = (int)R;
   sa.N = plan->N;
-  if (!ffts.empty())
+  if (sa.nblk > 0)
     staged(SPT_STAGE_FFT, s, [&] {
-      for (int i = 0; i < sa.nblk; ++i) launch_exec_fft<T>(ffts[i], plan->blk[i]->fft, s);
+      const FftDesc<T>* d = std::is_same<T, double>::value
+                                ? (const FftDesc<T>*)plan->fftdesc64.p
+                                : (const FftDesc<T>*)plan->fftdesc32.p;
+      launch_exec_fft_multi<T>(d, sa.nblk, plan->fft_threads, plan->fft_maxP, X, z0, (int)R,
+                               plan->N, s);
     });
   staged(SPT_STAGE_SPMM, s, [&] {
     if constexpr (std::is_same<T, float>::value) {
@@ -560,7 +607,7 @@ void execute_transposed_t(spt_plan_t plan, const T* F, T* Y, int64_t R, hipStrea
     ia.U = u;
     ia.Y = Y;
     ia.winv = std::is_same<T, double>::value ? (const T*)B.winv64.p : (const T*)B.winv32.p;
-    ia.tw = std::is_same<T, double>::value ? (const C*)B.tw64.p : (const C*)B.tw32.p;
+    ia.tw = B.tw64.as<double2>();
     ia.post = std::is_same<T, double>::value ? (const C*)B.post64.p : (const C*)B.post32.p;
     ia.N = plan->N;
     ia.R = (int)R;

@@ -17,10 +17,12 @@ namespace spt {
 // tiles of TILE_ROWS consecutive nodes, so that one workgroup owns the same
 // output rows in every block and sums the blocks in registers.
 constexpr int TILE_ROWS = 16;
+// Tiles per workgroup of the banded product (one wave per tile).
+constexpr int SPMM_GROUP = 4;
 // Largest number of blocks a plan may have (the recursion stops long before).
 constexpr int MAX_BLOCKS = 24;
 // Largest FFT radix pass count.
-constexpr int MAX_PASSES = 24;
+constexpr int MAX_PASSES = 16;
 
 struct Error : std::runtime_error {
   spt_status code;
@@ -58,7 +60,7 @@ struct ExecFftArgs {
   const T* X;         // R x N input (RHS-major)
   cplx_t<T>* Z;       // R x ldz output half spectrum
   const T* winv;      // 1/w over the block's L columns
-  const cplx_t<T>* tw;    // P twiddles e^{+2 pi i q/P}
+  const double2* tw;      // P twiddles e^{+2 pi i q/P} (float64 for every precision)
   const cplx_t<T>* post;  // P+1 twiddles e^{+i pi k/P}
   int64_t N;
   int R, L, P, ldz, m_off, c_lo, c_hi;
@@ -68,12 +70,29 @@ struct ExecFftArgs {
 template <typename T>
 void launch_exec_fft(const ExecFftArgs<T>& a, const FftPlan& fp, hipStream_t s);
 
+// One block of the fused x-side FFT launch (all blocks of a plan, all
+// right-hand sides in one grid); lives in device memory.
+template <typename T>
+struct FftDesc {
+  const T* winv;
+  const double2* tw;
+  const cplx_t<T>* post;
+  int64_t zoff;  // block spectra start at Z + R * zoff; right-hand side r at + r * ldz
+  FftPlan fp;
+  int L, m_off, c_lo, c_hi, ldz;
+  T scale;
+};
+
+template <typename T>
+void launch_exec_fft_multi(const FftDesc<T>* descs, int nblk, int threads, int max_P,
+                           const T* X, cplx_t<T>* Z, int R, int64_t N, hipStream_t s);
+
 template <typename T>
 struct InvFftArgs {      // transposed execute: half spectrum -> real, /w, keep retained
   const cplx_t<T>* U;   // R x ldu half spectrum
   T* Y;                 // R x N output (accumulated: +=) at degrees c + m_off, c in [c_lo, c_hi)
   const T* winv;
-  const cplx_t<T>* tw;
+  const double2* tw;
   const cplx_t<T>* post;
   int64_t N;
   int R, L, P, ldu, m_off, c_lo, c_hi;
@@ -94,18 +113,26 @@ struct RowFftArgs {      // precompute: forward F of windowed rows, float64
 void launch_row_fft(const RowFftArgs& a, const FftPlan& fp, hipStream_t s);
 
 // banded product, all blocks + tail, y = sum_i Re(A_i z_i) + B_tail x_tail
+struct TileMeta {      // one (tile, block): box columns k0 .. k0+kw-1 at val + off
+  int32_t k0, kw;
+  int64_t off;
+};
+template <typename T>
+struct SpmmBlock {     // one block: its tile boxes and where its half spectra live
+  const cplx_t<T>* val;
+  int64_t zoff;        // spectra of the block start at Z + R * zoff
+  int32_t ldz;         // P + 1
+  int32_t pad;
+};
 template <typename T>
 struct SpmmArgs {
+  const TileMeta* meta;        // n_tiles x nblk, tile-major
+  const SpmmBlock<T>* blocks;  // nblk
   int nblk;
   int n_tiles;
-  const int32_t* k0[MAX_BLOCKS];
-  const int32_t* kw[MAX_BLOCKS];
-  const int64_t* off[MAX_BLOCKS];
-  const cplx_t<T>* val[MAX_BLOCKS];
-  const cplx_t<T>* z[MAX_BLOCKS];
-  int ldz[MAX_BLOCKS];
+  const cplx_t<T>* Z;          // half spectra written by the FFT stage
   int tail;
-  const T* tailmat;   // tail x N (column m of the tail is contiguous over rows)
+  const T* tailmat;   // tail x (n_tiles * TILE_ROWS): column m of the tail over rows
   const T* X;
   T* Y;
   int R;

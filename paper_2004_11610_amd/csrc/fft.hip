@@ -10,8 +10,11 @@
 //
 // Conventions: F of eq. (1) has the kernel exp(-2 pi i jk/L)/sqrt(L) (SIGN -1,
 // used by the precomputation A_e W F); the computation stage applies F*
-// (SIGN +1).  Twiddle tables hold exp(+2 pi i q/P) (q < P) and exp(+i pi k/P)
-// (k <= P); SIGN -1 uses their conjugates.
+// (SIGN +1).  The pass twiddles exp(+2 pi i q/P) come from two float64 tables
+// of 128 + P/128 entries (w^q = lo[q % 128] hi[q / 128]; a butterfly forms w^jm
+// once and its powers in float64, for every precision); the unpack twiddles
+// exp(+i pi k/P) (k <= P) are a table in the working precision.  SIGN -1 uses
+// their conjugates.
 
 #include "common.hpp"
 
@@ -121,16 +124,27 @@ struct Dft<SIGN, 5, C> {
 // One Stockham pass of radix R over P points in LDS (in place through
 // registers).  Requires nthreads >= P/16, so each thread owns at most
 // ceil(16/R) butterflies.
+// two-level twiddle table of a length P: tw[i] = exp(2 pi i i / P) for
+// i < TW_LO, tw[TW_LO + i] = exp(2 pi i TW_LO i / P) for i <= P / TW_LO
+constexpr int TW_LO_BITS = 7;
+constexpr int TW_LO = 1 << TW_LO_BITS;
+
+template <typename C>
+__device__ __forceinline__ C to_c(double2 t) {
+  using T = decltype(C{}.x);
+  return C{(T)t.x, (T)t.y};
+}
+
 template <int SIGN, int R, typename C>
-__device__ __forceinline__ void stockham_pass(C* lds, int P, int Ns, const C* __restrict__ tw,
-                                              int tid, int nt) {
+__device__ __forceinline__ void stockham_pass(C* lds, int P, int Ns, const double2* __restrict__ tw,
+                                              int tid, int nt, bool active) {
   constexpr int MAXB = (16 + R - 1) / R;
   const int nb = P / R;
   C v[MAXB][R];
 #pragma unroll
   for (int b = 0; b < MAXB; ++b) {
     const int j = tid + b * nt;
-    if (j < nb) {
+    if (active && j < nb) {
 #pragma unroll
       for (int r = 0; r < R; ++r) v[b][r] = lds[j + r * nb];
     }
@@ -140,14 +154,19 @@ __device__ __forceinline__ void stockham_pass(C* lds, int P, int Ns, const C* __
 #pragma unroll
   for (int b = 0; b < MAXB; ++b) {
     const int j = tid + b * nt;
-    if (j < nb) {
+    if (active && j < nb) {
       const int jm = j % Ns;
       if (Ns > 1) {
+        // w^(jm r) = (w^jm)^r; w^q = lo[q % 128] hi[q / 128] from the two
+        // small float64 tables (they stay in L1), powers in float64
+        const int q = jm * stride;
+        double2 t1 = cmul(tw[q & (TW_LO - 1)], tw[TW_LO + (q >> TW_LO_BITS)]);
+        if (SIGN < 0) t1.y = -t1.y;
+        double2 t = t1;
 #pragma unroll
         for (int r = 1; r < R; ++r) {
-          C t = tw[jm * r * stride];
-          if (SIGN < 0) t.y = -t.y;
-          v[b][r] = cmul(v[b][r], t);
+          v[b][r] = cmul(v[b][r], to_c<C>(t));
+          if (r + 1 < R) t = cmul(t, t1);
         }
       }
       Dft<SIGN, R, C>::run(v[b]);
@@ -159,45 +178,63 @@ __device__ __forceinline__ void stockham_pass(C* lds, int P, int Ns, const C* __
   __syncthreads();
 }
 
+// all passes; threads with active == false only take part in the barriers
 template <int SIGN, typename C>
-__device__ void run_fft(C* lds, const FftPlan& fp, const C* __restrict__ tw, int tid, int nt) {
+__device__ void run_fft(C* lds, int P, int npass, const int* radix,
+                        const double2* __restrict__ tw, int tid, int nt, bool active) {
   int Ns = 1;
-  for (int p = 0; p < fp.npass; ++p) {
-    const int R = fp.radix[p];
+  for (int p = 0; p < npass; ++p) {
+    const int R = radix[p];
     switch (R) {
-      case 8: stockham_pass<SIGN, 8>(lds, fp.P, Ns, tw, tid, nt); break;
-      case 4: stockham_pass<SIGN, 4>(lds, fp.P, Ns, tw, tid, nt); break;
-      case 2: stockham_pass<SIGN, 2>(lds, fp.P, Ns, tw, tid, nt); break;
-      case 5: stockham_pass<SIGN, 5>(lds, fp.P, Ns, tw, tid, nt); break;
-      default: stockham_pass<SIGN, 3>(lds, fp.P, Ns, tw, tid, nt); break;
+      case 8: stockham_pass<SIGN, 8>(lds, P, Ns, tw, tid, nt, active); break;
+      case 4: stockham_pass<SIGN, 4>(lds, P, Ns, tw, tid, nt, active); break;
+      case 2: stockham_pass<SIGN, 2>(lds, P, Ns, tw, tid, nt, active); break;
+      case 5: stockham_pass<SIGN, 5>(lds, P, Ns, tw, tid, nt, active); break;
+      default: stockham_pass<SIGN, 3>(lds, P, Ns, tw, tid, nt, active); break;
     }
     Ns *= R;
   }
 }
 
+template <int SIGN, typename C>
+__device__ __forceinline__ void run_fft(C* lds, const FftPlan& fp, const double2* __restrict__ tw,
+                                        int tid, int nt) {
+  run_fft<SIGN>(lds, fp.P, fp.npass, fp.radix, tw, tid, nt, true);
+}
+
 // Unpack the packed length-P transform C into the half spectrum of the real
 // length-2P vector: Z_k = E_k + exp(SIGN i pi k/P) O_k, with
-// E_k = (C_k + conj C_{P-k})/2 and O_k = (C_k - conj C_{P-k})/(2i).
+// E_k = (C_k + conj C_{P-k})/2 and O_k = (C_k - conj C_{P-k})/(2i);
+// t = exp(+i pi k/P).
 template <int SIGN, typename C, typename T>
-__device__ __forceinline__ C unpack(const C* lds, int P, int k, const C* __restrict__ post,
-                                    T scale) {
+__device__ __forceinline__ C unpack_with(const C* lds, int P, int k, C t, T scale) {
   C ck = lds[k == P ? 0 : k];
   C cm = lds[k == 0 ? 0 : P - k];
   cm.y = -cm.y;
   C e = C{T(0.5) * (ck.x + cm.x), T(0.5) * (ck.y + cm.y)};
   C d = C{T(0.5) * (ck.x - cm.x), T(0.5) * (ck.y - cm.y)};
   C o = C{d.y, -d.x};  // d / i
-  C t = post[k];
   if (SIGN < 0) t.y = -t.y;
   C z = cadd(e, cmul(t, o));
   return C{z.x * scale, z.y * scale};
 }
 
+template <int SIGN, typename C, typename T>
+__device__ __forceinline__ C unpack(const C* lds, int P, int k, const C* __restrict__ post,
+                                    T scale) {
+  return unpack_with<SIGN>(lds, P, k, post[k], scale);
+}
+
 // ---------------------------------------------------------------- execute: E1 + E2
 // One workgroup per right-hand side: v_c = x_{c + m_off} / w_c on the retained
 // columns [c_lo, c_hi), 0 on the extras (eq. Fe1), then Z = F* v (half).
+// Workgroups of the FFT kernels have at most FFT_MAX_THREADS threads (12
+// waves: 3 per SIMD), which leaves each thread up to 170 registers for its
+// butterflies.
+constexpr int FFT_MAX_THREADS = 768;
+
 template <typename T>
-__global__ void exec_fft_kernel(ExecFftArgs<T> a, FftPlan fp) {
+__global__ __launch_bounds__(FFT_MAX_THREADS) void exec_fft_kernel(ExecFftArgs<T> a, FftPlan fp) {
   using C = cplx_t<T>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C* lds = reinterpret_cast<C*>(smem_raw);
@@ -216,12 +253,72 @@ __global__ void exec_fft_kernel(ExecFftArgs<T> a, FftPlan fp) {
   for (int k = tid; k <= a.P; k += nt) z[k] = unpack<+1>(lds, a.P, k, a.post, a.scale);
 }
 
+// Every block of a plan and every right-hand side in one grid: workgroup
+// blockIdx = b * R + r (blocks sorted by decreasing length, so the long FFTs
+// start first); a block uses the first fp.threads threads of the workgroup.
+// elements of one FFT per thread (make_fft_plan sizes workgroups so that
+// threads >= P / FFT_EPT)
+constexpr int FFT_EPT = 16;
+
+template <typename T>
+__global__ __launch_bounds__(FFT_MAX_THREADS) void exec_fft_multi_kernel(
+    const FftDesc<T>* __restrict__ descs, const T* __restrict__ X, cplx_t<T>* __restrict__ Z,
+    int R, int64_t N) {
+  using C = cplx_t<T>;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C* lds = reinterpret_cast<C*>(smem_raw);
+  const int b = blockIdx.x / R, r = blockIdx.x % R;
+  const FftDesc<T>* __restrict__ d = descs + b;
+  const int P = d->fp.P, nt = d->fp.threads;
+  const int tid = threadIdx.x;
+  const bool active = tid < nt;
+  const int c_lo = d->c_lo, c_hi = d->c_hi, m_off = d->m_off;
+  const T* __restrict__ x = X + (int64_t)r * N;
+  const T* __restrict__ winv = d->winv;
+  // global loads in two rounds of FFT_EPT / 2 per thread, all issued before
+  // the LDS writes of the round
+#pragma unroll
+  for (int h = 0; h < FFT_EPT; h += FFT_EPT / 2) {
+    T v0[FFT_EPT / 2], v1[FFT_EPT / 2];
+#pragma unroll
+    for (int e = 0; e < FFT_EPT / 2; ++e) {
+      const int j = tid + (h + e) * nt;
+      const int c0 = 2 * j, c1 = 2 * j + 1;
+      v0[e] = (active && j < P && c0 >= c_lo && c0 < c_hi) ? x[c0 + m_off] * winv[c0] : T(0);
+      v1[e] = (active && j < P && c1 >= c_lo && c1 < c_hi) ? x[c1 + m_off] * winv[c1] : T(0);
+    }
+#pragma unroll
+    for (int e = 0; e < FFT_EPT / 2; ++e) {
+      const int j = tid + (h + e) * nt;
+      if (active && j < P) lds[j] = C{v0[e], v1[e]};
+    }
+  }
+  __syncthreads();
+  run_fft<+1>(lds, P, d->fp.npass, d->fp.radix, d->tw, tid, nt, active);
+  if (active) {
+    C* __restrict__ z = Z + (int64_t)R * d->zoff + (int64_t)r * d->ldz;
+    const T scale = d->scale;
+    const C* __restrict__ post = d->post;
+    C tw[FFT_EPT + 1];
+#pragma unroll
+    for (int e = 0; e <= FFT_EPT; ++e) {
+      const int k = tid + e * nt;
+      tw[e] = k <= P ? post[k] : C{T(0), T(0)};
+    }
+#pragma unroll
+    for (int e = 0; e <= FFT_EPT; ++e) {
+      const int k = tid + e * nt;
+      if (k <= P) z[k] = unpack_with<+1>(lds, P, k, tw[e], scale);
+    }
+  }
+}
+
 // ---------------------------------------------------------------- transposed: E4
 // One workgroup per right-hand side: half spectrum U (k = 0..P) -> real g of
 // length 2P by F*, then y_{c + m_off} = g_c / w_c on the retained columns only
 // (the extras are discarded, eq. Fe2).
 template <typename T>
-__global__ void inv_fft_kernel(InvFftArgs<T> a, FftPlan fp) {
+__global__ __launch_bounds__(FFT_MAX_THREADS) void inv_fft_kernel(InvFftArgs<T> a, FftPlan fp) {
   using C = cplx_t<T>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C* lds = reinterpret_cast<C*>(smem_raw);
@@ -249,7 +346,7 @@ __global__ void inv_fft_kernel(InvFftArgs<T> a, FftPlan fp) {
 
 // ---------------------------------------------------------------- precompute: P5
 // One workgroup per row: F of a windowed row (float64), half spectrum out.
-__global__ void row_fft_kernel(RowFftArgs a, FftPlan fp) {
+__global__ __launch_bounds__(FFT_MAX_THREADS) void row_fft_kernel(RowFftArgs a, FftPlan fp) {
   using C = double2;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C* lds = reinterpret_cast<C*>(smem_raw);
@@ -284,6 +381,8 @@ void init_fft_kernels(size_t max_lds) {
   set_lds(inv_fft_kernel<double>, max_lds);
   set_lds(inv_fft_kernel<float>, max_lds);
   set_lds(row_fft_kernel, max_lds);
+  set_lds(exec_fft_multi_kernel<double>, max_lds);
+  set_lds(exec_fft_multi_kernel<float>, max_lds);
   done.push_back(dev);
 }
 
@@ -303,11 +402,12 @@ FftPlan make_fft_plan(int P) {
   if ((int)rad.size() > MAX_PASSES) throw Error(SPT_E_UNSUPPORTED, "too many FFT passes");
   fp.npass = (int)rad.size();
   for (int i = 0; i < fp.npass; ++i) fp.radix[i] = rad[i];
-  int t = (P + 15) / 16;
+  int t = (P + FFT_EPT - 1) / FFT_EPT;
   t = ((t + 63) / 64) * 64;
   if (t < 64) t = 64;
-  if (t > 1024) throw Error(SPT_E_UNSUPPORTED, "FFT length half " + std::to_string(P) +
-                                                   " exceeds the single-workgroup FFT");
+  if (t > FFT_MAX_THREADS)
+    throw Error(SPT_E_UNSUPPORTED, "FFT length half " + std::to_string(P) +
+                                       " exceeds the single-workgroup FFT");
   fp.threads = t;
   return fp;
 }
@@ -332,6 +432,19 @@ void launch_row_fft(const RowFftArgs& a, const FftPlan& fp, hipStream_t s) {
   SPT_HIP(hipGetLastError());
 }
 
+template <typename T>
+void launch_exec_fft_multi(const FftDesc<T>* descs, int nblk, int threads, int max_P,
+                           const T* X, cplx_t<T>* Z, int R, int64_t N, hipStream_t s) {
+  const size_t lds = sizeof(cplx_t<T>) * (size_t)max_P;
+  hipLaunchKernelGGL(exec_fft_multi_kernel<T>, dim3(nblk * R), dim3(threads), lds, s, descs, X,
+                     Z, R, N);
+  SPT_HIP(hipGetLastError());
+}
+
+template void launch_exec_fft_multi<double>(const FftDesc<double>*, int, int, int, const double*,
+                                            double2*, int, int64_t, hipStream_t);
+template void launch_exec_fft_multi<float>(const FftDesc<float>*, int, int, int, const float*,
+                                           float2*, int, int64_t, hipStream_t);
 template void launch_exec_fft<double>(const ExecFftArgs<double>&, const FftPlan&, hipStream_t);
 template void launch_exec_fft<float>(const ExecFftArgs<float>&, const FftPlan&, hipStream_t);
 template void launch_inv_fft<double>(const InvFftArgs<double>&, const FftPlan&, hipStream_t);

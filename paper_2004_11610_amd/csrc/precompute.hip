@@ -134,29 +134,36 @@ __device__ void poly_and_derivative(const FamilyArgs& f, double x, double& pn, d
   dpn = d;
 }
 
-// double-double helpers (error-free transformations with fma)
+// double-double helpers (error-free transformations with fma).  Contraction
+// of a*b+c into fma is switched off in them: it would fuse the rounded product
+// with a later sum and break the exact error terms.
 struct DD {
   double hi, lo;
 };
 __device__ __forceinline__ DD dd_norm(double hi, double lo) {
+#pragma clang fp contract(off)
   const double s = hi + lo;
   return DD{s, lo - (s - hi)};
 }
 __device__ __forceinline__ DD two_sum(double a, double b) {
+#pragma clang fp contract(off)
   const double s = a + b;
   const double bb = s - a;
   return DD{s, (a - (s - bb)) + (b - bb)};
 }
 __device__ __forceinline__ DD dd_mul(DD a, DD b) {
+#pragma clang fp contract(off)
   const double p = a.hi * b.hi;
   const double e = fma(a.hi, b.hi, -p);
   return dd_norm(p, e + (a.hi * b.lo + a.lo * b.hi));
 }
 __device__ __forceinline__ DD dd_sub(DD a, DD b) {
+#pragma clang fp contract(off)
   const DD s = two_sum(a.hi, -b.hi);
   return dd_norm(s.hi, s.lo + (a.lo - b.lo));
 }
 __device__ __forceinline__ DD dd_div(DD a, double d) {
+#pragma clang fp contract(off)
   const double q = a.hi / d;
   const double p = q * d;
   const double e = fma(q, d, -p);
@@ -166,6 +173,7 @@ __device__ __forceinline__ DD dd_div(DD a, double d) {
 // One Newton correction for a Laguerre root with L_N, L_N' in double-double:
 // near x = 0 the float64 recurrence loses ~k^2 eps (double characteristic root).
 __device__ double laguerre_dd_newton(int64_t N, double x) {
+#pragma clang fp contract(off)
   DD Lp{0.0, 0.0}, L{1.0, 0.0}, dp{0.0, 0.0}, d{0.0, 0.0};
   for (int64_t m = 0; m < N; ++m) {
     const DD c = two_sum(2.0 * (double)m + 1.0, -x);

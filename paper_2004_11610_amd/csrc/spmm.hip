@@ -12,6 +12,11 @@
 // All blocks of a plan share the same row tiles, so one wave owns 16 output
 // rows for a chunk of right-hand sides and sums every block and the direct
 // tail in registers before writing y once (E5: blocks are independent).
+//
+// The product is a chain of small dense contractions (each tile box is a
+// dense 16 x kw complex matrix), run on the matrix cores in all precisions.
+
+#include <type_traits>
 
 #include "common.hpp"
 
@@ -20,176 +25,232 @@ namespace {
 
 constexpr int WAVES_PER_WG = 4;
 
-// ---------------------------------------------------------------- VALU, T = double/float
-// lane = right-hand side, wave = one row tile; the box values are uniform
-// across the wave (scalar loads), z is per lane.
-template <typename T>
-__global__ __launch_bounds__(64 * WAVES_PER_WG) void spmm_valu_kernel(SpmmArgs<T> a) {
-  using C = cplx_t<T>;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int tile = blockIdx.x * WAVES_PER_WG + wave;
-  if (tile >= a.n_tiles) return;
-  const int r = blockIdx.y * 64 + lane;
-  const bool active = r < a.R;
-  const int rr = active ? r : 0;
-  T acc[TILE_ROWS];
-#pragma unroll
-  for (int q = 0; q < TILE_ROWS; ++q) acc[q] = T(0);
-
-  for (int b = 0; b < a.nblk; ++b) {
-    const int k0 = a.k0[b][tile];
-    const int kw = a.kw[b][tile];
-    const C* __restrict__ val = a.val[b] + a.off[b][tile];
-    const C* __restrict__ z = a.z[b] + (int64_t)rr * a.ldz[b] + k0;
-    for (int kk = 0; kk < kw; ++kk) {
-      const C zv = z[kk];
-#pragma unroll
-      for (int q = 0; q < TILE_ROWS; ++q) {
-        const C av = val[kk * TILE_ROWS + q];
-        acc[q] += av.x * zv.x - av.y * zv.y;
-      }
-    }
-  }
-  const int64_t n0 = (int64_t)tile * TILE_ROWS;
-  const int64_t ldt = (int64_t)a.n_tiles * TILE_ROWS;  // tail rows padded to tiles
-  const T* __restrict__ x = a.X + (int64_t)rr * a.N;
-  for (int m = 0; m < a.tail; ++m) {
-    const T xv = x[m];
-    const T* __restrict__ col = a.tailmat + (int64_t)m * ldt + n0;
-#pragma unroll
-    for (int q = 0; q < TILE_ROWS; ++q) acc[q] += col[q] * xv;
-  }
-  if (active) {
-    T* __restrict__ y = a.Y + (int64_t)r * a.N + n0;
-#pragma unroll
-    for (int q = 0; q < TILE_ROWS; ++q)
-      if (n0 + q < a.N) y[q] = acc[q];
-  }
-}
-
-// ---------------------------------------------------------------- split-bf16 MFMA
-// v_mfma_f32_16x16x32_bf16: D(16x16) += A(16x32) B(32x16) with, for lane l,
-// A[l % 16][8 (l / 16) + j], B[8 (l / 16) + j][l % 16] (j < 8) and
-// D[4 (l / 16) + i][l % 16] (i < 4).
+// ---------------------------------------------------------------- matrix-core product
+// One workgroup = one row tile (16 rows) x 64 right-hand sides; wave w owns the
+// right-hand sides 16w .. 16w+15, i.e. one 16 x 16 output tile, accumulated by
+// matrix-core instructions over the columns of every block's tile box and of
+// the direct tail.  The complex band is made real by doubling K:
+//   sum_k Re(a_k z_k) = sum_k (Re a_k Re z_k - Im a_k Im z_k).
+// Per step of 16 complex columns every lane (m = lane % 16, g = lane / 16)
+// holds the four columns 4g .. 4g+3 of row m of the box and of right-hand side
+// m of its wave.  Steps are taken in batches of E::SB (across block
+// boundaries): all loads of a batch are issued before its first matrix
+// instruction, so a wave waits for memory about once per batch.
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
 
-// round to nearest even bfloat16, returned as the float it represents
-__device__ __forceinline__ float bf16_round(float f) {
-  uint32_t u = __float_as_uint(f);
-  u = (u + 0x7FFFu + ((u >> 16) & 1u)) & 0xFFFF0000u;
-  return __uint_as_float(u);
-}
+typedef float f32x8 __attribute__((ext_vector_type(8)));
 
-// f = p0 + p1 + p2 with bfloat16 pieces (each residual is exact in float32)
-__device__ __forceinline__ void split3(float f, unsigned short& p0, unsigned short& p1,
-                                       unsigned short& p2) {
-  const float f0 = bf16_round(f);
-  const float e1 = f - f0;
-  const float f1 = bf16_round(e1);
-  const float f2 = bf16_round(e1 - f1);
-  p0 = (unsigned short)(__float_as_uint(f0) >> 16);
-  p1 = (unsigned short)(__float_as_uint(f1) >> 16);
-  p2 = (unsigned short)(__float_as_uint(f2) >> 16);
-}
-
+// f = p0 + p1 + p2 with bfloat16 pieces: each piece is the round-to-nearest-
+// even bfloat16 of what the previous ones leave (the residuals are exact in
+// float32); eight values at a time with the packed conversion instructions.
 struct Split8 {
-  u16x8 p[3];
-  __device__ __forceinline__ void set(int j, float f) {
-    unsigned short a, b, c;
-    split3(f, a, b, c);
-    p[0][j] = a;
-    p[1][j] = b;
-    p[2][j] = c;
+  bf16x8 p[3];
+  __device__ __forceinline__ explicit Split8(f32x8 f) {
+    p[0] = __builtin_convertvector(f, bf16x8);
+    const f32x8 r1 = f - __builtin_convertvector(p[0], f32x8);
+    p[1] = __builtin_convertvector(r1, bf16x8);
+    const f32x8 r2 = r1 - __builtin_convertvector(p[1], f32x8);
+    p[2] = __builtin_convertvector(r2, bf16x8);
   }
-  __device__ __forceinline__ bf16x8 get(int i) const { return __builtin_bit_cast(bf16x8, p[i]); }
+  __device__ __forceinline__ bf16x8 get(int i) const { return p[i]; }
 };
 
-// acc += sum over the six products A_i B_j with i + j <= 2
-__device__ __forceinline__ f32x4 mfma6(const Split8& A, const Split8& B, f32x4 acc) {
-  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.get(2), B.get(0), acc, 0, 0, 0);
-  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.get(1), B.get(1), acc, 0, 0, 0);
-  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.get(0), B.get(2), acc, 0, 0, 0);
-  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.get(1), B.get(0), acc, 0, 0, 0);
-  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.get(0), B.get(1), acc, 0, 0, 0);
-  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.get(0), B.get(0), acc, 0, 0, 0);
-  return acc;
+// Engines: the accumulation of one step (4 complex columns per lane, i.e. 32
+// real K per 16 x 16 tile) and of one real step (8 reals per lane).
+//
+// v_mfma_f64_16x16x4f64 / v_mfma_f32_16x16x4f32: lane l supplies A[l%16][l/16]
+// and B[l/16][l%16]; element i of its accumulator is D[l/16 + 4i][l%16] for
+// f64 and D[4(l/16) + i][l%16] for f32.
+// v_mfma_f32_16x16x32_bf16: lane l supplies A[l%16][8(l/16)+j] and
+// B[8(l/16)+j][l%16], j < 8; D as for f32.
+struct EngF64 {
+  using T = double;
+  using Acc = f64x4;
+  static constexpr int SB = 4;
+  __device__ static int row(int g, int i) { return g + 4 * i; }
+  __device__ static Acc zero() { return Acc{0.0, 0.0, 0.0, 0.0}; }
+  __device__ static Acc step(const double2* a, const double2* z, Acc acc) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[j].x, z[j].x, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-a[j].y, z[j].y, acc, 0, 0, 0);
+    }
+    return acc;
+  }
+  __device__ static Acc step_real(const double* a, const double* x, Acc acc) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[j], x[j], acc, 0, 0, 0);
+    return acc;
+  }
+};
+
+struct EngF32 {
+  using T = float;
+  using Acc = f32x4;
+  static constexpr int SB = 8;
+  __device__ static int row(int g, int i) { return 4 * g + i; }
+  __device__ static Acc zero() { return Acc{0.f, 0.f, 0.f, 0.f}; }
+  __device__ static Acc step(const float2* a, const float2* z, Acc acc) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[j].x, z[j].x, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(-a[j].y, z[j].y, acc, 0, 0, 0);
+    }
+    return acc;
+  }
+  __device__ static Acc step_real(const float* a, const float* x, Acc acc) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[j], x[j], acc, 0, 0, 0);
+    return acc;
+  }
+};
+
+// three bfloat16 pieces per operand, the six products of order <= 2 (small
+// ones first), float32 accumulation
+struct EngSplitBf16 {
+  using T = float;
+  using Acc = f32x4;
+  static constexpr int SB = 8;
+  __device__ static int row(int g, int i) { return 4 * g + i; }
+  __device__ static Acc zero() { return Acc{0.f, 0.f, 0.f, 0.f}; }
+  __device__ static Acc mma6(const Split8& A, const Split8& B, Acc acc) {
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.get(2), B.get(0), acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.get(1), B.get(1), acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.get(0), B.get(2), acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.get(1), B.get(0), acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.get(0), B.get(1), acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.get(0), B.get(0), acc, 0, 0, 0);
+    return acc;
+  }
+  __device__ static Acc step(const float2* a, const float2* z, Acc acc) {
+    f32x8 fa, fz;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      fa[2 * j] = a[j].x;
+      fa[2 * j + 1] = -a[j].y;
+      fz[2 * j] = z[j].x;
+      fz[2 * j + 1] = z[j].y;
+    }
+    return mma6(Split8(fa), Split8(fz), acc);
+  }
+  __device__ static Acc step_real(const float* a, const float* x, Acc acc) {
+    f32x8 fa, fx;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      fa[j] = a[j];
+      fx[j] = x[j];
+    }
+    return mma6(Split8(fa), Split8(fx), acc);
+  }
+};
+
+template <typename T>
+struct StepRegs {
+  cplx_t<T> a[4];
+  cplx_t<T> z[4];
+};
+
+// value of lane b (b wave-uniform) as a wave-uniform scalar
+__device__ __forceinline__ int lane_i32(int v, int b) { return __builtin_amdgcn_readlane(v, b); }
+__device__ __forceinline__ int64_t lane_i64(int64_t v, int b) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, b);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v >> 32), b);
+  return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
-// One wave: 16 rows x 64 right-hand sides (four 16x16 output tiles).  The
-// complex band is made real by K' = 2K: A'[q][2kk] = Re a, A'[q][2kk+1] = -Im a,
-// B'[2kk][r] = Re z, B'[2kk+1][r] = Im z, so sum_k' A' B' = Re(a z).
-__global__ __launch_bounds__(64 * WAVES_PER_WG) void spmm_split_bf16_kernel(SpmmArgs<float> a) {
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int tile = blockIdx.x * WAVES_PER_WG + wave;
-  if (tile >= a.n_tiles) return;
+template <typename E>
+__global__ __launch_bounds__(256) void spmm_mfma_kernel(SpmmArgs<typename E::T> args) {
+  using T = typename E::T;
+  using C = cplx_t<T>;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int tile = blockIdx.x;
+  const int r_wave = blockIdx.y * 64 + wave * 16;
+  if (r_wave >= args.R) return;  // wave-uniform: no right-hand side left
   const int m = lane & 15, g = lane >> 4;
-  const int r_base = blockIdx.y * 64;
-  f32x4 acc[4];
-#pragma unroll
-  for (int t = 0; t < 4; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const int r = r_wave + m;
+  const bool rok = r < args.R;
+  const int64_t rr = rok ? r : r_wave;
 
-  for (int b = 0; b < a.nblk; ++b) {
-    const int k0 = a.k0[b][tile];
-    const int kw = a.kw[b][tile];
-    const float2* __restrict__ val = a.val[b] + a.off[b][tile];
-    const float2* __restrict__ zb = a.z[b] + k0;
-    const int ldz = a.ldz[b];
-    for (int ks = 0; ks < kw; ks += 16) {
-      Split8 A;
+  // lane b holds the tile box and block descriptor of block b (one load each)
+  int k0_l = 0, kw_l = 0;
+  int64_t off_l = 0, val_l = 0, zoff_l = 0;
+  int ldz_l = 0;
+  if (lane < args.nblk) {
+    const TileMeta tm = args.meta[(int64_t)tile * args.nblk + lane];
+    const SpmmBlock<T> bd = args.blocks[lane];
+    k0_l = tm.k0;
+    kw_l = tm.kw;
+    off_l = tm.off;
+    val_l = (int64_t)(uintptr_t)bd.val;
+    zoff_l = bd.zoff;
+    ldz_l = bd.ldz;
+  }
+  auto next_item = [&](int b, int kk, int& ob, int& okk) {
+    while (b < args.nblk && kk >= lane_i32(kw_l, b)) {
+      ++b;
+      kk = 0;
+    }
+    ob = b;
+    okk = kk;
+  };
+  auto load = [&](int b, int kk, StepRegs<T>& s) {
+    const int kw = lane_i32(kw_l, b);
+    const int k0 = lane_i32(k0_l, b);
+    const C* __restrict__ val = (const C*)(uintptr_t)lane_i64(val_l, b) + lane_i64(off_l, b);
+    const C* __restrict__ zb =
+        args.Z + (int64_t)args.R * lane_i64(zoff_l, b) + rr * lane_i32(ldz_l, b) + k0;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int kk = ks + 4 * g + j;
-        const float2 av = kk < kw ? val[kk * TILE_ROWS + m] : float2{0.f, 0.f};
-        A.set(2 * j, av.x);
-        A.set(2 * j + 1, -av.y);
-      }
+    for (int j = 0; j < 4; ++j) {
+      const int c = kk + 4 * g + j;
+      const bool ok = c < kw;
+      s.a[j] = ok ? val[c * TILE_ROWS + m] : C{T(0), T(0)};
+      s.z[j] = (ok && rok) ? zb[c] : C{T(0), T(0)};
+    }
+  };
+
+  typename E::Acc acc = E::zero();
+  int b, kk;
+  next_item(0, 0, b, kk);
+  while (b < args.nblk) {
+    StepRegs<T> batch[E::SB];
+    int cnt = 0;
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const int r = r_base + 16 * t + m;
-        Split8 B;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int kk = ks + 4 * g + j;
-          const float2 zv = (kk < kw && r < a.R) ? zb[(int64_t)r * ldz + kk] : float2{0.f, 0.f};
-          B.set(2 * j, zv.x);
-          B.set(2 * j + 1, zv.y);
-        }
-        acc[t] = mfma6(A, B, acc[t]);
+    for (int i = 0; i < E::SB; ++i) {
+      if (b < args.nblk) {
+        load(b, kk, batch[i]);
+        cnt = i + 1;
+        next_item(b, kk + 16, b, kk);
       }
     }
+#pragma unroll
+    for (int i = 0; i < E::SB; ++i)
+      if (i < cnt) acc = E::step(batch[i].a, batch[i].z, acc);
   }
-  // direct tail: A'[q][m'] = tail[m'][row q], B'[m'][r] = x[r][m'], K = tail
+
+  // direct tail: A'[q][m'] = tail[m'][row q], B'[m'][r] = x[r][m']
   const int64_t n0 = (int64_t)tile * TILE_ROWS;
-  const int64_t ldt = (int64_t)a.n_tiles * TILE_ROWS;
-  for (int ks = 0; ks < a.tail; ks += 32) {
-    Split8 A;
+  const int64_t ldt = (int64_t)args.n_tiles * TILE_ROWS;
+  const T* __restrict__ xr = args.X + rr * args.N;
+  for (int ks = 0; ks < args.tail; ks += 32) {
+    T av[8], xv[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const int mm = ks + 8 * g + j;
-      A.set(j, mm < a.tail ? a.tailmat[(int64_t)mm * ldt + n0 + m] : 0.f);
+      const bool ok = mm < args.tail;
+      av[j] = ok ? args.tailmat[(int64_t)mm * ldt + n0 + m] : T(0);
+      xv[j] = (ok && rok) ? xr[mm] : T(0);
     }
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int r = r_base + 16 * t + m;
-      Split8 B;
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int mm = ks + 8 * g + j;
-        B.set(j, (mm < a.tail && r < a.R) ? a.X[(int64_t)r * a.N + mm] : 0.f);
-      }
-      acc[t] = mfma6(A, B, acc[t]);
-    }
+    acc = E::step_real(av, xv, acc);
   }
+  if (rok) {
+    T* __restrict__ y = args.Y + (int64_t)r * args.N + n0;
 #pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    const int r = r_base + 16 * t + m;
-    if (r < a.R) {
-      float* __restrict__ y = a.Y + (int64_t)r * a.N + n0 + 4 * g;
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-        if (n0 + 4 * g + i < a.N) y[i] = acc[t][i];
+    for (int i = 0; i < 4; ++i) {
+      const int q = E::row(g, i);
+      if (n0 + q < args.N) y[q] = acc[i];
     }
   }
 }
@@ -257,14 +318,14 @@ dim3 spmm_grid(int n_tiles, int R) {
 
 template <typename T>
 void launch_spmm(const SpmmArgs<T>& a, hipStream_t s) {
-  hipLaunchKernelGGL(spmm_valu_kernel<T>, spmm_grid(a.n_tiles, a.R), dim3(64 * WAVES_PER_WG), 0,
-                     s, a);
+  using E = typename std::conditional<std::is_same<T, double>::value, EngF64, EngF32>::type;
+  hipLaunchKernelGGL(spmm_mfma_kernel<E>, dim3(a.n_tiles, (a.R + 63) / 64), dim3(256), 0, s, a);
   SPT_HIP(hipGetLastError());
 }
 
 void launch_spmm_split_bf16(const SpmmArgs<float>& a, hipStream_t s) {
-  hipLaunchKernelGGL(spmm_split_bf16_kernel, spmm_grid(a.n_tiles, a.R),
-                     dim3(64 * WAVES_PER_WG), 0, s, a);
+  hipLaunchKernelGGL(spmm_mfma_kernel<EngSplitBf16>, dim3(a.n_tiles, (a.R + 63) / 64),
+                     dim3(256), 0, s, a);
   SPT_HIP(hipGetLastError());
 }
 
