@@ -9,7 +9,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/spt.h"
+#include "spt.h"
 
 namespace spt {
 
