@@ -63,9 +63,10 @@ def fft_algorithmic_bytes(plan, R, bc, bx):
     return R * (retained * bx + spectra * bc)
 
 
-def cpu_baseline(w, X, rows_sample=1024):
+def cpu_baseline(w, X, rows_sample=16384):
     """The oracle's direct float64 product (A from its recurrences, then BLAS),
-    timed on a sample of output rows and scaled to all N rows."""
+    timed on a sample of output rows (all of them by default) and scaled to all
+    N rows."""
     import numpy as np
     from threadpoolctl import threadpool_info
     from oracle import direct, matrix
@@ -90,6 +91,9 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="only run a plain device copy of this many MiB (5 launches) and exit: "
+                         "the reference reading for the HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the execute path is shown on one GPU's share "
@@ -99,6 +103,15 @@ def main():
 
     import numpy as np
     import torch
+    if args.copy_mib:
+        n = args.copy_mib << 18          # float32 elements
+        a = torch.ones(n, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            torch.mul(a, 2.0, out=b)     # one elementwise kernel: reads a, writes b
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 5}))
+        return
     import paper_2004_11610_amd as spt
     import workloads
 

@@ -95,6 +95,17 @@ typedef enum {
   SPT_MODE_DIRECT = 3  /* dense product with A (no compression)                */
 } spt_mode;
 
+/* How spt_execute runs the computation stage. */
+typedef enum {
+  SPT_EXECUTOR_PERSISTENT = 0, /* one launch: a persistent grid takes work items
+                                  (FFTs of every block, four-step FFTs of long
+                                  blocks, banded-product tiles) from a queue, a
+                                  tile's product of a block starting as soon as
+                                  that block's spectra are complete            */
+  SPT_EXECUTOR_STAGED = 1      /* two launches: all FFTs, then all products;
+                                  FFT half-lengths up to 12288                 */
+} spt_executor;
+
 /* Plan parameters.  A zero-filled struct selects every default. */
 typedef struct {
   double alpha, beta;     /* SPT_JACOBI only; alpha, beta > -1                    */
@@ -110,6 +121,7 @@ typedef struct {
                              (for geometry queries: spt_precompute then fails
                              with SPT_E_UNSUPPORTED unless every L_i has that
                              form)                                                 */
+  int32_t executor;       /* spt_executor of spt_execute                          */
   int64_t panel_rows;     /* rows per precompute panel; 0 -> automatic            */
   const double* nodes;    /* optional host array of the N nodes, in the family's
                              order (see above); NULL -> computed on the device.
@@ -166,10 +178,12 @@ spt_status spt_execute_transposed(spt_plan_t plan, const void* X, void* Y, int64
                                   int32_t prec, void* stream);
 
 /* Execute `count` plans (any families and sizes, each precomputed with `prec`)
- * in one launch sequence on `stream`: Y[i] = A_i X[i]^T with nrhs[i]
- * right-hand sides.  X, Y, nrhs are host arrays of `count` entries holding
- * device pointers / counts.  The first call for a given set of plans and
- * sizes records the launches in a HIP graph that later calls replay. */
+ * on `stream`: Y[i] = A_i X[i]^T with nrhs[i] right-hand sides.  X, Y, nrhs
+ * are host arrays of `count` entries holding device pointers / counts.  Every
+ * 64 plans run as one launch of the persistent executor (whatever each plan's
+ * executor parameter says); the first call for a set of plans and sizes builds
+ * its work queue (host work and a stream synchronisation), later calls reuse
+ * it.  Calls for the same plans must not overlap in time (shared counters). */
 spt_status spt_execute_batched(const spt_plan_t* plans, const void* const* X, void* const* Y,
                                const int64_t* nrhs, int32_t count, int32_t prec, void* stream);
 
@@ -198,7 +212,8 @@ enum {
   SPT_STAGE_SPMM_T = 2,     /* transposed banded product (all blocks)           */
   SPT_STAGE_INV_FFT = 3,    /* F*, divide by the window, discard the extras     */
   SPT_STAGE_TAIL_T = 4,     /* transposed direct tail                           */
-  SPT_NUM_STAGES = 5
+  SPT_STAGE_EXEC = 5,       /* persistent executor launch (the whole stage)     */
+  SPT_NUM_STAGES = 6
 };
 spt_status spt_profile_begin(void);
 spt_status spt_profile_end(double* ms, int64_t* launches);

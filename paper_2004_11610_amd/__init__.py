@@ -15,6 +15,7 @@ from ._lib import SptError  # noqa: F401
 CHEBYSHEV_T, LEGENDRE, JACOBI, LAGUERRE_FN, HERMITE_FN = 1, 2, 3, 4, 5
 F64, F32, SPLIT_BF16 = 0, 1, 2
 MODE_AUTO, MODE_ROW, MODE_DIRECT = 0, 1, 3
+EXECUTOR_PERSISTENT, EXECUTOR_STAGED = 0, 1
 FAMILIES = {"chebyshev_t": CHEBYSHEV_T, "legendre": LEGENDRE, "jacobi": JACOBI,
             "laguerre_fn": LAGUERRE_FN, "hermite_fn": HERMITE_FN}
 PRECISIONS = {"f64": F64, "f32": F32, "split_bf16": SPLIT_BF16}
@@ -42,13 +43,14 @@ class Plan:
 
     def __init__(self, family, N, eps, alpha=0.0, beta=0.0, eps2=0.0, mode=MODE_AUTO,
                  unweighted=False, precisions=0, min_block=0, exact_fft_len=False,
-                 panel_rows=0, nodes=None):
+                 panel_rows=0, nodes=None, executor=EXECUTOR_PERSISTENT):
         self._lib = _lib.load()
         self._h = c_void_p()
         p = _lib.SptParams()
         p.alpha, p.beta, p.eps2 = float(alpha), float(beta), float(eps2)
         p.mode, p.unweighted, p.precisions = int(mode), int(bool(unweighted)), int(precisions)
         p.min_block, p.exact_fft_len, p.panel_rows = int(min_block), int(bool(exact_fft_len)), int(panel_rows)
+        p.executor = int(executor)
         self._nodes_buf = None
         if nodes is not None:
             self._nodes_buf = (c_double * N)(*[float(v) for v in nodes])
@@ -155,7 +157,7 @@ def execute_batched(plans, Xs, Ys, prec=F64, stream=None):
     return Ys
 
 
-STAGES = ("fft", "spmm", "spmm_t", "inv_fft", "tail_t")
+STAGES = ("fft", "spmm", "spmm_t", "inv_fft", "tail_t", "exec")
 
 
 def profile_begin():

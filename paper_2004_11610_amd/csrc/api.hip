@@ -8,17 +8,25 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <atomic>
+#include <cstdlib>
 #include <mutex>
 #include <string>
 #include <vector>
 
 #include "common.hpp"
+#include "exec.hpp"
 #include "planner.hpp"
 
 namespace spt {
 namespace {
 
 thread_local std::string g_last_error;
+
+int64_t next_serial() {
+  static std::atomic<int64_t> n{0};
+  return ++n;
+}
 
 // ---------------------------------------------------------------- device buffers
 struct DevBuf {
@@ -73,6 +81,17 @@ struct DevBlock {
   double kappa = 0.0;
   std::vector<int32_t> h_k0, h_kw;
   std::vector<int64_t> h_off;
+  // persistent executor: one workgroup per batch of transforms (four == 0) or
+  // a four-step transform P = P1 * P2 (COL and ROW items)
+  int four = 0, P1 = 0, P2 = 0, lcw = 0, lgp = 0, n_col = 0, n_row = 0;
+  FftPlan f1, f2;
+};
+
+// launch description of the persistent executor for one plan or one batch
+struct ExecCtx {
+  std::vector<int64_t> key;
+  DevBuf plans, blocks, items, sync;
+  int n_items = 0, n_sync = 0, grid = 0;
 };
 
 bool is_jacobi(int f) { return f == SPT_LEGENDRE || f == SPT_JACOBI; }
@@ -105,6 +124,8 @@ struct spt_plan {
   spt::DevBuf spmmblk64, spmmblk32;  // SpmmBlock per block
   int fft_threads = 64, fft_maxP = 1;
   int64_t work_rhs = 0;
+  int64_t serial = 0;  // changes with every precompute (keys of executor contexts)
+  std::vector<std::unique_ptr<spt::ExecCtx>> ctx;  // executor contexts of spt_execute
 };
 
 namespace spt {
@@ -409,6 +430,196 @@ void build_tail(spt_plan_t plan, hipStream_t s) {
   SPT_HIP(hipStreamSynchronize(s));
 }
 
+// Executor geometry of a block: transforms with P <= split_points() run in one
+// workgroup (several right-hand sides at a time when they fit); longer ones as
+// four-step transforms P = P1 * P2, P1 the divisor nearest sqrt(P) for which a
+// column item holds >= 8 columns and a row item >= 1 pair of rows.
+int split_points() {
+  static const int v = [] {
+    const char* e = std::getenv("SPT_EXEC_SPLIT_P");
+    const int x = e ? std::atoi(e) : 0;
+    return x > 0 ? std::min(x, EXEC_POINTS) : EXEC_POINTS;
+  }();
+  return v;
+}
+
+int log2_floor(int v) {
+  int l = 0;
+  while ((2 << l) <= v) ++l;
+  return l;
+}
+
+uint32_t magic_of(int d) {
+  return (uint32_t)((((uint64_t)1 << 32) + (uint64_t)d - 1) / (uint64_t)d);
+}
+
+void exec_geometry(DevBlock& B) {
+  const int P = B.P;
+  B.four = P > split_points();
+  if (!B.four) {
+    B.f1 = make_fft_plan(P);
+    return;
+  }
+  int best = 0;
+  double best_score = 1e300;
+  for (int p1 = 2; p1 <= 1024 && p1 < P; ++p1) {
+    if (P % p1) continue;
+    const int p2 = P / p1;
+    if (2 * p2 > EXEC_POINTS) continue;
+    int cw = 1;
+    while (p2 % (2 * cw) == 0 && 2 * cw * p1 <= EXEC_POINTS && 2 * cw <= 64) cw *= 2;
+    if (cw * p1 > EXEC_POINTS) continue;
+    const double score = std::fabs(std::log((double)p1) - 0.5 * std::log((double)P)) +
+                         (cw < 8 ? 10.0 : 0.0);
+    if (score < best_score) {
+      best_score = score;
+      best = p1;
+    }
+  }
+  if (!best) throw Error(SPT_E_UNSUPPORTED, "no four-step split of FFT length half " +
+                                                std::to_string(P));
+  B.P1 = best;
+  B.P2 = P / best;
+  int cw = 1;
+  while (B.P2 % (2 * cw) == 0 && 2 * cw * B.P1 <= EXEC_POINTS && 2 * cw <= 64) cw *= 2;
+  B.lcw = log2_floor(cw);
+  const int npairs = B.P1 / 2 + 1;
+  int gp = 1;
+  while (4 * gp * B.P2 <= EXEC_POINTS && gp < npairs) gp *= 2;
+  B.lgp = log2_floor(gp);
+  B.n_col = B.P2 >> B.lcw;
+  B.n_row = (npairs + gp - 1) / gp;
+  B.f1 = make_fft_plan(B.P1);
+  B.f2 = make_fft_plan(B.P2);
+}
+
+// right-hand sides per ITEM_FFT of a block (a power of two <= 64)
+int fft_batch(int P, int64_t R) {
+  int nb = 1;
+  while (2 * nb * P <= EXEC_POINTS && 2 * nb <= 64 && nb < R) nb *= 2;
+  return nb;
+}
+
+int cu_count(int device) {
+  int v = 0;
+  SPT_HIP(hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, device));
+  return v;
+}
+
+// executor workspace per right-hand side, in complex values: the half spectra
+// of every block, then the four-step intermediates
+int64_t z_per_rhs(spt_plan_t plan) {
+  int64_t n = 0;
+  for (auto& B : plan->blk) n += B->P + 1;
+  return n;
+}
+int64_t w_per_rhs(spt_plan_t plan) {
+  int64_t n = 0;
+  for (auto& B : plan->blk)
+    if (B->four) n += B->P;
+  return n;
+}
+
+int engine_of(int prec) { return prec == SPT_F64 ? 0 : prec == SPT_F32 ? 1 : 2; }
+
+// Build the items, descriptors and counters of one launch over `count` plans.
+template <typename T>
+void build_exec_ctx(ExecCtx& c, const spt_plan_t* plans, const int64_t* R, int count, int prec,
+                    hipStream_t s) {
+  using C = cplx_t<T>;
+  const bool dbl = std::is_same<T, double>::value;
+  std::vector<ExecPlan<T>> ep(count);
+  std::vector<ExecBlock<T>> eb;
+  std::vector<size_t> first(count);
+  std::vector<int4> col, fft, row, spmm;
+  int nsync = EXEC_SYNC_BASE;
+  for (int i = 0; i < count; ++i) {
+    spt_plan_t plan = plans[i];
+    const int r = (int)R[i];
+    const int groups = (r + 15) / 16;
+    first[i] = eb.size();
+    int64_t zoff = 0, woff = 0;
+    for (size_t b = 0; b < plan->blk.size(); ++b) {
+      const DevBlock& B = *plan->blk[b];
+      ExecBlock<T> e{};
+      e.winv = (const T*)(dbl ? B.winv64.p : B.winv32.p);
+      e.tw = B.tw64.as<double2>();
+      e.post = (const C*)(dbl ? B.post64.p : B.post32.p);
+      e.val = (const C*)(dbl ? B.val64.p : B.val32.p);
+      e.zoff = zoff;
+      e.P = B.P;
+      e.m_off = B.g.m_off;
+      e.c_lo = B.g.c_lo;
+      e.c_hi = B.g.c_hi;
+      e.scale = (T)(1.0 / std::sqrt((double)B.g.L));
+      e.magic = magic_of(B.P);
+      e.magic1 = magic_of(B.P + 1);
+      e.four = B.four;
+      e.f1 = B.f1;
+      e.ctr = nsync;
+      nsync += groups;
+      if (B.four) {
+        e.woff = woff;
+        woff += B.P;
+        e.P1 = B.P1;
+        e.P2 = B.P2;
+        e.magic2 = magic_of(B.P2);
+        e.lcw = B.lcw;
+        e.lgp = B.lgp;
+        e.n_col = B.n_col;
+        e.n_row = B.n_row;
+        e.f2 = B.f2;
+        e.cctr = nsync;
+        nsync += r;
+        e.parts = B.n_row;
+        for (int rr = 0; rr < r; ++rr)
+          for (int g = 0; g < B.n_col; ++g)
+            col.push_back(make_int4(item_head(ITEM_COL, i), (int)b, rr, g));
+        for (int rr = 0; rr < r; ++rr)
+          for (int q = 0; q < B.n_row; ++q)
+            row.push_back(make_int4(item_head(ITEM_ROW, i), (int)b, rr, q));
+      } else {
+        e.parts = 1;
+        const int nb = fft_batch(B.P, r);
+        for (int r0 = 0; r0 < r; r0 += nb)
+          fft.push_back(make_int4(item_head(ITEM_FFT, i), (int)b, r0, log2_floor(nb)));
+      }
+      eb.push_back(e);
+      zoff += B.P + 1;
+    }
+    ExecPlan<T>& P = ep[i];
+    P.Z = plan->work.as<C>();
+    P.W = P.Z + (int64_t)r * zoff;
+    P.meta = plan->tilemeta.as<TileMeta>();
+    P.tailmat = (const T*)(dbl ? plan->tail64.p : plan->tail32.p);
+    P.N = plan->N;
+    P.R = r;
+    P.nblk = (int)plan->blk.size();
+    P.n_tiles = plan->n_tiles;
+    P.tail = (int)plan->tail;
+    for (int t = 0; t < plan->n_tiles; t += 2)
+      for (int r0 = 0; r0 < r; r0 += 64) spmm.push_back(make_int4(item_head(ITEM_SPMM, i), t, r0, 0));
+  }
+  upload(c.blocks, eb, s);
+  for (int i = 0; i < count; ++i) ep[i].blocks = c.blocks.as<ExecBlock<T>>() + first[i];
+  upload(c.plans, ep, s);
+  std::vector<int4> items;
+  items.reserve(col.size() + fft.size() + row.size() + spmm.size());
+  items.insert(items.end(), col.begin(), col.end());
+  items.insert(items.end(), fft.begin(), fft.end());
+  items.insert(items.end(), row.begin(), row.end());
+  items.insert(items.end(), spmm.begin(), spmm.end());
+  upload(c.items, items, s);
+  c.n_items = (int)items.size();
+  c.n_sync = nsync;
+  c.sync.alloc((size_t)nsync * sizeof(uint32_t));
+  SPT_HIP(hipMemsetAsync(c.sync.p, 0, c.sync.bytes, s));
+  SPT_HIP(hipStreamSynchronize(s));
+  init_exec_kernels();
+  const int occ = std::max(1, exec_occupancy(engine_of(prec)));
+  c.grid = std::max(1, std::min(c.n_items, occ * cu_count(plans[0]->device)));
+}
+
 template <typename T>
 std::vector<FftDesc<T>> fft_descs(spt_plan_t plan) {
   using C = cplx_t<T>;
@@ -438,6 +649,7 @@ std::vector<FftDesc<T>> fft_descs(spt_plan_t plan) {
 void build_fft_descs(spt_plan_t plan, hipStream_t s) {
   plan->fft_threads = 64;
   plan->fft_maxP = 1;
+  for (auto& B : plan->blk) exec_geometry(*B);
   for (auto& B : plan->blk) {
     plan->fft_threads = std::max(plan->fft_threads, B->fft.threads);
     plan->fft_maxP = std::max(plan->fft_maxP, B->P);
@@ -468,6 +680,8 @@ void precompute(spt_plan_t plan, hipStream_t s) {
   const size_t lds_max = max_lds_bytes(plan->device);
   init_fft_kernels(lds_max);
   plan->precomputed = false;
+  plan->ctx.clear();
+  plan->serial = next_serial();
   plan->prepared = plan->p.precisions ? plan->p.precisions : 7u;
   plan->n_tiles = (int)tiles_of(plan->N);
   int64_t K = plan->N;
@@ -507,10 +721,10 @@ void precompute(spt_plan_t plan, hipStream_t s) {
 
 // ---------------------------------------------------------------- execute
 void ensure_work(spt_plan_t plan, int64_t R) {
-  int64_t per = 0;
-  for (auto& B : plan->blk) per += B->P + 1;
+  const int64_t per = z_per_rhs(plan) + w_per_rhs(plan);
   const size_t bytes = (size_t)std::max<int64_t>(per, 1) * (size_t)R * sizeof(double2);
   if (bytes > plan->work.bytes) {
+    plan->ctx.clear();  // contexts hold the old workspace address
     plan->work.alloc(bytes);
     plan->work_rhs = R;
   }
@@ -531,8 +745,9 @@ void check_exec(spt_plan_t plan, const void* X, const void* Y, int64_t R, int pr
   if (x0 < y0 + n && y0 < x0 + n) throw Error(SPT_E_INVALID_ARG, "X and Y overlap");
 }
 
+// two launches: the fused FFT kernel of every block, then the banded product
 template <typename T>
-void execute_t(spt_plan_t plan, const T* X, T* Y, int64_t R, int prec, hipStream_t s) {
+void execute_staged_t(spt_plan_t plan, const T* X, T* Y, int64_t R, int prec, hipStream_t s) {
   using C = cplx_t<T>;
   ensure_work(plan, R);
   SpmmArgs<T> sa{};
@@ -665,22 +880,46 @@ void staged(int stage, hipStream_t s, F&& fn) {
   g_prof.recs.push_back(r);
 }
 
-// ---------------------------------------------------------------- batched graphs
-struct BatchCache {
-  std::vector<const void*> key;
-  hipGraphExec_t exec = nullptr;
-  hipStream_t stream = nullptr;
-  hipEvent_t ev_in = nullptr, ev_out = nullptr;
-  int device = -1;
-  ~BatchCache() { clear(); }
-  void clear() {
-    if (exec) (void)hipGraphExecDestroy(exec);
-    exec = nullptr;
-    key.clear();
+// ---------------------------------------------------------------- persistent executor
+template <typename T>
+void run_exec(ExecCtx& c, const void* const* X, void* const* Y, int count, int prec,
+              hipStream_t s) {
+  ExecArgs<T> a{};
+  a.plans = c.plans.as<ExecPlan<T>>();
+  a.items = c.items.as<int4>();
+  a.sync = c.sync.as<uint32_t>();
+  a.n_items = c.n_items;
+  a.n_sync = c.n_sync;
+  for (int i = 0; i < count; ++i) {
+    a.X[i] = static_cast<const T*>(X[i]);
+    a.Y[i] = static_cast<T*>(Y[i]);
   }
-};
+  staged(SPT_STAGE_EXEC, s, [&] { launch_exec<T>(a, engine_of(prec), c.grid, s); });
+}
+
+std::unique_ptr<ExecCtx> new_ctx(const std::vector<int64_t>& key, const spt_plan_t* plans,
+                                 const int64_t* R, int count, int prec, hipStream_t s) {
+  auto c = std::make_unique<ExecCtx>();
+  c->key = key;
+  if (prec == SPT_F64)
+    build_exec_ctx<double>(*c, plans, R, count, prec, s);
+  else
+    build_exec_ctx<float>(*c, plans, R, count, prec, s);
+  return c;
+}
+
+ExecCtx& plan_ctx(spt_plan_t plan, int64_t R, int prec, hipStream_t s) {
+  const std::vector<int64_t> key{prec, R, plan->serial, (int64_t)(intptr_t)plan->work.p};
+  for (auto& c : plan->ctx)
+    if (c->key == key) return *c;
+  if (plan->ctx.size() >= 8) plan->ctx.erase(plan->ctx.begin());
+  plan->ctx.push_back(new_ctx(key, &plan, &R, 1, prec, s));
+  return *plan->ctx.back();
+}
+
+// contexts of batched launches (a few recent sets of plans)
 std::mutex g_batch_mu;
-BatchCache g_batch;
+std::vector<std::unique_ptr<ExecCtx>> g_batch_ctx;
 
 template <typename F>
 spt_status guard(F&& fn) {
@@ -730,6 +969,8 @@ spt_status spt_plan_create(spt_plan_t* out, int32_t family, const spt_params* p,
     if (prm.mode != SPT_MODE_AUTO && prm.mode != SPT_MODE_ROW && prm.mode != SPT_MODE_DIRECT)
       throw Error(SPT_E_INVALID_ARG, "unknown mode");
     if (prm.precisions & ~7u) throw Error(SPT_E_INVALID_ARG, "unknown precision bits");
+    if (prm.executor != SPT_EXECUTOR_PERSISTENT && prm.executor != SPT_EXECUTOR_STAGED)
+      throw Error(SPT_E_INVALID_ARG, "unknown executor");
     if (prm.min_block < 0 || prm.panel_rows < 0) throw Error(SPT_E_INVALID_ARG, "negative size");
     auto plan = std::make_unique<spt_plan>();
     plan->family = family;
@@ -802,10 +1043,21 @@ spt_status spt_execute(spt_plan_t plan, const void* X, void* Y, int64_t nrhs, in
     check_exec(plan, X, Y, nrhs, prec);
     set_device(plan);
     hipStream_t s = static_cast<hipStream_t>(stream);
+    if (plan->p.executor == SPT_EXECUTOR_STAGED) {
+      if (prec == SPT_F64)
+        execute_staged_t<double>(plan, (const double*)X, (double*)Y, nrhs, prec, s);
+      else
+        execute_staged_t<float>(plan, (const float*)X, (float*)Y, nrhs, prec, s);
+      return;
+    }
+    ensure_work(plan, nrhs);
+    ExecCtx& c = plan_ctx(plan, nrhs, prec, s);
+    const void* xs[1] = {X};
+    void* ys[1] = {Y};
     if (prec == SPT_F64)
-      execute_t<double>(plan, (const double*)X, (double*)Y, nrhs, prec, s);
+      run_exec<double>(c, xs, ys, 1, prec, s);
     else
-      execute_t<float>(plan, (const float*)X, (float*)Y, nrhs, prec, s);
+      run_exec<float>(c, xs, ys, 1, prec, s);
   });
 }
 
@@ -836,67 +1088,30 @@ spt_status spt_execute_batched(const spt_plan_t* plans, const void* const* X, vo
         throw Error(SPT_E_INVALID_ARG, "batched plans live on different devices");
     }
     set_device(plans[0]);
-    for (int i = 0; i < count; ++i) ensure_work(plans[i], nrhs[i]);
-    std::vector<const void*> key;
-    key.push_back((const void*)(intptr_t)prec);
-    for (int i = 0; i < count; ++i) {
-      key.push_back(plans[i]);
-      key.push_back(X[i]);
-      key.push_back(Y[i]);
-      key.push_back((const void*)(intptr_t)nrhs[i]);
-      key.push_back(plans[i]->work.p);
-    }
-    std::lock_guard<std::mutex> lk(g_batch_mu);
-    BatchCache& bc = g_batch;
-    if (bc.device != plans[0]->device) {
-      bc.clear();
-      if (bc.stream) (void)hipStreamDestroy(bc.stream);
-      if (bc.ev_in) (void)hipEventDestroy(bc.ev_in);
-      if (bc.ev_out) (void)hipEventDestroy(bc.ev_out);
-      SPT_HIP(hipStreamCreateWithFlags(&bc.stream, hipStreamNonBlocking));
-      SPT_HIP(hipEventCreateWithFlags(&bc.ev_in, hipEventDisableTiming));
-      SPT_HIP(hipEventCreateWithFlags(&bc.ev_out, hipEventDisableTiming));
-      bc.device = plans[0]->device;
-    }
-    if (!bc.exec || bc.key != key) {
-      bc.clear();
-      hipGraph_t g = nullptr;
-      const bool prof = g_prof.on;
-      g_prof.on = false;  // no timing events inside a graph
-      struct Restore {
-        bool v;
-        ~Restore() { g_prof.on = v; }
-      } restore{prof};
-      SPT_HIP(hipStreamBeginCapture(bc.stream, hipStreamCaptureModeThreadLocal));
-      try {
-        for (int i = 0; i < count; ++i) {
-          if (prec == SPT_F64)
-            execute_t<double>(plans[i], (const double*)X[i], (double*)Y[i], nrhs[i], prec,
-                              bc.stream);
-          else
-            execute_t<float>(plans[i], (const float*)X[i], (float*)Y[i], nrhs[i], prec,
-                             bc.stream);
-        }
-      } catch (...) {
-        (void)hipStreamEndCapture(bc.stream, &g);
-        if (g) (void)hipGraphDestroy(g);
-        throw;
-      }
-      SPT_HIP(hipStreamEndCapture(bc.stream, &g));
-      hipError_t e = hipGraphInstantiate(&bc.exec, g, nullptr, nullptr, 0);
-      (void)hipGraphDestroy(g);
-      if (e != hipSuccess) {
-        bc.exec = nullptr;
-        throw Error(SPT_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
-      }
-      bc.key = key;
-    }
     hipStream_t s = static_cast<hipStream_t>(stream);
-    SPT_HIP(hipEventRecord(bc.ev_in, s));
-    SPT_HIP(hipStreamWaitEvent(bc.stream, bc.ev_in, 0));
-    SPT_HIP(hipGraphLaunch(bc.exec, bc.stream));
-    SPT_HIP(hipEventRecord(bc.ev_out, bc.stream));
-    SPT_HIP(hipStreamWaitEvent(s, bc.ev_out, 0));
+    for (int i = 0; i < count; ++i) ensure_work(plans[i], nrhs[i]);
+    std::lock_guard<std::mutex> lk(g_batch_mu);
+    for (int i0 = 0; i0 < count; i0 += EXEC_MAX_PLANS) {
+      const int n = std::min(count - i0, EXEC_MAX_PLANS);
+      std::vector<int64_t> key{prec, n};
+      for (int i = i0; i < i0 + n; ++i) {
+        key.push_back(plans[i]->serial);
+        key.push_back(nrhs[i]);
+        key.push_back((int64_t)(intptr_t)plans[i]->work.p);
+      }
+      ExecCtx* c = nullptr;
+      for (auto& e : g_batch_ctx)
+        if (e->key == key) c = e.get();
+      if (!c) {
+        if (g_batch_ctx.size() >= 4) g_batch_ctx.erase(g_batch_ctx.begin());
+        g_batch_ctx.push_back(new_ctx(key, plans + i0, nrhs + i0, n, prec, s));
+        c = g_batch_ctx.back().get();
+      }
+      if (prec == SPT_F64)
+        run_exec<double>(*c, X + i0, Y + i0, n, prec, s);
+      else
+        run_exec<float>(*c, X + i0, Y + i0, n, prec, s);
+    }
   });
 }
 
@@ -1010,12 +1225,15 @@ spt_status spt_plan_destroy(spt_plan_t plan) {
     (void)hipSetDevice(plan->device);
     (void)hipDeviceSynchronize();
     {
+      // batched contexts keyed by this plan's serial refer to its buffers
       std::lock_guard<std::mutex> lk(g_batch_mu);
-      for (const void* k : g_batch.key)
-        if (k == plan) {
-          g_batch.clear();
-          break;
-        }
+      auto uses = [&](const std::unique_ptr<ExecCtx>& c) {
+        for (size_t i = 2; i < c->key.size(); i += 3)  // key: prec, n, (serial, R, work)...
+          if (c->key[i] == plan->serial) return true;
+        return false;
+      };
+      g_batch_ctx.erase(std::remove_if(g_batch_ctx.begin(), g_batch_ctx.end(), uses),
+                        g_batch_ctx.end());
     }
     delete plan;
   });

@@ -1,0 +1,495 @@
+// Persistent executor kernel: the work items described in exec.hpp.
+
+#include <type_traits>
+
+#include "exec.hpp"
+#include "fft_core.hpp"
+#include "spmm_core.hpp"
+
+namespace spt {
+namespace {
+
+using namespace fftcore;
+using namespace spmmcore;
+
+// a wait gives up after this long (wall clock, 100 MHz ticks) or once another
+// wait has given up; what the waiting item writes is then NaN
+constexpr uint64_t WAIT_TICKS = 100000000ull;  // 1 s
+
+__device__ __forceinline__ uint32_t ld_relaxed(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// wait until *p >= target (wave-uniform result); false when the wait gave up
+__device__ bool wait_count(uint32_t* sync, const uint32_t* p, uint32_t target) {
+  if (__builtin_amdgcn_readfirstlane(ld_relaxed(p)) >= target) return true;
+  const uint64_t t0 = wall_clock64();
+  for (int it = 1;; ++it) {
+    __builtin_amdgcn_s_sleep(2);
+    if (__builtin_amdgcn_readfirstlane(ld_relaxed(p)) >= target) return true;
+    if ((it & 63) == 0) {
+      if (__builtin_amdgcn_readfirstlane(ld_relaxed(sync + EXEC_SYNC_ERR)) != 0) return false;
+      if (wall_clock64() - t0 > WAIT_TICKS) {
+        __hip_atomic_store(sync + EXEC_SYNC_ERR, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return false;
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ void acquire() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
+__device__ __forceinline__ void release() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
+
+__device__ __forceinline__ uint32_t udiv(uint32_t u, uint32_t magic) {
+  return __umulhi(u, magic);
+}
+
+// all threads: publish this workgroup's global writes, then thread 0 adds n
+__device__ __forceinline__ void signal(uint32_t* p, uint32_t n) {
+  release();
+  __syncthreads();
+  if (threadIdx.x == 0 && n) __hip_atomic_fetch_add(p, n, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <typename C, typename T>
+__device__ __forceinline__ C unpack_pair(C ck, C cm, C t, T scale) {
+  // Z_k = E_k + exp(i pi k/P) O_k, E = (C_k + conj C_{P-k})/2, O = (C_k - conj C_{P-k})/(2i)
+  cm.y = -cm.y;
+  const C e = C{T(0.5) * (ck.x + cm.x), T(0.5) * (ck.y + cm.y)};
+  const C d = C{T(0.5) * (ck.x - cm.x), T(0.5) * (ck.y - cm.y)};
+  const C o = C{d.y, -d.x};
+  const C z = cadd(e, cmul(t, o));
+  return C{z.x * scale, z.y * scale};
+}
+
+template <typename T>
+__device__ __forceinline__ T nan_of() {
+  return __builtin_nan("");
+}
+
+// ------------------------------------------------------------------ ITEM_FFT
+// 2^lb right-hand sides r0 .. of one block; point j of rhs r0 + t at
+// lds[(j << lb) + t]
+template <typename T>
+__device__ __forceinline__ void item_fft(const ExecPlan<T>& pl, const ExecBlock<T>& B, const T* __restrict__ X,
+                         int r0, int lb, cplx_t<T>* lds, uint32_t* sync) {
+  using C = cplx_t<T>;
+  const int tid = threadIdx.x;
+  const int P = B.P, nt = 1 << lb;
+  const uint32_t total = (uint32_t)P << lb;
+  const int R = pl.R;
+  const int64_t N = pl.N;
+  const int c_lo = B.c_lo, c_hi = B.c_hi, m_off = B.m_off;
+  const T* __restrict__ winv = B.winv;
+  {
+    T v0[EXEC_EPT], v1[EXEC_EPT];
+#pragma unroll
+    for (int e = 0; e < EXEC_EPT; ++e) {
+      const uint32_t u = tid + e * EXEC_THREADS;
+      const int t = (int)udiv(u, B.magic), j = (int)u - t * P;
+      const int r = r0 + t;
+      const bool ok = u < total && r < R;
+      const int c0 = 2 * j, c1 = 2 * j + 1;
+      const T* __restrict__ x = X + (int64_t)r * N + m_off;
+      v0[e] = (ok && c0 >= c_lo && c0 < c_hi) ? x[c0] * winv[c0] : T(0);
+      v1[e] = (ok && c1 >= c_lo && c1 < c_hi) ? x[c1] * winv[c1] : T(0);
+    }
+#pragma unroll
+    for (int e = 0; e < EXEC_EPT; ++e) {
+      const uint32_t u = tid + e * EXEC_THREADS;
+      const int t = (int)udiv(u, B.magic), j = (int)u - t * P;
+      if (u < total) lds[(j << lb) + t] = C{v0[e], v1[e]};
+    }
+  }
+  __syncthreads();
+  run_fft<+1, true, EXEC_EPT>(lds, P, lb, B.f1.npass, B.f1.radix, B.tw, 1, tid, EXEC_THREADS,
+                              true);
+  // half spectra, k = 0 .. P of every rhs (u = t * (P + 1) + k)
+  const uint32_t total1 = (uint32_t)(P + 1) << lb;
+  C* __restrict__ Z = pl.Z + (int64_t)R * B.zoff;
+  {
+    constexpr int NE = EXEC_EPT + 1;  // (P + 1) 2^lb <= EXEC_POINTS + 64
+    C tw[NE];
+#pragma unroll
+    for (int e = 0; e < NE; ++e) {
+      const uint32_t u = tid + e * EXEC_THREADS;
+      const int t = (int)udiv(u, B.magic1), k = (int)u - t * (P + 1);
+      tw[e] = u < total1 ? B.post[k] : C{T(0), T(0)};
+    }
+#pragma unroll
+    for (int e = 0; e < NE; ++e) {
+      const uint32_t u = tid + e * EXEC_THREADS;
+      const int t = (int)udiv(u, B.magic1), k = (int)u - t * (P + 1);
+      const int r = r0 + t;
+      if (u < total1 && r < R) {
+        const C ck = lds[((k == P ? 0 : k) << lb) + t];
+        const C cm = lds[((k == 0 ? 0 : P - k) << lb) + t];
+        Z[(int64_t)r * (P + 1) + k] = unpack_pair(ck, cm, tw[e], B.scale);
+      }
+    }
+  }
+  // one count per complete rhs, per group of 16
+  release();
+  __syncthreads();
+  if (tid == 0) {
+    const int r1 = min(r0 + nt, R);
+    for (int g = r0 >> 4; g <= (r1 - 1) >> 4; ++g) {
+      const int n = min(r1, 16 * g + 16) - max(r0, 16 * g);
+      __hip_atomic_fetch_add(sync + B.ctr + g, (uint32_t)n, __ATOMIC_RELEASE,
+                             __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
+// ------------------------------------------------------------------ ITEM_COL
+// u[n] = v[2n] + i v[2n+1], n = P2 n1 + n2.  Columns n2 = grp * 2^lcw + t:
+// point n1 of column t at lds[(n1 << lcw) + t] (that is lds[u] for the
+// load order u = (n1 << lcw) + t), length-P1 transforms, then
+// W[k1 * P2 + n2] = (sum_n1 u[P2 n1 + n2] w_P1^(n1 k1)) w_P^(n2 k1).
+template <typename T>
+__device__ __forceinline__ void item_col(const ExecPlan<T>& pl, const ExecBlock<T>& B, const T* __restrict__ X,
+                         int r, int grp, cplx_t<T>* lds, uint32_t* sync) {
+  using C = cplx_t<T>;
+  const int tid = threadIdx.x;
+  const int lcw = B.lcw, cw = 1 << lcw;
+  const int P1 = B.P1, P2 = B.P2;
+  const uint32_t total = (uint32_t)P1 << lcw;
+  const int c_lo = B.c_lo, c_hi = B.c_hi;
+  const T* __restrict__ x = X + (int64_t)r * pl.N + B.m_off;
+  const T* __restrict__ winv = B.winv;
+  const int n2base = grp << lcw;
+  {
+    T v0[EXEC_EPT], v1[EXEC_EPT];
+#pragma unroll
+    for (int e = 0; e < EXEC_EPT; ++e) {
+      const uint32_t u = tid + e * EXEC_THREADS;
+      const int t = (int)u & (cw - 1), n1 = (int)(u >> lcw);
+      const int n = n1 * P2 + n2base + t;
+      const int c0 = 2 * n, c1 = 2 * n + 1;
+      const bool ok = u < total;
+      v0[e] = (ok && c0 >= c_lo && c0 < c_hi) ? x[c0] * winv[c0] : T(0);
+      v1[e] = (ok && c1 >= c_lo && c1 < c_hi) ? x[c1] * winv[c1] : T(0);
+    }
+#pragma unroll
+    for (int e = 0; e < EXEC_EPT; ++e) {
+      const uint32_t u = tid + e * EXEC_THREADS;
+      if (u < total) lds[u] = C{v0[e], v1[e]};
+    }
+  }
+  __syncthreads();
+  run_fft<+1, true, EXEC_EPT>(lds, P1, lcw, B.f1.npass, B.f1.radix, B.tw, P2, tid, EXEC_THREADS,
+                              true);
+  C* __restrict__ W = pl.W + (int64_t)pl.R * B.woff + (int64_t)r * B.P;
+#pragma unroll
+  for (int e = 0; e < EXEC_EPT; ++e) {
+    const uint32_t u = tid + e * EXEC_THREADS;
+    if (u < total) {
+      const int t = (int)u & (cw - 1), k1 = (int)(u >> lcw);
+      const int n2 = n2base + t;
+      const C w = to_c<C>(twiddle(B.tw, n2 * k1));
+      W[(int64_t)k1 * P2 + n2] = cmul(lds[u], w);
+    }
+  }
+  signal(sync + B.cctr + r, 1);
+}
+
+// ------------------------------------------------------------------ ITEM_ROW
+// Row pairs j = grp * 2^lgp + i, i < 2^lgp: slot 2i holds row k1 = j, slot
+// 2i + 1 row (P1 - j) mod P1 (the same row for j = 0 and j = P1 / 2); point k2
+// of slot s at lds[(k2 << ls) + s], ls = lgp + 1.  After the length-P2
+// transforms slot s, point k2 is U_k, k = k1 + P1 k2, and its partner
+// U_{P-k} sits in the other slot of the pair at P2 - 1 - k2 (k1 > 0) or in the
+// same slot at (P2 - k2) mod P2 (k1 = 0).
+template <typename T>
+__device__ __forceinline__ void item_row(const ExecPlan<T>& pl, const ExecBlock<T>& B, int r, int grp,
+                         cplx_t<T>* lds, uint32_t* sync, int* s_flag) {
+  using C = cplx_t<T>;
+  const int tid = threadIdx.x;
+  const int P = B.P, P1 = B.P1, P2 = B.P2;
+  const int ls = B.lgp + 1, ns = 1 << ls;
+  const int npairs = P1 / 2 + 1;
+  const int j0 = grp << B.lgp;
+  if (tid < 64) {  // wave 0 waits
+    const bool ok = wait_count(sync, sync + B.cctr + r, (uint32_t)B.n_col);
+    if (tid == 0) *s_flag = ok;
+  }
+  __syncthreads();
+  acquire();
+  const bool ok = *s_flag != 0;
+  const uint32_t total = (uint32_t)P2 << ls;
+  const C* __restrict__ W = pl.W + (int64_t)pl.R * B.woff + (int64_t)r * P;
+  auto row_of = [&](int s, bool& valid) {
+    const int j = j0 + (s >> 1);
+    valid = j < npairs;
+    return (s & 1) ? (P1 - j) % P1 : j;
+  };
+  {
+    C v[EXEC_EPT];
+#pragma unroll
+    for (int e = 0; e < EXEC_EPT; ++e) {
+      const uint32_t u = tid + e * EXEC_THREADS;  // u = s * P2 + k2: rows read in order
+      const int s = (int)udiv(u, B.magic2), k2 = (int)u - s * P2;
+      bool valid;
+      const int k1 = row_of(s, valid);
+      v[e] = (u < total && valid) ? W[(int64_t)k1 * P2 + k2] : C{T(0), T(0)};
+    }
+#pragma unroll
+    for (int e = 0; e < EXEC_EPT; ++e) {
+      const uint32_t u = tid + e * EXEC_THREADS;
+      const int s = (int)udiv(u, B.magic2), k2 = (int)u - s * P2;
+      if (u < total) lds[(k2 << ls) + s] = v[e];
+    }
+  }
+  __syncthreads();
+  run_fft<+1, true, EXEC_EPT>(lds, P2, ls, B.f2.npass, B.f2.radix, B.tw, P1, tid, EXEC_THREADS,
+                              true);
+  C* __restrict__ Z = pl.Z + (int64_t)pl.R * B.zoff + (int64_t)r * (P + 1);
+  const T nanv = nan_of<T>();
+  {
+    C tw[EXEC_EPT];
+    int kk[EXEC_EPT];
+#pragma unroll
+    for (int e = 0; e < EXEC_EPT; ++e) {
+      const uint32_t u = tid + e * EXEC_THREADS;  // u = (k2 << ls) + s
+      const int s = (int)u & (ns - 1), k2 = (int)(u >> ls);
+      bool valid;
+      const int k1 = row_of(s, valid);
+      bool own = u < total && valid;
+      if (s & 1) {
+        bool v2;
+        own = own && k1 != row_of(s - 1, v2);  // a self-paired row is written by its even slot
+      }
+      kk[e] = own ? k1 + P1 * k2 : -1;
+      tw[e] = own ? B.post[kk[e]] : C{T(0), T(0)};
+    }
+#pragma unroll
+    for (int e = 0; e < EXEC_EPT; ++e) {
+      if (kk[e] >= 0) {
+        const uint32_t u = tid + e * EXEC_THREADS;
+        const int s = (int)u & (ns - 1), k2 = (int)(u >> ls);
+        const int k1 = kk[e] - P1 * k2;
+        const C ck = lds[u];
+        const C cm = k1 == 0 ? lds[(((P2 - k2) % P2) << ls) + s]
+                             : lds[((P2 - 1 - k2) << ls) + (s ^ 1)];
+        C z = unpack_pair(ck, cm, tw[e], B.scale);
+        if (!ok) z = C{nanv, nanv};
+        Z[kk[e]] = z;
+      }
+    }
+  }
+  if (grp == 0 && tid == 0) {  // k = P: C_P = C_0
+    const C c0 = lds[0];
+    C z = unpack_pair(c0, c0, B.post[P], B.scale);
+    if (!ok) z = C{nanv, nanv};
+    Z[P] = z;
+  }
+  signal(sync + B.ctr + (r >> 4), 1);
+}
+
+// ------------------------------------------------------------------ ITEM_SPMM
+// Tiles tile0, tile0 + 1 x 64 right-hand sides; wave w: tile tile0 + w / 4,
+// right-hand sides r0 + 16 (w % 4) ..
+template <typename E>
+__device__ __forceinline__ void item_spmm(const ExecPlan<typename E::T>& pl, const typename E::T* __restrict__ X,
+                          typename E::T* __restrict__ Y, int tile0, int r0, uint32_t* sync) {
+  using T = typename E::T;
+  using C = cplx_t<T>;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int R = pl.R;
+  const int tile = tile0 + (wave >> 2);
+  const int r_wave = r0 + (wave & 3) * 16;
+  if (r_wave >= R || tile >= pl.n_tiles) return;
+  const int grp = r_wave >> 4;
+  const int nvalid = min(16, R - r_wave);
+  const int m = lane & 15, g = lane >> 4;
+  const int r = r_wave + m;
+  const bool rok = r < R;
+  const int64_t rr = rok ? r : r_wave;
+  const int nblk = pl.nblk;
+
+  // lane b < nblk holds the tile box and descriptor fields of block b
+  int k0_l = 0, kw_l = 0, ldz_l = 0, ctr_l = 0, parts_l = 0;
+  int64_t off_l = 0, val_l = 0, zoff_l = 0;
+  if (lane < nblk) {
+    const TileMeta tm = pl.meta[(int64_t)tile * nblk + lane];
+    const ExecBlock<T>& bd = pl.blocks[lane];
+    k0_l = tm.k0;
+    kw_l = tm.kw;
+    off_l = tm.off;
+    val_l = (int64_t)(uintptr_t)bd.val;
+    zoff_l = bd.zoff;
+    ldz_l = bd.P + 1;
+    ctr_l = bd.ctr;
+    parts_l = bd.parts;
+  }
+
+  typename E::Acc acc = E::zero();
+  // direct tail: A'[q][m'] = tail[m'][row q], B'[m'][r] = x[r][m']
+  const int64_t n0 = (int64_t)tile * TILE_ROWS;
+  const int64_t ldt = (int64_t)pl.n_tiles * TILE_ROWS;
+  const T* __restrict__ xr = X + rr * pl.N;
+  for (int ks = 0; ks < pl.tail; ks += 32) {
+    T av[8], xv[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int mm = ks + 8 * g + j;
+      const bool ok = mm < pl.tail;
+      av[j] = ok ? pl.tailmat[(int64_t)mm * ldt + n0 + m] : T(0);
+      xv[j] = (ok && rok) ? xr[mm] : T(0);
+    }
+    acc = E::step_real(av, xv, acc);
+  }
+
+  bool ok = true;
+  for (int b = nblk - 1; b >= 0; --b) {
+    const int kw = lane_i32(kw_l, b);
+    if (kw == 0) continue;
+    const int k0 = lane_i32(k0_l, b);
+    const C* __restrict__ val = (const C*)(uintptr_t)lane_i64(val_l, b) + lane_i64(off_l, b);
+    const C* __restrict__ zb =
+        pl.Z + (int64_t)R * lane_i64(zoff_l, b) + rr * lane_i32(ldz_l, b) + k0;
+    const uint32_t need = (uint32_t)(lane_i32(parts_l, b) * nvalid);
+    if (!wait_count(sync, sync + lane_i32(ctr_l, b) + grp, need)) ok = false;
+    acquire();
+    for (int kk = 0; kk < kw; kk += 16 * E::SB) {
+      StepRegs<T> batch[E::SB];
+#pragma unroll
+      for (int i = 0; i < E::SB; ++i) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int c = kk + 16 * i + 4 * g + j;
+          const bool in = c < kw;
+          batch[i].a[j] = in ? val[c * TILE_ROWS + m] : C{T(0), T(0)};
+          batch[i].z[j] = (in && rok) ? zb[c] : C{T(0), T(0)};
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < E::SB; ++i)
+        if (kk + 16 * i < kw) acc = E::step(batch[i].a, batch[i].z, acc);
+    }
+  }
+  if (rok) {
+    T* __restrict__ y = Y + (int64_t)r * pl.N + n0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int q = E::row(g, i);
+      if (n0 + q < pl.N) y[q] = ok ? acc[i] : nan_of<T>();
+    }
+  }
+}
+
+// ------------------------------------------------------------------ kernel
+template <typename E>
+__global__ __launch_bounds__(EXEC_THREADS) __attribute__((amdgpu_waves_per_eu(4))) void exec_kernel(ExecArgs<typename E::T> a) {
+  using T = typename E::T;
+  using C = cplx_t<T>;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C* lds = reinterpret_cast<C*>(smem_raw);
+  __shared__ int4 s_item[2];
+  __shared__ int s_flag;
+  const int tid = threadIdx.x;
+  uint32_t* sync = a.sync;
+  if (tid == 0) {
+    const uint32_t i = __hip_atomic_fetch_add(sync + EXEC_SYNC_HEAD, 1u, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+    s_item[0] = i < (uint32_t)a.n_items ? a.items[i] : make_int4(-1, 0, 0, 0);
+  }
+  __syncthreads();
+  int cur = 0;
+  for (;;) {
+    const int4 it = s_item[cur];
+    if (it.x < 0) break;
+    // take the next item now; it is stored for the next round after this one
+    uint32_t nxt = 0;
+    if (tid == 0)
+      nxt = __hip_atomic_fetch_add(sync + EXEC_SYNC_HEAD, 1u, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+    const int kind = it.x & 15, p = it.x >> 4;
+    const ExecPlan<T>& pl = a.plans[p];
+    switch (kind) {
+      case ITEM_FFT: item_fft<T>(pl, pl.blocks[it.y], a.X[p], it.z, it.w, lds, sync); break;
+      case ITEM_COL: item_col<T>(pl, pl.blocks[it.y], a.X[p], it.z, it.w, lds, sync); break;
+      case ITEM_ROW: item_row<T>(pl, pl.blocks[it.y], it.z, it.w, lds, sync, &s_flag); break;
+      default: item_spmm<E>(pl, a.X[p], a.Y[p], it.y, it.z, sync); break;
+    }
+    if (tid == 0)
+      s_item[cur ^ 1] = nxt < (uint32_t)a.n_items ? a.items[nxt] : make_int4(-1, 0, 0, 0);
+    __syncthreads();
+    cur ^= 1;
+  }
+  // the last workgroup to finish clears the queue and every counter
+  if (tid == 0) {
+    release();
+    const uint32_t d = __hip_atomic_fetch_add(sync + EXEC_SYNC_DONE, 1u, __ATOMIC_ACQ_REL,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+    s_flag = d == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (s_flag) {
+    acquire();
+    for (int i = tid; i < a.n_sync; i += EXEC_THREADS)
+      if (i != EXEC_SYNC_ERR) sync[i] = 0u;
+  }
+}
+
+template <typename K>
+void set_lds(K kernel, size_t bytes) {
+  SPT_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+}
+
+template <typename E>
+size_t lds_of() {
+  return (size_t)EXEC_POINTS * sizeof(cplx_t<typename E::T>);
+}
+
+template <typename E>
+int occupancy_of() {
+  int n = 0;
+  SPT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      &n, reinterpret_cast<const void*>(exec_kernel<E>), EXEC_THREADS, lds_of<E>()));
+  return n;
+}
+
+}  // namespace
+
+void init_exec_kernels() {
+  static std::vector<int> done;
+  int dev = 0;
+  SPT_HIP(hipGetDevice(&dev));
+  for (int d : done)
+    if (d == dev) return;
+  set_lds(exec_kernel<EngF64>, lds_of<EngF64>());
+  set_lds(exec_kernel<EngF32>, lds_of<EngF32>());
+  set_lds(exec_kernel<EngSplitBf16>, lds_of<EngSplitBf16>());
+  done.push_back(dev);
+}
+
+int exec_occupancy(int engine) {
+  switch (engine) {
+    case 0: return occupancy_of<EngF64>();
+    case 1: return occupancy_of<EngF32>();
+    default: return occupancy_of<EngSplitBf16>();
+  }
+}
+
+template <>
+void launch_exec<double>(const ExecArgs<double>& a, int engine, int grid, hipStream_t s) {
+  (void)engine;
+  hipLaunchKernelGGL(exec_kernel<EngF64>, dim3(grid), dim3(EXEC_THREADS), lds_of<EngF64>(), s, a);
+  SPT_HIP(hipGetLastError());
+}
+
+template <>
+void launch_exec<float>(const ExecArgs<float>& a, int engine, int grid, hipStream_t s) {
+  if (engine == 2)
+    hipLaunchKernelGGL(exec_kernel<EngSplitBf16>, dim3(grid), dim3(EXEC_THREADS),
+                       lds_of<EngSplitBf16>(), s, a);
+  else
+    hipLaunchKernelGGL(exec_kernel<EngF32>, dim3(grid), dim3(EXEC_THREADS), lds_of<EngF32>(), s,
+                       a);
+  SPT_HIP(hipGetLastError());
+}
+
+}  // namespace spt

@@ -1,0 +1,241 @@
+// Device building blocks of the FFTs (shared by the FFT kernels and the
+// persistent executor): complex helpers, in-register DFTs of radix 2, 3, 4, 5
+// and 8, a batched LDS Stockham radix pass, and the unpacking of a packed real
+// transform into its half spectrum.
+//
+// Conventions: F of eq. (1) has the kernel exp(-2 pi i jk/L)/sqrt(L) (SIGN -1,
+// used by the precomputation A_e W F); the computation stage applies F*
+// (SIGN +1).  The pass twiddles exp(+2 pi i q/Pt) come from two float64 tables
+// of 128 + Pt/128 entries for the block's length Pt (w^q = lo[q % 128]
+// hi[q / 128]); a sub-transform of length P < Pt uses index q * (Pt / P).  A
+// butterfly forms w^jm once and its powers in float64, for every precision.
+// SIGN -1 uses the conjugates.
+#pragma once
+
+#include "common.hpp"
+
+namespace spt {
+namespace fftcore {
+
+template <typename C>
+__device__ __forceinline__ C cadd(C a, C b) { return C{a.x + b.x, a.y + b.y}; }
+template <typename C>
+__device__ __forceinline__ C csub(C a, C b) { return C{a.x - b.x, a.y - b.y}; }
+template <typename C>
+__device__ __forceinline__ C cmul(C a, C b) {
+  return C{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+// multiply by SIGN * i
+template <int SIGN, typename C>
+__device__ __forceinline__ C mul_si(C a) {
+  return SIGN > 0 ? C{-a.y, a.x} : C{a.y, -a.x};
+}
+
+// In-register DFTs X_k = sum_n x_n exp(SIGN 2 pi i n k / R).
+template <int SIGN, int R, typename C>
+struct Dft;
+
+template <int SIGN, typename C>
+struct Dft<SIGN, 2, C> {
+  __device__ __forceinline__ static void run(C* v) {
+    C a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+  }
+};
+
+template <int SIGN, typename C>
+struct Dft<SIGN, 4, C> {
+  __device__ __forceinline__ static void run(C* v) {
+    C s02 = cadd(v[0], v[2]), d02 = csub(v[0], v[2]);
+    C s13 = cadd(v[1], v[3]), d13 = mul_si<SIGN>(csub(v[1], v[3]));
+    v[0] = cadd(s02, s13);
+    v[2] = csub(s02, s13);
+    v[1] = cadd(d02, d13);
+    v[3] = csub(d02, d13);
+  }
+};
+
+template <int SIGN, typename C>
+struct Dft<SIGN, 8, C> {
+  __device__ __forceinline__ static void run(C* v) {
+    using T = decltype(v[0].x);
+    const T h = T(0.70710678118654752440);  // 1/sqrt(2)
+    C e[4] = {v[0], v[2], v[4], v[6]};
+    C o[4] = {v[1], v[3], v[5], v[7]};
+    Dft<SIGN, 4, C>::run(e);
+    Dft<SIGN, 4, C>::run(o);
+    // o_k *= exp(SIGN i pi k / 4)
+    C o1 = C{h * (o[1].x - SIGN * o[1].y), h * (o[1].y + SIGN * o[1].x)};
+    C o2 = mul_si<SIGN>(o[2]);
+    C o3 = C{h * (-o[3].x - SIGN * o[3].y), h * (-o[3].y + SIGN * o[3].x)};
+    v[0] = cadd(e[0], o[0]);
+    v[4] = csub(e[0], o[0]);
+    v[1] = cadd(e[1], o1);
+    v[5] = csub(e[1], o1);
+    v[2] = cadd(e[2], o2);
+    v[6] = csub(e[2], o2);
+    v[3] = cadd(e[3], o3);
+    v[7] = csub(e[3], o3);
+  }
+};
+
+template <int SIGN, typename C>
+struct Dft<SIGN, 3, C> {
+  __device__ __forceinline__ static void run(C* v) {
+    using T = decltype(v[0].x);
+    const T s3 = T(0.86602540378443864676);  // sqrt(3)/2
+    C t = cadd(v[1], v[2]);
+    C d = csub(v[1], v[2]);
+    C m = C{v[0].x - T(0.5) * t.x, v[0].y - T(0.5) * t.y};
+    C r = mul_si<SIGN>(C{s3 * d.x, s3 * d.y});
+    v[0] = cadd(v[0], t);
+    v[1] = cadd(m, r);
+    v[2] = csub(m, r);
+  }
+};
+
+template <int SIGN, typename C>
+struct Dft<SIGN, 5, C> {
+  __device__ __forceinline__ static void run(C* v) {
+    using T = decltype(v[0].x);
+    const T c1 = T(0.30901699437494742410);   // cos(2 pi/5)
+    const T c2 = T(-0.80901699437494742410);  // cos(4 pi/5)
+    const T s1 = T(0.95105651629515357212);   // sin(2 pi/5)
+    const T s2 = T(0.58778525229247312917);   // sin(4 pi/5)
+    C t1 = cadd(v[1], v[4]), t2 = cadd(v[2], v[3]);
+    C d1 = csub(v[1], v[4]), d2 = csub(v[2], v[3]);
+    C a1 = C{v[0].x + c1 * t1.x + c2 * t2.x, v[0].y + c1 * t1.y + c2 * t2.y};
+    C a2 = C{v[0].x + c2 * t1.x + c1 * t2.x, v[0].y + c2 * t1.y + c1 * t2.y};
+    C b1 = mul_si<SIGN>(C{s1 * d1.x + s2 * d2.x, s1 * d1.y + s2 * d2.y});
+    C b2 = mul_si<SIGN>(C{s2 * d1.x - s1 * d2.x, s2 * d1.y - s1 * d2.y});
+    v[0] = cadd(v[0], cadd(t1, t2));
+    v[1] = cadd(a1, b1);
+    v[4] = csub(a1, b1);
+    v[2] = cadd(a2, b2);
+    v[3] = csub(a2, b2);
+  }
+};
+
+// two-level twiddle table of a length P: tw[i] = exp(2 pi i i / P) for
+// i < TW_LO, tw[TW_LO + i] = exp(2 pi i TW_LO i / P) for i <= P / TW_LO
+constexpr int TW_LO_BITS = 7;
+constexpr int TW_LO = 1 << TW_LO_BITS;
+// elements of the transforms per thread (workgroups are sized so that
+// threads >= elements / FFT_EPT)
+constexpr int FFT_EPT = 16;
+
+template <typename C>
+__device__ __forceinline__ C to_c(double2 t) {
+  using T = decltype(C{}.x);
+  return C{(T)t.x, (T)t.y};
+}
+
+// w^q of the length-Pt table (two-level, float64)
+__device__ __forceinline__ double2 twiddle(const double2* __restrict__ tw, int q) {
+  return cmul(tw[q & (TW_LO - 1)], tw[TW_LO + (q >> TW_LO_BITS)]);
+}
+
+// One Stockham pass of radix R over 2^lb transforms of length P in LDS (in
+// place through registers).  BATCH == false: one transform, point j at lds[j].
+// BATCH == true: the transforms are interleaved, point j of transform t at
+// lds[(j << lb) + t], so neighbouring lanes touch neighbouring words.
+// Butterflies are spread over the nt threads; requires 2^lb * P <= EPT * nt,
+// so a thread owns at most ceil(EPT / R) butterflies.  tmul scales the
+// twiddle index when P divides the length of the table.
+template <int SIGN, int R, bool BATCH, int EPT, typename C>
+__device__ __forceinline__ void stockham_pass(C* lds, int P, int lb, int Ns,
+                                              const double2* __restrict__ tw, int tmul, int tid,
+                                              int nt, bool active) {
+  constexpr int MAXB = (EPT + R - 1) / R;
+  const int nb = P / R;
+  const int nbt = BATCH ? nb << lb : nb;
+  const int tmask = BATCH ? (1 << lb) - 1 : 0;
+  auto at = [&](int j, int t) { return BATCH ? (j << lb) + t : j; };
+  C v[MAXB][R];
+#pragma unroll
+  for (int b = 0; b < MAXB; ++b) {
+    const int u = tid + b * nt;
+    if (active && u < nbt) {
+      const int j = BATCH ? u >> lb : u, t = u & tmask;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[b][r] = lds[at(j + r * nb, t)];
+    }
+  }
+  __syncthreads();
+  const int stride = P / (Ns * R) * tmul;
+#pragma unroll
+  for (int b = 0; b < MAXB; ++b) {
+    const int u = tid + b * nt;
+    if (active && u < nbt) {
+      const int j = BATCH ? u >> lb : u, t = u & tmask;
+      const int jm = j % Ns;
+      if (Ns > 1) {
+        // w^(jm r) = (w^jm)^r, powers in float64
+        double2 t1 = twiddle(tw, jm * stride);
+        if (SIGN < 0) t1.y = -t1.y;
+        double2 w = t1;
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          v[b][r] = cmul(v[b][r], to_c<C>(w));
+          if (r + 1 < R) w = cmul(w, t1);
+        }
+      }
+      Dft<SIGN, R, C>::run(v[b]);
+      const int base = (j - jm) * R + jm;
+#pragma unroll
+      for (int r = 0; r < R; ++r) lds[at(base + r * Ns, t)] = v[b][r];
+    }
+  }
+  __syncthreads();
+}
+
+// all passes; threads with active == false only take part in the barriers
+template <int SIGN, bool BATCH, int EPT = FFT_EPT, typename C>
+__device__ __forceinline__ void run_fft(C* lds, int P, int lb, int npass, const int* radix,
+                        const double2* __restrict__ tw, int tmul, int tid, int nt, bool active) {
+  int Ns = 1;
+  for (int p = 0; p < npass; ++p) {
+    const int R = radix[p];
+    switch (R) {
+      case 8: stockham_pass<SIGN, 8, BATCH, EPT>(lds, P, lb, Ns, tw, tmul, tid, nt, active); break;
+      case 4: stockham_pass<SIGN, 4, BATCH, EPT>(lds, P, lb, Ns, tw, tmul, tid, nt, active); break;
+      case 2: stockham_pass<SIGN, 2, BATCH, EPT>(lds, P, lb, Ns, tw, tmul, tid, nt, active); break;
+      case 5: stockham_pass<SIGN, 5, BATCH, EPT>(lds, P, lb, Ns, tw, tmul, tid, nt, active); break;
+      default: stockham_pass<SIGN, 3, BATCH, EPT>(lds, P, lb, Ns, tw, tmul, tid, nt, active); break;
+    }
+    Ns *= R;
+  }
+}
+
+template <int SIGN, typename C>
+__device__ __forceinline__ void run_fft(C* lds, const FftPlan& fp, const double2* __restrict__ tw,
+                                        int tid, int nt) {
+  run_fft<SIGN, false, FFT_EPT>(lds, fp.P, 0, fp.npass, fp.radix, tw, 1, tid, nt, true);
+}
+
+// Unpack the packed length-P transform C into the half spectrum of the real
+// length-2P vector: Z_k = E_k + exp(SIGN i pi k/P) O_k, with
+// E_k = (C_k + conj C_{P-k})/2 and O_k = (C_k - conj C_{P-k})/(2i);
+// t = exp(+i pi k/P).
+template <int SIGN, typename C, typename T>
+__device__ __forceinline__ C unpack_with(const C* lds, int P, int k, C t, T scale) {
+  C ck = lds[k == P ? 0 : k];
+  C cm = lds[k == 0 ? 0 : P - k];
+  cm.y = -cm.y;
+  C e = C{T(0.5) * (ck.x + cm.x), T(0.5) * (ck.y + cm.y)};
+  C d = C{T(0.5) * (ck.x - cm.x), T(0.5) * (ck.y - cm.y)};
+  C o = C{d.y, -d.x};  // d / i
+  if (SIGN < 0) t.y = -t.y;
+  C z = cadd(e, cmul(t, o));
+  return C{z.x * scale, z.y * scale};
+}
+
+template <int SIGN, typename C, typename T>
+__device__ __forceinline__ C unpack(const C* lds, int P, int k, const C* __restrict__ post,
+                                    T scale) {
+  return unpack_with<SIGN>(lds, P, k, post[k], scale);
+}
+
+}  // namespace fftcore
+}  // namespace spt

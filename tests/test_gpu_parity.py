@@ -297,3 +297,49 @@ def test_batched_matches_single_plans(spt):
             torch.cuda.synchronize()
             for y, ref in zip(Ys, singles):
                 assert np.array_equal(to_host(y), ref), rep
+
+
+# ------------------------------------------------------------------ executors
+@pytest.mark.parametrize("fam,N,eps,R,kw", [
+    ("legendre", 7000, 1e-7, 3, {}),
+    ("chebyshev_t", 5000, 1e-9, 17, {}),
+    ("jacobi", 9000, 1e-7, 2, dict(alpha=-0.5, beta=-0.5))])
+def test_four_step_blocks_fp64(spt, fam, N, eps, R, kw):
+    """First block longer than one workgroup's FFT (P > 4096): the persistent
+    executor runs it as column and row items; F64 parity with the oracle."""
+    say("four-step", fam, N, eps, R, kw)
+    X = workloads.rhs("normal", R, N, 21)
+    p, _ = _check_f64(spt, fam, N, eps, X, **kw)
+    assert p.blocks()[0][0] // 2 > 4096
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2], ids=["f64", "f32", "split_bf16"])
+def test_staged_executor_matches_persistent(spt, prec):
+    """The two-launch executor and the persistent one compute the same stage
+    (different FFT factorisations and summation orders)."""
+    say("staged vs persistent, prec", prec)
+    N, R = 7000, 70
+    X = workloads.rhs("normal", R, N, 31)
+    a = spt.Plan("legendre", N, 1e-7).precompute()
+    b = spt.Plan("legendre", N, 1e-7, executor=spt.EXECUTOR_STAGED).precompute()
+    Ya, Yb = run(spt, a, X, prec), run(spt, b, X, prec)
+    e = rel_rows(Ya, Yb)
+    say("  rel %.3e" % e)
+    assert e <= (1e-13 if prec == spt.F64 else reduced_tol(a))
+
+
+def test_persistent_launches_repeat_exactly(spt):
+    """Counters return to zero after every launch: repeated and interleaved
+    launches (two right-hand-side counts, i.e. two work queues) give identical
+    results and no waits that gave up (those write NaN)."""
+    import torch
+    p = spt.Plan("legendre", 7000, 1e-7).precompute()
+    Xa = to_dev(workloads.rhs("normal", 3, 7000, 41), torch.float32)
+    Xb = to_dev(workloads.rhs("normal", 70, 7000, 42), torch.float32)
+    ya = to_host(p.execute(Xa, prec=spt.SPLIT_BF16))
+    yb = to_host(p.execute(Xb, prec=spt.SPLIT_BF16))
+    assert np.all(np.isfinite(ya)) and np.all(np.isfinite(yb))
+    for i in range(4):
+        say("  repeat", i)
+        assert np.array_equal(to_host(p.execute(Xb, prec=spt.SPLIT_BF16)), yb)
+        assert np.array_equal(to_host(p.execute(Xa, prec=spt.SPLIT_BF16)), ya)
