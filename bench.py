@@ -5,10 +5,12 @@ Workload: the Legendre transform of order N = 16384 (orthonormalised, Gauss-
 Legendre nodes), 64 right-hand sides x ~ N(0, 1) (seed 1), eps1 = 1e-7,
 eps2 = 1e-2, float64 precomputation.  One step = one spt_execute of all 64
 right-hand sides (extend + window + FFT of every block, banded product of every
-block and the direct tail).  The headline value is the split-bf16 path
-(float32 FFT, bfloat16x3 matrix-core product accumulated in float32); the
-float64 and float32 paths are timed beside it on the same plan, and the split
-path's error against the float64 path is reported.
+block and the direct tail): two launches, the FFTs of every block, then the
+banded products.  The headline value is the split-bf16 path (float32 FFT,
+three-piece bfloat16 matrix-core product accumulated in float32); the float64
+and float32 paths are timed beside it on the same plan, the split path's error
+against the float64 path is reported, and the one-launch persistent executor
+is timed on the same workload for comparison.
 
 Prints one JSON line.  --gpus must be 1 (the method is shown on one GPU's
 share; see the design notes for how it shards).
@@ -44,11 +46,29 @@ def timed_steps(fn, steps, warmup):
     return time.perf_counter() - t0
 
 
-def spmm_algorithmic_bytes(plan, R, bc, bx):
-    """Bytes the banded product must move per launch: the kept entries of every
-    block (bc per complex), one int32 band start per row and block, the direct
-    tail (N x t reals) and its t inputs per right-hand side, the half spectra
-    z_i it reads and the outputs y it writes."""
+def algorithmic_bytes(plan, R, bc, bx):
+    """Bytes the whole computation stage must move for R right-hand sides: the
+    kept entries of every block (bc per complex), one int32 band start per row
+    and block, the direct tail (N x t reals), x read and y written once, and the
+    half spectra z_i written by the FFTs and read back by the products."""
+    info = plan.info()
+    N, t = info["N"], info["tail"]
+    spectra = sum(L // 2 + 1 for L, _, _, _ in plan.blocks())
+    return (info["nnz"] * bc + 4 * N * info["n_blocks"] + N * t * bx
+            + R * (N * bx + N * bx + 2 * spectra * bc))
+
+
+def fft_bytes(plan, R, bc, bx):
+    """Bytes of the FFT launch: every block reads its retained columns of x
+    (together about N reals per right-hand side) and writes its half spectrum."""
+    spectra = sum(L // 2 + 1 for L, _, _, _ in plan.blocks())
+    retained = sum(hi - lo for _, _, lo, hi in plan.blocks())
+    return R * (retained * bx + spectra * bc)
+
+
+def product_bytes(plan, R, bc, bx):
+    """Bytes of the banded-product launch: the compressed blocks, band starts
+    and tail, the tail's x columns, the half spectra read, y written."""
     info = plan.info()
     N, t = info["N"], info["tail"]
     spectra = sum(L // 2 + 1 for L, _, _, _ in plan.blocks())
@@ -56,11 +76,37 @@ def spmm_algorithmic_bytes(plan, R, bc, bx):
             + R * (t * bx + N * bx + spectra * bc))
 
 
-def fft_algorithmic_bytes(plan, R, bc, bx):
-    """x read once per block over its retained columns, half spectra written."""
-    spectra = sum(L // 2 + 1 for L, _, _, _ in plan.blocks())
-    retained = sum(hi - lo for _, _, lo, hi in plan.blocks())
-    return R * (retained * bx + spectra * bc)
+KERNEL_SOURCES = ("fft.hip", "spmm.hip", "fft_core.hpp", "spmm_core.hpp", "common.hpp")
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2004_11610_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of a kernel from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy's reading), if it
+    was taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "%s_legendre_n16384_r64.md" % kernel)
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("- ") and ":" in line:
+                k, v = line[2:].split(":", 1)
+                vals[k.strip()] = v.strip().strip("`")
+    if vals.get("kernel sources sha256") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["HBM bytes per launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(w, X, rows_sample=16384):
@@ -134,17 +180,22 @@ def main():
     paths = {"f64": (spt.F64, X64, Y64), "f32": (spt.F32, X32, Y32),
              "split_bf16": (spt.SPLIT_BF16, X32, Ys)}
     res = {}
-    for name, (prec, X, Y) in paths.items():
-        log("time", name)
-        t = timed_steps(lambda: plan.execute(X, Y, prec=prec), args.steps, args.warmup)
-        res[name] = {"ms_per_step": 1e3 * t / args.steps, "value": R * args.steps / t}
-        # per-stage kernel times with HIP events on the execute stream
+
+    def measure(pl, prec, X, Y):
+        t = timed_steps(lambda: pl.execute(X, Y, prec=prec), args.steps, args.warmup)
+        r = {"ms_per_step": 1e3 * t / args.steps, "value": R * args.steps / t}
+        # kernel times with HIP events on the execute stream
         spt.profile_begin()
         for _ in range(args.steps):
-            plan.execute(X, Y, prec=prec)
+            pl.execute(X, Y, prec=prec)
         torch.cuda.synchronize()
         st = spt.profile_end()
-        res[name]["stage_ms"] = {k: v[0] / max(v[1], 1) for k, v in st.items() if v[1]}
+        r["kernel_ms"] = {k: v[0] / max(v[1], 1) for k, v in st.items() if v[1]}
+        return r
+
+    for name, (prec, X, Y) in paths.items():
+        log("time", name)
+        res[name] = measure(plan, prec, X, Y)
         log(name, res[name])
     torch.cuda.synchronize()
     y64 = Y64.cpu().numpy()
@@ -153,16 +204,31 @@ def main():
         y = Y.double().cpu().numpy()
         err[name] = float(np.max(np.linalg.norm(y - y64, axis=1) / np.linalg.norm(y64, axis=1)))
     log("errors vs f64", err)
+    # the one-launch persistent executor on the same workload, for comparison
+    pers = spt.Plan("legendre", N, w["eps"], executor=spt.EXECUTOR_PERSISTENT).precompute()
+    log("time split_bf16, persistent executor")
+    Yp = torch.empty_like(X32)
+    res_pers = measure(pers, spt.SPLIT_BF16, X32, Yp)
+    log("persistent", res_pers)
+    pers.close()
 
     split = res["split_bf16"]
-    spmm_ms = split["stage_ms"]["spmm"]
-    bytes_spmm = spmm_algorithmic_bytes(plan, R, 8, 4)
-    achieved = bytes_spmm / (spmm_ms * 1e-3) / 1e9
-    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-            "kernel": "spmm_split_bf16_kernel", "bytes_per_launch": bytes_spmm,
-            "avg_launch_ms": spmm_ms}
-    fft_ms = split["stage_ms"].get("fft")
+    km = split["kernel_ms"]
+    # the dominant launch of the step (the FFT launch) and the product launch
+    launches = {"fft": ("exec_fft_multi_kernel<float>", fft_bytes(plan, R, 8, 4)),
+                "spmm": ("spmm_mfma_kernel<EngSplitBf16>", product_bytes(plan, R, 8, 4))}
+
+    def roofline(stage):
+        name, nbytes = launches[stage]
+        achieved = nbytes / (km[stage] * 1e-3) / 1e9
+        return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS,
+                "traffic": measured_traffic("fft" if stage == "fft" else "spmm"),
+                "kernel": name, "bytes_per_launch": nbytes, "avg_launch_ms": km[stage]}
+
+    dominant = max(launches, key=lambda k: km.get(k, 0.0))
+    roof = roofline(dominant)
+    other = roofline("spmm" if dominant == "fft" else "fft")
     out = {
         "metric": METRIC,
         "value": split["value"],
@@ -180,13 +246,16 @@ def main():
                    "eps1": w["eps"], "eps2": info["eps2"], "blocks": [b[0] for b in plan.blocks()],
                    "tail": info["tail"], "nnz": info["nnz"], "parallelism": "single-gpu"},
         "paths": {k: {"value": v["value"], "ms_per_step": v["ms_per_step"],
-                      "stage_ms": v["stage_ms"]} for k, v in res.items()},
+                      "kernel_ms": v["kernel_ms"]} for k, v in res.items()},
+        "split_bf16_persistent_executor": {"value": res_pers["value"],
+                                           "ms_per_step": res_pers["ms_per_step"],
+                                           "kernel_ms": res_pers["kernel_ms"]},
         "split_vs_f64": split["value"] / res["f64"]["value"],
         "rel_err_vs_f64": err,
         "roofline": roof,
-        "fft_roofline": None if fft_ms is None else {
-            "achieved": fft_algorithmic_bytes(plan, R, 8, 4) / (fft_ms * 1e-3) / 1e9,
-            "peak": HBM_PEAK_GBS, "unit": "GB/s", "avg_launch_ms": fft_ms},
+        "roofline_other_launch": other,
+        "stage_bytes_per_step": algorithmic_bytes(plan, R, 8, 4),
+        "kernel_sources_sha256": kernel_source_hash(),
         "precompute_s": t_pre,
     }
     if not args.no_cpu_baseline:

@@ -97,13 +97,14 @@ typedef enum {
 
 /* How spt_execute runs the computation stage. */
 typedef enum {
-  SPT_EXECUTOR_PERSISTENT = 0, /* one launch: a persistent grid takes work items
+  SPT_EXECUTOR_AUTO = 0,       /* STAGED when every block's FFT half-length is at
+                                  most 12288, else PERSISTENT                   */
+  SPT_EXECUTOR_STAGED = 1,     /* two launches: all FFTs, then all products     */
+  SPT_EXECUTOR_PERSISTENT = 2  /* one launch: a persistent grid takes work items
                                   (FFTs of every block, four-step FFTs of long
                                   blocks, banded-product tiles) from a queue, a
-                                  tile's product of a block starting as soon as
-                                  that block's spectra are complete            */
-  SPT_EXECUTOR_STAGED = 1      /* two launches: all FFTs, then all products;
-                                  FFT half-lengths up to 12288                 */
+                                  tile's product of a block starting once that
+                                  block's spectra are complete                 */
 } spt_executor;
 
 /* Plan parameters.  A zero-filled struct selects every default. */

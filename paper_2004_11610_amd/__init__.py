@@ -15,7 +15,7 @@ from ._lib import SptError  # noqa: F401
 CHEBYSHEV_T, LEGENDRE, JACOBI, LAGUERRE_FN, HERMITE_FN = 1, 2, 3, 4, 5
 F64, F32, SPLIT_BF16 = 0, 1, 2
 MODE_AUTO, MODE_ROW, MODE_DIRECT = 0, 1, 3
-EXECUTOR_PERSISTENT, EXECUTOR_STAGED = 0, 1
+EXECUTOR_AUTO, EXECUTOR_STAGED, EXECUTOR_PERSISTENT = 0, 1, 2
 FAMILIES = {"chebyshev_t": CHEBYSHEV_T, "legendre": LEGENDRE, "jacobi": JACOBI,
             "laguerre_fn": LAGUERRE_FN, "hermite_fn": HERMITE_FN}
 PRECISIONS = {"f64": F64, "f32": F32, "split_bf16": SPLIT_BF16}
@@ -43,7 +43,7 @@ class Plan:
 
     def __init__(self, family, N, eps, alpha=0.0, beta=0.0, eps2=0.0, mode=MODE_AUTO,
                  unweighted=False, precisions=0, min_block=0, exact_fft_len=False,
-                 panel_rows=0, nodes=None, executor=EXECUTOR_PERSISTENT):
+                 panel_rows=0, nodes=None, executor=EXECUTOR_AUTO):
         self._lib = _lib.load()
         self._h = c_void_p()
         p = _lib.SptParams()

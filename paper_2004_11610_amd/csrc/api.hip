@@ -881,6 +881,17 @@ void staged(int stage, hipStream_t s, F&& fn) {
 }
 
 // ---------------------------------------------------------------- persistent executor
+// the staged kernels hold a block's whole transform in one workgroup
+bool uses_staged(spt_plan_t plan) {
+  if (plan->p.executor == SPT_EXECUTOR_PERSISTENT) return false;
+  bool fits = true;
+  for (auto& B : plan->blk) fits = fits && B->P <= STAGED_MAX_P;
+  if (plan->p.executor == SPT_EXECUTOR_STAGED && !fits)
+    throw Error(SPT_E_UNSUPPORTED, "the staged executor needs FFT half-lengths <= " +
+                                       std::to_string(STAGED_MAX_P));
+  return fits;
+}
+
 template <typename T>
 void run_exec(ExecCtx& c, const void* const* X, void* const* Y, int count, int prec,
               hipStream_t s) {
@@ -969,7 +980,7 @@ spt_status spt_plan_create(spt_plan_t* out, int32_t family, const spt_params* p,
     if (prm.mode != SPT_MODE_AUTO && prm.mode != SPT_MODE_ROW && prm.mode != SPT_MODE_DIRECT)
       throw Error(SPT_E_INVALID_ARG, "unknown mode");
     if (prm.precisions & ~7u) throw Error(SPT_E_INVALID_ARG, "unknown precision bits");
-    if (prm.executor != SPT_EXECUTOR_PERSISTENT && prm.executor != SPT_EXECUTOR_STAGED)
+    if (prm.executor < SPT_EXECUTOR_AUTO || prm.executor > SPT_EXECUTOR_PERSISTENT)
       throw Error(SPT_E_INVALID_ARG, "unknown executor");
     if (prm.min_block < 0 || prm.panel_rows < 0) throw Error(SPT_E_INVALID_ARG, "negative size");
     auto plan = std::make_unique<spt_plan>();
@@ -1043,7 +1054,7 @@ spt_status spt_execute(spt_plan_t plan, const void* X, void* Y, int64_t nrhs, in
     check_exec(plan, X, Y, nrhs, prec);
     set_device(plan);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    if (plan->p.executor == SPT_EXECUTOR_STAGED) {
+    if (uses_staged(plan)) {
       if (prec == SPT_F64)
         execute_staged_t<double>(plan, (const double*)X, (double*)Y, nrhs, prec, s);
       else

@@ -23,6 +23,9 @@ constexpr int SPMM_GROUP = 4;
 constexpr int MAX_BLOCKS = 24;
 // Largest FFT radix pass count.
 constexpr int MAX_PASSES = 16;
+// longest FFT half-length of the single-workgroup (staged) transforms: a
+// float64 transform of P points fills P * 16 bytes of the 160 KiB LDS
+constexpr int STAGED_MAX_P = 10240;
 
 struct Error : std::runtime_error {
   spt_status code;

@@ -40,14 +40,43 @@ __device__ bool wait_count(uint32_t* sync, const uint32_t* p, uint32_t target) {
 __device__ __forceinline__ void acquire() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
 __device__ __forceinline__ void release() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
 
+// Publication by a workgroup: every wave waits for its own memory operations
+// (its global stores have then reached the L2 of its XCD), a barrier, and one
+// agent-scope release by thread 0 (which writes the L2 back for the other
+// XCDs) before the counter update.  The cache-wide write-back then happens
+// once per item instead of once per wave.
+__device__ __forceinline__ void publish_prologue() {
+  __builtin_amdgcn_s_waitcnt(0);
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __syncthreads();
+}
+
+// Workgroup-wide wait: thread 0 polls, acquires for the workgroup (the
+// invalidation covers the CU's vector cache and the XCD's L2), and a barrier
+// releases the other waves.  Returns false (for every thread) when the wait
+// gave up.
+__device__ __forceinline__ bool wg_wait(uint32_t* sync, const uint32_t* p, uint32_t target,
+                                        int* s_flag) {
+  if (threadIdx.x < 64) {
+    const bool ok = wait_count(sync, p, target);
+    if (threadIdx.x == 0) {
+      acquire();
+      *s_flag = ok;
+    }
+  }
+  __syncthreads();
+  const bool ok = *s_flag != 0;
+  __syncthreads();  // s_flag is reused by the next wait
+  return ok;
+}
+
 __device__ __forceinline__ uint32_t udiv(uint32_t u, uint32_t magic) {
   return __umulhi(u, magic);
 }
 
 // all threads: publish this workgroup's global writes, then thread 0 adds n
 __device__ __forceinline__ void signal(uint32_t* p, uint32_t n) {
-  release();
-  __syncthreads();
+  publish_prologue();
   if (threadIdx.x == 0 && n) __hip_atomic_fetch_add(p, n, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
@@ -129,8 +158,7 @@ __device__ __forceinline__ void item_fft(const ExecPlan<T>& pl, const ExecBlock<
     }
   }
   // one count per complete rhs, per group of 16
-  release();
-  __syncthreads();
+  publish_prologue();
   if (tid == 0) {
     const int r1 = min(r0 + nt, R);
     for (int g = r0 >> 4; g <= (r1 - 1) >> 4; ++g) {
@@ -209,13 +237,7 @@ __device__ __forceinline__ void item_row(const ExecPlan<T>& pl, const ExecBlock<
   const int ls = B.lgp + 1, ns = 1 << ls;
   const int npairs = P1 / 2 + 1;
   const int j0 = grp << B.lgp;
-  if (tid < 64) {  // wave 0 waits
-    const bool ok = wait_count(sync, sync + B.cctr + r, (uint32_t)B.n_col);
-    if (tid == 0) *s_flag = ok;
-  }
-  __syncthreads();
-  acquire();
-  const bool ok = *s_flag != 0;
+  const bool ok = wg_wait(sync, sync + B.cctr + r, (uint32_t)B.n_col, s_flag);
   const uint32_t total = (uint32_t)P2 << ls;
   const C* __restrict__ W = pl.W + (int64_t)pl.R * B.woff + (int64_t)r * P;
   auto row_of = [&](int s, bool& valid) {
@@ -291,7 +313,8 @@ __device__ __forceinline__ void item_row(const ExecPlan<T>& pl, const ExecBlock<
 // right-hand sides r0 + 16 (w % 4) ..
 template <typename E>
 __device__ __forceinline__ void item_spmm(const ExecPlan<typename E::T>& pl, const typename E::T* __restrict__ X,
-                          typename E::T* __restrict__ Y, int tile0, int r0, uint32_t* sync) {
+                          typename E::T* __restrict__ Y, int tile0, int r0, uint32_t* sync,
+                          int* s_flag) {
   using T = typename E::T;
   using C = cplx_t<T>;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -299,9 +322,9 @@ __device__ __forceinline__ void item_spmm(const ExecPlan<typename E::T>& pl, con
   const int R = pl.R;
   const int tile = tile0 + (wave >> 2);
   const int r_wave = r0 + (wave & 3) * 16;
-  if (r_wave >= R || tile >= pl.n_tiles) return;
-  const int grp = r_wave >> 4;
-  const int nvalid = min(16, R - r_wave);
+  // waves without work still take part in the workgroup's waits
+  const bool active = r_wave < R && tile < pl.n_tiles;
+  const int g0 = r0 >> 4, g1 = (min(r0 + 64, R) - 1) >> 4;  // rhs groups of the item
   const int m = lane & 15, g = lane >> 4;
   const int r = r_wave + m;
   const bool rok = r < R;
@@ -312,7 +335,7 @@ __device__ __forceinline__ void item_spmm(const ExecPlan<typename E::T>& pl, con
   int k0_l = 0, kw_l = 0, ldz_l = 0, ctr_l = 0, parts_l = 0;
   int64_t off_l = 0, val_l = 0, zoff_l = 0;
   if (lane < nblk) {
-    const TileMeta tm = pl.meta[(int64_t)tile * nblk + lane];
+    const TileMeta tm = active ? pl.meta[(int64_t)tile * nblk + lane] : TileMeta{0, 0, 0};
     const ExecBlock<T>& bd = pl.blocks[lane];
     k0_l = tm.k0;
     kw_l = tm.kw;
@@ -329,7 +352,7 @@ __device__ __forceinline__ void item_spmm(const ExecPlan<typename E::T>& pl, con
   const int64_t n0 = (int64_t)tile * TILE_ROWS;
   const int64_t ldt = (int64_t)pl.n_tiles * TILE_ROWS;
   const T* __restrict__ xr = X + rr * pl.N;
-  for (int ks = 0; ks < pl.tail; ks += 32) {
+  for (int ks = 0; active && ks < pl.tail; ks += 32) {
     T av[8], xv[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
@@ -343,15 +366,30 @@ __device__ __forceinline__ void item_spmm(const ExecPlan<typename E::T>& pl, con
 
   bool ok = true;
   for (int b = nblk - 1; b >= 0; --b) {
-    const int kw = lane_i32(kw_l, b);
+    // every group of the item complete for block b (thread 0 waits for all)
+    {
+      const ExecBlock<T>& bd = pl.blocks[b];
+      bool okb = true;
+      if (threadIdx.x < 64) {
+        for (int g2 = g0; g2 <= g1; ++g2) {
+          const uint32_t need = (uint32_t)(bd.parts * min(16, R - 16 * g2));
+          if (!wait_count(sync, sync + bd.ctr + g2, need)) okb = false;
+        }
+        if (threadIdx.x == 0) {
+          acquire();
+          *s_flag = okb;
+        }
+      }
+      __syncthreads();
+      if (!*s_flag) ok = false;
+      __syncthreads();
+    }
+    const int kw = active ? lane_i32(kw_l, b) : 0;
     if (kw == 0) continue;
     const int k0 = lane_i32(k0_l, b);
     const C* __restrict__ val = (const C*)(uintptr_t)lane_i64(val_l, b) + lane_i64(off_l, b);
     const C* __restrict__ zb =
         pl.Z + (int64_t)R * lane_i64(zoff_l, b) + rr * lane_i32(ldz_l, b) + k0;
-    const uint32_t need = (uint32_t)(lane_i32(parts_l, b) * nvalid);
-    if (!wait_count(sync, sync + lane_i32(ctr_l, b) + grp, need)) ok = false;
-    acquire();
     for (int kk = 0; kk < kw; kk += 16 * E::SB) {
       StepRegs<T> batch[E::SB];
 #pragma unroll
@@ -369,7 +407,7 @@ __device__ __forceinline__ void item_spmm(const ExecPlan<typename E::T>& pl, con
         if (kk + 16 * i < kw) acc = E::step(batch[i].a, batch[i].z, acc);
     }
   }
-  if (rok) {
+  if (active && rok) {
     T* __restrict__ y = Y + (int64_t)r * pl.N + n0;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -411,7 +449,7 @@ __global__ __launch_bounds__(EXEC_THREADS) __attribute__((amdgpu_waves_per_eu(4)
       case ITEM_FFT: item_fft<T>(pl, pl.blocks[it.y], a.X[p], it.z, it.w, lds, sync); break;
       case ITEM_COL: item_col<T>(pl, pl.blocks[it.y], a.X[p], it.z, it.w, lds, sync); break;
       case ITEM_ROW: item_row<T>(pl, pl.blocks[it.y], it.z, it.w, lds, sync, &s_flag); break;
-      default: item_spmm<E>(pl, a.X[p], a.Y[p], it.y, it.z, sync); break;
+      default: item_spmm<E>(pl, a.X[p], a.Y[p], it.y, it.z, sync, &s_flag); break;
     }
     if (tid == 0)
       s_item[cur ^ 1] = nxt < (uint32_t)a.n_items ? a.items[nxt] : make_int4(-1, 0, 0, 0);

@@ -83,6 +83,8 @@ def test_direct_mode_plan():
     dict(family="legendre", N=64, eps=1e-7, mode=2),
     dict(family="legendre", N=64, eps=1e-7, precisions=8),
     dict(family="legendre", N=64, eps=1e-7, min_block=-1),
+    dict(family="legendre", N=64, eps=1e-7, executor=3),
+    dict(family="legendre", N=64, eps=1e-7, executor=-1),
 ])
 def test_plan_create_rejects_bad_arguments(args):
     with pytest.raises(spt.SptError) as e:

@@ -309,7 +309,7 @@ def test_four_step_blocks_fp64(spt, fam, N, eps, R, kw):
     executor runs it as column and row items; F64 parity with the oracle."""
     say("four-step", fam, N, eps, R, kw)
     X = workloads.rhs("normal", R, N, 21)
-    p, _ = _check_f64(spt, fam, N, eps, X, **kw)
+    p, _ = _check_f64(spt, fam, N, eps, X, executor=spt.EXECUTOR_PERSISTENT, **kw)
     assert p.blocks()[0][0] // 2 > 4096
 
 
@@ -320,7 +320,7 @@ def test_staged_executor_matches_persistent(spt, prec):
     say("staged vs persistent, prec", prec)
     N, R = 7000, 70
     X = workloads.rhs("normal", R, N, 31)
-    a = spt.Plan("legendre", N, 1e-7).precompute()
+    a = spt.Plan("legendre", N, 1e-7, executor=spt.EXECUTOR_PERSISTENT).precompute()
     b = spt.Plan("legendre", N, 1e-7, executor=spt.EXECUTOR_STAGED).precompute()
     Ya, Yb = run(spt, a, X, prec), run(spt, b, X, prec)
     e = rel_rows(Ya, Yb)
@@ -333,7 +333,7 @@ def test_persistent_launches_repeat_exactly(spt):
     launches (two right-hand-side counts, i.e. two work queues) give identical
     results and no waits that gave up (those write NaN)."""
     import torch
-    p = spt.Plan("legendre", 7000, 1e-7).precompute()
+    p = spt.Plan("legendre", 7000, 1e-7, executor=spt.EXECUTOR_PERSISTENT).precompute()
     Xa = to_dev(workloads.rhs("normal", 3, 7000, 41), torch.float32)
     Xb = to_dev(workloads.rhs("normal", 70, 7000, 42), torch.float32)
     ya = to_host(p.execute(Xa, prec=spt.SPLIT_BF16))
