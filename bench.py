@@ -214,9 +214,10 @@ def main():
 
     split = res["split_bf16"]
     km = split["kernel_ms"]
-    # the dominant launch of the step (the FFT launch) and the product launch
-    launches = {"fft": ("exec_fft_multi_kernel<float>", fft_bytes(plan, R, 8, 4)),
-                "spmm": ("spmm_mfma_kernel<EngSplitBf16>", product_bytes(plan, R, 8, 4))}
+    # the two launches of the split-bf16 step: spectra and matrix travel as
+    # three bfloat16 pieces (12 bytes per complex value), x and y as float32
+    launches = {"fft": ("exec_fft_multi_kernel<float, split>", fft_bytes(plan, R, 12, 4)),
+                "spmm": ("spmm_presplit_kernel", product_bytes(plan, R, 12, 4))}
 
     def roofline(stage):
         name, nbytes = launches[stage]
@@ -254,7 +255,7 @@ def main():
         "rel_err_vs_f64": err,
         "roofline": roof,
         "roofline_other_launch": other,
-        "stage_bytes_per_step": algorithmic_bytes(plan, R, 8, 4),
+        "stage_bytes_per_step": algorithmic_bytes(plan, R, 12, 4),
         "kernel_sources_sha256": kernel_source_hash(),
         "precompute_s": t_pre,
     }

@@ -97,9 +97,10 @@ typedef enum {
 
 /* How spt_execute runs the computation stage. */
 typedef enum {
-  SPT_EXECUTOR_AUTO = 0,       /* STAGED when every block's FFT half-length is at
-                                  most 12288, else PERSISTENT                   */
-  SPT_EXECUTOR_STAGED = 1,     /* two launches: all FFTs, then all products     */
+  SPT_EXECUTOR_AUTO = 0,       /* STAGED (the faster one on MI355X)             */
+  SPT_EXECUTOR_STAGED = 1,     /* launches in stream order: the FFTs of every
+                                  block (four-step ones in two launches), then
+                                  all banded products                          */
   SPT_EXECUTOR_PERSISTENT = 2  /* one launch: a persistent grid takes work items
                                   (FFTs of every block, four-step FFTs of long
                                   blocks, banded-product tiles) from a queue, a

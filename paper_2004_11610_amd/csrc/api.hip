@@ -72,15 +72,17 @@ struct DevBlock {
   BlockGeom g;
   int P = 0;
   FftPlan fft;
-  DevBuf winv64, winv32, tw64, post64, post32;
+  DevBuf winv64, winv32, tw64, post64, post32, posttw;
   DevBuf k0, kw, off;   // per tile
   DevBuf val64, val32;  // tile boxes
+  DevBuf valbf, soff;   // pre-split tile boxes of the split-bf16 path, their offsets
   int64_t nnz = 0, stored = 0;
   int max_band = 0;
   double maxabs = 0.0;
   double kappa = 0.0;
   std::vector<int32_t> h_k0, h_kw;
-  std::vector<int64_t> h_off;
+  std::vector<int64_t> h_off, h_soff;
+  int ldz4 = 0;  // P + 1 rounded up to a multiple of 4 (pre-split spectra)
   // persistent executor: one workgroup per batch of transforms (four == 0) or
   // a four-step transform P = P1 * P2 (COL and ROW items)
   int four = 0, P1 = 0, P2 = 0, lcw = 0, lgp = 0, n_col = 0, n_row = 0;
@@ -92,6 +94,9 @@ struct ExecCtx {
   std::vector<int64_t> key;
   DevBuf plans, blocks, items, sync;
   int n_items = 0, n_sync = 0, grid = 0;
+  DevBuf items2;  // staged FFT: the row items (second launch)
+  int n_items2 = 0;
+  int ntw = 0;     // largest twiddle table (entries) of the blocks
 };
 
 bool is_jacobi(int f) { return f == SPT_LEGENDRE || f == SPT_JACOBI; }
@@ -117,11 +122,13 @@ struct spt_plan {
   spt::DevBuf nodes, rowscale, ca, cb;
   double p0 = 0.0;
   std::vector<std::unique_ptr<spt::DevBlock>> blk;
-  spt::DevBuf tail64, tail32;
+  spt::DevBuf tail64, tail32, tailbf;
   spt::DevBuf work;  // execute workspace (half spectra)
   spt::DevBuf fftdesc64, fftdesc32;  // FftDesc per block for the fused FFT launch
   spt::DevBuf tilemeta;              // TileMeta per (tile, block)
   spt::DevBuf spmmblk64, spmmblk32;  // SpmmBlock per block
+  spt::DevBuf tilemeta_bf, spmmblk_bf;  // the same for the pre-split boxes
+  int64_t zper4 = 0;                    // sum of ldz4 over the blocks
   int fft_threads = 64, fft_maxP = 1;
   int64_t work_rhs = 0;
   int64_t serial = 0;  // changes with every precompute (keys of executor contexts)
@@ -267,6 +274,23 @@ void twiddles(int P, std::vector<long double>& twr, std::vector<long double>& tw
   }
 }
 
+// two-level table of exp(i pi k / P), k <= P (the unpack twiddles):
+// lo[q] = exp(i pi q / P), q < 128; hi[q] = exp(i pi 128 q / P), q <= P / 128
+std::vector<double2> post_table(int P) {
+  const long double pi = 3.141592653589793238462643383279502884L;
+  const int lo = 128, nhi = P / lo + 1;
+  std::vector<double2> t(lo + nhi);
+  for (int q = 0; q < lo; ++q) {
+    const long double a = pi * (long double)q / (long double)P;
+    t[q] = double2{(double)cosl(a), (double)sinl(a)};
+  }
+  for (int q = 0; q < nhi; ++q) {
+    const long double a = pi * (long double)(q * lo) / (long double)P;
+    t[lo + q] = double2{(double)cosl(a), (double)sinl(a)};
+  }
+  return t;
+}
+
 size_t max_lds_bytes(int device) {
   int v = 0;
   SPT_HIP(hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, device));
@@ -303,6 +327,7 @@ void build_block(spt_plan_t plan, DevBlock& B, hipStream_t s, size_t lds_max) {
   upload(B.tw64, to_vec2<double2, double>(twr, twi), s);
   upload(B.post64, to_vec2<double2, double>(por, poi), s);
   upload(B.post32, to_vec2<float2, float>(por, poi), s);
+  upload(B.posttw, post_table(P), s);
 
   const int64_t N = plan->N;
   const int64_t ntiles = plan->n_tiles;
@@ -383,8 +408,9 @@ void build_block(spt_plan_t plan, DevBlock& B, hipStream_t s, size_t lds_max) {
       hi = std::max(hi, hhi[n]);
       B.max_band = std::max(B.max_band, hhi[n] - hlo[n] + 1);
     }
-    B.h_k0[t] = hi < 0 ? 0 : lo;
-    B.h_kw[t] = hi < 0 ? 0 : hi - lo + 1;
+    // boxes start at a multiple of 4 columns (16-byte loads of pre-split spectra)
+    B.h_k0[t] = hi < 0 ? 0 : (lo & ~3);
+    B.h_kw[t] = hi < 0 ? 0 : hi - B.h_k0[t] + 1;
     B.h_off[t] = total;
     total += (int64_t)B.h_kw[t] * TILE_ROWS;
   }
@@ -408,6 +434,21 @@ void build_block(spt_plan_t plan, DevBlock& B, hipStream_t s, size_t lds_max) {
                 want64 ? B.val64.as<double2>() : nullptr, want32 ? B.val32.as<float2>() : nullptr,
                 s);
   }
+  // pre-split boxes of the split-bf16 path (3 pieces x 512 bfloat16 per step)
+  B.valbf.reset();
+  B.ldz4 = ((P + 1) + 3) & ~3;
+  B.h_soff.assign(ntiles, 0);
+  int64_t soff = 0;
+  for (int64_t t = 0; t < ntiles; ++t) {
+    B.h_soff[t] = soff;
+    soff += (int64_t)((B.h_kw[t] + 15) / 16) * 3 * 512;
+  }
+  if (plan->prepared & (1u << SPT_SPLIT_BF16)) {
+    upload(B.soff, B.h_soff, s);
+    B.valbf.alloc((size_t)std::max<int64_t>(soff, 1) * sizeof(uint16_t));
+    launch_split_pack(B.val32.as<float2>(), B.kw.as<int32_t>(), B.off.as<int64_t>(),
+                      B.soff.as<int64_t>(), (int)ntiles, B.valbf.as<uint16_t>(), s);
+  }
   SPT_HIP(hipStreamSynchronize(s));
   int64_t nnz = 0;
   for (int64_t n = 0; n < N; ++n) nnz += hcnt[n];
@@ -417,6 +458,7 @@ void build_block(spt_plan_t plan, DevBlock& B, hipStream_t s, size_t lds_max) {
 void build_tail(spt_plan_t plan, hipStream_t s) {
   plan->tail64.reset();
   plan->tail32.reset();
+  plan->tailbf.reset();
   const int64_t t = plan->tail;
   if (t <= 0) return;
   const int64_t ldt = (int64_t)plan->n_tiles * TILE_ROWS;
@@ -426,6 +468,12 @@ void build_tail(spt_plan_t plan, hipStream_t s) {
   if (plan->prepared & ((1u << SPT_F32) | (1u << SPT_SPLIT_BF16))) {
     plan->tail32.alloc((size_t)t * ldt * sizeof(float));
     launch_to_f32(plan->tail64.as<double>(), plan->tail32.as<float>(), t * ldt, s);
+  }
+  if (plan->prepared & (1u << SPT_SPLIT_BF16)) {
+    const int64_t tsteps = (t + 31) / 32;
+    plan->tailbf.alloc((size_t)plan->n_tiles * tsteps * 3 * 512 * sizeof(uint16_t));
+    launch_split_tail(plan->tail32.as<float>(), ldt, (int)t, plan->n_tiles,
+                      plan->tailbf.as<uint16_t>(), s);
   }
   SPT_HIP(hipStreamSynchronize(s));
 }
@@ -522,10 +570,14 @@ int64_t w_per_rhs(spt_plan_t plan) {
 
 int engine_of(int prec) { return prec == SPT_F64 ? 0 : prec == SPT_F32 ? 1 : 2; }
 
-// Build the items, descriptors and counters of one launch over `count` plans.
+// Build the items, descriptors and counters of one launch over `count` plans
+// (persistent executor), or the two FFT launches of one plan (staged; with
+// split, the spectra go to the pre-split planes and the four-step
+// intermediates follow them in the workspace).
 template <typename T>
 void build_exec_ctx(ExecCtx& c, const spt_plan_t* plans, const int64_t* R, int count, int prec,
-                    hipStream_t s) {
+                    hipStream_t s, bool staged = false) {
+  const bool split = staged && prec == SPT_SPLIT_BF16;
   using C = cplx_t<T>;
   const bool dbl = std::is_same<T, double>::value;
   std::vector<ExecPlan<T>> ep(count);
@@ -538,15 +590,20 @@ void build_exec_ctx(ExecCtx& c, const spt_plan_t* plans, const int64_t* R, int c
     const int r = (int)R[i];
     const int groups = (r + 15) / 16;
     first[i] = eb.size();
-    int64_t zoff = 0, woff = 0;
+    int64_t zoff = 0, woff = 0, zoff4 = 0;
     for (size_t b = 0; b < plan->blk.size(); ++b) {
       const DevBlock& B = *plan->blk[b];
       ExecBlock<T> e{};
       e.winv = (const T*)(dbl ? B.winv64.p : B.winv32.p);
       e.tw = B.tw64.as<double2>();
+      e.tw2 = B.posttw.as<double2>();
+      e.ntw = 128 + B.P / 128 + 1;
+      c.ntw = std::max(c.ntw, e.ntw);
       e.post = (const C*)(dbl ? B.post64.p : B.post32.p);
       e.val = (const C*)(dbl ? B.val64.p : B.val32.p);
       e.zoff = zoff;
+      e.zoff4 = zoff4;
+      e.ldz4 = B.ldz4;
       e.P = B.P;
       e.m_off = B.g.m_off;
       e.c_lo = B.g.c_lo;
@@ -586,10 +643,16 @@ void build_exec_ctx(ExecCtx& c, const spt_plan_t* plans, const int64_t* R, int c
       }
       eb.push_back(e);
       zoff += B.P + 1;
+      zoff4 += B.ldz4;
     }
     ExecPlan<T>& P = ep[i];
     P.Z = plan->work.as<C>();
     P.W = P.Z + (int64_t)r * zoff;
+    if (split) {
+      P.Zs = plan->work.as<uint32_t>();
+      P.zplane = (int64_t)r * zoff4;
+      P.W = reinterpret_cast<C*>(P.Zs + 3 * P.zplane);
+    }
     P.meta = plan->tilemeta.as<TileMeta>();
     P.tailmat = (const T*)(dbl ? plan->tail64.p : plan->tail32.p);
     P.N = plan->N;
@@ -597,8 +660,10 @@ void build_exec_ctx(ExecCtx& c, const spt_plan_t* plans, const int64_t* R, int c
     P.nblk = (int)plan->blk.size();
     P.n_tiles = plan->n_tiles;
     P.tail = (int)plan->tail;
-    for (int t = 0; t < plan->n_tiles; t += 2)
-      for (int r0 = 0; r0 < r; r0 += 64) spmm.push_back(make_int4(item_head(ITEM_SPMM, i), t, r0, 0));
+    if (!staged)
+      for (int t = 0; t < plan->n_tiles; t += 2)
+        for (int r0 = 0; r0 < r; r0 += 64)
+          spmm.push_back(make_int4(item_head(ITEM_SPMM, i), t, r0, 0));
   }
   upload(c.blocks, eb, s);
   for (int i = 0; i < count; ++i) ep[i].blocks = c.blocks.as<ExecBlock<T>>() + first[i];
@@ -607,8 +672,14 @@ void build_exec_ctx(ExecCtx& c, const spt_plan_t* plans, const int64_t* R, int c
   items.reserve(col.size() + fft.size() + row.size() + spmm.size());
   items.insert(items.end(), col.begin(), col.end());
   items.insert(items.end(), fft.begin(), fft.end());
-  items.insert(items.end(), row.begin(), row.end());
-  items.insert(items.end(), spmm.begin(), spmm.end());
+  if (staged) {
+    // first launch: column and single-workgroup items; second: row items
+    upload(c.items2, row, s);
+    c.n_items2 = (int)row.size();
+  } else {
+    items.insert(items.end(), row.begin(), row.end());
+    items.insert(items.end(), spmm.begin(), spmm.end());
+  }
   upload(c.items, items, s);
   c.n_items = (int)items.size();
   c.n_sync = nsync;
@@ -616,7 +687,9 @@ void build_exec_ctx(ExecCtx& c, const spt_plan_t* plans, const int64_t* R, int c
   SPT_HIP(hipMemsetAsync(c.sync.p, 0, c.sync.bytes, s));
   SPT_HIP(hipStreamSynchronize(s));
   init_exec_kernels();
-  const int occ = std::max(1, exec_occupancy(engine_of(prec)));
+  if (exec_lds_bytes<T>(c.ntw) + 256 > max_lds_bytes(plans[0]->device))
+    throw Error(SPT_E_UNSUPPORTED, "FFT twiddle tables exceed the LDS of a workgroup");
+  const int occ = std::max(1, exec_occupancy(engine_of(prec), c.ntw));
   c.grid = std::max(1, std::min(c.n_items, occ * cu_count(plans[0]->device)));
 }
 
@@ -625,7 +698,7 @@ std::vector<FftDesc<T>> fft_descs(spt_plan_t plan) {
   using C = cplx_t<T>;
   const bool dbl = std::is_same<T, double>::value;
   std::vector<FftDesc<T>> d;
-  int64_t zoff = 0;
+  int64_t zoff = 0, zoff4 = 0;
   for (auto& Bp : plan->blk) {
     DevBlock& B = *Bp;
     FftDesc<T> e{};
@@ -640,8 +713,11 @@ std::vector<FftDesc<T>> fft_descs(spt_plan_t plan) {
     e.c_hi = B.g.c_hi;
     e.ldz = B.P + 1;
     e.scale = (T)(1.0 / std::sqrt((double)B.g.L));
+    e.zoff4 = zoff4;
+    e.ldz4 = B.ldz4;
     d.push_back(e);
     zoff += B.P + 1;
+    zoff4 += B.ldz4;
   }
   return d;
 }
@@ -673,6 +749,21 @@ void build_fft_descs(spt_plan_t plan, hipStream_t s) {
   upload(plan->tilemeta, meta, s);
   upload(plan->spmmblk64, b64, s);
   upload(plan->spmmblk32, b32, s);
+  // pre-split boxes: the same tiles, offsets into the bfloat16 pieces
+  std::vector<TileMeta> meta_bf((size_t)plan->n_tiles * std::max(nblk, 1));
+  std::vector<SpmmSplitBlock> bbf;
+  int64_t zoff4 = 0;
+  for (int b = 0; b < nblk; ++b) {
+    const DevBlock& B = *plan->blk[b];
+    if (!B.h_soff.empty())
+      for (int t = 0; t < plan->n_tiles; ++t)
+        meta_bf[(size_t)t * nblk + b] = TileMeta{B.h_k0[t], B.h_kw[t], B.h_soff[t]};
+    bbf.push_back(SpmmSplitBlock{B.valbf.as<uint16_t>(), zoff4, B.ldz4, 0});
+    zoff4 += B.ldz4;
+  }
+  plan->zper4 = zoff4;
+  upload(plan->tilemeta_bf, meta_bf, s);
+  upload(plan->spmmblk_bf, bbf, s);
 }
 
 void precompute(spt_plan_t plan, hipStream_t s) {
@@ -722,7 +813,12 @@ void precompute(spt_plan_t plan, hipStream_t s) {
 // ---------------------------------------------------------------- execute
 void ensure_work(spt_plan_t plan, int64_t R) {
   const int64_t per = z_per_rhs(plan) + w_per_rhs(plan);
-  const size_t bytes = (size_t)std::max<int64_t>(per, 1) * (size_t)R * sizeof(double2);
+  // complex float64 spectra (and four-step intermediates), or the three
+  // bfloat16-pair planes of the split-bf16 path
+  const size_t bytes =
+      std::max((size_t)std::max<int64_t>(per, 1) * (size_t)R * sizeof(double2),
+               ((size_t)plan->zper4 * 3 * sizeof(uint32_t) + (size_t)w_per_rhs(plan) * sizeof(float2)) *
+                   (size_t)R);
   if (bytes > plan->work.bytes) {
     plan->ctx.clear();  // contexts hold the old workspace address
     plan->work.alloc(bytes);
@@ -745,42 +841,84 @@ void check_exec(spt_plan_t plan, const void* X, const void* Y, int64_t R, int pr
   if (x0 < y0 + n && y0 < x0 + n) throw Error(SPT_E_INVALID_ARG, "X and Y overlap");
 }
 
-// two launches: the fused FFT kernel of every block, then the banded product
+ExecCtx& plan_ctx(spt_plan_t plan, int64_t R, int prec, hipStream_t s, bool staged);
+
+// Staged execution in stream order.  FFTs: when every block's transform fits
+// one workgroup (P <= 10240, the fused kernel's LDS bound in float64), one
+// launch with a workgroup per (block, rhs); otherwise the FFT items, i.e. the
+// single-workgroup transforms and the column halves of the four-step ones, in
+// one launch and the row halves in a second.  Then the banded product.  The
+// split-bf16 path writes and reads the pre-split spectra.
 template <typename T>
 void execute_staged_t(spt_plan_t plan, const T* X, T* Y, int64_t R, int prec, hipStream_t s) {
   using C = cplx_t<T>;
   ensure_work(plan, R);
+  const int nblk = (int)plan->blk.size();
+  const bool split = std::is_same<T, float>::value && prec == SPT_SPLIT_BF16;
+  if (nblk > 0 && plan->fft_maxP <= FUSED_MAX_P) {
+    const FftDesc<T>* d = std::is_same<T, double>::value ? (const FftDesc<T>*)plan->fftdesc64.p
+                                                         : (const FftDesc<T>*)plan->fftdesc32.p;
+    staged(SPT_STAGE_FFT, s, [&] {
+      if constexpr (std::is_same<T, float>::value) {
+        if (split) {
+          launch_exec_fft_multi_split(d, nblk, plan->fft_threads, plan->fft_maxP, X,
+                                      plan->work.as<uint32_t>(), (int64_t)R * plan->zper4,
+                                      (int)R, plan->N, s);
+          return;
+        }
+      }
+      launch_exec_fft_multi<T>(d, nblk, plan->fft_threads, plan->fft_maxP, X, plan->work.as<C>(),
+                               (int)R, plan->N, s);
+    });
+  } else if (nblk > 0) {
+    ExecCtx& c = plan_ctx(plan, R, prec, s, true);
+    ExecArgs<T> a{};
+    a.plans = c.plans.as<ExecPlan<T>>();
+    a.ntw = c.ntw;
+    a.X[0] = X;
+    a.Y[0] = Y;
+    staged(SPT_STAGE_FFT, s, [&] {
+      a.items = c.items.as<int4>();
+      a.n_items = c.n_items;
+      launch_fft_items<T>(a, split, s);
+      a.items = c.items2.as<int4>();
+      a.n_items = c.n_items2;
+      launch_fft_items<T>(a, split, s);
+    });
+  }
+  if constexpr (std::is_same<T, float>::value) {
+    if (split) {
+      SpmmSplitArgs pa{};
+      pa.meta = plan->tilemeta_bf.as<TileMeta>();
+      pa.blocks = plan->spmmblk_bf.as<SpmmSplitBlock>();
+      pa.nblk = nblk;
+      pa.n_tiles = plan->n_tiles;
+      pa.Zs = plan->work.as<uint32_t>();
+      pa.zplane = (int64_t)R * plan->zper4;
+      pa.tail = (int)plan->tail;
+      pa.tailmat = plan->tailbf.as<uint16_t>();
+      pa.X = X;
+      pa.Y = Y;
+      pa.R = (int)R;
+      pa.N = plan->N;
+      staged(SPT_STAGE_SPMM, s, [&] { launch_spmm_presplit(pa, s); });
+      return;
+    }
+  }
   SpmmArgs<T> sa{};
-  sa.nblk = (int)plan->blk.size();
+  sa.nblk = nblk;
   sa.n_tiles = plan->n_tiles;
   sa.meta = plan->tilemeta.as<TileMeta>();
   sa.blocks = std::is_same<T, double>::value ? (const SpmmBlock<T>*)plan->spmmblk64.p
                                              : (const SpmmBlock<T>*)plan->spmmblk32.p;
-  C* const z0 = plan->work.as<C>();
-  sa.Z = z0;
+  sa.Z = plan->work.as<C>();
   sa.tail = (int)plan->tail;
   sa.tailmat = std::is_same<T, double>::value ? (const T*)plan->tail64.p : (const T*)plan->tail32.p;
   sa.X = X;
   sa.Y = Y;
   sa.R = (int)R;
   sa.N = plan->N;
-  if (sa.nblk > 0)
-    staged(SPT_STAGE_FFT, s, [&] {
-      const FftDesc<T>* d = std::is_same<T, double>::value
-                                ? (const FftDesc<T>*)plan->fftdesc64.p
-                                : (const FftDesc<T>*)plan->fftdesc32.p;
-      launch_exec_fft_multi<T>(d, sa.nblk, plan->fft_threads, plan->fft_maxP, X, z0, (int)R,
-                               plan->N, s);
-    });
-  staged(SPT_STAGE_SPMM, s, [&] {
-    if constexpr (std::is_same<T, float>::value) {
-      if (prec == SPT_SPLIT_BF16) {
-        launch_spmm_split_bf16(sa, s);
-        return;
-      }
-    }
-    launch_spmm<T>(sa, s);
-  });
+  staged(SPT_STAGE_SPMM, s, [&] { launch_spmm<T>(sa, s); });
 }
 
 template <typename T>
@@ -881,16 +1019,7 @@ void staged(int stage, hipStream_t s, F&& fn) {
 }
 
 // ---------------------------------------------------------------- persistent executor
-// the staged kernels hold a block's whole transform in one workgroup
-bool uses_staged(spt_plan_t plan) {
-  if (plan->p.executor == SPT_EXECUTOR_PERSISTENT) return false;
-  bool fits = true;
-  for (auto& B : plan->blk) fits = fits && B->P <= STAGED_MAX_P;
-  if (plan->p.executor == SPT_EXECUTOR_STAGED && !fits)
-    throw Error(SPT_E_UNSUPPORTED, "the staged executor needs FFT half-lengths <= " +
-                                       std::to_string(STAGED_MAX_P));
-  return fits;
-}
+bool uses_staged(spt_plan_t plan) { return plan->p.executor != SPT_EXECUTOR_PERSISTENT; }
 
 template <typename T>
 void run_exec(ExecCtx& c, const void* const* X, void* const* Y, int count, int prec,
@@ -901,6 +1030,7 @@ void run_exec(ExecCtx& c, const void* const* X, void* const* Y, int count, int p
   a.sync = c.sync.as<uint32_t>();
   a.n_items = c.n_items;
   a.n_sync = c.n_sync;
+  a.ntw = c.ntw;
   for (int i = 0; i < count; ++i) {
     a.X[i] = static_cast<const T*>(X[i]);
     a.Y[i] = static_cast<T*>(Y[i]);
@@ -909,22 +1039,23 @@ void run_exec(ExecCtx& c, const void* const* X, void* const* Y, int count, int p
 }
 
 std::unique_ptr<ExecCtx> new_ctx(const std::vector<int64_t>& key, const spt_plan_t* plans,
-                                 const int64_t* R, int count, int prec, hipStream_t s) {
+                                 const int64_t* R, int count, int prec, hipStream_t s,
+                                 bool staged = false) {
   auto c = std::make_unique<ExecCtx>();
   c->key = key;
   if (prec == SPT_F64)
-    build_exec_ctx<double>(*c, plans, R, count, prec, s);
+    build_exec_ctx<double>(*c, plans, R, count, prec, s, staged);
   else
-    build_exec_ctx<float>(*c, plans, R, count, prec, s);
+    build_exec_ctx<float>(*c, plans, R, count, prec, s, staged);
   return c;
 }
 
-ExecCtx& plan_ctx(spt_plan_t plan, int64_t R, int prec, hipStream_t s) {
-  const std::vector<int64_t> key{prec, R, plan->serial, (int64_t)(intptr_t)plan->work.p};
+ExecCtx& plan_ctx(spt_plan_t plan, int64_t R, int prec, hipStream_t s, bool staged) {
+  const std::vector<int64_t> key{prec, R, plan->serial, (int64_t)(intptr_t)plan->work.p, staged};
   for (auto& c : plan->ctx)
     if (c->key == key) return *c;
   if (plan->ctx.size() >= 8) plan->ctx.erase(plan->ctx.begin());
-  plan->ctx.push_back(new_ctx(key, &plan, &R, 1, prec, s));
+  plan->ctx.push_back(new_ctx(key, &plan, &R, 1, prec, s, staged));
   return *plan->ctx.back();
 }
 
@@ -1062,7 +1193,7 @@ spt_status spt_execute(spt_plan_t plan, const void* X, void* Y, int64_t nrhs, in
       return;
     }
     ensure_work(plan, nrhs);
-    ExecCtx& c = plan_ctx(plan, nrhs, prec, s);
+    ExecCtx& c = plan_ctx(plan, nrhs, prec, s, false);
     const void* xs[1] = {X};
     void* ys[1] = {Y};
     if (prec == SPT_F64)

@@ -23,9 +23,9 @@ constexpr int SPMM_GROUP = 4;
 constexpr int MAX_BLOCKS = 24;
 // Largest FFT radix pass count.
 constexpr int MAX_PASSES = 16;
-// longest FFT half-length of the single-workgroup (staged) transforms: a
+// longest FFT half-length of the fused one-workgroup-per-transform kernel: a
 // float64 transform of P points fills P * 16 bytes of the 160 KiB LDS
-constexpr int STAGED_MAX_P = 10240;
+constexpr int FUSED_MAX_P = 10240;
 
 struct Error : std::runtime_error {
   spt_status code;
@@ -84,6 +84,8 @@ struct FftDesc {
   FftPlan fp;
   int L, m_off, c_lo, c_hi, ldz;
   T scale;
+  int64_t zoff4;  // the same for the split planes (ldz4 = ldz rounded up to 4)
+  int ldz4;
 };
 
 template <typename T>
@@ -146,6 +148,47 @@ template <typename T>
 void launch_spmm(const SpmmArgs<T>& a, hipStream_t s);
 void launch_spmm_split_bf16(const SpmmArgs<float>& a, hipStream_t s);
 
+// Pre-split storage of the split-bf16 path.  Every value f is kept as three
+// bfloat16 pieces p0 + p1 + p2 (p0 = bf16(f), p1 = bf16(f - p0),
+// p2 = bf16(f - p0 - p1), round to nearest even).
+//  * Tile box of (tile, block), 16-column steps s: piece p of step s is 64
+//    lanes x 8 bfloat16 at val + off + (3 s + p) * 512 + 8 lane; lane l holds
+//    row l % 16, complex columns 16 s + 4 (l / 16) + j / 2 (j < 8), as
+//    (Re, -Im) pairs; columns past kw are zero.
+//  * Half spectra: three planes (plane stride zplane, in complex values);
+//    rhs r of a block at plane + zoff * R + r * ldz, ldz = P + 1 rounded up to
+//    a multiple of 4 (zeros past P); a complex value is a (Re, Im) bfloat16 pair.
+//  * Direct tail: per tile, 32-column steps s, piece p at
+//    tail + ((tile * tsteps + s) * 3 + p) * 512 + 8 lane, lane l holding row
+//    l % 16, tail columns 32 s + 8 (l / 16) + j.
+struct SpmmSplitBlock {
+  const uint16_t* val;
+  int64_t zoff;
+  int32_t ldz;
+  int32_t pad;
+};
+
+struct SpmmSplitArgs {
+  const TileMeta* meta;          // n_tiles x nblk (off in bfloat16 units)
+  const SpmmSplitBlock* blocks;  // nblk
+  int nblk;
+  int n_tiles;
+  const uint32_t* Zs;            // spectra planes of (Re, Im) bfloat16 pairs
+  int64_t zplane;
+  int tail;
+  const uint16_t* tailmat;       // pre-split tail
+  const float* X;
+  float* Y;
+  int R;
+  int64_t N;
+};
+void launch_spmm_presplit(const SpmmSplitArgs& a, hipStream_t s);
+
+// split-bf16 staged FFT: the half spectra go out as the three planes above
+void launch_exec_fft_multi_split(const FftDesc<float>* descs, int nblk, int threads, int max_P,
+                                 const float* X, uint32_t* Zs, int64_t zplane, int R, int64_t N,
+                                 hipStream_t s);
+
 // transposed banded product: u_i = A_i^T f (half spectrum), per block
 template <typename T>
 struct SpmmTArgs {
@@ -200,6 +243,12 @@ void launch_pack(const double2* spec, int64_t row0, int nrows, int64_t N, int P,
                  const int32_t* tile_k0, const int32_t* tile_kw, const int64_t* tile_off,
                  int tile0, double2* val64, float2* val32, hipStream_t s);
 void launch_to_f32(const double* in, float* out, int64_t n, hipStream_t s);
+// pre-split tile boxes from the float32 ones (layout above)
+void launch_split_pack(const float2* val32, const int32_t* tile_kw, const int64_t* tile_off,
+                       const int64_t* tile_soff, int ntiles, uint16_t* valbf, hipStream_t s);
+// pre-split direct tail from the float32 one (column m at tail32 + m * ldt)
+void launch_split_tail(const float* tail32, int64_t ldt, int tail, int ntiles, uint16_t* tailbf,
+                       hipStream_t s);
 void launch_nonfinite(const double* p, int64_t n, int* flag, hipStream_t s);
 
 }  // namespace spt

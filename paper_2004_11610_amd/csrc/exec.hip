@@ -96,14 +96,46 @@ __device__ __forceinline__ T nan_of() {
   return __builtin_nan("");
 }
 
+// copy the block's twiddle tables into LDS (read back after the next barrier)
+template <typename T>
+__device__ __forceinline__ void load_tables(const ExecBlock<T>& B, double2* ltw, bool post) {
+  for (int i = threadIdx.x; i < B.ntw; i += EXEC_THREADS) {
+    ltw[i] = B.tw[i];
+    if (post) ltw[B.ntw + i] = B.tw2[i];
+  }
+}
+
 // ------------------------------------------------------------------ ITEM_FFT
 // 2^lb right-hand sides r0 .. of one block; point j of rhs r0 + t at
 // lds[(j << lb) + t]
-template <typename T>
+// the half-spectrum value k of rhs r: complex, or its three bfloat16 pieces
+template <bool SPLIT, typename T, typename C>
+__device__ __forceinline__ void store_z(const ExecPlan<T>& pl, const ExecBlock<T>& B, int r, int k,
+                                        C z) {
+  if constexpr (SPLIT) {
+    uint32_t pc[3];
+    split2(f32x2{(float)z.x, (float)z.y}, pc);
+    uint32_t* zs = pl.Zs + (int64_t)pl.R * B.zoff4 + (int64_t)r * B.ldz4 + k;
+#pragma unroll
+    for (int p = 0; p < 3; ++p) zs[p * pl.zplane] = pc[p];
+  } else {
+    pl.Z[(int64_t)pl.R * B.zoff + (int64_t)r * (B.P + 1) + k] = z;
+  }
+}
+
+// pre-split spectra are zero past P up to the row length ldz4
+template <bool SPLIT, typename T>
+__device__ __forceinline__ void store_z_pad(const ExecPlan<T>& pl, const ExecBlock<T>& B, int r) {
+  if constexpr (SPLIT)
+    for (int k = B.P + 1; k < B.ldz4; ++k) store_z<true>(pl, B, r, k, cplx_t<T>{T(0), T(0)});
+}
+
+template <typename T, bool SYNC, bool SPLIT>
 __device__ __forceinline__ void item_fft(const ExecPlan<T>& pl, const ExecBlock<T>& B, const T* __restrict__ X,
-                         int r0, int lb, cplx_t<T>* lds, uint32_t* sync) {
+                         int r0, int lb, cplx_t<T>* lds, double2* ltw, uint32_t* sync) {
   using C = cplx_t<T>;
   const int tid = threadIdx.x;
+  load_tables(B, ltw, true);
   const int P = B.P, nt = 1 << lb;
   const uint32_t total = (uint32_t)P << lb;
   const int R = pl.R;
@@ -131,11 +163,10 @@ __device__ __forceinline__ void item_fft(const ExecPlan<T>& pl, const ExecBlock<
     }
   }
   __syncthreads();
-  run_fft<+1, true, EXEC_EPT>(lds, P, lb, B.f1.npass, B.f1.radix, B.tw, 1, tid, EXEC_THREADS,
+  run_fft<+1, true, EXEC_EPT>(lds, P, lb, B.f1.npass, B.f1.radix, ltw, 1, tid, EXEC_THREADS,
                               true);
   // half spectra, k = 0 .. P of every rhs (u = t * (P + 1) + k)
   const uint32_t total1 = (uint32_t)(P + 1) << lb;
-  C* __restrict__ Z = pl.Z + (int64_t)R * B.zoff;
   {
     constexpr int NE = EXEC_EPT + 1;  // (P + 1) 2^lb <= EXEC_POINTS + 64
     C tw[NE];
@@ -143,7 +174,7 @@ __device__ __forceinline__ void item_fft(const ExecPlan<T>& pl, const ExecBlock<
     for (int e = 0; e < NE; ++e) {
       const uint32_t u = tid + e * EXEC_THREADS;
       const int t = (int)udiv(u, B.magic1), k = (int)u - t * (P + 1);
-      tw[e] = u < total1 ? B.post[k] : C{T(0), T(0)};
+      tw[e] = u < total1 ? to_c<C>(twiddle(ltw + B.ntw, k)) : C{T(0), T(0)};
     }
 #pragma unroll
     for (int e = 0; e < NE; ++e) {
@@ -153,10 +184,12 @@ __device__ __forceinline__ void item_fft(const ExecPlan<T>& pl, const ExecBlock<
       if (u < total1 && r < R) {
         const C ck = lds[((k == P ? 0 : k) << lb) + t];
         const C cm = lds[((k == 0 ? 0 : P - k) << lb) + t];
-        Z[(int64_t)r * (P + 1) + k] = unpack_pair(ck, cm, tw[e], B.scale);
+        store_z<SPLIT>(pl, B, r, k, unpack_pair(ck, cm, tw[e], B.scale));
       }
     }
   }
+  if (SPLIT && tid < nt && r0 + tid < R) store_z_pad<SPLIT>(pl, B, r0 + tid);
+  if (!SYNC) return;
   // one count per complete rhs, per group of 16
   publish_prologue();
   if (tid == 0) {
@@ -174,11 +207,12 @@ __device__ __forceinline__ void item_fft(const ExecPlan<T>& pl, const ExecBlock<
 // point n1 of column t at lds[(n1 << lcw) + t] (that is lds[u] for the
 // load order u = (n1 << lcw) + t), length-P1 transforms, then
 // W[k1 * P2 + n2] = (sum_n1 u[P2 n1 + n2] w_P1^(n1 k1)) w_P^(n2 k1).
-template <typename T>
+template <typename T, bool SYNC>
 __device__ __forceinline__ void item_col(const ExecPlan<T>& pl, const ExecBlock<T>& B, const T* __restrict__ X,
-                         int r, int grp, cplx_t<T>* lds, uint32_t* sync) {
+                         int r, int grp, cplx_t<T>* lds, double2* ltw, uint32_t* sync) {
   using C = cplx_t<T>;
   const int tid = threadIdx.x;
+  load_tables(B, ltw, false);
   const int lcw = B.lcw, cw = 1 << lcw;
   const int P1 = B.P1, P2 = B.P2;
   const uint32_t total = (uint32_t)P1 << lcw;
@@ -205,7 +239,7 @@ __device__ __forceinline__ void item_col(const ExecPlan<T>& pl, const ExecBlock<
     }
   }
   __syncthreads();
-  run_fft<+1, true, EXEC_EPT>(lds, P1, lcw, B.f1.npass, B.f1.radix, B.tw, P2, tid, EXEC_THREADS,
+  run_fft<+1, true, EXEC_EPT>(lds, P1, lcw, B.f1.npass, B.f1.radix, ltw, P2, tid, EXEC_THREADS,
                               true);
   C* __restrict__ W = pl.W + (int64_t)pl.R * B.woff + (int64_t)r * B.P;
 #pragma unroll
@@ -214,11 +248,11 @@ __device__ __forceinline__ void item_col(const ExecPlan<T>& pl, const ExecBlock<
     if (u < total) {
       const int t = (int)u & (cw - 1), k1 = (int)(u >> lcw);
       const int n2 = n2base + t;
-      const C w = to_c<C>(twiddle(B.tw, n2 * k1));
+      const C w = to_c<C>(twiddle(ltw, n2 * k1));
       W[(int64_t)k1 * P2 + n2] = cmul(lds[u], w);
     }
   }
-  signal(sync + B.cctr + r, 1);
+  if (SYNC) signal(sync + B.cctr + r, 1);
 }
 
 // ------------------------------------------------------------------ ITEM_ROW
@@ -228,16 +262,17 @@ __device__ __forceinline__ void item_col(const ExecPlan<T>& pl, const ExecBlock<
 // transforms slot s, point k2 is U_k, k = k1 + P1 k2, and its partner
 // U_{P-k} sits in the other slot of the pair at P2 - 1 - k2 (k1 > 0) or in the
 // same slot at (P2 - k2) mod P2 (k1 = 0).
-template <typename T>
+template <typename T, bool SYNC, bool SPLIT>
 __device__ __forceinline__ void item_row(const ExecPlan<T>& pl, const ExecBlock<T>& B, int r, int grp,
-                         cplx_t<T>* lds, uint32_t* sync, int* s_flag) {
+                         cplx_t<T>* lds, double2* ltw, uint32_t* sync, int* s_flag) {
   using C = cplx_t<T>;
   const int tid = threadIdx.x;
+  load_tables(B, ltw, true);
   const int P = B.P, P1 = B.P1, P2 = B.P2;
   const int ls = B.lgp + 1, ns = 1 << ls;
   const int npairs = P1 / 2 + 1;
   const int j0 = grp << B.lgp;
-  const bool ok = wg_wait(sync, sync + B.cctr + r, (uint32_t)B.n_col, s_flag);
+  const bool ok = SYNC ? wg_wait(sync, sync + B.cctr + r, (uint32_t)B.n_col, s_flag) : true;
   const uint32_t total = (uint32_t)P2 << ls;
   const C* __restrict__ W = pl.W + (int64_t)pl.R * B.woff + (int64_t)r * P;
   auto row_of = [&](int s, bool& valid) {
@@ -263,9 +298,8 @@ __device__ __forceinline__ void item_row(const ExecPlan<T>& pl, const ExecBlock<
     }
   }
   __syncthreads();
-  run_fft<+1, true, EXEC_EPT>(lds, P2, ls, B.f2.npass, B.f2.radix, B.tw, P1, tid, EXEC_THREADS,
+  run_fft<+1, true, EXEC_EPT>(lds, P2, ls, B.f2.npass, B.f2.radix, ltw, P1, tid, EXEC_THREADS,
                               true);
-  C* __restrict__ Z = pl.Z + (int64_t)pl.R * B.zoff + (int64_t)r * (P + 1);
   const T nanv = nan_of<T>();
   {
     C tw[EXEC_EPT];
@@ -282,7 +316,7 @@ __device__ __forceinline__ void item_row(const ExecPlan<T>& pl, const ExecBlock<
         own = own && k1 != row_of(s - 1, v2);  // a self-paired row is written by its even slot
       }
       kk[e] = own ? k1 + P1 * k2 : -1;
-      tw[e] = own ? B.post[kk[e]] : C{T(0), T(0)};
+      tw[e] = own ? to_c<C>(twiddle(ltw + B.ntw, kk[e])) : C{T(0), T(0)};
     }
 #pragma unroll
     for (int e = 0; e < EXEC_EPT; ++e) {
@@ -295,17 +329,18 @@ __device__ __forceinline__ void item_row(const ExecPlan<T>& pl, const ExecBlock<
                              : lds[((P2 - 1 - k2) << ls) + (s ^ 1)];
         C z = unpack_pair(ck, cm, tw[e], B.scale);
         if (!ok) z = C{nanv, nanv};
-        Z[kk[e]] = z;
+        store_z<SPLIT>(pl, B, r, kk[e], z);
       }
     }
   }
   if (grp == 0 && tid == 0) {  // k = P: C_P = C_0
     const C c0 = lds[0];
-    C z = unpack_pair(c0, c0, B.post[P], B.scale);
+    C z = unpack_pair(c0, c0, to_c<C>(twiddle(ltw + B.ntw, P)), B.scale);
     if (!ok) z = C{nanv, nanv};
-    Z[P] = z;
+    store_z<SPLIT>(pl, B, r, P, z);
+    store_z_pad<SPLIT>(pl, B, r);
   }
-  signal(sync + B.ctr + (r >> 4), 1);
+  if (SYNC) signal(sync + B.ctr + (r >> 4), 1);
 }
 
 // ------------------------------------------------------------------ ITEM_SPMM
@@ -424,6 +459,7 @@ __global__ __launch_bounds__(EXEC_THREADS) __attribute__((amdgpu_waves_per_eu(4)
   using C = cplx_t<T>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C* lds = reinterpret_cast<C*>(smem_raw);
+  double2* ltw = reinterpret_cast<double2*>(smem_raw + EXEC_POINTS * sizeof(C));
   __shared__ int4 s_item[2];
   __shared__ int s_flag;
   const int tid = threadIdx.x;
@@ -446,9 +482,15 @@ __global__ __launch_bounds__(EXEC_THREADS) __attribute__((amdgpu_waves_per_eu(4)
     const int kind = it.x & 15, p = it.x >> 4;
     const ExecPlan<T>& pl = a.plans[p];
     switch (kind) {
-      case ITEM_FFT: item_fft<T>(pl, pl.blocks[it.y], a.X[p], it.z, it.w, lds, sync); break;
-      case ITEM_COL: item_col<T>(pl, pl.blocks[it.y], a.X[p], it.z, it.w, lds, sync); break;
-      case ITEM_ROW: item_row<T>(pl, pl.blocks[it.y], it.z, it.w, lds, sync, &s_flag); break;
+      case ITEM_FFT:
+        item_fft<T, true, false>(pl, pl.blocks[it.y], a.X[p], it.z, it.w, lds, ltw, sync);
+        break;
+      case ITEM_COL:
+        item_col<T, true>(pl, pl.blocks[it.y], a.X[p], it.z, it.w, lds, ltw, sync);
+        break;
+      case ITEM_ROW:
+        item_row<T, true, false>(pl, pl.blocks[it.y], it.z, it.w, lds, ltw, sync, &s_flag);
+        break;
       default: item_spmm<E>(pl, a.X[p], a.Y[p], it.y, it.z, sync, &s_flag); break;
     }
     if (tid == 0)
@@ -471,6 +513,30 @@ __global__ __launch_bounds__(EXEC_THREADS) __attribute__((amdgpu_waves_per_eu(4)
   }
 }
 
+// FFT items without queue or counters: workgroup b runs item b
+template <typename T, bool SPLIT>
+__global__ __launch_bounds__(EXEC_THREADS) void fft_items_kernel(ExecArgs<T> a) {
+  using C = cplx_t<T>;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C* lds = reinterpret_cast<C*>(smem_raw);
+  double2* ltw = reinterpret_cast<double2*>(smem_raw + EXEC_POINTS * sizeof(C));
+  __shared__ int s_flag;
+  const int4 it = a.items[blockIdx.x];
+  const int kind = it.x & 15, p = it.x >> 4;
+  const ExecPlan<T>& pl = a.plans[p];
+  switch (kind) {
+    case ITEM_FFT:
+      item_fft<T, false, SPLIT>(pl, pl.blocks[it.y], a.X[p], it.z, it.w, lds, ltw, nullptr);
+      break;
+    case ITEM_COL:
+      item_col<T, false>(pl, pl.blocks[it.y], a.X[p], it.z, it.w, lds, ltw, nullptr);
+      break;
+    default:
+      item_row<T, false, SPLIT>(pl, pl.blocks[it.y], it.z, it.w, lds, ltw, nullptr, &s_flag);
+      break;
+  }
+}
+
 template <typename K>
 void set_lds(K kernel, size_t bytes) {
   SPT_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
@@ -478,16 +544,18 @@ void set_lds(K kernel, size_t bytes) {
 }
 
 template <typename E>
-size_t lds_of() {
-  return (size_t)EXEC_POINTS * sizeof(cplx_t<typename E::T>);
-}
-
-template <typename E>
-int occupancy_of() {
+int occupancy_of(size_t lds) {
   int n = 0;
   SPT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-      &n, reinterpret_cast<const void*>(exec_kernel<E>), EXEC_THREADS, lds_of<E>()));
+      &n, reinterpret_cast<const void*>(exec_kernel<E>), EXEC_THREADS, lds));
   return n;
+}
+
+size_t device_lds() {
+  int dev = 0, v = 0;
+  SPT_HIP(hipGetDevice(&dev));
+  SPT_HIP(hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  return (size_t)v;
 }
 
 }  // namespace
@@ -498,24 +566,30 @@ void init_exec_kernels() {
   SPT_HIP(hipGetDevice(&dev));
   for (int d : done)
     if (d == dev) return;
-  set_lds(exec_kernel<EngF64>, lds_of<EngF64>());
-  set_lds(exec_kernel<EngF32>, lds_of<EngF32>());
-  set_lds(exec_kernel<EngSplitBf16>, lds_of<EngSplitBf16>());
+  // the kernels' static LDS (item slots, flags) stays below 256 bytes
+  const size_t lds = device_lds() - 256;
+  set_lds(exec_kernel<EngF64>, lds);
+  set_lds(exec_kernel<EngF32>, lds);
+  set_lds(exec_kernel<EngSplitBf16>, lds);
+  set_lds(fft_items_kernel<double, false>, lds);
+  set_lds(fft_items_kernel<float, false>, lds);
+  set_lds(fft_items_kernel<float, true>, lds);
   done.push_back(dev);
 }
 
-int exec_occupancy(int engine) {
+int exec_occupancy(int engine, int ntw) {
   switch (engine) {
-    case 0: return occupancy_of<EngF64>();
-    case 1: return occupancy_of<EngF32>();
-    default: return occupancy_of<EngSplitBf16>();
+    case 0: return occupancy_of<EngF64>(exec_lds_bytes<double>(ntw));
+    case 1: return occupancy_of<EngF32>(exec_lds_bytes<float>(ntw));
+    default: return occupancy_of<EngSplitBf16>(exec_lds_bytes<float>(ntw));
   }
 }
 
 template <>
 void launch_exec<double>(const ExecArgs<double>& a, int engine, int grid, hipStream_t s) {
   (void)engine;
-  hipLaunchKernelGGL(exec_kernel<EngF64>, dim3(grid), dim3(EXEC_THREADS), lds_of<EngF64>(), s, a);
+  hipLaunchKernelGGL(exec_kernel<EngF64>, dim3(grid), dim3(EXEC_THREADS),
+                     exec_lds_bytes<double>(a.ntw), s, a);
   SPT_HIP(hipGetLastError());
 }
 
@@ -523,10 +597,31 @@ template <>
 void launch_exec<float>(const ExecArgs<float>& a, int engine, int grid, hipStream_t s) {
   if (engine == 2)
     hipLaunchKernelGGL(exec_kernel<EngSplitBf16>, dim3(grid), dim3(EXEC_THREADS),
-                       lds_of<EngSplitBf16>(), s, a);
+                       exec_lds_bytes<float>(a.ntw), s, a);
   else
-    hipLaunchKernelGGL(exec_kernel<EngF32>, dim3(grid), dim3(EXEC_THREADS), lds_of<EngF32>(), s,
-                       a);
+    hipLaunchKernelGGL(exec_kernel<EngF32>, dim3(grid), dim3(EXEC_THREADS),
+                       exec_lds_bytes<float>(a.ntw), s, a);
+  SPT_HIP(hipGetLastError());
+}
+
+template <>
+void launch_fft_items<double>(const ExecArgs<double>& a, bool split, hipStream_t s) {
+  (void)split;
+  if (a.n_items <= 0) return;
+  hipLaunchKernelGGL((fft_items_kernel<double, false>), dim3(a.n_items), dim3(EXEC_THREADS),
+                     exec_lds_bytes<double>(a.ntw), s, a);
+  SPT_HIP(hipGetLastError());
+}
+
+template <>
+void launch_fft_items<float>(const ExecArgs<float>& a, bool split, hipStream_t s) {
+  if (a.n_items <= 0) return;
+  if (split)
+    hipLaunchKernelGGL((fft_items_kernel<float, true>), dim3(a.n_items), dim3(EXEC_THREADS),
+                       exec_lds_bytes<float>(a.ntw), s, a);
+  else
+    hipLaunchKernelGGL((fft_items_kernel<float, false>), dim3(a.n_items), dim3(EXEC_THREADS),
+                       exec_lds_bytes<float>(a.ntw), s, a);
   SPT_HIP(hipGetLastError());
 }
 

@@ -48,10 +48,14 @@ template <typename T>
 struct ExecBlock {
   const T* winv;             // 1 / w_c, c < L
   const double2* tw;         // two-level table of exp(2 pi i q / P)
+  const double2* tw2;        // two-level table of exp(i pi k / P), k <= P
+  int ntw;                   // entries of either table: 128 + P / 128 + 1
   const cplx_t<T>* post;     // exp(i pi k / P), k <= P
   const cplx_t<T>* val;      // tile boxes of the compressed block
   int64_t zoff;              // spectra of rhs r: Z + R * zoff + r * (P + 1)
   int64_t woff;              // four-step intermediate of rhs r: W + R * woff + r * P
+  int64_t zoff4;             // pre-split spectra of rhs r: plane + R * zoff4 + r * ldz4
+  int ldz4;                  // P + 1 rounded up to a multiple of 4
   int P, m_off, c_lo, c_hi;
   T scale;                   // 1 / sqrt(L)
   uint32_t magic;            // ceil(2^32 / P): u / P = umulhi(u, magic) for u * P < 2^32
@@ -71,6 +75,8 @@ template <typename T>
 struct ExecPlan {
   cplx_t<T>* Z;              // half spectra of every block
   cplx_t<T>* W;              // four-step intermediates
+  uint32_t* Zs;              // pre-split spectra (three planes, staged split-bf16 path)
+  int64_t zplane;            // plane stride, in (Re, Im) bfloat16 pairs
   const TileMeta* meta;      // tile box of (tile, block) at meta[tile * nblk + block]
   const ExecBlock<T>* blocks;
   const T* tailmat;          // direct tail, column m at tailmat + m * n_tiles * 16
@@ -84,15 +90,28 @@ struct ExecArgs {
   const int4* items;
   uint32_t* sync;
   int n_items, n_sync;
+  int ntw;                   // entries of the largest twiddle table (LDS copies)
   const T* X[EXEC_MAX_PLANS];
   T* Y[EXEC_MAX_PLANS];
 };
 
+// dynamic LDS of the item kernels: the transform points, then the two twiddle
+// tables of the block being transformed
+template <typename T>
+inline size_t exec_lds_bytes(int ntw) {
+  return (size_t)EXEC_POINTS * sizeof(cplx_t<T>) + 2 * (size_t)ntw * sizeof(double2);
+}
+
 // engine: 0 = float64, 1 = float32, 2 = split bfloat16 (T = float)
 template <typename T>
 void launch_exec(const ExecArgs<T>& a, int engine, int grid, hipStream_t s);
+// The FFT items without the queue and the counters (items of one launch do
+// not depend on each other): one workgroup per item of a.items[0 .. n_items).
+// split: spectra go out as the three bfloat16 planes (T = float).
+template <typename T>
+void launch_fft_items(const ExecArgs<T>& a, bool split, hipStream_t s);
 // resident workgroups per CU of the executor kernel of this engine
-int exec_occupancy(int engine);
+int exec_occupancy(int engine, int ntw);
 void init_exec_kernels();
 
 }  // namespace spt

@@ -17,6 +17,7 @@
 // their conjugates.
 
 #include "fft_core.hpp"
+#include "spmm_core.hpp"
 
 namespace spt {
 namespace {
@@ -52,10 +53,12 @@ __global__ __launch_bounds__(FFT_MAX_THREADS) void exec_fft_kernel(ExecFftArgs<T
 // blockIdx = b * R + r (blocks sorted by decreasing length, so the long FFTs
 // start first); a block uses the first fp.threads threads of the workgroup.
 
-template <typename T>
+// SPLIT: the half spectra are written as three bfloat16 planes (the pieces of
+// the split-bf16 product, layout in common.hpp) instead of complex values.
+template <typename T, bool SPLIT>
 __global__ __launch_bounds__(FFT_MAX_THREADS) void exec_fft_multi_kernel(
     const FftDesc<T>* __restrict__ descs, const T* __restrict__ X, cplx_t<T>* __restrict__ Z,
-    int R, int64_t N) {
+    uint32_t* __restrict__ Zs, int64_t zplane, int R, int64_t N) {
   using C = cplx_t<T>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C* lds = reinterpret_cast<C*>(smem_raw);
@@ -88,7 +91,6 @@ __global__ __launch_bounds__(FFT_MAX_THREADS) void exec_fft_multi_kernel(
   __syncthreads();
   run_fft<+1, false>(lds, P, 0, d->fp.npass, d->fp.radix, d->tw, 1, tid, nt, active);
   if (active) {
-    C* __restrict__ z = Z + (int64_t)R * d->zoff + (int64_t)r * d->ldz;
     const T scale = d->scale;
     const C* __restrict__ post = d->post;
     C tw[FFT_EPT + 1];
@@ -97,10 +99,28 @@ __global__ __launch_bounds__(FFT_MAX_THREADS) void exec_fft_multi_kernel(
       const int k = tid + e * nt;
       tw[e] = k <= P ? post[k] : C{T(0), T(0)};
     }
+    if constexpr (!SPLIT) {
+      C* __restrict__ z = Z + (int64_t)R * d->zoff + (int64_t)r * d->ldz;
 #pragma unroll
-    for (int e = 0; e <= FFT_EPT; ++e) {
-      const int k = tid + e * nt;
-      if (k <= P) z[k] = unpack_with<+1>(lds, P, k, tw[e], scale);
+      for (int e = 0; e <= FFT_EPT; ++e) {
+        const int k = tid + e * nt;
+        if (k <= P) z[k] = unpack_with<+1>(lds, P, k, tw[e], scale);
+      }
+    } else {
+      // k < ldz4 <= P + 4 <= FFT_EPT * nt + nt: zeros past P
+      uint32_t* __restrict__ zs = Zs + (int64_t)R * d->zoff4 + (int64_t)r * d->ldz4;
+      const int ldz4 = d->ldz4;
+#pragma unroll
+      for (int e = 0; e <= FFT_EPT; ++e) {
+        const int k = tid + e * nt;
+        if (k < ldz4) {
+          const C z = k <= P ? unpack_with<+1>(lds, P, k, tw[e], scale) : C{T(0), T(0)};
+          uint32_t pc[3];
+          spmmcore::split2(spmmcore::f32x2{(float)z.x, (float)z.y}, pc);
+#pragma unroll
+          for (int p = 0; p < 3; ++p) zs[p * zplane + k] = pc[p];
+        }
+      }
     }
   }
 }
@@ -173,8 +193,9 @@ void init_fft_kernels(size_t max_lds) {
   set_lds(inv_fft_kernel<double>, max_lds);
   set_lds(inv_fft_kernel<float>, max_lds);
   set_lds(row_fft_kernel, max_lds);
-  set_lds(exec_fft_multi_kernel<double>, max_lds);
-  set_lds(exec_fft_multi_kernel<float>, max_lds);
+  set_lds(exec_fft_multi_kernel<double, false>, max_lds);
+  set_lds(exec_fft_multi_kernel<float, false>, max_lds);
+  set_lds(exec_fft_multi_kernel<float, true>, max_lds);
   done.push_back(dev);
 }
 
@@ -228,8 +249,17 @@ template <typename T>
 void launch_exec_fft_multi(const FftDesc<T>* descs, int nblk, int threads, int max_P,
                            const T* X, cplx_t<T>* Z, int R, int64_t N, hipStream_t s) {
   const size_t lds = sizeof(cplx_t<T>) * (size_t)max_P;
-  hipLaunchKernelGGL(exec_fft_multi_kernel<T>, dim3(nblk * R), dim3(threads), lds, s, descs, X,
-                     Z, R, N);
+  hipLaunchKernelGGL((exec_fft_multi_kernel<T, false>), dim3(nblk * R), dim3(threads), lds, s,
+                     descs, X, Z, (uint32_t*)nullptr, (int64_t)0, R, N);
+  SPT_HIP(hipGetLastError());
+}
+
+void launch_exec_fft_multi_split(const FftDesc<float>* descs, int nblk, int threads, int max_P,
+                                 const float* X, uint32_t* Zs, int64_t zplane, int R, int64_t N,
+                                 hipStream_t s) {
+  const size_t lds = sizeof(float2) * (size_t)max_P;
+  hipLaunchKernelGGL((exec_fft_multi_kernel<float, true>), dim3(nblk * R), dim3(threads), lds, s,
+                     descs, X, (float2*)nullptr, Zs, zplane, R, N);
   SPT_HIP(hipGetLastError());
 }
 

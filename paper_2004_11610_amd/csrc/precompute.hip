@@ -4,6 +4,7 @@
 // packing of the kept entries into row tiles.
 
 #include "common.hpp"
+#include "spmm_core.hpp"
 
 namespace spt {
 namespace {
@@ -390,6 +391,57 @@ __global__ void to_f32_kernel(const double* __restrict__ in, float* __restrict__
     out[i] = (float)in[i];
 }
 
+// Pre-split tile boxes (layout in common.hpp): one workgroup per tile, one
+// thread per (step, lane) of the box.
+__global__ __launch_bounds__(256) void split_pack_kernel(const float2* __restrict__ val32,
+                                                         const int32_t* __restrict__ tkw,
+                                                         const int64_t* __restrict__ toff,
+                                                         const int64_t* __restrict__ tsoff,
+                                                         uint16_t* __restrict__ valbf) {
+  using namespace spmmcore;
+  const int t = blockIdx.x;
+  const int kw = tkw[t];
+  const int steps = (kw + 15) / 16;
+  const float2* __restrict__ v = val32 + toff[t];
+  bf16x8* __restrict__ out = reinterpret_cast<bf16x8*>(valbf + tsoff[t]);
+  for (int idx = threadIdx.x; idx < steps * 64; idx += blockDim.x) {
+    const int st = idx / 64, lane = idx % 64;
+    const int m = lane & 15, g = lane >> 4;
+    f32x8 f;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int c = 16 * st + 4 * g + (j >> 1);
+      const float2 a = c < kw ? v[c * TILE_ROWS + m] : float2{0.f, 0.f};
+      f[j] = (j & 1) ? -a.y : a.x;
+    }
+    const Split8 sp(f);
+#pragma unroll
+    for (int p = 0; p < 3; ++p) out[(3 * st + p) * 64 + lane] = sp.get(p);
+  }
+}
+
+__global__ __launch_bounds__(256) void split_tail_kernel(const float* __restrict__ tail32,
+                                                         int64_t ldt, int tail,
+                                                         uint16_t* __restrict__ tailbf) {
+  using namespace spmmcore;
+  const int t = blockIdx.x;
+  const int tsteps = (tail + 31) / 32;
+  bf16x8* __restrict__ out = reinterpret_cast<bf16x8*>(tailbf);
+  for (int idx = threadIdx.x; idx < tsteps * 64; idx += blockDim.x) {
+    const int st = idx / 64, lane = idx % 64;
+    const int m = lane & 15, g = lane >> 4;
+    f32x8 f;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int mm = 32 * st + 8 * g + j;
+      f[j] = mm < tail ? tail32[(int64_t)mm * ldt + (int64_t)t * TILE_ROWS + m] : 0.f;
+    }
+    const Split8 sp(f);
+#pragma unroll
+    for (int p = 0; p < 3; ++p) out[(((int64_t)t * tsteps + st) * 3 + p) * 64 + lane] = sp.get(p);
+  }
+}
+
 int blocks_for(int64_t n, int threads) {
   int64_t b = (n + threads - 1) / threads;
   return (int)std::min<int64_t>(std::max<int64_t>(b, 1), 65535 * 16);
@@ -444,6 +496,21 @@ void launch_pack(const double2* spec, int64_t row0, int nrows, int64_t N, int P,
   const int ntile = (nrows + TILE_ROWS - 1) / TILE_ROWS;
   hipLaunchKernelGGL(pack_kernel, dim3(ntile), dim3(256), 0, s, spec, row0, nrows, N, P, thr,
                      tile_k0, tile_kw, tile_off, tile0, val64, val32);
+  SPT_HIP(hipGetLastError());
+}
+
+void launch_split_pack(const float2* val32, const int32_t* tile_kw, const int64_t* tile_off,
+                       const int64_t* tile_soff, int ntiles, uint16_t* valbf, hipStream_t s) {
+  if (ntiles <= 0) return;
+  hipLaunchKernelGGL(split_pack_kernel, dim3(ntiles), dim3(256), 0, s, val32, tile_kw, tile_off,
+                     tile_soff, valbf);
+  SPT_HIP(hipGetLastError());
+}
+
+void launch_split_tail(const float* tail32, int64_t ldt, int tail, int ntiles, uint16_t* tailbf,
+                       hipStream_t s) {
+  if (ntiles <= 0 || tail <= 0) return;
+  hipLaunchKernelGGL(split_tail_kernel, dim3(ntiles), dim3(256), 0, s, tail32, ldt, tail, tailbf);
   SPT_HIP(hipGetLastError());
 }
 

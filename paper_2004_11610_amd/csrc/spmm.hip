@@ -129,6 +129,112 @@ __global__ __launch_bounds__(256) void spmm_mfma_kernel(SpmmArgs<typename E::T> 
   }
 }
 
+// ---------------------------------------------------------------- pre-split product
+// Same tiling as spmm_mfma_kernel (workgroup = tile x 64 right-hand sides,
+// wave = 16 of them); both operands arrive as bfloat16 pieces (layout in
+// common.hpp), so a step is three 16-byte loads of each operand and the six
+// matrix-core products, with no conversion in the loop.
+constexpr int PRESPLIT_SB = 4;
+
+struct PieceRegs {
+  bf16x8 a[3];
+  bf16x8 z[3];
+};
+
+__device__ __forceinline__ f32x4 mma6_pieces(const bf16x8* A, const bf16x8* B, f32x4 acc) {
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[2], B[0], acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[1], B[1], acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[0], B[2], acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[1], B[0], acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[0], B[1], acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[0], B[0], acc, 0, 0, 0);
+  return acc;
+}
+
+__global__ __launch_bounds__(256) void spmm_presplit_kernel(SpmmSplitArgs args) {
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int tile = blockIdx.x;
+  const int r_wave = blockIdx.y * 64 + wave * 16;
+  if (r_wave >= args.R) return;  // wave-uniform
+  const int m = lane & 15, g = lane >> 4;
+  const int r = r_wave + m;
+  const bool rok = r < args.R;
+  const int64_t rr = rok ? r : r_wave;
+  const bf16x8 zero8 = bf16x8{};
+
+  int k0_l = 0, kw_l = 0, ldz_l = 0;
+  int64_t off_l = 0, val_l = 0, zoff_l = 0;
+  if (lane < args.nblk) {
+    const TileMeta tm = args.meta[(int64_t)tile * args.nblk + lane];
+    const SpmmSplitBlock bd = args.blocks[lane];
+    k0_l = tm.k0;
+    kw_l = tm.kw;
+    off_l = tm.off;
+    val_l = (int64_t)(uintptr_t)bd.val;
+    zoff_l = bd.zoff;
+    ldz_l = bd.ldz;
+  }
+  f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int b = 0; b < args.nblk; ++b) {
+    const int kw = lane_i32(kw_l, b);
+    const int steps = (kw + 15) >> 4;
+    const bf16x8* __restrict__ va =
+        reinterpret_cast<const bf16x8*>((const uint16_t*)(uintptr_t)lane_i64(val_l, b) +
+                                        lane_i64(off_l, b)) + lane;
+    // pieces of z: rhs rr, complex columns k0 + 16 s + 4 g .. + 3 (16 bytes)
+    const uint32_t* __restrict__ zb = args.Zs + (int64_t)args.R * lane_i64(zoff_l, b) +
+                                      rr * lane_i32(ldz_l, b) + lane_i32(k0_l, b) + 4 * g;
+    for (int s0 = 0; s0 < steps; s0 += PRESPLIT_SB) {
+      PieceRegs st[PRESPLIT_SB];
+#pragma unroll
+      for (int i = 0; i < PRESPLIT_SB; ++i) {
+        const int s = s0 + i;
+        const bool in = s < steps;
+        const bool zin = in && rok && 16 * s + 4 * g < kw;
+#pragma unroll
+        for (int p = 0; p < 3; ++p) {
+          st[i].a[p] = in ? va[(3 * s + p) * 64] : zero8;
+          st[i].z[p] = zin ? *reinterpret_cast<const bf16x8*>(zb + p * args.zplane + 16 * s)
+                           : zero8;
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < PRESPLIT_SB; ++i)
+        if (s0 + i < steps) acc = mma6_pieces(st[i].a, st[i].z, acc);
+    }
+  }
+  // direct tail: pre-split rows, x split here
+  const int64_t n0 = (int64_t)tile * TILE_ROWS;
+  const float* __restrict__ xr = args.X + rr * args.N;
+  const int tsteps = (args.tail + 31) / 32;
+  const bf16x8* __restrict__ ta = reinterpret_cast<const bf16x8*>(args.tailmat);
+  for (int s = 0; s < tsteps; ++s) {
+    f32x8 xv;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int mm = 32 * s + 8 * g + j;
+      xv[j] = (mm < args.tail && rok) ? xr[mm] : 0.f;
+    }
+    const Split8 xs(xv);
+    bf16x8 A[3], B[3];
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+      A[p] = ta[(((int64_t)tile * tsteps + s) * 3 + p) * 64 + lane];
+      B[p] = xs.get(p);
+    }
+    acc = mma6_pieces(A, B, acc);
+  }
+  if (rok) {
+    float* __restrict__ y = args.Y + (int64_t)r * args.N + n0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int q = 4 * g + i;
+      if (n0 + q < args.N) y[q] = acc[i];
+    }
+  }
+}
+
 // ---------------------------------------------------------------- transposed
 // u[r][k] = sum_n Add[n][k] f[r][n] over the half spectrum (c_k removed), one
 // wave per row tile, lane = right-hand side, accumulated with atomics since
@@ -194,6 +300,11 @@ template <typename T>
 void launch_spmm(const SpmmArgs<T>& a, hipStream_t s) {
   using E = typename std::conditional<std::is_same<T, double>::value, EngF64, EngF32>::type;
   hipLaunchKernelGGL(spmm_mfma_kernel<E>, dim3(a.n_tiles, (a.R + 63) / 64), dim3(256), 0, s, a);
+  SPT_HIP(hipGetLastError());
+}
+
+void launch_spmm_presplit(const SpmmSplitArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(spmm_presplit_kernel, dim3(a.n_tiles, (a.R + 63) / 64), dim3(256), 0, s, a);
   SPT_HIP(hipGetLastError());
 }
 

@@ -32,6 +32,21 @@ struct Split8 {
   __device__ __forceinline__ bf16x8 get(int i) const { return p[i]; }
 };
 
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+
+// the same three pieces for a pair of values, each pair packed in 32 bits
+__device__ __forceinline__ void split2(f32x2 f, uint32_t out[3]) {
+  const bf16x2 p0 = __builtin_convertvector(f, bf16x2);
+  const f32x2 r1 = f - __builtin_convertvector(p0, f32x2);
+  const bf16x2 p1 = __builtin_convertvector(r1, bf16x2);
+  const f32x2 r2 = r1 - __builtin_convertvector(p1, f32x2);
+  const bf16x2 p2 = __builtin_convertvector(r2, bf16x2);
+  out[0] = __builtin_bit_cast(uint32_t, p0);
+  out[1] = __builtin_bit_cast(uint32_t, p1);
+  out[2] = __builtin_bit_cast(uint32_t, p2);
+}
+
 // Engines: the accumulation of one step (4 complex columns per lane, i.e. 32
 // real K per 16 x 16 tile) and of one real step (8 reals per lane).
 //

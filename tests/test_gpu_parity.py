@@ -275,7 +275,9 @@ def test_batched_matches_single_plans(spt):
     specs = [("legendre", 1000, {}, 5), ("hermite_fn", 600, {}, 1),
              ("jacobi", 1500, dict(alpha=2.0, beta=3.0), 70), ("chebyshev_t", 777, {}, 3),
              ("jacobi", 2048, dict(alpha=-0.5, beta=-0.5), 130)]
-    plans = [spt.Plan(f, N, 1e-7, mode=spt.MODE_ROW, **kw).precompute() for f, N, kw, _ in specs]
+    # single executes on the persistent executor too, so that results match bit for bit
+    plans = [spt.Plan(f, N, 1e-7, mode=spt.MODE_ROW, executor=spt.EXECUTOR_PERSISTENT, **kw)
+             .precompute() for f, N, kw, _ in specs]
     for prec, dt in ((spt.F64, torch.float64), (spt.F32, torch.float32),
                      (spt.SPLIT_BF16, torch.float32)):
         say("batched prec", prec)
