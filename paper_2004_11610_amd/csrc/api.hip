@@ -715,6 +715,8 @@ std::vector<FftDesc<T>> fft_descs(spt_plan_t plan) {
     e.scale = (T)(1.0 / std::sqrt((double)B.g.L));
     e.zoff4 = zoff4;
     e.ldz4 = B.ldz4;
+    e.tw2 = B.posttw.as<double2>();
+    e.ntw = 128 + B.P / 128 + 1;
     d.push_back(e);
     zoff += B.P + 1;
     zoff4 += B.ldz4;

@@ -86,6 +86,8 @@ struct FftDesc {
   T scale;
   int64_t zoff4;  // the same for the split planes (ldz4 = ldz rounded up to 4)
   int ldz4;
+  const double2* tw2;  // two-level table of exp(i pi k / P), k <= P
+  int ntw;             // entries of tw and of tw2: 128 + P / 128 + 1
 };
 
 template <typename T>

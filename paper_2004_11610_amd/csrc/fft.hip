@@ -70,6 +70,16 @@ __global__ __launch_bounds__(FFT_MAX_THREADS) void exec_fft_multi_kernel(
   const int c_lo = d->c_lo, c_hi = d->c_hi, m_off = d->m_off;
   const T* __restrict__ x = X + (int64_t)r * N;
   const T* __restrict__ winv = d->winv;
+  // float32: the pass and unpack twiddle tables are copied into LDS after the
+  // points (float64 transforms fill the LDS with their points alone)
+  constexpr bool LTW = sizeof(T) == 4;
+  double2* ltw = reinterpret_cast<double2*>(smem_raw + ((d->fp.P * sizeof(C) + 15) & ~(size_t)15));
+  if (LTW)
+    for (int i = tid; i < d->ntw; i += blockDim.x) {
+      ltw[i] = d->tw[i];
+      ltw[d->ntw + i] = d->tw2[i];
+    }
+  const double2* __restrict__ tw_pass = LTW ? ltw : d->tw;
   // global loads in two rounds of FFT_EPT / 2 per thread, all issued before
   // the LDS writes of the round
 #pragma unroll
@@ -89,7 +99,7 @@ __global__ __launch_bounds__(FFT_MAX_THREADS) void exec_fft_multi_kernel(
     }
   }
   __syncthreads();
-  run_fft<+1, false>(lds, P, 0, d->fp.npass, d->fp.radix, d->tw, 1, tid, nt, active);
+  run_fft<+1, false>(lds, P, 0, d->fp.npass, d->fp.radix, tw_pass, 1, tid, nt, active);
   if (active) {
     const T scale = d->scale;
     const C* __restrict__ post = d->post;
@@ -97,7 +107,10 @@ __global__ __launch_bounds__(FFT_MAX_THREADS) void exec_fft_multi_kernel(
 #pragma unroll
     for (int e = 0; e <= FFT_EPT; ++e) {
       const int k = tid + e * nt;
-      tw[e] = k <= P ? post[k] : C{T(0), T(0)};
+      if (LTW)
+        tw[e] = k <= P ? to_c<C>(twiddle(ltw + d->ntw, k)) : C{T(0), T(0)};
+      else
+        tw[e] = k <= P ? post[k] : C{T(0), T(0)};
     }
     if constexpr (!SPLIT) {
       C* __restrict__ z = Z + (int64_t)R * d->zoff + (int64_t)r * d->ldz;
@@ -170,6 +183,14 @@ __global__ __launch_bounds__(FFT_MAX_THREADS) void row_fft_kernel(RowFftArgs a, 
   run_fft<-1>(lds, fp, a.tw, tid, nt);
   C* __restrict__ s = a.spec + row * (a.P + 1);
   for (int k = tid; k <= a.P; k += nt) s[k] = unpack<-1>(lds, a.P, k, a.post, a.scale);
+}
+
+// points, then (float32) the two twiddle tables of 128 + P / 128 + 1 entries
+template <typename T>
+size_t fused_lds_bytes(int max_P) {
+  size_t b = ((size_t)max_P * sizeof(cplx_t<T>) + 15) & ~(size_t)15;
+  if (sizeof(T) == 4) b += 2 * (size_t)(128 + max_P / 128 + 1) * sizeof(double2);
+  return b;
 }
 
 template <typename K>
@@ -248,7 +269,7 @@ void launch_row_fft(const RowFftArgs& a, const FftPlan& fp, hipStream_t s) {
 template <typename T>
 void launch_exec_fft_multi(const FftDesc<T>* descs, int nblk, int threads, int max_P,
                            const T* X, cplx_t<T>* Z, int R, int64_t N, hipStream_t s) {
-  const size_t lds = sizeof(cplx_t<T>) * (size_t)max_P;
+  const size_t lds = fused_lds_bytes<T>(max_P);
   hipLaunchKernelGGL((exec_fft_multi_kernel<T, false>), dim3(nblk * R), dim3(threads), lds, s,
                      descs, X, Z, (uint32_t*)nullptr, (int64_t)0, R, N);
   SPT_HIP(hipGetLastError());
@@ -257,7 +278,7 @@ void launch_exec_fft_multi(const FftDesc<T>* descs, int nblk, int threads, int m
 void launch_exec_fft_multi_split(const FftDesc<float>* descs, int nblk, int threads, int max_P,
                                  const float* X, uint32_t* Zs, int64_t zplane, int R, int64_t N,
                                  hipStream_t s) {
-  const size_t lds = sizeof(float2) * (size_t)max_P;
+  const size_t lds = fused_lds_bytes<float>(max_P);
   hipLaunchKernelGGL((exec_fft_multi_kernel<float, true>), dim3(nblk * R), dim3(threads), lds, s,
                      descs, X, (float2*)nullptr, Zs, zplane, R, N);
   SPT_HIP(hipGetLastError());

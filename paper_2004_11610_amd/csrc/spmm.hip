@@ -40,7 +40,7 @@ __global__ __launch_bounds__(256) void spmm_mfma_kernel(SpmmArgs<typename E::T> 
   using C = cplx_t<T>;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  const int tile = blockIdx.x;
+  const int tile = xcd_tile(blockIdx.x, args.n_tiles);
   const int r_wave = blockIdx.y * 64 + wave * 16;
   if (r_wave >= args.R) return;  // wave-uniform: no right-hand side left
   const int m = lane & 15, g = lane >> 4;
@@ -154,7 +154,7 @@ __device__ __forceinline__ f32x4 mma6_pieces(const bf16x8* A, const bf16x8* B, f
 __global__ __launch_bounds__(256) void spmm_presplit_kernel(SpmmSplitArgs args) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  const int tile = blockIdx.x;
+  const int tile = xcd_tile(blockIdx.x, args.n_tiles);
   const int r_wave = blockIdx.y * 64 + wave * 16;
   if (r_wave >= args.R) return;  // wave-uniform
   const int m = lane & 15, g = lane >> 4;

@@ -32,6 +32,15 @@ struct Split8 {
   __device__ __forceinline__ bf16x8 get(int i) const { return p[i]; }
 };
 
+// Workgroups are dealt to the 8 XCDs in turn (workgroup b to XCD b % 8).
+// Row tile of workgroup b: consecutive tiles on the same XCD, so that the
+// half-spectrum columns shared by neighbouring tiles are fetched into that
+// XCD's L2 once.  A bijection of [0, n).
+__device__ __forceinline__ int xcd_tile(int b, int n) {
+  const int n8 = n >> 3;
+  return b < 8 * n8 ? (b & 7) * n8 + (b >> 3) : b;
+}
+
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 
