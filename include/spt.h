@@ -175,7 +175,8 @@ spt_status spt_execute(spt_plan_t plan, const void* X, void* Y, int64_t nrhs, in
                        void* stream);
 
 /* Transposed product (Alg. 2 / block Alg. 4): Y[r*N + m] = sum_j A[j,m] X[r*N + j].
- * Same arguments and rules as spt_execute. */
+ * Same arguments and rules as spt_execute; F64 or F32; every block's FFT
+ * half-length must be at most 10240 (SPT_E_UNSUPPORTED otherwise). */
 spt_status spt_execute_transposed(spt_plan_t plan, const void* X, void* Y, int64_t nrhs,
                                   int32_t prec, void* stream);
 

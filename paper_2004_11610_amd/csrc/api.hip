@@ -298,14 +298,79 @@ size_t max_lds_bytes(int device) {
 }
 
 // ---------------------------------------------------------------- precompute
+// Executor geometry of a block: transforms with P <= split_points() run in one
+// workgroup (several right-hand sides at a time when they fit); longer ones as
+// four-step transforms P = P1 * P2, P1 the divisor nearest sqrt(P) for which a
+// column item holds >= 8 columns and a row item >= 1 pair of rows.
+int split_points() {
+  static const int v = [] {
+    const char* e = std::getenv("SPT_EXEC_SPLIT_P");
+    const int x = e ? std::atoi(e) : 0;
+    return x > 0 ? std::min(x, EXEC_POINTS) : EXEC_POINTS;
+  }();
+  return v;
+}
+
+int log2_floor(int v) {
+  int l = 0;
+  while ((2 << l) <= v) ++l;
+  return l;
+}
+
+uint32_t magic_of(int d) {
+  return (uint32_t)((((uint64_t)1 << 32) + (uint64_t)d - 1) / (uint64_t)d);
+}
+
+void exec_geometry(DevBlock& B) {
+  const int P = B.P;
+  B.four = P > split_points();
+  if (!B.four) {
+    B.f1 = make_fft_plan(P);
+    return;
+  }
+  int best = 0;
+  double best_score = 1e300;
+  for (int p1 = 2; p1 <= 1024 && p1 < P; ++p1) {
+    if (P % p1) continue;
+    const int p2 = P / p1;
+    if (2 * p2 > EXEC_POINTS) continue;
+    int cw = 1;
+    while (p2 % (2 * cw) == 0 && 2 * cw * p1 <= EXEC_POINTS && 2 * cw <= 64) cw *= 2;
+    if (cw * p1 > EXEC_POINTS) continue;
+    const double score = std::fabs(std::log((double)p1) - 0.5 * std::log((double)P)) +
+                         (cw < 8 ? 10.0 : 0.0);
+    if (score < best_score) {
+      best_score = score;
+      best = p1;
+    }
+  }
+  if (!best) throw Error(SPT_E_UNSUPPORTED, "no four-step split of FFT length half " +
+                                                std::to_string(P));
+  B.P1 = best;
+  B.P2 = P / best;
+  int cw = 1;
+  while (B.P2 % (2 * cw) == 0 && 2 * cw * B.P1 <= EXEC_POINTS && 2 * cw <= 64) cw *= 2;
+  B.lcw = log2_floor(cw);
+  const int npairs = B.P1 / 2 + 1;
+  int gp = 1;
+  while (4 * gp * B.P2 <= EXEC_POINTS && gp < npairs) gp *= 2;
+  B.lgp = log2_floor(gp);
+  B.n_col = B.P2 >> B.lcw;
+  B.n_row = (npairs + gp - 1) / gp;
+  B.f1 = make_fft_plan(B.P1);
+  B.f2 = make_fft_plan(B.P2);
+}
+
 void build_block(spt_plan_t plan, DevBlock& B, hipStream_t s, size_t lds_max) {
   const int L = B.g.L, P = L / 2;
   if (L % 2) throw Error(SPT_E_UNSUPPORTED, "odd block length " + std::to_string(L));
   B.P = P;
-  B.fft = make_fft_plan(P);
-  if ((size_t)P * sizeof(double2) > lds_max)
-    throw Error(SPT_E_UNSUPPORTED, "block FFT length " + std::to_string(L) +
-                                       " exceeds the LDS of one workgroup");
+  // rows whose transform does not fit one workgroup's LDS go by four steps
+  const bool big = P > FUSED_MAX_P || (size_t)P * sizeof(double2) > lds_max;
+  if (!big) B.fft = make_fft_plan(P);
+  exec_geometry(B);
+  if (big && !B.four)
+    throw Error(SPT_E_UNSUPPORTED, "no four-step split of FFT length " + std::to_string(L));
   // window over the L columns and its reciprocal
   std::vector<double> w(L), winv(L);
   std::vector<float> winv32(L);
@@ -331,16 +396,68 @@ void build_block(spt_plan_t plan, DevBlock& B, hipStream_t s, size_t lds_max) {
 
   const int64_t N = plan->N;
   const int64_t ntiles = plan->n_tiles;
-  // rows per panel: A_e W rows (8 L bytes) + their half spectra (16 (P+1) bytes)
+  // rows per panel: A_e W rows (8 L bytes) + their half spectra (16 (P+1)
+  // bytes) + the four-step intermediate (16 P bytes)
   int64_t budget = (int64_t)8 << 30;
-  int64_t rows = plan->p.panel_rows > 0 ? plan->p.panel_rows
-                                        : budget / (8 * (int64_t)L + 16 * (int64_t)(P + 1));
+  const int64_t row_bytes = 8 * (int64_t)L + 16 * (int64_t)(P + 1) + (big ? 16 * (int64_t)P : 0);
+  int64_t rows = plan->p.panel_rows > 0 ? plan->p.panel_rows : budget / row_bytes;
   rows = std::max<int64_t>(TILE_ROWS, (rows / TILE_ROWS) * TILE_ROWS);
   rows = std::min<int64_t>(rows, ntiles * TILE_ROWS);
   const int64_t npanel = (N + rows - 1) / rows;
   DevBuf rowbuf, spec, maxbits, klo, khi, kcnt;
   rowbuf.alloc((size_t)rows * L * sizeof(double));
   spec.alloc((size_t)rows * (P + 1) * sizeof(double2));
+  // four-step row transforms: one block descriptor, column and row items of
+  // every panel row (row-major, so a shorter panel takes a prefix)
+  DevBuf wbuf, fplan, fblock, fcol, frow;
+  ExecArgs<double> fa4{};
+  if (big) {
+    wbuf.alloc((size_t)rows * P * sizeof(double2));
+    ExecBlock<double> e{};
+    e.tw = B.tw64.as<double2>();
+    e.tw2 = B.posttw.as<double2>();
+    e.ntw = 128 + P / 128 + 1;
+    e.winv = nullptr;
+    e.P = P;
+    e.m_off = 0;
+    e.c_lo = 0;
+    e.c_hi = L;
+    e.scale = 1.0 / std::sqrt((double)L);
+    e.magic = magic_of(P);
+    e.magic1 = magic_of(P + 1);
+    e.magic2 = magic_of(B.P2);
+    e.four = 1;
+    e.P1 = B.P1;
+    e.P2 = B.P2;
+    e.lcw = B.lcw;
+    e.lgp = B.lgp;
+    e.n_col = B.n_col;
+    e.n_row = B.n_row;
+    e.f1 = B.f1;
+    e.f2 = B.f2;
+    upload(fblock, std::vector<ExecBlock<double>>{e}, s);
+    ExecPlan<double> pl{};
+    pl.Z = spec.as<double2>();
+    pl.W = wbuf.as<double2>();
+    pl.blocks = fblock.as<ExecBlock<double>>();
+    pl.N = L;
+    pl.R = (int)rows;
+    pl.nblk = 1;
+    upload(fplan, std::vector<ExecPlan<double>>{pl}, s);
+    std::vector<int4> ic, ir;
+    for (int r = 0; r < (int)rows; ++r) {
+      for (int g = 0; g < B.n_col; ++g) ic.push_back(make_int4(item_head(ITEM_COL, 0), 0, r, g));
+      for (int q = 0; q < B.n_row; ++q) ir.push_back(make_int4(item_head(ITEM_ROW, 0), 0, r, q));
+    }
+    upload(fcol, ic, s);
+    upload(frow, ir, s);
+    init_exec_kernels();
+    if (exec_lds_bytes<double>(e.ntw) + 256 > lds_max)
+      throw Error(SPT_E_UNSUPPORTED, "FFT twiddle tables exceed the LDS of a workgroup");
+    fa4.plans = fplan.as<ExecPlan<double>>();
+    fa4.ntw = e.ntw;
+    fa4.X[0] = rowbuf.as<double>();
+  }
   maxbits.alloc(sizeof(unsigned long long));
   klo.alloc(rows * sizeof(int32_t));
   khi.alloc(rows * sizeof(int32_t));
@@ -357,8 +474,17 @@ void build_block(spt_plan_t plan, DevBlock& B, hipStream_t s, size_t lds_max) {
   ra.scale = 1.0 / std::sqrt((double)L);
   auto spectrum = [&](int64_t row0, int nr) {
     launch_rec_rows(fa, row0, nr, B.g.m_off, L, dw.as<double>(), rowbuf.as<double>(), s);
-    ra.nrows = nr;
-    launch_row_fft(ra, B.fft, s);
+    if (!big) {
+      ra.nrows = nr;
+      launch_row_fft(ra, B.fft, s);
+      return;
+    }
+    fa4.items = fcol.as<int4>();
+    fa4.n_items = nr * B.n_col;
+    launch_row_fft4(fa4, s);
+    fa4.items = frow.as<int4>();
+    fa4.n_items = nr * B.n_row;
+    launch_row_fft4(fa4, s);
   };
   auto panel_rows = [&](int64_t p) { return (int)std::min<int64_t>(rows, N - p * rows); };
 
@@ -476,69 +602,6 @@ void build_tail(spt_plan_t plan, hipStream_t s) {
                       plan->tailbf.as<uint16_t>(), s);
   }
   SPT_HIP(hipStreamSynchronize(s));
-}
-
-// Executor geometry of a block: transforms with P <= split_points() run in one
-// workgroup (several right-hand sides at a time when they fit); longer ones as
-// four-step transforms P = P1 * P2, P1 the divisor nearest sqrt(P) for which a
-// column item holds >= 8 columns and a row item >= 1 pair of rows.
-int split_points() {
-  static const int v = [] {
-    const char* e = std::getenv("SPT_EXEC_SPLIT_P");
-    const int x = e ? std::atoi(e) : 0;
-    return x > 0 ? std::min(x, EXEC_POINTS) : EXEC_POINTS;
-  }();
-  return v;
-}
-
-int log2_floor(int v) {
-  int l = 0;
-  while ((2 << l) <= v) ++l;
-  return l;
-}
-
-uint32_t magic_of(int d) {
-  return (uint32_t)((((uint64_t)1 << 32) + (uint64_t)d - 1) / (uint64_t)d);
-}
-
-void exec_geometry(DevBlock& B) {
-  const int P = B.P;
-  B.four = P > split_points();
-  if (!B.four) {
-    B.f1 = make_fft_plan(P);
-    return;
-  }
-  int best = 0;
-  double best_score = 1e300;
-  for (int p1 = 2; p1 <= 1024 && p1 < P; ++p1) {
-    if (P % p1) continue;
-    const int p2 = P / p1;
-    if (2 * p2 > EXEC_POINTS) continue;
-    int cw = 1;
-    while (p2 % (2 * cw) == 0 && 2 * cw * p1 <= EXEC_POINTS && 2 * cw <= 64) cw *= 2;
-    if (cw * p1 > EXEC_POINTS) continue;
-    const double score = std::fabs(std::log((double)p1) - 0.5 * std::log((double)P)) +
-                         (cw < 8 ? 10.0 : 0.0);
-    if (score < best_score) {
-      best_score = score;
-      best = p1;
-    }
-  }
-  if (!best) throw Error(SPT_E_UNSUPPORTED, "no four-step split of FFT length half " +
-                                                std::to_string(P));
-  B.P1 = best;
-  B.P2 = P / best;
-  int cw = 1;
-  while (B.P2 % (2 * cw) == 0 && 2 * cw * B.P1 <= EXEC_POINTS && 2 * cw <= 64) cw *= 2;
-  B.lcw = log2_floor(cw);
-  const int npairs = B.P1 / 2 + 1;
-  int gp = 1;
-  while (4 * gp * B.P2 <= EXEC_POINTS && gp < npairs) gp *= 2;
-  B.lgp = log2_floor(gp);
-  B.n_col = B.P2 >> B.lcw;
-  B.n_row = (npairs + gp - 1) / gp;
-  B.f1 = make_fft_plan(B.P1);
-  B.f2 = make_fft_plan(B.P2);
 }
 
 // right-hand sides per ITEM_FFT of a block (a power of two <= 64)
@@ -933,6 +996,9 @@ __global__ void zero_kernel(T* p, int64_t n) {
 template <typename T>
 void execute_transposed_t(spt_plan_t plan, const T* F, T* Y, int64_t R, hipStream_t s) {
   using C = cplx_t<T>;
+  if (plan->fft_maxP > FUSED_MAX_P)
+    throw Error(SPT_E_UNSUPPORTED, "the transposed product needs FFT half-lengths <= " +
+                                       std::to_string(FUSED_MAX_P));
   ensure_work(plan, R);
   int64_t per = 0;
   for (auto& B : plan->blk) per += B->P + 1;

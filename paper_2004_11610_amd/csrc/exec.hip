@@ -80,9 +80,11 @@ __device__ __forceinline__ void signal(uint32_t* p, uint32_t n) {
   if (threadIdx.x == 0 && n) __hip_atomic_fetch_add(p, n, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-template <typename C, typename T>
+template <int SIGN = +1, typename C, typename T>
 __device__ __forceinline__ C unpack_pair(C ck, C cm, C t, T scale) {
-  // Z_k = E_k + exp(i pi k/P) O_k, E = (C_k + conj C_{P-k})/2, O = (C_k - conj C_{P-k})/(2i)
+  // Z_k = E_k + exp(SIGN i pi k/P) O_k, E = (C_k + conj C_{P-k})/2,
+  // O = (C_k - conj C_{P-k})/(2i); t = exp(+i pi k/P)
+  if (SIGN < 0) t.y = -t.y;
   cm.y = -cm.y;
   const C e = C{T(0.5) * (ck.x + cm.x), T(0.5) * (ck.y + cm.y)};
   const C d = C{T(0.5) * (ck.x - cm.x), T(0.5) * (ck.y - cm.y)};
@@ -207,7 +209,9 @@ __device__ __forceinline__ void item_fft(const ExecPlan<T>& pl, const ExecBlock<
 // point n1 of column t at lds[(n1 << lcw) + t] (that is lds[u] for the
 // load order u = (n1 << lcw) + t), length-P1 transforms, then
 // W[k1 * P2 + n2] = (sum_n1 u[P2 n1 + n2] w_P1^(n1 k1)) w_P^(n2 k1).
-template <typename T, bool SYNC>
+// SIGN -1 (the precomputation's F): rows of X are taken as they are
+// (B.winv == nullptr, no window division, no extras)
+template <typename T, bool SYNC, int SIGN = +1>
 __device__ __forceinline__ void item_col(const ExecPlan<T>& pl, const ExecBlock<T>& B, const T* __restrict__ X,
                          int r, int grp, cplx_t<T>* lds, double2* ltw, uint32_t* sync) {
   using C = cplx_t<T>;
@@ -229,8 +233,13 @@ __device__ __forceinline__ void item_col(const ExecPlan<T>& pl, const ExecBlock<
       const int n = n1 * P2 + n2base + t;
       const int c0 = 2 * n, c1 = 2 * n + 1;
       const bool ok = u < total;
-      v0[e] = (ok && c0 >= c_lo && c0 < c_hi) ? x[c0] * winv[c0] : T(0);
-      v1[e] = (ok && c1 >= c_lo && c1 < c_hi) ? x[c1] * winv[c1] : T(0);
+      if (SIGN > 0) {
+        v0[e] = (ok && c0 >= c_lo && c0 < c_hi) ? x[c0] * winv[c0] : T(0);
+        v1[e] = (ok && c1 >= c_lo && c1 < c_hi) ? x[c1] * winv[c1] : T(0);
+      } else {
+        v0[e] = ok ? x[c0] : T(0);
+        v1[e] = ok ? x[c1] : T(0);
+      }
     }
 #pragma unroll
     for (int e = 0; e < EXEC_EPT; ++e) {
@@ -239,8 +248,8 @@ __device__ __forceinline__ void item_col(const ExecPlan<T>& pl, const ExecBlock<
     }
   }
   __syncthreads();
-  run_fft<+1, true, EXEC_EPT>(lds, P1, lcw, B.f1.npass, B.f1.radix, ltw, P2, tid, EXEC_THREADS,
-                              true);
+  run_fft<SIGN, true, EXEC_EPT>(lds, P1, lcw, B.f1.npass, B.f1.radix, ltw, P2, tid, EXEC_THREADS,
+                                true);
   C* __restrict__ W = pl.W + (int64_t)pl.R * B.woff + (int64_t)r * B.P;
 #pragma unroll
   for (int e = 0; e < EXEC_EPT; ++e) {
@@ -248,7 +257,9 @@ __device__ __forceinline__ void item_col(const ExecPlan<T>& pl, const ExecBlock<
     if (u < total) {
       const int t = (int)u & (cw - 1), k1 = (int)(u >> lcw);
       const int n2 = n2base + t;
-      const C w = to_c<C>(twiddle(ltw, n2 * k1));
+      double2 w64 = twiddle(ltw, n2 * k1);
+      if (SIGN < 0) w64.y = -w64.y;
+      const C w = to_c<C>(w64);
       W[(int64_t)k1 * P2 + n2] = cmul(lds[u], w);
     }
   }
@@ -262,7 +273,7 @@ __device__ __forceinline__ void item_col(const ExecPlan<T>& pl, const ExecBlock<
 // transforms slot s, point k2 is U_k, k = k1 + P1 k2, and its partner
 // U_{P-k} sits in the other slot of the pair at P2 - 1 - k2 (k1 > 0) or in the
 // same slot at (P2 - k2) mod P2 (k1 = 0).
-template <typename T, bool SYNC, bool SPLIT>
+template <typename T, bool SYNC, bool SPLIT, int SIGN = +1>
 __device__ __forceinline__ void item_row(const ExecPlan<T>& pl, const ExecBlock<T>& B, int r, int grp,
                          cplx_t<T>* lds, double2* ltw, uint32_t* sync, int* s_flag) {
   using C = cplx_t<T>;
@@ -298,8 +309,8 @@ __device__ __forceinline__ void item_row(const ExecPlan<T>& pl, const ExecBlock<
     }
   }
   __syncthreads();
-  run_fft<+1, true, EXEC_EPT>(lds, P2, ls, B.f2.npass, B.f2.radix, ltw, P1, tid, EXEC_THREADS,
-                              true);
+  run_fft<SIGN, true, EXEC_EPT>(lds, P2, ls, B.f2.npass, B.f2.radix, ltw, P1, tid, EXEC_THREADS,
+                                true);
   const T nanv = nan_of<T>();
   {
     C tw[EXEC_EPT];
@@ -327,7 +338,7 @@ __device__ __forceinline__ void item_row(const ExecPlan<T>& pl, const ExecBlock<
         const C ck = lds[u];
         const C cm = k1 == 0 ? lds[(((P2 - k2) % P2) << ls) + s]
                              : lds[((P2 - 1 - k2) << ls) + (s ^ 1)];
-        C z = unpack_pair(ck, cm, tw[e], B.scale);
+        C z = unpack_pair<SIGN>(ck, cm, tw[e], B.scale);
         if (!ok) z = C{nanv, nanv};
         store_z<SPLIT>(pl, B, r, kk[e], z);
       }
@@ -335,7 +346,7 @@ __device__ __forceinline__ void item_row(const ExecPlan<T>& pl, const ExecBlock<
   }
   if (grp == 0 && tid == 0) {  // k = P: C_P = C_0
     const C c0 = lds[0];
-    C z = unpack_pair(c0, c0, to_c<C>(twiddle(ltw + B.ntw, P)), B.scale);
+    C z = unpack_pair<SIGN>(c0, c0, to_c<C>(twiddle(ltw + B.ntw, P)), B.scale);
     if (!ok) z = C{nanv, nanv};
     store_z<SPLIT>(pl, B, r, P, z);
     store_z_pad<SPLIT>(pl, B, r);
@@ -537,6 +548,23 @@ __global__ __launch_bounds__(EXEC_THREADS) void fft_items_kernel(ExecArgs<T> a) 
   }
 }
 
+// Precomputation (float64, F): the column or the row halves of four-step
+// transforms of the rows of a panel; items as in fft_items_kernel.
+__global__ __launch_bounds__(EXEC_THREADS) void row_fft4_kernel(ExecArgs<double> a) {
+  using C = double2;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C* lds = reinterpret_cast<C*>(smem_raw);
+  double2* ltw = reinterpret_cast<double2*>(smem_raw + EXEC_POINTS * sizeof(C));
+  __shared__ int s_flag;
+  const int4 it = a.items[blockIdx.x];
+  const ExecPlan<double>& pl = a.plans[0];
+  if ((it.x & 15) == ITEM_COL)
+    item_col<double, false, -1>(pl, pl.blocks[it.y], a.X[0], it.z, it.w, lds, ltw, nullptr);
+  else
+    item_row<double, false, false, -1>(pl, pl.blocks[it.y], it.z, it.w, lds, ltw, nullptr,
+                                       &s_flag);
+}
+
 template <typename K>
 void set_lds(K kernel, size_t bytes) {
   SPT_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
@@ -574,6 +602,7 @@ void init_exec_kernels() {
   set_lds(fft_items_kernel<double, false>, lds);
   set_lds(fft_items_kernel<float, false>, lds);
   set_lds(fft_items_kernel<float, true>, lds);
+  set_lds(row_fft4_kernel, lds);
   done.push_back(dev);
 }
 
@@ -601,6 +630,13 @@ void launch_exec<float>(const ExecArgs<float>& a, int engine, int grid, hipStrea
   else
     hipLaunchKernelGGL(exec_kernel<EngF32>, dim3(grid), dim3(EXEC_THREADS),
                        exec_lds_bytes<float>(a.ntw), s, a);
+  SPT_HIP(hipGetLastError());
+}
+
+void launch_row_fft4(const ExecArgs<double>& a, hipStream_t s) {
+  if (a.n_items <= 0) return;
+  hipLaunchKernelGGL(row_fft4_kernel, dim3(a.n_items), dim3(EXEC_THREADS),
+                     exec_lds_bytes<double>(a.ntw), s, a);
   SPT_HIP(hipGetLastError());
 }
 

@@ -110,6 +110,11 @@ void launch_exec(const ExecArgs<T>& a, int engine, int grid, hipStream_t s);
 // split: spectra go out as the three bfloat16 planes (T = float).
 template <typename T>
 void launch_fft_items(const ExecArgs<T>& a, bool split, hipStream_t s);
+// Precomputation: F of the rows of a panel by four-step items (float64);
+// a.plans[0] describes the panel: X[0] = the rows (stride N = L), Z = the half
+// spectra (stride P + 1), W = the intermediate (stride P), R = rows; the
+// block's winv is null.
+void launch_row_fft4(const ExecArgs<double>& a, hipStream_t s);
 // resident workgroups per CU of the executor kernel of this engine
 int exec_occupancy(int engine, int ntw);
 void init_exec_kernels();

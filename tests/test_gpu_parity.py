@@ -345,3 +345,60 @@ def test_persistent_launches_repeat_exactly(spt):
         say("  repeat", i)
         assert np.array_equal(to_host(p.execute(Xb, prec=spt.SPLIT_BF16)), yb)
         assert np.array_equal(to_host(p.execute(Xa, prec=spt.SPLIT_BF16)), ya)
+
+
+# ------------------------------------------------------------------ long blocks
+LONG_N = 24000  # first block L = 30000: P = 15000 > 10240, four-step transforms
+
+
+def test_long_block_precompute_sampled_rows(spt):
+    """Precompute of a block whose rows do not fit one workgroup's FFT (four
+    steps, float64): sampled stored rows against the oracle's A_e W F rows,
+    thresholded at the library's block maximum (entries within 0.1% of the
+    threshold are not compared)."""
+    from oracle import compressed as oc
+    say("long block precompute", LONG_N)
+    fam = oracle_family("legendre", LONG_N)
+    p = spt.Plan("legendre", LONG_N, 1e-7, mode=spt.MODE_ROW, nodes=fam.nodes()).precompute()
+    op = oc.Plan(fam, 1e-7)
+    blk = op.blocks[0]
+    L = p.blocks()[0][0]
+    assert L == blk.L and L // 2 > 10240
+    P = L // 2
+    rows = np.arange(7, LONG_N, LONG_N // 12)
+    ref = oc._spectrum(op, blk, rows)[:, : P + 1]
+    got = np.array([p.compressed_rows(0, int(r), 1)[0] for r in rows])
+    ck = np.full(P + 1, 2.0)
+    ck[0] = ck[P] = 1.0
+    mx = p.info()["max_abs"][0]
+    assert np.abs(ref).max() <= mx * (1 + 1e-12)
+    thr = 1e-7 * mx
+    keep = np.abs(ref) > thr * 1.001
+    drop = np.abs(ref) < thr * 0.999
+    err = np.abs(got[keep] - (ref * ck[None, :])[keep]).max() / mx
+    say("  max |stored - oracle| / max %.3e over %d kept entries" % (err, int(keep.sum())))
+    # the float64 recurrences drift by ~k eps near x = +-1, k up to L
+    assert err <= 4 * L * np.finfo(float).eps
+    assert np.all(got[drop] == 0)
+
+
+@pytest.mark.parametrize("executor", ["staged", "persistent"])
+def test_long_block_execute(spt, executor):
+    """Execute with a four-step first block: F64 against sampled rows of the
+    direct product, F32 and split-bf16 against F64."""
+    say("long block execute", executor)
+    ex = spt.EXECUTOR_STAGED if executor == "staged" else spt.EXECUTOR_PERSISTENT
+    fam = oracle_family("legendre", LONG_N)
+    p = spt.Plan("legendre", LONG_N, 1e-7, nodes=fam.nodes(), executor=ex).precompute()
+    X = workloads.rhs("normal", 3, LONG_N, 61)
+    Y64 = run(spt, p, X, spt.F64)
+    rows = np.arange(0, LONG_N, 211)
+    Yd = oracle_direct("legendre", LONG_N, X, rows=rows)
+    e = rel_rows(Y64[:, rows], Yd)
+    say("  F64 vs direct (sampled rows) %.3e" % e)
+    assert e <= 1e-6
+    for prec in (spt.F32, spt.SPLIT_BF16):
+        e = rel_rows(run(spt, p, X, prec), Y64)
+        say("  prec", prec, "rel vs F64 %.3e" % e)
+        assert e <= reduced_tol(p)
+
