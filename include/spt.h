@@ -183,10 +183,12 @@ spt_status spt_execute_transposed(spt_plan_t plan, const void* X, void* Y, int64
 /* Execute `count` plans (any families and sizes, each precomputed with `prec`)
  * on `stream`: Y[i] = A_i X[i]^T with nrhs[i] right-hand sides.  X, Y, nrhs
  * are host arrays of `count` entries holding device pointers / counts.  Every
- * 64 plans run as one launch of the persistent executor (whatever each plan's
- * executor parameter says); the first call for a set of plans and sizes builds
- * its work queue (host work and a stream synchronisation), later calls reuse
- * it.  Calls for the same plans must not overlap in time (shared counters). */
+ * 64 plans run together: with the executor of plans[0] PERSISTENT, as one
+ * launch of the persistent executor; otherwise as three launches (the FFT
+ * items of every plan in two, then every plan's banded products in one).  The
+ * first call for a set of plans and sizes builds the work lists (host work and
+ * a stream synchronisation), later calls reuse them.  Calls for the same plans
+ * must not overlap in time (shared workspaces and counters). */
 spt_status spt_execute_batched(const spt_plan_t* plans, const void* const* X, void* const* Y,
                                const int64_t* nrhs, int32_t count, int32_t prec, void* stream);
 

@@ -97,6 +97,8 @@ struct ExecCtx {
   DevBuf items2;  // staged FFT: the row items (second launch)
   int n_items2 = 0;
   int ntw = 0;     // largest twiddle table (entries) of the blocks
+  DevBuf sargs, sitems;  // staged batch: product arguments per plan, product items
+  int n_sitems = 0;
 };
 
 bool is_jacobi(int f) { return f == SPT_LEGENDRE || f == SPT_JACOBI; }
@@ -1106,15 +1108,121 @@ void run_exec(ExecCtx& c, const void* const* X, void* const* Y, int count, int p
   staged(SPT_STAGE_EXEC, s, [&] { launch_exec<T>(a, engine_of(prec), c.grid, s); });
 }
 
+int xcd_tile_host(int b, int n) {
+  const int n8 = n >> 3;
+  return b < 8 * n8 ? (b & 7) * n8 + (b >> 3) : b;
+}
+
+// Product arguments and items of a staged batch (items of a plan's chunk of 64
+// right-hand sides start at a multiple of 8, tiles in XCD order).
+template <typename T>
+void build_batch_products(ExecCtx& c, const spt_plan_t* plans, const int64_t* R, int count,
+                          int prec, hipStream_t s) {
+  const bool dbl = std::is_same<T, double>::value;
+  std::vector<int4> items;
+  for (int i = 0; i < count; ++i) {
+    const spt_plan_t plan = plans[i];
+    for (int r0 = 0; r0 < R[i]; r0 += 64) {
+      while (items.size() % 8) items.push_back(make_int4(i, -1, 0, 0));
+      for (int t = 0; t < plan->n_tiles; ++t)
+        items.push_back(make_int4(i, xcd_tile_host(t, plan->n_tiles), r0, 0));
+    }
+  }
+  upload(c.sitems, items, s);
+  c.n_sitems = (int)items.size();
+  if (prec == SPT_SPLIT_BF16) {
+    std::vector<SpmmSplitArgs> a(count);
+    for (int i = 0; i < count; ++i) {
+      const spt_plan_t plan = plans[i];
+      a[i].meta = plan->tilemeta_bf.as<TileMeta>();
+      a[i].blocks = plan->spmmblk_bf.as<SpmmSplitBlock>();
+      a[i].nblk = (int)plan->blk.size();
+      a[i].n_tiles = plan->n_tiles;
+      a[i].Zs = plan->work.as<uint32_t>();
+      a[i].zplane = R[i] * plan->zper4;
+      a[i].tail = (int)plan->tail;
+      a[i].tailmat = plan->tailbf.as<uint16_t>();
+      a[i].R = (int)R[i];
+      a[i].N = plan->N;
+    }
+    upload(c.sargs, a, s);
+    return;
+  }
+  std::vector<SpmmArgs<T>> a(count);
+  for (int i = 0; i < count; ++i) {
+    const spt_plan_t plan = plans[i];
+    a[i].meta = plan->tilemeta.as<TileMeta>();
+    a[i].blocks = dbl ? (const SpmmBlock<T>*)plan->spmmblk64.p
+                      : (const SpmmBlock<T>*)plan->spmmblk32.p;
+    a[i].nblk = (int)plan->blk.size();
+    a[i].n_tiles = plan->n_tiles;
+    a[i].Z = plan->work.as<cplx_t<T>>();
+    a[i].tail = (int)plan->tail;
+    a[i].tailmat = dbl ? (const T*)plan->tail64.p : (const T*)plan->tail32.p;
+    a[i].R = (int)R[i];
+    a[i].N = plan->N;
+  }
+  upload(c.sargs, a, s);
+}
+
+// Staged batch: FFT items of every plan (two launches), then one product launch.
+template <typename T>
+void run_batch_staged(ExecCtx& c, const void* const* X, void* const* Y, int count, int prec,
+                      hipStream_t s) {
+  const bool split = std::is_same<T, float>::value && prec == SPT_SPLIT_BF16;
+  ExecArgs<T> a{};
+  a.plans = c.plans.as<ExecPlan<T>>();
+  a.ntw = c.ntw;
+  for (int i = 0; i < count; ++i) {
+    a.X[i] = static_cast<const T*>(X[i]);
+    a.Y[i] = static_cast<T*>(Y[i]);
+  }
+  staged(SPT_STAGE_FFT, s, [&] {
+    a.items = c.items.as<int4>();
+    a.n_items = c.n_items;
+    launch_fft_items<T>(a, split, s);
+    a.items = c.items2.as<int4>();
+    a.n_items = c.n_items2;
+    launch_fft_items<T>(a, split, s);
+  });
+  staged(SPT_STAGE_SPMM, s, [&] {
+    if (split) {
+      SpmmSplitBatch b{};
+      b.plans = c.sargs.as<SpmmSplitArgs>();
+      b.items = c.sitems.as<int4>();
+      for (int i = 0; i < count; ++i) {
+        b.X[i] = static_cast<const float*>(X[i]);
+        b.Y[i] = static_cast<float*>(Y[i]);
+      }
+      launch_spmm_presplit_items(b, c.n_sitems, s);
+      return;
+    }
+    SpmmBatch<T> b{};
+    b.plans = c.sargs.as<SpmmArgs<T>>();
+    b.items = c.sitems.as<int4>();
+    for (int i = 0; i < count; ++i) {
+      b.X[i] = static_cast<const T*>(X[i]);
+      b.Y[i] = static_cast<T*>(Y[i]);
+    }
+    launch_spmm_items<T>(b, c.n_sitems, s);
+  });
+}
+
 std::unique_ptr<ExecCtx> new_ctx(const std::vector<int64_t>& key, const spt_plan_t* plans,
                                  const int64_t* R, int count, int prec, hipStream_t s,
-                                 bool staged = false) {
+                                 bool staged = false, bool batch = false) {
   auto c = std::make_unique<ExecCtx>();
   c->key = key;
   if (prec == SPT_F64)
     build_exec_ctx<double>(*c, plans, R, count, prec, s, staged);
   else
     build_exec_ctx<float>(*c, plans, R, count, prec, s, staged);
+  if (staged && batch) {
+    if (prec == SPT_F64)
+      build_batch_products<double>(*c, plans, R, count, prec, s);
+    else
+      build_batch_products<float>(*c, plans, R, count, prec, s);
+  }
   return c;
 }
 
@@ -1301,9 +1409,11 @@ spt_status spt_execute_batched(const spt_plan_t* plans, const void* const* X, vo
     hipStream_t s = static_cast<hipStream_t>(stream);
     for (int i = 0; i < count; ++i) ensure_work(plans[i], nrhs[i]);
     std::lock_guard<std::mutex> lk(g_batch_mu);
+    // persistent when the first plan asks for it, staged launches otherwise
+    const bool staged = plans[0]->p.executor != SPT_EXECUTOR_PERSISTENT;
     for (int i0 = 0; i0 < count; i0 += EXEC_MAX_PLANS) {
       const int n = std::min(count - i0, EXEC_MAX_PLANS);
-      std::vector<int64_t> key{prec, n};
+      std::vector<int64_t> key{prec, n, staged};
       for (int i = i0; i < i0 + n; ++i) {
         key.push_back(plans[i]->serial);
         key.push_back(nrhs[i]);
@@ -1314,13 +1424,19 @@ spt_status spt_execute_batched(const spt_plan_t* plans, const void* const* X, vo
         if (e->key == key) c = e.get();
       if (!c) {
         if (g_batch_ctx.size() >= 4) g_batch_ctx.erase(g_batch_ctx.begin());
-        g_batch_ctx.push_back(new_ctx(key, plans + i0, nrhs + i0, n, prec, s));
+        g_batch_ctx.push_back(new_ctx(key, plans + i0, nrhs + i0, n, prec, s, staged, true));
         c = g_batch_ctx.back().get();
       }
-      if (prec == SPT_F64)
+      if (staged) {
+        if (prec == SPT_F64)
+          run_batch_staged<double>(*c, X + i0, Y + i0, n, prec, s);
+        else
+          run_batch_staged<float>(*c, X + i0, Y + i0, n, prec, s);
+      } else if (prec == SPT_F64) {
         run_exec<double>(*c, X + i0, Y + i0, n, prec, s);
-      else
+      } else {
         run_exec<float>(*c, X + i0, Y + i0, n, prec, s);
+      }
     }
   });
 }
@@ -1438,7 +1554,7 @@ spt_status spt_plan_destroy(spt_plan_t plan) {
       // batched contexts keyed by this plan's serial refer to its buffers
       std::lock_guard<std::mutex> lk(g_batch_mu);
       auto uses = [&](const std::unique_ptr<ExecCtx>& c) {
-        for (size_t i = 2; i < c->key.size(); i += 3)  // key: prec, n, (serial, R, work)...
+        for (size_t i = 3; i < c->key.size(); i += 3)  // key: prec, n, staged, (serial, R, work)...
           if (c->key[i] == plan->serial) return true;
         return false;
       };

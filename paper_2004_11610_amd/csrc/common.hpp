@@ -186,6 +186,27 @@ struct SpmmSplitArgs {
 };
 void launch_spmm_presplit(const SpmmSplitArgs& a, hipStream_t s);
 
+// Products of several plans in one launch: items (plan, row tile or -1, first
+// rhs) index per-plan argument blocks in device memory; X and Y of each plan
+// travel in the kernel arguments.
+constexpr int BATCH_MAX_PLANS = 64;
+template <typename T>
+struct SpmmBatch {
+  const SpmmArgs<T>* plans;
+  const int4* items;
+  const T* X[BATCH_MAX_PLANS];
+  T* Y[BATCH_MAX_PLANS];
+};
+struct SpmmSplitBatch {
+  const SpmmSplitArgs* plans;
+  const int4* items;
+  const float* X[BATCH_MAX_PLANS];
+  float* Y[BATCH_MAX_PLANS];
+};
+template <typename T>
+void launch_spmm_items(const SpmmBatch<T>& b, int n_items, hipStream_t s);
+void launch_spmm_presplit_items(const SpmmSplitBatch& b, int n_items, hipStream_t s);
+
 // split-bf16 staged FFT: the half spectra go out as the three planes above
 void launch_exec_fft_multi_split(const FftDesc<float>* descs, int nblk, int threads, int max_P,
                                  const float* X, uint32_t* Zs, int64_t zplane, int R, int64_t N,

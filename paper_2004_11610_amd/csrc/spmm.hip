@@ -34,14 +34,14 @@ constexpr int WAVES_PER_WG = 4;
 // the direct tail.  Steps are taken in batches of E::SB (across block
 // boundaries): all loads of a batch are issued before its first matrix
 // instruction, so a wave waits for memory about once per batch.
+// one workgroup: row tile `tile` x right-hand sides r0 .. r0 + 63
 template <typename E>
-__global__ __launch_bounds__(256) void spmm_mfma_kernel(SpmmArgs<typename E::T> args) {
+__device__ __forceinline__ void mfma_tile(const SpmmArgs<typename E::T>& args, int tile, int r0) {
   using T = typename E::T;
   using C = cplx_t<T>;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  const int tile = xcd_tile(blockIdx.x, args.n_tiles);
-  const int r_wave = blockIdx.y * 64 + wave * 16;
+  const int r_wave = r0 + wave * 16;
   if (r_wave >= args.R) return;  // wave-uniform: no right-hand side left
   const int m = lane & 15, g = lane >> 4;
   const int r = r_wave + m;
@@ -151,11 +151,10 @@ __device__ __forceinline__ f32x4 mma6_pieces(const bf16x8* A, const bf16x8* B, f
   return acc;
 }
 
-__global__ __launch_bounds__(256) void spmm_presplit_kernel(SpmmSplitArgs args) {
+__device__ __forceinline__ void presplit_tile(const SpmmSplitArgs& args, int tile, int r0) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  const int tile = xcd_tile(blockIdx.x, args.n_tiles);
-  const int r_wave = blockIdx.y * 64 + wave * 16;
+  const int r_wave = r0 + wave * 16;
   if (r_wave >= args.R) return;  // wave-uniform
   const int m = lane & 15, g = lane >> 4;
   const int r = r_wave + m;
@@ -235,6 +234,36 @@ __global__ __launch_bounds__(256) void spmm_presplit_kernel(SpmmSplitArgs args) 
   }
 }
 
+template <typename E>
+__global__ __launch_bounds__(256) void spmm_mfma_kernel(SpmmArgs<typename E::T> args) {
+  mfma_tile<E>(args, xcd_tile(blockIdx.x, args.n_tiles), blockIdx.y * 64);
+}
+
+__global__ __launch_bounds__(256) void spmm_presplit_kernel(SpmmSplitArgs args) {
+  presplit_tile(args, xcd_tile(blockIdx.x, args.n_tiles), blockIdx.y * 64);
+}
+
+// Several plans in one launch: workgroup b takes item b = (plan, tile, r0);
+// tile < 0 pads a plan's items to a multiple of 8 (XCD order as above).
+template <typename E>
+__global__ __launch_bounds__(256) void spmm_mfma_items_kernel(SpmmBatch<typename E::T> b) {
+  const int4 it = b.items[blockIdx.x];
+  if (it.y < 0) return;
+  SpmmArgs<typename E::T> a = b.plans[it.x];
+  a.X = b.X[it.x];
+  a.Y = b.Y[it.x];
+  mfma_tile<E>(a, it.y, it.z);
+}
+
+__global__ __launch_bounds__(256) void spmm_presplit_items_kernel(SpmmSplitBatch b) {
+  const int4 it = b.items[blockIdx.x];
+  if (it.y < 0) return;
+  SpmmSplitArgs a = b.plans[it.x];
+  a.X = b.X[it.x];
+  a.Y = b.Y[it.x];
+  presplit_tile(a, it.y, it.z);
+}
+
 // ---------------------------------------------------------------- transposed
 // u[r][k] = sum_n Add[n][k] f[r][n] over the half spectrum (c_k removed), one
 // wave per row tile, lane = right-hand side, accumulated with atomics since
@@ -300,6 +329,22 @@ template <typename T>
 void launch_spmm(const SpmmArgs<T>& a, hipStream_t s) {
   using E = typename std::conditional<std::is_same<T, double>::value, EngF64, EngF32>::type;
   hipLaunchKernelGGL(spmm_mfma_kernel<E>, dim3(a.n_tiles, (a.R + 63) / 64), dim3(256), 0, s, a);
+  SPT_HIP(hipGetLastError());
+}
+
+template <typename T>
+void launch_spmm_items(const SpmmBatch<T>& b, int n_items, hipStream_t s) {
+  if (n_items <= 0) return;
+  using E = typename std::conditional<std::is_same<T, double>::value, EngF64, EngF32>::type;
+  hipLaunchKernelGGL(spmm_mfma_items_kernel<E>, dim3(n_items), dim3(256), 0, s, b);
+  SPT_HIP(hipGetLastError());
+}
+template void launch_spmm_items<double>(const SpmmBatch<double>&, int, hipStream_t);
+template void launch_spmm_items<float>(const SpmmBatch<float>&, int, hipStream_t);
+
+void launch_spmm_presplit_items(const SpmmSplitBatch& b, int n_items, hipStream_t s) {
+  if (n_items <= 0) return;
+  hipLaunchKernelGGL(spmm_presplit_items_kernel, dim3(n_items), dim3(256), 0, s, b);
   SPT_HIP(hipGetLastError());
 }
 

@@ -402,3 +402,26 @@ def test_long_block_execute(spt, executor):
         say("  prec", prec, "rel vs F64 %.3e" % e)
         assert e <= reduced_tol(p)
 
+
+def test_batched_staged_matches_single_plans(spt):
+    """Staged batch (FFT items of every plan, then one product launch) against
+    single executes of the same plans (whose FFTs may take the fused kernel:
+    rounding differs)."""
+    import torch
+    specs = [("legendre", 1000, {}, 5), ("hermite_fn", 600, {}, 1),
+             ("jacobi", 1500, dict(alpha=2.0, beta=3.0), 70), ("chebyshev_t", 777, {}, 3),
+             ("jacobi", 9000, dict(alpha=-0.5, beta=-0.5), 130), ("legendre", 24000, {}, 2)]
+    plans = [spt.Plan(f, N, 1e-7, mode=spt.MODE_ROW, **kw).precompute() for f, N, kw, _ in specs]
+    for prec, dt in ((spt.F64, torch.float64), (spt.F32, torch.float32),
+                     (spt.SPLIT_BF16, torch.float32)):
+        say("staged batch prec", prec)
+        Xs = [to_dev(workloads.rhs("normal", R, N, 70 + i), dt)
+              for i, (_, N, _, R) in enumerate(specs)]
+        Ys = [torch.full_like(x, float("nan")) for x in Xs]
+        singles = [to_host(p.execute(x, prec=prec)) for p, x in zip(plans, Xs)]
+        for rep in range(2):
+            spt.execute_batched(plans, Xs, Ys, prec=prec)
+            for p, y, ref in zip(plans, Ys, singles):
+                e = rel_rows(to_host(y), ref)
+                assert e <= (1e-13 if prec == spt.F64 else reduced_tol(p)), (rep, e)
+
