@@ -90,7 +90,9 @@ typedef enum {
 } spt_precision;
 
 typedef enum {
-  SPT_MODE_AUTO = 0,   /* ROW unless the compressed form stores more than dense */
+  SPT_MODE_AUTO = 0,   /* ROW unless the compressed form stores more than dense
+                          (decided on the built blocks for N <= 8192, from 8
+                          panels of 64 sampled rows per block above)          */
   SPT_MODE_ROW = 1,    /* row compression (Alg. 1 / block Alg. 3)              */
   SPT_MODE_DIRECT = 3  /* dense product with A (no compression)                */
 } spt_mode;

@@ -363,7 +363,12 @@ void exec_geometry(DevBlock& B) {
   B.f2 = make_fft_plan(B.P2);
 }
 
-void build_block(spt_plan_t plan, DevBlock& B, hipStream_t s, size_t lds_max) {
+// Build the compressed block B (three passes over row panels).  With
+// `estimate`, only 8 panels of 64 rows spread over the rows are transformed
+// (maximum and tile boxes from those rows) and the return value is the
+// estimated number of stored entries; nothing is packed.
+int64_t build_block(spt_plan_t plan, DevBlock& B, hipStream_t s, size_t lds_max,
+                    bool estimate = false) {
   const int L = B.g.L, P = L / 2;
   if (L % 2) throw Error(SPT_E_UNSUPPORTED, "odd block length " + std::to_string(L));
   B.P = P;
@@ -403,6 +408,7 @@ void build_block(spt_plan_t plan, DevBlock& B, hipStream_t s, size_t lds_max) {
   int64_t budget = (int64_t)8 << 30;
   const int64_t row_bytes = 8 * (int64_t)L + 16 * (int64_t)(P + 1) + (big ? 16 * (int64_t)P : 0);
   int64_t rows = plan->p.panel_rows > 0 ? plan->p.panel_rows : budget / row_bytes;
+  if (estimate) rows = 64;
   rows = std::max<int64_t>(TILE_ROWS, (rows / TILE_ROWS) * TILE_ROWS);
   rows = std::min<int64_t>(rows, ntiles * TILE_ROWS);
   const int64_t npanel = (N + rows - 1) / rows;
@@ -488,12 +494,24 @@ void build_block(spt_plan_t plan, DevBlock& B, hipStream_t s, size_t lds_max) {
     fa4.n_items = nr * B.n_row;
     launch_row_fft4(fa4, s);
   };
-  auto panel_rows = [&](int64_t p) { return (int)std::min<int64_t>(rows, N - p * rows); };
+  // the row panels: all rows, or the sample
+  std::vector<std::pair<int64_t, int>> panels;
+  if (estimate) {
+    for (int i = 0; i < 8; ++i) {
+      const int64_t r0 = ((int64_t)i * N / 8) & ~(int64_t)(TILE_ROWS - 1);
+      if (panels.empty() || r0 >= panels.back().first + panels.back().second)
+        panels.push_back({r0, (int)std::min<int64_t>(rows, N - r0)});
+    }
+  } else {
+    for (int64_t p = 0; p < npanel; ++p)
+      panels.push_back({p * rows, (int)std::min<int64_t>(rows, N - p * rows)});
+  }
+  const bool multi = panels.size() > 1;
 
   // pass 1: max |A_e W F| over the block (Alg. 1 step 1.3)
-  for (int64_t p = 0; p < npanel; ++p) {
-    const int nr = panel_rows(p);
-    spectrum(p * rows, nr);
+  for (const auto& pn : panels) {
+    const int nr = pn.second;
+    spectrum(pn.first, nr);
     launch_maxabs(spec.as<double2>(), (int64_t)nr * (P + 1), maxbits.as<unsigned long long>(), s);
   }
   unsigned long long bits = 0;
@@ -508,19 +526,36 @@ void build_block(spt_plan_t plan, DevBlock& B, hipStream_t s, size_t lds_max) {
   const double thr = plan->eps1 * B.maxabs;
 
   // pass 2: band of every row, tile boxes on the host
-  std::vector<int32_t> hlo(N), hhi(N), hcnt(N);
-  for (int64_t p = 0; p < npanel; ++p) {
-    const int nr = panel_rows(p);
-    if (npanel > 1) spectrum(p * rows, nr);
+  std::vector<int32_t> hlo(N), hhi(N, -1), hcnt(N);
+  for (const auto& pn : panels) {
+    const int nr = pn.second;
+    if (multi) spectrum(pn.first, nr);
     launch_extents(spec.as<double2>(), nr, P, thr, klo.as<int32_t>(), khi.as<int32_t>(),
                    kcnt.as<int32_t>(), s);
-    SPT_HIP(hipMemcpyAsync(hcnt.data() + p * rows, kcnt.p, nr * sizeof(int32_t),
+    SPT_HIP(hipMemcpyAsync(hcnt.data() + pn.first, kcnt.p, nr * sizeof(int32_t),
                            hipMemcpyDeviceToHost, s));
-    SPT_HIP(hipMemcpyAsync(hlo.data() + p * rows, klo.p, nr * sizeof(int32_t),
+    SPT_HIP(hipMemcpyAsync(hlo.data() + pn.first, klo.p, nr * sizeof(int32_t),
                            hipMemcpyDeviceToHost, s));
-    SPT_HIP(hipMemcpyAsync(hhi.data() + p * rows, khi.p, nr * sizeof(int32_t),
+    SPT_HIP(hipMemcpyAsync(hhi.data() + pn.first, khi.p, nr * sizeof(int32_t),
                            hipMemcpyDeviceToHost, s));
     SPT_HIP(hipStreamSynchronize(s));
+  }
+  if (estimate) {
+    // boxes of the sampled tiles, scaled to all tiles
+    int64_t sum = 0, ntile_s = 0;
+    for (const auto& pn : panels)
+      for (int64_t t = pn.first / TILE_ROWS; t * TILE_ROWS < pn.first + pn.second; ++t) {
+        int lo = 0x7FFFFFFF, hi = -1;
+        for (int64_t q = 0; q < TILE_ROWS; ++q) {
+          const int64_t n = t * TILE_ROWS + q;
+          if (n >= N || hhi[n] < 0) continue;
+          lo = std::min(lo, hlo[n]);
+          hi = std::max(hi, hhi[n]);
+        }
+        if (hi >= 0) sum += (int64_t)(hi - (lo & ~3) + 1) * TILE_ROWS;
+        ++ntile_s;
+      }
+    return ntile_s ? (int64_t)((double)sum * (double)ntiles / (double)ntile_s) : 0;
   }
   B.h_k0.assign(ntiles, 0);
   B.h_kw.assign(ntiles, 0);
@@ -554,11 +589,11 @@ void build_block(spt_plan_t plan, DevBlock& B, hipStream_t s, size_t lds_max) {
   if (want32) B.val32.alloc(std::max<int64_t>(total, 1) * sizeof(float2));
 
   // pass 3: pack the kept entries (times c_k) into the tiles
-  for (int64_t p = 0; p < npanel; ++p) {
-    const int nr = panel_rows(p);
-    if (npanel > 1) spectrum(p * rows, nr);
-    launch_pack(spec.as<double2>(), p * rows, nr, N, P, thr, B.k0.as<int32_t>(),
-                B.kw.as<int32_t>(), B.off.as<int64_t>(), (int)((p * rows) / TILE_ROWS),
+  for (const auto& pn : panels) {
+    const int nr = pn.second;
+    if (multi) spectrum(pn.first, nr);
+    launch_pack(spec.as<double2>(), pn.first, nr, N, P, thr, B.k0.as<int32_t>(),
+                B.kw.as<int32_t>(), B.off.as<int64_t>(), (int)(pn.first / TILE_ROWS),
                 want64 ? B.val64.as<double2>() : nullptr, want32 ? B.val32.as<float2>() : nullptr,
                 s);
   }
@@ -581,6 +616,7 @@ void build_block(spt_plan_t plan, DevBlock& B, hipStream_t s, size_t lds_max) {
   int64_t nnz = 0;
   for (int64_t n = 0; n < N; ++n) nnz += hcnt[n];
   B.nnz = nnz;
+  return B.stored;
 }
 
 void build_tail(spt_plan_t plan, hipStream_t s) {
@@ -853,6 +889,19 @@ void precompute(spt_plan_t plan, hipStream_t s) {
   SPT_HIP(hipStreamSynchronize(s));
   plan->blk.clear();
   plan->mode = plan->requested_mode == SPT_MODE_DIRECT ? SPT_MODE_DIRECT : SPT_MODE_ROW;
+  // AUTO: fewest stored reals, the compressed blocks (complex = 2 reals, plus
+  // the direct tail) against the dense matrix; decided on the built blocks up
+  // to N = AUTO_EXACT_N, from sampled rows above
+  const bool autom = plan->requested_mode == SPT_MODE_AUTO;
+  if (plan->mode == SPT_MODE_ROW && autom && plan->N > AUTO_EXACT_N) {
+    int64_t est = plan->tail * plan->N;
+    for (auto& g : plan->geom) {
+      DevBlock tmp;
+      tmp.g = g;
+      est += 2 * build_block(plan, tmp, s, lds_max, true);
+    }
+    if (est > plan->N * plan->N) plan->mode = SPT_MODE_DIRECT;
+  }
   if (plan->mode == SPT_MODE_ROW) {
     for (auto& g : plan->geom) {
       auto B = std::make_unique<DevBlock>();
@@ -860,10 +909,9 @@ void precompute(spt_plan_t plan, hipStream_t s) {
       build_block(plan, *B, s, lds_max);
       plan->blk.push_back(std::move(B));
     }
-    if (plan->requested_mode == SPT_MODE_AUTO) {
-      // fewest stored bytes: the compressed blocks against the dense matrix
+    if (autom && plan->N <= AUTO_EXACT_N) {
       int64_t stored = 0;
-      for (auto& B : plan->blk) stored += 2 * B->stored;  // complex = 2 reals
+      for (auto& B : plan->blk) stored += 2 * B->stored;
       stored += plan->tail * plan->N;
       if (stored > plan->N * plan->N) {
         plan->blk.clear();

@@ -26,6 +26,9 @@ constexpr int MAX_PASSES = 16;
 // longest FFT half-length of the fused one-workgroup-per-transform kernel: a
 // float64 transform of P points fills P * 16 bytes of the 160 KiB LDS
 constexpr int FUSED_MAX_P = 10240;
+// AUTO mode compares built blocks with the dense matrix up to this N, and an
+// estimate from sampled rows above it
+constexpr int64_t AUTO_EXACT_N = 8192;
 
 struct Error : std::runtime_error {
   spt_status code;
