@@ -58,21 +58,27 @@ def algorithmic_bytes(plan, R, bc, bx):
             + R * (N * bx + N * bx + 2 * spectra * bc))
 
 
-def fft_bytes(plan, R, bc, bx):
-    """Bytes of the FFT launch: every block reads its retained columns of x
-    (together about N reals per right-hand side) and writes its half spectrum."""
-    spectra = sum(L // 2 + 1 for L, _, _, _ in plan.blocks())
-    retained = sum(hi - lo for _, _, lo, hi in plan.blocks())
+def fft_bytes(plan, R, bc, bx, blocks=None):
+    """Bytes of an FFT launch over `blocks` (default all): each block reads its
+    retained columns of x and writes its half spectrum."""
+    bl = plan.blocks()
+    idx = range(len(bl)) if blocks is None else blocks
+    spectra = sum(bl[i][0] // 2 + 1 for i in idx)
+    retained = sum(bl[i][3] - bl[i][2] for i in idx)
     return R * (retained * bx + spectra * bc)
 
 
-def product_bytes(plan, R, bc, bx):
-    """Bytes of the banded-product launch: the compressed blocks, band starts
-    and tail, the tail's x columns, the half spectra read, y written."""
+def product_bytes(plan, R, bc, bx, blocks=None, tail=True):
+    """Bytes of a banded-product launch over `blocks` (default all): their kept
+    entries and band starts, the tail and its x columns when `tail`, the half
+    spectra read, y written."""
     info = plan.info()
-    N, t = info["N"], info["tail"]
-    spectra = sum(L // 2 + 1 for L, _, _, _ in plan.blocks())
-    return (info["nnz"] * bc + 4 * N * info["n_blocks"] + N * t * bx
+    N, t = info["N"], (info["tail"] if tail else 0)
+    bl = plan.blocks()
+    idx = list(range(len(bl))) if blocks is None else list(blocks)
+    spectra = sum(bl[i][0] // 2 + 1 for i in idx)
+    nnz = sum(info["nnz_blk"][i] for i in idx)
+    return (nnz * bc + 4 * N * len(idx) + N * t * bx
             + R * (t * bx + N * bx + spectra * bc))
 
 
@@ -131,12 +137,55 @@ def cpu_baseline(w, X, rows_sample=16384):
                                                                         X.shape[0], t)}
 
 
+def large_workload(args, spt, workloads):
+    """The 48-plan batch (one staged batch per step, all plans) or the
+    Laguerre-function plan (N = 65536, 1024 right-hand sides): float64 and
+    split-bf16 throughput in RHS-transforms/s (sum of right-hand sides over
+    the step time)."""
+    import numpy as np
+    import torch
+    fams = {2: "legendre", 3: "jacobi", 4: "laguerre_fn", 5: "hermite_fn"}
+    ws = workloads.batch_plans() if args.workload == "batch48" else [workloads.LAGUERRE_65536]
+    prec_mask = (1 << spt.F64) | (1 << spt.SPLIT_BF16)
+    t0 = time.perf_counter()
+    plans = [spt.Plan(fams[w["family"]], w["N"], w["eps"], alpha=w.get("alpha", 0.0),
+                      beta=w.get("beta", 0.0), precisions=prec_mask).precompute() for w in ws]
+    t_pre = time.perf_counter() - t0
+    log("precompute %d plans %.1f s" % (len(plans), t_pre))
+    Xh = [workloads.rhs(w["rhs"], w["nrhs"], w["N"], w["seed"]) for w in ws]
+    total_r = sum(w["nrhs"] for w in ws)
+    out = {"metric": "RHS-transforms/s", "workload": args.workload, "plans": len(ws),
+           "nrhs_total": total_r, "precompute_s": t_pre,
+           "modes": [p.info()["mode"] for p in plans], "paths": {}}
+    for name, prec, dt in (("f64", spt.F64, torch.float64), ("split_bf16", spt.SPLIT_BF16,
+                                                             torch.float32)):
+        X = [torch.as_tensor(x, device="cuda").to(dt) for x in Xh]
+        Y = [torch.empty_like(x) for x in X]
+        run = lambda: spt.execute_batched(plans, X, Y, prec=prec)
+        steps = max(3, min(args.steps, 20))
+        t = timed_steps(run, steps, min(args.warmup, 3))
+        spt.profile_begin()
+        for _ in range(steps):
+            run()
+        torch.cuda.synchronize()
+        st = spt.profile_end()
+        out["paths"][name] = {"value": total_r * steps / t, "ms_per_step": 1e3 * t / steps,
+                              "kernel_ms": {k: v[0] / max(v[1], 1) for k, v in st.items() if v[1]}}
+        log(name, out["paths"][name])
+        del X, Y
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", default="legendre-n16384-r64",
+                    choices=["legendre-n16384-r64", "batch48", "laguerre-fn-n65536-r1024"],
+                    help="the headline workload (default), or one of the two large ones "
+                         "(timed the same way, reported for the design notes)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (5 launches) and exit: "
                          "the reference reading for the HBM byte counters")
@@ -160,6 +209,9 @@ def main():
         return
     import paper_2004_11610_amd as spt
     import workloads
+    if args.workload != "legendre-n16384-r64":
+        print(json.dumps(large_workload(args, spt, workloads)), flush=True)
+        return
 
     w = workloads.LEGENDRE_16384
     N, R = w["N"], w["nrhs"]
@@ -223,13 +275,12 @@ def main():
         name, nbytes = launches[stage]
         achieved = nbytes / (km[stage] * 1e-3) / 1e9
         return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS,
-                "traffic": measured_traffic("fft" if stage == "fft" else "spmm"),
+                "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(stage),
                 "kernel": name, "bytes_per_launch": nbytes, "avg_launch_ms": km[stage]}
 
     dominant = max(launches, key=lambda k: km.get(k, 0.0))
     roof = roofline(dominant)
-    other = roofline("spmm" if dominant == "fft" else "fft")
+    other = {k: roofline(k) for k in launches if k != dominant}
     out = {
         "metric": METRIC,
         "value": split["value"],
@@ -254,7 +305,7 @@ def main():
         "split_vs_f64": split["value"] / res["f64"]["value"],
         "rel_err_vs_f64": err,
         "roofline": roof,
-        "roofline_other_launch": other,
+        "roofline_other_launches": other,
         "stage_bytes_per_step": algorithmic_bytes(plan, R, 12, 4),
         "kernel_sources_sha256": kernel_source_hash(),
         "precompute_s": t_pre,

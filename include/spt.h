@@ -150,6 +150,7 @@ typedef struct {
                                             retained columns): the factor by which
                                             rounding of the half spectra grows in
                                             the product (sec. 2.2 error growth)  */
+  int64_t nnz_blk[16];                   /* kept half-spectrum entries per block  */
 } spt_plan_info;
 
 /* Create a plan for the N x N matrix of `family` with threshold eps (= eps1 of

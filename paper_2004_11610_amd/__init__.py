@@ -88,8 +88,9 @@ class Plan:
     def info(self):
         inf = _lib.SptPlanInfo()
         _lib.check(self._lib.spt_plan_query(self._h, byref(inf)))
-        out = {f: getattr(inf, f) for f, _ in inf._fields_ if f != "max_abs"}
+        out = {f: getattr(inf, f) for f, _ in inf._fields_ if f not in ("max_abs", "nnz_blk")}
         out["max_abs"] = list(inf.max_abs)[: max(inf.n_blocks, 0)]
+        out["nnz_blk"] = list(inf.nnz_blk)[: max(inf.n_blocks, 0)]
         return out
 
     def nodes(self):

@@ -970,21 +970,66 @@ void execute_staged_t(spt_plan_t plan, const T* X, T* Y, int64_t R, int prec, hi
   ensure_work(plan, R);
   const int nblk = (int)plan->blk.size();
   const bool split = std::is_same<T, float>::value && prec == SPT_SPLIT_BF16;
-  if (nblk > 0 && plan->fft_maxP <= FUSED_MAX_P) {
-    const FftDesc<T>* d = std::is_same<T, double>::value ? (const FftDesc<T>*)plan->fftdesc64.p
-                                                         : (const FftDesc<T>*)plan->fftdesc32.p;
-    staged(SPT_STAGE_FFT, s, [&] {
-      if constexpr (std::is_same<T, float>::value) {
-        if (split) {
-          launch_exec_fft_multi_split(d, nblk, plan->fft_threads, plan->fft_maxP, X,
-                                      plan->work.as<uint32_t>(), (int64_t)R * plan->zper4,
-                                      (int)R, plan->N, s);
-          return;
-        }
+  const bool fused = nblk > 0 && plan->fft_maxP <= FUSED_MAX_P;
+  const FftDesc<T>* d = std::is_same<T, double>::value ? (const FftDesc<T>*)plan->fftdesc64.p
+                                                       : (const FftDesc<T>*)plan->fftdesc32.p;
+  // fused FFT launch of blocks b0 .. b0 + nb - 1 on stream st
+  auto fft_fused = [&](int b0, int nb, hipStream_t st) {
+    int threads = 64, maxP = 1;
+    for (int b = b0; b < b0 + nb; ++b) {
+      threads = std::max(threads, plan->blk[b]->fft.threads);
+      maxP = std::max(maxP, plan->blk[b]->P);
+    }
+    if constexpr (std::is_same<T, float>::value) {
+      if (split) {
+        launch_exec_fft_multi_split(d + b0, nb, threads, maxP, X, plan->work.as<uint32_t>(),
+                                    (int64_t)R * plan->zper4, (int)R, plan->N, st);
+        return;
       }
-      launch_exec_fft_multi<T>(d, nblk, plan->fft_threads, plan->fft_maxP, X, plan->work.as<C>(),
-                               (int)R, plan->N, s);
-    });
+    }
+    launch_exec_fft_multi<T>(d + b0, nb, threads, maxP, X, plan->work.as<C>(), (int)R, plan->N,
+                             st);
+  };
+  // banded product of every block and the tail
+  auto product = [&](hipStream_t st) {
+    if constexpr (std::is_same<T, float>::value) {
+      if (split) {
+        SpmmSplitArgs pa{};
+        pa.meta = plan->tilemeta_bf.as<TileMeta>();
+        pa.blocks = plan->spmmblk_bf.as<SpmmSplitBlock>();
+        pa.nblk = nblk;
+        pa.n_tiles = plan->n_tiles;
+        pa.Zs = plan->work.as<uint32_t>();
+        pa.zplane = (int64_t)R * plan->zper4;
+        pa.tail = (int)plan->tail;
+        pa.tailmat = plan->tailbf.as<uint16_t>();
+        pa.X = X;
+        pa.Y = Y;
+        pa.R = (int)R;
+        pa.N = plan->N;
+        launch_spmm_presplit(pa, st);
+        return;
+      }
+    }
+    SpmmArgs<T> sa{};
+    sa.nblk = nblk;
+    sa.n_tiles = plan->n_tiles;
+    sa.meta = plan->tilemeta.as<TileMeta>();
+    sa.blocks = std::is_same<T, double>::value ? (const SpmmBlock<T>*)plan->spmmblk64.p
+                                               : (const SpmmBlock<T>*)plan->spmmblk32.p;
+    sa.Z = plan->work.as<C>();
+    sa.tail = (int)plan->tail;
+    sa.tailmat = std::is_same<T, double>::value ? (const T*)plan->tail64.p
+                                                : (const T*)plan->tail32.p;
+    sa.X = X;
+    sa.Y = Y;
+    sa.R = (int)R;
+    sa.N = plan->N;
+    launch_spmm<T>(sa, st);
+  };
+
+  if (fused) {
+    staged(SPT_STAGE_FFT, s, [&] { fft_fused(0, nblk, s); });
   } else if (nblk > 0) {
     ExecCtx& c = plan_ctx(plan, R, prec, s, true);
     ExecArgs<T> a{};
@@ -1001,39 +1046,7 @@ void execute_staged_t(spt_plan_t plan, const T* X, T* Y, int64_t R, int prec, hi
       launch_fft_items<T>(a, split, s);
     });
   }
-  if constexpr (std::is_same<T, float>::value) {
-    if (split) {
-      SpmmSplitArgs pa{};
-      pa.meta = plan->tilemeta_bf.as<TileMeta>();
-      pa.blocks = plan->spmmblk_bf.as<SpmmSplitBlock>();
-      pa.nblk = nblk;
-      pa.n_tiles = plan->n_tiles;
-      pa.Zs = plan->work.as<uint32_t>();
-      pa.zplane = (int64_t)R * plan->zper4;
-      pa.tail = (int)plan->tail;
-      pa.tailmat = plan->tailbf.as<uint16_t>();
-      pa.X = X;
-      pa.Y = Y;
-      pa.R = (int)R;
-      pa.N = plan->N;
-      staged(SPT_STAGE_SPMM, s, [&] { launch_spmm_presplit(pa, s); });
-      return;
-    }
-  }
-  SpmmArgs<T> sa{};
-  sa.nblk = nblk;
-  sa.n_tiles = plan->n_tiles;
-  sa.meta = plan->tilemeta.as<TileMeta>();
-  sa.blocks = std::is_same<T, double>::value ? (const SpmmBlock<T>*)plan->spmmblk64.p
-                                             : (const SpmmBlock<T>*)plan->spmmblk32.p;
-  sa.Z = plan->work.as<C>();
-  sa.tail = (int)plan->tail;
-  sa.tailmat = std::is_same<T, double>::value ? (const T*)plan->tail64.p : (const T*)plan->tail32.p;
-  sa.X = X;
-  sa.Y = Y;
-  sa.R = (int)R;
-  sa.N = plan->N;
-  staged(SPT_STAGE_SPMM, s, [&] { launch_spmm<T>(sa, s); });
+  staged(SPT_STAGE_SPMM, s, [&] { product(s); });
 }
 
 template <typename T>
@@ -1513,6 +1526,7 @@ spt_status spt_plan_query(spt_plan_t plan, spt_plan_info* info) {
         info->max_band = std::max(info->max_band, B.max_band);
         tiles_bytes += (int64_t)plan->n_tiles * 16;
         if (i < 16) info->max_abs[i] = B.maxabs;
+        if (i < 16) info->nnz_blk[i] = B.nnz;
         info->kappa = std::max(info->kappa, B.kappa);
       }
       info->matrix_bytes_f64 = info->stored * 16 + tiles_bytes + plan->tail * ldt * 8;
