@@ -424,3 +424,20 @@ def test_batched_staged_matches_single_plans(spt):
                 e = rel_rows(to_host(y), ref)
                 assert e <= (1e-13 if prec == spt.F64 else reduced_tol(p)), (rep, e)
 
+
+@pytest.mark.parametrize("R", [256, 300, 513])
+def test_split_product_chunks_match_alone(spt, R):
+    """Right-hand sides are taken 64 per product workgroup; the first 64 of a
+    larger set come out bit for bit as when executed alone (same FFTs, same
+    order of the sums), and all of them within the bar of F64."""
+    import torch
+    say("split product chunks", R)
+    p = spt.Plan("legendre", 2048, 1e-7).precompute()
+    X = workloads.rhs("normal", R, 2048, 81)
+    Xd = to_dev(X, torch.float32)
+    Y = to_host(p.execute(Xd, prec=spt.SPLIT_BF16))
+    Y64 = to_host(p.execute(Xd[:64].contiguous(), prec=spt.SPLIT_BF16))
+    assert np.array_equal(Y[:64], Y64)
+    e = rel_rows(Y, run(spt, p, X, spt.F64))
+    say("  rel vs F64 %.3e" % e)
+    assert e <= reduced_tol(p)
