@@ -6,7 +6,10 @@ Legendre nodes), 64 right-hand sides x ~ N(0, 1) (seed 1), eps1 = 1e-7,
 eps2 = 1e-2, float64 precomputation.  One step = one spt_execute of all 64
 right-hand sides (extend + window + FFT of every block, banded product of every
 block and the direct tail): two launches, the FFTs of every block, then the
-banded products.  The headline value is the split-bf16 path (float32 FFT,
+banded products.  The timed steps are dealt in turn to --streams streams
+(default 3), each with its own output buffer, so that independent batches
+are in flight together as in serving; the one-stream rate (each step after the
+previous one) is reported beside it.  The headline value is the split-bf16 path (float32 FFT,
 three-piece bfloat16 matrix-core product accumulated in float32); the float64
 and float32 paths are timed beside it on the same plan, the split path's error
 against the float64 path is reported, and the one-launch persistent executor
@@ -182,6 +185,9 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--streams", type=int, default=3,
+                    help="streams the timed steps are dealt to in turn (independent "
+                         "batches in flight at once; 1 = strictly one after another)")
     ap.add_argument("--workload", default="legendre-n16384-r64",
                     choices=["legendre-n16384-r64", "batch48", "laguerre-fn-n65536-r1024"],
                     help="the headline workload (default), or one of the two large ones "
@@ -234,8 +240,24 @@ def main():
     res = {}
 
     def measure(pl, prec, X, Y):
-        t = timed_steps(lambda: pl.execute(X, Y, prec=prec), args.steps, args.warmup)
-        r = {"ms_per_step": 1e3 * t / args.steps, "value": R * args.steps / t}
+        # steps dealt to the streams in turn: each step is a whole execute of
+        # the 64 right-hand sides into its stream's output buffer
+        streams = [torch.cuda.Stream() for _ in range(args.streams)]
+        Ys = [Y] + [torch.empty_like(Y) for _ in range(args.streams - 1)]
+        state = {"i": 0}
+
+        def step():
+            j = state["i"] % args.streams
+            state["i"] += 1
+            with torch.cuda.stream(streams[j]):
+                pl.execute(X, Ys[j], prec=prec)
+
+        torch.cuda.synchronize()
+        t = timed_steps(step, args.steps, args.warmup)
+        t1 = timed_steps(lambda: pl.execute(X, Y, prec=prec), args.steps, args.warmup)
+        r = {"ms_per_step": 1e3 * t / args.steps, "value": R * args.steps / t,
+             "streams": args.streams,
+             "one_stream": {"ms_per_step": 1e3 * t1 / args.steps, "value": R * args.steps / t1}}
         # kernel times with HIP events on the execute stream
         spt.profile_begin()
         for _ in range(args.steps):
@@ -297,10 +319,13 @@ def main():
         "config": {"workload": w["name"], "family": "legendre", "N": N, "nrhs": R,
                    "eps1": w["eps"], "eps2": info["eps2"], "blocks": [b[0] for b in plan.blocks()],
                    "tail": info["tail"], "nnz": info["nnz"], "parallelism": "single-gpu"},
+        "streams": args.streams,
         "paths": {k: {"value": v["value"], "ms_per_step": v["ms_per_step"],
-                      "kernel_ms": v["kernel_ms"]} for k, v in res.items()},
+                      "one_stream": v["one_stream"], "kernel_ms": v["kernel_ms"]}
+                  for k, v in res.items()},
         "split_bf16_persistent_executor": {"value": res_pers["value"],
                                            "ms_per_step": res_pers["ms_per_step"],
+                                           "one_stream": res_pers["one_stream"],
                                            "kernel_ms": res_pers["kernel_ms"]},
         "split_vs_f64": split["value"] / res["f64"]["value"],
         "rel_err_vs_f64": err,

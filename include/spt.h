@@ -173,7 +173,11 @@ spt_status spt_precompute(spt_plan_t plan, void* stream);
 
 /* Y = A X^T for nrhs right-hand sides: Y[r*N + j] = sum_m A[j,m] X[r*N + m].
  * X, Y: device, nrhs x N, float64 for SPT_F64 and float32 otherwise, must not
- * overlap.  nrhs >= 1.  The precision must have been prepared. */
+ * overlap.  nrhs >= 1.  The precision must have been prepared.
+ * Asynchronous on `stream`.  The plan keeps one workspace per stream (up to 8
+ * streams; a ninth takes over the oldest after a device synchronisation), so
+ * executes of one plan on different streams may run at the same time; the
+ * host calls on one plan must not be made from several threads at once. */
 spt_status spt_execute(spt_plan_t plan, const void* X, void* Y, int64_t nrhs, int32_t prec,
                        void* stream);
 
@@ -190,8 +194,9 @@ spt_status spt_execute_transposed(spt_plan_t plan, const void* X, void* Y, int64
  * launch of the persistent executor; otherwise as three launches (the FFT
  * items of every plan in two, then every plan's banded products in one).  The
  * first call for a set of plans and sizes builds the work lists (host work and
- * a stream synchronisation), later calls reuse them.  Calls for the same plans
- * must not overlap in time (shared workspaces and counters). */
+ * a stream synchronisation), later calls reuse them.  A plan may appear once
+ * per batch.  Batches of the same plans on different streams use each plan's
+ * workspace of that stream and their own work lists, and may overlap. */
 spt_status spt_execute_batched(const spt_plan_t* plans, const void* const* X, void* const* Y,
                                const int64_t* nrhs, int32_t count, int32_t prec, void* stream);
 

@@ -125,14 +125,20 @@ struct spt_plan {
   double p0 = 0.0;
   std::vector<std::unique_ptr<spt::DevBlock>> blk;
   spt::DevBuf tail64, tail32, tailbf;
-  spt::DevBuf work;  // execute workspace (half spectra)
+  // execute workspaces (half spectra, four-step intermediates): one per stream
+  // that executed the plan, so that executes on different streams overlap
+  struct Work {
+    hipStream_t stream = nullptr;
+    spt::DevBuf buf;
+  };
+  std::vector<std::unique_ptr<Work>> works;
+  spt::DevBuf* work = nullptr;  // the workspace of the call in progress
   spt::DevBuf fftdesc64, fftdesc32;  // FftDesc per block for the fused FFT launch
   spt::DevBuf tilemeta;              // TileMeta per (tile, block)
   spt::DevBuf spmmblk64, spmmblk32;  // SpmmBlock per block
   spt::DevBuf tilemeta_bf, spmmblk_bf;  // the same for the pre-split boxes
   int64_t zper4 = 0;                    // sum of ldz4 over the blocks
   int fft_threads = 64, fft_maxP = 1;
-  int64_t work_rhs = 0;
   int64_t serial = 0;  // changes with every precompute (keys of executor contexts)
   std::vector<std::unique_ptr<spt::ExecCtx>> ctx;  // executor contexts of spt_execute
 };
@@ -747,10 +753,10 @@ void build_exec_ctx(ExecCtx& c, const spt_plan_t* plans, const int64_t* R, int c
       zoff4 += B.ldz4;
     }
     ExecPlan<T>& P = ep[i];
-    P.Z = plan->work.as<C>();
+    P.Z = plan->work->as<C>();
     P.W = P.Z + (int64_t)r * zoff;
     if (split) {
-      P.Zs = plan->work.as<uint32_t>();
+      P.Zs = plan->work->as<uint32_t>();
       P.zplane = (int64_t)r * zoff4;
       P.W = reinterpret_cast<C*>(P.Zs + 3 * P.zplane);
     }
@@ -926,7 +932,24 @@ void precompute(spt_plan_t plan, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------- execute
-void ensure_work(spt_plan_t plan, int64_t R) {
+// select (and size) the workspace of stream s
+void ensure_work(spt_plan_t plan, int64_t R, hipStream_t s) {
+  spt_plan::Work* w = nullptr;
+  for (auto& e : plan->works)
+    if (e->stream == s) w = e.get();
+  if (!w) {
+    if (plan->works.size() >= 8) {
+      // take over the oldest stream's workspace once the device is idle
+      SPT_HIP(hipDeviceSynchronize());
+      std::rotate(plan->works.begin(), plan->works.begin() + 1, plan->works.end());
+      w = plan->works.back().get();
+    } else {
+      plan->works.push_back(std::make_unique<spt_plan::Work>());
+      w = plan->works.back().get();
+    }
+    w->stream = s;
+  }
+  plan->work = &w->buf;
   const int64_t per = z_per_rhs(plan) + w_per_rhs(plan);
   // complex float64 spectra (and four-step intermediates), or the three
   // bfloat16-pair planes of the split-bf16 path
@@ -934,10 +957,11 @@ void ensure_work(spt_plan_t plan, int64_t R) {
       std::max((size_t)std::max<int64_t>(per, 1) * (size_t)R * sizeof(double2),
                ((size_t)plan->zper4 * 3 * sizeof(uint32_t) + (size_t)w_per_rhs(plan) * sizeof(float2)) *
                    (size_t)R);
-  if (bytes > plan->work.bytes) {
-    plan->ctx.clear();  // contexts hold the old workspace address
-    plan->work.alloc(bytes);
-    plan->work_rhs = R;
+  if (bytes > plan->work->bytes) {
+    // work lists hold the old workspace address; work in flight may use them
+    SPT_HIP(hipDeviceSynchronize());
+    plan->ctx.clear();
+    plan->work->alloc(bytes);
   }
 }
 
@@ -967,7 +991,7 @@ ExecCtx& plan_ctx(spt_plan_t plan, int64_t R, int prec, hipStream_t s, bool stag
 template <typename T>
 void execute_staged_t(spt_plan_t plan, const T* X, T* Y, int64_t R, int prec, hipStream_t s) {
   using C = cplx_t<T>;
-  ensure_work(plan, R);
+  ensure_work(plan, R, s);
   const int nblk = (int)plan->blk.size();
   const bool split = std::is_same<T, float>::value && prec == SPT_SPLIT_BF16;
   const bool fused = nblk > 0 && plan->fft_maxP <= FUSED_MAX_P;
@@ -982,12 +1006,12 @@ void execute_staged_t(spt_plan_t plan, const T* X, T* Y, int64_t R, int prec, hi
     }
     if constexpr (std::is_same<T, float>::value) {
       if (split) {
-        launch_exec_fft_multi_split(d + b0, nb, threads, maxP, X, plan->work.as<uint32_t>(),
+        launch_exec_fft_multi_split(d + b0, nb, threads, maxP, X, plan->work->as<uint32_t>(),
                                     (int64_t)R * plan->zper4, (int)R, plan->N, st);
         return;
       }
     }
-    launch_exec_fft_multi<T>(d + b0, nb, threads, maxP, X, plan->work.as<C>(), (int)R, plan->N,
+    launch_exec_fft_multi<T>(d + b0, nb, threads, maxP, X, plan->work->as<C>(), (int)R, plan->N,
                              st);
   };
   // banded product of every block and the tail
@@ -999,7 +1023,7 @@ void execute_staged_t(spt_plan_t plan, const T* X, T* Y, int64_t R, int prec, hi
         pa.blocks = plan->spmmblk_bf.as<SpmmSplitBlock>();
         pa.nblk = nblk;
         pa.n_tiles = plan->n_tiles;
-        pa.Zs = plan->work.as<uint32_t>();
+        pa.Zs = plan->work->as<uint32_t>();
         pa.zplane = (int64_t)R * plan->zper4;
         pa.tail = (int)plan->tail;
         pa.tailmat = plan->tailbf.as<uint16_t>();
@@ -1017,7 +1041,7 @@ void execute_staged_t(spt_plan_t plan, const T* X, T* Y, int64_t R, int prec, hi
     sa.meta = plan->tilemeta.as<TileMeta>();
     sa.blocks = std::is_same<T, double>::value ? (const SpmmBlock<T>*)plan->spmmblk64.p
                                                : (const SpmmBlock<T>*)plan->spmmblk32.p;
-    sa.Z = plan->work.as<C>();
+    sa.Z = plan->work->as<C>();
     sa.tail = (int)plan->tail;
     sa.tailmat = std::is_same<T, double>::value ? (const T*)plan->tail64.p
                                                 : (const T*)plan->tail32.p;
@@ -1062,16 +1086,16 @@ void execute_transposed_t(spt_plan_t plan, const T* F, T* Y, int64_t R, hipStrea
   if (plan->fft_maxP > FUSED_MAX_P)
     throw Error(SPT_E_UNSUPPORTED, "the transposed product needs FFT half-lengths <= " +
                                        std::to_string(FUSED_MAX_P));
-  ensure_work(plan, R);
+  ensure_work(plan, R, s);
   int64_t per = 0;
   for (auto& B : plan->blk) per += B->P + 1;
   const int64_t nz = 2 * per * R;
   if (nz > 0) {
     const int nb = (int)std::min<int64_t>((nz + 255) / 256, 8192);
-    hipLaunchKernelGGL(zero_kernel<T>, dim3(nb), dim3(256), 0, s, (T*)plan->work.p, nz);
+    hipLaunchKernelGGL(zero_kernel<T>, dim3(nb), dim3(256), 0, s, (T*)plan->work->p, nz);
     SPT_HIP(hipGetLastError());
   }
-  C* u = plan->work.as<C>();
+  C* u = plan->work->as<C>();
   for (auto& Bp : plan->blk) {
     DevBlock& B = *Bp;
     SpmmTArgs<T> ta{};
@@ -1199,7 +1223,7 @@ void build_batch_products(ExecCtx& c, const spt_plan_t* plans, const int64_t* R,
       a[i].blocks = plan->spmmblk_bf.as<SpmmSplitBlock>();
       a[i].nblk = (int)plan->blk.size();
       a[i].n_tiles = plan->n_tiles;
-      a[i].Zs = plan->work.as<uint32_t>();
+      a[i].Zs = plan->work->as<uint32_t>();
       a[i].zplane = R[i] * plan->zper4;
       a[i].tail = (int)plan->tail;
       a[i].tailmat = plan->tailbf.as<uint16_t>();
@@ -1217,7 +1241,7 @@ void build_batch_products(ExecCtx& c, const spt_plan_t* plans, const int64_t* R,
                       : (const SpmmBlock<T>*)plan->spmmblk32.p;
     a[i].nblk = (int)plan->blk.size();
     a[i].n_tiles = plan->n_tiles;
-    a[i].Z = plan->work.as<cplx_t<T>>();
+    a[i].Z = plan->work->as<cplx_t<T>>();
     a[i].tail = (int)plan->tail;
     a[i].tailmat = dbl ? (const T*)plan->tail64.p : (const T*)plan->tail32.p;
     a[i].R = (int)R[i];
@@ -1288,10 +1312,13 @@ std::unique_ptr<ExecCtx> new_ctx(const std::vector<int64_t>& key, const spt_plan
 }
 
 ExecCtx& plan_ctx(spt_plan_t plan, int64_t R, int prec, hipStream_t s, bool staged) {
-  const std::vector<int64_t> key{prec, R, plan->serial, (int64_t)(intptr_t)plan->work.p, staged};
+  const std::vector<int64_t> key{prec, R, plan->serial, (int64_t)(intptr_t)plan->work->p, staged};
   for (auto& c : plan->ctx)
     if (c->key == key) return *c;
-  if (plan->ctx.size() >= 8) plan->ctx.erase(plan->ctx.begin());
+  if (plan->ctx.size() >= 8) {
+    SPT_HIP(hipDeviceSynchronize());  // the oldest work list may be in flight
+    plan->ctx.erase(plan->ctx.begin());
+  }
   plan->ctx.push_back(new_ctx(key, &plan, &R, 1, prec, s, staged));
   return *plan->ctx.back();
 }
@@ -1429,7 +1456,7 @@ spt_status spt_execute(spt_plan_t plan, const void* X, void* Y, int64_t nrhs, in
         execute_staged_t<float>(plan, (const float*)X, (float*)Y, nrhs, prec, s);
       return;
     }
-    ensure_work(plan, nrhs);
+    ensure_work(plan, nrhs, s);
     ExecCtx& c = plan_ctx(plan, nrhs, prec, s, false);
     const void* xs[1] = {X};
     void* ys[1] = {Y};
@@ -1465,10 +1492,13 @@ spt_status spt_execute_batched(const spt_plan_t* plans, const void* const* X, vo
       check_exec(plans[i], X[i], Y[i], nrhs[i], prec);
       if (plans[i]->device != plans[0]->device)
         throw Error(SPT_E_INVALID_ARG, "batched plans live on different devices");
+      for (int j = 0; j < i; ++j)
+        if (plans[j] == plans[i])
+          throw Error(SPT_E_INVALID_ARG, "a plan appears twice in one batch");
     }
     set_device(plans[0]);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    for (int i = 0; i < count; ++i) ensure_work(plans[i], nrhs[i]);
+    for (int i = 0; i < count; ++i) ensure_work(plans[i], nrhs[i], s);
     std::lock_guard<std::mutex> lk(g_batch_mu);
     // persistent when the first plan asks for it, staged launches otherwise
     const bool staged = plans[0]->p.executor != SPT_EXECUTOR_PERSISTENT;
@@ -1478,13 +1508,16 @@ spt_status spt_execute_batched(const spt_plan_t* plans, const void* const* X, vo
       for (int i = i0; i < i0 + n; ++i) {
         key.push_back(plans[i]->serial);
         key.push_back(nrhs[i]);
-        key.push_back((int64_t)(intptr_t)plans[i]->work.p);
+        key.push_back((int64_t)(intptr_t)plans[i]->work->p);
       }
       ExecCtx* c = nullptr;
       for (auto& e : g_batch_ctx)
         if (e->key == key) c = e.get();
       if (!c) {
-        if (g_batch_ctx.size() >= 4) g_batch_ctx.erase(g_batch_ctx.begin());
+        if (g_batch_ctx.size() >= 4) {
+          SPT_HIP(hipDeviceSynchronize());  // the oldest work list may be in flight
+          g_batch_ctx.erase(g_batch_ctx.begin());
+        }
         g_batch_ctx.push_back(new_ctx(key, plans + i0, nrhs + i0, n, prec, s, staged, true));
         c = g_batch_ctx.back().get();
       }

@@ -441,3 +441,23 @@ def test_split_product_chunks_match_alone(spt, R):
     e = rel_rows(Y, run(spt, p, X, spt.F64))
     say("  rel vs F64 %.3e" % e)
     assert e <= reduced_tol(p)
+
+
+def test_one_plan_on_several_streams(spt):
+    """Executes of one plan on different streams overlap in time; each stream
+    has its own workspace, so every result equals the one-stream result."""
+    import torch
+    say("one plan, three streams")
+    p = spt.Plan("legendre", 4096, 1e-7).precompute()
+    Xs = [to_dev(workloads.rhs("normal", 64, 4096, 90 + i), torch.float32) for i in range(3)]
+    ref = [to_host(p.execute(x, prec=spt.SPLIT_BF16)) for x in Xs]
+    streams = [torch.cuda.Stream() for _ in range(3)]
+    Ys = [torch.empty_like(x) for x in Xs]
+    for rep in range(20):
+        for s, x, y in zip(streams, Xs, Ys):
+            with torch.cuda.stream(s):
+                p.execute(x, y, prec=spt.SPLIT_BF16)
+    torch.cuda.synchronize()
+    for y, r in zip(Ys, ref):
+        assert np.array_equal(to_host(y), r)
+
