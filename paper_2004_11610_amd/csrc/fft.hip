@@ -103,16 +103,16 @@ __global__ __launch_bounds__(FFT_MAX_THREADS) void exec_fft_multi_kernel(
   if (active) {
     const T scale = d->scale;
     const C* __restrict__ post = d->post;
-    C tw[FFT_EPT + 1];
-#pragma unroll
-    for (int e = 0; e <= FFT_EPT; ++e) {
-      const int k = tid + e * nt;
-      if (LTW)
-        tw[e] = k <= P ? to_c<C>(twiddle(ltw + d->ntw, k)) : C{T(0), T(0)};
-      else
-        tw[e] = k <= P ? post[k] : C{T(0), T(0)};
-    }
     if constexpr (!SPLIT) {
+      C tw[FFT_EPT + 1];
+#pragma unroll
+      for (int e = 0; e <= FFT_EPT; ++e) {
+        const int k = tid + e * nt;
+        if (LTW)
+          tw[e] = k <= P ? to_c<C>(twiddle(ltw + d->ntw, k)) : C{T(0), T(0)};
+        else
+          tw[e] = k <= P ? post[k] : C{T(0), T(0)};
+      }
       C* __restrict__ z = Z + (int64_t)R * d->zoff + (int64_t)r * d->ldz;
 #pragma unroll
       for (int e = 0; e <= FFT_EPT; ++e) {
@@ -120,19 +120,26 @@ __global__ __launch_bounds__(FFT_MAX_THREADS) void exec_fft_multi_kernel(
         if (k <= P) z[k] = unpack_with<+1>(lds, P, k, tw[e], scale);
       }
     } else {
-      // k < ldz4 <= P + 4 <= FFT_EPT * nt + nt: zeros past P
+      // four consecutive k per thread (ldz4 is a multiple of 4): each plane
+      // gets one 16-byte store per group; zeros past P
       uint32_t* __restrict__ zs = Zs + (int64_t)R * d->zoff4 + (int64_t)r * d->ldz4;
-      const int ldz4 = d->ldz4;
+      const int ng = d->ldz4 / 4;
+      for (int q = tid; q < ng; q += nt) {
+        uint32_t pc[4][3];
 #pragma unroll
-      for (int e = 0; e <= FFT_EPT; ++e) {
-        const int k = tid + e * nt;
-        if (k < ldz4) {
-          const C z = k <= P ? unpack_with<+1>(lds, P, k, tw[e], scale) : C{T(0), T(0)};
-          uint32_t pc[3];
-          spmmcore::split2(spmmcore::f32x2{(float)z.x, (float)z.y}, pc);
-#pragma unroll
-          for (int p = 0; p < 3; ++p) zs[p * zplane + k] = pc[p];
+        for (int j = 0; j < 4; ++j) {
+          const int k = 4 * q + j;
+          C z = C{T(0), T(0)};
+          if (k <= P) {
+            const C t = LTW ? to_c<C>(twiddle(ltw + d->ntw, k)) : post[k];
+            z = unpack_with<+1>(lds, P, k, t, scale);
+          }
+          spmmcore::split2(spmmcore::f32x2{(float)z.x, (float)z.y}, pc[j]);
         }
+#pragma unroll
+        for (int p = 0; p < 3; ++p)
+          *reinterpret_cast<uint4*>(zs + p * zplane + 4 * q) =
+              uint4{pc[0][p], pc[1][p], pc[2][p], pc[3][p]};
       }
     }
   }
