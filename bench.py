@@ -7,7 +7,7 @@ eps2 = 1e-2, float64 precomputation.  One step = one spt_execute of all 64
 right-hand sides (extend + window + FFT of every block, banded product of every
 block and the direct tail): two launches, the FFTs of every block, then the
 banded products.  The timed steps are dealt in turn to --streams streams
-(default 3), each with its own output buffer, so that independent batches
+(default 4), each with its own output buffer, so that independent batches
 are in flight together as in serving; the one-stream rate (each step after the
 previous one) is reported beside it.  The headline value is the split-bf16 path (float32 FFT,
 three-piece bfloat16 matrix-core product accumulated in float32); the float64
@@ -185,7 +185,7 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--streams", type=int, default=3,
+    ap.add_argument("--streams", type=int, default=4,
                     help="streams the timed steps are dealt to in turn (independent "
                          "batches in flight at once; 1 = strictly one after another)")
     ap.add_argument("--workload", default="legendre-n16384-r64",
