@@ -151,6 +151,12 @@ typedef struct {
                                             rounding of the half spectra grows in
                                             the product (sec. 2.2 error growth)  */
   int64_t nnz_blk[16];                   /* kept half-spectrum entries per block  */
+  int64_t window_lds;                    /* SPLIT_BF16 product: LDS bytes of a workgroup
+                                            of the windowed kernel, 0 when the plan
+                                            uses the per-tile kernel              */
+  int64_t window_cols;                   /* sum over groups of 4 row tiles and over
+                                            blocks of the spectrum columns that the
+                                            windowed kernel stages in LDS          */
 } spt_plan_info;
 
 /* Create a plan for the N x N matrix of `family` with threshold eps (= eps1 of

@@ -73,6 +73,7 @@ struct DevBlock {
   int P = 0;
   FftPlan fft;
   DevBuf winv64, winv32, tw64, post64, post32, posttw;
+  DevBuf ptw64, ptw32;  // pass twiddles of the fused FFT (FftDesc::ptw)
   DevBuf k0, kw, off;   // per tile
   DevBuf val64, val32;  // tile boxes
   DevBuf valbf, soff;   // pre-split tile boxes of the split-bf16 path, their offsets
@@ -138,6 +139,15 @@ struct spt_plan {
   spt::DevBuf spmmblk64, spmmblk32;  // SpmmBlock per block
   spt::DevBuf tilemeta_bf, spmmblk_bf;  // the same for the pre-split boxes
   int64_t zper4 = 0;                    // sum of ldz4 over the blocks
+  // windowed split-bf16 product: WinMeta per (tile group, block); used when
+  // every group's windows fit the LDS of a workgroup
+  spt::DevBuf winmeta;
+  int n_groups = 0;
+  size_t win_lds = 0;
+  int64_t win_cols = 0;
+  int win_rg = 4;                  // groups of 16 right-hand sides per workgroup
+  int win_xlds = 0, win_tpad = 0;  // x of the direct tail in LDS (16-byte units), its pitch
+  bool win_ok = false;
   int fft_threads = 64, fft_maxP = 1;
   int64_t serial = 0;  // changes with every precompute (keys of executor contexts)
   std::vector<std::unique_ptr<spt::ExecCtx>> ctx;  // executor contexts of spt_execute
@@ -282,6 +292,25 @@ void twiddles(int P, std::vector<long double>& twr, std::vector<long double>& tw
   }
 }
 
+// Pass twiddles of the fused FFT of plan fp (the FftDesc::ptw layout):
+// exp(2 pi i jm r / (Ns R)) for pass (R, Ns), r = 1 .. R-1, jm < Ns.
+void pass_twiddles(const FftPlan& fp, std::vector<long double>& re, std::vector<long double>& im) {
+  const long double pi = 3.141592653589793238462643383279502884L;
+  re.clear();
+  im.clear();
+  int64_t Ns = 1;
+  for (int p = 0; p < fp.npass; ++p) {
+    const int64_t R = fp.radix[p], n = Ns * R;
+    for (int64_t r = 1; r < R; ++r)
+      for (int64_t jm = 0; jm < Ns; ++jm) {
+        const long double a = 2.0L * pi * (long double)((jm * r) % n) / (long double)n;
+        re.push_back(cosl(a));
+        im.push_back(sinl(a));
+      }
+    Ns = n;
+  }
+}
+
 // two-level table of exp(i pi k / P), k <= P (the unpack twiddles):
 // lo[q] = exp(i pi q / P), q < 128; hi[q] = exp(i pi 128 q / P), q <= P / 128
 std::vector<double2> post_table(int P) {
@@ -327,6 +356,12 @@ int log2_floor(int v) {
 
 uint32_t magic_of(int d) {
   return (uint32_t)((((uint64_t)1 << 32) + (uint64_t)d - 1) / (uint64_t)d);
+}
+
+// The windowed product (diagnostics: SPT_SPMM_WINDOW=0 keeps the per-tile one).
+bool window_product_enabled() {
+  const char* e = std::getenv("SPT_SPMM_WINDOW");
+  return !(e && e[0] == '0');
 }
 
 void exec_geometry(DevBlock& B) {
@@ -406,6 +441,14 @@ int64_t build_block(spt_plan_t plan, DevBlock& B, hipStream_t s, size_t lds_max,
   upload(B.post64, to_vec2<double2, double>(por, poi), s);
   upload(B.post32, to_vec2<float2, float>(por, poi), s);
   upload(B.posttw, post_table(P), s);
+  if (!big) {
+    std::vector<long double> pr, pi_;
+    pass_twiddles(B.fft, pr, pi_);
+    pr.push_back(1.0L);  // never empty
+    pi_.push_back(0.0L);
+    upload(B.ptw64, to_vec2<double2, double>(pr, pi_), s);
+    upload(B.ptw32, to_vec2<float2, float>(pr, pi_), s);
+  }
 
   const int64_t N = plan->N;
   const int64_t ntiles = plan->n_tiles;
@@ -824,11 +867,85 @@ std::vector<FftDesc<T>> fft_descs(spt_plan_t plan) {
     e.ldz4 = B.ldz4;
     e.tw2 = B.posttw.as<double2>();
     e.ntw = 128 + B.P / 128 + 1;
+    e.ptw = (const C*)(dbl ? B.ptw64.p : B.ptw32.p);
     d.push_back(e);
     zoff += B.P + 1;
     zoff4 += B.ldz4;
   }
   return d;
+}
+
+// Windows of the windowed split-bf16 product: for each group of WIN_TILES row
+// tiles and each block, the union of the tiles' boxes (columns k0 .. k0 +
+// ceil4(kw) - 1, which is what a step reads) and its place in LDS.
+void build_windows(spt_plan_t plan, hipStream_t s) {
+  plan->win_ok = false;
+  plan->win_lds = 0;
+  const int nblk = (int)plan->blk.size();
+  plan->n_groups = (plan->n_tiles + WIN_TILES - 1) / WIN_TILES;
+  if (nblk == 0 || nblk > 64 || !window_product_enabled()) return;
+  for (auto& B : plan->blk)
+    if (B->h_soff.empty()) return;
+  // union of the boxes of each (group, block): [lo, hi) columns
+  std::vector<std::pair<int, int>> span((size_t)plan->n_groups * nblk, {0, 0});
+  for (int gi = 0; gi < plan->n_groups; ++gi)
+    for (int b = 0; b < nblk; ++b) {
+      const DevBlock& B = *plan->blk[b];
+      int lo = INT32_MAX, hi = 0;
+      for (int t = gi * WIN_TILES; t < std::min(plan->n_tiles, (gi + 1) * WIN_TILES); ++t)
+        if (B.h_kw[t] > 0) {
+          lo = std::min(lo, B.h_k0[t]);
+          hi = std::max(hi, B.h_k0[t] + ((B.h_kw[t] + 3) & ~3));
+        }
+      if (lo < hi) span[(size_t)gi * nblk + b] = {lo, hi};
+    }
+  const int tpad = plan->tail > 0 ? 32 * (int)((plan->tail + 31) / 32) + 4 : 0;
+  const size_t lds_max = max_lds_bytes(plan->device);
+  // layout for rg groups of 16 right-hand sides: windows, then the tail's x
+  auto layout = [&](int rg, std::vector<WinMeta>* win, int64_t* cols) {
+    const int nr = 16 * rg;
+    int64_t most = 0, c = 0;
+    for (int gi = 0; gi < plan->n_groups; ++gi) {
+      int64_t units = 0;
+      for (int b = 0; b < nblk; ++b) {
+        const auto sp = span[(size_t)gi * nblk + b];
+        WinMeta w{};
+        w.pitch = 3;
+        if (sp.first < sp.second) {
+          w.k0 = sp.first;
+          w.w4 = (sp.second - sp.first) / 4;
+          w.pitch = std::max(w.w4 | 1, 3);
+          w.magic = magic_of(w.pitch);
+          w.units = (3 * nr * w.pitch + 63) & ~63;
+          w.lds = (int32_t)units;
+          units += w.units;
+          c += sp.second - sp.first;
+        }
+        if (win) (*win)[(size_t)gi * nblk + b] = w;
+      }
+      most = std::max(most, units);
+    }
+    if (cols) *cols = c;
+    return std::make_pair(most, (size_t)most * 16 + (size_t)tpad * nr * sizeof(float));
+  };
+  // 64 right-hand sides per workgroup when their windows fit the LDS, else 32
+  // (diagnostics: SPT_SPMM_WINDOW_RG=4 or 2)
+  int rg = layout(4, nullptr, nullptr).second <= lds_max ? 4 : 2;
+  if (const char* e = std::getenv("SPT_SPMM_WINDOW_RG")) {
+    if (e[0] == '4') rg = 4;
+    if (e[0] == '2') rg = 2;
+  }
+  std::vector<WinMeta> win((size_t)plan->n_groups * nblk);
+  int64_t cols = 0;
+  const auto lay = layout(rg, &win, &cols);
+  if (lay.second > lds_max) return;
+  upload(plan->winmeta, win, s);
+  plan->win_rg = rg;
+  plan->win_xlds = (int)lay.first;
+  plan->win_tpad = tpad;
+  plan->win_lds = lay.second;
+  plan->win_cols = cols;
+  plan->win_ok = true;
 }
 
 void build_fft_descs(spt_plan_t plan, hipStream_t s) {
@@ -873,12 +990,14 @@ void build_fft_descs(spt_plan_t plan, hipStream_t s) {
   plan->zper4 = zoff4;
   upload(plan->tilemeta_bf, meta_bf, s);
   upload(plan->spmmblk_bf, bbf, s);
+  build_windows(plan, s);
 }
 
 void precompute(spt_plan_t plan, hipStream_t s) {
   set_device(plan);
   const size_t lds_max = max_lds_bytes(plan->device);
   init_fft_kernels(lds_max);
+  init_spmm_kernels(lds_max);
   plan->precomputed = false;
   plan->ctx.clear();
   plan->serial = next_serial();
@@ -1031,7 +1150,13 @@ void execute_staged_t(spt_plan_t plan, const T* X, T* Y, int64_t R, int prec, hi
         pa.Y = Y;
         pa.R = (int)R;
         pa.N = plan->N;
-        launch_spmm_presplit(pa, st);
+        // the windowed kernel forms byte offsets within the three spectrum
+        // planes in 32 bits
+        if (plan->win_ok && 12.0 * (double)R * (double)plan->zper4 < 4294967296.0)
+          launch_spmm_window(pa, plan->winmeta.as<WinMeta>(), plan->n_groups, plan->win_rg,
+                             plan->win_xlds, plan->win_tpad, plan->win_lds, st);
+        else
+          launch_spmm_presplit(pa, st);
         return;
       }
     }
@@ -1564,6 +1689,10 @@ spt_status spt_plan_query(spt_plan_t plan, spt_plan_info* info) {
       }
       info->matrix_bytes_f64 = info->stored * 16 + tiles_bytes + plan->tail * ldt * 8;
       info->matrix_bytes_f32 = info->stored * 8 + tiles_bytes + plan->tail * ldt * 4;
+      if (plan->win_ok) {
+        info->window_lds = (int64_t)plan->win_lds;
+        info->window_cols = plan->win_cols;
+      }
     }
   });
 }

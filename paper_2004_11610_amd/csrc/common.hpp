@@ -43,6 +43,25 @@ struct Error : std::runtime_error {
                          std::string(#call) + ": " + hipGetErrorString(e_));            \
   } while (0)
 
+// load through a global-memory pointer: a pointer loaded from memory or rebuilt
+// from an integer is generic, and a generic (flat) load also waits for and is
+// waited on by LDS traffic
+template <typename V>
+__device__ __forceinline__ V gload(const V* p) {
+  return *(const __attribute__((address_space(1))) V*)p;
+}
+// HIP's float2 / double2 are classes: load their native vector
+__device__ __forceinline__ float2 gload(const float2* p) {
+  typedef float v2 __attribute__((ext_vector_type(2)));
+  const v2 v = *(const __attribute__((address_space(1))) v2*)p;
+  return float2{v.x, v.y};
+}
+__device__ __forceinline__ double2 gload(const double2* p) {
+  typedef double v2 __attribute__((ext_vector_type(2)));
+  const v2 v = *(const __attribute__((address_space(1))) v2*)p;
+  return double2{v.x, v.y};
+}
+
 template <typename T> struct cplx;
 template <> struct cplx<double> { using type = double2; };
 template <> struct cplx<float> { using type = float2; };
@@ -91,6 +110,10 @@ struct FftDesc {
   int ldz4;
   const double2* tw2;  // two-level table of exp(i pi k / P), k <= P
   int ntw;             // entries of tw and of tw2: 128 + P / 128 + 1
+  // pass twiddles of fp in the working precision: pass p (radix R, Ns points
+  // already combined) keeps exp(2 pi i jm r / (Ns R)) at ptw[off_p + (r-1) Ns
+  // + jm], r = 1 .. R-1, jm < Ns; off_p = sum of (R-1) Ns over earlier passes
+  const cplx_t<T>* ptw;
 };
 
 template <typename T>
@@ -188,6 +211,30 @@ struct SpmmSplitArgs {
   int64_t N;
 };
 void launch_spmm_presplit(const SpmmSplitArgs& a, hipStream_t s);
+
+// Windowed pre-split product: a workgroup takes WIN_TILES consecutive row
+// tiles and NR = 16 rg right-hand sides (rg = 4 or 2), and the half spectra
+// its tiles' boxes need in each block (the union of the boxes, a window of
+// consecutive columns) are staged in LDS once for all of them.  Window of
+// (tile group, block) in LDS: row q = NR p + i (piece p, right-hand side
+// r0 + i) at lds + q * pitch, pitch 16-byte units (4 complex columns each)
+// from column k0.
+constexpr int WIN_TILES = 4;
+struct WinMeta {
+  int32_t k0;      // first column of the window (multiple of 4)
+  int32_t w4;      // width in groups of 4 columns (0: no box of the block in the group)
+  int32_t pitch;   // LDS row pitch in 16-byte units: odd, >= max(w4, 3)
+  int32_t lds;     // offset of the window in LDS, 16-byte units
+  uint32_t magic;  // ceil(2^32 / pitch): q = umulhi(u, magic) = u / pitch for u * pitch < 2^32
+  int32_t units;   // 16-byte units of the window, 3 * NR * pitch rounded up to 64
+  int32_t pad[2];
+};
+// win: n_groups x nblk, group-major.  LDS: the windows (the largest sum of a
+// group's windows), then from 16-byte unit xlds the direct tail's x of the NR
+// right-hand sides, tpad = 32 * ceil(tail / 32) + 4 floats apart (0: no tail).
+void launch_spmm_window(const SpmmSplitArgs& a, const WinMeta* win, int n_groups, int rg,
+                        int xlds, int tpad, size_t lds_bytes, hipStream_t s);
+void init_spmm_kernels(size_t max_lds);
 
 // Products of several plans in one launch: items (plan, row tile or -1, first
 // rhs) index per-plan argument blocks in device memory; X and Y of each plan

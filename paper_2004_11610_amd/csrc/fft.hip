@@ -10,11 +10,13 @@
 //
 // Conventions: F of eq. (1) has the kernel exp(-2 pi i jk/L)/sqrt(L) (SIGN -1,
 // used by the precomputation A_e W F); the computation stage applies F*
-// (SIGN +1).  The pass twiddles exp(+2 pi i q/P) come from two float64 tables
-// of 128 + P/128 entries (w^q = lo[q % 128] hi[q / 128]; a butterfly forms w^jm
-// once and its powers in float64, for every precision); the unpack twiddles
-// exp(+i pi k/P) (k <= P) are a table in the working precision.  SIGN -1 uses
-// their conjugates.
+// (SIGN +1).  The fused computation-stage kernel in float32 reads its pass
+// twiddles exp(+2 pi i jm r/(Ns R)) from one table per block (each entry
+// rounded once from extended precision); the other kernels form them from two
+// float64 tables of 128 + P/128 entries (w^q = lo[q % 128]
+// hi[q / 128]), a butterfly taking w^jm once and its powers in float64.  The
+// unpack twiddles exp(+i pi k/P) (k <= P) are a table in the working
+// precision.  SIGN -1 uses the conjugates.
 
 #include "fft_core.hpp"
 #include "spmm_core.hpp"
@@ -70,54 +72,43 @@ __global__ __launch_bounds__(FFT_MAX_THREADS) void exec_fft_multi_kernel(
   const int c_lo = d->c_lo, c_hi = d->c_hi, m_off = d->m_off;
   const T* __restrict__ x = X + (int64_t)r * N;
   const T* __restrict__ winv = d->winv;
-  // float32: the pass and unpack twiddle tables are copied into LDS after the
-  // points (float64 transforms fill the LDS with their points alone)
-  constexpr bool LTW = sizeof(T) == 4;
-  double2* ltw = reinterpret_cast<double2*>(smem_raw + ((d->fp.P * sizeof(C) + 15) & ~(size_t)15));
-  if (LTW)
-    for (int i = tid; i < d->ntw; i += blockDim.x) {
-      ltw[i] = d->tw[i];
-      ltw[d->ntw + i] = d->tw2[i];
-    }
-  const double2* __restrict__ tw_pass = LTW ? ltw : d->tw;
-  // global loads in two rounds of FFT_EPT / 2 per thread, all issued before
-  // the LDS writes of the round
+  // E1: the thread's points requested together (float32: all at once;
+  // float64: in two rounds, for registers), then written to LDS
+  constexpr int ROUND = sizeof(T) == 4 ? FFT_EPT : FFT_EPT / 2;
 #pragma unroll
-  for (int h = 0; h < FFT_EPT; h += FFT_EPT / 2) {
-    T v0[FFT_EPT / 2], v1[FFT_EPT / 2];
+  for (int h = 0; h < FFT_EPT; h += ROUND) {
+    T v0[ROUND], v1[ROUND];
 #pragma unroll
-    for (int e = 0; e < FFT_EPT / 2; ++e) {
+    for (int e = 0; e < ROUND; ++e) {
       const int j = tid + (h + e) * nt;
       const int c0 = 2 * j, c1 = 2 * j + 1;
-      v0[e] = (active && j < P && c0 >= c_lo && c0 < c_hi) ? x[c0 + m_off] * winv[c0] : T(0);
-      v1[e] = (active && j < P && c1 >= c_lo && c1 < c_hi) ? x[c1 + m_off] * winv[c1] : T(0);
+      const bool in0 = active && j < P && c0 >= c_lo && c0 < c_hi;
+      const bool in1 = active && j < P && c1 >= c_lo && c1 < c_hi;
+      v0[e] = in0 ? gload(x + c0 + m_off) * gload(winv + c0) : T(0);
+      v1[e] = in1 ? gload(x + c1 + m_off) * gload(winv + c1) : T(0);
     }
 #pragma unroll
-    for (int e = 0; e < FFT_EPT / 2; ++e) {
+    for (int e = 0; e < ROUND; ++e) {
       const int j = tid + (h + e) * nt;
       if (active && j < P) lds[j] = C{v0[e], v1[e]};
     }
   }
   __syncthreads();
-  run_fft<+1, false>(lds, P, 0, d->fp.npass, d->fp.radix, tw_pass, 1, tid, nt, active);
+  // E2: F*; float32 reads its pass twiddles from the block's table, float64
+  // forms them from the two-level table (its registers hold no prefetch)
+  if constexpr (sizeof(T) == 4)
+    run_fft_tab<+1>(lds, P, d->fp.npass, d->fp.radix, d->ptw, tid, nt, active);
+  else
+    run_fft<+1, false>(lds, P, 0, d->fp.npass, d->fp.radix, d->tw, 1, tid, nt, active);
   if (active) {
     const T scale = d->scale;
     const C* __restrict__ post = d->post;
     if constexpr (!SPLIT) {
-      C tw[FFT_EPT + 1];
-#pragma unroll
-      for (int e = 0; e <= FFT_EPT; ++e) {
-        const int k = tid + e * nt;
-        if (LTW)
-          tw[e] = k <= P ? to_c<C>(twiddle(ltw + d->ntw, k)) : C{T(0), T(0)};
-        else
-          tw[e] = k <= P ? post[k] : C{T(0), T(0)};
-      }
       C* __restrict__ z = Z + (int64_t)R * d->zoff + (int64_t)r * d->ldz;
 #pragma unroll
       for (int e = 0; e <= FFT_EPT; ++e) {
         const int k = tid + e * nt;
-        if (k <= P) z[k] = unpack_with<+1>(lds, P, k, tw[e], scale);
+        if (k <= P) z[k] = unpack_with<+1>(lds, P, k, gload(post + k), scale);
       }
     } else {
       // four consecutive k per thread (ldz4 is a multiple of 4): each plane
@@ -125,15 +116,15 @@ __global__ __launch_bounds__(FFT_MAX_THREADS) void exec_fft_multi_kernel(
       uint32_t* __restrict__ zs = Zs + (int64_t)R * d->zoff4 + (int64_t)r * d->ldz4;
       const int ng = d->ldz4 / 4;
       for (int q = tid; q < ng; q += nt) {
+        C t[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) t[j] = gload(post + min(4 * q + j, P));
         uint32_t pc[4][3];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           const int k = 4 * q + j;
           C z = C{T(0), T(0)};
-          if (k <= P) {
-            const C t = LTW ? to_c<C>(twiddle(ltw + d->ntw, k)) : post[k];
-            z = unpack_with<+1>(lds, P, k, t, scale);
-          }
+          if (k <= P) z = unpack_with<+1>(lds, P, k, t[j], scale);
           spmmcore::split2(spmmcore::f32x2{(float)z.x, (float)z.y}, pc[j]);
         }
 #pragma unroll
@@ -195,9 +186,7 @@ __global__ __launch_bounds__(FFT_MAX_THREADS) void row_fft_kernel(RowFftArgs a, 
 // points, then (float32) the two twiddle tables of 128 + P / 128 + 1 entries
 template <typename T>
 size_t fused_lds_bytes(int max_P) {
-  size_t b = ((size_t)max_P * sizeof(cplx_t<T>) + 15) & ~(size_t)15;
-  if (sizeof(T) == 4) b += 2 * (size_t)(128 + max_P / 128 + 1) * sizeof(double2);
-  return b;
+  return (size_t)max_P * sizeof(cplx_t<T>);
 }
 
 template <typename K>

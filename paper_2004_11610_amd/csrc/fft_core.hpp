@@ -5,11 +5,12 @@
 //
 // Conventions: F of eq. (1) has the kernel exp(-2 pi i jk/L)/sqrt(L) (SIGN -1,
 // used by the precomputation A_e W F); the computation stage applies F*
-// (SIGN +1).  The pass twiddles exp(+2 pi i q/Pt) come from two float64 tables
-// of 128 + Pt/128 entries for the block's length Pt (w^q = lo[q % 128]
-// hi[q / 128]); a sub-transform of length P < Pt uses index q * (Pt / P).  A
-// butterfly forms w^jm once and its powers in float64, for every precision.
-// SIGN -1 uses the conjugates.
+// (SIGN +1).  stockham_pass takes its twiddles exp(+2 pi i q/Pt) from two
+// float64 tables of 128 + Pt/128 entries for the block's length Pt (w^q =
+// lo[q % 128] hi[q / 128]; a sub-transform of length P < Pt uses index
+// q * (Pt / P)); a butterfly forms w^jm once and its powers in float64, for
+// every precision.  stockham_pass_tab reads every w^(jm r) from a per-pass
+// table in the working precision instead.  SIGN -1 uses the conjugates.
 #pragma once
 
 #include "common.hpp"
@@ -204,6 +205,74 @@ __device__ __forceinline__ void run_fft(C* lds, int P, int lb, int npass, const 
       case 5: stockham_pass<SIGN, 5, BATCH, EPT>(lds, P, lb, Ns, tw, tmul, tid, nt, active); break;
       default: stockham_pass<SIGN, 3, BATCH, EPT>(lds, P, lb, Ns, tw, tmul, tid, nt, active); break;
     }
+    Ns *= R;
+  }
+}
+
+// The same pass over one transform, with its twiddles w^(jm r) (r = 1 .. R-1)
+// read from the pass's table tab[(r-1) Ns + jm] in the working precision.
+// float32: the table loads go out with the LDS reads, before the barrier;
+// float64 would load them after it (registers).
+template <int SIGN, int R, int EPT, typename C>
+__device__ __forceinline__ void stockham_pass_tab(C* lds, int P, int Ns, const C* __restrict__ tab,
+                                                  int tid, int nt, bool active) {
+  constexpr int MAXB = (EPT + R - 1) / R;
+  constexpr bool EARLY = sizeof(C) == 8;
+  const int nb = P / R;
+  C v[MAXB][R];
+  C w[MAXB][R - 1];
+#pragma unroll
+  for (int b = 0; b < MAXB; ++b) {
+    const int j = tid + b * nt;
+    if (active && j < nb) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[b][r] = lds[j + r * nb];
+      if (EARLY && Ns > 1) {
+        const int jm = j % Ns;
+#pragma unroll
+        for (int r = 1; r < R; ++r) w[b][r - 1] = gload(tab + (r - 1) * Ns + jm);
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < MAXB; ++b) {
+    const int j = tid + b * nt;
+    if (active && j < nb) {
+      const int jm = j % Ns;
+      if (Ns > 1) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          C t = EARLY ? w[b][r - 1] : gload(tab + (r - 1) * Ns + jm);
+          if (SIGN < 0) t.y = -t.y;
+          v[b][r] = cmul(v[b][r], t);
+        }
+      }
+      Dft<SIGN, R, C>::run(v[b]);
+      const int base = (j - jm) * R + jm;
+#pragma unroll
+      for (int r = 0; r < R; ++r) lds[base + r * Ns] = v[b][r];
+    }
+  }
+  __syncthreads();
+}
+
+// all passes of one transform with table twiddles (tab: the FftDesc layout)
+template <int SIGN, int EPT = FFT_EPT, typename C>
+__device__ __forceinline__ void run_fft_tab(C* lds, int P, int npass, const int* radix,
+                                            const C* __restrict__ tab, int tid, int nt,
+                                            bool active) {
+  int Ns = 1;
+  for (int p = 0; p < npass; ++p) {
+    const int R = radix[p];
+    switch (R) {
+      case 8: stockham_pass_tab<SIGN, 8, EPT>(lds, P, Ns, tab, tid, nt, active); break;
+      case 4: stockham_pass_tab<SIGN, 4, EPT>(lds, P, Ns, tab, tid, nt, active); break;
+      case 2: stockham_pass_tab<SIGN, 2, EPT>(lds, P, Ns, tab, tid, nt, active); break;
+      case 5: stockham_pass_tab<SIGN, 5, EPT>(lds, P, Ns, tab, tid, nt, active); break;
+      default: stockham_pass_tab<SIGN, 3, EPT>(lds, P, Ns, tab, tid, nt, active); break;
+    }
+    tab += (R - 1) * Ns;
     Ns *= R;
   }
 }

@@ -17,6 +17,7 @@
 // dense 16 x kw complex matrix), run on the matrix cores in all precisions.
 
 #include <type_traits>
+#include <vector>
 
 #include "spmm_core.hpp"
 
@@ -234,6 +235,218 @@ __device__ __forceinline__ void presplit_tile(const SpmmSplitArgs& args, int til
   }
 }
 
+// ---------------------------------------------------------------- windowed pre-split product
+// One workgroup = WIN_TILES consecutive row tiles x 16 RG right-hand sides
+// (RG = 4 or 2); wave w owns row tile w for all of them (RG 16 x 16
+// accumulators).
+// Neighbouring tiles need overlapping columns of each block's half spectra, so
+// the workgroup first copies, for every block, the union of its tiles' boxes
+// (all three pieces, all the workgroup's right-hand sides) into LDS with direct
+// global-to-LDS loads, which hold no registers while in flight; every wave then
+// reads its steps' spectra from LDS and only its matrix pieces from memory.
+// Each spectrum column crosses from L2 once per workgroup, not once per tile
+// and group of 16 right-hand sides.
+constexpr int WIN_SLOTS = 8;  // steps whose matrix pieces are loaded together
+
+// acc[q] += A * B[q] over the six piece products (small ones first), the RG
+// accumulators interleaved
+template <int RG>
+__device__ __forceinline__ void mma6xg(const bf16x8* A, const bf16x8 (*B)[3], f32x4* acc) {
+  constexpr int ia[6] = {2, 1, 0, 1, 0, 0};
+  constexpr int ib[6] = {0, 1, 2, 0, 1, 0};
+#pragma unroll
+  for (int k = 0; k < 6; ++k)
+#pragma unroll
+    for (int q = 0; q < RG; ++q)
+      acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[ia[k]], B[q][ib[k]], acc[q], 0, 0, 0);
+}
+
+// RG: groups of 16 right-hand sides per workgroup (4 or 2); the windows hold
+// 3 * 16 RG rows.
+template <int RG>
+__global__ __launch_bounds__(256) void spmm_window_kernel(SpmmSplitArgs args,
+                                                          const WinMeta* __restrict__ win,
+                                                          int n_groups, int xlds, int tpad) {
+  extern __shared__ __align__(16) uint4 zl[];
+  const int grp = xcd_tile(blockIdx.x, n_groups);
+  constexpr int NR = 16 * RG;  // right-hand sides of the workgroup
+  const int r0 = blockIdx.y * NR;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int m = lane & 15, g = lane >> 4;
+  const int nblk = args.nblk;
+  const int tile = grp * WIN_TILES + wave;
+  const bool has_tile = tile < args.n_tiles;  // wave-uniform
+  const bf16x8 zero8 = bf16x8{};
+
+  // lane b < nblk: the window of block b, its descriptor and the box of (tile, b)
+  int wk0_l = 0, ww4_l = 0, wpitch_l = 3, wlds_l = 0, wunits_l = 0, wmagic_l = 0;
+  int k0_l = 0, kw_l = 0, ldz_l = 0;
+  int64_t off_l = 0, val_l = 0, zoff_l = 0;
+  if (lane < nblk) {
+    const WinMeta wm = win[(int64_t)grp * nblk + lane];
+    wk0_l = wm.k0;
+    ww4_l = wm.w4;
+    wpitch_l = wm.pitch;
+    wlds_l = wm.lds;
+    wunits_l = wm.units;
+    wmagic_l = (int)wm.magic;
+    const SpmmSplitBlock bd = args.blocks[lane];
+    val_l = (int64_t)(uintptr_t)bd.val;
+    zoff_l = bd.zoff;
+    ldz_l = bd.ldz;
+    if (has_tile) {
+      const TileMeta tm = args.meta[(int64_t)tile * nblk + lane];
+      k0_l = tm.k0;
+      kw_l = tm.kw;
+      off_l = tm.off;
+    }
+  }
+  // every address below derives from these: waiting here, on every path, keeps
+  // the loads issued below free of waits for one another
+  __builtin_amdgcn_s_waitcnt(0);
+  // steps of the tile are numbered through the blocks in order; lane b holds
+  // the number of the first step of block b
+  int start_l = 0, total = 0;
+  for (int bb = 0; bb < nblk; ++bb) {
+    if (lane == bb) start_l = total;
+    total += (lane_i32(kw_l, bb) + 15) >> 4;
+  }
+  const int end_l = start_l + (lane < nblk ? (kw_l + 15) >> 4 : 0);
+
+  // 1. windows -> LDS: unit u of a window is row u / pitch, column group
+  // u % pitch; units past the window's width or rows (padding) and right-hand
+  // sides past R load a valid neighbour and are never read
+  for (int bw = 0; bw < nblk; ++bw) {
+    const int units = lane_i32(wunits_l, bw);
+    if (units == 0) continue;
+    const int w4 = lane_i32(ww4_l, bw), pitch = lane_i32(wpitch_l, bw);
+    const uint32_t magic = (uint32_t)lane_i32(wmagic_l, bw);
+    const int ldz = lane_i32(ldz_l, bw);
+    uint4* __restrict__ dst = zl + lane_i32(wlds_l, bw);
+    // byte offsets from the window's first column fit 32 bits (checked on the host)
+    const char* __restrict__ zw = reinterpret_cast<const char*>(
+        args.Zs + (int64_t)args.R * lane_i64(zoff_l, bw) + lane_i32(wk0_l, bw));
+    for (int c = wave; c * 64 < units; c += 4) {
+      const uint32_t u = (uint32_t)(c * 64 + lane);
+      const uint32_t q = __umulhi(u, magic);
+      const uint32_t cg = min(u - q * (uint32_t)pitch, (uint32_t)w4 - 1u);
+      const uint32_t p = min(q / NR, 2u);
+      const uint32_t rhs = (uint32_t)min(r0 + (int)(q % NR), args.R - 1);
+      const uint32_t off = (p * (uint32_t)args.zplane + rhs * (uint32_t)ldz + 4u * cg) * 4u;
+      __builtin_amdgcn_global_load_lds(zw + off, dst + c * 64, 16, 0, 0);
+    }
+  }
+  // x of the direct tail -> LDS after the windows: right-hand side r0 + i at
+  // xl + i * tpad (tpad = 32 * tail steps + 4 floats, NR * tpad a multiple of
+  // 64); columns past the tail repeat its last one and are never used
+  float* __restrict__ xl = reinterpret_cast<float*>(zl + xlds);
+  for (int c = wave; c * 64 < NR * tpad; c += 4) {
+    const int u = c * 64 + lane;
+    const int i = u / tpad, mm = u - i * tpad;
+    const float* src = args.X + (int64_t)min(r0 + i, args.R - 1) * args.N + min(mm, args.tail - 1);
+    __builtin_amdgcn_global_load_lds(src, xl + c * 64, 4, 0, 0);
+  }
+
+  // 2. while those are in flight: the matrix pieces of the tile's first
+  // WIN_SLOTS steps and of its first tail step (branch-free: past the last
+  // step the loads repeat it, so that they are all in flight together)
+  bf16x8 A[WIN_SLOTS][3];
+  int sb[WIN_SLOTS], ss[WIN_SLOTS];
+  int next = 0, cnt = 0;
+  auto load_steps = [&]() {
+#pragma unroll
+    for (int i = 0; i < WIN_SLOTS; ++i) {
+      const int j = min(next + i, total - 1);
+      const int bk = (int)__popcll(__ballot(lane < nblk && end_l <= j));
+      const int st = j - lane_i32(start_l, bk);
+      const bf16x8* __restrict__ va =
+          reinterpret_cast<const bf16x8*>((const uint16_t*)(uintptr_t)lane_i64(val_l, bk) +
+                                          lane_i64(off_l, bk)) + lane;
+#pragma unroll
+      for (int p = 0; p < 3; ++p) A[i][p] = gload(va + (3 * st + p) * 64);
+      sb[i] = bk;
+      ss[i] = st;
+    }
+    cnt = min(WIN_SLOTS, total - next);
+    next += WIN_SLOTS;
+  };
+  const int64_t n0 = (int64_t)tile * TILE_ROWS;
+  const int tsteps = has_tile ? (args.tail + 31) / 32 : 0;
+  const bf16x8* __restrict__ ta = reinterpret_cast<const bf16x8*>(args.tailmat);
+  bf16x8 TA[3];
+  auto load_tail = [&](int st) {
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+      TA[p] = gload(ta + (((int64_t)tile * tsteps + st) * 3 + p) * 64 + lane);
+  };
+  if (total > 0) load_steps();
+  if (tsteps > 0) load_tail(0);
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (!has_tile) return;
+
+  // 3. every block's steps: matrix pieces from memory, spectra from LDS
+  f32x4 acc[RG];
+#pragma unroll
+  for (int q = 0; q < RG; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+  while (cnt > 0) {
+#pragma unroll
+    for (int i = 0; i < WIN_SLOTS; ++i) {
+      if (i < cnt) {
+        const int bk = sb[i], st = ss[i];
+        const int pitch = lane_i32(wpitch_l, bk);
+        // columns k0 + 16 st + 4 g .. + 3 of the tile's box, in the window;
+        // groups past the box (whose matrix pieces are zero) read the window's
+        // last group instead, a finite value
+        const int cg = min(((lane_i32(k0_l, bk) - lane_i32(wk0_l, bk)) >> 2) + 4 * st + g,
+                           lane_i32(ww4_l, bk) - 1);
+        const uint4* __restrict__ zr = zl + lane_i32(wlds_l, bk) + cg + m * pitch;
+        bf16x8 Z[RG][3];
+#pragma unroll
+        for (int q = 0; q < RG; ++q)
+#pragma unroll
+          for (int p = 0; p < 3; ++p)
+            Z[q][p] = __builtin_bit_cast(bf16x8, zr[(p * NR + 16 * q) * pitch]);
+        mma6xg<RG>(A[i], Z, acc);
+      }
+    }
+    if (next >= total) break;
+    load_steps();
+  }
+
+  // 4. direct tail: x from LDS, split here
+  for (int st = 0; st < tsteps; ++st) {
+    if (st > 0) load_tail(st);
+    bf16x8 B[RG][3];
+#pragma unroll
+    for (int q = 0; q < RG; ++q) {
+      const float4* xq = reinterpret_cast<const float4*>(xl + (16 * q + m) * tpad + 32 * st + 8 * g);
+      const float4 lo = xq[0], hi = xq[1];
+      const float v[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+      f32x8 xv;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) xv[j] = 32 * st + 8 * g + j < args.tail ? v[j] : 0.f;
+      const Split8 xs(xv);
+#pragma unroll
+      for (int p = 0; p < 3; ++p) B[q][p] = xs.get(p);
+    }
+    mma6xg<RG>(TA, B, acc);
+  }
+
+  // 5. y: lane (m, g) holds rows 4g .. 4g+3 of right-hand side r0 + 16 q + m
+#pragma unroll
+  for (int q = 0; q < RG; ++q) {
+    const int rhs = r0 + 16 * q + m;
+    if (rhs < args.R) {
+      float* __restrict__ y = args.Y + (int64_t)rhs * args.N + n0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (n0 + 4 * g + i < args.N) y[4 * g + i] = acc[q][i];
+    }
+  }
+}
+
 template <typename E>
 __global__ __launch_bounds__(256) void spmm_mfma_kernel(SpmmArgs<typename E::T> args) {
   mfma_tile<E>(args, xcd_tile(blockIdx.x, args.n_tiles), blockIdx.y * 64);
@@ -351,6 +564,31 @@ void launch_spmm_presplit_items(const SpmmSplitBatch& b, int n_items, hipStream_
 void launch_spmm_presplit(const SpmmSplitArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(spmm_presplit_kernel, dim3(a.n_tiles, (a.R + 63) / 64), dim3(256), 0, s, a);
   SPT_HIP(hipGetLastError());
+}
+
+void launch_spmm_window(const SpmmSplitArgs& a, const WinMeta* win, int n_groups, int rg,
+                        int xlds, int tpad, size_t lds_bytes, hipStream_t s) {
+  if (rg == 4)
+    hipLaunchKernelGGL(spmm_window_kernel<4>, dim3(n_groups, (a.R + 63) / 64), dim3(256),
+                       lds_bytes, s, a, win, n_groups, xlds, tpad);
+  else
+    hipLaunchKernelGGL(spmm_window_kernel<2>, dim3(n_groups, (a.R + 31) / 32), dim3(256),
+                       lds_bytes, s, a, win, n_groups, xlds, tpad);
+  SPT_HIP(hipGetLastError());
+}
+
+// Allow the windowed product the whole LDS of a workgroup (once per device).
+void init_spmm_kernels(size_t max_lds) {
+  static std::vector<int> done;
+  int dev = 0;
+  SPT_HIP(hipGetDevice(&dev));
+  for (int d : done)
+    if (d == dev) return;
+  SPT_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(spmm_window_kernel<4>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_lds));
+  SPT_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(spmm_window_kernel<2>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_lds));
+  done.push_back(dev);
 }
 
 void launch_spmm_split_bf16(const SpmmArgs<float>& a, hipStream_t s) {
