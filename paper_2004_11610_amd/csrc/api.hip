@@ -358,6 +358,11 @@ uint32_t magic_of(int d) {
   return (uint32_t)((((uint64_t)1 << 32) + (uint64_t)d - 1) / (uint64_t)d);
 }
 
+int fft_max_lb() {
+  const char* e = std::getenv("SPT_FFT_MAX_LB");
+  return e ? std::max(0, std::min(10, std::atoi(e))) : 2;
+}
+
 // The windowed product (diagnostics: SPT_SPMM_WINDOW=0 keeps the per-tile one).
 bool window_product_enabled() {
   const char* e = std::getenv("SPT_SPMM_WINDOW");
@@ -868,6 +873,11 @@ std::vector<FftDesc<T>> fft_descs(spt_plan_t plan) {
     e.tw2 = B.posttw.as<double2>();
     e.ntw = 128 + B.P / 128 + 1;
     e.ptw = (const C*)(dbl ? B.ptw64.p : B.ptw32.p);
+    // up to 4 right-hand sides per workgroup of a short block: 2^lb transforms
+    // interleaved put 64 / 2^lb consecutive points of a row in a wave's
+    // loads and stores (diagnostics: SPT_FFT_MAX_LB)
+    e.lb = 0;
+    while (e.lb < fft_max_lb() && ((int64_t)B.P << (e.lb + 1)) <= plan->fft_maxP) ++e.lb;
     d.push_back(e);
     zoff += B.P + 1;
     zoff4 += B.ldz4;

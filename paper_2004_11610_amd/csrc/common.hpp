@@ -114,6 +114,9 @@ struct FftDesc {
   // already combined) keeps exp(2 pi i jm r / (Ns R)) at ptw[off_p + (r-1) Ns
   // + jm], r = 1 .. R-1, jm < Ns; off_p = sum of (R-1) Ns over earlier passes
   const cplx_t<T>* ptw;
+  // the fused launch gives each workgroup 2^lb right-hand sides of this block
+  // (2^lb P <= the launch's largest P)
+  int lb;
 };
 
 template <typename T>

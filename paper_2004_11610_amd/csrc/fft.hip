@@ -26,10 +26,10 @@ namespace {
 
 using namespace fftcore;
 
-// Workgroups of the FFT kernels have at most FFT_MAX_THREADS threads (12
-// waves: 3 per SIMD), which leaves each thread up to 170 registers for its
-// butterflies.
-constexpr int FFT_MAX_THREADS = 768;
+// Workgroups of the FFT kernels have at most FFT_MAX_THREADS threads (16
+// waves: 4 per SIMD, which hide each other's LDS and memory waits), which
+// leaves each thread up to 128 registers for its butterflies.
+constexpr int FFT_MAX_THREADS = 1024;
 
 template <typename T>
 __global__ __launch_bounds__(FFT_MAX_THREADS) void exec_fft_kernel(ExecFftArgs<T> a, FftPlan fp) {
@@ -52,88 +52,119 @@ __global__ __launch_bounds__(FFT_MAX_THREADS) void exec_fft_kernel(ExecFftArgs<T
 }
 
 // Every block of a plan and every right-hand side in one grid: workgroup
-// blockIdx = b * R + r (blocks sorted by decreasing length, so the long FFTs
-// start first); a block uses the first fp.threads threads of the workgroup.
+// (x, y) takes block y (blocks sorted by decreasing length) and its
+// right-hand sides r0 = x 2^lb .. r0 + 2^lb - 1 (lb = FftDesc::lb), their
+// transforms interleaved in LDS (point j of transform t at lds[(j << lb) + t])
+// so that a short block fills the workgroup as a long one does; workgroups
+// past a block's right-hand sides return at once.
 
 // SPLIT: the half spectra are written as three bfloat16 planes (the pieces of
 // the split-bf16 product, layout in common.hpp) instead of complex values.
-template <typename T, bool SPLIT>
-__global__ __launch_bounds__(FFT_MAX_THREADS) void exec_fft_multi_kernel(
-    const FftDesc<T>* __restrict__ descs, const T* __restrict__ X, cplx_t<T>* __restrict__ Z,
-    uint32_t* __restrict__ Zs, int64_t zplane, int R, int64_t N) {
+// BATCH == false: one transform (lb == 0), indexed without the interleaving.
+template <typename T, bool SPLIT, bool BATCH>
+__device__ __forceinline__ void fft_multi_body(const FftDesc<T>* __restrict__ d,
+                                               const T* __restrict__ X, cplx_t<T>* __restrict__ Z,
+                                               uint32_t* __restrict__ Zs, int64_t zplane, int R,
+                                               int64_t N, int lb_, int r0) {
   using C = cplx_t<T>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C* lds = reinterpret_cast<C*>(smem_raw);
-  const int b = blockIdx.x / R, r = blockIdx.x % R;
-  const FftDesc<T>* __restrict__ d = descs + b;
-  const int P = d->fp.P, nt = d->fp.threads;
+  const int lb = BATCH ? lb_ : 0;
+  const int cnt = BATCH ? min(1 << lb, R - r0) : 1;  // transforms of the workgroup
+  const int tmask = (1 << lb) - 1;
+  const int P = d->fp.P, nt = blockDim.x;
   const int tid = threadIdx.x;
-  const bool active = tid < nt;
   const int c_lo = d->c_lo, c_hi = d->c_hi, m_off = d->m_off;
-  const T* __restrict__ x = X + (int64_t)r * N;
   const T* __restrict__ winv = d->winv;
   // E1: the thread's points requested together (float32: all at once;
-  // float64: in two rounds, for registers), then written to LDS
+  // float64: in two rounds, for registers), then written to LDS; transforms
+  // past the last right-hand side are zero
   constexpr int ROUND = sizeof(T) == 4 ? FFT_EPT : FFT_EPT / 2;
+  const int pts = P << lb;
 #pragma unroll
   for (int h = 0; h < FFT_EPT; h += ROUND) {
     T v0[ROUND], v1[ROUND];
 #pragma unroll
     for (int e = 0; e < ROUND; ++e) {
-      const int j = tid + (h + e) * nt;
+      const int u = tid + (h + e) * nt;
+      const int j = u >> lb, t = u & tmask;
       const int c0 = 2 * j, c1 = 2 * j + 1;
-      const bool in0 = active && j < P && c0 >= c_lo && c0 < c_hi;
-      const bool in1 = active && j < P && c1 >= c_lo && c1 < c_hi;
-      v0[e] = in0 ? gload(x + c0 + m_off) * gload(winv + c0) : T(0);
-      v1[e] = in1 ? gload(x + c1 + m_off) * gload(winv + c1) : T(0);
+      const bool in = u < pts && t < cnt;
+      const T* __restrict__ x = X + (int64_t)(r0 + (BATCH && in ? t : 0)) * N;
+      v0[e] = in && c0 >= c_lo && c0 < c_hi ? gload(x + c0 + m_off) * gload(winv + c0) : T(0);
+      v1[e] = in && c1 >= c_lo && c1 < c_hi ? gload(x + c1 + m_off) * gload(winv + c1) : T(0);
     }
 #pragma unroll
     for (int e = 0; e < ROUND; ++e) {
-      const int j = tid + (h + e) * nt;
-      if (active && j < P) lds[j] = C{v0[e], v1[e]};
+      const int u = tid + (h + e) * nt;
+      if (u < pts) lds[u] = C{v0[e], v1[e]};
     }
   }
   __syncthreads();
   // E2: F*; float32 reads its pass twiddles from the block's table, float64
   // forms them from the two-level table (its registers hold no prefetch)
   if constexpr (sizeof(T) == 4)
-    run_fft_tab<+1>(lds, P, d->fp.npass, d->fp.radix, d->ptw, tid, nt, active);
+    run_fft_tab<+1, BATCH>(lds, P, lb, d->fp.npass, d->fp.radix, d->ptw, tid, nt, true);
   else
-    run_fft<+1, false>(lds, P, 0, d->fp.npass, d->fp.radix, d->tw, 1, tid, nt, active);
-  if (active) {
-    const T scale = d->scale;
-    const C* __restrict__ post = d->post;
-    if constexpr (!SPLIT) {
-      C* __restrict__ z = Z + (int64_t)R * d->zoff + (int64_t)r * d->ldz;
+    run_fft<+1, BATCH>(lds, P, lb, d->fp.npass, d->fp.radix, d->tw, 1, tid, nt, true);
+  // unpack point k of transform t (see unpack_with)
+  const T scale = d->scale;
+  const C* __restrict__ post = d->post;
+  auto unpack_at = [&](int k, int t, C tw) {
+    C ck = lds[((k == P ? 0 : k) << lb) + t];
+    C cm = lds[((k == 0 ? 0 : P - k) << lb) + t];
+    cm.y = -cm.y;
+    const C e = C{T(0.5) * (ck.x + cm.x), T(0.5) * (ck.y + cm.y)};
+    const C dd = C{T(0.5) * (ck.x - cm.x), T(0.5) * (ck.y - cm.y)};
+    const C o = C{dd.y, -dd.x};  // dd / i
+    const C z = cadd(e, cmul(tw, o));
+    return C{z.x * scale, z.y * scale};
+  };
+  if constexpr (!SPLIT) {
+    const int n = (P + 1) << lb;
+    for (int u = tid; u < n; u += nt) {
+      const int k = u >> lb, t = u & tmask;
+      if (t < cnt)
+        Z[(int64_t)R * d->zoff + (int64_t)(r0 + t) * d->ldz + k] = unpack_at(k, t, gload(post + k));
+    }
+  } else {
+    // four consecutive k per thread (ldz4 is a multiple of 4): each plane gets
+    // one 16-byte store per group; zeros past P
+    const int n = (d->ldz4 / 4) << lb;
+    for (int u = tid; u < n; u += nt) {
+      const int q = u >> lb, t = u & tmask;
+      if (t >= cnt) continue;
+      C tw[4];
 #pragma unroll
-      for (int e = 0; e <= FFT_EPT; ++e) {
-        const int k = tid + e * nt;
-        if (k <= P) z[k] = unpack_with<+1>(lds, P, k, gload(post + k), scale);
+      for (int j = 0; j < 4; ++j) tw[j] = gload(post + min(4 * q + j, P));
+      uint32_t pc[4][3];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int k = 4 * q + j;
+        const C z = k <= P ? unpack_at(k, t, tw[j]) : C{T(0), T(0)};
+        spmmcore::split2(spmmcore::f32x2{(float)z.x, (float)z.y}, pc[j]);
       }
-    } else {
-      // four consecutive k per thread (ldz4 is a multiple of 4): each plane
-      // gets one 16-byte store per group; zeros past P
-      uint32_t* __restrict__ zs = Zs + (int64_t)R * d->zoff4 + (int64_t)r * d->ldz4;
-      const int ng = d->ldz4 / 4;
-      for (int q = tid; q < ng; q += nt) {
-        C t[4];
+      uint32_t* __restrict__ zs = Zs + (int64_t)R * d->zoff4 + (int64_t)(r0 + t) * d->ldz4;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) t[j] = gload(post + min(4 * q + j, P));
-        uint32_t pc[4][3];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int k = 4 * q + j;
-          C z = C{T(0), T(0)};
-          if (k <= P) z = unpack_with<+1>(lds, P, k, t[j], scale);
-          spmmcore::split2(spmmcore::f32x2{(float)z.x, (float)z.y}, pc[j]);
-        }
-#pragma unroll
-        for (int p = 0; p < 3; ++p)
-          *reinterpret_cast<uint4*>(zs + p * zplane + 4 * q) =
-              uint4{pc[0][p], pc[1][p], pc[2][p], pc[3][p]};
-      }
+      for (int p = 0; p < 3; ++p)
+        *reinterpret_cast<uint4*>(zs + p * zplane + 4 * q) =
+            uint4{pc[0][p], pc[1][p], pc[2][p], pc[3][p]};
     }
   }
+}
+
+template <typename T, bool SPLIT>
+__global__ __launch_bounds__(FFT_MAX_THREADS) void exec_fft_multi_kernel(
+    const FftDesc<T>* __restrict__ descs, const T* __restrict__ X, cplx_t<T>* __restrict__ Z,
+    uint32_t* __restrict__ Zs, int64_t zplane, int R, int64_t N) {
+  const FftDesc<T>* __restrict__ d = descs + blockIdx.y;
+  const int lb = d->lb;
+  const int r0 = (int)blockIdx.x << lb;
+  if (r0 >= R) return;
+  if (lb == 0)
+    fft_multi_body<T, SPLIT, false>(d, X, Z, Zs, zplane, R, N, 0, r0);
+  else
+    fft_multi_body<T, SPLIT, true>(d, X, Z, Zs, zplane, R, N, lb, r0);
 }
 
 // ---------------------------------------------------------------- transposed: E4
@@ -266,7 +297,7 @@ template <typename T>
 void launch_exec_fft_multi(const FftDesc<T>* descs, int nblk, int threads, int max_P,
                            const T* X, cplx_t<T>* Z, int R, int64_t N, hipStream_t s) {
   const size_t lds = fused_lds_bytes<T>(max_P);
-  hipLaunchKernelGGL((exec_fft_multi_kernel<T, false>), dim3(nblk * R), dim3(threads), lds, s,
+  hipLaunchKernelGGL((exec_fft_multi_kernel<T, false>), dim3(R, nblk), dim3(threads), lds, s,
                      descs, X, Z, (uint32_t*)nullptr, (int64_t)0, R, N);
   SPT_HIP(hipGetLastError());
 }
@@ -275,7 +306,7 @@ void launch_exec_fft_multi_split(const FftDesc<float>* descs, int nblk, int thre
                                  const float* X, uint32_t* Zs, int64_t zplane, int R, int64_t N,
                                  hipStream_t s) {
   const size_t lds = fused_lds_bytes<float>(max_P);
-  hipLaunchKernelGGL((exec_fft_multi_kernel<float, true>), dim3(nblk * R), dim3(threads), lds, s,
+  hipLaunchKernelGGL((exec_fft_multi_kernel<float, true>), dim3(R, nblk), dim3(threads), lds, s,
                      descs, X, (float2*)nullptr, Zs, zplane, R, N);
   SPT_HIP(hipGetLastError());
 }
