@@ -72,6 +72,11 @@ struct DevBlock {
   BlockGeom g;
   int P = 0;
   FftPlan fft;
+  // the fused computation-stage FFT: its plan (P, or P / 2 when the transform
+  // is split by output parity), the split, and 2^lbw right-hand sides per
+  // workgroup
+  FftPlan fftw;
+  int half = 0, lbw = 0;
   DevBuf winv64, winv32, tw64, post64, post32, posttw;
   DevBuf ptw64, ptw32;  // pass twiddles of the fused FFT (FftDesc::ptw)
   DevBuf k0, kw, off;   // per tile
@@ -149,6 +154,7 @@ struct spt_plan {
   int win_xlds = 0, win_tpad = 0;  // x of the direct tail in LDS (16-byte units), its pitch
   bool win_ok = false;
   int fft_threads = 64, fft_maxP = 1;
+  int fft_wgP = 1;  // most points of one workgroup of the fused FFT
   int64_t serial = 0;  // changes with every precompute (keys of executor contexts)
   std::vector<std::unique_ptr<spt::ExecCtx>> ctx;  // executor contexts of spt_execute
 };
@@ -420,7 +426,11 @@ int64_t build_block(spt_plan_t plan, DevBlock& B, hipStream_t s, size_t lds_max,
   B.P = P;
   // rows whose transform does not fit one workgroup's LDS go by four steps
   const bool big = P > FUSED_MAX_P || (size_t)P * sizeof(double2) > lds_max;
-  if (!big) B.fft = make_fft_plan(P);
+  if (!big) {
+    B.fft = make_fft_plan(P);
+    B.half = P >= FUSED_HALF_MIN_P && P % 2 == 0 ? 1 : 0;
+    B.fftw = B.half ? make_fft_plan(P / 2) : B.fft;
+  }
   exec_geometry(B);
   if (big && !B.four)
     throw Error(SPT_E_UNSUPPORTED, "no four-step split of FFT length " + std::to_string(L));
@@ -448,7 +458,7 @@ int64_t build_block(spt_plan_t plan, DevBlock& B, hipStream_t s, size_t lds_max,
   upload(B.posttw, post_table(P), s);
   if (!big) {
     std::vector<long double> pr, pi_;
-    pass_twiddles(B.fft, pr, pi_);
+    pass_twiddles(B.fftw, pr, pi_);
     pr.push_back(1.0L);  // never empty
     pi_.push_back(0.0L);
     upload(B.ptw64, to_vec2<double2, double>(pr, pi_), s);
@@ -861,7 +871,7 @@ std::vector<FftDesc<T>> fft_descs(spt_plan_t plan) {
     e.tw = B.tw64.as<double2>();
     e.post = (const C*)(dbl ? B.post64.p : B.post32.p);
     e.zoff = zoff;
-    e.fp = B.fft;
+    e.fp = B.fftw;
     e.L = B.g.L;
     e.m_off = B.g.m_off;
     e.c_lo = B.g.c_lo;
@@ -876,8 +886,12 @@ std::vector<FftDesc<T>> fft_descs(spt_plan_t plan) {
     // up to 4 right-hand sides per workgroup of a short block: 2^lb transforms
     // interleaved put 64 / 2^lb consecutive points of a row in a wave's
     // loads and stores (diagnostics: SPT_FFT_MAX_LB)
+    e.half = B.half;
+    e.ntab = B.fftw.P - 1;
     e.lb = 0;
-    while (e.lb < fft_max_lb() && ((int64_t)B.P << (e.lb + 1)) <= plan->fft_maxP) ++e.lb;
+    while (!B.half && e.lb < fft_max_lb() && ((int64_t)B.fftw.P << (e.lb + 1)) <= plan->fft_wgP)
+      ++e.lb;
+    B.lbw = e.lb;
     d.push_back(e);
     zoff += B.P + 1;
     zoff4 += B.ldz4;
@@ -962,9 +976,11 @@ void build_fft_descs(spt_plan_t plan, hipStream_t s) {
   plan->fft_threads = 64;
   plan->fft_maxP = 1;
   for (auto& B : plan->blk) exec_geometry(*B);
+  plan->fft_wgP = 1;
   for (auto& B : plan->blk) {
-    plan->fft_threads = std::max(plan->fft_threads, B->fft.threads);
+    plan->fft_threads = std::max(plan->fft_threads, B->fftw.threads);
     plan->fft_maxP = std::max(plan->fft_maxP, B->P);
+    plan->fft_wgP = std::max(plan->fft_wgP, B->fftw.P);
   }
   upload(plan->fftdesc64, fft_descs<double>(plan), s);
   upload(plan->fftdesc32, fft_descs<float>(plan), s);
@@ -1128,20 +1144,25 @@ void execute_staged_t(spt_plan_t plan, const T* X, T* Y, int64_t R, int prec, hi
                                                        : (const FftDesc<T>*)plan->fftdesc32.p;
   // fused FFT launch of blocks b0 .. b0 + nb - 1 on stream st
   auto fft_fused = [&](int b0, int nb, hipStream_t st) {
-    int threads = 64, maxP = 1;
+    int threads = 64;
+    size_t lds = 16;
+    int64_t gx = 1;
     for (int b = b0; b < b0 + nb; ++b) {
-      threads = std::max(threads, plan->blk[b]->fft.threads);
-      maxP = std::max(maxP, plan->blk[b]->P);
+      const DevBlock& B = *plan->blk[b];
+      threads = std::max(threads, B.fftw.threads);
+      lds = std::max(lds, fused_lds_bytes<T>(B.fftw.P << B.lbw, B.fftw.P - 1, 128 + B.P / 128 + 1));
+      gx = std::max<int64_t>(gx, B.half ? 2 * R : (R + (1 << B.lbw) - 1) >> B.lbw);
     }
     if constexpr (std::is_same<T, float>::value) {
       if (split) {
-        launch_exec_fft_multi_split(d + b0, nb, threads, maxP, X, plan->work->as<uint32_t>(),
-                                    (int64_t)R * plan->zper4, (int)R, plan->N, st);
+        launch_exec_fft_multi_split(d + b0, nb, threads, lds, (int)gx, X,
+                                    plan->work->as<uint32_t>(), (int64_t)R * plan->zper4, (int)R,
+                                    plan->N, st);
         return;
       }
     }
-    launch_exec_fft_multi<T>(d + b0, nb, threads, maxP, X, plan->work->as<C>(), (int)R, plan->N,
-                             st);
+    launch_exec_fft_multi<T>(d + b0, nb, threads, lds, (int)gx, X, plan->work->as<C>(), (int)R,
+                             plan->N, st);
   };
   // banded product of every block and the tail
   auto product = [&](hipStream_t st) {

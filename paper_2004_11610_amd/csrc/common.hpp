@@ -26,6 +26,9 @@ constexpr int MAX_PASSES = 16;
 // longest FFT half-length of the fused one-workgroup-per-transform kernel: a
 // float64 transform of P points fills P * 16 bytes of the 160 KiB LDS
 constexpr int FUSED_MAX_P = 10240;
+// the fused FFT splits transforms of an even number of points, at least
+// this many, into two workgroups (by the parity of the outputs)
+constexpr int FUSED_HALF_MIN_P = 4096;
 // AUTO mode compares built blocks with the dense matrix up to this N, and an
 // estimate from sampled rows above it
 constexpr int64_t AUTO_EXACT_N = 8192;
@@ -115,13 +118,26 @@ struct FftDesc {
   // + jm], r = 1 .. R-1, jm < Ns; off_p = sum of (R-1) Ns over earlier passes
   const cplx_t<T>* ptw;
   // the fused launch gives each workgroup 2^lb right-hand sides of this block
-  // (2^lb P <= the launch's largest P)
+  // (2^lb fp.P <= the launch's largest fp.P)
   int lb;
+  // 1: the transform of P = L/2 points is split by the parity of its outputs
+  // into two halves of fp.P = P/2 points, one workgroup each (fp, ptw: P/2)
+  int half;
+  int ntab;  // entries of ptw
 };
 
+// grid: gx x nblk workgroups of `threads`; lds: bytes of the largest
+// workgroup (fused_lds_bytes)
 template <typename T>
-void launch_exec_fft_multi(const FftDesc<T>* descs, int nblk, int threads, int max_P,
+void launch_exec_fft_multi(const FftDesc<T>* descs, int nblk, int threads, size_t lds, int gx,
                            const T* X, cplx_t<T>* Z, int R, int64_t N, hipStream_t s);
+// LDS of a fused FFT workgroup of pts points whose block has a pass table of
+// ntab entries (float32) or a two-level table of ntw entries (float64)
+template <typename T>
+inline size_t fused_lds_bytes(int pts, int ntab, int ntw) {
+  const size_t data = ((size_t)pts * sizeof(cplx_t<T>) + 15) & ~(size_t)15;
+  return data + (sizeof(T) == 4 ? (size_t)ntab * sizeof(cplx_t<T>) : (size_t)ntw * 16);
+}
 
 template <typename T>
 struct InvFftArgs {      // transposed execute: half spectrum -> real, /w, keep retained
@@ -261,9 +277,9 @@ void launch_spmm_items(const SpmmBatch<T>& b, int n_items, hipStream_t s);
 void launch_spmm_presplit_items(const SpmmSplitBatch& b, int n_items, hipStream_t s);
 
 // split-bf16 staged FFT: the half spectra go out as the three planes above
-void launch_exec_fft_multi_split(const FftDesc<float>* descs, int nblk, int threads, int max_P,
-                                 const float* X, uint32_t* Zs, int64_t zplane, int R, int64_t N,
-                                 hipStream_t s);
+void launch_exec_fft_multi_split(const FftDesc<float>* descs, int nblk, int threads, size_t lds,
+                                 int gx, const float* X, uint32_t* Zs, int64_t zplane, int R,
+                                 int64_t N, hipStream_t s);
 
 // transposed banded product: u_i = A_i^T f (half spectrum), per block
 template <typename T>

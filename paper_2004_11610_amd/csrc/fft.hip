@@ -18,6 +18,8 @@
 // unpack twiddles exp(+i pi k/P) (k <= P) are a table in the working
 // precision.  SIGN -1 uses the conjugates.
 
+#include <type_traits>
+
 #include "fft_core.hpp"
 #include "spmm_core.hpp"
 
@@ -51,9 +53,71 @@ __global__ __launch_bounds__(FFT_MAX_THREADS) void exec_fft_kernel(ExecFftArgs<T
   for (int k = tid; k <= a.P; k += nt) z[k] = unpack<+1>(lds, a.P, k, a.post, a.scale);
 }
 
+// The pass twiddles of a block staged into LDS after its points (so that the
+// passes wait for no global memory): float32 the per-pass table (ntab = fp.P -
+// 1 entries), float64 the two-level table (ntw entries).  load() requests
+// them; store() writes them once they arrive, after the caller has requested
+// its points, so both share one wait.
+template <typename T>
+struct TabStage {
+  using C = cplx_t<T>;
+  using V = typename std::conditional<sizeof(T) == 4, C, double2>::type;
+  static constexpr int SLOTS = sizeof(T) == 4 ? FFT_EPT : 2;
+  V v[SLOTS];
+  const V* src;
+  int n;
+  __device__ __forceinline__ void load(const FftDesc<T>* d, int tid, int nt) {
+    if constexpr (sizeof(T) == 4) {
+      src = d->ptw;
+      n = d->ntab;
+    } else {
+      src = d->tw;
+      n = d->ntw;
+    }
+#pragma unroll
+    for (int e = 0; e < SLOTS; ++e) v[e] = gload(src + min(tid + e * nt, n - 1));
+  }
+  __device__ __forceinline__ void store(V* dst, int tid, int nt) const {
+#pragma unroll
+    for (int e = 0; e < SLOTS; ++e)
+      if (tid + e * nt < n) dst[tid + e * nt] = v[e];
+    for (int i = tid + SLOTS * nt; i < n; i += nt) dst[i] = gload(src + i);
+  }
+};
+
+// LDS byte offset of the staged twiddles behind pts points
+template <typename T>
+__host__ __device__ inline size_t tab_offset(int pts) {
+  return ((size_t)pts * sizeof(cplx_t<T>) + 15) & ~(size_t)15;
+}
+
+// (v_c, v_(c+1)) = x_(c + m_off) / w_c on the retained columns [c_lo, c_hi),
+// 0 elsewhere, for an even c.  VEC (m_off, N, c_lo and c_hi even, so that a
+// pair lies wholly inside or outside the retained columns): x and 1/w are read
+// as aligned pairs, from column c_lo when the pair is outside (a valid
+// address; the value is discarded).
+template <bool VEC, typename T>
+__device__ __forceinline__ cplx_t<T> point_pair(const T* __restrict__ x, const T* __restrict__ winv,
+                                                int c, int c_lo, int c_hi, int m_off) {
+  using C = cplx_t<T>;
+  if constexpr (VEC) {
+    const bool in = c >= c_lo && c < c_hi;
+    const int cc = in ? c : c_lo;
+    const C xv = gload(reinterpret_cast<const C*>(x + m_off + cc));
+    const C wv = gload(reinterpret_cast<const C*>(winv + cc));
+    return in ? C{xv.x * wv.x, xv.y * wv.y} : C{T(0), T(0)};
+  } else {
+    auto val = [&](int cv) {
+      return cv >= c_lo && cv < c_hi ? gload(x + cv + m_off) * gload(winv + cv) : T(0);
+    };
+    return C{val(c), val(c + 1)};
+  }
+}
+
 // Every block of a plan and every right-hand side in one grid: workgroup
-// (x, y) takes block y (blocks sorted by decreasing length) and its
-// right-hand sides r0 = x 2^lb .. r0 + 2^lb - 1 (lb = FftDesc::lb), their
+// (x, y) takes block y (blocks sorted by decreasing length) and either one
+// parity half of right-hand side x / 2 (FftDesc::half), or the right-hand
+// sides r0 = x 2^lb .. r0 + 2^lb - 1 (lb = FftDesc::lb), their
 // transforms interleaved in LDS (point j of transform t at lds[(j << lb) + t])
 // so that a short block fills the workgroup as a long one does; workgroups
 // past a block's right-hand sides return at once.
@@ -61,7 +125,8 @@ __global__ __launch_bounds__(FFT_MAX_THREADS) void exec_fft_kernel(ExecFftArgs<T
 // SPLIT: the half spectra are written as three bfloat16 planes (the pieces of
 // the split-bf16 product, layout in common.hpp) instead of complex values.
 // BATCH == false: one transform (lb == 0), indexed without the interleaving.
-template <typename T, bool SPLIT, bool BATCH>
+// EARLY: the unpack twiddles are requested with the points (registers permitting)
+template <typename T, bool SPLIT, bool BATCH, bool EARLY>
 __device__ __forceinline__ void fft_multi_body(const FftDesc<T>* __restrict__ d,
                                                const T* __restrict__ X, cplx_t<T>* __restrict__ Z,
                                                uint32_t* __restrict__ Zs, int64_t zplane, int R,
@@ -76,40 +141,67 @@ __device__ __forceinline__ void fft_multi_body(const FftDesc<T>* __restrict__ d,
   const int tid = threadIdx.x;
   const int c_lo = d->c_lo, c_hi = d->c_hi, m_off = d->m_off;
   const T* __restrict__ winv = d->winv;
-  // E1: the thread's points requested together (float32: all at once;
-  // float64: in two rounds, for registers), then written to LDS; transforms
-  // past the last right-hand side are zero
-  constexpr int ROUND = sizeof(T) == 4 ? FFT_EPT : FFT_EPT / 2;
-  const int pts = P << lb;
-#pragma unroll
-  for (int h = 0; h < FFT_EPT; h += ROUND) {
-    T v0[ROUND], v1[ROUND];
-#pragma unroll
-    for (int e = 0; e < ROUND; ++e) {
-      const int u = tid + (h + e) * nt;
-      const int j = u >> lb, t = u & tmask;
-      const int c0 = 2 * j, c1 = 2 * j + 1;
-      const bool in = u < pts && t < cnt;
-      const T* __restrict__ x = X + (int64_t)(r0 + (BATCH && in ? t : 0)) * N;
-      v0[e] = in && c0 >= c_lo && c0 < c_hi ? gload(x + c0 + m_off) * gload(winv + c0) : T(0);
-      v1[e] = in && c1 >= c_lo && c1 < c_hi ? gload(x + c1 + m_off) * gload(winv + c1) : T(0);
-    }
-#pragma unroll
-    for (int e = 0; e < ROUND; ++e) {
-      const int u = tid + (h + e) * nt;
-      if (u < pts) lds[u] = C{v0[e], v1[e]};
-    }
-  }
-  __syncthreads();
-  // E2: F*; float32 reads its pass twiddles from the block's table, float64
-  // forms them from the two-level table (its registers hold no prefetch)
-  if constexpr (sizeof(T) == 4)
-    run_fft_tab<+1, BATCH>(lds, P, lb, d->fp.npass, d->fp.radix, d->ptw, tid, nt, true);
-  else
-    run_fft<+1, BATCH>(lds, P, lb, d->fp.npass, d->fp.radix, d->tw, 1, tid, nt, true);
-  // unpack point k of transform t (see unpack_with)
   const T scale = d->scale;
   const C* __restrict__ post = d->post;
+  // The unpack twiddles of the thread's outputs (see below) and the pass
+  // twiddles are requested first, then the points, so that all of them arrive
+  // within one wait.
+  constexpr int GS = FFT_EPT / 4 + 2;  // output groups per thread (SPLIT)
+  constexpr int NTW = SPLIT ? 4 * GS : FFT_EPT + 1;
+  C tw[NTW];
+  auto load_tw = [&]() {
+#pragma unroll
+    for (int e = 0; e < NTW; ++e) {
+      if constexpr (SPLIT)
+        tw[e] = gload(post + min(4 * ((tid + (e / 4) * nt) >> lb) + (e % 4), P));
+      else
+        tw[e] = gload(post + min((tid + e * nt) >> lb, P));
+    }
+  };
+  if constexpr (EARLY) load_tw();
+  TabStage<T> ts;
+  ts.load(d, tid, nt);
+  // E1: the thread's points (float32: all at once; float64: in two rounds, for
+  // registers), written to LDS; transforms past the last right-hand side are
+  // zero.  Loads are branch-free: indexes past the end are clamped.
+  constexpr int ROUND = sizeof(T) == 4 ? FFT_EPT : FFT_EPT / 2;
+  const int pts = P << lb;
+  auto* ltab = reinterpret_cast<typename TabStage<T>::V*>(smem_raw + tab_offset<T>(pts));
+  auto input = [&](auto vtag) {
+    constexpr bool VEC = decltype(vtag)::value;
+#pragma unroll
+    for (int h = 0; h < FFT_EPT; h += ROUND) {
+      C v[ROUND];
+#pragma unroll
+      for (int e = 0; e < ROUND; ++e) {
+        const int u = tid + (h + e) * nt;
+        const int uu = min(u, pts - 1);
+        const int j = uu >> lb, t = uu & tmask;
+        const T* __restrict__ x = X + (int64_t)(r0 + (BATCH ? min(t, cnt - 1) : 0)) * N;
+        const C pr = point_pair<VEC>(x, winv, 2 * j, c_lo, c_hi, m_off);
+        v[e] = u < pts && t < cnt ? pr : C{T(0), T(0)};
+      }
+      if (h == 0) ts.store(ltab, tid, nt);
+#pragma unroll
+      for (int e = 0; e < ROUND; ++e) {
+        const int u = tid + (h + e) * nt;
+        if (u < pts) lds[u] = v[e];
+      }
+    }
+  };
+  if (((m_off | (int)N | c_lo | c_hi) & 1) == 0)
+    input(std::true_type{});
+  else
+    input(std::false_type{});
+  __syncthreads();
+  // E2: F*; float32 reads its pass twiddles from the block's table, float64
+  // forms them from the two-level table
+  if constexpr (sizeof(T) == 4)
+    run_fft_tab<+1, BATCH>(lds, P, lb, d->fp.npass, d->fp.radix, ltab, tid, nt, true);
+  else
+    run_fft<+1, BATCH>(lds, P, lb, d->fp.npass, d->fp.radix, ltab, 1, tid, nt, true);
+  if constexpr (!EARLY) load_tw();
+  // unpack point k of transform t (see unpack_with)
   auto unpack_at = [&](int k, int t, C tw) {
     C ck = lds[((k == P ? 0 : k) << lb) + t];
     C cm = lds[((k == 0 ? 0 : P - k) << lb) + t];
@@ -120,28 +212,33 @@ __device__ __forceinline__ void fft_multi_body(const FftDesc<T>* __restrict__ d,
     const C z = cadd(e, cmul(tw, o));
     return C{z.x * scale, z.y * scale};
   };
+  // the thread's outputs u = tid + e nt (u < (P + 1) << lb <= FFT_EPT nt +
+  // 2^lb)
   if constexpr (!SPLIT) {
     const int n = (P + 1) << lb;
-    for (int u = tid; u < n; u += nt) {
+#pragma unroll
+    for (int e = 0; e <= FFT_EPT; ++e) {
+      const int u = tid + e * nt;
       const int k = u >> lb, t = u & tmask;
-      if (t < cnt)
-        Z[(int64_t)R * d->zoff + (int64_t)(r0 + t) * d->ldz + k] = unpack_at(k, t, gload(post + k));
+      if (u < n && t < cnt)
+        Z[(int64_t)R * d->zoff + (int64_t)(r0 + t) * d->ldz + k] = unpack_at(k, t, tw[e]);
     }
   } else {
     // four consecutive k per thread (ldz4 is a multiple of 4): each plane gets
-    // one 16-byte store per group; zeros past P
+    // one 16-byte store per group; zeros past P.  Groups u = tid + e nt, e <
+    // GS (n <= FFT_EPT nt / 4 + 2^lb + 1 <= GS nt)
     const int n = (d->ldz4 / 4) << lb;
-    for (int u = tid; u < n; u += nt) {
+#pragma unroll
+    for (int e = 0; e < GS; ++e) {
+      const int u = tid + e * nt;
+      if (u >= n) break;
       const int q = u >> lb, t = u & tmask;
       if (t >= cnt) continue;
-      C tw[4];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) tw[j] = gload(post + min(4 * q + j, P));
       uint32_t pc[4][3];
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int k = 4 * q + j;
-        const C z = k <= P ? unpack_at(k, t, tw[j]) : C{T(0), T(0)};
+        const C z = k <= P ? unpack_at(k, t, tw[4 * e + j]) : C{T(0), T(0)};
         spmmcore::split2(spmmcore::f32x2{(float)z.x, (float)z.y}, pc[j]);
       }
       uint32_t* __restrict__ zs = Zs + (int64_t)R * d->zoff4 + (int64_t)(r0 + t) * d->ldz4;
@@ -153,18 +250,124 @@ __device__ __forceinline__ void fft_multi_body(const FftDesc<T>* __restrict__ d,
   }
 }
 
-template <typename T, bool SPLIT>
-__global__ __launch_bounds__(FFT_MAX_THREADS) void exec_fft_multi_kernel(
+// One half of a transform split by output parity (FftDesc::half): with
+// w = exp(2 pi i / P) and H = P / 2, the outputs of parity p are
+//   C[2m + p] = sum_n w^(2nm) y_n,  y_n = w^(np) (c_n + (-1)^p c_(n+H)),
+// a transform of H points (one decimation-in-frequency step).  The unpack
+// pairs C_k with C_(P-k), of the same parity, so the half is complete: it
+// writes the half spectrum at every k of parity p (zeros past P).
+template <typename T, bool SPLIT, bool EARLY>
+__device__ __forceinline__ void fft_half_body(const FftDesc<T>* __restrict__ d,
+                                              const T* __restrict__ X, cplx_t<T>* __restrict__ Z,
+                                              uint32_t* __restrict__ Zs, int64_t zplane, int R,
+                                              int64_t N, int r, int par) {
+  using C = cplx_t<T>;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C* lds = reinterpret_cast<C*>(smem_raw);
+  const int H = d->fp.P, P = 2 * H, nt = blockDim.x;
+  const int tid = threadIdx.x;
+  const int c_lo = d->c_lo, c_hi = d->c_hi, m_off = d->m_off;
+  const T* __restrict__ winv = d->winv;
+  const T* __restrict__ x = X + (int64_t)r * N;
+  const C* __restrict__ post = d->post;  // post[2n] = w^n
+  // the unpack twiddles of the thread's outputs k = 2 (tid + e nt) + par and
+  // the pass twiddles first, then the points: one wait for all of them
+  C tw[FFT_EPT + 1];
+  auto load_tw = [&]() {
+#pragma unroll
+    for (int e = 0; e <= FFT_EPT; ++e) tw[e] = gload(post + min(2 * (tid + e * nt) + par, P));
+  };
+  if constexpr (EARLY) load_tw();
+  TabStage<T> ts;
+  ts.load(d, tid, nt);
+  auto* ltab = reinterpret_cast<typename TabStage<T>::V*>(smem_raw + tab_offset<T>(H));
+  constexpr int ROUND = sizeof(T) == 4 ? FFT_EPT : FFT_EPT / 2;
+  auto input = [&](auto vtag) {
+    constexpr bool VEC = decltype(vtag)::value;
+#pragma unroll
+    for (int h = 0; h < FFT_EPT; h += ROUND) {
+      C y[ROUND];
+#pragma unroll
+      for (int e = 0; e < ROUND; ++e) {
+        const int n = min(tid + (h + e) * nt, H - 1);
+        const C a = point_pair<VEC>(x, winv, 2 * n, c_lo, c_hi, m_off);
+        const C b = point_pair<VEC>(x, winv, 2 * n + P, c_lo, c_hi, m_off);
+        y[e] = par ? cmul(csub(a, b), gload(post + 2 * n)) : cadd(a, b);
+      }
+      if (h == 0) ts.store(ltab, tid, nt);
+#pragma unroll
+      for (int e = 0; e < ROUND; ++e) {
+        const int n = tid + (h + e) * nt;
+        if (n < H) lds[n] = y[e];
+      }
+    }
+  };
+  if (((m_off | (int)N | c_lo | c_hi) & 1) == 0)
+    input(std::true_type{});
+  else
+    input(std::false_type{});
+  __syncthreads();
+  if constexpr (sizeof(T) == 4)
+    run_fft_tab<+1, false>(lds, H, 0, d->fp.npass, d->fp.radix, ltab, tid, nt, true);
+  else  // the two-level table is of length P = 2H: index scale 2
+    run_fft<+1, false>(lds, H, 0, d->fp.npass, d->fp.radix, ltab, 2, tid, nt, true);
+  if constexpr (!EARLY) load_tw();
+  // k = 2m + par: C_k at lds[m mod H], C_(P-k) at lds[(H - m) mod H] (par 0)
+  // or lds[H - 1 - m] (par 1)
+  const T scale = d->scale;
+  auto zval = [&](int m, C tw) {
+    const int k = 2 * m + par;
+    if (k > P) return C{T(0), T(0)};
+    C ck = lds[m == H ? 0 : m];
+    C cm = lds[par ? H - 1 - m : (m == 0 || m == H ? 0 : H - m)];
+    cm.y = -cm.y;
+    const C e = C{T(0.5) * (ck.x + cm.x), T(0.5) * (ck.y + cm.y)};
+    const C dd = C{T(0.5) * (ck.x - cm.x), T(0.5) * (ck.y - cm.y)};
+    const C o = C{dd.y, -dd.x};  // dd / i
+    const C z = cadd(e, cmul(tw, o));
+    return C{z.x * scale, z.y * scale};
+  };
+  // outputs k = 2m + par < kend; the thread's m are tid + e nt, e <= FFT_EPT
+  // (H <= FFT_EPT nt)
+  const int kend = SPLIT ? d->ldz4 : P + 1;
+#pragma unroll
+  for (int e = 0; e <= FFT_EPT; ++e) {
+    const int m = tid + e * nt, k = 2 * m + par;
+    if (k >= kend) break;
+    const C z = zval(m, tw[e]);
+    if constexpr (!SPLIT) {
+      Z[(int64_t)R * d->zoff + (int64_t)r * d->ldz + k] = z;
+    } else {
+      uint32_t pc[3];
+      spmmcore::split2(spmmcore::f32x2{(float)z.x, (float)z.y}, pc);
+      uint32_t* __restrict__ zs = Zs + (int64_t)R * d->zoff4 + (int64_t)r * d->ldz4 + k;
+#pragma unroll
+      for (int p = 0; p < 3; ++p) zs[p * zplane] = pc[p];
+    }
+  }
+}
+
+// MAXT: the launch's threads are at most MAXT (512 leaves each thread 256
+// registers, 1024 leaves 128)
+template <typename T, bool SPLIT, int MAXT>
+__global__ __launch_bounds__(MAXT) void exec_fft_multi_kernel(
     const FftDesc<T>* __restrict__ descs, const T* __restrict__ X, cplx_t<T>* __restrict__ Z,
     uint32_t* __restrict__ Zs, int64_t zplane, int R, int64_t N) {
   const FftDesc<T>* __restrict__ d = descs + blockIdx.y;
+  if (d->half) {
+    // workgroup x = 2 r + parity
+    const int r = (int)blockIdx.x >> 1;
+    if (r < R)
+      fft_half_body<T, SPLIT, (MAXT <= 512)>(d, X, Z, Zs, zplane, R, N, r, (int)blockIdx.x & 1);
+    return;
+  }
   const int lb = d->lb;
   const int r0 = (int)blockIdx.x << lb;
   if (r0 >= R) return;
   if (lb == 0)
-    fft_multi_body<T, SPLIT, false>(d, X, Z, Zs, zplane, R, N, 0, r0);
+    fft_multi_body<T, SPLIT, false, (MAXT <= 512)>(d, X, Z, Zs, zplane, R, N, 0, r0);
   else
-    fft_multi_body<T, SPLIT, true>(d, X, Z, Zs, zplane, R, N, lb, r0);
+    fft_multi_body<T, SPLIT, true, (MAXT <= 512)>(d, X, Z, Zs, zplane, R, N, lb, r0);
 }
 
 // ---------------------------------------------------------------- transposed: E4
@@ -215,10 +418,7 @@ __global__ __launch_bounds__(FFT_MAX_THREADS) void row_fft_kernel(RowFftArgs a, 
 }
 
 // points, then (float32) the two twiddle tables of 128 + P / 128 + 1 entries
-template <typename T>
-size_t fused_lds_bytes(int max_P) {
-  return (size_t)max_P * sizeof(cplx_t<T>);
-}
+
 
 template <typename K>
 void set_lds(K kernel, size_t bytes) {
@@ -241,9 +441,12 @@ void init_fft_kernels(size_t max_lds) {
   set_lds(inv_fft_kernel<double>, max_lds);
   set_lds(inv_fft_kernel<float>, max_lds);
   set_lds(row_fft_kernel, max_lds);
-  set_lds(exec_fft_multi_kernel<double, false>, max_lds);
-  set_lds(exec_fft_multi_kernel<float, false>, max_lds);
-  set_lds(exec_fft_multi_kernel<float, true>, max_lds);
+  set_lds(exec_fft_multi_kernel<double, false, 512>, max_lds);
+  set_lds(exec_fft_multi_kernel<float, false, 512>, max_lds);
+  set_lds(exec_fft_multi_kernel<float, true, 512>, max_lds);
+  set_lds(exec_fft_multi_kernel<double, false, 1024>, max_lds);
+  set_lds(exec_fft_multi_kernel<float, false, 1024>, max_lds);
+  set_lds(exec_fft_multi_kernel<float, true, 1024>, max_lds);
   done.push_back(dev);
 }
 
@@ -294,27 +497,33 @@ void launch_row_fft(const RowFftArgs& a, const FftPlan& fp, hipStream_t s) {
 }
 
 template <typename T>
-void launch_exec_fft_multi(const FftDesc<T>* descs, int nblk, int threads, int max_P,
+void launch_exec_fft_multi(const FftDesc<T>* descs, int nblk, int threads, size_t lds, int gx,
                            const T* X, cplx_t<T>* Z, int R, int64_t N, hipStream_t s) {
-  const size_t lds = fused_lds_bytes<T>(max_P);
-  hipLaunchKernelGGL((exec_fft_multi_kernel<T, false>), dim3(R, nblk), dim3(threads), lds, s,
-                     descs, X, Z, (uint32_t*)nullptr, (int64_t)0, R, N);
+  if (threads <= 512)
+    hipLaunchKernelGGL((exec_fft_multi_kernel<T, false, 512>), dim3(gx, nblk), dim3(threads), lds,
+                       s, descs, X, Z, (uint32_t*)nullptr, (int64_t)0, R, N);
+  else
+    hipLaunchKernelGGL((exec_fft_multi_kernel<T, false, 1024>), dim3(gx, nblk), dim3(threads), lds,
+                       s, descs, X, Z, (uint32_t*)nullptr, (int64_t)0, R, N);
   SPT_HIP(hipGetLastError());
 }
 
-void launch_exec_fft_multi_split(const FftDesc<float>* descs, int nblk, int threads, int max_P,
-                                 const float* X, uint32_t* Zs, int64_t zplane, int R, int64_t N,
-                                 hipStream_t s) {
-  const size_t lds = fused_lds_bytes<float>(max_P);
-  hipLaunchKernelGGL((exec_fft_multi_kernel<float, true>), dim3(R, nblk), dim3(threads), lds, s,
-                     descs, X, (float2*)nullptr, Zs, zplane, R, N);
+void launch_exec_fft_multi_split(const FftDesc<float>* descs, int nblk, int threads, size_t lds,
+                                 int gx, const float* X, uint32_t* Zs, int64_t zplane, int R,
+                                 int64_t N, hipStream_t s) {
+  if (threads <= 512)
+    hipLaunchKernelGGL((exec_fft_multi_kernel<float, true, 512>), dim3(gx, nblk), dim3(threads),
+                       lds, s, descs, X, (float2*)nullptr, Zs, zplane, R, N);
+  else
+    hipLaunchKernelGGL((exec_fft_multi_kernel<float, true, 1024>), dim3(gx, nblk), dim3(threads),
+                       lds, s, descs, X, (float2*)nullptr, Zs, zplane, R, N);
   SPT_HIP(hipGetLastError());
 }
 
-template void launch_exec_fft_multi<double>(const FftDesc<double>*, int, int, int, const double*,
-                                            double2*, int, int64_t, hipStream_t);
-template void launch_exec_fft_multi<float>(const FftDesc<float>*, int, int, int, const float*,
-                                           float2*, int, int64_t, hipStream_t);
+template void launch_exec_fft_multi<double>(const FftDesc<double>*, int, int, size_t, int,
+                                            const double*, double2*, int, int64_t, hipStream_t);
+template void launch_exec_fft_multi<float>(const FftDesc<float>*, int, int, size_t, int,
+                                           const float*, float2*, int, int64_t, hipStream_t);
 template void launch_exec_fft<double>(const ExecFftArgs<double>&, const FftPlan&, hipStream_t);
 template void launch_exec_fft<float>(const ExecFftArgs<float>&, const FftPlan&, hipStream_t);
 template void launch_inv_fft<double>(const InvFftArgs<double>&, const FftPlan&, hipStream_t);

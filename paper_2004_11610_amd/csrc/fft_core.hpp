@@ -211,9 +211,9 @@ __device__ __forceinline__ void run_fft(C* lds, int P, int lb, int npass, const 
 
 // The same pass over 2^lb interleaved transforms (point j of transform t at
 // lds[(j << lb) + t]), with the twiddles w^(jm r) (r = 1 .. R-1) read from the
-// pass's table tab[(r-1) Ns + jm] in the working precision.  float32: the
-// table loads go out with the LDS reads, before the barrier; float64 would
-// load them after it (registers).
+// pass's table tab[(r-1) Ns + jm] in the working precision (a copy in LDS).
+// float32: the table reads go out with the point reads, before the barrier;
+// float64 would read them after it (registers).
 template <int SIGN, int R, bool BATCH, int EPT, typename C>
 __device__ __forceinline__ void stockham_pass_tab(C* lds, int P, int lb_, int Ns,
                                                   const C* __restrict__ tab, int tid, int nt,
@@ -236,7 +236,7 @@ __device__ __forceinline__ void stockham_pass_tab(C* lds, int P, int lb_, int Ns
       if (EARLY && Ns > 1) {
         const int jm = j % Ns;
 #pragma unroll
-        for (int r = 1; r < R; ++r) w[b][r - 1] = gload(tab + (r - 1) * Ns + jm);
+        for (int r = 1; r < R; ++r) w[b][r - 1] = tab[(r - 1) * Ns + jm];
       }
     }
   }
@@ -250,7 +250,7 @@ __device__ __forceinline__ void stockham_pass_tab(C* lds, int P, int lb_, int Ns
       if (Ns > 1) {
 #pragma unroll
         for (int r = 1; r < R; ++r) {
-          C tw = EARLY ? w[b][r - 1] : gload(tab + (r - 1) * Ns + jm);
+          C tw = EARLY ? w[b][r - 1] : tab[(r - 1) * Ns + jm];
           if (SIGN < 0) tw.y = -tw.y;
           v[b][r] = cmul(v[b][r], tw);
         }

@@ -314,6 +314,18 @@ def test_four_step_blocks_fp64(spt, fam, N, eps, R, kw):
     assert p.blocks()[0][0] // 2 > 4096
 
 
+@pytest.mark.parametrize("fam,N,R,kw", [
+    ("legendre", 7000, 3, {}), ("jacobi", 9000, 1, dict(alpha=-0.5, beta=-0.5))])
+def test_parity_halves_fp64(spt, fam, N, R, kw):
+    """Blocks with an even P >= 4096 points go through the fused FFT as two
+    workgroups, one per parity of the outputs (Legendre 7000: P = 4374); an
+    odd P stays whole (Jacobi 9000: P = 5625); F64 parity with the oracle."""
+    say("parity halves", fam, N, R, kw)
+    X = workloads.rhs("normal", R, N, 23)
+    p, _ = _check_f64(spt, fam, N, 1e-7, X, executor=spt.EXECUTOR_STAGED, **kw)
+    assert p.blocks()[0][0] // 2 >= 4096
+
+
 @pytest.mark.parametrize("prec", [0, 1, 2], ids=["f64", "f32", "split_bf16"])
 def test_staged_executor_matches_persistent(spt, prec):
     """The two-launch executor and the persistent one compute the same stage
