@@ -290,8 +290,9 @@ def main():
     km = split["kernel_ms"]
     # the two launches of the split-bf16 step: spectra and matrix travel as
     # three bfloat16 pieces (12 bytes per complex value), x and y as float32
-    launches = {"fft": ("exec_fft_multi_kernel<float, split>", fft_bytes(plan, R, 12, 4)),
-                "spmm": ("spmm_presplit_kernel", product_bytes(plan, R, 12, 4))}
+    spmm_kernel = "spmm_window_kernel" if info["window_lds"] > 0 else "spmm_presplit_kernel"
+    launches = {"fft": ("exec_fft_multi_kernel<float, true>", fft_bytes(plan, R, 12, 4)),
+                "spmm": (spmm_kernel, product_bytes(plan, R, 12, 4))}
 
     def roofline(stage):
         name, nbytes = launches[stage]

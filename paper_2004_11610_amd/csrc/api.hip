@@ -952,9 +952,11 @@ void build_windows(spt_plan_t plan, hipStream_t s) {
     if (cols) *cols = c;
     return std::make_pair(most, (size_t)most * 16 + (size_t)tpad * nr * sizeof(float));
   };
-  // 64 right-hand sides per workgroup when their windows fit the LDS, else 32
-  // (diagnostics: SPT_SPMM_WINDOW_RG=4 or 2)
-  int rg = layout(4, nullptr, nullptr).second <= lds_max ? 4 : 2;
+  // 64 right-hand sides per workgroup (more reuse of each matrix piece) when
+  // two such workgroups still fit a CU's LDS, else 32, which leaves room for
+  // the FFTs of other streams beside the product (diagnostics:
+  // SPT_SPMM_WINDOW_RG=4 or 2)
+  int rg = 2 * layout(4, nullptr, nullptr).second <= lds_max ? 4 : 2;
   if (const char* e = std::getenv("SPT_SPMM_WINDOW_RG")) {
     if (e[0] == '4') rg = 4;
     if (e[0] == '2') rg = 2;

@@ -116,7 +116,7 @@ __device__ __forceinline__ cplx_t<T> point_pair(const T* __restrict__ x, const T
 
 // Every block of a plan and every right-hand side in one grid: workgroup
 // (x, y) takes block y (blocks sorted by decreasing length) and either one
-// parity half of right-hand side x / 2 (FftDesc::half), or the right-hand
+// parity half of right-hand side x mod R (FftDesc::half), or the right-hand
 // sides r0 = x 2^lb .. r0 + 2^lb - 1 (lb = FftDesc::lb), their
 // transforms interleaved in LDS (point j of transform t at lds[(j << lb) + t])
 // so that a short block fills the workgroup as a long one does; workgroups
@@ -355,10 +355,12 @@ __global__ __launch_bounds__(MAXT) void exec_fft_multi_kernel(
     uint32_t* __restrict__ Zs, int64_t zplane, int R, int64_t N) {
   const FftDesc<T>* __restrict__ d = descs + blockIdx.y;
   if (d->half) {
-    // workgroup x = 2 r + parity
-    const int r = (int)blockIdx.x >> 1;
-    if (r < R)
-      fft_half_body<T, SPLIT, (MAXT <= 512)>(d, X, Z, Zs, zplane, R, N, r, (int)blockIdx.x & 1);
+    // workgroup x = parity R + r: the two halves of a right-hand side are R
+    // workgroups apart, on the same XCD when R is a multiple of 8, so that
+    // their reads of the row and their interleaved writes meet in one L2
+    const int par = (int)blockIdx.x >= R ? 1 : 0;
+    const int r = (int)blockIdx.x - par * R;
+    fft_half_body<T, SPLIT, (MAXT <= 512)>(d, X, Z, Zs, zplane, R, N, r, par);
     return;
   }
   const int lb = d->lb;
