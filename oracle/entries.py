@@ -4,7 +4,9 @@ Test infrastructure only (see ``oracle/__init__``).
 
 * Chebyshev T_m(x_j) = cos(m theta_j) at Chebyshev-Gauss nodes, eq. (cheb_matrix);
   theta_j = pi (2j+1) / (2N), so m theta_j = pi q / (2N) with the integer
-  q = m (2j+1) mod 4N, which keeps the angle exact for large m.
+  q = m (2j+1) mod 4N, which keeps the angle exact for large m.  The other
+  trigonometric generators, sin(m theta_j) (sec. 2) and cos(m theta_j)^s
+  (eq. cosd2), use the same angle.
 * Orthonormal Jacobi polynomials p_m^{(alpha,beta)} (the matrix of eq. (Jac_matrix)
   normalised as in sec. 5.2): x p_m = a_{m+1} p_{m+1} + b_m p_m + a_m p_{m-1}
   with the textbook coefficients (DLMF 18.9.2, 18.2.11), p_0 = mu0^{-1/2}.
@@ -62,6 +64,21 @@ def chebyshev_t(j, N, m0, m1):
     m = np.arange(m0, m1, dtype=np.int64)
     q = np.mod(np.outer(2 * j + 1, m), 4 * N)
     return np.cos(np.pi * q.astype(np.float64) / (2.0 * N))
+
+
+def sine(j, N, m0, m1):
+    """sin(m theta_j) at the Chebyshev-Gauss angles: the sine generator that
+    Algorithms 1 and 2 compress as they do the cosine one (sec. 2, after
+    Algorithm 2); the same exact angle as chebyshev_t."""
+    j = np.asarray(j, dtype=np.int64)
+    m = np.arange(m0, m1, dtype=np.int64)
+    q = np.mod(np.outer(2 * j + 1, m), 4 * N)
+    return np.sin(np.pi * q.astype(np.float64) / (2.0 * N))
+
+
+def cos_power(j, N, m0, m1, s):
+    """cos(m theta_j)^s, eq. (cosd2) (s = 2, 3, 4, 5), at the Chebyshev-Gauss angles."""
+    return chebyshev_t(j, N, m0, m1) ** int(s)
 
 
 # --------------------------------------------------------------------------- Jacobi

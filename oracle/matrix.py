@@ -4,6 +4,8 @@ Test infrastructure only (see ``oracle/__init__``).
 
 family          A[j, m]                                    nodes x_j
 CHEBYSHEV_T     T_m(x_j) = cos(m theta_j)   eq. (cheb_matrix)   Chebyshev-Gauss, descending
+SINE            sin(m theta_j)              sec. 2            Chebyshev-Gauss angles
+COS_POWER       cos(m theta_j)^s, s=2..5    eq. (cosd2)       Chebyshev-Gauss angles
 LEGENDRE        sqrt(lambda_j) p_m(x_j)     sec. 5.2          Gauss-Legendre, descending
 JACOBI          sqrt(lambda_j) p_m^{(a,b)}(x_j)  sec. 5.2     Gauss-Jacobi, descending
 LAGUERRE_FN     l_m(x_j) = exp(-x_j/2) L_m(x_j)   sec. 4      Gauss-Laguerre, ascending
@@ -13,23 +15,28 @@ p_m is the orthonormal Jacobi polynomial and lambda_j the Christoffel weight, so
 the LEGENDRE/JACOBI matrix is orthogonal (B^{-1} = B^T, sec. 5.2).  With
 ``orthonormal=False`` the sqrt(lambda_j) factor is left out.  Column m may run
 past N-1 (the right extras of a block are the continued recurrence) and, for
-CHEBYSHEV_T only, below 0 (the left extras of Algorithm 1).
+the trigonometric generators only (CHEBYSHEV_T, SINE, COS_POWER), below 0 (the
+left extras of Algorithm 1).
 """
 
 import numpy as np
 
 from . import entries, nodes
 
-CHEBYSHEV_T, LEGENDRE, JACOBI, LAGUERRE_FN, HERMITE_FN = 1, 2, 3, 4, 5
+CHEBYSHEV_T, LEGENDRE, JACOBI, LAGUERRE_FN, HERMITE_FN, SINE, COS_POWER = 1, 2, 3, 4, 5, 6, 7
 FAMILY_NAMES = {CHEBYSHEV_T: "chebyshev_t", LEGENDRE: "legendre", JACOBI: "jacobi",
-                LAGUERRE_FN: "laguerre_fn", HERMITE_FN: "hermite_fn"}
+                LAGUERRE_FN: "laguerre_fn", HERMITE_FN: "hermite_fn", SINE: "sine",
+                COS_POWER: "cos_power"}
+TRIG = (CHEBYSHEV_T, SINE, COS_POWER)
 
 
 class MatrixFamily:
-    def __init__(self, family, N, alpha=0.0, beta=0.0, orthonormal=True):
+    def __init__(self, family, N, alpha=0.0, beta=0.0, orthonormal=True, power=2):
         if family == LEGENDRE:
             alpha, beta = 0.0, 0.0
-        self.family, self.N = family, N
+        if family == COS_POWER and power not in (2, 3, 4, 5):
+            raise ValueError("cos power s must be 2, 3, 4 or 5")
+        self.family, self.N, self.power = family, N, int(power)
         self.alpha, self.beta, self.orthonormal = float(alpha), float(beta), bool(orthonormal)
         self._x = {}
         self._lam = {}
@@ -37,11 +44,11 @@ class MatrixFamily:
     @property
     def two_sided(self):
         """Algorithm 1 (extras on both sides) applies only where m < 0 is defined."""
-        return self.family == CHEBYSHEV_T
+        return self.family in TRIG
 
     def _compute_nodes(self, rows):
         f, N = self.family, self.N
-        if f == CHEBYSHEV_T:
+        if f in TRIG:
             return nodes.chebyshev_gauss(N, rows)
         if f in (LEGENDRE, JACOBI):
             return nodes.gauss_jacobi(N, self.alpha, self.beta, rows)
@@ -79,8 +86,12 @@ class MatrixFamily:
         f = self.family
         if f == CHEBYSHEV_T:
             return entries.chebyshev_t(rows, self.N, m0, m1)
+        if f == SINE:
+            return entries.sine(rows, self.N, m0, m1)
+        if f == COS_POWER:
+            return entries.cos_power(rows, self.N, m0, m1, self.power)
         if m0 < 0:
-            raise ValueError("negative degrees are defined only for CHEBYSHEV_T")
+            raise ValueError("negative degrees are defined only for the trigonometric generators")
         x = self.nodes(rows)
         if f in (LEGENDRE, JACOBI):
             P = entries.jacobi_orthonormal(self.alpha, self.beta, x, m0, m1)

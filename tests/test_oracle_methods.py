@@ -9,7 +9,8 @@ from oracle import compressed, direct, matrix, params, transposed
 
 ALL_FAMS = [(matrix.CHEBYSHEV_T, {}), (matrix.LEGENDRE, {}),
             (matrix.JACOBI, dict(alpha=-0.5, beta=-0.5)), (matrix.JACOBI, dict(alpha=2.0, beta=3.0)),
-            (matrix.LAGUERRE_FN, {}), (matrix.HERMITE_FN, {})]
+            (matrix.LAGUERRE_FN, {}), (matrix.HERMITE_FN, {}), (matrix.SINE, {}),
+            (matrix.COS_POWER, dict(power=2)), (matrix.COS_POWER, dict(power=5))]
 
 
 def rel(a, b):
@@ -25,6 +26,44 @@ def test_chebyshev_direct_is_a_dct(N):
     y = direct.matvec(matrix.MatrixFamily(matrix.CHEBYSHEV_T, N), x[None, :])[0]
     ref = (scipy.fft.dct(x, type=3) + x[0]) / 2.0
     np.testing.assert_allclose(y, ref, atol=1e-12 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("N", [64, 4096])
+def test_sine_direct_is_a_dst(N):
+    # the sine generator (sec. 2): with theta_j = pi(j+1/2)/N, sum_{m<N} x_m sin(m theta_j)
+    # = DST-III(x')_j / 2 for x' = (x_1, ..., x_{N-1}, 0) (SciPy's unnormalised DST-III,
+    # whose last input enters as (-1)^j x'_{N-1} = 0)
+    x = np.random.default_rng(4).standard_normal(N)
+    y = direct.matvec(matrix.MatrixFamily(matrix.SINE, N), x[None, :])[0]
+    xs = np.concatenate([x[1:], [0.0]])
+    ref = scipy.fft.dst(xs, type=3) / 2.0
+    np.testing.assert_allclose(y, ref, atol=1e-12 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("s", [2, 3, 4, 5])
+def test_cos_power_entries_by_power_reduction(s):
+    # eq. (cosd2): cos^s(phi) = 2^(1-s) sum_{k < s/2} C(s,k) cos((s-2k) phi)
+    # (+ 2^(-s) C(s, s/2) for even s), with cos(n m theta_j) = T_{|n m|}(x_j) from
+    # NumPy's Chebyshev series (Clenshaw) at the node x_j = cos(theta_j); negative m too
+    from math import comb
+    N = 40
+    fam = matrix.MatrixFamily(matrix.COS_POWER, N, power=s)
+    rows = np.arange(N)
+    x = np.cos(np.pi * (rows + 0.5) / N)
+    ms = np.arange(-5, 60)
+    ref = np.zeros((N, ms.size))
+    for k in range((s + 1) // 2):
+        for c, m in enumerate(ms):
+            e = np.zeros(abs((s - 2 * k) * m) + 1)
+            e[-1] = 1.0
+            ref[:, c] += 2.0 ** (1 - s) * comb(s, k) * np.polynomial.chebyshev.chebval(x, e)
+    if s % 2 == 0:
+        ref += 2.0 ** (-s) * comb(s, s // 2)
+    np.testing.assert_allclose(fam.block(rows, -5, 60), ref, atol=1e-12)
+    # the family is two-sided (Algorithm 1), like CHEBYSHEV_T
+    assert fam.two_sided and matrix.MatrixFamily(matrix.SINE, N).two_sided
+    with pytest.raises(ValueError):
+        matrix.MatrixFamily(matrix.COS_POWER, N, power=6)
 
 
 @pytest.mark.parametrize("fam_id,kw", ALL_FAMS)
@@ -125,6 +164,25 @@ def test_error_falls_with_eps1_and_scales_with_eps1_over_eps2():
             last = e
             errs[eps1, eps2] = e
             assert 1e-4 * eps1 / eps2 <= e <= 3.0 * eps1 / eps2, (eps1, eps2, e)
+
+
+def test_trig_generators_compress_like_the_cosine():
+    # sec. 2 / eq. (cosd2): Algorithm 1 compresses sin(m theta) and cos^s(m theta)
+    # rows as it does cos(m theta): error of order eps1/eps2, and a sparsity that
+    # grows with the number of tones in the row (sin: one pair +-theta, like cos;
+    # cos^3: +-theta and +-3 theta, two pairs)
+    N, eps1, eps2 = 512, 1e-8, 1e-2
+    X = np.random.default_rng(9).standard_normal((4, N))
+    kept = {}
+    for name, fam in (("cos", matrix.MatrixFamily(matrix.CHEBYSHEV_T, N)),
+                      ("sin", matrix.MatrixFamily(matrix.SINE, N)),
+                      ("cos3", matrix.MatrixFamily(matrix.COS_POWER, N, power=3))):
+        C = compressed.Compressed(compressed.Plan(fam, eps1, eps2))
+        e = rel(C.execute(X), direct.matvec(fam, X))
+        assert 1e-4 * eps1 / eps2 <= e <= 3.0 * eps1 / eps2, (name, e)
+        kept[name] = sum(C.nnz()) / N
+    assert abs(kept["sin"] - kept["cos"]) <= 0.05 * kept["cos"]
+    assert 1.5 * kept["cos"] <= kept["cos3"] <= 2.2 * kept["cos"]
 
 
 def test_kept_pattern_is_hermitian_and_banded():
