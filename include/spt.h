@@ -32,8 +32,15 @@
  *                    ascending (sec. 4).
  *   SPT_HERMITE_FN   A[j,m] = psi_m(x_j), Hermite functions, Gauss-Hermite
  *                    nodes ascending.
- *   All but SPT_CHEBYSHEV_T use the block method (sec. 3): extras on the
- *   right only, recursion on the first s_i columns, the last columns direct.
+ *   SPT_SINE         A[j,m] = sin(m theta_j) at the Chebyshev-Gauss angles: a
+ *                    generator Algorithms 1 and 2 compress as they do the
+ *                    cosine one (sec. 2, after Algorithm 2).
+ *   SPT_COS_POWER    A[j,m] = cos(m theta_j)^s, s = spt_params.power in 2..5
+ *                    (eq. cosd2), at the Chebyshev-Gauss angles.
+ *   The trigonometric generators (SPT_CHEBYSHEV_T, SPT_SINE, SPT_COS_POWER)
+ *   use Algorithm 1, extras on both sides (the generator continues to m < 0);
+ *   the others use the block method (sec. 3): extras on the right only,
+ *   recursion on the first s_i columns, the last columns direct.
  *
  * Conventions for every call:
  *   - Every function returns spt_status: SPT_OK (0) or a negative error code;
@@ -76,7 +83,9 @@ typedef enum {
   SPT_LEGENDRE = 2,
   SPT_JACOBI = 3,
   SPT_LAGUERRE_FN = 4,
-  SPT_HERMITE_FN = 5
+  SPT_HERMITE_FN = 5,
+  SPT_SINE = 6,
+  SPT_COS_POWER = 7
 } spt_family;
 
 /* Arithmetic of the execute path.  The precomputation is always float64. */
@@ -129,7 +138,10 @@ typedef struct {
   int64_t panel_rows;     /* rows per precompute panel; 0 -> automatic            */
   const double* nodes;    /* optional host array of the N nodes, in the family's
                              order (see above); NULL -> computed on the device.
-                             Copied during spt_plan_create.                       */
+                             Copied during spt_plan_create.  The trigonometric
+                             generators take their angles from the node index
+                             and ignore it.                                       */
+  int32_t power;          /* SPT_COS_POWER: s in 2..5 (others ignore it)          */
 } spt_params;
 
 typedef struct spt_plan* spt_plan_t;

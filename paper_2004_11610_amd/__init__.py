@@ -12,12 +12,13 @@ from ctypes import byref, c_double, c_int32, c_int64, c_void_p
 from . import _lib
 from ._lib import SptError  # noqa: F401
 
-CHEBYSHEV_T, LEGENDRE, JACOBI, LAGUERRE_FN, HERMITE_FN = 1, 2, 3, 4, 5
+CHEBYSHEV_T, LEGENDRE, JACOBI, LAGUERRE_FN, HERMITE_FN, SINE, COS_POWER = 1, 2, 3, 4, 5, 6, 7
 F64, F32, SPLIT_BF16 = 0, 1, 2
 MODE_AUTO, MODE_ROW, MODE_DIRECT = 0, 1, 3
 EXECUTOR_AUTO, EXECUTOR_STAGED, EXECUTOR_PERSISTENT = 0, 1, 2
 FAMILIES = {"chebyshev_t": CHEBYSHEV_T, "legendre": LEGENDRE, "jacobi": JACOBI,
-            "laguerre_fn": LAGUERRE_FN, "hermite_fn": HERMITE_FN}
+            "laguerre_fn": LAGUERRE_FN, "hermite_fn": HERMITE_FN, "sine": SINE,
+            "cos_power": COS_POWER}
 PRECISIONS = {"f64": F64, "f32": F32, "split_bf16": SPLIT_BF16}
 
 
@@ -43,7 +44,7 @@ class Plan:
 
     def __init__(self, family, N, eps, alpha=0.0, beta=0.0, eps2=0.0, mode=MODE_AUTO,
                  unweighted=False, precisions=0, min_block=0, exact_fft_len=False,
-                 panel_rows=0, nodes=None, executor=EXECUTOR_AUTO):
+                 panel_rows=0, nodes=None, executor=EXECUTOR_AUTO, power=0):
         self._lib = _lib.load()
         self._h = c_void_p()
         p = _lib.SptParams()
@@ -51,6 +52,7 @@ class Plan:
         p.mode, p.unweighted, p.precisions = int(mode), int(bool(unweighted)), int(precisions)
         p.min_block, p.exact_fft_len, p.panel_rows = int(min_block), int(bool(exact_fft_len)), int(panel_rows)
         p.executor = int(executor)
+        p.power = int(power)
         self._nodes_buf = None
         if nodes is not None:
             self._nodes_buf = (c_double * N)(*[float(v) for v in nodes])

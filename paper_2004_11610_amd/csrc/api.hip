@@ -205,6 +205,7 @@ void family_tables(spt_plan_t plan, int64_t K, hipStream_t s) {
 FamilyArgs family_args(spt_plan_t plan, bool with_scale) {
   FamilyArgs f{};
   f.family = plan->family;
+  f.power = plan->p.power;
   f.N = plan->N;
   f.unweighted = plan->p.unweighted;
   f.x = plan->nodes.as<double>();
@@ -1519,7 +1520,7 @@ spt_status spt_plan_create(spt_plan_t* out, int32_t family, const spt_params* p,
   return guard([&] {
     if (!out) throw Error(SPT_E_INVALID_ARG, "out is NULL");
     *out = nullptr;
-    if (family < SPT_CHEBYSHEV_T || family > SPT_HERMITE_FN)
+    if (family < SPT_CHEBYSHEV_T || family > SPT_COS_POWER)
       throw Error(SPT_E_INVALID_ARG, "unknown family " + std::to_string(family));
     if (N < 2 || N > (int64_t)1 << 24) throw Error(SPT_E_INVALID_ARG, "N out of range");
     spt_params prm{};
@@ -1530,6 +1531,8 @@ spt_status spt_plan_create(spt_plan_t* out, int32_t family, const spt_params* p,
     if (family == SPT_JACOBI && !(prm.alpha > -1.0 && prm.beta > -1.0))
       throw Error(SPT_E_INVALID_ARG, "Jacobi needs alpha, beta > -1");
     if (family == SPT_LEGENDRE) prm.alpha = prm.beta = 0.0;
+    if (family == SPT_COS_POWER && (prm.power < 2 || prm.power > 5))
+      throw Error(SPT_E_INVALID_ARG, "cos power s must be 2, 3, 4 or 5");
     if (prm.mode != SPT_MODE_AUTO && prm.mode != SPT_MODE_ROW && prm.mode != SPT_MODE_DIRECT)
       throw Error(SPT_E_INVALID_ARG, "unknown mode");
     if (prm.precisions & ~7u) throw Error(SPT_E_INVALID_ARG, "unknown precision bits");
@@ -1555,7 +1558,7 @@ spt_status spt_plan_create(spt_plan_t* out, int32_t family, const spt_params* p,
     if (prm.mode == SPT_MODE_DIRECT) {
       plan->geom.clear();
       plan->tail = N;
-    } else if (family == SPT_CHEBYSHEV_T) {
+    } else if (is_trig(family)) {
       partition_two_sided(N, plan->zeta, eps2, round_fft, plan->geom, plan->tail);
     } else {
       partition_one_sided(N, plan->zeta, eps2, min_block, round_fft, plan->geom, plan->tail);

@@ -303,8 +303,15 @@ void launch_tail_transposed(const T* tailmat, int tail, const T* F, T* Y, int R,
                             hipStream_t s);
 
 // ---------------------------------------------------------------- precompute kernels
+// the trigonometric generators: closed-form entries at the Chebyshev-Gauss
+// angles, extras on both sides (Algorithm 1)
+__host__ __device__ inline bool is_trig(int family) {
+  return family == SPT_CHEBYSHEV_T || family == SPT_SINE || family == SPT_COS_POWER;
+}
+
 struct FamilyArgs {
   int family;
+  int power;              // s of SPT_COS_POWER
   int64_t N;
   int unweighted;
   const double* x;        // nodes

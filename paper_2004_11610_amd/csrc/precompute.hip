@@ -28,7 +28,7 @@ __device__ __forceinline__ void exp_neg_scaled(double a, double& mant, int& E) {
 
 // Recurrence state of one row, advanced one degree at a time.
 struct RowRec {
-  int family;
+  int family, power;
   double x, p_prev, p, scale;  // value = p * 2^E * scale
   int E;
   int m;                       // degree of p
@@ -36,6 +36,7 @@ struct RowRec {
 
   __device__ void init(const FamilyArgs& f, int64_t jj) {
     family = f.family;
+    power = f.power;
     j = jj;
     N = f.N;
     x = f.x[jj];
@@ -57,12 +58,21 @@ struct RowRec {
       p = 1.0;
     }
   }
-  // value at degree mm (Chebyshev only: closed form with an exact angle)
-  __device__ double cheb(int64_t mm) const {
+  // value at degree mm of a trigonometric generator: closed form with an exact
+  // angle, m theta_j = pi q / (2N) with q = m (2j+1) mod 4N
+  __device__ double trig(int64_t mm) const {
     const int64_t fourN = 4 * N;
     int64_t q = ((mm % fourN) * ((2 * j + 1) % fourN)) % fourN;
     if (q < 0) q += fourN;
-    return cospi((double)q / (double)(2 * N));
+    const double a = (double)q / (double)(2 * N);
+    if (family == SPT_SINE) return sinpi(a);
+    const double c = cospi(a);
+    if (family == SPT_COS_POWER) {
+      double v = c;
+      for (int i = 1; i < power; ++i) v *= c;
+      return v;
+    }
+    return c;
   }
   __device__ double value() const { return ldexp(p, E) * scale; }
   __device__ void advance(const FamilyArgs& f) {
@@ -201,7 +211,7 @@ __global__ void nodes_kernel(FamilyArgs f, const double* __restrict__ diag,
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t N = f.N;
   if (j >= N) return;
-  if (f.family == SPT_CHEBYSHEV_T) {
+  if (is_trig(f.family)) {  // Chebyshev-Gauss nodes x_j = cos(theta_j)
     x_out[j] = cospi((double)(2 * j + 1) / (double)(2 * N));
     return;
   }
@@ -260,15 +270,15 @@ __global__ __launch_bounds__(64) void rec_rows_kernel(FamilyArgs f, int64_t row0
   const bool active = lr < nrows && j < f.N;
   RowRec rec;
   rec.init(f, active ? j : 0);
-  const bool cheb = f.family == SPT_CHEBYSHEV_T;
-  // one-sided blocks start at degree 0 > m0 never happens; m0 < 0 only for Chebyshev
+  const bool trig = is_trig(f.family);
+  // m0 < 0 only for the trigonometric generators (extras on both sides)
   for (int c0 = 0; c0 < L; c0 += 64) {
     for (int cc = 0; cc < 64; ++cc) {
       const int c = c0 + cc;
       double v = 0.0;
       if (c < L) {
-        if (cheb) {
-          v = rec.cheb((int64_t)m0 + c);
+        if (trig) {
+          v = rec.trig((int64_t)m0 + c);
         } else {
           v = rec.value();
           if (c + 1 < L) rec.advance(f);
@@ -298,8 +308,8 @@ __global__ void rec_tail_kernel(FamilyArgs f, int t, int64_t ldt, double* __rest
   RowRec rec;
   rec.init(f, j);
   for (int m = 0; m < t; ++m) {
-    out[(int64_t)m * ldt + j] = f.family == SPT_CHEBYSHEV_T ? rec.cheb(m) : rec.value();
-    if (f.family != SPT_CHEBYSHEV_T && m + 1 < t) rec.advance(f);
+    out[(int64_t)m * ldt + j] = is_trig(f.family) ? rec.trig(m) : rec.value();
+    if (!is_trig(f.family) && m + 1 < t) rec.advance(f);
   }
 }
 

@@ -10,7 +10,8 @@ from oracle import compressed, direct, matrix
 
 FAM_IDS = {"chebyshev_t": matrix.CHEBYSHEV_T, "legendre": matrix.LEGENDRE,
            "jacobi": matrix.JACOBI, "laguerre_fn": matrix.LAGUERRE_FN,
-           "hermite_fn": matrix.HERMITE_FN}
+           "hermite_fn": matrix.HERMITE_FN, "sine": matrix.SINE,
+           "cos_power": matrix.COS_POWER}
 
 
 def say(*msg):
@@ -20,20 +21,20 @@ def say(*msg):
 
 
 @functools.lru_cache(maxsize=32)
-def oracle_family(fam, N, alpha=0.0, beta=0.0, unweighted=False):
+def oracle_family(fam, N, alpha=0.0, beta=0.0, unweighted=False, power=2):
     return matrix.MatrixFamily(FAM_IDS[fam], N, alpha=alpha, beta=beta,
-                               orthonormal=not unweighted)
+                               orthonormal=not unweighted, power=power)
 
 
 @functools.lru_cache(maxsize=16)
 def oracle_compressed(fam, N, eps, eps2=1e-2, min_block=32, alpha=0.0, beta=0.0,
-                      unweighted=False):
-    f = oracle_family(fam, N, alpha, beta, unweighted)
+                      unweighted=False, power=2):
+    f = oracle_family(fam, N, alpha, beta, unweighted, power)
     return compressed.Compressed(compressed.Plan(f, eps, eps2, min_block=min_block))
 
 
-def oracle_direct(fam, N, X, rows=None, alpha=0.0, beta=0.0, unweighted=False):
-    return direct.matvec(oracle_family(fam, N, alpha, beta, unweighted), X, rows=rows)
+def oracle_direct(fam, N, X, rows=None, alpha=0.0, beta=0.0, unweighted=False, power=2):
+    return direct.matvec(oracle_family(fam, N, alpha, beta, unweighted, power), X, rows=rows)
 
 
 def to_dev(X, dtype):

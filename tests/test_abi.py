@@ -36,7 +36,8 @@ def test_library_exports_every_declared_symbol():
 
 FAM_IDS = {"chebyshev_t": matrix.CHEBYSHEV_T, "legendre": matrix.LEGENDRE,
            "jacobi": matrix.JACOBI, "laguerre_fn": matrix.LAGUERRE_FN,
-           "hermite_fn": matrix.HERMITE_FN}
+           "hermite_fn": matrix.HERMITE_FN, "sine": matrix.SINE,
+           "cos_power": matrix.COS_POWER}
 
 PLAN_CASES = [("legendre", 256, 1e-12, {}), ("legendre", 4096, 1e-12, {}),
               ("legendre", 16384, 1e-7, {}), ("chebyshev_t", 4096, 1e-12, {}),
@@ -44,7 +45,8 @@ PLAN_CASES = [("legendre", 256, 1e-12, {}), ("legendre", 4096, 1e-12, {}),
               ("hermite_fn", 3000, 1e-7, {}), ("jacobi", 65536, 1e-7, dict(alpha=2.0, beta=3.0)),
               ("legendre", 16384, 1e-10, dict(eps2=1e-4, min_block=20)),
               ("legendre", 777, 1e-9, dict(exact_fft_len=True, eps2=1e-3)),
-              ("legendre", 40, 1e-7, {}), ("legendre", 33, 1e-7, {})]
+              ("legendre", 40, 1e-7, {}), ("legendre", 33, 1e-7, {}),
+              ("sine", 2000, 1e-8, {}), ("cos_power", 1500, 1e-7, dict(power=3))]
 
 
 @pytest.mark.parametrize("fam,N,eps,kw", PLAN_CASES)
@@ -75,7 +77,8 @@ def test_direct_mode_plan():
 
 
 @pytest.mark.parametrize("args", [
-    dict(family=0, N=64, eps=1e-7), dict(family=6, N=64, eps=1e-7),
+    dict(family=0, N=64, eps=1e-7), dict(family=8, N=64, eps=1e-7),
+    dict(family="cos_power", N=64, eps=1e-7), dict(family="cos_power", N=64, eps=1e-7, power=6),
     dict(family="legendre", N=1, eps=1e-7), dict(family="legendre", N=64, eps=0.0),
     dict(family="legendre", N=64, eps=1.0), dict(family="legendre", N=64, eps=0.5),
     dict(family="legendre", N=64, eps=1e-7, eps2=1e-8),

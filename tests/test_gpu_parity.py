@@ -89,16 +89,34 @@ def _check_f64(spt, fam, N, eps, X, tol=1e-12, own_nodes=False, **kw):
     p = spt.Plan(fam, N, eps, nodes=nodes, **kw).precompute()
     Y = run(spt, p, X, spt.F64)
     C = oracle_compressed(fam, N, eps, kw.get("eps2", 1e-2), kw.get("min_block", 32),
-                          kw.get("alpha", 0.0), kw.get("beta", 0.0), kw.get("unweighted", False))
+                          kw.get("alpha", 0.0), kw.get("beta", 0.0), kw.get("unweighted", False),
+                          kw.get("power", 2))
     Yc = C.execute(X)
     Yd = oracle_direct(fam, N, X, alpha=kw.get("alpha", 0.0), beta=kw.get("beta", 0.0),
-                       unweighted=kw.get("unweighted", False))
+                       unweighted=kw.get("unweighted", False), power=kw.get("power", 2))
     e_c, e_d, e_cd = rel_rows(Y, Yc), rel_rows(Y, Yd), rel_rows(Yc, Yd)
     say("  rel vs oracle-C %.3e  vs direct %.3e  (oracle-C vs direct %.3e)" % (e_c, e_d, e_cd))
     if not own_nodes:
         assert e_c <= tol
     assert e_d <= e_cd + tol
     return p, Y
+
+
+@pytest.mark.parametrize("fam,N,R,kw", [
+    ("sine", 1000, 3, {}), ("sine", 3001, 2, {}), ("cos_power", 777, 3, dict(power=2)),
+    ("cos_power", 1500, 2, dict(power=3)), ("cos_power", 1024, 1, dict(power=5))])
+def test_trig_generators_fp64(spt, fam, N, R, kw):
+    """sin(m theta_j) (sec. 2) and cos^s(m theta_j) (eq. cosd2) through Algorithm
+    1 (extras on both sides): F64 parity with the oracle's compressed method on
+    the same thresholded matrix; F32 and split-bf16 within the reduced bar."""
+    say("trig generator", fam, N, R, kw)
+    X = workloads.rhs("normal", R, N, 61)
+    p, Y64 = _check_f64(spt, fam, N, 1e-9, X, **kw)
+    assert p.blocks()[0][1] < 0  # left extras: Algorithm 1
+    for prec in (spt.F32, spt.SPLIT_BF16):
+        e = rel_rows(run(spt, p, X, prec), Y64)
+        say("  prec", prec, "rel vs F64 %.3e" % e)
+        assert e <= reduced_tol(p)
 
 
 def test_legendre_256_fp64(spt):
@@ -247,17 +265,20 @@ def test_nonfinite_input_propagates(spt):
 @pytest.mark.parametrize("fam,N,eps,kw", [
     ("legendre", 256, 1e-12, {}), ("chebyshev_t", 1000, 1e-10, {}),
     ("jacobi", 1234, 1e-9, dict(alpha=0.5, beta=1.5)), ("legendre", 4096, 1e-12, {}),
-    ("hermite_fn", 500, 1e-10, {})])
+    ("hermite_fn", 500, 1e-10, {}), ("sine", 900, 1e-10, {}),
+    ("cos_power", 700, 1e-10, dict(power=4))])
 @pytest.mark.parametrize("R", [1, 66])
 def test_transposed_fp64(spt, fam, N, eps, kw, R):
     from oracle import direct, transposed
     say("transposed", fam, N, eps, kw, "R =", R)
-    f = oracle_family(fam, N, kw.get("alpha", 0.0), kw.get("beta", 0.0))
+    f = oracle_family(fam, N, kw.get("alpha", 0.0), kw.get("beta", 0.0),
+                      power=kw.get("power", 2))
     p = spt.Plan(fam, N, eps, mode=spt.MODE_ROW, nodes=f.nodes(), **kw).precompute()
     F = workloads.rhs("normal", R, N, 300 + N)
     import torch
     Y = to_host(p.execute_transposed(to_dev(F, torch.float64), prec=spt.F64))
-    C = oracle_compressed(fam, N, eps, 1e-2, 32, kw.get("alpha", 0.0), kw.get("beta", 0.0))
+    C = oracle_compressed(fam, N, eps, 1e-2, 32, kw.get("alpha", 0.0), kw.get("beta", 0.0),
+                          power=kw.get("power", 2))
     Yt = transposed.execute(C, F)
     Yd = direct.matvec_transposed(f, F)
     e_c, e_d, e_cd = rel_rows(Y, Yt), rel_rows(Y, Yd), rel_rows(Yt, Yd)
