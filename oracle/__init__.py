@@ -19,6 +19,8 @@ compressed  Algorithm 1 (two-sided extras) and the block Algorithm 3 (one-sided
 transposed  Algorithm 2 / block Algorithm 4 (product with the transpose): sparse
             product with the column-compressed matrix, F*, divide by the window,
             discard the extras.
+appendix_a  Appendix A: compressed rows of the trigonometric generators from the
+            closed-form row spectra convolved with 2q+1 window coefficients.
 
 Pins (what ties this oracle to something other than itself) live in
 ``tests/test_oracle_*.py``.  Parity unpinned: the compression ratios of the
@@ -26,4 +28,4 @@ Laguerre and Hermite function families at their Gauss nodes (the paper gives
 them only for an equispaced grid, and only as figures).
 """
 
-from . import params, nodes, entries, direct, compressed, transposed  # noqa: F401
+from . import params, nodes, entries, direct, compressed, transposed, appendix_a  # noqa: F401

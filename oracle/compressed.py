@@ -53,10 +53,13 @@ def _spectrum(plan, blk, rows):
 class Compressed:
     """The thresholded compressed blocks Add_i (scipy CSR, N x L_i) and the tail."""
 
-    def __init__(self, plan, threshold=True, panel=2048):
+    def __init__(self, plan, threshold=True, panel=2048, spectrum=None):
+        """spectrum(plan, blk, rows): the rows of Add (default: eq. A_comp by FFT;
+        oracle.appendix_a gives the fast precomputation of Appendix A)."""
         self.plan = plan
         N = plan.fam.N
         self.mats, self.maxabs, self.thresholds = [], [], []
+        _spectrum = spectrum or globals()["_spectrum"]
         for blk in plan.blocks:
             panels = [np.arange(p, min(p + panel, N)) for p in range(0, N, panel)]
             if len(panels) == 1:

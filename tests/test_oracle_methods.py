@@ -213,3 +213,60 @@ def test_transposed_thresholded_accuracy():
     Fv = np.random.default_rng(11).standard_normal((3, N))
     e = rel(transposed.execute(C, Fv), direct.matvec_transposed(fam, Fv))
     assert e <= 3e-7
+
+
+# ------------------------------------------------------------------ Appendix A
+APPA_FAMS = [(matrix.CHEBYSHEV_T, {}), (matrix.SINE, {}), (matrix.COS_POWER, dict(power=2)),
+             (matrix.COS_POWER, dict(power=3))]
+
+
+@pytest.mark.parametrize("fam_id,kw", APPA_FAMS)
+def test_appendix_a_row_spectra_are_the_rows_dft(fam_id, kw):
+    # eqs. y1-y3: the closed-form DFT of a trigonometric row equals NumPy's FFT of
+    # the explicit row, including the left extras' phase (m_off < 0)
+    from oracle import appendix_a
+    N, L, m_off = 100, 300, -37
+    fam = matrix.MatrixFamily(fam_id, N, **kw)
+    rows = np.array([0, 1, 50, 99])
+    U = appendix_a.row_spectra(fam, rows, m_off, L)
+    ref = np.fft.fft(fam.block(rows, m_off, m_off + L), axis=1, norm="ortho")
+    np.testing.assert_allclose(U, ref, atol=1e-12 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("fam_id,kw", APPA_FAMS)
+def test_appendix_a_full_convolution_is_eq_a_comp(fam_id, kw):
+    # eq. conv_appendix with every window coefficient is exactly A_e W F (eq. A_comp)
+    from oracle import appendix_a
+    fam = matrix.MatrixFamily(fam_id, 80, **kw)
+    plan = compressed.Plan(fam, 1e-7, 1e-2)
+    blk = plan.blocks[0]
+    rows = np.arange(0, 80, 9)
+    U = appendix_a.row_spectra(fam, rows, blk.m_offset, blk.L)
+    vt = appendix_a.window_spectrum(plan, blk)
+    S = sum(vt[m] * np.roll(U, m, axis=1) for m in range(blk.L)) / np.sqrt(blk.L)
+    ref = compressed._spectrum(plan, blk, rows)
+    np.testing.assert_allclose(S, ref, atol=1e-13 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("fam_id,kw", APPA_FAMS)
+@pytest.mark.parametrize("eps1", [1e-7, 1e-10])
+def test_appendix_a_truncation_stays_below_the_threshold(fam_id, kw, eps1):
+    # with q = 12 window coefficients each entry moves by a fraction of the
+    # threshold eps1 * max (measured: at most 0.15 of it; the window's side lobes
+    # stand at ~eps1 / m), so the method's error against A x stays that of the
+    # FFT-built rows
+    from oracle import appendix_a
+    N = 512
+    fam = matrix.MatrixFamily(fam_id, N, **kw)
+    plan = compressed.Plan(fam, eps1, 1e-2)
+    blk = plan.blocks[0]
+    rows = np.arange(0, N, 11)
+    S = compressed._spectrum(plan, blk, rows)
+    Sa = appendix_a.spectrum(plan, blk, rows, q=12)
+    mx = np.abs(S).max()
+    assert np.abs(Sa - S).max() <= 0.25 * eps1 * mx
+    X = np.random.default_rng(3).standard_normal((3, N))
+    Yd = direct.matvec(fam, X)
+    ef = rel(compressed.Compressed(plan).execute(X), Yd)
+    Ya = appendix_a.compressed_method(plan, q=12).execute(X)
+    assert rel(Ya, Yd) <= 1.05 * ef
