@@ -142,6 +142,14 @@ typedef struct {
                              generators take their angles from the node index
                              and ignore it.                                       */
   int32_t power;          /* SPT_COS_POWER: s in 2..5 (others ignore it)          */
+  int32_t trig_conv_q;    /* trigonometric generators only: 0 -> compressed rows
+                             by row FFTs (eq. A_comp); q in 1..64 -> by the fast
+                             precomputation of Appendix A: the closed-form DFT
+                             of each row convolved with the 2q+1 window
+                             coefficients m = -q..q (eq. conv_appendix), only
+                             near each tone of the row.  The window's side
+                             lobes make this an approximation: q = 12 moves an
+                             entry by < 0.25 eps max|A_e W F|                     */
 } spt_params;
 
 typedef struct spt_plan* spt_plan_t;

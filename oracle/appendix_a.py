@@ -49,14 +49,19 @@ def tones(fam):
 
 def geometric(phi, L):
     """G_k(phi) = L^{-1/2} sum_{c<L} e^{i c phi} w^{ck}, w = e^{-2 pi i/L}, for k = 0 .. L-1
-    (eq. y3; phi is an array of one angle per row, the result rows x L)."""
+    (eq. y3; phi is an array of one angle per row, the result rows x L).
+
+    The sum of e^{i c x}, x = phi - 2 pi k / L, is written as the Dirichlet
+    kernel e^{i (L-1) x/2} sin(L x/2) / sin(x/2) (L at x = 0), with x reduced
+    into [-pi, pi): the quotient of eq. y3, (e^{i L x} - 1) / (e^{i x} - 1),
+    divides two rounding errors when phi falls on a bin."""
     k = np.arange(L)
-    z = np.exp(1j * phi)[:, None] * np.exp(-2j * np.pi * k / L)[None, :]
-    num = np.exp(1j * L * phi)[:, None] - 1.0
+    x = np.asarray(phi, dtype=np.float64)[:, None] - 2.0 * np.pi * k[None, :] / L
+    x = x - 2.0 * np.pi * np.round(x / (2.0 * np.pi))
     with np.errstate(divide="ignore", invalid="ignore"):
-        g = num / (z - 1.0)
-    # where z = 1 every term of the sum is 1
-    return np.where(np.abs(z - 1.0) < 1e-300, L + 0j, g) / np.sqrt(L)
+        d = np.sin(L * x / 2.0) / np.sin(x / 2.0)
+    d = np.where(x == 0.0, float(L), d)
+    return np.exp(0.5j * (L - 1) * x) * d / np.sqrt(L)
 
 
 def row_spectra(fam, rows, m_off, L):
@@ -79,14 +84,25 @@ def window_spectrum(plan, blk):
 
 
 def spectrum(plan, blk, rows, q=12):
-    """Add[rows, :] by Appendix A: L^{-1/2} sum_{|m| <= q} (F w)_m (F u)_{(k-m) mod L}."""
+    """Add[rows, :] by Appendix A: L^{-1/2} sum_{|m| <= q} (F w)_m (F u)_{(k-m) mod L}.
+
+    The rows are real, so their spectra are conjugate-symmetric (sec. 5.1): the
+    entries k = 0 .. L/2 are evaluated and k > L/2 is their mirror, so that the
+    threshold keeps k and L - k together (evaluated separately, the two closed
+    forms round differently)."""
     L = blk.L
     U = row_spectra(plan.fam, rows, blk.m_offset, L)
     vt = window_spectrum(plan, blk)
     S = np.zeros_like(U)
     for m in range(-q, q + 1):
         S += vt[m % L] * np.roll(U, m, axis=1)
-    return S / np.sqrt(L)
+    S /= np.sqrt(L)
+    h = L // 2
+    S[:, L - np.arange(1, (L + 1) // 2)] = np.conj(S[:, np.arange(1, (L + 1) // 2)])
+    if L % 2 == 0:
+        S[:, h] = S[:, h].real
+    S[:, 0] = S[:, 0].real
+    return S
 
 
 def compressed_method(plan, q=12, threshold=True):

@@ -44,7 +44,7 @@ class Plan:
 
     def __init__(self, family, N, eps, alpha=0.0, beta=0.0, eps2=0.0, mode=MODE_AUTO,
                  unweighted=False, precisions=0, min_block=0, exact_fft_len=False,
-                 panel_rows=0, nodes=None, executor=EXECUTOR_AUTO, power=0):
+                 panel_rows=0, nodes=None, executor=EXECUTOR_AUTO, power=0, trig_conv_q=0):
         self._lib = _lib.load()
         self._h = c_void_p()
         p = _lib.SptParams()
@@ -53,6 +53,7 @@ class Plan:
         p.min_block, p.exact_fft_len, p.panel_rows = int(min_block), int(bool(exact_fft_len)), int(panel_rows)
         p.executor = int(executor)
         p.power = int(power)
+        p.trig_conv_q = int(trig_conv_q)
         self._nodes_buf = None
         if nodes is not None:
             self._nodes_buf = (c_double * N)(*[float(v) for v in nodes])

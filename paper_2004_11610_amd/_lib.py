@@ -16,7 +16,8 @@ class SptParams(ctypes.Structure):
     _fields_ = [("alpha", c_double), ("beta", c_double), ("eps2", c_double),
                 ("mode", c_int32), ("unweighted", c_int32), ("precisions", c_uint32),
                 ("min_block", c_int32), ("exact_fft_len", c_int32), ("executor", c_int32),
-                ("panel_rows", c_int64), ("nodes", POINTER(c_double)), ("power", c_int32)]
+                ("panel_rows", c_int64), ("nodes", POINTER(c_double)), ("power", c_int32),
+                ("trig_conv_q", c_int32)]
 
 
 class SptPlanInfo(ctypes.Structure):

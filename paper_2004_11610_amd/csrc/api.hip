@@ -537,6 +537,70 @@ int64_t build_block(spt_plan_t plan, DevBlock& B, hipStream_t s, size_t lds_max,
   kcnt.alloc(rows * sizeof(int32_t));
   SPT_HIP(hipMemsetAsync(maxbits.p, 0, sizeof(unsigned long long), s));
   const FamilyArgs fa = family_args(plan, is_jacobi(plan->family) && !plan->p.unweighted);
+  // Appendix A (trig_conv_q > 0): the window's spectrum near m = 0 and the
+  // tones of the generator; the band half-width B reaches where the window's
+  // side lobes fall below 0.1 eps1 (else the block falls back to row FFTs)
+  DevBuf vtbuf;
+  TrigSpecArgs ta{};
+  int qa = is_trig(plan->family) ? plan->p.trig_conv_q : 0;
+  if (qa > 0) {
+    const int D = 2 * qa + 8;
+    std::vector<double> vr(D + 1), vi(D + 1);
+    const long double two_pi = 6.283185307179586476925286766559005768L;
+    for (int m = 0; m <= D; ++m) {
+      long double sr = 0.0L, si = 0.0L;
+      for (int c = 0; c < L; ++c) {
+        const long double a = two_pi * (long double)(((int64_t)c * m) % L) / (long double)L;
+        sr += (long double)w[c] * cosl(a);
+        si -= (long double)w[c] * sinl(a);
+      }
+      vr[m] = (double)(sr / sqrtl((long double)L));
+      vi[m] = (double)(si / sqrtl((long double)L));
+    }
+    const double v0 = std::hypot(vr[0], vi[0]);
+    int bw = -1;
+    for (int d = D; d >= 1; --d) {
+      if (std::hypot(vr[d], vi[d]) >= 0.1 * plan->eps1 * v0) break;
+      bw = d;
+    }
+    if (bw < 0 || bw > D - 2) {
+      qa = 0;  // side lobes too high within D bins: row FFTs
+    } else {
+      // the window is real: vt_{-m} = conj(vt_m)
+      std::vector<double2> vt(2 * qa + 1);
+      for (int m = -qa; m <= qa; ++m)
+        vt[m + qa] = m >= 0 ? double2{vr[m], vi[m]} : double2{vr[-m], -vi[-m]};
+      upload(vtbuf, vt, s);
+      ta.N = N;
+      ta.L = L;
+      ta.P = P;
+      ta.m_off = B.g.m_off;
+      ta.q = qa;
+      ta.B = bw + 2;
+      ta.vt = vtbuf.as<double2>();
+      ta.sine = plan->family == SPT_SINE ? 1 : 0;
+      if (plan->family == SPT_COS_POWER) {
+        const int sp = plan->p.power;
+        auto binom = [](int n, int k) {
+          double r = 1.0;
+          for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
+          return r;
+        };
+        for (int k = 0; 2 * k < sp; ++k) {
+          ta.tone[ta.ntones] = sp - 2 * k;
+          ta.coef[ta.ntones++] = std::ldexp(binom(sp, k), 1 - sp);
+        }
+        if (sp % 2 == 0) {
+          ta.tone[ta.ntones] = 0;
+          ta.coef[ta.ntones++] = std::ldexp(binom(sp, sp / 2), -sp);
+        }
+      } else {
+        ta.tone[0] = 1;
+        ta.coef[0] = 1.0;
+        ta.ntones = 1;
+      }
+    }
+  }
   RowFftArgs ra{};
   ra.rows = rowbuf.as<double>();
   ra.spec = spec.as<double2>();
@@ -546,6 +610,14 @@ int64_t build_block(spt_plan_t plan, DevBlock& B, hipStream_t s, size_t lds_max,
   ra.P = P;
   ra.scale = 1.0 / std::sqrt((double)L);
   auto spectrum = [&](int64_t row0, int nr) {
+    if (qa > 0) {
+      SPT_HIP(hipMemsetAsync(spec.p, 0, (size_t)nr * (P + 1) * sizeof(double2), s));
+      ta.row0 = row0;
+      ta.nrows = nr;
+      ta.spec = spec.as<double2>();
+      launch_trig_spec(ta, s);
+      return;
+    }
     launch_rec_rows(fa, row0, nr, B.g.m_off, L, dw.as<double>(), rowbuf.as<double>(), s);
     if (!big) {
       ra.nrows = nr;
@@ -1533,6 +1605,10 @@ spt_status spt_plan_create(spt_plan_t* out, int32_t family, const spt_params* p,
     if (family == SPT_LEGENDRE) prm.alpha = prm.beta = 0.0;
     if (family == SPT_COS_POWER && (prm.power < 2 || prm.power > 5))
       throw Error(SPT_E_INVALID_ARG, "cos power s must be 2, 3, 4 or 5");
+    if (prm.trig_conv_q < 0 || prm.trig_conv_q > 64)
+      throw Error(SPT_E_INVALID_ARG, "trig_conv_q must lie in 0..64");
+    if (prm.trig_conv_q > 0 && !is_trig(family))
+      throw Error(SPT_E_INVALID_ARG, "Appendix A covers the trigonometric generators only");
     if (prm.mode != SPT_MODE_AUTO && prm.mode != SPT_MODE_ROW && prm.mode != SPT_MODE_DIRECT)
       throw Error(SPT_E_INVALID_ARG, "unknown mode");
     if (prm.precisions & ~7u) throw Error(SPT_E_INVALID_ARG, "unknown precision bits");

@@ -326,6 +326,26 @@ struct FamilyArgs {
 void launch_nodes(const FamilyArgs& f, const double* diag, const double* off2, double lo,
                   double hi, double* x_out, hipStream_t s);
 void launch_weights(const FamilyArgs& f, double* rowscale, hipStream_t s);
+
+// Appendix A: compressed rows of a trigonometric generator without a row FFT.
+// Row j's entry k of the half spectrum is L^{-1/2} sum_{|m| <= q} vt_m
+// U_{(k-m) mod L}, with vt the window's spectrum (2q+1 coefficients) and U the
+// closed-form DFT of the row's tones (eq. y3 and its cos / sin halves); only
+// the bins within B of each tone are evaluated, the rest of the panel is zero.
+constexpr int TRIG_MAX_TONES = 4;
+struct TrigSpecArgs {
+  int64_t N;
+  int L, P, m_off, q, B;
+  int sine;                       // 1: the sine generator (tones are sines)
+  int ntones;
+  int tone[TRIG_MAX_TONES];       // t >= 0: the tone pair exp(+-i t m theta_j)
+  double coef[TRIG_MAX_TONES];
+  const double2* vt;              // window spectrum, m = -q .. q
+  int64_t row0;
+  int nrows;
+  double2* spec;                  // nrows x (P+1), zero elsewhere (caller clears)
+};
+void launch_trig_spec(const TrigSpecArgs& a, hipStream_t s);
 // rows [row0, row0+nrows) x degrees [m0, m0+L), times window w (NULL = 1),
 // row-major into out (ld = L)
 void launch_rec_rows(const FamilyArgs& f, int64_t row0, int nrows, int m0, int L,

@@ -314,6 +314,81 @@ __global__ void rec_tail_kernel(FamilyArgs f, int t, int64_t ldt, double* __rest
 }
 
 // ---------------------------------------------------------------- threshold
+// ---------------------------------------------------------------- Appendix A
+// G_k(phi) = L^{-1/2} sum_{c<L} exp(i c phi) exp(-2 pi i c k/L) for phi = t theta_j
+// (t may be negative), by the geometric series with the angle kept exact: with
+// x = phi - 2 pi k/L = pi n / (2 N L), n = t (2j+1) L - 4 N k an integer,
+//   G = L^{-1/2} exp(i (L-1) x/2) sin(L x/2) / sin(x/2),  or L^{1/2} when x = 0 mod 2 pi.
+__device__ double2 trig_geometric(int64_t t, int64_t j, int64_t k, int64_t N, int64_t L) {
+  const int64_t M4 = 4 * N * L;             // x / 2 = pi n / M4
+  const int64_t M8 = 2 * M4;
+  int64_t n = (t * (2 * j + 1) * L - 4 * N * k) % M8;
+  if (n < 0) n += M8;
+  const double rl = 1.0 / sqrt((double)L);
+  if (n % M4 == 0) return double2{sqrt((double)L), 0.0};
+  const int64_t n8 = n % (8 * N);           // L x / 2 = pi n / (4N)
+  const double s1 = sinpi((double)n8 / (double)(4 * N));
+  const double s2 = sinpi((double)n / (double)M4);
+  const int64_t ph = (int64_t)(((unsigned __int128)(L - 1) * (unsigned __int128)n) %
+                               (unsigned __int128)M8);
+  double sp, cp;
+  sincospi((double)ph / (double)M4, &sp, &cp);
+  const double a = rl * s1 / s2;
+  return double2{a * cp, a * sp};
+}
+
+// One thread per (row, tone, bin offset d in [-B, B]): entry k of the half
+// spectrum near the tone's bin t (2j+1) L / (4N) (mirrored into 0 .. P)
+__global__ void trig_spec_kernel(TrigSpecArgs a) {
+  const int64_t per_row = (int64_t)a.ntones * (2 * a.B + 1);
+  const int64_t item = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (item >= per_row * a.nrows) return;
+  const int r = (int)(item / per_row);
+  const int rem = (int)(item % per_row);
+  const int ti = rem / (2 * a.B + 1), d = rem % (2 * a.B + 1) - a.B;
+  const int64_t N = a.N, L = a.L, j = a.row0 + r;
+  const int64_t t0 = a.tone[ti];
+  int64_t kc = ((t0 * (2 * j + 1) * L + 2 * N) / (4 * N)) % L;  // nearest bin of the tone
+  int64_t k = ((kc + d) % L + L) % L;
+  if (k > a.P) k = L - k;
+  // U_k' = sum_tones coef (ph G(t) +- conj(ph) G(-t)) / 2 (cos) or / 2i (sin),
+  // ph = exp(i t m_off theta_j)
+  double2 ph[TRIG_MAX_TONES];
+  for (int u = 0; u < a.ntones; ++u) {
+    int64_t qv = ((int64_t)a.tone[u] * a.m_off % (4 * N)) * ((2 * j + 1) % (4 * N)) % (4 * N);
+    if (qv < 0) qv += 4 * N;
+    double sp, cp;
+    sincospi((double)qv / (double)(2 * N), &sp, &cp);
+    ph[u] = double2{cp, sp};
+  }
+  double vr = 0.0, vi = 0.0;
+  for (int m = -a.q; m <= a.q; ++m) {
+    const int64_t kp = ((k - m) % L + L) % L;
+    double ur = 0.0, ui = 0.0;
+    for (int u = 0; u < a.ntones; ++u) {
+      const double2 gp = trig_geometric(a.tone[u], j, kp, N, L);
+      const double2 gm = trig_geometric(-(int64_t)a.tone[u], j, kp, N, L);
+      const double2 p = ph[u];
+      // ph gp and conj(ph) gm
+      const double ar = p.x * gp.x - p.y * gp.y, ai = p.x * gp.y + p.y * gp.x;
+      const double br = p.x * gm.x + p.y * gm.y, bi = p.x * gm.y - p.y * gm.x;
+      const double c = 0.5 * a.coef[u];
+      if (a.sine) {  // (A - B) / (2i) = -i (A - B) / 2
+        ur += c * (ai - bi);
+        ui -= c * (ar - br);
+      } else {
+        ur += c * (ar + br);
+        ui += c * (ai + bi);
+      }
+    }
+    const double2 w = a.vt[m + a.q];
+    vr += w.x * ur - w.y * ui;
+    vi += w.x * ui + w.y * ur;
+  }
+  const double rl = 1.0 / sqrt((double)L);
+  a.spec[(int64_t)r * (a.P + 1) + k] = double2{vr * rl, vi * rl};
+}
+
 __global__ void maxabs_kernel(const double2* __restrict__ s, int64_t n,
                               unsigned long long* __restrict__ max_bits) {
   double mx = 0.0;
@@ -475,6 +550,13 @@ void launch_rec_rows(const FamilyArgs& f, int64_t row0, int nrows, int m0, int L
                      const double* w, double* out, hipStream_t s) {
   hipLaunchKernelGGL(rec_rows_kernel, dim3((nrows + 63) / 64), dim3(64), 0, s, f, row0, nrows,
                      m0, L, w, out);
+  SPT_HIP(hipGetLastError());
+}
+
+void launch_trig_spec(const TrigSpecArgs& a, hipStream_t s) {
+  const int64_t items = (int64_t)a.nrows * a.ntones * (2 * a.B + 1);
+  if (items <= 0) return;
+  hipLaunchKernelGGL(trig_spec_kernel, dim3((unsigned)((items + 255) / 256)), dim3(256), 0, s, a);
   SPT_HIP(hipGetLastError());
 }
 

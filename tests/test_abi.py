@@ -79,6 +79,9 @@ def test_direct_mode_plan():
 @pytest.mark.parametrize("args", [
     dict(family=0, N=64, eps=1e-7), dict(family=8, N=64, eps=1e-7),
     dict(family="cos_power", N=64, eps=1e-7), dict(family="cos_power", N=64, eps=1e-7, power=6),
+    dict(family="legendre", N=64, eps=1e-7, trig_conv_q=12),
+    dict(family="chebyshev_t", N=64, eps=1e-7, trig_conv_q=65),
+    dict(family="sine", N=64, eps=1e-7, trig_conv_q=-1),
     dict(family="legendre", N=1, eps=1e-7), dict(family="legendre", N=64, eps=0.0),
     dict(family="legendre", N=64, eps=1.0), dict(family="legendre", N=64, eps=0.5),
     dict(family="legendre", N=64, eps=1e-7, eps2=1e-8),

@@ -119,6 +119,36 @@ def test_trig_generators_fp64(spt, fam, N, R, kw):
         assert e <= reduced_tol(p)
 
 
+@pytest.mark.parametrize("fam,N,eps,R,kw", [
+    ("chebyshev_t", 1000, 1e-9, 3, {}), ("sine", 2048, 1e-7, 2, {}),
+    ("cos_power", 1500, 1e-8, 1, dict(power=3)), ("cos_power", 777, 1e-10, 2, dict(power=2))])
+def test_appendix_a_precompute_fp64(spt, fam, N, eps, R, kw):
+    """Appendix A (trig_conv_q = 12): the compressed rows from the closed-form
+    row spectra convolved with 25 window coefficients, on the device; F64
+    parity with the oracle's Appendix A method (same truncation, same
+    threshold), and against A x no worse than the FFT-built rows."""
+    from oracle import appendix_a, compressed
+    say("appendix A", fam, N, eps, R, kw)
+    f = oracle_family(fam, N, power=kw.get("power", 2))
+    X = workloads.rhs("normal", R, N, 71)
+    p = spt.Plan(fam, N, eps, mode=spt.MODE_ROW, trig_conv_q=12, **kw).precompute()
+    Y = run(spt, p, X, spt.F64)
+    oplan = compressed.Plan(f, eps, 1e-2)
+    Ca = appendix_a.compressed_method(oplan, q=12)
+    Yd = oracle_direct(fam, N, X, power=kw.get("power", 2))
+    e_fft = rel_rows(compressed.Compressed(oplan).execute(X), Yd)
+    e_a, e_d = rel_rows(Y, Ca.execute(X)), rel_rows(Y, Yd)
+    say("  vs oracle Appendix A %.3e  vs direct %.3e  (FFT rows vs direct %.3e)" % (e_a, e_d, e_fft))
+    assert e_a <= 1e-12
+    assert e_d <= 1.05 * e_fft + 1e-12
+    # the same kept set: the oracle counts the full spectrum (k and L - k), the
+    # library the half (k = 0 and L/2 once)
+    full = sum(Ca.nnz())
+    assert abs(2 * p.info()["nnz"] - full) <= 0.01 * full + 2 * N
+    for prec in (spt.F32, spt.SPLIT_BF16):
+        assert rel_rows(run(spt, p, X, prec), Y) <= reduced_tol(p)
+
+
 def test_legendre_256_fp64(spt):
     w = workloads.LEGENDRE_256
     say(w["name"])

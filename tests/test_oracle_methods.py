@@ -221,13 +221,16 @@ APPA_FAMS = [(matrix.CHEBYSHEV_T, {}), (matrix.SINE, {}), (matrix.COS_POWER, dic
 
 
 @pytest.mark.parametrize("fam_id,kw", APPA_FAMS)
-def test_appendix_a_row_spectra_are_the_rows_dft(fam_id, kw):
+@pytest.mark.parametrize("N,L,m_off,rows", [(100, 300, -37, [0, 1, 50, 99]),
+                                            (1000, 1728, -364, [0, 687, 999])])
+def test_appendix_a_row_spectra_are_the_rows_dft(fam_id, kw, N, L, m_off, rows):
     # eqs. y1-y3: the closed-form DFT of a trigonometric row equals NumPy's FFT of
-    # the explicit row, including the left extras' phase (m_off < 0)
+    # the explicit row, including the left extras' phase (m_off < 0); row 687
+    # of N = 1000 puts its tone exactly on bin 594 of L = 1728, where the
+    # quotient form of the geometric series divides two rounding errors
     from oracle import appendix_a
-    N, L, m_off = 100, 300, -37
     fam = matrix.MatrixFamily(fam_id, N, **kw)
-    rows = np.array([0, 1, 50, 99])
+    rows = np.array(rows)
     U = appendix_a.row_spectra(fam, rows, m_off, L)
     ref = np.fft.fft(fam.block(rows, m_off, m_off + L), axis=1, norm="ortho")
     np.testing.assert_allclose(U, ref, atol=1e-12 * np.abs(ref).max())
