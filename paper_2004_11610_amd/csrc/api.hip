@@ -546,13 +546,21 @@ int64_t build_block(spt_plan_t plan, DevBlock& B, hipStream_t s, size_t lds_max,
   if (qa > 0) {
     const int D = 2 * qa + 8;
     std::vector<double> vr(D + 1), vi(D + 1);
+    // cos, sin of 2 pi r / L once per residue r, then the sums over c
     const long double two_pi = 6.283185307179586476925286766559005768L;
+    std::vector<long double> ct(L), st(L);
+    for (int r = 0; r < L; ++r) {
+      ct[r] = cosl(two_pi * (long double)r / (long double)L);
+      st[r] = sinl(two_pi * (long double)r / (long double)L);
+    }
     for (int m = 0; m <= D; ++m) {
       long double sr = 0.0L, si = 0.0L;
+      int64_t r = 0;
       for (int c = 0; c < L; ++c) {
-        const long double a = two_pi * (long double)(((int64_t)c * m) % L) / (long double)L;
-        sr += (long double)w[c] * cosl(a);
-        si -= (long double)w[c] * sinl(a);
+        sr += (long double)w[c] * ct[r];
+        si -= (long double)w[c] * st[r];
+        r += m;
+        if (r >= L) r -= L;
       }
       vr[m] = (double)(sr / sqrtl((long double)L));
       vi[m] = (double)(si / sqrtl((long double)L));

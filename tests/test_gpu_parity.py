@@ -139,7 +139,10 @@ def test_appendix_a_precompute_fp64(spt, fam, N, eps, R, kw):
     e_fft = rel_rows(compressed.Compressed(oplan).execute(X), Yd)
     e_a, e_d = rel_rows(Y, Ca.execute(X)), rel_rows(Y, Yd)
     say("  vs oracle Appendix A %.3e  vs direct %.3e  (FFT rows vs direct %.3e)" % (e_a, e_d, e_fft))
-    assert e_a <= 1e-12
+    # the oracle forms x = phi - 2 pi k / L in float64, so sin(L x / 2) carries an
+    # absolute error of ~L u; the library reduces its angles exactly in integers.
+    # A wrong tone, phase or truncation shows at the eps1 level, far above.
+    assert e_a <= 1e-11
     assert e_d <= 1.05 * e_fft + 1e-12
     # the same kept set: the oracle counts the full spectrum (k and L - k), the
     # library the half (k = 0 and L/2 once)
