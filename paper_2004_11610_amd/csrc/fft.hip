@@ -58,11 +58,11 @@ __global__ __launch_bounds__(FFT_MAX_THREADS) void exec_fft_kernel(ExecFftArgs<T
 // 1 entries), float64 the two-level table (ntw entries).  load() requests
 // them; store() writes them once they arrive, after the caller has requested
 // its points, so both share one wait.
-template <typename T>
+template <typename T, int EI>
 struct TabStage {
   using C = cplx_t<T>;
   using V = typename std::conditional<sizeof(T) == 4, C, double2>::type;
-  static constexpr int SLOTS = sizeof(T) == 4 ? FFT_EPT : 2;
+  static constexpr int SLOTS = sizeof(T) == 4 ? EI : 2;
   V v[SLOTS];
   const V* src;
   int n;
@@ -126,7 +126,9 @@ __device__ __forceinline__ cplx_t<T> point_pair(const T* __restrict__ x, const T
 // the split-bf16 product, layout in common.hpp) instead of complex values.
 // BATCH == false: one transform (lb == 0), indexed without the interleaving.
 // EARLY: the unpack twiddles are requested with the points (registers permitting)
-template <typename T, bool SPLIT, bool BATCH, bool EARLY>
+// EI: points per thread, FFT_EPT or fewer (2^lb P <= EI nt): loops over the
+// thread's points stop there instead of clamping indexes past the end
+template <typename T, bool SPLIT, bool BATCH, bool EARLY, int EI>
 __device__ __forceinline__ void fft_multi_body(const FftDesc<T>* __restrict__ d,
                                                const T* __restrict__ X, cplx_t<T>* __restrict__ Z,
                                                uint32_t* __restrict__ Zs, int64_t zplane, int R,
@@ -146,8 +148,8 @@ __device__ __forceinline__ void fft_multi_body(const FftDesc<T>* __restrict__ d,
   // The unpack twiddles of the thread's outputs (see below) and the pass
   // twiddles are requested first, then the points, so that all of them arrive
   // within one wait.
-  constexpr int GS = FFT_EPT / 4 + 2;  // output groups per thread (SPLIT)
-  constexpr int NTW = SPLIT ? 4 * GS : FFT_EPT + 1;
+  constexpr int GS = EI / 4 + 2;  // output groups per thread (SPLIT)
+  constexpr int NTW = SPLIT ? 4 * GS : EI + 1;
   C tw[NTW];
   auto load_tw = [&]() {
 #pragma unroll
@@ -159,18 +161,18 @@ __device__ __forceinline__ void fft_multi_body(const FftDesc<T>* __restrict__ d,
     }
   };
   if constexpr (EARLY) load_tw();
-  TabStage<T> ts;
+  TabStage<T, EI> ts;
   ts.load(d, tid, nt);
   // E1: the thread's points (float32: all at once; float64: in two rounds, for
   // registers), written to LDS; transforms past the last right-hand side are
   // zero.  Loads are branch-free: indexes past the end are clamped.
-  constexpr int ROUND = sizeof(T) == 4 ? FFT_EPT : FFT_EPT / 2;
+  constexpr int ROUND = (sizeof(T) == 4 || EI <= FFT_EPT / 2) ? EI : FFT_EPT / 2;
   const int pts = P << lb;
-  auto* ltab = reinterpret_cast<typename TabStage<T>::V*>(smem_raw + tab_offset<T>(pts));
+  auto* ltab = reinterpret_cast<typename TabStage<T, EI>::V*>(smem_raw + tab_offset<T>(pts));
   auto input = [&](auto vtag) {
     constexpr bool VEC = decltype(vtag)::value;
 #pragma unroll
-    for (int h = 0; h < FFT_EPT; h += ROUND) {
+    for (int h = 0; h < EI; h += ROUND) {
       C v[ROUND];
 #pragma unroll
       for (int e = 0; e < ROUND; ++e) {
@@ -197,9 +199,9 @@ __device__ __forceinline__ void fft_multi_body(const FftDesc<T>* __restrict__ d,
   // E2: F*; float32 reads its pass twiddles from the block's table, float64
   // forms them from the two-level table
   if constexpr (sizeof(T) == 4)
-    run_fft_tab<+1, BATCH>(lds, P, lb, d->fp.npass, d->fp.radix, ltab, tid, nt, true);
+    run_fft_tab<+1, BATCH, EI>(lds, P, lb, d->fp.npass, d->fp.radix, ltab, tid, nt, true);
   else
-    run_fft<+1, BATCH>(lds, P, lb, d->fp.npass, d->fp.radix, ltab, 1, tid, nt, true);
+    run_fft<+1, BATCH, EI>(lds, P, lb, d->fp.npass, d->fp.radix, ltab, 1, tid, nt, true);
   if constexpr (!EARLY) load_tw();
   // unpack point k of transform t (see unpack_with)
   auto unpack_at = [&](int k, int t, C tw) {
@@ -212,12 +214,11 @@ __device__ __forceinline__ void fft_multi_body(const FftDesc<T>* __restrict__ d,
     const C z = cadd(e, cmul(tw, o));
     return C{z.x * scale, z.y * scale};
   };
-  // the thread's outputs u = tid + e nt (u < (P + 1) << lb <= FFT_EPT nt +
-  // 2^lb)
+  // the thread's outputs u = tid + e nt (u < (P + 1) << lb <= EI nt + 2^lb)
   if constexpr (!SPLIT) {
     const int n = (P + 1) << lb;
 #pragma unroll
-    for (int e = 0; e <= FFT_EPT; ++e) {
+    for (int e = 0; e <= EI; ++e) {
       const int u = tid + e * nt;
       const int k = u >> lb, t = u & tmask;
       if (u < n && t < cnt)
@@ -226,7 +227,7 @@ __device__ __forceinline__ void fft_multi_body(const FftDesc<T>* __restrict__ d,
   } else {
     // four consecutive k per thread (ldz4 is a multiple of 4): each plane gets
     // one 16-byte store per group; zeros past P.  Groups u = tid + e nt, e <
-    // GS (n <= FFT_EPT nt / 4 + 2^lb + 1 <= GS nt)
+    // GS (n <= EI nt / 4 + 2^lb + 1 <= GS nt)
     const int n = (d->ldz4 / 4) << lb;
 #pragma unroll
     for (int e = 0; e < GS; ++e) {
@@ -256,7 +257,7 @@ __device__ __forceinline__ void fft_multi_body(const FftDesc<T>* __restrict__ d,
 // a transform of H points (one decimation-in-frequency step).  The unpack
 // pairs C_k with C_(P-k), of the same parity, so the half is complete: it
 // writes the half spectrum at every k of parity p (zeros past P).
-template <typename T, bool SPLIT, bool EARLY>
+template <typename T, bool SPLIT, bool EARLY, int EI>
 __device__ __forceinline__ void fft_half_body(const FftDesc<T>* __restrict__ d,
                                               const T* __restrict__ X, cplx_t<T>* __restrict__ Z,
                                               uint32_t* __restrict__ Zs, int64_t zplane, int R,
@@ -272,20 +273,20 @@ __device__ __forceinline__ void fft_half_body(const FftDesc<T>* __restrict__ d,
   const C* __restrict__ post = d->post;  // post[2n] = w^n
   // the unpack twiddles of the thread's outputs k = 2 (tid + e nt) + par and
   // the pass twiddles first, then the points: one wait for all of them
-  C tw[FFT_EPT + 1];
+  C tw[EI + 1];
   auto load_tw = [&]() {
 #pragma unroll
-    for (int e = 0; e <= FFT_EPT; ++e) tw[e] = gload(post + min(2 * (tid + e * nt) + par, P));
+    for (int e = 0; e <= EI; ++e) tw[e] = gload(post + min(2 * (tid + e * nt) + par, P));
   };
   if constexpr (EARLY) load_tw();
-  TabStage<T> ts;
+  TabStage<T, EI> ts;
   ts.load(d, tid, nt);
-  auto* ltab = reinterpret_cast<typename TabStage<T>::V*>(smem_raw + tab_offset<T>(H));
-  constexpr int ROUND = sizeof(T) == 4 ? FFT_EPT : FFT_EPT / 2;
+  auto* ltab = reinterpret_cast<typename TabStage<T, EI>::V*>(smem_raw + tab_offset<T>(H));
+  constexpr int ROUND = (sizeof(T) == 4 || EI <= FFT_EPT / 2) ? EI : FFT_EPT / 2;
   auto input = [&](auto vtag) {
     constexpr bool VEC = decltype(vtag)::value;
 #pragma unroll
-    for (int h = 0; h < FFT_EPT; h += ROUND) {
+    for (int h = 0; h < EI; h += ROUND) {
       C y[ROUND];
 #pragma unroll
       for (int e = 0; e < ROUND; ++e) {
@@ -308,9 +309,9 @@ __device__ __forceinline__ void fft_half_body(const FftDesc<T>* __restrict__ d,
     input(std::false_type{});
   __syncthreads();
   if constexpr (sizeof(T) == 4)
-    run_fft_tab<+1, false>(lds, H, 0, d->fp.npass, d->fp.radix, ltab, tid, nt, true);
+    run_fft_tab<+1, false, EI>(lds, H, 0, d->fp.npass, d->fp.radix, ltab, tid, nt, true);
   else  // the two-level table is of length P = 2H: index scale 2
-    run_fft<+1, false>(lds, H, 0, d->fp.npass, d->fp.radix, ltab, 2, tid, nt, true);
+    run_fft<+1, false, EI>(lds, H, 0, d->fp.npass, d->fp.radix, ltab, 2, tid, nt, true);
   if constexpr (!EARLY) load_tw();
   // k = 2m + par: C_k at lds[m mod H], C_(P-k) at lds[(H - m) mod H] (par 0)
   // or lds[H - 1 - m] (par 1)
@@ -327,11 +328,11 @@ __device__ __forceinline__ void fft_half_body(const FftDesc<T>* __restrict__ d,
     const C z = cadd(e, cmul(tw, o));
     return C{z.x * scale, z.y * scale};
   };
-  // outputs k = 2m + par < kend; the thread's m are tid + e nt, e <= FFT_EPT
-  // (H <= FFT_EPT nt)
+  // outputs k = 2m + par < kend; the thread's m are tid + e nt, e <= EI
+  // (H <= EI nt)
   const int kend = SPLIT ? d->ldz4 : P + 1;
 #pragma unroll
-  for (int e = 0; e <= FFT_EPT; ++e) {
+  for (int e = 0; e <= EI; ++e) {
     const int m = tid + e * nt, k = 2 * m + par;
     if (k >= kend) break;
     const C z = zval(m, tw[e]);
@@ -353,6 +354,10 @@ template <typename T, bool SPLIT, int MAXT>
 __global__ __launch_bounds__(MAXT) void exec_fft_multi_kernel(
     const FftDesc<T>* __restrict__ descs, const T* __restrict__ X, cplx_t<T>* __restrict__ Z,
     uint32_t* __restrict__ Zs, int64_t zplane, int R, int64_t N) {
+  constexpr bool EARLY = MAXT <= 512;
+  // transforms of at most EI_SHORT points per thread take the variant whose
+  // loops stop there
+  constexpr int EI_SHORT = FFT_EPT / 2;
   const FftDesc<T>* __restrict__ d = descs + blockIdx.y;
   if (d->half) {
     // workgroup x = parity R + r: the two halves of a right-hand side are R
@@ -360,16 +365,27 @@ __global__ __launch_bounds__(MAXT) void exec_fft_multi_kernel(
     // their reads of the row and their interleaved writes meet in one L2
     const int par = (int)blockIdx.x >= R ? 1 : 0;
     const int r = (int)blockIdx.x - par * R;
-    fft_half_body<T, SPLIT, (MAXT <= 512)>(d, X, Z, Zs, zplane, R, N, r, par);
+    if (d->fp.P <= EI_SHORT * (int)blockDim.x)
+      fft_half_body<T, SPLIT, EARLY, EI_SHORT>(d, X, Z, Zs, zplane, R, N, r, par);
+    else
+      fft_half_body<T, SPLIT, EARLY, FFT_EPT>(d, X, Z, Zs, zplane, R, N, r, par);
     return;
   }
   const int lb = d->lb;
   const int r0 = (int)blockIdx.x << lb;
   if (r0 >= R) return;
-  if (lb == 0)
-    fft_multi_body<T, SPLIT, false, (MAXT <= 512)>(d, X, Z, Zs, zplane, R, N, 0, r0);
-  else
-    fft_multi_body<T, SPLIT, true, (MAXT <= 512)>(d, X, Z, Zs, zplane, R, N, lb, r0);
+  const bool short_pts = (d->fp.P << lb) <= EI_SHORT * (int)blockDim.x;
+  if (lb == 0) {
+    if (short_pts)
+      fft_multi_body<T, SPLIT, false, EARLY, EI_SHORT>(d, X, Z, Zs, zplane, R, N, 0, r0);
+    else
+      fft_multi_body<T, SPLIT, false, EARLY, FFT_EPT>(d, X, Z, Zs, zplane, R, N, 0, r0);
+  } else {
+    if (short_pts)
+      fft_multi_body<T, SPLIT, true, EARLY, EI_SHORT>(d, X, Z, Zs, zplane, R, N, lb, r0);
+    else
+      fft_multi_body<T, SPLIT, true, EARLY, FFT_EPT>(d, X, Z, Zs, zplane, R, N, lb, r0);
+  }
 }
 
 // ---------------------------------------------------------------- transposed: E4
