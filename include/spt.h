@@ -208,8 +208,10 @@ spt_status spt_execute(spt_plan_t plan, const void* X, void* Y, int64_t nrhs, in
                        void* stream);
 
 /* Transposed product (Alg. 2 / block Alg. 4): Y[r*N + m] = sum_j A[j,m] X[r*N + j].
- * Same arguments and rules as spt_execute; F64 or F32; every block's FFT
- * half-length must be at most 10240 (SPT_E_UNSUPPORTED otherwise). */
+ * Same arguments and rules as spt_execute; F64 or F32 (SPT_E_UNSUPPORTED for
+ * split-bf16).  Blocks with an FFT half-length above 10240 take a four-step
+ * inverse transform (the workspace then holds P complex values per right-hand
+ * side for each such block). */
 spt_status spt_execute_transposed(spt_plan_t plan, const void* X, void* Y, int64_t nrhs,
                                   int32_t prec, void* stream);
 

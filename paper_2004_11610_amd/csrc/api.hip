@@ -1319,15 +1319,35 @@ __global__ void zero_kernel(T* p, int64_t n) {
     p[i] = T(0);
 }
 
+// Blocks of the transposed product whose inverse transform runs in four steps:
+// those longer than one workgroup's FFT, and (diagnostics: SPT_INV_FFT_FOUR=1)
+// every block with a four-step geometry.
+bool inv_four_step(const DevBlock& B) {
+  if (B.P > FUSED_MAX_P) return true;
+  const char* e = std::getenv("SPT_INV_FFT_FOUR");
+  return B.four && e && e[0] == '1';
+}
+
+// log2 of the transforms of n points per workgroup of a four-step inverse
+// pass (at most 64, at most `count`, about 4096 points per workgroup)
+int inv_four_lb(int n, int count) {
+  int lb = 0;
+  while (lb < 6 && (n << (lb + 1)) <= 4096 && (2 << lb) <= count) ++lb;
+  return lb;
+}
+
 template <typename T>
 void execute_transposed_t(spt_plan_t plan, const T* F, T* Y, int64_t R, hipStream_t s) {
   using C = cplx_t<T>;
-  if (plan->fft_maxP > FUSED_MAX_P)
-    throw Error(SPT_E_UNSUPPORTED, "the transposed product needs FFT half-lengths <= " +
-                                       std::to_string(FUSED_MAX_P));
+  for (auto& B : plan->blk)
+    if (inv_four_step(*B) && !B->four)
+      throw Error(SPT_E_UNSUPPORTED, "block of FFT length half " + std::to_string(B->P) +
+                                         " has no four-step split");
   ensure_work(plan, R, s);
   int64_t per = 0;
   for (auto& B : plan->blk) per += B->P + 1;
+  // four-step intermediates after the half spectra (w_per_rhs)
+  C* wbuf = plan->work->as<C>() + per * R;
   const int64_t nz = 2 * per * R;
   if (nz > 0) {
     const int nb = (int)std::min<int64_t>((nz + 255) / 256, 8192);
@@ -1365,7 +1385,33 @@ void execute_transposed_t(spt_plan_t plan, const T* F, T* Y, int64_t R, hipStrea
     ia.c_lo = B.g.c_lo;
     ia.c_hi = B.g.c_hi;
     ia.scale = (T)(1.0 / std::sqrt((double)B.g.L));
-    staged(SPT_STAGE_INV_FFT, s, [&] { launch_inv_fft<T>(ia, B.fft, s); });
+    if (inv_four_step(B)) {
+      InvFft4Args<T> fa{};
+      fa.U = u;
+      fa.W = wbuf;
+      fa.Y = Y;
+      fa.winv = ia.winv;
+      fa.tw = ia.tw;
+      fa.post = ia.post;
+      fa.N = ia.N;
+      fa.R = ia.R;
+      fa.P = B.P;
+      fa.P1 = B.P1;
+      fa.P2 = B.P2;
+      fa.ldu = ia.ldu;
+      fa.m_off = ia.m_off;
+      fa.c_lo = ia.c_lo;
+      fa.c_hi = ia.c_hi;
+      fa.lb1 = inv_four_lb(B.P2, B.P1);
+      fa.lb2 = inv_four_lb(B.P1, B.P2);
+      fa.f1 = B.f1;
+      fa.f2 = B.f2;
+      fa.scale = ia.scale;
+      staged(SPT_STAGE_INV_FFT, s, [&] { launch_inv_fft4<T>(fa, s); });
+      wbuf += (size_t)R * B.P;
+    } else {
+      staged(SPT_STAGE_INV_FFT, s, [&] { launch_inv_fft<T>(ia, B.fft, s); });
+    }
     u += (size_t)R * (B.P + 1);
   }
   if (plan->tail > 0)

@@ -142,7 +142,7 @@ inline size_t fused_lds_bytes(int pts, int ntab, int ntw) {
 template <typename T>
 struct InvFftArgs {      // transposed execute: half spectrum -> real, /w, keep retained
   const cplx_t<T>* U;   // R x ldu half spectrum
-  T* Y;                 // R x N output (accumulated: +=) at degrees c + m_off, c in [c_lo, c_hi)
+  T* Y;                 // R x N output, written at degrees c + m_off, c in [c_lo, c_hi)
   const T* winv;
   const double2* tw;
   const cplx_t<T>* post;
@@ -153,6 +153,24 @@ struct InvFftArgs {      // transposed execute: half spectrum -> real, /w, keep 
 
 template <typename T>
 void launch_inv_fft(const InvFftArgs<T>& a, const FftPlan& fp, hipStream_t s);
+
+template <typename T>
+struct InvFft4Args {      // transposed execute of a block with P = P1 P2 (four steps)
+  const cplx_t<T>* U;     // R x ldu half spectrum
+  cplx_t<T>* W;           // R x P intermediate, W[j2 P1 + k1]
+  T* Y;                   // R x N output, written at degrees c + m_off, c in [c_lo, c_hi)
+  const T* winv;
+  const double2* tw;      // two-level table of the length P
+  const cplx_t<T>* post;
+  int64_t N;
+  int R, P, P1, P2, ldu, m_off, c_lo, c_hi;
+  int lb1, lb2;           // 2^lb1 transforms over k2, 2^lb2 over k1, per workgroup
+  FftPlan f1, f2;         // passes of the P1- and P2-point transforms
+  T scale;
+};
+
+template <typename T>
+void launch_inv_fft4(const InvFft4Args<T>& a, hipStream_t s);
 
 struct RowFftArgs {      // precompute: forward F of windowed rows, float64
   const double* rows;    // nrows x L

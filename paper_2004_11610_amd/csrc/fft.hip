@@ -419,6 +419,86 @@ __global__ __launch_bounds__(FFT_MAX_THREADS) void inv_fft_kernel(InvFftArgs<T> 
   }
 }
 
+// ---------------------------------------------------------------- transposed: E4 in four steps
+// Blocks whose transform does not fit one workgroup, P = P1 P2.  With a_k the
+// packed half spectrum of inv_fft_kernel, k = k1 + P1 k2 and j = j2 + P2 j1,
+//   c_j = sum_k1 w_P1^(j1 k1) [ w_P^(j2 k1) sum_k2 w_P2^(j2 k2) a_(k1 + P1 k2) ]
+// (w_n = exp(2 pi i / n)).  inv_fft4_col_kernel: per right-hand side and group
+// of 2^lb1 consecutive k1, the P2-point transforms over k2 (interleaved in LDS,
+// point k2 of transform t at lds[(k2 << lb) + t]), times w_P^(j2 k1), written to
+// W[j2 P1 + k1].  inv_fft4_row_kernel: per group of 2^lb2 consecutive j2, the
+// P1-point transforms over k1, then g_2j + i g_(2j+1) = c_j is divided by the
+// window on the retained columns (eq. Fe2).  Workgroup b takes right-hand side
+// b / groups and group b % groups.
+template <typename T>
+__global__ __launch_bounds__(FFT_MAX_THREADS) void inv_fft4_col_kernel(InvFft4Args<T> a) {
+  using C = cplx_t<T>;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C* lds = reinterpret_cast<C*>(smem_raw);
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int lb = a.lb1, tmask = (1 << lb) - 1;
+  const int groups = (a.P1 + tmask) >> lb;
+  const int r = (int)blockIdx.x / groups;
+  const int k1_0 = ((int)blockIdx.x - r * groups) << lb;
+  const C* __restrict__ u = a.U + (int64_t)r * a.ldu;
+  const int pts = a.P2 << lb;
+  for (int i = tid; i < pts; i += nt) {
+    const int k2 = i >> lb, k1 = k1_0 + (i & tmask);
+    C v = C{T(0), T(0)};
+    if (k1 < a.P1) {
+      const int k = k1 + a.P1 * k2;
+      const C uk = u[k];
+      C um = u[a.P - k];
+      um.y = -um.y;  // conj U_(P-k)
+      const C ge = cadd(uk, um);
+      const C go = cmul(csub(uk, um), a.post[k]);
+      v = C{ge.x - go.y, ge.y + go.x};  // ge + i go
+    }
+    lds[i] = v;
+  }
+  __syncthreads();
+  // w_P2 = w_P^P1: the length-P table at index scale P1
+  run_fft<+1, true>(lds, a.P2, lb, a.f2.npass, a.f2.radix, a.tw, a.P1, tid, nt, true);
+  C* __restrict__ w = a.W + (int64_t)r * a.P;
+  for (int i = tid; i < pts; i += nt) {
+    const int j2 = i >> lb, k1 = k1_0 + (i & tmask);
+    if (k1 < a.P1) w[(int64_t)j2 * a.P1 + k1] = cmul(lds[i], to_c<C>(twiddle(a.tw, j2 * k1)));
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(FFT_MAX_THREADS) void inv_fft4_row_kernel(InvFft4Args<T> a) {
+  using C = cplx_t<T>;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C* lds = reinterpret_cast<C*>(smem_raw);
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int lb = a.lb2, tmask = (1 << lb) - 1;
+  const int groups = (a.P2 + tmask) >> lb;
+  const int r = (int)blockIdx.x / groups;
+  const int j2_0 = ((int)blockIdx.x - r * groups) << lb;
+  const int ncol = min(1 << lb, a.P2 - j2_0);
+  // the group's rows W[j2_0 .. j2_0 + ncol - 1][*] are contiguous
+  const C* __restrict__ w = a.W + (int64_t)r * a.P + (int64_t)j2_0 * a.P1;
+  const int pts = a.P1 << lb;
+  for (int i = tid; i < pts; i += nt) {
+    const int t = i / a.P1, k1 = i - t * a.P1;
+    lds[(k1 << lb) + t] = t < ncol ? w[i] : C{T(0), T(0)};
+  }
+  __syncthreads();
+  // w_P1 = w_P^P2
+  run_fft<+1, true>(lds, a.P1, lb, a.f1.npass, a.f1.radix, a.tw, a.P2, tid, nt, true);
+  T* __restrict__ y = a.Y + (int64_t)r * a.N;
+  for (int i = tid; i < pts; i += nt) {
+    const int j1 = i >> lb, t = i & tmask;
+    if (t >= ncol) continue;
+    const int j = j2_0 + t + a.P2 * j1;
+    const C c = lds[i];
+    const int c0 = 2 * j, c1 = 2 * j + 1;
+    if (c0 >= a.c_lo && c0 < a.c_hi) y[c0 + a.m_off] = c.x * a.scale * a.winv[c0];
+    if (c1 >= a.c_lo && c1 < a.c_hi) y[c1 + a.m_off] = c.y * a.scale * a.winv[c1];
+  }
+}
+
 // ---------------------------------------------------------------- precompute: P5
 // One workgroup per row: F of a windowed row (float64), half spectrum out.
 __global__ __launch_bounds__(FFT_MAX_THREADS) void row_fft_kernel(RowFftArgs a, FftPlan fp) {
@@ -458,6 +538,10 @@ void init_fft_kernels(size_t max_lds) {
   set_lds(exec_fft_kernel<float>, max_lds);
   set_lds(inv_fft_kernel<double>, max_lds);
   set_lds(inv_fft_kernel<float>, max_lds);
+  set_lds(inv_fft4_col_kernel<double>, max_lds);
+  set_lds(inv_fft4_col_kernel<float>, max_lds);
+  set_lds(inv_fft4_row_kernel<double>, max_lds);
+  set_lds(inv_fft4_row_kernel<float>, max_lds);
   set_lds(row_fft_kernel, max_lds);
   set_lds(exec_fft_multi_kernel<double, false, 512>, max_lds);
   set_lds(exec_fft_multi_kernel<float, false, 512>, max_lds);
@@ -546,5 +630,31 @@ template void launch_exec_fft<double>(const ExecFftArgs<double>&, const FftPlan&
 template void launch_exec_fft<float>(const ExecFftArgs<float>&, const FftPlan&, hipStream_t);
 template void launch_inv_fft<double>(const InvFftArgs<double>&, const FftPlan&, hipStream_t);
 template void launch_inv_fft<float>(const InvFftArgs<float>&, const FftPlan&, hipStream_t);
+
+// threads for pts points of batched transforms (FFT_EPT per thread)
+static int batch_threads(int pts) {
+  int t = (pts + FFT_EPT - 1) / FFT_EPT;
+  t = ((t + 63) / 64) * 64;
+  return t < 64 ? 64 : t;
+}
+
+template <typename T>
+void launch_inv_fft4(const InvFft4Args<T>& a, hipStream_t s) {
+  const int p1 = a.P2 << a.lb1, p2 = a.P1 << a.lb2;
+  if (p1 > FFT_EPT * FFT_MAX_THREADS || p2 > FFT_EPT * FFT_MAX_THREADS)
+    throw Error(SPT_E_INVALID_ARG, "four-step inverse transform groups exceed one workgroup");
+  const int64_t g1 = (int64_t)a.R * ((a.P1 + (1 << a.lb1) - 1) >> a.lb1);
+  const int64_t g2 = (int64_t)a.R * ((a.P2 + (1 << a.lb2) - 1) >> a.lb2);
+  if (g1 > INT32_MAX || g2 > INT32_MAX) throw Error(SPT_E_INVALID_ARG, "too many right-hand sides");
+  hipLaunchKernelGGL(inv_fft4_col_kernel<T>, dim3((unsigned)g1), dim3(batch_threads(p1)),
+                     sizeof(cplx_t<T>) * (size_t)p1, s, a);
+  SPT_HIP(hipGetLastError());
+  hipLaunchKernelGGL(inv_fft4_row_kernel<T>, dim3((unsigned)g2), dim3(batch_threads(p2)),
+                     sizeof(cplx_t<T>) * (size_t)p2, s, a);
+  SPT_HIP(hipGetLastError());
+}
+
+template void launch_inv_fft4<double>(const InvFft4Args<double>&, hipStream_t);
+template void launch_inv_fft4<float>(const InvFft4Args<float>&, hipStream_t);
 
 }  // namespace spt

@@ -322,6 +322,60 @@ def test_transposed_fp64(spt, fam, N, eps, kw, R):
     assert rel_rows(Y32, Y) <= reduced_tol(p)
 
 
+@pytest.mark.parametrize("fam,N,kw", [
+    ("legendre", 7000, {}), ("jacobi", 9000, dict(alpha=-0.5, beta=-0.5))])
+def test_transposed_four_step_fp64(spt, monkeypatch, fam, N, kw):
+    """The four-step inverse transform of the transposed product, forced on
+    first blocks that also fit one workgroup (Legendre 7000: P = 4374, Jacobi
+    9000: P = 5625, odd): oracle parity, and agreement with the
+    single-workgroup transform."""
+    from oracle import transposed
+    say("transposed four-step", fam, N, kw)
+    f = oracle_family(fam, N, kw.get("alpha", 0.0), kw.get("beta", 0.0))
+    p = spt.Plan(fam, N, 1e-7, mode=spt.MODE_ROW, nodes=f.nodes(), **kw).precompute()
+    assert p.blocks()[0][0] // 2 > 4096
+    F = workloads.rhs("normal", 5, N, 77)
+    import torch
+    Y1 = to_host(p.execute_transposed(to_dev(F, torch.float64), prec=spt.F64))
+    monkeypatch.setenv("SPT_INV_FFT_FOUR", "1")
+    Y4 = to_host(p.execute_transposed(to_dev(F, torch.float64), prec=spt.F64))
+    C = oracle_compressed(fam, N, 1e-7, 1e-2, 32, kw.get("alpha", 0.0), kw.get("beta", 0.0))
+    Yt = transposed.execute(C, F)
+    e_c, e_1 = rel_rows(Y4, Yt), rel_rows(Y4, Y1)
+    say("  four-step vs oracle-T %.3e  vs one workgroup %.3e" % (e_c, e_1))
+    assert e_c <= 1e-12 and e_1 <= 1e-13
+    Y32 = to_host(p.execute_transposed(to_dev(F, torch.float32), prec=spt.F32))
+    assert rel_rows(Y32, Y4) <= reduced_tol(p)
+
+
+def test_long_block_transposed(spt):
+    """Transposed product with a first block longer than one workgroup's FFT
+    (P = 15000 > 10240, four steps): it is the adjoint of the forward product
+    over the same compressed blocks, <A_c x, f> = <x, A_c^T f>, to rounding;
+    sampled degrees against the direct A^T f; F32 against F64."""
+    from oracle import direct
+    import torch
+    say("long block transposed", LONG_N)
+    fam = oracle_family("legendre", LONG_N)
+    p = spt.Plan("legendre", LONG_N, 1e-7, mode=spt.MODE_ROW, nodes=fam.nodes()).precompute()
+    assert p.blocks()[0][0] // 2 > 10240
+    X = workloads.rhs("normal", 3, LONG_N, 81)
+    F = workloads.rhs("normal", 3, LONG_N, 82)
+    Yf = run(spt, p, X, spt.F64)
+    Yt = to_host(p.execute_transposed(to_dev(F, torch.float64), prec=spt.F64))
+    lhs, rhs = np.sum(Yf * F, axis=1), np.sum(X * Yt, axis=1)
+    scale = np.linalg.norm(Yf, axis=1) * np.linalg.norm(F, axis=1)
+    e_adj = np.max(np.abs(lhs - rhs) / scale)
+    cols = np.arange(5, LONG_N, 97)
+    Yd = direct.matvec_transposed(fam, F, cols=cols)
+    e_d = rel_rows(Yt[:, cols], Yd)
+    say("  adjoint %.3e  vs direct (sampled degrees) %.3e" % (e_adj, e_d))
+    assert e_adj <= 1e-12
+    assert e_d <= 1e-6
+    Y32 = to_host(p.execute_transposed(to_dev(F, torch.float32), prec=spt.F32))
+    assert rel_rows(Y32, Yt) <= reduced_tol(p)
+
+
 # ------------------------------------------------------------------ batched execution
 def test_batched_matches_single_plans(spt):
     import torch
