@@ -239,9 +239,10 @@ def main():
              "split_bf16": (spt.SPLIT_BF16, X32, Ys)}
     res = {}
 
-    def measure(pl, prec, X, Y):
+    def measure(pl, prec, X, Y, transposed=False):
         # steps dealt to the streams in turn: each step is a whole execute of
         # the 64 right-hand sides into its stream's output buffer
+        run = pl.execute_transposed if transposed else pl.execute
         streams = [torch.cuda.Stream() for _ in range(args.streams)]
         Ys = [Y] + [torch.empty_like(Y) for _ in range(args.streams - 1)]
         state = {"i": 0}
@@ -250,18 +251,18 @@ def main():
             j = state["i"] % args.streams
             state["i"] += 1
             with torch.cuda.stream(streams[j]):
-                pl.execute(X, Ys[j], prec=prec)
+                run(X, Ys[j], prec=prec)
 
         torch.cuda.synchronize()
         t = timed_steps(step, args.steps, args.warmup)
-        t1 = timed_steps(lambda: pl.execute(X, Y, prec=prec), args.steps, args.warmup)
+        t1 = timed_steps(lambda: run(X, Y, prec=prec), args.steps, args.warmup)
         r = {"ms_per_step": 1e3 * t / args.steps, "value": R * args.steps / t,
              "streams": args.streams,
              "one_stream": {"ms_per_step": 1e3 * t1 / args.steps, "value": R * args.steps / t1}}
         # kernel times with HIP events on the execute stream
         spt.profile_begin()
         for _ in range(args.steps):
-            pl.execute(X, Y, prec=prec)
+            run(X, Y, prec=prec)
         torch.cuda.synchronize()
         st = spt.profile_end()
         r["kernel_ms"] = {k: v[0] / max(v[1], 1) for k, v in st.items() if v[1]}
@@ -278,6 +279,13 @@ def main():
         y = Y.double().cpu().numpy()
         err[name] = float(np.max(np.linalg.norm(y - y64, axis=1) / np.linalg.norm(y64, axis=1)))
     log("errors vs f64", err)
+    # the transposed product (Alg. 2/4) on the same plan and inputs
+    res_t = {}
+    for name in ("f64", "f32"):
+        prec, X, Y = paths[name]
+        log("time transposed", name)
+        res_t[name] = measure(plan, prec, X, torch.empty_like(Y), transposed=True)
+        log("transposed", name, res_t[name])
     # the one-launch persistent executor on the same workload, for comparison
     pers = spt.Plan("legendre", N, w["eps"], executor=spt.EXECUTOR_PERSISTENT).precompute()
     log("time split_bf16, persistent executor")
@@ -328,6 +336,9 @@ def main():
                                            "ms_per_step": res_pers["ms_per_step"],
                                            "one_stream": res_pers["one_stream"],
                                            "kernel_ms": res_pers["kernel_ms"]},
+        "transposed": {k: {"value": v["value"], "ms_per_step": v["ms_per_step"],
+                           "one_stream": v["one_stream"], "kernel_ms": v["kernel_ms"]}
+                       for k, v in res_t.items()},
         "split_vs_f64": split["value"] / res["f64"]["value"],
         "rel_err_vs_f64": err,
         "roofline": roof,

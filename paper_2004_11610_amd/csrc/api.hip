@@ -80,6 +80,8 @@ struct DevBlock {
   DevBuf winv64, winv32, tw64, post64, post32, posttw;
   DevBuf ptw64, ptw32;  // pass twiddles of the fused FFT (FftDesc::ptw)
   DevBuf k0, kw, off;   // per tile
+  DevBuf tcseg, tcent;  // transposed product: row tiles per TCHUNK spectrum columns
+  int n_tseg = 0;
   DevBuf val64, val32;  // tile boxes
   DevBuf valbf, soff;   // pre-split tile boxes of the split-bf16 path, their offsets
   int64_t nnz = 0, stored = 0;
@@ -726,6 +728,39 @@ int64_t build_block(spt_plan_t plan, DevBlock& B, hipStream_t s, size_t lds_max,
   upload(B.k0, B.h_k0, s);
   upload(B.kw, B.h_kw, s);
   upload(B.off, B.h_off, s);
+  {
+    // the row tiles whose boxes meet each TCHUNK columns of the half spectrum
+    const int nch = (P + 1 + TCHUNK - 1) / TCHUNK;
+    std::vector<int32_t> ptr(nch + 1, 0);
+    auto chunks = [&](int64_t t, int& c0, int& c1) {
+      c0 = B.h_k0[t] / TCHUNK;
+      c1 = std::min(nch - 1, (B.h_k0[t] + B.h_kw[t] - 1) / TCHUNK);
+    };
+    for (int64_t t = 0; t < ntiles; ++t) {
+      if (B.h_kw[t] <= 0) continue;
+      int c0, c1;
+      chunks(t, c0, c1);
+      for (int c = c0; c <= c1; ++c) ++ptr[c + 1];
+    }
+    for (int c = 0; c < nch; ++c) ptr[c + 1] += ptr[c];
+    std::vector<TChunkEnt> ents(std::max(ptr[nch], 1));
+    std::vector<int32_t> pos(ptr.begin(), ptr.end() - 1);
+    for (int64_t t = 0; t < ntiles; ++t) {
+      if (B.h_kw[t] <= 0) continue;
+      int c0, c1;
+      chunks(t, c0, c1);
+      for (int c = c0; c <= c1; ++c)
+        ents[pos[c]++] = TChunkEnt{B.h_off[t], (int32_t)t, B.h_k0[t], B.h_kw[t], 0};
+    }
+    std::vector<int4> segs;
+    for (int c = 0; c < nch; ++c)
+      for (int e = ptr[c]; e < ptr[c + 1]; e += TSEG)
+        segs.push_back(int4{c, e, std::min(e + TSEG, ptr[c + 1]), ptr[c + 1] - ptr[c] <= TSEG});
+    B.n_tseg = (int)segs.size();
+    if (segs.empty()) segs.push_back(int4{0, 0, 0, 0});
+    upload(B.tcseg, segs, s);
+    upload(B.tcent, ents, s);
+  }
   const bool want64 = plan->prepared & (1u << SPT_F64);
   const bool want32 = plan->prepared & ((1u << SPT_F32) | (1u << SPT_SPLIT_BF16));
   B.val64.reset();
@@ -1312,13 +1347,6 @@ void execute_staged_t(spt_plan_t plan, const T* X, T* Y, int64_t R, int prec, hi
   staged(SPT_STAGE_SPMM, s, [&] { product(s); });
 }
 
-template <typename T>
-__global__ void zero_kernel(T* p, int64_t n) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x)
-    p[i] = T(0);
-}
-
 // Blocks of the transposed product whose inverse transform runs in four steps:
 // those longer than one workgroup's FFT, and (diagnostics: SPT_INV_FFT_FOUR=1)
 // every block with a four-step geometry.
@@ -1337,6 +1365,13 @@ int inv_four_lb(int n, int count) {
 }
 
 template <typename T>
+__global__ void zero_kernel(T* p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = T(0);
+}
+
+template <typename T>
 void execute_transposed_t(spt_plan_t plan, const T* F, T* Y, int64_t R, hipStream_t s) {
   using C = cplx_t<T>;
   for (auto& B : plan->blk)
@@ -1348,6 +1383,8 @@ void execute_transposed_t(spt_plan_t plan, const T* F, T* Y, int64_t R, hipStrea
   for (auto& B : plan->blk) per += B->P + 1;
   // four-step intermediates after the half spectra (w_per_rhs)
   C* wbuf = plan->work->as<C>() + per * R;
+  // the half spectra are sums of atomic adds: zeroed first, by a kernel (a
+  // memset node would not replay correctly in a captured graph)
   const int64_t nz = 2 * per * R;
   if (nz > 0) {
     const int nb = (int)std::min<int64_t>((nz + 255) / 256, 8192);
@@ -1358,14 +1395,13 @@ void execute_transposed_t(spt_plan_t plan, const T* F, T* Y, int64_t R, hipStrea
   for (auto& Bp : plan->blk) {
     DevBlock& B = *Bp;
     SpmmTArgs<T> ta{};
-    ta.k0 = B.k0.as<int32_t>();
-    ta.kw = B.kw.as<int32_t>();
-    ta.off = B.off.as<int64_t>();
+    ta.segs = B.tcseg.as<int4>();
+    ta.ents = B.tcent.as<TChunkEnt>();
     ta.val = std::is_same<T, double>::value ? (const C*)B.val64.p : (const C*)B.val32.p;
     ta.u = u;
     ta.ldu = B.P + 1;
     ta.P = B.P;
-    ta.n_tiles = plan->n_tiles;
+    ta.n_segs = B.n_tseg;
     ta.F = F;
     ta.R = (int)R;
     ta.N = plan->N;

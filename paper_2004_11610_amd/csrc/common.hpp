@@ -300,15 +300,23 @@ void launch_exec_fft_multi_split(const FftDesc<float>* descs, int nblk, int thre
                                  int64_t N, hipStream_t s);
 
 // transposed banded product: u_i = A_i^T f (half spectrum), per block
+// The transposed product gathers by columns of the half spectrum: the row
+// tiles whose boxes meet columns [TCHUNK c, TCHUNK c + TCHUNK) of a block.
+constexpr int TCHUNK = 32;
+constexpr int TSEG = 8;    // row tiles per segment (one workgroup each)
+struct TChunkEnt {
+  int64_t off;             // the tile's first stored value
+  int32_t tile, k0, kw, pad;
+};
+
 template <typename T>
 struct SpmmTArgs {
-  const int32_t* k0;
-  const int32_t* kw;
-  const int64_t* off;
+  const int4* segs;        // n_segs segments: {chunk c, first entry, end entry, only segment of c}
+  const TChunkEnt* ents;   // per chunk, the row tiles meeting it, split into segments
   const cplx_t<T>* val;
-  cplx_t<T>* u;       // R x ldu, zeroed then accumulated
-  int ldu, P, n_tiles;
-  const T* F;         // R x N
+  cplx_t<T>* u;            // R x ldu, zeroed; a chunk's only segment stores, several add
+  int ldu, P, n_segs;
+  const T* F;              // R x N
   int R;
   int64_t N;
 };

@@ -26,8 +26,6 @@ namespace {
 
 using namespace spmmcore;
 
-constexpr int WAVES_PER_WG = 4;
-
 // ---------------------------------------------------------------- matrix-core product
 // One workgroup = one row tile (16 rows) x 64 right-hand sides; wave w owns the
 // right-hand sides 16w .. 16w+15, i.e. one 16 x 16 output tile, accumulated by
@@ -478,37 +476,118 @@ __global__ __launch_bounds__(256) void spmm_presplit_items_kernel(SpmmSplitBatch
 }
 
 // ---------------------------------------------------------------- transposed
-// u[r][k] = sum_n Add[n][k] f[r][n] over the half spectrum (c_k removed), one
-// wave per row tile, lane = right-hand side, accumulated with atomics since
-// neighbouring tiles share columns.
+// u[r][k] = c'_k sum_n Add[n][k] f[r][n] over the half spectrum (c'_k = 1 at
+// k = 0 and P, else 1/2: the c_k folded into the stored values taken out).
+// By columns: the row tiles whose boxes meet the columns [TCHUNK c, TCHUNK c +
+// TCHUNK) are listed at precompute and split into segments of at most TSEG
+// tiles.  Workgroup (s, g) takes segment s for the right-hand sides 64 g ..
+// 64 g + 63, staging each tile's f values (64 x 16) and box columns (16 x TCHUNK)
+// in LDS (the next tile's are requested before the current one is used).  The
+// only segment of a chunk stores its sums; several add theirs to the zeroed u
+// with one atomic per value: a short block's few columns gather thousands of
+// tiles, spread over many workgroups.  Thread:
+// columns 2 cg, 2 cg + 1 and right-hand sides 4 rq .. 4 rq + 3 of the chunk.
 template <typename T>
-__global__ __launch_bounds__(64 * WAVES_PER_WG) void spmm_transposed_kernel(SpmmTArgs<T> a) {
+__global__ __launch_bounds__(256) void spmm_transposed_kernel(SpmmTArgs<T> a) {
   using C = cplx_t<T>;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int tile = blockIdx.x * WAVES_PER_WG + wave;
-  if (tile >= a.n_tiles) return;
-  const int r = blockIdx.y * 64 + lane;
-  if (r >= a.R) return;
-  const int64_t n0 = (int64_t)tile * TILE_ROWS;
-  T f[TILE_ROWS];
-  const T* __restrict__ fr = a.F + (int64_t)r * a.N;
+  static_assert(TCHUNK == 32, "thread layout: 16 column pairs x 16 groups of 4 right-hand sides");
+  constexpr int FPT = 64 * TILE_ROWS / 256;      // f values per thread and tile
+  constexpr int APT = TILE_ROWS * TCHUNK / 256;  // box values per thread and tile
+  constexpr int EB = 256;                        // list entries staged at a time
+  __shared__ T fs[64][TILE_ROWS + 1];
+  __shared__ C as[TILE_ROWS][TCHUNK];
+  __shared__ TChunkEnt ents[EB];
+  const int tid = threadIdx.x;
+  const int4 seg = a.segs[blockIdx.x];
+  const int r0 = blockIdx.y * 64;
+  const int kc = seg.x * TCHUNK;
+  const int cg = tid & 15, rq = tid >> 4;
+  C acc[4][2];
 #pragma unroll
-  for (int q = 0; q < TILE_ROWS; ++q) f[q] = (n0 + q < a.N) ? fr[n0 + q] : T(0);
-  const int k0 = a.k0[tile], kw = a.kw[tile];
-  const C* __restrict__ val = a.val + a.off[tile];
-  C* __restrict__ u = a.u + (int64_t)r * a.ldu;
-  for (int kk = 0; kk < kw; ++kk) {
-    T sr = T(0), si = T(0);
+  for (int j = 0; j < 4; ++j) acc[j][0] = acc[j][1] = C{T(0), T(0)};
+  T fr[FPT];
+  C ar[APT];
+  auto fetch = [&](const TChunkEnt& e) {
+    const int64_t n0 = (int64_t)e.tile * TILE_ROWS;
 #pragma unroll
-    for (int q = 0; q < TILE_ROWS; ++q) {
-      const C av = val[kk * TILE_ROWS + q];
-      sr += av.x * f[q];
-      si += av.y * f[q];
+    for (int i = 0; i < FPT; ++i) {
+      const int idx = tid + i * 256, r = r0 + (idx >> 4);
+      const int64_t n = n0 + (idx & 15);
+      fr[i] = (r < a.R && n < a.N) ? gload(a.F + (int64_t)r * a.N + n) : T(0);
     }
-    const int k = k0 + kk;
-    const T ck = (k == 0 || k == a.P) ? T(1) : T(0.5);
-    atomicAdd(&u[k].x, sr * ck);
-    atomicAdd(&u[k].y, si * ck);
+    const C* __restrict__ val = a.val + e.off;
+#pragma unroll
+    for (int i = 0; i < APT; ++i) {
+      const int idx = tid + i * 256;
+      const int kk = kc + (idx >> 4) - e.k0;
+      ar[i] = (kk >= 0 && kk < e.kw) ? gload(val + (int64_t)kk * TILE_ROWS + (idx & 15))
+                                     : C{T(0), T(0)};
+    }
+  };
+  const int e_begin = seg.y, e_end = seg.z;
+  for (int b0 = e_begin; b0 < e_end; b0 += EB) {
+    const int nb = min(EB, e_end - b0);
+    __syncthreads();
+    if (tid < nb) ents[tid] = a.ents[b0 + tid];
+    __syncthreads();
+    fetch(ents[0]);
+    for (int i = 0; i < nb; ++i) {
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < FPT; ++j) {
+        const int idx = tid + j * 256;
+        fs[idx >> 4][idx & 15] = fr[j];
+      }
+#pragma unroll
+      for (int j = 0; j < APT; ++j) {
+        const int idx = tid + j * 256;
+        as[idx & 15][idx >> 4] = ar[j];
+      }
+      __syncthreads();
+      if (i + 1 < nb) fetch(ents[i + 1]);
+      // the tile's 16 rows summed first, then added (running sums stay short)
+      C part[4][2];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) part[j][0] = part[j][1] = C{T(0), T(0)};
+#pragma unroll
+      for (int q = 0; q < TILE_ROWS; ++q) {
+        const C a0 = as[q][2 * cg], a1 = as[q][2 * cg + 1];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const T fv = fs[4 * rq + j][q];
+          part[j][0].x += a0.x * fv;
+          part[j][0].y += a0.y * fv;
+          part[j][1].x += a1.x * fv;
+          part[j][1].y += a1.y * fv;
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+#pragma unroll
+        for (int c2 = 0; c2 < 2; ++c2) {
+          acc[j][c2].x += part[j][c2].x;
+          acc[j][c2].y += part[j][c2].y;
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int r = r0 + 4 * rq + j;
+    if (r >= a.R) continue;
+#pragma unroll
+    for (int c2 = 0; c2 < 2; ++c2) {
+      const int k = kc + 2 * cg + c2;
+      if (k > a.P) continue;
+      const T ck = (k == 0 || k == a.P) ? T(1) : T(0.5);
+      C* __restrict__ uk = a.u + (int64_t)r * a.ldu + k;
+      if (seg.w) {
+        *uk = C{acc[j][c2].x * ck, acc[j][c2].y * ck};
+      } else {
+        atomicAdd(&uk->x, acc[j][c2].x * ck);
+        atomicAdd(&uk->y, acc[j][c2].y * ck);
+      }
+    }
   }
 }
 
@@ -530,10 +609,6 @@ __global__ __launch_bounds__(256) void tail_transposed_kernel(const T* __restric
     __syncthreads();
   }
   if (threadIdx.x == 0) Y[(int64_t)r * N + m] = part[0];
-}
-
-dim3 spmm_grid(int n_tiles, int R) {
-  return dim3((n_tiles + WAVES_PER_WG - 1) / WAVES_PER_WG, (R + 63) / 64);
 }
 
 }  // namespace
@@ -599,8 +674,10 @@ void launch_spmm_split_bf16(const SpmmArgs<float>& a, hipStream_t s) {
 
 template <typename T>
 void launch_spmm_transposed(const SpmmTArgs<T>& a, hipStream_t s) {
-  hipLaunchKernelGGL(spmm_transposed_kernel<T>, spmm_grid(a.n_tiles, a.R),
-                     dim3(64 * WAVES_PER_WG), 0, s, a);
+  if (a.R > 65535 * 64) throw Error(SPT_E_INVALID_ARG, "too many right-hand sides");
+  if (a.n_segs <= 0) return;
+  hipLaunchKernelGGL(spmm_transposed_kernel<T>, dim3(a.n_segs, (a.R + 63) / 64), dim3(256), 0, s,
+                     a);
   SPT_HIP(hipGetLastError());
 }
 
