@@ -80,8 +80,11 @@ struct DevBlock {
   DevBuf winv64, winv32, tw64, post64, post32, posttw;
   DevBuf ptw64, ptw32;  // pass twiddles of the fused FFT (FftDesc::ptw)
   DevBuf k0, kw, off;   // per tile
-  DevBuf tcseg, tcent;  // transposed product: row tiles per TCHUNK spectrum columns
-  int n_tseg = 0;
+  bool big = false;  // the transform does not fit one workgroup (four steps)
+  // transposed product: the segments of row tiles per TCHUNK spectrum columns
+  std::vector<int4> h_tseg;
+  std::vector<TChunkEnt> h_tent;
+  std::vector<int> h_tempty;  // chunks that no tile meets (their u is zero)
   DevBuf val64, val32;  // tile boxes
   DevBuf valbf, soff;   // pre-split tile boxes of the split-bf16 path, their offsets
   int64_t nnz = 0, stored = 0;
@@ -149,6 +152,11 @@ struct spt_plan {
   // windowed split-bf16 product: WinMeta per (tile group, block); used when
   // every group's windows fit the LDS of a workgroup
   spt::DevBuf winmeta;
+  spt::DevBuf tseg, tent, tblk;  // the transposed product's segments, tile lists, blocks
+  spt::DevBuf tred;              // its chunks of several segments
+  int n_tseg = 0, n_tred = 0, n_tslot = 0;
+  spt::DevBuf invdesc64, invdesc32;  // its single-workgroup inverse transforms
+  int n_inv = 0, inv_threads = 64, inv_maxP = 1;
   int n_groups = 0;
   size_t win_lds = 0;
   int64_t win_cols = 0;
@@ -429,6 +437,7 @@ int64_t build_block(spt_plan_t plan, DevBlock& B, hipStream_t s, size_t lds_max,
   B.P = P;
   // rows whose transform does not fit one workgroup's LDS go by four steps
   const bool big = P > FUSED_MAX_P || (size_t)P * sizeof(double2) > lds_max;
+  B.big = big;
   if (!big) {
     B.fft = make_fft_plan(P);
     B.half = P >= FUSED_HALF_MIN_P && P % 2 == 0 ? 1 : 0;
@@ -743,7 +752,7 @@ int64_t build_block(spt_plan_t plan, DevBlock& B, hipStream_t s, size_t lds_max,
       for (int c = c0; c <= c1; ++c) ++ptr[c + 1];
     }
     for (int c = 0; c < nch; ++c) ptr[c + 1] += ptr[c];
-    std::vector<TChunkEnt> ents(std::max(ptr[nch], 1));
+    std::vector<TChunkEnt> ents(ptr[nch]);
     std::vector<int32_t> pos(ptr.begin(), ptr.end() - 1);
     for (int64_t t = 0; t < ntiles; ++t) {
       if (B.h_kw[t] <= 0) continue;
@@ -752,14 +761,15 @@ int64_t build_block(spt_plan_t plan, DevBlock& B, hipStream_t s, size_t lds_max,
       for (int c = c0; c <= c1; ++c)
         ents[pos[c]++] = TChunkEnt{B.h_off[t], (int32_t)t, B.h_k0[t], B.h_kw[t], 0};
     }
-    std::vector<int4> segs;
+    B.h_tseg.clear();
+    B.h_tempty.clear();
+    for (int c = 0; c < nch; ++c)
+      if (ptr[c + 1] == ptr[c]) B.h_tempty.push_back(c);
     for (int c = 0; c < nch; ++c)
       for (int e = ptr[c]; e < ptr[c + 1]; e += TSEG)
-        segs.push_back(int4{c, e, std::min(e + TSEG, ptr[c + 1]), ptr[c + 1] - ptr[c] <= TSEG});
-    B.n_tseg = (int)segs.size();
-    if (segs.empty()) segs.push_back(int4{0, 0, 0, 0});
-    upload(B.tcseg, segs, s);
-    upload(B.tcent, ents, s);
+        B.h_tseg.push_back(
+            int4{c, e, std::min(e + TSEG, ptr[c + 1]), ptr[c + 1] - ptr[c] <= TSEG ? 1 : 0});
+    B.h_tent = std::move(ents);
   }
   const bool want64 = plan->prepared & (1u << SPT_F64);
   const bool want32 = plan->prepared & ((1u << SPT_F32) | (1u << SPT_SPLIT_BF16));
@@ -848,6 +858,8 @@ int64_t w_per_rhs(spt_plan_t plan) {
     if (B->four) n += B->P;
   return n;
 }
+// the transposed product's partial sums, after the four-step intermediates
+int64_t t_per_rhs(spt_plan_t plan) { return (int64_t)plan->n_tslot * TCHUNK; }
 
 int engine_of(int prec) { return prec == SPT_F64 ? 0 : prec == SPT_F32 ? 1 : 2; }
 
@@ -1135,6 +1147,73 @@ void build_fft_descs(spt_plan_t plan, hipStream_t s) {
   upload(plan->tilemeta_bf, meta_bf, s);
   upload(plan->spmmblk_bf, bbf, s);
   build_windows(plan, s);
+  // the transposed product's segments of every block, in one list; the
+  // segments of chunks with several get slots of partial sums
+  static_assert(MAX_BLOCKS <= (1 << TSEG_BLOCK_BITS), "segment block field");
+  std::vector<int4> tseg, tred;
+  std::vector<TChunkEnt> tent;
+  std::vector<TBlkInfo> tblk;
+  int64_t uoff = 0;
+  int slots = 0;
+  for (int b = 0; b < nblk; ++b) {
+    const DevBlock& B = *plan->blk[b];
+    const int base = (int)tent.size();
+    for (size_t i = 0; i < B.h_tseg.size(); ++i) {
+      const int4& g = B.h_tseg[i];
+      if (g.w) {
+        tseg.push_back(int4{g.x, g.y + base, g.z + base, (b << 1) | 1});
+        continue;
+      }
+      if (i == 0 || B.h_tseg[i - 1].x != g.x) tred.push_back(int4{b, g.x, slots, 0});
+      ++tred.back().w;
+      tseg.push_back(int4{g.x, g.y + base, g.z + base, (slots++ << (TSEG_BLOCK_BITS + 1)) | (b << 1)});
+    }
+    for (int c : B.h_tempty) tred.push_back(int4{b, c, 0, 0});  // no slots: zeros
+    tent.insert(tent.end(), B.h_tent.begin(), B.h_tent.end());
+    tblk.push_back(TBlkInfo{B.val64.p, B.val32.p, uoff, B.P, 0});
+    uoff += B.P + 1;
+  }
+  if ((int64_t)slots >= ((int64_t)1 << (31 - TSEG_BLOCK_BITS - 1)))
+    throw Error(SPT_E_UNSUPPORTED, "too many transposed-product segments");
+  plan->n_tseg = (int)tseg.size();
+  plan->n_tred = (int)tred.size();
+  plan->n_tslot = slots;
+  if (tseg.empty()) tseg.push_back(int4{0, 0, 0, 0});
+  if (tred.empty()) tred.push_back(int4{0, 0, 0, 0});
+  upload(plan->tred, tred, s);
+  if (tent.empty()) tent.push_back(TChunkEnt{});
+  if (tblk.empty()) tblk.push_back(TBlkInfo{});
+  upload(plan->tseg, tseg, s);
+  upload(plan->tent, tent, s);
+  upload(plan->tblk, tblk, s);
+  // the single-workgroup inverse transforms of the transposed product
+  std::vector<InvFftDesc<double>> inv64;
+  std::vector<InvFftDesc<float>> inv32;
+  plan->inv_threads = 64;
+  plan->inv_maxP = 1;
+  uoff = 0;
+  for (int b = 0; b < nblk; ++b) {
+    const DevBlock& B = *plan->blk[b];
+    if (!B.big) {
+      const double sc = 1.0 / std::sqrt((double)B.g.L);
+      inv64.push_back(InvFftDesc<double>{B.winv64.as<double>(), B.tw64.as<double2>(),
+                                         B.post64.as<double2>(), uoff, B.P, (int)B.g.m_off,
+                                         (int)B.g.c_lo, (int)B.g.c_hi, sc, B.fft});
+      inv32.push_back(InvFftDesc<float>{B.winv32.as<float>(), B.tw64.as<double2>(),
+                                        B.post32.as<float2>(), uoff, B.P, (int)B.g.m_off,
+                                        (int)B.g.c_lo, (int)B.g.c_hi, (float)sc, B.fft});
+      plan->inv_threads = std::max(plan->inv_threads, B.fft.threads);
+      plan->inv_maxP = std::max(plan->inv_maxP, B.P);
+    }
+    uoff += B.P + 1;
+  }
+  plan->n_inv = (int)inv64.size();
+  if (inv64.empty()) {
+    inv64.push_back(InvFftDesc<double>{});
+    inv32.push_back(InvFftDesc<float>{});
+  }
+  upload(plan->invdesc64, inv64, s);
+  upload(plan->invdesc32, inv32, s);
 }
 
 void precompute(spt_plan_t plan, hipStream_t s) {
@@ -1213,7 +1292,7 @@ void ensure_work(spt_plan_t plan, int64_t R, hipStream_t s) {
     w->stream = s;
   }
   plan->work = &w->buf;
-  const int64_t per = z_per_rhs(plan) + w_per_rhs(plan);
+  const int64_t per = z_per_rhs(plan) + w_per_rhs(plan) + t_per_rhs(plan);
   // complex float64 spectra (and four-step intermediates), or the three
   // bfloat16-pair planes of the split-bf16 path
   const size_t bytes =
@@ -1350,11 +1429,11 @@ void execute_staged_t(spt_plan_t plan, const T* X, T* Y, int64_t R, int prec, hi
 // Blocks of the transposed product whose inverse transform runs in four steps:
 // those longer than one workgroup's FFT, and (diagnostics: SPT_INV_FFT_FOUR=1)
 // every block with a four-step geometry.
-bool inv_four_step(const DevBlock& B) {
-  if (B.P > FUSED_MAX_P) return true;
+bool inv_four_forced() {
   const char* e = std::getenv("SPT_INV_FFT_FOUR");
-  return B.four && e && e[0] == '1';
+  return e && e[0] == '1';
 }
+bool inv_four_step(const DevBlock& B) { return B.big || (B.four && inv_four_forced()); }
 
 // log2 of the transforms of n points per workgroup of a four-step inverse
 // pass (at most 64, at most `count`, about 4096 points per workgroup)
@@ -1362,13 +1441,6 @@ int inv_four_lb(int n, int count) {
   int lb = 0;
   while (lb < 6 && (n << (lb + 1)) <= 4096 && (2 << lb) <= count) ++lb;
   return lb;
-}
-
-template <typename T>
-__global__ void zero_kernel(T* p, int64_t n) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x)
-    p[i] = T(0);
 }
 
 template <typename T>
@@ -1383,29 +1455,33 @@ void execute_transposed_t(spt_plan_t plan, const T* F, T* Y, int64_t R, hipStrea
   for (auto& B : plan->blk) per += B->P + 1;
   // four-step intermediates after the half spectra (w_per_rhs)
   C* wbuf = plan->work->as<C>() + per * R;
-  // the half spectra are sums of atomic adds: zeroed first, by a kernel (a
-  // memset node would not replay correctly in a captured graph)
-  const int64_t nz = 2 * per * R;
-  if (nz > 0) {
-    const int nb = (int)std::min<int64_t>((nz + 255) / 256, 8192);
-    hipLaunchKernelGGL(zero_kernel<T>, dim3(nb), dim3(256), 0, s, (T*)plan->work->p, nz);
-    SPT_HIP(hipGetLastError());
-  }
   C* u = plan->work->as<C>();
+  SpmmTArgs<T> ta{};
+  ta.segs = plan->tseg.as<int4>();
+  ta.ents = plan->tent.as<TChunkEnt>();
+  ta.blk = plan->tblk.as<TBlkInfo>();
+  ta.u = u;
+  ta.part = u + (z_per_rhs(plan) + w_per_rhs(plan)) * R;
+  ta.red = plan->tred.as<int4>();
+  ta.n_segs = plan->n_tseg;
+  ta.n_red = plan->n_tred;
+  ta.F = F;
+  ta.R = (int)R;
+  ta.N = plan->N;
+  staged(SPT_STAGE_SPMM_T, s, [&] { launch_spmm_transposed<T>(ta, s); });
+  // the blocks that fit one workgroup in one launch (per block when four
+  // steps are forced, a diagnostic)
+  const bool multi = !inv_four_forced();
+  if (multi && plan->n_inv > 0)
+    staged(SPT_STAGE_INV_FFT, s, [&] {
+      launch_inv_fft_multi<T>(
+          std::is_same<T, double>::value ? (const InvFftDesc<T>*)plan->invdesc64.p
+                                         : (const InvFftDesc<T>*)plan->invdesc32.p,
+          plan->n_inv, plan->inv_threads, sizeof(C) * (size_t)plan->inv_maxP, u, Y, (int)R,
+          plan->N, s);
+    });
   for (auto& Bp : plan->blk) {
     DevBlock& B = *Bp;
-    SpmmTArgs<T> ta{};
-    ta.segs = B.tcseg.as<int4>();
-    ta.ents = B.tcent.as<TChunkEnt>();
-    ta.val = std::is_same<T, double>::value ? (const C*)B.val64.p : (const C*)B.val32.p;
-    ta.u = u;
-    ta.ldu = B.P + 1;
-    ta.P = B.P;
-    ta.n_segs = B.n_tseg;
-    ta.F = F;
-    ta.R = (int)R;
-    ta.N = plan->N;
-    staged(SPT_STAGE_SPMM_T, s, [&] { launch_spmm_transposed<T>(ta, s); });
     InvFftArgs<T> ia{};
     ia.U = u;
     ia.Y = Y;
@@ -1445,7 +1521,7 @@ void execute_transposed_t(spt_plan_t plan, const T* F, T* Y, int64_t R, hipStrea
       fa.scale = ia.scale;
       staged(SPT_STAGE_INV_FFT, s, [&] { launch_inv_fft4<T>(fa, s); });
       wbuf += (size_t)R * B.P;
-    } else {
+    } else if (!multi) {
       staged(SPT_STAGE_INV_FFT, s, [&] { launch_inv_fft<T>(ia, B.fft, s); });
     }
     u += (size_t)R * (B.P + 1);

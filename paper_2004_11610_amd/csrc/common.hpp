@@ -154,6 +154,24 @@ struct InvFftArgs {      // transposed execute: half spectrum -> real, /w, keep 
 template <typename T>
 void launch_inv_fft(const InvFftArgs<T>& a, const FftPlan& fp, hipStream_t s);
 
+// The single-workgroup inverse transforms of every block in one launch:
+// workgroup (r, b) takes right-hand side r of block descs[b] (half spectra at
+// uoff R complex values into U).
+template <typename T>
+struct InvFftDesc {
+  const T* winv;
+  const double2* tw;
+  const cplx_t<T>* post;
+  int64_t uoff;
+  int P, m_off, c_lo, c_hi;
+  T scale;
+  FftPlan fp;
+};
+
+template <typename T>
+void launch_inv_fft_multi(const InvFftDesc<T>* descs, int nblk, int threads, size_t lds,
+                          const cplx_t<T>* U, T* Y, int R, int64_t N, hipStream_t s);
+
 template <typename T>
 struct InvFft4Args {      // transposed execute of a block with P = P1 P2 (four steps)
   const cplx_t<T>* U;     // R x ldu half spectrum
@@ -304,18 +322,31 @@ void launch_exec_fft_multi_split(const FftDesc<float>* descs, int nblk, int thre
 // tiles whose boxes meet columns [TCHUNK c, TCHUNK c + TCHUNK) of a block.
 constexpr int TCHUNK = 32;
 constexpr int TSEG = 8;    // row tiles per segment (one workgroup each)
+constexpr int TSEG_BLOCK_BITS = 5;  // block field of a segment (MAX_BLOCKS <= 32)
 struct TChunkEnt {
   int64_t off;             // the tile's first stored value
   int32_t tile, k0, kw, pad;
 };
 
+// per block: its stored values and where its half spectra start in the
+// workspace (uoff R complex values in)
+struct TBlkInfo {
+  const void* val64;
+  const void* val32;
+  int64_t uoff;
+  int32_t P, pad;
+};
+
 template <typename T>
 struct SpmmTArgs {
-  const int4* segs;        // n_segs segments: {chunk c, first entry, end entry, only segment of c}
-  const TChunkEnt* ents;   // per chunk, the row tiles meeting it, split into segments
-  const cplx_t<T>* val;
-  cplx_t<T>* u;            // R x ldu, zeroed; a chunk's only segment stores, several add
-  int ldu, P, n_segs;
+  const int4* segs;        // n_segs segments of every block: {chunk c, first entry, end entry,
+                           // slot << 6 | block << 1 | (1 if the only segment of c)}
+  const TChunkEnt* ents;   // per block and chunk, the row tiles meeting it
+  const TBlkInfo* blk;
+  cplx_t<T>* u;            // the workspace: block b's R x (P + 1) half spectra at uoff R
+  cplx_t<T>* part;         // R x TCHUNK partial sums per slot (chunks of several segments)
+  const int4* red;         // n_red chunks of several segments: {block, chunk, first slot, slots}
+  int n_segs, n_red;
   const T* F;              // R x N
   int R;
   int64_t N;

@@ -419,6 +419,43 @@ __global__ __launch_bounds__(FFT_MAX_THREADS) void inv_fft_kernel(InvFftArgs<T> 
   }
 }
 
+// The same for every block of a plan in one launch (descriptors in device
+// memory; the workgroup has the threads of the longest transform).
+template <typename T>
+__global__ __launch_bounds__(FFT_MAX_THREADS) void inv_fft_multi_kernel(
+    const InvFftDesc<T>* __restrict__ descs, const cplx_t<T>* __restrict__ U, T* __restrict__ Y,
+    int R, int64_t N) {
+  using C = cplx_t<T>;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C* lds = reinterpret_cast<C*>(smem_raw);
+  const InvFftDesc<T>* __restrict__ d = descs + blockIdx.y;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int r = blockIdx.x;
+  const int P = d->P;
+  const C* __restrict__ u = U + d->uoff * R + (int64_t)r * (P + 1);
+  const C* __restrict__ post = d->post;
+  for (int k = tid; k < P; k += nt) {
+    const C uk = u[k];
+    C um = u[P - k];
+    um.y = -um.y;  // conj U_(P-k)
+    const C ge = cadd(uk, um);
+    const C go = cmul(csub(uk, um), post[k]);
+    lds[k] = C{ge.x - go.y, ge.y + go.x};  // ge + i go
+  }
+  __syncthreads();
+  run_fft<+1, false>(lds, P, 0, d->fp.npass, d->fp.radix, d->tw, 1, tid, nt, true);
+  const T scale = d->scale;
+  const T* __restrict__ winv = d->winv;
+  const int c_lo = d->c_lo, c_hi = d->c_hi, m_off = d->m_off;
+  T* __restrict__ y = Y + (int64_t)r * N;
+  for (int j = tid; j < P; j += nt) {
+    const C c = lds[j];
+    const int c0 = 2 * j, c1 = 2 * j + 1;
+    if (c0 >= c_lo && c0 < c_hi) y[c0 + m_off] = c.x * scale * winv[c0];
+    if (c1 >= c_lo && c1 < c_hi) y[c1 + m_off] = c.y * scale * winv[c1];
+  }
+}
+
 // ---------------------------------------------------------------- transposed: E4 in four steps
 // Blocks whose transform does not fit one workgroup, P = P1 P2.  With a_k the
 // packed half spectrum of inv_fft_kernel, k = k1 + P1 k2 and j = j2 + P2 j1,
@@ -538,6 +575,8 @@ void init_fft_kernels(size_t max_lds) {
   set_lds(exec_fft_kernel<float>, max_lds);
   set_lds(inv_fft_kernel<double>, max_lds);
   set_lds(inv_fft_kernel<float>, max_lds);
+  set_lds(inv_fft_multi_kernel<double>, max_lds);
+  set_lds(inv_fft_multi_kernel<float>, max_lds);
   set_lds(inv_fft4_col_kernel<double>, max_lds);
   set_lds(inv_fft4_col_kernel<float>, max_lds);
   set_lds(inv_fft4_row_kernel<double>, max_lds);
@@ -654,6 +693,19 @@ void launch_inv_fft4(const InvFft4Args<T>& a, hipStream_t s) {
   SPT_HIP(hipGetLastError());
 }
 
+template <typename T>
+void launch_inv_fft_multi(const InvFftDesc<T>* descs, int nblk, int threads, size_t lds,
+                          const cplx_t<T>* U, T* Y, int R, int64_t N, hipStream_t s) {
+  if (nblk <= 0) return;
+  hipLaunchKernelGGL(inv_fft_multi_kernel<T>, dim3(R, nblk), dim3(threads), lds, s, descs, U, Y,
+                     R, N);
+  SPT_HIP(hipGetLastError());
+}
+
+template void launch_inv_fft_multi<double>(const InvFftDesc<double>*, int, int, size_t,
+                                           const double2*, double*, int, int64_t, hipStream_t);
+template void launch_inv_fft_multi<float>(const InvFftDesc<float>*, int, int, size_t,
+                                          const float2*, float*, int, int64_t, hipStream_t);
 template void launch_inv_fft4<double>(const InvFft4Args<double>&, hipStream_t);
 template void launch_inv_fft4<float>(const InvFft4Args<float>&, hipStream_t);
 

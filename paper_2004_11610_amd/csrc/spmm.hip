@@ -479,14 +479,17 @@ __global__ __launch_bounds__(256) void spmm_presplit_items_kernel(SpmmSplitBatch
 // u[r][k] = c'_k sum_n Add[n][k] f[r][n] over the half spectrum (c'_k = 1 at
 // k = 0 and P, else 1/2: the c_k folded into the stored values taken out).
 // By columns: the row tiles whose boxes meet the columns [TCHUNK c, TCHUNK c +
-// TCHUNK) are listed at precompute and split into segments of at most TSEG
-// tiles.  Workgroup (s, g) takes segment s for the right-hand sides 64 g ..
-// 64 g + 63, staging each tile's f values (64 x 16) and box columns (16 x TCHUNK)
-// in LDS (the next tile's are requested before the current one is used).  The
-// only segment of a chunk stores its sums; several add theirs to the zeroed u
-// with one atomic per value: a short block's few columns gather thousands of
-// tiles, spread over many workgroups.  Thread:
-// columns 2 cg, 2 cg + 1 and right-hand sides 4 rq .. 4 rq + 3 of the chunk.
+// TCHUNK) of a block are listed at precompute and split into segments of at
+// most TSEG tiles; one launch takes the segments of every block.  Workgroup
+// (s, g) takes segment s for the right-hand sides 64 g .. 64 g + 63, staging
+// the tiles' f values (64 x 16) and box columns (16 x TCHUNK) in LDS two tiles
+// at a time (the next two are requested before the current ones are used).
+// The only segment of a chunk stores its sums in u; when there are several (a
+// short block's few columns gather thousands of tiles, spread over many
+// workgroups) each stores into a slot of partial sums, and
+// spmm_t_reduce_kernel adds a chunk's slots in order (deterministic, no
+// atomics).  Thread: columns 2 cg, 2 cg + 1 and right-hand sides 4 rq ..
+// 4 rq + 3 of the chunk.
 template <typename T>
 __global__ __launch_bounds__(256) void spmm_transposed_kernel(SpmmTArgs<T> a) {
   using C = cplx_t<T>;
@@ -494,35 +497,46 @@ __global__ __launch_bounds__(256) void spmm_transposed_kernel(SpmmTArgs<T> a) {
   constexpr int FPT = 64 * TILE_ROWS / 256;      // f values per thread and tile
   constexpr int APT = TILE_ROWS * TCHUNK / 256;  // box values per thread and tile
   constexpr int EB = 256;                        // list entries staged at a time
-  __shared__ T fs[64][TILE_ROWS + 1];
-  __shared__ C as[TILE_ROWS][TCHUNK];
+  constexpr int TPR = 2;                         // tiles staged per round
+  __shared__ T fs[TPR][64][TILE_ROWS + 1];
+  __shared__ C as[TPR][TILE_ROWS][TCHUNK];
   __shared__ TChunkEnt ents[EB];
   const int tid = threadIdx.x;
   const int4 seg = a.segs[blockIdx.x];
+  const TBlkInfo bi = a.blk[(seg.w >> 1) & ((1 << TSEG_BLOCK_BITS) - 1)];
+  const C* __restrict__ vals = static_cast<const C*>(sizeof(T) == 8 ? bi.val64 : bi.val32);
+  const int P = bi.P;
+  const int64_t ldu = P + 1;
+  C* __restrict__ u = a.u + bi.uoff * a.R;
   const int r0 = blockIdx.y * 64;
   const int kc = seg.x * TCHUNK;
   const int cg = tid & 15, rq = tid >> 4;
   C acc[4][2];
 #pragma unroll
   for (int j = 0; j < 4; ++j) acc[j][0] = acc[j][1] = C{T(0), T(0)};
-  T fr[FPT];
-  C ar[APT];
-  auto fetch = [&](const TChunkEnt& e) {
+  T fr[TPR][FPT];
+  C ar[TPR][APT];
+  auto fetch = [&](int t, const TChunkEnt& e) {
     const int64_t n0 = (int64_t)e.tile * TILE_ROWS;
 #pragma unroll
     for (int i = 0; i < FPT; ++i) {
       const int idx = tid + i * 256, r = r0 + (idx >> 4);
       const int64_t n = n0 + (idx & 15);
-      fr[i] = (r < a.R && n < a.N) ? gload(a.F + (int64_t)r * a.N + n) : T(0);
+      fr[t][i] = (r < a.R && n < a.N) ? gload(a.F + (int64_t)r * a.N + n) : T(0);
     }
-    const C* __restrict__ val = a.val + e.off;
+    const C* __restrict__ val = vals + e.off;
 #pragma unroll
     for (int i = 0; i < APT; ++i) {
       const int idx = tid + i * 256;
       const int kk = kc + (idx >> 4) - e.k0;
-      ar[i] = (kk >= 0 && kk < e.kw) ? gload(val + (int64_t)kk * TILE_ROWS + (idx & 15))
-                                     : C{T(0), T(0)};
+      ar[t][i] = (kk >= 0 && kk < e.kw) ? gload(val + (int64_t)kk * TILE_ROWS + (idx & 15))
+                                        : C{T(0), T(0)};
     }
+  };
+  auto fetch_round = [&](int i0, int nb) {
+#pragma unroll
+    for (int t = 0; t < TPR; ++t)
+      if (i0 + t < nb) fetch(t, ents[i0 + t]);
   };
   const int e_begin = seg.y, e_end = seg.z;
   for (int b0 = e_begin; b0 < e_end; b0 += EB) {
@@ -530,43 +544,52 @@ __global__ __launch_bounds__(256) void spmm_transposed_kernel(SpmmTArgs<T> a) {
     __syncthreads();
     if (tid < nb) ents[tid] = a.ents[b0 + tid];
     __syncthreads();
-    fetch(ents[0]);
-    for (int i = 0; i < nb; ++i) {
+    fetch_round(0, nb);
+    for (int i0 = 0; i0 < nb; i0 += TPR) {
+      const int cnt = min(TPR, nb - i0);
       __syncthreads();
 #pragma unroll
-      for (int j = 0; j < FPT; ++j) {
-        const int idx = tid + j * 256;
-        fs[idx >> 4][idx & 15] = fr[j];
-      }
+      for (int t = 0; t < TPR; ++t) {
+        if (t >= cnt) break;
 #pragma unroll
-      for (int j = 0; j < APT; ++j) {
-        const int idx = tid + j * 256;
-        as[idx & 15][idx >> 4] = ar[j];
-      }
-      __syncthreads();
-      if (i + 1 < nb) fetch(ents[i + 1]);
-      // the tile's 16 rows summed first, then added (running sums stay short)
-      C part[4][2];
+        for (int j = 0; j < FPT; ++j) {
+          const int idx = tid + j * 256;
+          fs[t][idx >> 4][idx & 15] = fr[t][j];
+        }
 #pragma unroll
-      for (int j = 0; j < 4; ++j) part[j][0] = part[j][1] = C{T(0), T(0)};
-#pragma unroll
-      for (int q = 0; q < TILE_ROWS; ++q) {
-        const C a0 = as[q][2 * cg], a1 = as[q][2 * cg + 1];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const T fv = fs[4 * rq + j][q];
-          part[j][0].x += a0.x * fv;
-          part[j][0].y += a0.y * fv;
-          part[j][1].x += a1.x * fv;
-          part[j][1].y += a1.y * fv;
+        for (int j = 0; j < APT; ++j) {
+          const int idx = tid + j * 256;
+          as[t][idx & 15][idx >> 4] = ar[t][j];
         }
       }
+      __syncthreads();
+      if (i0 + TPR < nb) fetch_round(i0 + TPR, nb);
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
+      for (int t = 0; t < TPR; ++t) {
+        if (t >= cnt) break;
+        // the tile's 16 rows summed first, then added (running sums stay short)
+        C part[4][2];
 #pragma unroll
-        for (int c2 = 0; c2 < 2; ++c2) {
-          acc[j][c2].x += part[j][c2].x;
-          acc[j][c2].y += part[j][c2].y;
+        for (int j = 0; j < 4; ++j) part[j][0] = part[j][1] = C{T(0), T(0)};
+#pragma unroll
+        for (int q = 0; q < TILE_ROWS; ++q) {
+          const C a0 = as[t][q][2 * cg], a1 = as[t][q][2 * cg + 1];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const T fv = fs[t][4 * rq + j][q];
+            part[j][0].x += a0.x * fv;
+            part[j][0].y += a0.y * fv;
+            part[j][1].x += a1.x * fv;
+            part[j][1].y += a1.y * fv;
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+#pragma unroll
+          for (int c2 = 0; c2 < 2; ++c2) {
+            acc[j][c2].x += part[j][c2].x;
+            acc[j][c2].y += part[j][c2].y;
+          }
         }
       }
     }
@@ -578,17 +601,49 @@ __global__ __launch_bounds__(256) void spmm_transposed_kernel(SpmmTArgs<T> a) {
 #pragma unroll
     for (int c2 = 0; c2 < 2; ++c2) {
       const int k = kc + 2 * cg + c2;
-      if (k > a.P) continue;
-      const T ck = (k == 0 || k == a.P) ? T(1) : T(0.5);
-      C* __restrict__ uk = a.u + (int64_t)r * a.ldu + k;
-      if (seg.w) {
-        *uk = C{acc[j][c2].x * ck, acc[j][c2].y * ck};
-      } else {
-        atomicAdd(&uk->x, acc[j][c2].x * ck);
-        atomicAdd(&uk->y, acc[j][c2].y * ck);
-      }
+      if (k > P) continue;
+      const T ck = (k == 0 || k == P) ? T(1) : T(0.5);
+      const C v = C{acc[j][c2].x * ck, acc[j][c2].y * ck};
+      if (seg.w & 1)
+        u[(int64_t)r * ldu + k] = v;
+      else
+        a.part[((int64_t)(seg.w >> (TSEG_BLOCK_BITS + 1)) * a.R + r) * TCHUNK + 2 * cg + c2] = v;
     }
   }
+}
+
+// u of the chunks with several segments (and zeros for chunks no tile meets):
+// workgroup (i, g) adds the slots of chunk red[i] in order for the right-hand
+// sides 8 g .. 8 g + 7, one value per thread, eight slots requested at a time
+template <typename T>
+__global__ __launch_bounds__(256) void spmm_t_reduce_kernel(SpmmTArgs<T> a) {
+  using C = cplx_t<T>;
+  static_assert(TCHUNK == 32, "256 threads: 8 right-hand sides x 32 columns");
+  const int4 rd = a.red[blockIdx.x];
+  const TBlkInfo bi = a.blk[rd.x];
+  const int P = bi.P;
+  const int r = blockIdx.y * 8 + (threadIdx.x >> 5), c = threadIdx.x & 31, k = rd.y * TCHUNK + c;
+  if (r >= a.R || k > P) return;
+  const int64_t stride = (int64_t)a.R * TCHUNK;
+  const C* __restrict__ p = a.part + ((int64_t)rd.z * a.R + r) * TCHUNK + c;
+  C s = C{T(0), T(0)};
+  int i = 0;
+  for (; i + 8 <= rd.w; i += 8) {
+    C v[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = p[(int64_t)(i + j) * stride];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      s.x += v[j].x;
+      s.y += v[j].y;
+    }
+  }
+  for (; i < rd.w; ++i) {
+    const C v = p[(int64_t)i * stride];
+    s.x += v.x;
+    s.y += v.y;
+  }
+  a.u[bi.uoff * a.R + (int64_t)r * (P + 1) + k] = s;
 }
 
 // fhat[r][m] = sum_j tail[m][j] f[r][j] for m < tail: one workgroup per (m, r)
@@ -599,8 +654,20 @@ __global__ __launch_bounds__(256) void tail_transposed_kernel(const T* __restric
   const int m = blockIdx.x, r = blockIdx.y;
   const T* __restrict__ col = tailmat + (int64_t)m * ldt;
   const T* __restrict__ f = F + (int64_t)r * N;
+  // eight loads of each in flight per thread (blockDim.x is 256)
   T s = T(0);
-  for (int64_t j = threadIdx.x; j < N; j += blockDim.x) s += col[j] * f[j];
+  int64_t j = threadIdx.x;
+  for (; j + 7 * 256 < N; j += 8 * 256) {
+    T cv[8], fv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      cv[u] = col[j + u * 256];
+      fv[u] = f[j + u * 256];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += cv[u] * fv[u];
+  }
+  for (; j < N; j += 256) s += col[j] * f[j];
   __shared__ T part[256];
   part[threadIdx.x] = s;
   __syncthreads();
@@ -674,10 +741,13 @@ void launch_spmm_split_bf16(const SpmmArgs<float>& a, hipStream_t s) {
 
 template <typename T>
 void launch_spmm_transposed(const SpmmTArgs<T>& a, hipStream_t s) {
-  if (a.R > 65535 * 64) throw Error(SPT_E_INVALID_ARG, "too many right-hand sides");
+  if (a.R > 65535 * 8) throw Error(SPT_E_INVALID_ARG, "too many right-hand sides");
   if (a.n_segs <= 0) return;
   hipLaunchKernelGGL(spmm_transposed_kernel<T>, dim3(a.n_segs, (a.R + 63) / 64), dim3(256), 0, s,
                      a);
+  SPT_HIP(hipGetLastError());
+  if (a.n_red <= 0) return;
+  hipLaunchKernelGGL(spmm_t_reduce_kernel<T>, dim3(a.n_red, (a.R + 7) / 8), dim3(256), 0, s, a);
   SPT_HIP(hipGetLastError());
 }
 
