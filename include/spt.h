@@ -177,6 +177,10 @@ typedef struct {
   int64_t window_cols;                   /* sum over groups of 4 row tiles and over
                                             blocks of the spectrum columns that the
                                             windowed kernel stages in LDS          */
+  int64_t window_chunked;                /* 1: the windows are too wide for LDS and
+                                            pass through it in chunks of 32 columns
+                                            (window_lds is then the chunked
+                                            kernel's)                              */
 } spt_plan_info;
 
 /* Create a plan for the N x N matrix of `family` with threshold eps (= eps1 of

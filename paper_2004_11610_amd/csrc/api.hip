@@ -163,6 +163,7 @@ struct spt_plan {
   int win_rg = 4;                  // groups of 16 right-hand sides per workgroup
   int win_xlds = 0, win_tpad = 0;  // x of the direct tail in LDS (16-byte units), its pitch
   bool win_ok = false;
+  bool win_chunked = false;  // the windows pass through LDS in chunks (too wide to fit)
   int fft_threads = 64, fft_maxP = 1;
   int fft_wgP = 1;  // most points of one workgroup of the fused FFT
   int64_t serial = 0;  // changes with every precompute (keys of executor contexts)
@@ -1032,6 +1033,7 @@ std::vector<FftDesc<T>> fft_descs(spt_plan_t plan) {
 // ceil4(kw) - 1, which is what a step reads) and its place in LDS.
 void build_windows(spt_plan_t plan, hipStream_t s) {
   plan->win_ok = false;
+  plan->win_chunked = false;
   plan->win_lds = 0;
   const int nblk = (int)plan->blk.size();
   plan->n_groups = (plan->n_tiles + WIN_TILES - 1) / WIN_TILES;
@@ -1092,7 +1094,18 @@ void build_windows(spt_plan_t plan, hipStream_t s) {
   std::vector<WinMeta> win((size_t)plan->n_groups * nblk);
   int64_t cols = 0;
   const auto lay = layout(rg, &win, &cols);
-  if (lay.second > lds_max) return;
+  if (lay.second > lds_max) {
+    // the windows pass through LDS in chunks (64 right-hand sides per workgroup)
+    if (spmm_chunk_lds_bytes(tpad) > lds_max) return;
+    upload(plan->winmeta, win, s);
+    plan->win_rg = 4;
+    plan->win_tpad = tpad;
+    plan->win_lds = spmm_chunk_lds_bytes(tpad);
+    plan->win_cols = cols;
+    plan->win_chunked = true;
+    plan->win_ok = true;
+    return;
+  }
   upload(plan->winmeta, win, s);
   plan->win_rg = rg;
   plan->win_xlds = (int)lay.first;
@@ -1380,7 +1393,9 @@ void execute_staged_t(spt_plan_t plan, const T* X, T* Y, int64_t R, int prec, hi
         pa.N = plan->N;
         // the windowed kernel forms byte offsets within the three spectrum
         // planes in 32 bits
-        if (plan->win_ok && 12.0 * (double)R * (double)plan->zper4 < 4294967296.0)
+        if (plan->win_ok && plan->win_chunked)
+          launch_spmm_chunk(pa, plan->winmeta.as<WinMeta>(), plan->n_groups, plan->win_tpad, st);
+        else if (plan->win_ok && 12.0 * (double)R * (double)plan->zper4 < 4294967296.0)
           launch_spmm_window(pa, plan->winmeta.as<WinMeta>(), plan->n_groups, plan->win_rg,
                              plan->win_xlds, plan->win_tpad, plan->win_lds, st);
         else
@@ -1970,6 +1985,7 @@ spt_status spt_plan_query(spt_plan_t plan, spt_plan_info* info) {
       if (plan->win_ok) {
         info->window_lds = (int64_t)plan->win_lds;
         info->window_cols = plan->win_cols;
+        info->window_chunked = plan->win_chunked ? 1 : 0;
       }
     }
   });

@@ -287,6 +287,11 @@ struct WinMeta {
 // win: n_groups x nblk, group-major.  LDS: the windows (the largest sum of a
 // group's windows), then from 16-byte unit xlds the direct tail's x of the NR
 // right-hand sides, tpad = 32 * ceil(tail / 32) + 4 floats apart (0: no tail).
+// Plans whose windows do not fit: the same windows (k0, w4 only) staged in
+// chunks; LDS bytes of a workgroup for a tail pitch tpad.
+size_t spmm_chunk_lds_bytes(int tpad);
+void launch_spmm_chunk(const SpmmSplitArgs& a, const WinMeta* win, int n_groups, int tpad,
+                       hipStream_t s);
 void launch_spmm_window(const SpmmSplitArgs& a, const WinMeta* win, int n_groups, int rg,
                         int xlds, int tpad, size_t lds_bytes, hipStream_t s);
 void init_spmm_kernels(size_t max_lds);

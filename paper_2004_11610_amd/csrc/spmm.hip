@@ -445,6 +445,212 @@ __global__ __launch_bounds__(256) void spmm_window_kernel(SpmmSplitArgs args,
   }
 }
 
+// ---------------------------------------------------------------- chunked windowed product
+// For plans whose windows do not fit a workgroup's LDS (wide boxes, e.g. the
+// Laguerre and Hermite functions, where the product is a nearly dense
+// contraction): the workgroup of the windowed product (WIN_TILES row tiles x
+// CK_NR right-hand sides, wave = one tile), but each block's union window
+// passes through LDS in chunks of CK_G column groups of 4, plus CK_HALO groups
+// so that every step starting in the chunk lies in it.  Two buffers: the next
+// chunk (direct global-to-LDS loads) and the tile's matrix pieces for it are
+// requested before the current chunk is used.  The spectra of a chunk cross
+// from L2 once for the four tiles instead of once per tile.  A tile's steps
+// are taken in the per-tile product's order (blocks in order, steps in order
+// within a block), so the sums are the same bits.
+constexpr int CK_G = 8;
+constexpr int CK_HALO = 3;
+constexpr int CK_PITCH = 11;  // LDS row pitch in 16-byte units: odd, >= CK_G + CK_HALO
+constexpr int CK_NR = 64;
+constexpr int CK_UNITS = 3 * CK_NR * CK_PITCH;  // 16-byte units of one buffer
+static_assert(CK_UNITS % 64 == 0 && CK_PITCH >= CK_G + CK_HALO, "chunk buffer layout");
+
+__global__ __launch_bounds__(256) void spmm_chunk_kernel(SpmmSplitArgs args,
+                                                         const WinMeta* __restrict__ win,
+                                                         int n_groups, int tpad) {
+  constexpr int RG = CK_NR / 16, NR = CK_NR;
+  extern __shared__ __align__(16) uint4 zl[];
+  const int grp = xcd_tile(blockIdx.x, n_groups);
+  const int r0 = blockIdx.y * NR;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int m = lane & 15, g = lane >> 4;
+  const int nblk = args.nblk;
+  const int tile = grp * WIN_TILES + wave;
+  const bool has_tile = tile < args.n_tiles;  // wave-uniform
+  const bf16x8 zero8 = bf16x8{};
+
+  // lane b < nblk: the union window of block b (k0, w4), its descriptor and
+  // the box of (tile, b)
+  int wk0_l = 0, ww4_l = 0, k0_l = 0, kw_l = 0, ldz_l = 0;
+  int64_t off_l = 0, val_l = 0, zoff_l = 0;
+  if (lane < nblk) {
+    const WinMeta wm = win[(int64_t)grp * nblk + lane];
+    wk0_l = wm.k0;
+    ww4_l = wm.w4;
+    const SpmmSplitBlock bd = args.blocks[lane];
+    val_l = (int64_t)(uintptr_t)bd.val;
+    zoff_l = bd.zoff;
+    ldz_l = bd.ldz;
+    if (has_tile) {
+      const TileMeta tm = args.meta[(int64_t)tile * nblk + lane];
+      k0_l = tm.k0;
+      kw_l = tm.kw;
+      off_l = tm.off;
+    }
+  }
+  __builtin_amdgcn_s_waitcnt(0);
+  // chunks are numbered through the blocks in order; lane b holds the number
+  // of the first chunk of block b
+  int cstart_l = 0, nch = 0;
+  for (int bb = 0; bb < nblk; ++bb) {
+    if (lane == bb) cstart_l = nch;
+    nch += (lane_i32(ww4_l, bb) + CK_G - 1) / CK_G;
+  }
+  const int cend_l = cstart_l + (lane < nblk ? (ww4_l + CK_G - 1) / CK_G : 0);
+  auto block_of = [&](int c) { return (int)__popcll(__ballot(lane < nblk && cend_l <= c)); };
+
+  // chunk c (block b, chunk j: window groups CK_G j .. CK_G j + nst - 1) into
+  // buffer c & 1: row q = p NR + i (piece p, right-hand side r0 + i), groups
+  // past the window repeat its last one, right-hand sides past R the last one
+  auto stage = [&](int c) {
+    const int b = block_of(c);
+    const int j = c - lane_i32(cstart_l, b);
+    const int gbeg = j * CK_G;
+    const int nst = min(CK_G + CK_HALO, lane_i32(ww4_l, b) - gbeg);
+    const int64_t ldz = lane_i32(ldz_l, b);
+    const char* __restrict__ zw = reinterpret_cast<const char*>(
+        args.Zs + (int64_t)args.R * lane_i64(zoff_l, b) + lane_i32(wk0_l, b) + 4 * gbeg);
+    uint4* __restrict__ dst = zl + (c & 1) * CK_UNITS;
+    for (int cc = wave; cc * 64 < CK_UNITS; cc += 4) {
+      const int u = cc * 64 + lane;
+      const int row = u / CK_PITCH, col = min(u - row * CK_PITCH, nst - 1);
+      const int p = row / NR, rhs = min(r0 + row - p * NR, args.R - 1);
+      const int64_t off = ((int64_t)p * args.zplane + rhs * ldz + 4 * col) * 4;
+      __builtin_amdgcn_global_load_lds(zw + off, dst + cc * 64, 16, 0, 0);
+    }
+  };
+  // the tile's steps in chunk c: s_lo .. s_lo + ns - 1 (at most 2: the steps
+  // whose first group base + 4 s lies in [CK_G j, CK_G j + CK_G)), their
+  // matrix pieces
+  auto load_a = [&](int c, bf16x8 (*Ar)[3], int& s_lo, int& ns) {
+    const int b = block_of(c);
+    const int j = c - lane_i32(cstart_l, b);
+    const int base = (lane_i32(k0_l, b) - lane_i32(wk0_l, b)) >> 2;
+    const int S = (lane_i32(kw_l, b) + 15) >> 4;
+    const int lo = max(0, (CK_G * j - base + 3) >> 2);
+    const int hi = min(S, (CK_G * j + CK_G - base + 3) >> 2);
+    s_lo = lo;
+    ns = has_tile ? max(0, hi - lo) : 0;
+    const bf16x8* __restrict__ va =
+        reinterpret_cast<const bf16x8*>((const uint16_t*)(uintptr_t)lane_i64(val_l, b) +
+                                        lane_i64(off_l, b)) + lane;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int p = 0; p < 3; ++p) Ar[i][p] = i < ns ? gload(va + (3 * (lo + i) + p) * 64) : zero8;
+  };
+
+  // x of the direct tail -> LDS after the two buffers (as the windowed product)
+  float* __restrict__ xl = reinterpret_cast<float*>(zl + 2 * CK_UNITS);
+  for (int c = wave; c * 64 < NR * tpad; c += 4) {
+    const int u = c * 64 + lane;
+    const int i = u / tpad, mm = u - i * tpad;
+    const float* src = args.X + (int64_t)min(r0 + i, args.R - 1) * args.N + min(mm, args.tail - 1);
+    __builtin_amdgcn_global_load_lds(src, xl + c * 64, 4, 0, 0);
+  }
+  bf16x8 Acur[2][3], Anext[2][3];
+  int slo_c = 0, ns_c = 0, slo_n = 0, ns_n = 0;
+  if (nch > 0) {
+    stage(0);
+    load_a(0, Acur, slo_c, ns_c);
+  }
+  const int64_t n0 = (int64_t)tile * TILE_ROWS;
+  const int tsteps = has_tile ? (args.tail + 31) / 32 : 0;
+  const bf16x8* __restrict__ ta = reinterpret_cast<const bf16x8*>(args.tailmat);
+  bf16x8 TA[3];
+  auto load_tail = [&](int st) {
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+      TA[p] = gload(ta + (((int64_t)tile * tsteps + st) * 3 + p) * 64 + lane);
+  };
+  if (tsteps > 0) load_tail(0);
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+
+  f32x4 acc[RG];
+#pragma unroll
+  for (int q = 0; q < RG; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int c = 0; c < nch; ++c) {
+    // buffer (c + 1) & 1 was last read for chunk c - 1, before the barrier
+    if (c + 1 < nch) {
+      stage(c + 1);
+      load_a(c + 1, Anext, slo_n, ns_n);
+    }
+    if (ns_c > 0) {
+      const int b = block_of(c);
+      const int j = c - lane_i32(cstart_l, b);
+      const int base = (lane_i32(k0_l, b) - lane_i32(wk0_l, b)) >> 2;
+      const int nst = min(CK_G + CK_HALO, lane_i32(ww4_l, b) - CK_G * j);
+      const uint4* __restrict__ zb = zl + (c & 1) * CK_UNITS + m * CK_PITCH;
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        if (i < ns_c) {
+          // groups past the tile's box (zero matrix pieces) read the chunk's
+          // last staged group, a finite value
+          const int lg = min(base + 4 * (slo_c + i) + g - CK_G * j, nst - 1);
+          bf16x8 Z[RG][3];
+#pragma unroll
+          for (int q = 0; q < RG; ++q)
+#pragma unroll
+            for (int p = 0; p < 3; ++p)
+              Z[q][p] = __builtin_bit_cast(bf16x8, zb[(p * NR + 16 * q) * CK_PITCH + lg]);
+          mma6xg<RG>(Acur[i], Z, acc);
+        }
+      }
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int p = 0; p < 3; ++p) Acur[i][p] = Anext[i][p];
+    slo_c = slo_n;
+    ns_c = ns_n;
+  }
+  if (!has_tile) return;
+
+  // direct tail: x from LDS, split here
+  for (int st = 0; st < tsteps; ++st) {
+    if (st > 0) load_tail(st);
+    bf16x8 B[RG][3];
+#pragma unroll
+    for (int q = 0; q < RG; ++q) {
+      const float4* xq = reinterpret_cast<const float4*>(xl + (16 * q + m) * tpad + 32 * st + 8 * g);
+      const float4 lo = xq[0], hi = xq[1];
+      const float v[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+      f32x8 xv;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) xv[j] = 32 * st + 8 * g + j < args.tail ? v[j] : 0.f;
+      const Split8 xs(xv);
+#pragma unroll
+      for (int p = 0; p < 3; ++p) B[q][p] = xs.get(p);
+    }
+    mma6xg<RG>(TA, B, acc);
+  }
+
+  // y: lane (m, g) holds rows 4g .. 4g+3 of right-hand side r0 + 16 q + m
+#pragma unroll
+  for (int q = 0; q < RG; ++q) {
+    const int rhs = r0 + 16 * q + m;
+    if (rhs < args.R) {
+      float* __restrict__ y = args.Y + (int64_t)rhs * args.N + n0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (n0 + 4 * g + i < args.N) y[4 * g + i] = acc[q][i];
+    }
+  }
+}
+
 template <typename E>
 __global__ __launch_bounds__(256) void spmm_mfma_kernel(SpmmArgs<typename E::T> args) {
   mfma_tile<E>(args, xcd_tile(blockIdx.x, args.n_tiles), blockIdx.y * 64);
@@ -708,6 +914,17 @@ void launch_spmm_presplit(const SpmmSplitArgs& a, hipStream_t s) {
   SPT_HIP(hipGetLastError());
 }
 
+size_t spmm_chunk_lds_bytes(int tpad) {
+  return (size_t)2 * CK_UNITS * 16 + (size_t)CK_NR * tpad * sizeof(float);
+}
+
+void launch_spmm_chunk(const SpmmSplitArgs& a, const WinMeta* win, int n_groups, int tpad,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(spmm_chunk_kernel, dim3(n_groups, (a.R + CK_NR - 1) / CK_NR), dim3(256),
+                     spmm_chunk_lds_bytes(tpad), s, a, win, n_groups, tpad);
+  SPT_HIP(hipGetLastError());
+}
+
 void launch_spmm_window(const SpmmSplitArgs& a, const WinMeta* win, int n_groups, int rg,
                         int xlds, int tpad, size_t lds_bytes, hipStream_t s) {
   if (rg == 4)
@@ -729,6 +946,8 @@ void init_spmm_kernels(size_t max_lds) {
   SPT_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(spmm_window_kernel<4>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_lds));
   SPT_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(spmm_window_kernel<2>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_lds));
+  SPT_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(spmm_chunk_kernel),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_lds));
   done.push_back(dev);
 }

@@ -616,14 +616,15 @@ def test_one_plan_on_several_streams(spt):
 @pytest.mark.parametrize("fam,N,R,kw", [
     ("legendre", 16384, 64, {}), ("legendre", 1000, 1, {}), ("legendre", 1000, 70, {}),
     ("chebyshev_t", 3000, 130, {}), ("laguerre_fn", 5000, 64, {}),
-    ("hermite_fn", 2049, 17, {}), ("jacobi", 4100, 200, dict(alpha=-0.5, beta=0.5))])
+    ("laguerre_fn", 3001, 130, {}), ("hermite_fn", 2049, 17, {}),
+    ("jacobi", 4100, 200, dict(alpha=-0.5, beta=0.5))])
 def test_windowed_product_matches_per_tile(spt, monkeypatch, fam, N, R, kw, rg):
     """The windowed split-bf16 product (spectra staged in LDS per group of four
-    row tiles, 64 or 32 right-hand sides per workgroup) takes the same steps in
-    the same order as the per-tile product, so both give the same bits (up to
-    the sign of an exact zero); ragged tile groups (N not a multiple of 64),
-    right-hand-side chunks with fewer columns than a workgroup's and several
-    chunks."""
+    row tiles, 64 or 32 right-hand sides per workgroup; for windows too wide
+    for LDS, in chunks of 32 columns) takes the same steps in the same order as
+    the per-tile product, so both give the same bits (up to the sign of an
+    exact zero); ragged tile groups (N not a multiple of 64), right-hand-side
+    chunks with fewer columns than a workgroup's and several chunks."""
     say("windowed product", fam, N, R, kw, "rg", rg)
     monkeypatch.setenv("SPT_SPMM_WINDOW_RG", rg)
     p = spt.Plan(fam, N, 1e-7, **kw).precompute()
@@ -633,9 +634,11 @@ def test_windowed_product_matches_per_tile(spt, monkeypatch, fam, N, R, kw, rg):
     q = spt.Plan(fam, N, 1e-7, **kw).precompute()
     monkeypatch.delenv("SPT_SPMM_WINDOW")
     assert q.info()["window_lds"] == 0
-    say("  blocks %d window LDS %d B, %d columns" % (info["n_blocks"], info["window_lds"],
-                                                      info["window_cols"]))
+    say("  blocks %d window LDS %d B, %d columns, chunked %d" % (
+        info["n_blocks"], info["window_lds"], info["window_cols"], info["window_chunked"]))
     if fam == "legendre" and N == 16384:
-        assert info["window_lds"] > 0
+        assert info["window_lds"] > 0 and info["window_chunked"] == 0
+    if fam == "laguerre_fn":
+        assert info["window_chunked"] == 1
     X = workloads.rhs("normal", R, N, 97)
     assert np.array_equal(run(spt, p, X, spt.SPLIT_BF16), run(spt, q, X, spt.SPLIT_BF16))
