@@ -110,6 +110,9 @@ struct ExecCtx {
   int ntw = 0;     // largest twiddle table (entries) of the blocks
   DevBuf sargs, sitems;  // staged batch: product arguments per plan, product items
   int n_sitems = 0;
+  DevBuf witems;         // split-bf16 staged batch: chunked-product items of windowed plans
+  int n_witems = 0;
+  size_t wlds = 0;
 };
 
 bool is_jacobi(int f) { return f == SPT_LEGENDRE || f == SPT_JACOBI; }
@@ -381,10 +384,15 @@ int fft_max_lb() {
   return e ? std::max(0, std::min(10, std::atoi(e))) : 2;
 }
 
-// The windowed product (diagnostics: SPT_SPMM_WINDOW=0 keeps the per-tile one).
+// The windowed product (diagnostics: SPT_SPMM_WINDOW=0 keeps the per-tile one,
+// SPT_SPMM_WINDOW=chunk stages every plan's windows in chunks).
 bool window_product_enabled() {
   const char* e = std::getenv("SPT_SPMM_WINDOW");
   return !(e && e[0] == '0');
+}
+bool window_chunks_forced() {
+  const char* e = std::getenv("SPT_SPMM_WINDOW");
+  return e && std::strcmp(e, "chunk") == 0;
 }
 
 void exec_geometry(DevBlock& B) {
@@ -1094,7 +1102,7 @@ void build_windows(spt_plan_t plan, hipStream_t s) {
   std::vector<WinMeta> win((size_t)plan->n_groups * nblk);
   int64_t cols = 0;
   const auto lay = layout(rg, &win, &cols);
-  if (lay.second > lds_max) {
+  if (lay.second > lds_max || window_chunks_forced()) {
     // the windows pass through LDS in chunks (64 right-hand sides per workgroup)
     if (spmm_chunk_lds_bytes(tpad) > lds_max) return;
     upload(plan->winmeta, win, s);
@@ -1616,17 +1624,28 @@ template <typename T>
 void build_batch_products(ExecCtx& c, const spt_plan_t* plans, const int64_t* R, int count,
                           int prec, hipStream_t s) {
   const bool dbl = std::is_same<T, double>::value;
-  std::vector<int4> items;
+  // split-bf16: plans with windows take the chunked product (groups of 4 row
+  // tiles), the others the per-tile product
+  const bool chunked = prec == SPT_SPLIT_BF16;
+  std::vector<int4> items, witems;
+  c.wlds = 0;
   for (int i = 0; i < count; ++i) {
     const spt_plan_t plan = plans[i];
+    const bool win = chunked && plan->win_ok;
+    std::vector<int4>& it = win ? witems : items;
+    const int n = win ? plan->n_groups : plan->n_tiles;
+    if (win) c.wlds = std::max(c.wlds, spmm_chunk_lds_bytes(plan->win_tpad));
     for (int r0 = 0; r0 < R[i]; r0 += 64) {
-      while (items.size() % 8) items.push_back(make_int4(i, -1, 0, 0));
-      for (int t = 0; t < plan->n_tiles; ++t)
-        items.push_back(make_int4(i, xcd_tile_host(t, plan->n_tiles), r0, 0));
+      while (it.size() % 8) it.push_back(make_int4(i, -1, 0, 0));
+      for (int t = 0; t < n; ++t) it.push_back(make_int4(i, xcd_tile_host(t, n), r0, 0));
     }
   }
+  if (items.empty()) items.push_back(make_int4(0, -1, 0, 0));
+  if (witems.empty()) witems.push_back(make_int4(0, -1, 0, 0));
   upload(c.sitems, items, s);
+  upload(c.witems, witems, s);
   c.n_sitems = (int)items.size();
+  c.n_witems = c.wlds > 0 ? (int)witems.size() : 0;
   if (prec == SPT_SPLIT_BF16) {
     std::vector<SpmmSplitArgs> a(count);
     for (int i = 0; i < count; ++i) {
@@ -1641,6 +1660,11 @@ void build_batch_products(ExecCtx& c, const spt_plan_t* plans, const int64_t* R,
       a[i].tailmat = plan->tailbf.as<uint16_t>();
       a[i].R = (int)R[i];
       a[i].N = plan->N;
+      if (plan->win_ok) {
+        a[i].win = plan->winmeta.as<WinMeta>();
+        a[i].n_groups = plan->n_groups;
+        a[i].tpad = plan->win_tpad;
+      }
     }
     upload(c.sargs, a, s);
     return;
@@ -1686,11 +1710,14 @@ void run_batch_staged(ExecCtx& c, const void* const* X, void* const* Y, int coun
     if (split) {
       SpmmSplitBatch b{};
       b.plans = c.sargs.as<SpmmSplitArgs>();
-      b.items = c.sitems.as<int4>();
       for (int i = 0; i < count; ++i) {
         b.X[i] = static_cast<const float*>(X[i]);
         b.Y[i] = static_cast<float*>(Y[i]);
       }
+      // each launch reads its own item list (n items each)
+      b.items = c.witems.as<int4>();
+      launch_spmm_chunk_items(b, c.n_witems, c.wlds, s);
+      b.items = c.sitems.as<int4>();
       launch_spmm_presplit_items(b, c.n_sitems, s);
       return;
     }

@@ -251,6 +251,7 @@ struct SpmmSplitBlock {
   int32_t pad;
 };
 
+struct WinMeta;
 struct SpmmSplitArgs {
   const TileMeta* meta;          // n_tiles x nblk (off in bfloat16 units)
   const SpmmSplitBlock* blocks;  // nblk
@@ -264,6 +265,8 @@ struct SpmmSplitArgs {
   float* Y;
   int R;
   int64_t N;
+  const WinMeta* win;            // staged batches: the plan's windows (chunked product),
+  int n_groups, tpad;            // or null for the per-tile product
 };
 void launch_spmm_presplit(const SpmmSplitArgs& a, hipStream_t s);
 
@@ -316,6 +319,9 @@ struct SpmmSplitBatch {
 template <typename T>
 void launch_spmm_items(const SpmmBatch<T>& b, int n_items, hipStream_t s);
 void launch_spmm_presplit_items(const SpmmSplitBatch& b, int n_items, hipStream_t s);
+// items {plan, tile group, first right-hand side, 0} of the chunked product
+// (group < 0: padding); lds: the largest spmm_chunk_lds_bytes of the plans
+void launch_spmm_chunk_items(const SpmmSplitBatch& b, int n_items, size_t lds, hipStream_t s);
 
 // split-bf16 staged FFT: the half spectra go out as the three planes above
 void launch_exec_fft_multi_split(const FftDesc<float>* descs, int nblk, int threads, size_t lds,

@@ -464,13 +464,11 @@ constexpr int CK_NR = 64;
 constexpr int CK_UNITS = 3 * CK_NR * CK_PITCH;  // 16-byte units of one buffer
 static_assert(CK_UNITS % 64 == 0 && CK_PITCH >= CK_G + CK_HALO, "chunk buffer layout");
 
-__global__ __launch_bounds__(256) void spmm_chunk_kernel(SpmmSplitArgs args,
-                                                         const WinMeta* __restrict__ win,
-                                                         int n_groups, int tpad) {
+__device__ __forceinline__ void chunk_group(const SpmmSplitArgs& args,
+                                            const WinMeta* __restrict__ win, int grp, int r0,
+                                            int tpad) {
   constexpr int RG = CK_NR / 16, NR = CK_NR;
   extern __shared__ __align__(16) uint4 zl[];
-  const int grp = xcd_tile(blockIdx.x, n_groups);
-  const int r0 = blockIdx.y * NR;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   const int m = lane & 15, g = lane >> 4;
@@ -649,6 +647,22 @@ __global__ __launch_bounds__(256) void spmm_chunk_kernel(SpmmSplitArgs args,
         if (n0 + 4 * g + i < args.N) y[4 * g + i] = acc[q][i];
     }
   }
+}
+
+__global__ __launch_bounds__(256) void spmm_chunk_kernel(SpmmSplitArgs args,
+                                                         const WinMeta* __restrict__ win,
+                                                         int n_groups, int tpad) {
+  chunk_group(args, win, xcd_tile(blockIdx.x, n_groups), blockIdx.y * CK_NR, tpad);
+}
+
+// Several plans in one launch: workgroup b takes item b = (plan, group, r0)
+__global__ __launch_bounds__(256) void spmm_chunk_items_kernel(SpmmSplitBatch b) {
+  const int4 it = b.items[blockIdx.x];
+  if (it.y < 0) return;
+  SpmmSplitArgs a = b.plans[it.x];
+  a.X = b.X[it.x];
+  a.Y = b.Y[it.x];
+  chunk_group(a, a.win, it.y, it.z, a.tpad);
 }
 
 template <typename E>
@@ -914,6 +928,12 @@ void launch_spmm_presplit(const SpmmSplitArgs& a, hipStream_t s) {
   SPT_HIP(hipGetLastError());
 }
 
+void launch_spmm_chunk_items(const SpmmSplitBatch& b, int n_items, size_t lds, hipStream_t s) {
+  if (n_items <= 0) return;
+  hipLaunchKernelGGL(spmm_chunk_items_kernel, dim3(n_items), dim3(256), lds, s, b);
+  SPT_HIP(hipGetLastError());
+}
+
 size_t spmm_chunk_lds_bytes(int tpad) {
   return (size_t)2 * CK_UNITS * 16 + (size_t)CK_NR * tpad * sizeof(float);
 }
@@ -948,6 +968,8 @@ void init_spmm_kernels(size_t max_lds) {
   SPT_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(spmm_window_kernel<2>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_lds));
   SPT_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(spmm_chunk_kernel),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_lds));
+  SPT_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(spmm_chunk_items_kernel),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_lds));
   done.push_back(dev);
 }

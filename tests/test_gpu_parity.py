@@ -574,6 +574,25 @@ def test_batched_staged_matches_single_plans(spt):
                 assert e <= (1e-13 if prec == spt.F64 else reduced_tol(p)), (rep, e)
 
 
+def test_batch_of_windowed_plans_matches_single(spt):
+    """A staged split-bf16 batch whose plans all have windows runs only the
+    chunked product's items (the per-tile item list holds one padding entry);
+    a plan whose FFTs are four-step items in both paths (P = 15000) gives the
+    same bits batched, alone or beside another plan, as executed singly."""
+    import torch
+    say("batch of windowed plans")
+    big = spt.Plan("legendre", LONG_N, 1e-7).precompute()
+    small = spt.Plan("legendre", 1000, 1e-7).precompute()
+    assert big.info()["window_lds"] > 0 and small.info()["window_lds"] > 0
+    Xb = to_dev(workloads.rhs("normal", 2, LONG_N, 75), torch.float32)
+    Xs = to_dev(workloads.rhs("normal", 5, 1000, 70), torch.float32)
+    ref = to_host(big.execute(Xb, prec=spt.SPLIT_BF16))
+    for plans, Xl in (([big], [Xb]), ([small, big], [Xs, Xb])):
+        Ys = [torch.full_like(x, float("nan")) for x in Xl]
+        spt.execute_batched(plans, Xl, Ys, prec=spt.SPLIT_BF16)
+        assert np.array_equal(to_host(Ys[-1]), ref)
+
+
 @pytest.mark.parametrize("R", [256, 300, 513])
 def test_split_product_chunks_match_alone(spt, R):
     """Right-hand sides are taken 64 per product workgroup; the first 64 of a
