@@ -574,6 +574,21 @@ def test_batched_staged_matches_single_plans(spt):
                 assert e <= (1e-13 if prec == spt.F64 else reduced_tol(p)), (rep, e)
 
 
+@pytest.mark.parametrize("N,R", [(7000, 3), (16384, 64), (LONG_N, 2)])
+def test_forced_chunks_match_per_tile(spt, monkeypatch, N, R):
+    """The chunked product on plans whose windows would fit whole (forced by
+    SPT_SPMM_WINDOW=chunk): the same bits as the per-tile product."""
+    say("forced chunks", N, R)
+    monkeypatch.setenv("SPT_SPMM_WINDOW", "chunk")
+    p = spt.Plan("legendre", N, 1e-7).precompute()
+    monkeypatch.setenv("SPT_SPMM_WINDOW", "0")
+    q = spt.Plan("legendre", N, 1e-7).precompute()
+    monkeypatch.delenv("SPT_SPMM_WINDOW")
+    assert p.info()["window_chunked"] == 1 and q.info()["window_lds"] == 0
+    X = workloads.rhs("normal", R, N, 75)
+    assert np.array_equal(run(spt, p, X, spt.SPLIT_BF16), run(spt, q, X, spt.SPLIT_BF16))
+
+
 def test_batch_of_windowed_plans_matches_single(spt):
     """A staged split-bf16 batch whose plans all have windows runs only the
     chunked product's items (the per-tile item list holds one padding entry);
