@@ -174,6 +174,17 @@ def large_workload(args, spt, workloads):
         st = spt.profile_end()
         out["paths"][name] = {"value": total_r * steps / t, "ms_per_step": 1e3 * t / steps,
                               "kernel_ms": {k: v[0] / max(v[1], 1) for k, v in st.items() if v[1]}}
+        # matrix-core work of the product as issued: every stored box entry
+        # (complex, zeros inside the boxes included) times every right-hand
+        # side, 4 flop each (Re a Re z - Im a Im z), six piece products in
+        # split-bf16
+        km = out["paths"][name]["kernel_ms"].get("spmm")
+        if km:
+            flop = sum(p.info()["stored"] * w["nrhs"] for p, w in zip(plans, ws)) * 4.0
+            flop *= 6.0 if name == "split_bf16" else 1.0
+            peak = 2500.0 if name == "split_bf16" else 78.6
+            out["paths"][name]["product_tflops"] = flop / (km * 1e-3) / 1e12
+            out["paths"][name]["product_mfma_frac"] = flop / (km * 1e-3) / 1e12 / peak
         log(name, out["paths"][name])
         del X, Y
     return out
