@@ -574,17 +574,22 @@ def test_batched_staged_matches_single_plans(spt):
                 assert e <= (1e-13 if prec == spt.F64 else reduced_tol(p)), (rep, e)
 
 
-@pytest.mark.parametrize("N,R", [(7000, 3), (16384, 64), (LONG_N, 2)])
-def test_forced_chunks_match_per_tile(spt, monkeypatch, N, R):
+@pytest.mark.parametrize("fam,N,R", [("legendre", 7000, 3), ("legendre", 16384, 64),
+                                     ("legendre", LONG_N, 2), ("chebyshev_t", 3000, 130)])
+def test_forced_chunks_match_per_tile(spt, monkeypatch, fam, N, R):
     """The chunked product on plans whose windows would fit whole (forced by
-    SPT_SPMM_WINDOW=chunk): the same bits as the per-tile product."""
-    say("forced chunks", N, R)
+    SPT_SPMM_WINDOW=chunk): the same bits as the per-tile product; a first
+    block of four-step transforms (N = 24000), no direct tail (Chebyshev, one
+    two-sided block), several right-hand-side chunks."""
+    say("forced chunks", fam, N, R)
     monkeypatch.setenv("SPT_SPMM_WINDOW", "chunk")
-    p = spt.Plan("legendre", N, 1e-7).precompute()
+    p = spt.Plan(fam, N, 1e-7).precompute()
     monkeypatch.setenv("SPT_SPMM_WINDOW", "0")
-    q = spt.Plan("legendre", N, 1e-7).precompute()
+    q = spt.Plan(fam, N, 1e-7).precompute()
     monkeypatch.delenv("SPT_SPMM_WINDOW")
     assert p.info()["window_chunked"] == 1 and q.info()["window_lds"] == 0
+    if fam == "chebyshev_t":
+        assert p.info()["tail"] == 0
     X = workloads.rhs("normal", R, N, 75)
     assert np.array_equal(run(spt, p, X, spt.SPLIT_BF16), run(spt, q, X, spt.SPLIT_BF16))
 
