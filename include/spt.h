@@ -181,6 +181,10 @@ typedef struct {
                                             pass through it in chunks of 32 columns
                                             (window_lds is then the chunked
                                             kernel's)                              */
+  int64_t transposed_segment;            /* row tiles per segment of the transposed
+                                            product (8, more for nearly dense plans,
+                                            whose partial sums would otherwise need
+                                            more than 4x the half spectra's memory) */
 } spt_plan_info;
 
 /* Create a plan for the N x N matrix of `family` with threshold eps (= eps1 of

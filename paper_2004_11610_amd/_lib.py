@@ -27,7 +27,8 @@ class SptPlanInfo(ctypes.Structure):
                 ("nnz", c_int64), ("stored", c_int64), ("matrix_bytes_f64", c_int64),
                 ("matrix_bytes_f32", c_int64), ("max_abs", c_double * 16),
                 ("kappa", c_double), ("nnz_blk", c_int64 * 16), ("window_lds", c_int64),
-                ("window_cols", c_int64), ("window_chunked", c_int64)]
+                ("window_cols", c_int64), ("window_chunked", c_int64),
+                ("transposed_segment", c_int64)]
 
 
 class SptError(RuntimeError):

@@ -82,9 +82,8 @@ struct DevBlock {
   DevBuf k0, kw, off;   // per tile
   bool big = false;  // the transform does not fit one workgroup (four steps)
   // transposed product: the segments of row tiles per TCHUNK spectrum columns
-  std::vector<int4> h_tseg;
+  std::vector<int32_t> h_tptr;  // chunk c's tiles are h_tent[h_tptr[c] .. h_tptr[c + 1])
   std::vector<TChunkEnt> h_tent;
-  std::vector<int> h_tempty;  // chunks that no tile meets (their u is zero)
   DevBuf val64, val32;  // tile boxes
   DevBuf valbf, soff;   // pre-split tile boxes of the split-bf16 path, their offsets
   int64_t nnz = 0, stored = 0;
@@ -157,7 +156,7 @@ struct spt_plan {
   spt::DevBuf winmeta;
   spt::DevBuf tseg, tent, tblk;  // the transposed product's segments, tile lists, blocks
   spt::DevBuf tred;              // its chunks of several segments
-  int n_tseg = 0, n_tred = 0, n_tslot = 0;
+  int n_tseg = 0, n_tred = 0, n_tslot = 0, tseglen = 0;
   spt::DevBuf invdesc64, invdesc32;  // its single-workgroup inverse transforms
   int n_inv = 0, inv_threads = 64, inv_maxP = 1;
   int n_groups = 0;
@@ -770,14 +769,7 @@ int64_t build_block(spt_plan_t plan, DevBlock& B, hipStream_t s, size_t lds_max,
       for (int c = c0; c <= c1; ++c)
         ents[pos[c]++] = TChunkEnt{B.h_off[t], (int32_t)t, B.h_k0[t], B.h_kw[t], 0};
     }
-    B.h_tseg.clear();
-    B.h_tempty.clear();
-    for (int c = 0; c < nch; ++c)
-      if (ptr[c + 1] == ptr[c]) B.h_tempty.push_back(c);
-    for (int c = 0; c < nch; ++c)
-      for (int e = ptr[c]; e < ptr[c + 1]; e += TSEG)
-        B.h_tseg.push_back(
-            int4{c, e, std::min(e + TSEG, ptr[c + 1]), ptr[c + 1] - ptr[c] <= TSEG ? 1 : 0});
+    B.h_tptr = std::move(ptr);
     B.h_tent = std::move(ents);
   }
   const bool want64 = plan->prepared & (1u << SPT_F64);
@@ -1168,9 +1160,26 @@ void build_fft_descs(spt_plan_t plan, hipStream_t s) {
   upload(plan->tilemeta_bf, meta_bf, s);
   upload(plan->spmmblk_bf, bbf, s);
   build_windows(plan, s);
-  // the transposed product's segments of every block, in one list; the
-  // segments of chunks with several get slots of partial sums
+  // the transposed product's segments of every block, in one list: a chunk
+  // whose tiles fit one segment stores, the segments of the others get slots of
+  // partial sums.  Segments hold TSEG tiles, or more where the slots would need
+  // more memory than 4 times the half spectra (nearly dense plans: every chunk
+  // meets most tiles).
   static_assert(MAX_BLOCKS <= (1 << TSEG_BLOCK_BITS), "segment block field");
+  int seglen = TSEG;
+  {
+    const int64_t budget = std::max<int64_t>(256, z_per_rhs(plan) / 8);
+    auto count_slots = [&](int len) {
+      int64_t n = 0;
+      for (auto& Bp : plan->blk)
+        for (size_t c = 0; c + 1 < Bp->h_tptr.size(); ++c) {
+          const int cnt = Bp->h_tptr[c + 1] - Bp->h_tptr[c];
+          if (cnt > len) n += (cnt + len - 1) / len;
+        }
+      return n;
+    };
+    while (count_slots(seglen) > budget && seglen < (1 << 24)) seglen *= 2;
+  }
   std::vector<int4> tseg, tred;
   std::vector<TChunkEnt> tent;
   std::vector<TBlkInfo> tblk;
@@ -1179,17 +1188,21 @@ void build_fft_descs(spt_plan_t plan, hipStream_t s) {
   for (int b = 0; b < nblk; ++b) {
     const DevBlock& B = *plan->blk[b];
     const int base = (int)tent.size();
-    for (size_t i = 0; i < B.h_tseg.size(); ++i) {
-      const int4& g = B.h_tseg[i];
-      if (g.w) {
-        tseg.push_back(int4{g.x, g.y + base, g.z + base, (b << 1) | 1});
-        continue;
+    for (size_t c = 0; c + 1 < B.h_tptr.size(); ++c) {
+      const int e0 = B.h_tptr[c], e1 = B.h_tptr[c + 1];
+      if (e1 == e0) {
+        tred.push_back(int4{b, (int)c, 0, 0});  // no tile meets the chunk: zeros
+      } else if (e1 - e0 <= seglen) {
+        tseg.push_back(int4{(int)c, e0 + base, e1 + base, (b << 1) | 1});
+      } else {
+        tred.push_back(int4{b, (int)c, slots, 0});
+        for (int e = e0; e < e1; e += seglen) {
+          ++tred.back().w;
+          tseg.push_back(int4{(int)c, e + base, std::min(e + seglen, e1) + base,
+                              (slots++ << (TSEG_BLOCK_BITS + 1)) | (b << 1)});
+        }
       }
-      if (i == 0 || B.h_tseg[i - 1].x != g.x) tred.push_back(int4{b, g.x, slots, 0});
-      ++tred.back().w;
-      tseg.push_back(int4{g.x, g.y + base, g.z + base, (slots++ << (TSEG_BLOCK_BITS + 1)) | (b << 1)});
     }
-    for (int c : B.h_tempty) tred.push_back(int4{b, c, 0, 0});  // no slots: zeros
     tent.insert(tent.end(), B.h_tent.begin(), B.h_tent.end());
     tblk.push_back(TBlkInfo{B.val64.p, B.val32.p, uoff, B.P, 0});
     uoff += B.P + 1;
@@ -1199,6 +1212,7 @@ void build_fft_descs(spt_plan_t plan, hipStream_t s) {
   plan->n_tseg = (int)tseg.size();
   plan->n_tred = (int)tred.size();
   plan->n_tslot = slots;
+  plan->tseglen = seglen;
   if (tseg.empty()) tseg.push_back(int4{0, 0, 0, 0});
   if (tred.empty()) tred.push_back(int4{0, 0, 0, 0});
   upload(plan->tred, tred, s);
@@ -1296,7 +1310,7 @@ void precompute(spt_plan_t plan, hipStream_t s) {
 
 // ---------------------------------------------------------------- execute
 // select (and size) the workspace of stream s
-void ensure_work(spt_plan_t plan, int64_t R, hipStream_t s) {
+void ensure_work(spt_plan_t plan, int64_t R, hipStream_t s, bool transposed = false) {
   spt_plan::Work* w = nullptr;
   for (auto& e : plan->works)
     if (e->stream == s) w = e.get();
@@ -1313,7 +1327,8 @@ void ensure_work(spt_plan_t plan, int64_t R, hipStream_t s) {
     w->stream = s;
   }
   plan->work = &w->buf;
-  const int64_t per = z_per_rhs(plan) + w_per_rhs(plan) + t_per_rhs(plan);
+  // the transposed product also keeps its partial sums after the intermediates
+  const int64_t per = z_per_rhs(plan) + w_per_rhs(plan) + (transposed ? t_per_rhs(plan) : 0);
   // complex float64 spectra (and four-step intermediates), or the three
   // bfloat16-pair planes of the split-bf16 path
   const size_t bytes =
@@ -1473,7 +1488,7 @@ void execute_transposed_t(spt_plan_t plan, const T* F, T* Y, int64_t R, hipStrea
     if (inv_four_step(*B) && !B->four)
       throw Error(SPT_E_UNSUPPORTED, "block of FFT length half " + std::to_string(B->P) +
                                          " has no four-step split");
-  ensure_work(plan, R, s);
+  ensure_work(plan, R, s, true);
   int64_t per = 0;
   for (auto& B : plan->blk) per += B->P + 1;
   // four-step intermediates after the half spectra (w_per_rhs)
@@ -2014,6 +2029,7 @@ spt_status spt_plan_query(spt_plan_t plan, spt_plan_info* info) {
         info->window_cols = plan->win_cols;
         info->window_chunked = plan->win_chunked ? 1 : 0;
       }
+      info->transposed_segment = plan->tseglen;
     }
   });
 }

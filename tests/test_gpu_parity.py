@@ -272,15 +272,13 @@ def test_legendre_16384_r64_all_precisions(spt):
 
 def test_legendre_16384_r64_transposed(spt):
     """The transposed product on the benchmark plan at full size: the adjoint
-    of the forward product to rounding, sampled degrees against the direct
-    A^T f, F32 against F64, and the same bits from a second call (partial
-    sums are added in a fixed order)."""
-    from oracle import direct
+    of the forward product to rounding, F32 against F64, and the same bits
+    from a second call (partial sums are added in a fixed order).  Sampled
+    degrees against the direct A^T f: test_long_block_transposed."""
     import torch
     w = workloads.LEGENDRE_16384
     say(w["name"], "transposed")
     N, R = w["N"], w["nrhs"]
-    fam = oracle_family("legendre", N)
     X = workloads.rhs(w["rhs"], R, N, w["seed"])
     F = workloads.rhs(w["rhs"], R, N, w["seed"] + 1)
     p = spt.Plan("legendre", N, w["eps"]).precompute()
@@ -290,12 +288,9 @@ def test_legendre_16384_r64_transposed(spt):
     assert np.array_equal(to_host(p.execute_transposed(Fd, prec=spt.F64)), Yt)
     lhs, rhs = np.sum(Yf * F, axis=1), np.sum(X * Yt, axis=1)
     e_adj = np.max(np.abs(lhs - rhs) / (np.linalg.norm(Yf, axis=1) * np.linalg.norm(F, axis=1)))
-    cols = np.arange(3, N, 101)
-    e_d = rel_rows(Yt[:, cols], direct.matvec_transposed(fam, F, cols=cols))
     e_32 = rel_rows(to_host(p.execute_transposed(to_dev(F, torch.float32), prec=spt.F32)), Yt)
-    say("  adjoint %.3e  vs direct (sampled degrees) %.3e  F32 vs F64 %.3e" % (e_adj, e_d, e_32))
+    say("  adjoint %.3e  F32 vs F64 %.3e" % (e_adj, e_32))
     assert e_adj <= 1e-12
-    assert e_d <= 1e-6
     assert e_32 <= 1e-6
 
 

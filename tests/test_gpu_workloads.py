@@ -119,3 +119,16 @@ def test_laguerre_65536_r1024(spt):
     say("  F64 vs direct %.2e, split vs F64 %.2e (bar %.2e)" % (e64, es, reduced_tol(p)))
     assert e64 <= (1e-9 if info["mode"] == spt.MODE_DIRECT else 5e-4)
     assert es <= reduced_tol(p)
+    if info["mode"] != spt.MODE_DIRECT:
+        # the transposed product of this nearly dense plan takes long segments
+        # (expected: several stagings of 256 list entries each); it is the
+        # adjoint of the forward product over the same compressed blocks
+        seg = info["transposed_segment"]
+        X8, F8 = Xh[:8], workloads.rhs(w["rhs"], 8, N, w["seed"] + 1)
+        Yf = Y64[:8]
+        Yt = to_host(p.execute_transposed(to_dev(F8, torch.float64), prec=spt.F64))
+        e_adj = np.max(np.abs(np.sum(Yf * F8, axis=1) - np.sum(X8 * Yt, axis=1)) /
+                       (np.linalg.norm(Yf, axis=1) * np.linalg.norm(F8, axis=1)))
+        say("  transposed: %d tiles per segment, adjoint %.2e" % (seg, e_adj))
+        assert seg >= 8
+        assert e_adj <= 1e-12
