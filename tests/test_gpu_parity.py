@@ -346,6 +346,26 @@ def test_transposed_fp64(spt, fam, N, eps, kw, R):
     assert rel_rows(Y32, Y) <= reduced_tol(p)
 
 
+@pytest.mark.parametrize("fam,N,R", [("legendre", 300, 3), ("hermite_fn", 257, 70)])
+def test_transposed_direct_mode(spt, fam, N, R):
+    """A plan in DIRECT mode (the whole matrix as the direct tail, no blocks):
+    the transposed product is A^T f by the tail kernel alone, against the
+    oracle's direct product; F32 against F64."""
+    from oracle import direct
+    import torch
+    say("transposed direct mode", fam, N, R)
+    f = oracle_family(fam, N)
+    p = spt.Plan(fam, N, 1e-7, mode=spt.MODE_DIRECT, nodes=f.nodes()).precompute()
+    assert p.info()["mode"] == spt.MODE_DIRECT and p.info()["tail"] == N
+    F = workloads.rhs("normal", R, N, 91)
+    Y = to_host(p.execute_transposed(to_dev(F, torch.float64), prec=spt.F64))
+    e = rel_rows(Y, direct.matvec_transposed(f, F))
+    say("  rel vs direct %.3e" % e)
+    assert e <= 1e-12
+    Y32 = to_host(p.execute_transposed(to_dev(F, torch.float32), prec=spt.F32))
+    assert rel_rows(Y32, Y) <= 1e-5
+
+
 @pytest.mark.parametrize("fam,N,kw", [
     ("legendre", 7000, {}), ("jacobi", 9000, dict(alpha=-0.5, beta=-0.5))])
 def test_transposed_four_step_fp64(spt, monkeypatch, fam, N, kw):
