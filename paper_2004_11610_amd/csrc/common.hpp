@@ -332,7 +332,7 @@ void launch_exec_fft_multi_split(const FftDesc<float>* descs, int nblk, int thre
 // The transposed product gathers by columns of the half spectrum: the row
 // tiles whose boxes meet columns [TCHUNK c, TCHUNK c + TCHUNK) of a block.
 constexpr int TCHUNK = 32;
-constexpr int TSEG = 8;    // row tiles per segment (one workgroup each)
+constexpr int TSEG = 8;    // row tiles per segment (one workgroup each), at least
 constexpr int TSEG_BLOCK_BITS = 5;  // block field of a segment (MAX_BLOCKS <= 32)
 struct TChunkEnt {
   int64_t off;             // the tile's first stored value

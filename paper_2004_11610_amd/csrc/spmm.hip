@@ -699,8 +699,10 @@ __global__ __launch_bounds__(256) void spmm_presplit_items_kernel(SpmmSplitBatch
 // u[r][k] = c'_k sum_n Add[n][k] f[r][n] over the half spectrum (c'_k = 1 at
 // k = 0 and P, else 1/2: the c_k folded into the stored values taken out).
 // By columns: the row tiles whose boxes meet the columns [TCHUNK c, TCHUNK c +
-// TCHUNK) of a block are listed at precompute and split into segments of at
-// most TSEG tiles; one launch takes the segments of every block.  Workgroup
+// TCHUNK) of a block are listed at precompute and split into segments (TSEG
+// tiles, longer on nearly dense plans, whose partial sums would otherwise
+// outgrow the workspace); one launch takes the segments of every block.  The
+// list entries are staged 256 at a time.  Workgroup
 // (s, g) takes segment s for the right-hand sides 64 g .. 64 g + 63, staging
 // the tiles' f values (64 x 16) and box columns (16 x TCHUNK) in LDS two tiles
 // at a time (the next two are requested before the current ones are used).
