@@ -613,7 +613,8 @@ def test_batch_of_windowed_plans_matches_single(spt):
     """A staged split-bf16 batch whose plans all have windows runs only the
     chunked product's items (the per-tile item list holds one padding entry);
     a plan whose FFTs are four-step items in both paths (P = 15000) gives the
-    same bits batched, alone or beside another plan, as executed singly."""
+    same bits batched, alone or beside another plan, as executed singly; with
+    a plan without windows in the batch, both product launches run."""
     import torch
     say("batch of windowed plans")
     big = spt.Plan("legendre", LONG_N, 1e-7).precompute()
@@ -626,6 +627,17 @@ def test_batch_of_windowed_plans_matches_single(spt):
         Ys = [torch.full_like(x, float("nan")) for x in Xl]
         spt.execute_batched(plans, Xl, Ys, prec=spt.SPLIT_BF16)
         assert np.array_equal(to_host(Ys[-1]), ref)
+    # with a plan that has no windows (DIRECT mode: per-tile items) in the
+    # same batch, both product launches run
+    dense = spt.Plan("hermite_fn", 300, 1e-7, mode=spt.MODE_DIRECT).precompute()
+    assert dense.info()["window_lds"] == 0
+    Xd = to_dev(workloads.rhs("normal", 70, 300, 76), torch.float32)
+    refd = to_host(dense.execute(Xd, prec=spt.SPLIT_BF16))
+    Ys = [torch.full_like(x, float("nan")) for x in (Xs, Xd, Xb)]
+    spt.execute_batched([small, dense, big], [Xs, Xd, Xb], Ys, prec=spt.SPLIT_BF16)
+    assert np.array_equal(to_host(Ys[2]), ref)
+    assert rel_rows(to_host(Ys[1]), refd) <= 1e-6
+    assert np.all(np.isfinite(to_host(Ys[0])))
 
 
 @pytest.mark.parametrize("R", [256, 300, 513])
