@@ -1440,6 +1440,13 @@ void execute_staged_t(spt_plan_t plan, const T* X, T* Y, int64_t R, int prec, hi
     sa.Y = Y;
     sa.R = (int)R;
     sa.N = plan->N;
+    if constexpr (std::is_same<T, double>::value) {
+      // windows too wide for LDS: the chunked float64 product
+      if (plan->win_ok && plan->win_chunked) {
+        launch_spmm_chunk_f64(sa, plan->winmeta.as<WinMeta>(), plan->n_groups, st);
+        return;
+      }
+    }
     launch_spmm<T>(sa, st);
   };
 

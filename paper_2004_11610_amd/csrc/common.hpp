@@ -293,6 +293,9 @@ struct WinMeta {
 // Plans whose windows do not fit: the same windows (k0, w4 only) staged in
 // chunks; LDS bytes of a workgroup for a tail pitch tpad.
 size_t spmm_chunk_lds_bytes(int tpad);
+// the float64 matrix-core product through the same chunked windows
+void launch_spmm_chunk_f64(const SpmmArgs<double>& a, const WinMeta* win, int n_groups,
+                           hipStream_t s);
 void launch_spmm_chunk(const SpmmSplitArgs& a, const WinMeta* win, int n_groups, int tpad,
                        hipStream_t s);
 void launch_spmm_window(const SpmmSplitArgs& a, const WinMeta* win, int n_groups, int rg,

@@ -649,6 +649,187 @@ __device__ __forceinline__ void chunk_group(const SpmmSplitArgs& args,
   }
 }
 
+// The chunked windows for the float64 matrix-core product (spmm_mfma_kernel's
+// steps): workgroup = WIN_TILES row tiles x 64 right-hand sides, wave = one
+// tile (four groups of 16 right-hand sides); each chunk of a block's union
+// window lands in LDS as complex float64 values, row i for right-hand side
+// r0 + i (one 16-byte unit per column).  A tile's steps are taken in the
+// per-tile product's order, so the sums are the same bits.
+constexpr int CKF_COLS = 4 * (CK_G + CK_HALO);  // columns of a staged chunk
+constexpr int CKF_PITCH = CKF_COLS + 1;         // odd row pitch (16-byte units)
+constexpr int CKF_UNITS = CK_NR * CKF_PITCH;    // units of one buffer
+static_assert(CKF_UNITS % 64 == 0, "chunk buffer layout");
+
+__global__ __launch_bounds__(256) void spmm_chunk_f64_kernel(SpmmArgs<double> args,
+                                                             const WinMeta* __restrict__ win,
+                                                             int n_groups) {
+  using E = EngF64;
+  using C = double2;
+  constexpr int NR = CK_NR, RG = NR / 16;
+  extern __shared__ __align__(16) C zc[];
+  const int grp = xcd_tile(blockIdx.x, n_groups);
+  const int r0 = blockIdx.y * NR;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int m = lane & 15, g = lane >> 4;
+  const int nblk = args.nblk;
+  const int tile = grp * WIN_TILES + wave;
+  const bool has_tile = tile < args.n_tiles;  // wave-uniform
+
+  int wk0_l = 0, ww4_l = 0, k0_l = 0, kw_l = 0, ldz_l = 0;
+  int64_t off_l = 0, val_l = 0, zoff_l = 0;
+  if (lane < nblk) {
+    const WinMeta wm = win[(int64_t)grp * nblk + lane];
+    wk0_l = wm.k0;
+    ww4_l = wm.w4;
+    const SpmmBlock<double> bd = args.blocks[lane];
+    val_l = (int64_t)(uintptr_t)bd.val;
+    zoff_l = bd.zoff;
+    ldz_l = bd.ldz;
+    if (has_tile) {
+      const TileMeta tm = args.meta[(int64_t)tile * nblk + lane];
+      k0_l = tm.k0;
+      kw_l = tm.kw;
+      off_l = tm.off;
+    }
+  }
+  __builtin_amdgcn_s_waitcnt(0);
+  int cstart_l = 0, nch = 0;
+  for (int bb = 0; bb < nblk; ++bb) {
+    if (lane == bb) cstart_l = nch;
+    nch += (lane_i32(ww4_l, bb) + CK_G - 1) / CK_G;
+  }
+  const int cend_l = cstart_l + (lane < nblk ? (ww4_l + CK_G - 1) / CK_G : 0);
+  auto block_of = [&](int c) { return (int)__popcll(__ballot(lane < nblk && cend_l <= c)); };
+
+  // chunk c (block b, columns 4 CK_G j .. + ncol - 1 of the window) into
+  // buffer c & 1; columns past the window, or past a spectrum row (P + 1
+  // values: a window ends on a multiple of 4 columns), repeat the last one,
+  // right-hand sides past R the last one
+  auto stage = [&](int c) {
+    const int b = block_of(c);
+    const int j = c - lane_i32(cstart_l, b);
+    const int ncol = 4 * min(CK_G + CK_HALO, lane_i32(ww4_l, b) - CK_G * j);
+    const int64_t ldz = lane_i32(ldz_l, b);
+    const int c0 = lane_i32(wk0_l, b) + 4 * CK_G * j;  // <= P: a chunk starts inside its window
+    const int cmax = min(ncol, (int)ldz - c0) - 1;
+    const C* __restrict__ zw = args.Z + (int64_t)args.R * lane_i64(zoff_l, b) + c0;
+    C* __restrict__ dst = zc + (c & 1) * CKF_UNITS;
+    for (int cc = wave; cc * 64 < CKF_UNITS; cc += 4) {
+      const int u = cc * 64 + lane;
+      const int row = u / CKF_PITCH, col = min(u - row * CKF_PITCH, cmax);
+      const int64_t rhs = min(r0 + row, args.R - 1);
+      __builtin_amdgcn_global_load_lds(reinterpret_cast<const char*>(zw + rhs * ldz + col),
+                                       dst + cc * 64, 16, 0, 0);
+    }
+  };
+  // the tile's steps in chunk c (at most 2) and their matrix values: step s
+  // covers box columns 16 s .. 16 s + 15, lane (m, g) column 16 s + 4 g + j of row m
+  auto load_a = [&](int c, C (*Ar)[4], int& s_lo, int& ns) {
+    const int b = block_of(c);
+    const int j = c - lane_i32(cstart_l, b);
+    const int base = (lane_i32(k0_l, b) - lane_i32(wk0_l, b)) >> 2;
+    const int kw = lane_i32(kw_l, b);
+    const int S = (kw + 15) >> 4;
+    const int lo = max(0, (CK_G * j - base + 3) >> 2);
+    const int hi = min(S, (CK_G * j + CK_G - base + 3) >> 2);
+    s_lo = lo;
+    ns = has_tile ? max(0, hi - lo) : 0;
+    const C* __restrict__ val = (const C*)(uintptr_t)lane_i64(val_l, b) + lane_i64(off_l, b);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) {
+        const int col = 16 * (lo + i) + 4 * g + jj;
+        Ar[i][jj] = (i < ns && col < kw) ? gload(val + (int64_t)col * TILE_ROWS + m) : C{0.0, 0.0};
+      }
+  };
+
+  C Acur[2][4], Anext[2][4];
+  int slo_c = 0, ns_c = 0, slo_n = 0, ns_n = 0;
+  if (nch > 0) {
+    stage(0);
+    load_a(0, Acur, slo_c, ns_c);
+  }
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+
+  typename E::Acc acc[RG];
+#pragma unroll
+  for (int q = 0; q < RG; ++q) acc[q] = E::zero();
+  for (int c = 0; c < nch; ++c) {
+    if (c + 1 < nch) {
+      stage(c + 1);
+      load_a(c + 1, Anext, slo_n, ns_n);
+    }
+    if (ns_c > 0) {
+      const int b = block_of(c);
+      const int j = c - lane_i32(cstart_l, b);
+      const int base = (lane_i32(k0_l, b) - lane_i32(wk0_l, b)) >> 2;
+      const int ncol = 4 * min(CK_G + CK_HALO, lane_i32(ww4_l, b) - CK_G * j);
+      const C* __restrict__ zb = zc + (c & 1) * CKF_UNITS + m * CKF_PITCH;
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        if (i < ns_c) {
+#pragma unroll
+          for (int q = 0; q < RG; ++q) {
+            C z[4];
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj) {
+              // columns past the tile's box (zero matrix values) may read
+              // the chunk's last staged column, a finite value
+              const int lc = min(4 * (base + 4 * (slo_c + i) - CK_G * j) + 4 * g + jj, ncol - 1);
+              z[jj] = zb[16 * q * CKF_PITCH + lc];
+            }
+            acc[q] = E::step(Acur[i], z, acc[q]);
+          }
+        }
+      }
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) Acur[i][jj] = Anext[i][jj];
+    slo_c = slo_n;
+    ns_c = ns_n;
+  }
+  if (!has_tile) return;
+
+  // direct tail (as spmm_mfma_kernel, per group of 16 right-hand sides)
+  const int64_t n0 = (int64_t)tile * TILE_ROWS;
+  const int64_t ldt = (int64_t)args.n_tiles * TILE_ROWS;
+#pragma unroll
+  for (int q = 0; q < RG; ++q) {
+    const int r = r0 + 16 * q + m;
+    const bool rok = r < args.R;
+    const int64_t rr = rok ? r : r0 + 16 * q;
+    const bool qok = r0 + 16 * q < args.R;  // wave-uniform
+    if (!qok) continue;
+    const double* __restrict__ xr = args.X + rr * args.N;  // rr < R (qok)
+    for (int ks = 0; ks < args.tail; ks += 32) {
+      double av[8], xv[8];
+#pragma unroll
+      for (int jj = 0; jj < 8; ++jj) {
+        const int mm = ks + 8 * g + jj;
+        const bool ok = mm < args.tail;
+        av[jj] = ok ? args.tailmat[(int64_t)mm * ldt + n0 + m] : 0.0;
+        xv[jj] = (ok && rok) ? xr[mm] : 0.0;
+      }
+      acc[q] = E::step_real(av, xv, acc[q]);
+    }
+    if (rok) {
+      double* __restrict__ y = args.Y + (int64_t)r * args.N + n0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = E::row(g, i);
+        if (n0 + row < args.N) y[row] = acc[q][i];
+      }
+    }
+  }
+}
+
 __global__ __launch_bounds__(256) void spmm_chunk_kernel(SpmmSplitArgs args,
                                                          const WinMeta* __restrict__ win,
                                                          int n_groups, int tpad) {
@@ -936,6 +1117,13 @@ void launch_spmm_chunk_items(const SpmmSplitBatch& b, int n_items, size_t lds, h
   SPT_HIP(hipGetLastError());
 }
 
+void launch_spmm_chunk_f64(const SpmmArgs<double>& a, const WinMeta* win, int n_groups,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(spmm_chunk_f64_kernel, dim3(n_groups, (a.R + CK_NR - 1) / CK_NR), dim3(256),
+                     (size_t)2 * CKF_UNITS * sizeof(double2), s, a, win, n_groups);
+  SPT_HIP(hipGetLastError());
+}
+
 size_t spmm_chunk_lds_bytes(int tpad) {
   return (size_t)2 * CK_UNITS * 16 + (size_t)CK_NR * tpad * sizeof(float);
 }
@@ -972,6 +1160,8 @@ void init_spmm_kernels(size_t max_lds) {
   SPT_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(spmm_chunk_kernel),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_lds));
   SPT_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(spmm_chunk_items_kernel),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_lds));
+  SPT_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(spmm_chunk_f64_kernel),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_lds));
   done.push_back(dev);
 }

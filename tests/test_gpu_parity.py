@@ -592,8 +592,9 @@ def test_batched_staged_matches_single_plans(spt):
 @pytest.mark.parametrize("fam,N,R", [("legendre", 7000, 3), ("legendre", 16384, 64),
                                      ("legendre", LONG_N, 2), ("chebyshev_t", 3000, 130)])
 def test_forced_chunks_match_per_tile(spt, monkeypatch, fam, N, R):
-    """The chunked product on plans whose windows would fit whole (forced by
-    SPT_SPMM_WINDOW=chunk): the same bits as the per-tile product; a first
+    """The chunked products (split-bf16 and float64) on plans whose windows
+    would fit whole (forced by SPT_SPMM_WINDOW=chunk): the same bits as the
+    per-tile products; a first
     block of four-step transforms (N = 24000), no direct tail (Chebyshev, one
     two-sided block), several right-hand-side chunks."""
     say("forced chunks", fam, N, R)
@@ -606,6 +607,7 @@ def test_forced_chunks_match_per_tile(spt, monkeypatch, fam, N, R):
     if fam == "chebyshev_t":
         assert p.info()["tail"] == 0
     X = workloads.rhs("normal", R, N, 75)
+    assert np.array_equal(run(spt, p, X, spt.F64), run(spt, q, X, spt.F64))
     assert np.array_equal(run(spt, p, X, spt.SPLIT_BF16), run(spt, q, X, spt.SPLIT_BF16))
 
 
@@ -708,3 +710,6 @@ def test_windowed_product_matches_per_tile(spt, monkeypatch, fam, N, R, kw, rg):
         assert info["window_chunked"] == 1
     X = workloads.rhs("normal", R, N, 97)
     assert np.array_equal(run(spt, p, X, spt.SPLIT_BF16), run(spt, q, X, spt.SPLIT_BF16))
+    if info["window_chunked"]:
+        # the float64 product through the same chunked windows
+        assert np.array_equal(run(spt, p, X, spt.F64), run(spt, q, X, spt.F64))
