@@ -1965,6 +1965,15 @@ spt_status spt_execute_batched(const spt_plan_t* plans, const void* const* X, vo
     }
     set_device(plans[0]);
     hipStream_t s = static_cast<hipStream_t>(stream);
+    if (count == 1 && uses_staged(plans[0])) {
+      // one plan: its own staged launches (fused FFT, windowed or chunked
+      // product in every precision), as spt_execute
+      if (prec == SPT_F64)
+        execute_staged_t<double>(plans[0], (const double*)X[0], (double*)Y[0], nrhs[0], prec, s);
+      else
+        execute_staged_t<float>(plans[0], (const float*)X[0], (float*)Y[0], nrhs[0], prec, s);
+      return;
+    }
     for (int i = 0; i < count; ++i) ensure_work(plans[i], nrhs[i], s);
     std::lock_guard<std::mutex> lk(g_batch_mu);
     // persistent when the first plan asks for it, staged launches otherwise
