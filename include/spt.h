@@ -227,8 +227,10 @@ spt_status spt_execute_transposed(spt_plan_t plan, const void* X, void* Y, int64
  * on `stream`: Y[i] = A_i X[i]^T with nrhs[i] right-hand sides.  X, Y, nrhs
  * are host arrays of `count` entries holding device pointers / counts.  Every
  * 64 plans run together: with the executor of plans[0] PERSISTENT, as one
- * launch of the persistent executor; otherwise as three launches (the FFT
- * items of every plan in two, then every plan's banded products in one).  The
+ * launch of the persistent executor; otherwise as the FFT items of every plan
+ * in two launches, then the banded products (split-bf16: one launch for the
+ * plans with windows, one for the others; a batch of a single plan runs that
+ * plan's own launches, as spt_execute).  The
  * first call for a set of plans and sizes builds the work lists (host work and
  * a stream synchronisation), later calls reuse them.  A plan may appear once
  * per batch.  Batches of the same plans on different streams use each plan's
