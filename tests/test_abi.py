@@ -122,3 +122,29 @@ def test_user_nodes_are_copied():
     assert p.info()["N"] == 50
     with pytest.raises(spt.SptError):
         spt.Plan("legendre", 3, 1e-7, nodes=[0.1, float("nan"), 0.3])
+
+
+def test_plan_info_layout_matches_header():
+    """The binding's spt_plan_info mirrors include/spt.h field by field: the
+    header's member names in order equal the ctypes fields, and a plan that is
+    not precomputed reports its host-side values with the device-side ones
+    (windows, segments) zero."""
+    with open(os.path.join(ROOT, "include", "spt.h")) as f:
+        text = f.read()
+    end = text.index("} spt_plan_info;")
+    body = text[text.rindex("typedef struct {", 0, end):end]
+    body = re.sub(r"/\*.*?\*/", "", body[body.index("{") + 1:], flags=re.S)
+    names = []
+    for decl in body.split(";"):
+        words = decl.split()
+        if not words:
+            continue
+        # "type a, b[16]": the declarators after the type
+        for d in " ".join(words[1:]).split(","):
+            names.append(re.sub(r"\[\d+\]", "", d).strip())
+    assert names == [f for f, _ in _lib.SptPlanInfo._fields_]
+    p = spt.Plan("legendre", 4096, 1e-7)
+    info = p.info()
+    assert info["N"] == 4096 and info["precomputed"] == 0 and info["n_blocks"] > 0
+    assert info["window_lds"] == 0 and info["window_chunked"] == 0
+    assert info["transposed_segment"] == 0
