@@ -215,6 +215,28 @@ def test_transposed_thresholded_accuracy():
     assert e <= 3e-7
 
 
+@pytest.mark.parametrize("fam_id,N,kw", [(matrix.JACOBI, 400, dict(alpha=0.5, beta=1.5)),
+                                         (matrix.CHEBYSHEV_T, 300, {}),
+                                         (matrix.HERMITE_FN, 200, {})])
+def test_transposed_is_adjoint_of_compressed(fam_id, N, kw):
+    """With the threshold on, the transposed method (Alg. 2/4: sparse product,
+    inverse DFT, division by the window, truncation) is the exact adjoint of
+    the row-compressed method over the same blocks (sec. 3): <A_c x, f> =
+    <x, A_c^T f> to rounding, while both differ from A by the compression
+    error.  The two share no arithmetic beyond the stored blocks."""
+    fam = matrix.MatrixFamily(fam_id, N, **kw)
+    C = compressed.Compressed(compressed.Plan(fam, 1e-6, 1e-2))
+    rng = np.random.default_rng(13)
+    X, F = rng.standard_normal((2, N)), rng.standard_normal((2, N))
+    Yf, Yt = C.execute(X), transposed.execute(C, F)
+    lhs, rhs_ = np.sum(Yf * F, axis=1), np.sum(X * Yt, axis=1)
+    scale = np.linalg.norm(Yf, axis=1) * np.linalg.norm(F, axis=1)
+    assert np.max(np.abs(lhs - rhs_) / scale) <= 1e-13
+    # ... and the threshold is on: the compressed product is not A
+    Yd = direct.matvec(fam, X)
+    assert rel(Yf, Yd) > 1e-12
+
+
 # ------------------------------------------------------------------ Appendix A
 APPA_FAMS = [(matrix.CHEBYSHEV_T, {}), (matrix.SINE, {}), (matrix.COS_POWER, dict(power=2)),
              (matrix.COS_POWER, dict(power=3))]
