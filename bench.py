@@ -118,10 +118,10 @@ def measured_traffic(kernel):
         return None
 
 
-def cpu_baseline(w, X, rows_sample=16384):
+def cpu_baseline(w, X, rows_sample=16384, compressed_leg=True):
     """The oracle's direct float64 product (A from its recurrences, then BLAS),
     timed on a sample of output rows (all of them by default) and scaled to all
-    N rows."""
+    N rows; beside it, the oracle's compressed method on the same plan."""
     import numpy as np
     from threadpoolctl import threadpool_info
     from oracle import direct, matrix
@@ -134,10 +134,29 @@ def cpu_baseline(w, X, rows_sample=16384):
     t = time.perf_counter() - t0
     threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
     value = X.shape[0] / (t * w["N"] / rows.size)
-    return {"value": value, "unit": "RHS-transforms/s", "cores": int(threads), "kind": "oracle",
-            "sample": "direct float64 product (recurrence-built A, BLAS) on %d of %d rows, all %d "
-                      "right-hand sides, %.1f s, scaled to all rows" % (rows.size, w["N"],
-                                                                        X.shape[0], t)}
+    out = {"value": value, "unit": "RHS-transforms/s", "cores": int(threads), "kind": "oracle",
+           "sample": "direct float64 product (recurrence-built A, BLAS) on %d of %d rows, all %d "
+                     "right-hand sides, %.1f s, scaled to all rows" % (rows.size, w["N"],
+                                                                       X.shape[0], t)}
+    if compressed_leg:
+        # the oracle's compressed method (full spectrum, scipy.sparse): its
+        # precomputation once (not part of the rate), then executes of all the
+        # right-hand sides
+        from oracle import compressed
+        t0 = time.perf_counter()
+        comp = compressed.Compressed(compressed.Plan(fam, w["eps"], 1e-2))
+        t_pre = time.perf_counter() - t0
+        reps = 3
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            comp.execute(X)
+        t = (time.perf_counter() - t0) / reps
+        out["compressed"] = {"value": X.shape[0] / t, "unit": "RHS-transforms/s",
+                             "cores": int(threads), "precompute_s": t_pre,
+                             "sample": "the oracle's compressed method (numpy FFTs, scipy.sparse "
+                                       "product), all %d rows and %d right-hand sides, mean of "
+                                       "%d executes" % (w["N"], X.shape[0], reps)}
+    return out
 
 
 def large_workload(args, spt, workloads):
@@ -196,6 +215,9 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cpu-compressed", action="store_true",
+                    help="skip the oracle's compressed method in the CPU baseline (its "
+                         "precomputation takes about a minute)")
     ap.add_argument("--streams", type=int, default=4,
                     help="streams the timed steps are dealt to in turn (independent "
                          "batches in flight at once; 1 = strictly one after another)")
@@ -297,6 +319,27 @@ def main():
         log("time transposed", name)
         res_t[name] = measure(plan, prec, X, torch.empty_like(Y), transposed=True)
         log("transposed", name, res_t[name])
+    # cold caches: before every timed execute a 1 GiB buffer is written, which
+    # evicts the L2s and the 256 MB Infinity Cache; the execute (HIP events on
+    # its stream) then reads the plan and x from HBM
+    log("cold-cache executes")
+    cold = {}
+    flush = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+    for name, (prec, X, Y) in paths.items():
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(20)]
+        for a, b in ev:
+            flush.fill_(1.0)
+            a.record()
+            plan.execute(X, Y, prec=prec)
+            b.record()
+        torch.cuda.synchronize()
+        ms = sorted(a.elapsed_time(b) for a, b in ev)
+        med = ms[len(ms) // 2]
+        cold[name] = {"ms_per_execute": med, "value": R / (med * 1e-3),
+                      "note": "median of 20 executes, each after a 1 GiB write"}
+    del flush
+    log("cold", cold)
     # the one-launch persistent executor on the same workload, for comparison
     pers = spt.Plan("legendre", N, w["eps"], executor=spt.EXECUTOR_PERSISTENT).precompute()
     log("time split_bf16, persistent executor")
@@ -307,18 +350,25 @@ def main():
 
     split = res["split_bf16"]
     km = split["kernel_ms"]
-    # the two launches of the split-bf16 step: spectra and matrix travel as
-    # three bfloat16 pieces (12 bytes per complex value), x and y as float32
+    # the two launches of the split-bf16 step.  Algorithmic bytes count the
+    # method's data at the path's precision: 8 bytes per complex value of the
+    # compressed blocks and of the half spectra, 4 per real of x and y.  The
+    # library's layout stores both as three bfloat16 pieces (12 bytes per
+    # complex value); those bytes are reported as layout_bytes_per_launch, and
+    # what HBM actually moved as traffic (rocprofv3 counters).
     spmm_kernel = "spmm_window_kernel" if info["window_lds"] > 0 else "spmm_presplit_kernel"
-    launches = {"fft": ("exec_fft_multi_kernel<float, true>", fft_bytes(plan, R, 12, 4)),
-                "spmm": (spmm_kernel, product_bytes(plan, R, 12, 4))}
+    launches = {"fft": ("exec_fft_multi_kernel<float, true>", fft_bytes(plan, R, 8, 4),
+                        fft_bytes(plan, R, 12, 4)),
+                "spmm": (spmm_kernel, product_bytes(plan, R, 8, 4),
+                         product_bytes(plan, R, 12, 4))}
 
     def roofline(stage):
-        name, nbytes = launches[stage]
+        name, nbytes, layout = launches[stage]
         achieved = nbytes / (km[stage] * 1e-3) / 1e9
         return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(stage),
-                "kernel": name, "bytes_per_launch": nbytes, "avg_launch_ms": km[stage]}
+                "kernel": name, "bytes_per_launch": nbytes, "layout_bytes_per_launch": layout,
+                "avg_launch_ms": km[stage]}
 
     dominant = max(launches, key=lambda k: km.get(k, 0.0))
     roof = roofline(dominant)
@@ -354,13 +404,14 @@ def main():
         "rel_err_vs_f64": err,
         "roofline": roof,
         "roofline_other_launches": other,
-        "stage_bytes_per_step": algorithmic_bytes(plan, R, 12, 4),
+        "stage_bytes_per_step": algorithmic_bytes(plan, R, 8, 4),
+        "cold": cold,
         "kernel_sources_sha256": kernel_source_hash(),
         "precompute_s": t_pre,
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline(w, Xh)
+        out["cpu_baseline"] = cpu_baseline(w, Xh, compressed_leg=not args.no_cpu_compressed)
     print(json.dumps(out), flush=True)
 
 

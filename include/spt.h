@@ -238,6 +238,33 @@ spt_status spt_execute_transposed(spt_plan_t plan, const void* X, void* Y, int64
 spt_status spt_execute_batched(const spt_plan_t* plans, const void* const* X, void* const* Y,
                                const int64_t* nrhs, int32_t count, int32_t prec, void* stream);
 
+/* Device memory of the library (compressed blocks, tables, workspaces, work
+ * lists).  With a hook pair set, every later allocation calls
+ * alloc(bytes, stream, ctx), which returns device memory of the current device
+ * aligned to 256 bytes, or NULL when it has none (the call that needed it then
+ * returns SPT_E_OOM and leaves its plan valid: a later call allocates again);
+ * stream is the stream of the call that allocates (NULL for the null stream).
+ * Each buffer is freed through the hook that allocated it, with the same
+ * stream and ctx, once no launch uses it (plans free theirs in
+ * spt_plan_destroy, after a device synchronisation).  Both NULL restores
+ * hipMalloc / hipFree for later allocations; giving one hook alone is
+ * SPT_E_INVALID_ARG.  Process-wide; buffers allocated before the call keep
+ * their allocator.  Lets a framework's caching allocator (PyTorch's, say)
+ * own the memory. */
+typedef void* (*spt_alloc_fn)(size_t bytes, void* stream, void* ctx);
+typedef void (*spt_free_fn)(void* ptr, void* stream, void* ctx);
+spt_status spt_set_allocator(spt_alloc_fn alloc, spt_free_fn free_, void* ctx);
+
+/* Bound of a dependency wait of the persistent executor (SPT_EXECUTOR_PERSISTENT)
+ * for this plan's launches and the batches it leads (plans[0]), in ticks of
+ * the 100 MHz wall clock; 0 restores the default of 1e8 (1 s).  A wait that
+ * reaches the bound gives up: the launch drains, the outputs that waited hold
+ * NaN, and the next persistent execute on the same plans and sizes returns
+ * SPT_E_HIP without running (the call after it runs normally).  For tests of
+ * that path; waits end without it, since items only wait for items taken
+ * before them.  Synchronises the device when contexts exist. */
+spt_status spt_plan_set_exec_wait(spt_plan_t plan, int64_t ticks);
+
 /* Plan summary; info is a host struct filled by the call. */
 spt_status spt_plan_query(spt_plan_t plan, spt_plan_info* info);
 

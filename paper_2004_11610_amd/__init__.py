@@ -112,6 +112,10 @@ class Plan:
             out.ctypes.data_as(ctypes.POINTER(c_double))))
         return out
 
+    def set_exec_wait(self, ticks):
+        """Bound of the persistent executor's dependency waits (100 MHz ticks, 0 = 1 s)."""
+        _lib.check(self._lib.spt_plan_set_exec_wait(self._h, c_int64(int(ticks))))
+
     # ------------------------------------------------------------------ work
     def precompute(self, stream=None):
         _lib.check(self._lib.spt_precompute(self._h, _stream_ptr(stream)))
@@ -148,9 +152,16 @@ class Plan:
 
 
 def execute_batched(plans, Xs, Ys, prec=F64, stream=None):
-    """Y_i = X_i A_i^T for every plan, recorded once in a HIP graph and replayed."""
+    """Y_i = X_i A_i^T for every plan (spt_execute_batched: the plans' FFTs and
+    products in shared launches, or one persistent launch)."""
     prec = PRECISIONS.get(prec, prec)
     n = len(plans)
+    if len(Xs) != n or len(Ys) != n:
+        raise ValueError("plans, Xs and Ys must have the same length")
+    for p, x, y in zip(plans, Xs, Ys):
+        if y is None:
+            raise ValueError("execute_batched needs every output tensor")
+        p._check_io(x, y, prec)
     hp = (c_void_p * n)(*[p.handle.value for p in plans])
     xs = (c_void_p * n)(*[x.data_ptr() for x in Xs])
     ys = (c_void_p * n)(*[y.data_ptr() for y in Ys])
@@ -159,6 +170,51 @@ def execute_batched(plans, Xs, Ys, prec=F64, stream=None):
     _lib.check(lib.spt_execute_batched(hp, xs, ys, rs, c_int32(n), c_int32(prec),
                                        _stream_ptr(stream)))
     return Ys
+
+
+_hooks = None  # the ctypes callbacks of spt_set_allocator, kept alive while set
+
+
+def set_allocator(alloc=None, free=None):
+    """Route the library's device memory through alloc(bytes, stream) -> int
+    pointer (0 when out of memory) and free(ptr, stream) (spt_set_allocator);
+    with no arguments, back to hipMalloc / hipFree.  Buffers keep the
+    allocator that made them, so the hooks stay referenced here for good."""
+    global _hooks
+    lib = _lib.load()
+    if alloc is None and free is None:
+        _lib.check(lib.spt_set_allocator(_lib.ALLOC_FN(), _lib.FREE_FN(), None))
+        return
+
+    def _a(n, stream, ctx):
+        try:
+            return int(alloc(int(n), int(stream or 0)) or 0)
+        except Exception:
+            return 0
+
+    def _f(ptr, stream, ctx):
+        free(int(ptr), int(stream or 0))
+
+    hooks = (_lib.ALLOC_FN(_a), _lib.FREE_FN(_f))
+    _lib.check(lib.spt_set_allocator(hooks[0], hooks[1], None))
+    _kept.append(hooks)
+    _hooks = hooks
+
+
+_kept = []
+
+
+def use_torch_allocator():
+    """Let PyTorch's caching allocator own the library's device memory."""
+    import torch
+
+    def alloc(n, stream):
+        return torch.cuda.caching_allocator_alloc(n, stream=stream)
+
+    def free(ptr, stream):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    set_allocator(alloc, free)
 
 
 STAGES = ("fft", "spmm", "spmm_t", "inv_fft", "tail_t", "exec")

@@ -31,6 +31,10 @@ class SptPlanInfo(ctypes.Structure):
                 ("transposed_segment", c_int64)]
 
 
+ALLOC_FN = ctypes.CFUNCTYPE(c_void_p, ctypes.c_size_t, c_void_p, c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, c_void_p, c_void_p, c_void_p)
+
+
 class SptError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__("%s (%d): %s" % (ERRORS.get(code, "?"), code, msg))
@@ -59,6 +63,8 @@ def load():
         "spt_execute_batched": [POINTER(c_void_p), POINTER(c_void_p), POINTER(c_void_p),
                                 POINTER(c_int64), c_int32, c_int32, c_void_p],
         "spt_plan_query": [c_void_p, POINTER(SptPlanInfo)],
+        "spt_plan_set_exec_wait": [c_void_p, c_int64],
+        "spt_set_allocator": [ALLOC_FN, FREE_FN, c_void_p],
         "spt_plan_nodes": [c_void_p, POINTER(c_double)],
         "spt_plan_compressed_rows": [c_void_p, c_int32, c_int64, c_int64, POINTER(c_double)],
         "spt_plan_destroy": [c_void_p],

@@ -29,27 +29,59 @@ int64_t next_serial() {
 }
 
 // ---------------------------------------------------------------- device buffers
+// The allocator of device memory (spt_set_allocator): a caller's hook pair, or
+// hipMalloc / hipFree when none is set.  A buffer remembers the hook that
+// allocated it and is freed through the same one.
+struct Allocator {
+  spt_alloc_fn alloc = nullptr;
+  spt_free_fn free = nullptr;
+  void* ctx = nullptr;
+};
+std::mutex g_alloc_mu;
+Allocator g_alloc;
+
+Allocator current_allocator() {
+  std::lock_guard<std::mutex> lk(g_alloc_mu);
+  return g_alloc;
+}
+
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  Allocator a;             // who allocated p
+  hipStream_t st = nullptr;  // the stream passed to the hook
   DevBuf() = default;
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
   ~DevBuf() { reset(); }
   void reset() {
-    if (p) (void)hipFree(p);
+    if (p) {
+      if (a.free)
+        a.free(p, st, a.ctx);
+      else
+        (void)hipFree(p);
+    }
     p = nullptr;
     bytes = 0;
   }
-  void alloc(size_t n) {
+  void alloc(size_t n, hipStream_t s = nullptr) {
     reset();
     if (n == 0) return;
-    hipError_t e = hipMalloc(&p, n);
-    if (e != hipSuccess) {
-      p = nullptr;
-      (void)hipGetLastError();
-      throw Error(SPT_E_OOM, "hipMalloc(" + std::to_string(n) + " bytes) failed: " +
-                                 hipGetErrorString(e));
+    a = current_allocator();
+    st = s;
+    if (a.alloc) {
+      p = a.alloc(n, s, a.ctx);
+      if (!p)
+        throw Error(SPT_E_OOM, "the allocator hook returned NULL for " + std::to_string(n) +
+                                   " bytes");
+    } else {
+      hipError_t e = hipMalloc(&p, n);
+      if (e != hipSuccess) {
+        p = nullptr;
+        (void)hipGetLastError();
+        throw Error(SPT_E_OOM, "hipMalloc(" + std::to_string(n) + " bytes) failed: " +
+                                   hipGetErrorString(e));
+      }
     }
     bytes = n;
   }
@@ -61,7 +93,7 @@ struct DevBuf {
 
 template <typename T>
 void upload(DevBuf& b, const std::vector<T>& h, hipStream_t s) {
-  b.alloc(h.size() * sizeof(T));
+  b.alloc(h.size() * sizeof(T), s);
   if (!h.empty()) {
     SPT_HIP(hipMemcpyAsync(b.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
     SPT_HIP(hipStreamSynchronize(s));
@@ -104,6 +136,23 @@ struct ExecCtx {
   std::vector<int64_t> key;
   DevBuf plans, blocks, items, sync;
   int n_items = 0, n_sync = 0, grid = 0;
+  // persistent launches: a host-visible word that the launch's last workgroup
+  // sets when a dependency wait gave up, and an event after the launch; the
+  // next launch on the context reports it
+  uint32_t* herr = nullptr;
+  uint32_t* derr = nullptr;
+  hipEvent_t done = nullptr;
+  bool pending = false;
+  ExecCtx() = default;
+  ExecCtx(const ExecCtx&) = delete;
+  ExecCtx& operator=(const ExecCtx&) = delete;
+  ~ExecCtx() {
+    if (done) {
+      (void)hipEventSynchronize(done);
+      (void)hipEventDestroy(done);
+    }
+    if (herr) (void)hipHostFree(herr);
+  }
   DevBuf items2;  // staged FFT: the row items (second launch)
   int n_items2 = 0;
   int ntw = 0;     // largest twiddle table (entries) of the blocks
@@ -170,6 +219,7 @@ struct spt_plan {
   int fft_wgP = 1;  // most points of one workgroup of the fused FFT
   int64_t serial = 0;  // changes with every precompute (keys of executor contexts)
   std::vector<std::unique_ptr<spt::ExecCtx>> ctx;  // executor contexts of spt_execute
+  uint32_t exec_wait = spt::EXEC_WAIT_DEFAULT;      // persistent executor: wait bound, ticks
 };
 
 namespace spt {
@@ -979,6 +1029,9 @@ void build_exec_ctx(ExecCtx& c, const spt_plan_t* plans, const int64_t* R, int c
   c.n_sync = nsync;
   c.sync.alloc((size_t)nsync * sizeof(uint32_t));
   SPT_HIP(hipMemsetAsync(c.sync.p, 0, c.sync.bytes, s));
+  const uint32_t wait = plans[0]->exec_wait;
+  SPT_HIP(hipMemcpyAsync(c.sync.as<uint32_t>() + EXEC_SYNC_WAIT, &wait, sizeof(wait),
+                         hipMemcpyHostToDevice, s));
   SPT_HIP(hipStreamSynchronize(s));
   init_exec_kernels();
   if (exec_lds_bytes<T>(c.ntw) + 256 > max_lds_bytes(plans[0]->device))
@@ -1339,7 +1392,7 @@ void ensure_work(spt_plan_t plan, int64_t R, hipStream_t s, bool transposed = fa
     // work lists hold the old workspace address; work in flight may use them
     SPT_HIP(hipDeviceSynchronize());
     plan->ctx.clear();
-    plan->work->alloc(bytes);
+    plan->work->alloc(bytes, s);
   }
 }
 
@@ -1618,13 +1671,37 @@ void staged(int stage, hipStream_t s, F&& fn) {
 // ---------------------------------------------------------------- persistent executor
 bool uses_staged(spt_plan_t plan) { return plan->p.executor != SPT_EXECUTOR_PERSISTENT; }
 
+// Report a dependency wait that gave up in the previous persistent launch on
+// context c (its outputs hold NaN).  Waits for that launch: launches on one
+// context run in stream order anyway, and the word is reused by the next one.
+void check_exec_error(ExecCtx& c) {
+  if (!c.pending) return;
+  SPT_HIP(hipEventSynchronize(c.done));
+  c.pending = false;
+  if (__atomic_load_n(c.herr, __ATOMIC_ACQUIRE) != 0) {
+    *c.herr = 0;
+    throw Error(SPT_E_HIP,
+                "persistent executor: a dependency wait of the previous launch on these plans "
+                "and sizes gave up (its outputs hold NaN); this call did not run");
+  }
+}
+
 template <typename T>
 void run_exec(ExecCtx& c, const void* const* X, void* const* Y, int count, int prec,
               hipStream_t s) {
+  check_exec_error(c);
+  if (!c.herr) {
+    SPT_HIP(hipHostMalloc((void**)&c.herr, sizeof(uint32_t),
+                          hipHostMallocMapped | hipHostMallocCoherent));
+    *c.herr = 0;
+    SPT_HIP(hipHostGetDevicePointer((void**)&c.derr, c.herr, 0));
+    SPT_HIP(hipEventCreateWithFlags(&c.done, hipEventDisableTiming));
+  }
   ExecArgs<T> a{};
   a.plans = c.plans.as<ExecPlan<T>>();
   a.items = c.items.as<int4>();
   a.sync = c.sync.as<uint32_t>();
+  a.err_out = c.derr;
   a.n_items = c.n_items;
   a.n_sync = c.n_sync;
   a.ntw = c.ntw;
@@ -1633,7 +1710,10 @@ void run_exec(ExecCtx& c, const void* const* X, void* const* Y, int count, int p
     a.Y[i] = static_cast<T*>(Y[i]);
   }
   staged(SPT_STAGE_EXEC, s, [&] { launch_exec<T>(a, engine_of(prec), c.grid, s); });
+  SPT_HIP(hipEventRecord(c.done, s));
+  c.pending = true;
 }
+
 
 int xcd_tile_host(int b, int n) {
   const int n8 = n >> 3;
@@ -1787,6 +1867,25 @@ ExecCtx& plan_ctx(spt_plan_t plan, int64_t R, int prec, hipStream_t s, bool stag
 // contexts of batched launches (a few recent sets of plans)
 std::mutex g_batch_mu;
 std::vector<std::unique_ptr<ExecCtx>> g_batch_ctx;
+
+// new bound of the persistent executor's dependency waits of this plan: its
+// own contexts and the batch contexts that it leads (plans[0] of the batch)
+void set_exec_wait(spt_plan_t plan, uint32_t ticks) {
+  plan->exec_wait = ticks;
+  std::vector<ExecCtx*> cs;
+  for (auto& c : plan->ctx) cs.push_back(c.get());
+  {
+    std::lock_guard<std::mutex> lk(g_batch_mu);
+    for (auto& c : g_batch_ctx)
+      if (c->key.size() > 3 && c->key[3] == plan->serial) cs.push_back(c.get());
+  }
+  if (cs.empty()) return;
+  set_device(plan);
+  SPT_HIP(hipDeviceSynchronize());  // launches in flight read the old bound
+  for (ExecCtx* c : cs)
+    SPT_HIP(hipMemcpy(c->sync.as<uint32_t>() + EXEC_SYNC_WAIT, &ticks, sizeof(ticks),
+                      hipMemcpyHostToDevice));
+}
 
 template <typename F>
 spt_status guard(F&& fn) {
@@ -2008,6 +2107,25 @@ spt_status spt_execute_batched(const spt_plan_t* plans, const void* const* X, vo
         run_exec<float>(*c, X + i0, Y + i0, n, prec, s);
       }
     }
+  });
+}
+
+spt_status spt_set_allocator(spt_alloc_fn alloc, spt_free_fn free_, void* ctx) {
+  return guard([&] {
+    if ((alloc == nullptr) != (free_ == nullptr))
+      throw Error(SPT_E_INVALID_ARG, "give both hooks or neither");
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    g_alloc.alloc = alloc;
+    g_alloc.free = free_;
+    g_alloc.ctx = alloc ? ctx : nullptr;
+  });
+}
+
+spt_status spt_plan_set_exec_wait(spt_plan_t plan, int64_t ticks) {
+  return guard([&] {
+    check_plan(plan);
+    if (ticks < 0 || ticks > 0xffffffffll) throw Error(SPT_E_INVALID_ARG, "ticks out of range");
+    set_exec_wait(plan, ticks == 0 ? EXEC_WAIT_DEFAULT : (uint32_t)ticks);
   });
 }
 

@@ -12,9 +12,9 @@ namespace {
 using namespace fftcore;
 using namespace spmmcore;
 
-// a wait gives up after this long (wall clock, 100 MHz ticks) or once another
-// wait has given up; what the waiting item writes is then NaN
-constexpr uint64_t WAIT_TICKS = 100000000ull;  // 1 s
+// a wait gives up after sync[EXEC_SYNC_WAIT] ticks of the 100 MHz wall clock
+// (1 s unless the host set another bound) or once another wait of the launch
+// has given up; what the waiting item writes is then NaN
 
 __device__ __forceinline__ uint32_t ld_relaxed(const uint32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -24,12 +24,13 @@ __device__ __forceinline__ uint32_t ld_relaxed(const uint32_t* p) {
 __device__ bool wait_count(uint32_t* sync, const uint32_t* p, uint32_t target) {
   if (__builtin_amdgcn_readfirstlane(ld_relaxed(p)) >= target) return true;
   const uint64_t t0 = wall_clock64();
+  const uint64_t limit = __builtin_amdgcn_readfirstlane(ld_relaxed(sync + EXEC_SYNC_WAIT));
   for (int it = 1;; ++it) {
     __builtin_amdgcn_s_sleep(2);
     if (__builtin_amdgcn_readfirstlane(ld_relaxed(p)) >= target) return true;
-    if ((it & 63) == 0) {
+    if ((it & 7) == 0) {
       if (__builtin_amdgcn_readfirstlane(ld_relaxed(sync + EXEC_SYNC_ERR)) != 0) return false;
-      if (wall_clock64() - t0 > WAIT_TICKS) {
+      if (wall_clock64() - t0 > limit) {
         __hip_atomic_store(sync + EXEC_SYNC_ERR, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         return false;
       }
@@ -509,7 +510,9 @@ __global__ __launch_bounds__(EXEC_THREADS) __attribute__((amdgpu_waves_per_eu(4)
     __syncthreads();
     cur ^= 1;
   }
-  // the last workgroup to finish clears the queue and every counter
+  // the last workgroup to finish reports whether a wait gave up (to the
+  // host-visible word) and clears the queue, the counters and that flag; the
+  // host-set wait bound stays
   if (tid == 0) {
     release();
     const uint32_t d = __hip_atomic_fetch_add(sync + EXEC_SYNC_DONE, 1u, __ATOMIC_ACQ_REL,
@@ -519,8 +522,12 @@ __global__ __launch_bounds__(EXEC_THREADS) __attribute__((amdgpu_waves_per_eu(4)
   __syncthreads();
   if (s_flag) {
     acquire();
+    if (tid == 0 && a.err_out)
+      __hip_atomic_store(a.err_out, ld_relaxed(sync + EXEC_SYNC_ERR), __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_SYSTEM);
+    __syncthreads();
     for (int i = tid; i < a.n_sync; i += EXEC_THREADS)
-      if (i != EXEC_SYNC_ERR) sync[i] = 0u;
+      if (i != EXEC_SYNC_WAIT) sync[i] = 0u;
   }
 }
 

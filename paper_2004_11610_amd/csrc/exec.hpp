@@ -34,8 +34,10 @@ constexpr int EXEC_POINTS = EXEC_THREADS * EXEC_EPT;  // complex points of one w
 constexpr int EXEC_MAX_PLANS = 64;  // plans of one launch (X, Y travel as arguments)
 constexpr int EXEC_SYNC_HEAD = 0;   // next item
 constexpr int EXEC_SYNC_DONE = 1;   // finished workgroups
-constexpr int EXEC_SYNC_ERR = 2;    // set by a wait that gave up (sticky)
+constexpr int EXEC_SYNC_ERR = 2;    // set by a wait that gave up (sticky within a launch)
+constexpr int EXEC_SYNC_WAIT = 3;   // bound of a dependency wait, 100 MHz ticks (host-set)
 constexpr int EXEC_SYNC_BASE = 4;   // dependency counters start here
+constexpr uint32_t EXEC_WAIT_DEFAULT = 100000000u;  // 1 s
 
 enum : int { ITEM_FFT = 0, ITEM_COL = 1, ITEM_ROW = 2, ITEM_SPMM = 3 };
 
@@ -89,6 +91,7 @@ struct ExecArgs {
   const ExecPlan<T>* plans;
   const int4* items;
   uint32_t* sync;
+  uint32_t* err_out;         // host-visible word: the launch's EXEC_SYNC_ERR at its end
   int n_items, n_sync;
   int ntw;                   // entries of the largest twiddle table (LDS copies)
   const T* X[EXEC_MAX_PLANS];

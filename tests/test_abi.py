@@ -148,3 +148,38 @@ def test_plan_info_layout_matches_header():
     assert info["N"] == 4096 and info["precomputed"] == 0 and info["n_blocks"] > 0
     assert info["window_lds"] == 0 and info["window_chunked"] == 0
     assert info["transposed_segment"] == 0
+
+
+def test_exec_wait_bound_arguments():
+    lib = _lib.load()
+    assert lib.spt_plan_set_exec_wait(None, 0) == -1
+    p = spt.Plan("legendre", 64, 1e-7, executor=spt.EXECUTOR_PERSISTENT)
+    p.set_exec_wait(1)   # no launch context yet: host state only
+    p.set_exec_wait(0)
+    with pytest.raises(spt.SptError) as e:
+        p.set_exec_wait(-1)
+    assert e.value.code == -1
+
+
+def test_execute_batched_checks_every_tensor():
+    """The binding validates each (plan, X, Y) of a batch before any device
+    call: dtype, device, shape and output size."""
+    import torch
+    p = spt.Plan("legendre", 64, 1e-7)
+    q = spt.Plan("legendre", 96, 1e-7)
+    x = torch.zeros((2, 64), dtype=torch.float64)
+    y = torch.zeros((2, 64), dtype=torch.float64)
+    with pytest.raises(ValueError):   # host tensors
+        spt.execute_batched([p], [x], [y], prec=spt.F64)
+    with pytest.raises(ValueError):   # a float64 X for the float32 paths
+        spt.execute_batched([p], [x], [y], prec=spt.SPLIT_BF16)
+    with pytest.raises(ValueError):   # lengths differ
+        spt.execute_batched([p, q], [x], [y], prec=spt.F64)
+    with pytest.raises(ValueError):   # missing output
+        spt.execute_batched([p], [x], [None], prec=spt.F64)
+
+
+def test_set_allocator_arguments():
+    lib = _lib.load()
+    assert lib.spt_set_allocator(_lib.ALLOC_FN(lambda n, s, c: 0), _lib.FREE_FN(), None) == -1
+    assert lib.spt_set_allocator(_lib.ALLOC_FN(), _lib.FREE_FN(), None) == 0

@@ -510,6 +510,54 @@ def test_persistent_launches_repeat_exactly(spt):
         assert np.array_equal(to_host(p.execute(Xa, prec=spt.SPLIT_BF16)), ya)
 
 
+def test_persistent_wait_give_up_is_reported(spt):
+    """A dependency wait that reaches its bound (set from the host to one
+    tick, so every wait that is not met at once gives up) makes the launch
+    drain with NaN outputs; the next persistent execute on that context
+    reports it as SPT_E_HIP without running, and with the default bound the
+    same context then computes the staged executor's result again."""
+    import torch
+    N, R = 16384, 64
+    say("persistent give-up", N, R)
+    X = to_dev(workloads.rhs("normal", R, N, 43), torch.float64)
+    p = spt.Plan("legendre", N, 1e-7, executor=spt.EXECUTOR_PERSISTENT,
+                 precisions=1 << spt.F64).precompute()
+    q = spt.Plan("legendre", N, 1e-7, precisions=1 << spt.F64).precompute()
+    ref = to_host(q.execute(X, prec=spt.F64))
+    Y = torch.empty_like(X)
+    p.execute(X, Y, prec=spt.F64)
+    torch.cuda.synchronize()
+    p.set_exec_wait(1)
+    p.execute(X, Y, prec=spt.F64)
+    torch.cuda.synchronize()
+    assert np.any(np.isnan(to_host(Y)))
+    with pytest.raises(spt.SptError) as e:
+        p.execute(X, Y, prec=spt.F64)
+    assert e.value.code == -3 and "gave up" in str(e.value)
+    p.set_exec_wait(0)
+    for i in range(2):
+        say("  clean launch", i)
+        y = to_host(p.execute(X, Y, prec=spt.F64))
+        assert np.all(np.isfinite(y))
+        assert rel_rows(y, ref) <= 1e-13
+
+
+def test_nonfinite_precompute_is_numeric_error(spt):
+    """Nodes far outside the Legendre interval overflow the recurrence: the
+    precomputation stops with SPT_E_NUMERIC and leaves the plan valid but not
+    precomputed."""
+    import torch
+    say("numeric error")
+    p = spt.Plan("legendre", 64, 1e-7, mode=spt.MODE_ROW, nodes=np.full(64, 1e200))
+    with pytest.raises(spt.SptError) as e:
+        p.precompute()
+    assert e.value.code == -6
+    assert p.info()["precomputed"] == 0
+    with pytest.raises(spt.SptError) as e:
+        p.execute(torch.zeros((1, 64), dtype=torch.float64, device="cuda"))
+    assert e.value.code == -2
+
+
 # ------------------------------------------------------------------ long blocks
 LONG_N = 24000  # first block L = 30000: P = 15000 > 10240, four-step transforms
 
