@@ -225,6 +225,9 @@ def main():
                     choices=["legendre-n16384-r64", "batch48", "laguerre-fn-n65536-r1024"],
                     help="the headline workload (default), or one of the two large ones "
                          "(timed the same way, reported for the design notes)")
+    ap.add_argument("--reduced-fft", type=int, default=0, choices=[0, 1, 2],
+                    help="arithmetic of the float32 paths' FFTs: 0 chosen by the plan "
+                         "(spt_params.reduced_fft), 1 float32, 2 float64")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (5 launches) and exit: "
                          "the reference reading for the HBM byte counters")
@@ -256,7 +259,7 @@ def main():
     N, R = w["N"], w["nrhs"]
     log("precompute", w["name"])
     t0 = time.perf_counter()
-    plan = spt.Plan("legendre", N, w["eps"]).precompute()
+    plan = spt.Plan("legendre", N, w["eps"], reduced_fft=args.reduced_fft).precompute()
     t_pre = time.perf_counter() - t0
     info = plan.info()
     log("precompute %.2f s, blocks %s, tail %d, nnz %d" % (t_pre, plan.blocks(), info["tail"],
@@ -357,7 +360,9 @@ def main():
     # complex value); those bytes are reported as layout_bytes_per_launch, and
     # what HBM actually moved as traffic (rocprofv3 counters).
     spmm_kernel = "spmm_window_kernel" if info["window_lds"] > 0 else "spmm_presplit_kernel"
-    launches = {"fft": ("exec_fft_multi_kernel<float, true>", fft_bytes(plan, R, 8, 4),
+    fft_kernel = ("exec_fft_multi_kernel<double, float, true>" if info["reduced_fft_f64"]
+                  else "exec_fft_multi_kernel<float, float, true>")
+    launches = {"fft": (fft_kernel, fft_bytes(plan, R, 8, 4),
                         fft_bytes(plan, R, 12, 4)),
                 "spmm": (spmm_kernel, product_bytes(plan, R, 8, 4),
                          product_bytes(plan, R, 12, 4))}
@@ -388,7 +393,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": w["name"], "family": "legendre", "N": N, "nrhs": R,
                    "eps1": w["eps"], "eps2": info["eps2"], "blocks": [b[0] for b in plan.blocks()],
-                   "tail": info["tail"], "nnz": info["nnz"], "parallelism": "single-gpu"},
+                   "tail": info["tail"], "nnz": info["nnz"], "parallelism": "single-gpu",
+                   "reduced_fft_f64": info["reduced_fft_f64"],
+                   "reduced_fft_f32_err": info["reduced_fft_f32_err"]},
         "streams": args.streams,
         "paths": {k: {"value": v["value"], "ms_per_step": v["ms_per_step"],
                       "one_stream": v["one_stream"], "kernel_ms": v["kernel_ms"]}

@@ -150,6 +150,21 @@ typedef struct {
                              near each tone of the row.  The window's side
                              lobes make this an approximation: q = 12 moves an
                              entry by < 0.25 eps max|A_e W F|                     */
+  int32_t reduced_fft;    /* arithmetic of the x-side FFTs (and of the transposed
+                             product's single-workgroup inverse FFTs) of the
+                             SPT_F32 and SPT_SPLIT_BF16 paths, staged executor:
+                             0 -> chosen at spt_precompute from 4 seeded N(0,1)
+                             right-hand sides through the split-bf16 path (the
+                             float32 path if only that is prepared) with float32
+                             FFTs: kept when within 7e-7 of the float64 path
+                             (relative 2-norm), or, without a float64 path,
+                             within 5e-7 of the same path with float64 FFTs;
+                             1 -> float32; 2 -> float64 (float32 in and out,
+                             each spectrum value rounded once to float32).  The
+                             spectra's rounding is amplified by kappa
+                             (spt_plan_info) in the product, so long blocks and
+                             two-sided plans can exceed 1e-6 with float32 FFTs.
+                             The persistent executor always runs float32 FFTs. */
 } spt_params;
 
 typedef struct spt_plan* spt_plan_t;
@@ -185,6 +200,13 @@ typedef struct {
                                             product (8, more for nearly dense plans,
                                             whose partial sums would otherwise need
                                             more than 4x the half spectra's memory) */
+  int64_t reduced_fft_f64;               /* 1: the F32 and SPLIT_BF16 paths' FFTs run
+                                            in float64 arithmetic (spt_params.reduced_fft) */
+  double reduced_fft_f32_err;            /* the measurement behind an automatic choice
+                                            (spt_params.reduced_fft): relative error
+                                            with float32 FFTs against the float64 path
+                                            (or the same path with float64 FFTs); 0
+                                            when not measured                        */
 } spt_plan_info;
 
 /* Create a plan for the N x N matrix of `family` with threshold eps (= eps1 of

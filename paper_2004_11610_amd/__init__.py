@@ -15,6 +15,7 @@ from ._lib import SptError  # noqa: F401
 CHEBYSHEV_T, LEGENDRE, JACOBI, LAGUERRE_FN, HERMITE_FN, SINE, COS_POWER = 1, 2, 3, 4, 5, 6, 7
 F64, F32, SPLIT_BF16 = 0, 1, 2
 MODE_AUTO, MODE_ROW, MODE_DIRECT = 0, 1, 3
+FFT_AUTO, FFT_F32, FFT_F64 = 0, 1, 2
 EXECUTOR_AUTO, EXECUTOR_STAGED, EXECUTOR_PERSISTENT = 0, 1, 2
 FAMILIES = {"chebyshev_t": CHEBYSHEV_T, "legendre": LEGENDRE, "jacobi": JACOBI,
             "laguerre_fn": LAGUERRE_FN, "hermite_fn": HERMITE_FN, "sine": SINE,
@@ -44,7 +45,8 @@ class Plan:
 
     def __init__(self, family, N, eps, alpha=0.0, beta=0.0, eps2=0.0, mode=MODE_AUTO,
                  unweighted=False, precisions=0, min_block=0, exact_fft_len=False,
-                 panel_rows=0, nodes=None, executor=EXECUTOR_AUTO, power=0, trig_conv_q=0):
+                 panel_rows=0, nodes=None, executor=EXECUTOR_AUTO, power=0, trig_conv_q=0,
+                 reduced_fft=0):
         self._lib = _lib.load()
         self._h = c_void_p()
         p = _lib.SptParams()
@@ -54,6 +56,7 @@ class Plan:
         p.executor = int(executor)
         p.power = int(power)
         p.trig_conv_q = int(trig_conv_q)
+        p.reduced_fft = int(reduced_fft)
         self._nodes_buf = None
         if nodes is not None:
             self._nodes_buf = (c_double * N)(*[float(v) for v in nodes])

@@ -11,6 +11,7 @@
 #include <atomic>
 #include <cstdlib>
 #include <mutex>
+#include <random>
 #include <string>
 #include <vector>
 
@@ -161,6 +162,8 @@ struct ExecCtx {
   DevBuf witems;         // split-bf16 staged batch: chunked-product items of windowed plans
   int n_witems = 0;
   size_t wlds = 0;
+  bool fft64 = false;    // plans and blocks describe float64 transforms
+  bool xf = false;       // ... of float32 right-hand sides (the float32 paths)
 };
 
 bool is_jacobi(int f) { return f == SPT_LEGENDRE || f == SPT_JACOBI; }
@@ -220,6 +223,10 @@ struct spt_plan {
   int64_t serial = 0;  // changes with every precompute (keys of executor contexts)
   std::vector<std::unique_ptr<spt::ExecCtx>> ctx;  // executor contexts of spt_execute
   uint32_t exec_wait = spt::EXEC_WAIT_DEFAULT;      // persistent executor: wait bound, ticks
+  // the float32 and split-bf16 paths' x-side FFTs in float64 arithmetic
+  // (spt_params.reduced_fft)
+  bool reduced_fft64 = false;
+  double reduced_fft32_err = 0.0;
 };
 
 namespace spt {
@@ -996,6 +1003,10 @@ void build_exec_ctx(ExecCtx& c, const spt_plan_t* plans, const int64_t* R, int c
       P.Zs = plan->work->as<uint32_t>();
       P.zplane = (int64_t)r * zoff4;
       P.W = reinterpret_cast<C*>(P.Zs + 3 * P.zplane);
+    } else if (dbl && prec == SPT_F32) {
+      // float32 spectra of float64 transforms; the float64 intermediate sits
+      // behind them (at twice their size)
+      P.Zf = plan->work->as<float2>();
     }
     P.meta = plan->tilemeta.as<TileMeta>();
     P.tailmat = (const T*)(dbl ? plan->tail64.p : plan->tail32.p);
@@ -1304,6 +1315,8 @@ void build_fft_descs(spt_plan_t plan, hipStream_t s) {
   upload(plan->invdesc32, inv32, s);
 }
 
+void choose_reduced_fft(spt_plan_t plan, hipStream_t s);
+
 void precompute(spt_plan_t plan, hipStream_t s) {
   set_device(plan);
   const size_t lds_max = max_lds_bytes(plan->device);
@@ -1358,7 +1371,79 @@ void precompute(spt_plan_t plan, hipStream_t s) {
   if (plan->mode == SPT_MODE_DIRECT) plan->tail = plan->N;
   build_tail(plan, s);
   build_fft_descs(plan, s);
+  choose_reduced_fft(plan, s);
   plan->precomputed = true;
+}
+
+template <typename T>
+void execute_staged_t(spt_plan_t plan, const T* X, T* Y, int64_t R, int prec, hipStream_t s);
+
+// Arithmetic of the float32 and split-bf16 paths' x-side FFTs
+// (spt_params.reduced_fft).  The automatic choice runs 4 right-hand sides
+// x ~ N(0, 1) (a fixed seed) through the split-bf16 path (the float32 path
+// when only that is prepared) with float32 FFTs and keeps them when the result
+// is within REDUCED_TOTAL_BUDGET of the float64 path's (relative 2-norm, max
+// over the right-hand sides): 70% of the 1e-6 target, the rest a margin for
+// other inputs.  Without a float64 path the float32 FFTs are compared with
+// float64 ones and kept within REDUCED_FFT32_BUDGET.  What float32 FFTs add is
+// their rounding of the half spectra, amplified in the product by kappa.
+constexpr double REDUCED_TOTAL_BUDGET = 7e-7;
+constexpr double REDUCED_FFT32_BUDGET = 5e-7;
+
+void choose_reduced_fft(spt_plan_t plan, hipStream_t s) {
+  plan->reduced_fft64 = plan->p.reduced_fft == 2;
+  plan->reduced_fft32_err = 0.0;
+  const bool sp = plan->prepared & (1u << SPT_SPLIT_BF16);
+  const bool f32 = plan->prepared & (1u << SPT_F32);
+  const bool f64 = plan->prepared & (1u << SPT_F64);
+  if (plan->p.reduced_fft != 0 || plan->blk.empty() || !(sp || f32)) return;
+  const int prec = sp ? SPT_SPLIT_BF16 : SPT_F32;
+  const int R = 4;
+  const int64_t N = plan->N;
+  const size_t n = (size_t)R * N;
+  std::vector<double> hx(n);
+  std::mt19937_64 gen(0x5eed2004116ull);
+  std::normal_distribution<double> nd;
+  for (double& v : hx) v = nd(gen);
+  std::vector<float> hx32(hx.begin(), hx.end());
+  DevBuf x, y32, yref;
+  upload(x, hx32, s);
+  y32.alloc(n * sizeof(float), s);
+  plan->reduced_fft64 = false;
+  execute_staged_t<float>(plan, x.as<float>(), y32.as<float>(), R, prec, s);
+  std::vector<float> h32(n);
+  std::vector<double> href(n);
+  if (f64) {
+    DevBuf x64;
+    upload(x64, hx, s);
+    yref.alloc(n * sizeof(double), s);
+    execute_staged_t<double>(plan, x64.as<double>(), yref.as<double>(), R, SPT_F64, s);
+    SPT_HIP(hipMemcpyAsync(href.data(), yref.p, n * sizeof(double), hipMemcpyDeviceToHost, s));
+  } else {
+    yref.alloc(n * sizeof(float), s);
+    plan->reduced_fft64 = true;
+    execute_staged_t<float>(plan, x.as<float>(), yref.as<float>(), R, prec, s);
+    std::vector<float> h(n);
+    SPT_HIP(hipMemcpyAsync(h.data(), yref.p, n * sizeof(float), hipMemcpyDeviceToHost, s));
+    SPT_HIP(hipStreamSynchronize(s));
+    href.assign(h.begin(), h.end());
+  }
+  SPT_HIP(hipMemcpyAsync(h32.data(), y32.p, n * sizeof(float), hipMemcpyDeviceToHost, s));
+  SPT_HIP(hipStreamSynchronize(s));
+  double worst = 0.0;
+  for (int r = 0; r < R; ++r) {
+    double num = 0.0, den = 0.0;
+    for (int64_t j = 0; j < N; ++j) {
+      const double a = h32[(size_t)r * N + j], b = href[(size_t)r * N + j];
+      num += (a - b) * (a - b);
+      den += b * b;
+    }
+    if (!(den > 0.0) || !std::isfinite(num))
+      throw Error(SPT_E_NUMERIC, "non-finite or zero result while choosing the FFT arithmetic");
+    worst = std::max(worst, std::sqrt(num / den));
+  }
+  plan->reduced_fft32_err = worst;
+  plan->reduced_fft64 = worst > (f64 ? REDUCED_TOTAL_BUDGET : REDUCED_FFT32_BUDGET);
 }
 
 // ---------------------------------------------------------------- execute
@@ -1413,6 +1498,30 @@ void check_exec(spt_plan_t plan, const void* X, const void* Y, int64_t R, int pr
 
 ExecCtx& plan_ctx(spt_plan_t plan, int64_t R, int prec, hipStream_t s, bool staged);
 
+// The staged FFT items of context c (two launches: single-workgroup transforms
+// and column halves, then row halves), in the context's arithmetic: float64
+// when c.fft64 (a split-bf16 context of float64 FFTs, or a float64 one).
+template <typename T>
+void fft_items_of(ExecCtx& c, const void* const* X, int count, bool split, hipStream_t s) {
+  ExecArgs<T> a{};
+  a.plans = c.plans.as<ExecPlan<T>>();
+  a.ntw = c.ntw;
+  for (int i = 0; i < count; ++i) a.X[i] = X[i];
+  a.items = c.items.as<int4>();
+  a.n_items = c.n_items;
+  launch_fft_items<T>(a, split, c.xf, s);
+  a.items = c.items2.as<int4>();
+  a.n_items = c.n_items2;
+  launch_fft_items<T>(a, split, c.xf, s);
+}
+
+void run_fft_items(ExecCtx& c, const void* const* X, int count, bool split, hipStream_t s) {
+  if (c.fft64)
+    fft_items_of<double>(c, X, count, split, s);
+  else
+    fft_items_of<float>(c, X, count, split, s);
+}
+
 // Staged execution in stream order.  FFTs: when every block's transform fits
 // one workgroup (P <= 10240, the fused kernel's LDS bound in float64), one
 // launch with a workgroup per (block, rhs); otherwise the FFT items, i.e. the
@@ -1440,6 +1549,19 @@ void execute_staged_t(spt_plan_t plan, const T* X, T* Y, int64_t R, int prec, hi
       gx = std::max<int64_t>(gx, B.half ? 2 * R : (R + (1 << B.lbw) - 1) >> B.lbw);
     }
     if constexpr (std::is_same<T, float>::value) {
+      if (plan->reduced_fft64) {
+        size_t lds64 = 16;
+        for (int b = b0; b < b0 + nb; ++b) {
+          const DevBlock& B = *plan->blk[b];
+          lds64 = std::max(lds64, fused_lds_bytes<double>(B.fftw.P << B.lbw, B.fftw.P - 1,
+                                                          128 + B.P / 128 + 1));
+        }
+        launch_exec_fft_multi_x32(plan->fftdesc64.as<FftDesc<double>>() + b0, nb, threads, lds64,
+                                  (int)gx, X, split ? nullptr : plan->work->as<float2>(),
+                                  split ? plan->work->as<uint32_t>() : nullptr,
+                                  (int64_t)R * plan->zper4, (int)R, plan->N, st);
+        return;
+      }
       if (split) {
         launch_exec_fft_multi_split(d + b0, nb, threads, lds, (int)gx, X,
                                     plan->work->as<uint32_t>(), (int64_t)R * plan->zper4, (int)R,
@@ -1507,19 +1629,8 @@ void execute_staged_t(spt_plan_t plan, const T* X, T* Y, int64_t R, int prec, hi
     staged(SPT_STAGE_FFT, s, [&] { fft_fused(0, nblk, s); });
   } else if (nblk > 0) {
     ExecCtx& c = plan_ctx(plan, R, prec, s, true);
-    ExecArgs<T> a{};
-    a.plans = c.plans.as<ExecPlan<T>>();
-    a.ntw = c.ntw;
-    a.X[0] = X;
-    a.Y[0] = Y;
-    staged(SPT_STAGE_FFT, s, [&] {
-      a.items = c.items.as<int4>();
-      a.n_items = c.n_items;
-      launch_fft_items<T>(a, split, s);
-      a.items = c.items2.as<int4>();
-      a.n_items = c.n_items2;
-      launch_fft_items<T>(a, split, s);
-    });
+    const void* xs[1] = {X};
+    staged(SPT_STAGE_FFT, s, [&] { run_fft_items(c, xs, 1, split, s); });
   }
   staged(SPT_STAGE_SPMM, s, [&] { product(s); });
 }
@@ -1572,6 +1683,14 @@ void execute_transposed_t(spt_plan_t plan, const T* F, T* Y, int64_t R, hipStrea
   const bool multi = !inv_four_forced();
   if (multi && plan->n_inv > 0)
     staged(SPT_STAGE_INV_FFT, s, [&] {
+      if constexpr (std::is_same<T, float>::value) {
+        if (plan->reduced_fft64) {
+          launch_inv_fft_multi_x32(plan->invdesc64.as<InvFftDesc<double>>(), plan->n_inv,
+                                   plan->inv_threads, sizeof(double2) * (size_t)plan->inv_maxP,
+                                   u, Y, (int)R, plan->N, s);
+          return;
+        }
+      }
       launch_inv_fft_multi<T>(
           std::is_same<T, double>::value ? (const InvFftDesc<T>*)plan->invdesc64.p
                                          : (const InvFftDesc<T>*)plan->invdesc32.p,
@@ -1706,7 +1825,7 @@ void run_exec(ExecCtx& c, const void* const* X, void* const* Y, int count, int p
   a.n_sync = c.n_sync;
   a.ntw = c.ntw;
   for (int i = 0; i < count; ++i) {
-    a.X[i] = static_cast<const T*>(X[i]);
+    a.X[i] = X[i];
     a.Y[i] = static_cast<T*>(Y[i]);
   }
   staged(SPT_STAGE_EXEC, s, [&] { launch_exec<T>(a, engine_of(prec), c.grid, s); });
@@ -1793,21 +1912,7 @@ template <typename T>
 void run_batch_staged(ExecCtx& c, const void* const* X, void* const* Y, int count, int prec,
                       hipStream_t s) {
   const bool split = std::is_same<T, float>::value && prec == SPT_SPLIT_BF16;
-  ExecArgs<T> a{};
-  a.plans = c.plans.as<ExecPlan<T>>();
-  a.ntw = c.ntw;
-  for (int i = 0; i < count; ++i) {
-    a.X[i] = static_cast<const T*>(X[i]);
-    a.Y[i] = static_cast<T*>(Y[i]);
-  }
-  staged(SPT_STAGE_FFT, s, [&] {
-    a.items = c.items.as<int4>();
-    a.n_items = c.n_items;
-    launch_fft_items<T>(a, split, s);
-    a.items = c.items2.as<int4>();
-    a.n_items = c.n_items2;
-    launch_fft_items<T>(a, split, s);
-  });
+  staged(SPT_STAGE_FFT, s, [&] { run_fft_items(c, X, count, split, s); });
   staged(SPT_STAGE_SPMM, s, [&] {
     if (split) {
       SpmmSplitBatch b{};
@@ -1834,12 +1939,24 @@ void run_batch_staged(ExecCtx& c, const void* const* X, void* const* Y, int coun
   });
 }
 
+// Staged transforms of the float32 paths in float64 arithmetic: when any plan
+// of the set asks for them (a batch then runs all its plans' transforms that
+// way).
+bool wants_fft64(const spt_plan_t* plans, int count, int prec, bool staged) {
+  if (prec == SPT_F64 || !staged) return false;
+  for (int i = 0; i < count; ++i)
+    if (plans[i]->reduced_fft64) return true;
+  return false;
+}
+
 std::unique_ptr<ExecCtx> new_ctx(const std::vector<int64_t>& key, const spt_plan_t* plans,
                                  const int64_t* R, int count, int prec, hipStream_t s,
                                  bool staged = false, bool batch = false) {
   auto c = std::make_unique<ExecCtx>();
   c->key = key;
-  if (prec == SPT_F64)
+  c->fft64 = prec == SPT_F64 || wants_fft64(plans, count, prec, staged);
+  c->xf = c->fft64 && prec != SPT_F64;
+  if (c->fft64)
     build_exec_ctx<double>(*c, plans, R, count, prec, s, staged);
   else
     build_exec_ctx<float>(*c, plans, R, count, prec, s, staged);
@@ -1853,7 +1970,8 @@ std::unique_ptr<ExecCtx> new_ctx(const std::vector<int64_t>& key, const spt_plan
 }
 
 ExecCtx& plan_ctx(spt_plan_t plan, int64_t R, int prec, hipStream_t s, bool staged) {
-  const std::vector<int64_t> key{prec, R, plan->serial, (int64_t)(intptr_t)plan->work->p, staged};
+  const std::vector<int64_t> key{prec, R, plan->serial, (int64_t)(intptr_t)plan->work->p, staged,
+                                 plan->reduced_fft64};
   for (auto& c : plan->ctx)
     if (c->key == key) return *c;
   if (plan->ctx.size() >= 8) {
@@ -1944,6 +2062,8 @@ spt_status spt_plan_create(spt_plan_t* out, int32_t family, const spt_params* p,
     if (prm.executor < SPT_EXECUTOR_AUTO || prm.executor > SPT_EXECUTOR_PERSISTENT)
       throw Error(SPT_E_INVALID_ARG, "unknown executor");
     if (prm.min_block < 0 || prm.panel_rows < 0) throw Error(SPT_E_INVALID_ARG, "negative size");
+    if (prm.reduced_fft < 0 || prm.reduced_fft > 2)
+      throw Error(SPT_E_INVALID_ARG, "reduced_fft must be 0 (automatic), 1 or 2");
     auto plan = std::make_unique<spt_plan>();
     plan->family = family;
     plan->N = N;
@@ -2164,6 +2284,8 @@ spt_status spt_plan_query(spt_plan_t plan, spt_plan_info* info) {
         info->window_chunked = plan->win_chunked ? 1 : 0;
       }
       info->transposed_segment = plan->tseglen;
+      info->reduced_fft_f64 = plan->reduced_fft64 ? 1 : 0;
+      info->reduced_fft_f32_err = plan->reduced_fft32_err;
     }
   });
 }

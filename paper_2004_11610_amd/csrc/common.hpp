@@ -171,6 +171,10 @@ struct InvFftDesc {
 template <typename T>
 void launch_inv_fft_multi(const InvFftDesc<T>* descs, int nblk, int threads, size_t lds,
                           const cplx_t<T>* U, T* Y, int R, int64_t N, hipStream_t s);
+// the float32 path's single-workgroup inverse transforms in float64 arithmetic
+// (float32 U and Y, the float64 descriptors and tables; lds for double2 points)
+void launch_inv_fft_multi_x32(const InvFftDesc<double>* descs, int nblk, int threads, size_t lds,
+                              const float2* U, float* Y, int R, int64_t N, hipStream_t s);
 
 template <typename T>
 struct InvFft4Args {      // transposed execute of a block with P = P1 P2 (four steps)
@@ -330,6 +334,13 @@ void launch_spmm_chunk_items(const SpmmSplitBatch& b, int n_items, size_t lds, h
 void launch_exec_fft_multi_split(const FftDesc<float>* descs, int nblk, int threads, size_t lds,
                                  int gx, const float* X, uint32_t* Zs, int64_t zplane, int R,
                                  int64_t N, hipStream_t s);
+// the float32 paths' transforms in float64 arithmetic (float32 X, the float64
+// descriptors and tables; lds from fused_lds_bytes<double>): each spectrum
+// value is rounded once to float32, then split into the three planes Zs
+// (split-bf16) or stored in Z (float32 path, Zs null)
+void launch_exec_fft_multi_x32(const FftDesc<double>* descs, int nblk, int threads, size_t lds,
+                               int gx, const float* X, float2* Z, uint32_t* Zs, int64_t zplane,
+                               int R, int64_t N, hipStream_t s);
 
 // transposed banded product: u_i = A_i^T f (half spectrum), per block
 // The transposed product gathers by columns of the half spectrum: the row

@@ -122,7 +122,11 @@ __device__ __forceinline__ void store_z(const ExecPlan<T>& pl, const ExecBlock<T
 #pragma unroll
     for (int p = 0; p < 3; ++p) zs[p * pl.zplane] = pc[p];
   } else {
-    pl.Z[(int64_t)pl.R * B.zoff + (int64_t)r * (B.P + 1) + k] = z;
+    const int64_t i = (int64_t)pl.R * B.zoff + (int64_t)r * (B.P + 1) + k;
+    if (pl.Zf)
+      pl.Zf[i] = float2{(float)z.x, (float)z.y};
+    else
+      pl.Z[i] = z;
   }
 }
 
@@ -133,8 +137,8 @@ __device__ __forceinline__ void store_z_pad(const ExecPlan<T>& pl, const ExecBlo
     for (int k = B.P + 1; k < B.ldz4; ++k) store_z<true>(pl, B, r, k, cplx_t<T>{T(0), T(0)});
 }
 
-template <typename T, bool SYNC, bool SPLIT>
-__device__ __forceinline__ void item_fft(const ExecPlan<T>& pl, const ExecBlock<T>& B, const T* __restrict__ X,
+template <typename T, bool SYNC, bool SPLIT, typename TI = T>
+__device__ __forceinline__ void item_fft(const ExecPlan<T>& pl, const ExecBlock<T>& B, const TI* __restrict__ X,
                          int r0, int lb, cplx_t<T>* lds, double2* ltw, uint32_t* sync) {
   using C = cplx_t<T>;
   const int tid = threadIdx.x;
@@ -154,9 +158,9 @@ __device__ __forceinline__ void item_fft(const ExecPlan<T>& pl, const ExecBlock<
       const int r = r0 + t;
       const bool ok = u < total && r < R;
       const int c0 = 2 * j, c1 = 2 * j + 1;
-      const T* __restrict__ x = X + (int64_t)r * N + m_off;
-      v0[e] = (ok && c0 >= c_lo && c0 < c_hi) ? x[c0] * winv[c0] : T(0);
-      v1[e] = (ok && c1 >= c_lo && c1 < c_hi) ? x[c1] * winv[c1] : T(0);
+      const TI* __restrict__ x = X + (int64_t)r * N + m_off;
+      v0[e] = (ok && c0 >= c_lo && c0 < c_hi) ? T(x[c0]) * winv[c0] : T(0);
+      v1[e] = (ok && c1 >= c_lo && c1 < c_hi) ? T(x[c1]) * winv[c1] : T(0);
     }
 #pragma unroll
     for (int e = 0; e < EXEC_EPT; ++e) {
@@ -212,8 +216,8 @@ __device__ __forceinline__ void item_fft(const ExecPlan<T>& pl, const ExecBlock<
 // W[k1 * P2 + n2] = (sum_n1 u[P2 n1 + n2] w_P1^(n1 k1)) w_P^(n2 k1).
 // SIGN -1 (the precomputation's F): rows of X are taken as they are
 // (B.winv == nullptr, no window division, no extras)
-template <typename T, bool SYNC, int SIGN = +1>
-__device__ __forceinline__ void item_col(const ExecPlan<T>& pl, const ExecBlock<T>& B, const T* __restrict__ X,
+template <typename T, bool SYNC, int SIGN = +1, typename TI = T>
+__device__ __forceinline__ void item_col(const ExecPlan<T>& pl, const ExecBlock<T>& B, const TI* __restrict__ X,
                          int r, int grp, cplx_t<T>* lds, double2* ltw, uint32_t* sync) {
   using C = cplx_t<T>;
   const int tid = threadIdx.x;
@@ -222,7 +226,7 @@ __device__ __forceinline__ void item_col(const ExecPlan<T>& pl, const ExecBlock<
   const int P1 = B.P1, P2 = B.P2;
   const uint32_t total = (uint32_t)P1 << lcw;
   const int c_lo = B.c_lo, c_hi = B.c_hi;
-  const T* __restrict__ x = X + (int64_t)r * pl.N + B.m_off;
+  const TI* __restrict__ x = X + (int64_t)r * pl.N + B.m_off;
   const T* __restrict__ winv = B.winv;
   const int n2base = grp << lcw;
   {
@@ -235,11 +239,11 @@ __device__ __forceinline__ void item_col(const ExecPlan<T>& pl, const ExecBlock<
       const int c0 = 2 * n, c1 = 2 * n + 1;
       const bool ok = u < total;
       if (SIGN > 0) {
-        v0[e] = (ok && c0 >= c_lo && c0 < c_hi) ? x[c0] * winv[c0] : T(0);
-        v1[e] = (ok && c1 >= c_lo && c1 < c_hi) ? x[c1] * winv[c1] : T(0);
+        v0[e] = (ok && c0 >= c_lo && c0 < c_hi) ? T(x[c0]) * winv[c0] : T(0);
+        v1[e] = (ok && c1 >= c_lo && c1 < c_hi) ? T(x[c1]) * winv[c1] : T(0);
       } else {
-        v0[e] = ok ? x[c0] : T(0);
-        v1[e] = ok ? x[c1] : T(0);
+        v0[e] = ok ? T(x[c0]) : T(0);
+        v1[e] = ok ? T(x[c1]) : T(0);
       }
     }
 #pragma unroll
@@ -495,15 +499,19 @@ __global__ __launch_bounds__(EXEC_THREADS) __attribute__((amdgpu_waves_per_eu(4)
     const ExecPlan<T>& pl = a.plans[p];
     switch (kind) {
       case ITEM_FFT:
-        item_fft<T, true, false>(pl, pl.blocks[it.y], a.X[p], it.z, it.w, lds, ltw, sync);
+        item_fft<T, true, false>(pl, pl.blocks[it.y], static_cast<const T*>(a.X[p]), it.z, it.w,
+                                 lds, ltw, sync);
         break;
       case ITEM_COL:
-        item_col<T, true>(pl, pl.blocks[it.y], a.X[p], it.z, it.w, lds, ltw, sync);
+        item_col<T, true>(pl, pl.blocks[it.y], static_cast<const T*>(a.X[p]), it.z, it.w, lds,
+                          ltw, sync);
         break;
       case ITEM_ROW:
         item_row<T, true, false>(pl, pl.blocks[it.y], it.z, it.w, lds, ltw, sync, &s_flag);
         break;
-      default: item_spmm<E>(pl, a.X[p], a.Y[p], it.y, it.z, sync, &s_flag); break;
+      default:
+        item_spmm<E>(pl, static_cast<const T*>(a.X[p]), a.Y[p], it.y, it.z, sync, &s_flag);
+        break;
     }
     if (tid == 0)
       s_item[cur ^ 1] = nxt < (uint32_t)a.n_items ? a.items[nxt] : make_int4(-1, 0, 0, 0);
@@ -531,8 +539,9 @@ __global__ __launch_bounds__(EXEC_THREADS) __attribute__((amdgpu_waves_per_eu(4)
   }
 }
 
-// FFT items without queue or counters: workgroup b runs item b
-template <typename T, bool SPLIT>
+// FFT items without queue or counters: workgroup b runs item b; TI is the
+// type of the right-hand sides
+template <typename T, typename TI, bool SPLIT>
 __global__ __launch_bounds__(EXEC_THREADS) void fft_items_kernel(ExecArgs<T> a) {
   using C = cplx_t<T>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -544,10 +553,12 @@ __global__ __launch_bounds__(EXEC_THREADS) void fft_items_kernel(ExecArgs<T> a) 
   const ExecPlan<T>& pl = a.plans[p];
   switch (kind) {
     case ITEM_FFT:
-      item_fft<T, false, SPLIT>(pl, pl.blocks[it.y], a.X[p], it.z, it.w, lds, ltw, nullptr);
+      item_fft<T, false, SPLIT, TI>(pl, pl.blocks[it.y], static_cast<const TI*>(a.X[p]), it.z,
+                                    it.w, lds, ltw, nullptr);
       break;
     case ITEM_COL:
-      item_col<T, false>(pl, pl.blocks[it.y], a.X[p], it.z, it.w, lds, ltw, nullptr);
+      item_col<T, false, +1, TI>(pl, pl.blocks[it.y], static_cast<const TI*>(a.X[p]), it.z, it.w,
+                                 lds, ltw, nullptr);
       break;
     default:
       item_row<T, false, SPLIT>(pl, pl.blocks[it.y], it.z, it.w, lds, ltw, nullptr, &s_flag);
@@ -566,7 +577,8 @@ __global__ __launch_bounds__(EXEC_THREADS) void row_fft4_kernel(ExecArgs<double>
   const int4 it = a.items[blockIdx.x];
   const ExecPlan<double>& pl = a.plans[0];
   if ((it.x & 15) == ITEM_COL)
-    item_col<double, false, -1>(pl, pl.blocks[it.y], a.X[0], it.z, it.w, lds, ltw, nullptr);
+    item_col<double, false, -1>(pl, pl.blocks[it.y], static_cast<const double*>(a.X[0]), it.z,
+                                it.w, lds, ltw, nullptr);
   else
     item_row<double, false, false, -1>(pl, pl.blocks[it.y], it.z, it.w, lds, ltw, nullptr,
                                        &s_flag);
@@ -606,9 +618,11 @@ void init_exec_kernels() {
   set_lds(exec_kernel<EngF64>, lds);
   set_lds(exec_kernel<EngF32>, lds);
   set_lds(exec_kernel<EngSplitBf16>, lds);
-  set_lds(fft_items_kernel<double, false>, lds);
-  set_lds(fft_items_kernel<float, false>, lds);
-  set_lds(fft_items_kernel<float, true>, lds);
+  set_lds(fft_items_kernel<double, double, false>, lds);
+  set_lds(fft_items_kernel<double, float, true>, lds);
+  set_lds(fft_items_kernel<double, float, false>, lds);
+  set_lds(fft_items_kernel<float, float, false>, lds);
+  set_lds(fft_items_kernel<float, float, true>, lds);
   set_lds(row_fft4_kernel, lds);
   done.push_back(dev);
 }
@@ -648,23 +662,30 @@ void launch_row_fft4(const ExecArgs<double>& a, hipStream_t s) {
 }
 
 template <>
-void launch_fft_items<double>(const ExecArgs<double>& a, bool split, hipStream_t s) {
-  (void)split;
+void launch_fft_items<double>(const ExecArgs<double>& a, bool split, bool xf, hipStream_t s) {
   if (a.n_items <= 0) return;
-  hipLaunchKernelGGL((fft_items_kernel<double, false>), dim3(a.n_items), dim3(EXEC_THREADS),
-                     exec_lds_bytes<double>(a.ntw), s, a);
+  if (split)
+    hipLaunchKernelGGL((fft_items_kernel<double, float, true>), dim3(a.n_items),
+                       dim3(EXEC_THREADS), exec_lds_bytes<double>(a.ntw), s, a);
+  else if (xf)
+    hipLaunchKernelGGL((fft_items_kernel<double, float, false>), dim3(a.n_items),
+                       dim3(EXEC_THREADS), exec_lds_bytes<double>(a.ntw), s, a);
+  else
+    hipLaunchKernelGGL((fft_items_kernel<double, double, false>), dim3(a.n_items),
+                       dim3(EXEC_THREADS), exec_lds_bytes<double>(a.ntw), s, a);
   SPT_HIP(hipGetLastError());
 }
 
 template <>
-void launch_fft_items<float>(const ExecArgs<float>& a, bool split, hipStream_t s) {
+void launch_fft_items<float>(const ExecArgs<float>& a, bool split, bool xf, hipStream_t s) {
+  (void)xf;
   if (a.n_items <= 0) return;
   if (split)
-    hipLaunchKernelGGL((fft_items_kernel<float, true>), dim3(a.n_items), dim3(EXEC_THREADS),
-                       exec_lds_bytes<float>(a.ntw), s, a);
+    hipLaunchKernelGGL((fft_items_kernel<float, float, true>), dim3(a.n_items),
+                       dim3(EXEC_THREADS), exec_lds_bytes<float>(a.ntw), s, a);
   else
-    hipLaunchKernelGGL((fft_items_kernel<float, false>), dim3(a.n_items), dim3(EXEC_THREADS),
-                       exec_lds_bytes<float>(a.ntw), s, a);
+    hipLaunchKernelGGL((fft_items_kernel<float, float, false>), dim3(a.n_items),
+                       dim3(EXEC_THREADS), exec_lds_bytes<float>(a.ntw), s, a);
   SPT_HIP(hipGetLastError());
 }
 

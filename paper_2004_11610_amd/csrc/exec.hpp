@@ -78,6 +78,8 @@ struct ExecPlan {
   cplx_t<T>* Z;              // half spectra of every block
   cplx_t<T>* W;              // four-step intermediates
   uint32_t* Zs;              // pre-split spectra (three planes, staged split-bf16 path)
+  float2* Zf;                // float32 spectra of a float64 transform (staged F32 path
+                             // with float64 FFTs; replaces Z as the output), or null
   int64_t zplane;            // plane stride, in (Re, Im) bfloat16 pairs
   const TileMeta* meta;      // tile box of (tile, block) at meta[tile * nblk + block]
   const ExecBlock<T>* blocks;
@@ -94,7 +96,9 @@ struct ExecArgs {
   uint32_t* err_out;         // host-visible word: the launch's EXEC_SYNC_ERR at its end
   int n_items, n_sync;
   int ntw;                   // entries of the largest twiddle table (LDS copies)
-  const T* X[EXEC_MAX_PLANS];
+  // right-hand sides: T, except float for the split-bf16 FFT items in float64
+  // arithmetic (T = double, launch_fft_items with split)
+  const void* X[EXEC_MAX_PLANS];
   T* Y[EXEC_MAX_PLANS];
 };
 
@@ -110,9 +114,12 @@ template <typename T>
 void launch_exec(const ExecArgs<T>& a, int engine, int grid, hipStream_t s);
 // The FFT items without the queue and the counters (items of one launch do
 // not depend on each other): one workgroup per item of a.items[0 .. n_items).
-// split: spectra go out as the three bfloat16 planes (T = float).
+// split: spectra go out as the three bfloat16 planes.  With T = double and
+// split or xf the right-hand sides are float (a.X) and the transforms run in
+// float64 arithmetic, each spectrum value rounded once to float32 (before its
+// split, or into ExecPlan::Zf).
 template <typename T>
-void launch_fft_items(const ExecArgs<T>& a, bool split, hipStream_t s);
+void launch_fft_items(const ExecArgs<T>& a, bool split, bool xf, hipStream_t s);
 // Precomputation: F of the rows of a panel by four-step items (float64);
 // a.plans[0] describes the panel: X[0] = the rows (stride N = L), Z = the half
 // spectra (stride P + 1), W = the intermediate (stride P), R = rows; the

@@ -96,19 +96,21 @@ __host__ __device__ inline size_t tab_offset(int pts) {
 // pair lies wholly inside or outside the retained columns): x and 1/w are read
 // as aligned pairs, from column c_lo when the pair is outside (a valid
 // address; the value is discarded).
-template <bool VEC, typename T>
-__device__ __forceinline__ cplx_t<T> point_pair(const T* __restrict__ x, const T* __restrict__ winv,
+// x is of type TI (float32 input of the split-bf16 path whose transform runs
+// in float64 arithmetic: T = double, TI = float), the window reciprocals of T.
+template <bool VEC, typename T, typename TI>
+__device__ __forceinline__ cplx_t<T> point_pair(const TI* __restrict__ x, const T* __restrict__ winv,
                                                 int c, int c_lo, int c_hi, int m_off) {
   using C = cplx_t<T>;
   if constexpr (VEC) {
     const bool in = c >= c_lo && c < c_hi;
     const int cc = in ? c : c_lo;
-    const C xv = gload(reinterpret_cast<const C*>(x + m_off + cc));
+    const cplx_t<TI> xv = gload(reinterpret_cast<const cplx_t<TI>*>(x + m_off + cc));
     const C wv = gload(reinterpret_cast<const C*>(winv + cc));
-    return in ? C{xv.x * wv.x, xv.y * wv.y} : C{T(0), T(0)};
+    return in ? C{T(xv.x) * wv.x, T(xv.y) * wv.y} : C{T(0), T(0)};
   } else {
     auto val = [&](int cv) {
-      return cv >= c_lo && cv < c_hi ? gload(x + cv + m_off) * gload(winv + cv) : T(0);
+      return cv >= c_lo && cv < c_hi ? T(gload(x + cv + m_off)) * gload(winv + cv) : T(0);
     };
     return C{val(c), val(c + 1)};
   }
@@ -128,9 +130,9 @@ __device__ __forceinline__ cplx_t<T> point_pair(const T* __restrict__ x, const T
 // EARLY: the unpack twiddles are requested with the points (registers permitting)
 // EI: points per thread, FFT_EPT or fewer (2^lb P <= EI nt): loops over the
 // thread's points stop there instead of clamping indexes past the end
-template <typename T, bool SPLIT, bool BATCH, bool EARLY, int EI>
+template <typename T, typename TI, bool SPLIT, bool BATCH, bool EARLY, int EI>
 __device__ __forceinline__ void fft_multi_body(const FftDesc<T>* __restrict__ d,
-                                               const T* __restrict__ X, cplx_t<T>* __restrict__ Z,
+                                               const TI* __restrict__ X, cplx_t<TI>* __restrict__ Z,
                                                uint32_t* __restrict__ Zs, int64_t zplane, int R,
                                                int64_t N, int lb_, int r0) {
   using C = cplx_t<T>;
@@ -179,7 +181,7 @@ __device__ __forceinline__ void fft_multi_body(const FftDesc<T>* __restrict__ d,
         const int u = tid + (h + e) * nt;
         const int uu = min(u, pts - 1);
         const int j = uu >> lb, t = uu & tmask;
-        const T* __restrict__ x = X + (int64_t)(r0 + (BATCH ? min(t, cnt - 1) : 0)) * N;
+        const TI* __restrict__ x = X + (int64_t)(r0 + (BATCH ? min(t, cnt - 1) : 0)) * N;
         const C pr = point_pair<VEC>(x, winv, 2 * j, c_lo, c_hi, m_off);
         v[e] = u < pts && t < cnt ? pr : C{T(0), T(0)};
       }
@@ -221,8 +223,10 @@ __device__ __forceinline__ void fft_multi_body(const FftDesc<T>* __restrict__ d,
     for (int e = 0; e <= EI; ++e) {
       const int u = tid + e * nt;
       const int k = u >> lb, t = u & tmask;
-      if (u < n && t < cnt)
-        Z[(int64_t)R * d->zoff + (int64_t)(r0 + t) * d->ldz + k] = unpack_at(k, t, tw[e]);
+      if (u < n && t < cnt) {
+        const C z = unpack_at(k, t, tw[e]);
+        Z[(int64_t)R * d->zoff + (int64_t)(r0 + t) * d->ldz + k] = cplx_t<TI>{TI(z.x), TI(z.y)};
+      }
     }
   } else {
     // four consecutive k per thread (ldz4 is a multiple of 4): each plane gets
@@ -257,9 +261,9 @@ __device__ __forceinline__ void fft_multi_body(const FftDesc<T>* __restrict__ d,
 // a transform of H points (one decimation-in-frequency step).  The unpack
 // pairs C_k with C_(P-k), of the same parity, so the half is complete: it
 // writes the half spectrum at every k of parity p (zeros past P).
-template <typename T, bool SPLIT, bool EARLY, int EI>
+template <typename T, typename TI, bool SPLIT, bool EARLY, int EI>
 __device__ __forceinline__ void fft_half_body(const FftDesc<T>* __restrict__ d,
-                                              const T* __restrict__ X, cplx_t<T>* __restrict__ Z,
+                                              const TI* __restrict__ X, cplx_t<TI>* __restrict__ Z,
                                               uint32_t* __restrict__ Zs, int64_t zplane, int R,
                                               int64_t N, int r, int par) {
   using C = cplx_t<T>;
@@ -269,7 +273,7 @@ __device__ __forceinline__ void fft_half_body(const FftDesc<T>* __restrict__ d,
   const int tid = threadIdx.x;
   const int c_lo = d->c_lo, c_hi = d->c_hi, m_off = d->m_off;
   const T* __restrict__ winv = d->winv;
-  const T* __restrict__ x = X + (int64_t)r * N;
+  const TI* __restrict__ x = X + (int64_t)r * N;
   const C* __restrict__ post = d->post;  // post[2n] = w^n
   // the unpack twiddles of the thread's outputs k = 2 (tid + e nt) + par and
   // the pass twiddles first, then the points: one wait for all of them
@@ -337,7 +341,7 @@ __device__ __forceinline__ void fft_half_body(const FftDesc<T>* __restrict__ d,
     if (k >= kend) break;
     const C z = zval(m, tw[e]);
     if constexpr (!SPLIT) {
-      Z[(int64_t)R * d->zoff + (int64_t)r * d->ldz + k] = z;
+      Z[(int64_t)R * d->zoff + (int64_t)r * d->ldz + k] = cplx_t<TI>{TI(z.x), TI(z.y)};
     } else {
       uint32_t pc[3];
       spmmcore::split2(spmmcore::f32x2{(float)z.x, (float)z.y}, pc);
@@ -349,10 +353,12 @@ __device__ __forceinline__ void fft_half_body(const FftDesc<T>* __restrict__ d,
 }
 
 // MAXT: the launch's threads are at most MAXT (512 leaves each thread 256
-// registers, 1024 leaves 128)
-template <typename T, bool SPLIT, int MAXT>
+// registers, 1024 leaves 128).  TI: type of X and of the complex spectra Z
+// (float with T = double: the float32 paths' transforms in float64
+// arithmetic, each spectrum value rounded once to float32).
+template <typename T, typename TI, bool SPLIT, int MAXT>
 __global__ __launch_bounds__(MAXT) void exec_fft_multi_kernel(
-    const FftDesc<T>* __restrict__ descs, const T* __restrict__ X, cplx_t<T>* __restrict__ Z,
+    const FftDesc<T>* __restrict__ descs, const TI* __restrict__ X, cplx_t<TI>* __restrict__ Z,
     uint32_t* __restrict__ Zs, int64_t zplane, int R, int64_t N) {
   constexpr bool EARLY = MAXT <= 512;
   // transforms of at most EI_SHORT points per thread take the variant whose
@@ -366,9 +372,9 @@ __global__ __launch_bounds__(MAXT) void exec_fft_multi_kernel(
     const int par = (int)blockIdx.x >= R ? 1 : 0;
     const int r = (int)blockIdx.x - par * R;
     if (d->fp.P <= EI_SHORT * (int)blockDim.x)
-      fft_half_body<T, SPLIT, EARLY, EI_SHORT>(d, X, Z, Zs, zplane, R, N, r, par);
+      fft_half_body<T, TI, SPLIT, EARLY, EI_SHORT>(d, X, Z, Zs, zplane, R, N, r, par);
     else
-      fft_half_body<T, SPLIT, EARLY, FFT_EPT>(d, X, Z, Zs, zplane, R, N, r, par);
+      fft_half_body<T, TI, SPLIT, EARLY, FFT_EPT>(d, X, Z, Zs, zplane, R, N, r, par);
     return;
   }
   const int lb = d->lb;
@@ -377,14 +383,14 @@ __global__ __launch_bounds__(MAXT) void exec_fft_multi_kernel(
   const bool short_pts = (d->fp.P << lb) <= EI_SHORT * (int)blockDim.x;
   if (lb == 0) {
     if (short_pts)
-      fft_multi_body<T, SPLIT, false, EARLY, EI_SHORT>(d, X, Z, Zs, zplane, R, N, 0, r0);
+      fft_multi_body<T, TI, SPLIT, false, EARLY, EI_SHORT>(d, X, Z, Zs, zplane, R, N, 0, r0);
     else
-      fft_multi_body<T, SPLIT, false, EARLY, FFT_EPT>(d, X, Z, Zs, zplane, R, N, 0, r0);
+      fft_multi_body<T, TI, SPLIT, false, EARLY, FFT_EPT>(d, X, Z, Zs, zplane, R, N, 0, r0);
   } else {
     if (short_pts)
-      fft_multi_body<T, SPLIT, true, EARLY, EI_SHORT>(d, X, Z, Zs, zplane, R, N, lb, r0);
+      fft_multi_body<T, TI, SPLIT, true, EARLY, EI_SHORT>(d, X, Z, Zs, zplane, R, N, lb, r0);
     else
-      fft_multi_body<T, SPLIT, true, EARLY, FFT_EPT>(d, X, Z, Zs, zplane, R, N, lb, r0);
+      fft_multi_body<T, TI, SPLIT, true, EARLY, FFT_EPT>(d, X, Z, Zs, zplane, R, N, lb, r0);
   }
 }
 
@@ -421,9 +427,11 @@ __global__ __launch_bounds__(FFT_MAX_THREADS) void inv_fft_kernel(InvFftArgs<T> 
 
 // The same for every block of a plan in one launch (descriptors in device
 // memory; the workgroup has the threads of the longest transform).
-template <typename T>
+// TI: type of U and Y (float with T = double: the float32 path's transform in
+// float64 arithmetic)
+template <typename T, typename TI = T>
 __global__ __launch_bounds__(FFT_MAX_THREADS) void inv_fft_multi_kernel(
-    const InvFftDesc<T>* __restrict__ descs, const cplx_t<T>* __restrict__ U, T* __restrict__ Y,
+    const InvFftDesc<T>* __restrict__ descs, const cplx_t<TI>* __restrict__ U, TI* __restrict__ Y,
     int R, int64_t N) {
   using C = cplx_t<T>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -432,11 +440,11 @@ __global__ __launch_bounds__(FFT_MAX_THREADS) void inv_fft_multi_kernel(
   const int tid = threadIdx.x, nt = blockDim.x;
   const int r = blockIdx.x;
   const int P = d->P;
-  const C* __restrict__ u = U + d->uoff * R + (int64_t)r * (P + 1);
+  const cplx_t<TI>* __restrict__ u = U + d->uoff * R + (int64_t)r * (P + 1);
   const C* __restrict__ post = d->post;
   for (int k = tid; k < P; k += nt) {
-    const C uk = u[k];
-    C um = u[P - k];
+    const C uk = C{T(u[k].x), T(u[k].y)};
+    C um = C{T(u[P - k].x), T(u[P - k].y)};
     um.y = -um.y;  // conj U_(P-k)
     const C ge = cadd(uk, um);
     const C go = cmul(csub(uk, um), post[k]);
@@ -447,12 +455,12 @@ __global__ __launch_bounds__(FFT_MAX_THREADS) void inv_fft_multi_kernel(
   const T scale = d->scale;
   const T* __restrict__ winv = d->winv;
   const int c_lo = d->c_lo, c_hi = d->c_hi, m_off = d->m_off;
-  T* __restrict__ y = Y + (int64_t)r * N;
+  TI* __restrict__ y = Y + (int64_t)r * N;
   for (int j = tid; j < P; j += nt) {
     const C c = lds[j];
     const int c0 = 2 * j, c1 = 2 * j + 1;
-    if (c0 >= c_lo && c0 < c_hi) y[c0 + m_off] = c.x * scale * winv[c0];
-    if (c1 >= c_lo && c1 < c_hi) y[c1 + m_off] = c.y * scale * winv[c1];
+    if (c0 >= c_lo && c0 < c_hi) y[c0 + m_off] = TI(c.x * scale * winv[c0]);
+    if (c1 >= c_lo && c1 < c_hi) y[c1 + m_off] = TI(c.y * scale * winv[c1]);
   }
 }
 
@@ -576,18 +584,23 @@ void init_fft_kernels(size_t max_lds) {
   set_lds(inv_fft_kernel<double>, max_lds);
   set_lds(inv_fft_kernel<float>, max_lds);
   set_lds(inv_fft_multi_kernel<double>, max_lds);
+  set_lds(inv_fft_multi_kernel<double, float>, max_lds);
   set_lds(inv_fft_multi_kernel<float>, max_lds);
   set_lds(inv_fft4_col_kernel<double>, max_lds);
   set_lds(inv_fft4_col_kernel<float>, max_lds);
   set_lds(inv_fft4_row_kernel<double>, max_lds);
   set_lds(inv_fft4_row_kernel<float>, max_lds);
   set_lds(row_fft_kernel, max_lds);
-  set_lds(exec_fft_multi_kernel<double, false, 512>, max_lds);
-  set_lds(exec_fft_multi_kernel<float, false, 512>, max_lds);
-  set_lds(exec_fft_multi_kernel<float, true, 512>, max_lds);
-  set_lds(exec_fft_multi_kernel<double, false, 1024>, max_lds);
-  set_lds(exec_fft_multi_kernel<float, false, 1024>, max_lds);
-  set_lds(exec_fft_multi_kernel<float, true, 1024>, max_lds);
+  set_lds(exec_fft_multi_kernel<double, double, false, 512>, max_lds);
+  set_lds(exec_fft_multi_kernel<float, float, false, 512>, max_lds);
+  set_lds(exec_fft_multi_kernel<float, float, true, 512>, max_lds);
+  set_lds(exec_fft_multi_kernel<double, float, true, 512>, max_lds);
+  set_lds(exec_fft_multi_kernel<double, float, false, 512>, max_lds);
+  set_lds(exec_fft_multi_kernel<double, double, false, 1024>, max_lds);
+  set_lds(exec_fft_multi_kernel<float, float, false, 1024>, max_lds);
+  set_lds(exec_fft_multi_kernel<float, float, true, 1024>, max_lds);
+  set_lds(exec_fft_multi_kernel<double, float, true, 1024>, max_lds);
+  set_lds(exec_fft_multi_kernel<double, float, false, 1024>, max_lds);
   done.push_back(dev);
 }
 
@@ -641,11 +654,11 @@ template <typename T>
 void launch_exec_fft_multi(const FftDesc<T>* descs, int nblk, int threads, size_t lds, int gx,
                            const T* X, cplx_t<T>* Z, int R, int64_t N, hipStream_t s) {
   if (threads <= 512)
-    hipLaunchKernelGGL((exec_fft_multi_kernel<T, false, 512>), dim3(gx, nblk), dim3(threads), lds,
-                       s, descs, X, Z, (uint32_t*)nullptr, (int64_t)0, R, N);
+    hipLaunchKernelGGL((exec_fft_multi_kernel<T, T, false, 512>), dim3(gx, nblk), dim3(threads),
+                       lds, s, descs, X, Z, (uint32_t*)nullptr, (int64_t)0, R, N);
   else
-    hipLaunchKernelGGL((exec_fft_multi_kernel<T, false, 1024>), dim3(gx, nblk), dim3(threads), lds,
-                       s, descs, X, Z, (uint32_t*)nullptr, (int64_t)0, R, N);
+    hipLaunchKernelGGL((exec_fft_multi_kernel<T, T, false, 1024>), dim3(gx, nblk), dim3(threads),
+                       lds, s, descs, X, Z, (uint32_t*)nullptr, (int64_t)0, R, N);
   SPT_HIP(hipGetLastError());
 }
 
@@ -653,11 +666,34 @@ void launch_exec_fft_multi_split(const FftDesc<float>* descs, int nblk, int thre
                                  int gx, const float* X, uint32_t* Zs, int64_t zplane, int R,
                                  int64_t N, hipStream_t s) {
   if (threads <= 512)
-    hipLaunchKernelGGL((exec_fft_multi_kernel<float, true, 512>), dim3(gx, nblk), dim3(threads),
-                       lds, s, descs, X, (float2*)nullptr, Zs, zplane, R, N);
+    hipLaunchKernelGGL((exec_fft_multi_kernel<float, float, true, 512>), dim3(gx, nblk),
+                       dim3(threads), lds, s, descs, X, (float2*)nullptr, Zs, zplane, R, N);
   else
-    hipLaunchKernelGGL((exec_fft_multi_kernel<float, true, 1024>), dim3(gx, nblk), dim3(threads),
-                       lds, s, descs, X, (float2*)nullptr, Zs, zplane, R, N);
+    hipLaunchKernelGGL((exec_fft_multi_kernel<float, float, true, 1024>), dim3(gx, nblk),
+                       dim3(threads), lds, s, descs, X, (float2*)nullptr, Zs, zplane, R, N);
+  SPT_HIP(hipGetLastError());
+}
+
+void launch_exec_fft_multi_x32(const FftDesc<double>* descs, int nblk, int threads, size_t lds,
+                               int gx, const float* X, float2* Z, uint32_t* Zs, int64_t zplane,
+                               int R, int64_t N, hipStream_t s) {
+  if (Zs) {
+    if (threads <= 512)
+      hipLaunchKernelGGL((exec_fft_multi_kernel<double, float, true, 512>), dim3(gx, nblk),
+                         dim3(threads), lds, s, descs, X, (float2*)nullptr, Zs, zplane, R, N);
+    else
+      hipLaunchKernelGGL((exec_fft_multi_kernel<double, float, true, 1024>), dim3(gx, nblk),
+                         dim3(threads), lds, s, descs, X, (float2*)nullptr, Zs, zplane, R, N);
+  } else {
+    if (threads <= 512)
+      hipLaunchKernelGGL((exec_fft_multi_kernel<double, float, false, 512>), dim3(gx, nblk),
+                         dim3(threads), lds, s, descs, X, Z, (uint32_t*)nullptr, (int64_t)0, R,
+                         N);
+    else
+      hipLaunchKernelGGL((exec_fft_multi_kernel<double, float, false, 1024>), dim3(gx, nblk),
+                         dim3(threads), lds, s, descs, X, Z, (uint32_t*)nullptr, (int64_t)0, R,
+                         N);
+  }
   SPT_HIP(hipGetLastError());
 }
 
@@ -699,6 +735,14 @@ void launch_inv_fft_multi(const InvFftDesc<T>* descs, int nblk, int threads, siz
   if (nblk <= 0) return;
   hipLaunchKernelGGL(inv_fft_multi_kernel<T>, dim3(R, nblk), dim3(threads), lds, s, descs, U, Y,
                      R, N);
+  SPT_HIP(hipGetLastError());
+}
+
+void launch_inv_fft_multi_x32(const InvFftDesc<double>* descs, int nblk, int threads, size_t lds,
+                              const float2* U, float* Y, int R, int64_t N, hipStream_t s) {
+  if (nblk <= 0) return;
+  hipLaunchKernelGGL((inv_fft_multi_kernel<double, float>), dim3(R, nblk), dim3(threads), lds, s,
+                     descs, U, Y, R, N);
   SPT_HIP(hipGetLastError());
 }
 

@@ -140,14 +140,17 @@ struct PieceRegs {
   bf16x8 z[3];
 };
 
+// The six piece products of a step are summed from zero (their rounding is
+// relative to the step's own sum) and the step's sum is then added to the
+// running sum: one rounding of the running sum per step instead of six.
 __device__ __forceinline__ f32x4 mma6_pieces(const bf16x8* A, const bf16x8* B, f32x4 acc) {
-  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[2], B[0], acc, 0, 0, 0);
-  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[1], B[1], acc, 0, 0, 0);
-  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[0], B[2], acc, 0, 0, 0);
-  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[1], B[0], acc, 0, 0, 0);
-  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[0], B[1], acc, 0, 0, 0);
-  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[0], B[0], acc, 0, 0, 0);
-  return acc;
+  f32x4 t = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[2], B[0], f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+  t = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[1], B[1], t, 0, 0, 0);
+  t = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[0], B[2], t, 0, 0, 0);
+  t = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[1], B[0], t, 0, 0, 0);
+  t = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[0], B[1], t, 0, 0, 0);
+  t = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[0], B[0], t, 0, 0, 0);
+  return acc + t;
 }
 
 __device__ __forceinline__ void presplit_tile(const SpmmSplitArgs& args, int tile, int r0) {
@@ -246,17 +249,22 @@ __device__ __forceinline__ void presplit_tile(const SpmmSplitArgs& args, int til
 // and group of 16 right-hand sides.
 constexpr int WIN_SLOTS = 8;  // steps whose matrix pieces are loaded together
 
-// acc[q] += A * B[q] over the six piece products (small ones first), the RG
-// accumulators interleaved
+// acc[q] += A * B[q] over the six piece products (small ones first, summed
+// from zero as in mma6_pieces), the RG accumulators interleaved
 template <int RG>
 __device__ __forceinline__ void mma6xg(const bf16x8* A, const bf16x8 (*B)[3], f32x4* acc) {
   constexpr int ia[6] = {2, 1, 0, 1, 0, 0};
   constexpr int ib[6] = {0, 1, 2, 0, 1, 0};
+  f32x4 t[RG];
+#pragma unroll
+  for (int q = 0; q < RG; ++q) t[q] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
   for (int k = 0; k < 6; ++k)
 #pragma unroll
     for (int q = 0; q < RG; ++q)
-      acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[ia[k]], B[q][ib[k]], acc[q], 0, 0, 0);
+      t[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[ia[k]], B[q][ib[k]], t[q], 0, 0, 0);
+#pragma unroll
+  for (int q = 0; q < RG; ++q) acc[q] += t[q];
 }
 
 // RG: groups of 16 right-hand sides per workgroup (4 or 2); the windows hold
@@ -892,10 +900,13 @@ __global__ __launch_bounds__(256) void spmm_presplit_items_kernel(SpmmSplitBatch
 // workgroups) each stores into a slot of partial sums, and
 // spmm_t_reduce_kernel adds a chunk's slots in order (deterministic, no
 // atomics).  Thread: columns 2 cg, 2 cg + 1 and right-hand sides 4 rq ..
-// 4 rq + 3 of the chunk.
+// 4 rq + 3 of the chunk.  Sums are accumulated in float64 for either
+// precision (float32: products of float32 values are exact in float64, and
+// the sums are rounded to float32 once, where they are stored).
 template <typename T>
 __global__ __launch_bounds__(256) void spmm_transposed_kernel(SpmmTArgs<T> a) {
   using C = cplx_t<T>;
+  using D = double2;
   static_assert(TCHUNK == 32, "thread layout: 16 column pairs x 16 groups of 4 right-hand sides");
   constexpr int FPT = 64 * TILE_ROWS / 256;      // f values per thread and tile
   constexpr int APT = TILE_ROWS * TCHUNK / 256;  // box values per thread and tile
@@ -914,9 +925,9 @@ __global__ __launch_bounds__(256) void spmm_transposed_kernel(SpmmTArgs<T> a) {
   const int r0 = blockIdx.y * 64;
   const int kc = seg.x * TCHUNK;
   const int cg = tid & 15, rq = tid >> 4;
-  C acc[4][2];
+  D acc[4][2];
 #pragma unroll
-  for (int j = 0; j < 4; ++j) acc[j][0] = acc[j][1] = C{T(0), T(0)};
+  for (int j = 0; j < 4; ++j) acc[j][0] = acc[j][1] = D{0.0, 0.0};
   T fr[TPR][FPT];
   C ar[TPR][APT];
   auto fetch = [&](int t, const TChunkEnt& e) {
@@ -971,19 +982,19 @@ __global__ __launch_bounds__(256) void spmm_transposed_kernel(SpmmTArgs<T> a) {
       for (int t = 0; t < TPR; ++t) {
         if (t >= cnt) break;
         // the tile's 16 rows summed first, then added (running sums stay short)
-        C part[4][2];
+        D part[4][2];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) part[j][0] = part[j][1] = C{T(0), T(0)};
+        for (int j = 0; j < 4; ++j) part[j][0] = part[j][1] = D{0.0, 0.0};
 #pragma unroll
         for (int q = 0; q < TILE_ROWS; ++q) {
           const C a0 = as[t][q][2 * cg], a1 = as[t][q][2 * cg + 1];
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
-            const T fv = fs[t][4 * rq + j][q];
-            part[j][0].x += a0.x * fv;
-            part[j][0].y += a0.y * fv;
-            part[j][1].x += a1.x * fv;
-            part[j][1].y += a1.y * fv;
+            const double fv = fs[t][4 * rq + j][q];
+            part[j][0].x += (double)a0.x * fv;
+            part[j][0].y += (double)a0.y * fv;
+            part[j][1].x += (double)a1.x * fv;
+            part[j][1].y += (double)a1.y * fv;
           }
         }
 #pragma unroll
@@ -1005,8 +1016,8 @@ __global__ __launch_bounds__(256) void spmm_transposed_kernel(SpmmTArgs<T> a) {
     for (int c2 = 0; c2 < 2; ++c2) {
       const int k = kc + 2 * cg + c2;
       if (k > P) continue;
-      const T ck = (k == 0 || k == P) ? T(1) : T(0.5);
-      const C v = C{acc[j][c2].x * ck, acc[j][c2].y * ck};
+      const double ck = (k == 0 || k == P) ? 1.0 : 0.5;
+      const C v = C{T(acc[j][c2].x * ck), T(acc[j][c2].y * ck)};
       if (seg.w & 1)
         u[(int64_t)r * ldu + k] = v;
       else
@@ -1029,7 +1040,7 @@ __global__ __launch_bounds__(256) void spmm_t_reduce_kernel(SpmmTArgs<T> a) {
   if (r >= a.R || k > P) return;
   const int64_t stride = (int64_t)a.R * TCHUNK;
   const C* __restrict__ p = a.part + ((int64_t)rd.z * a.R + r) * TCHUNK + c;
-  C s = C{T(0), T(0)};
+  double2 s = double2{0.0, 0.0};  // float64 sums, as in spmm_transposed_kernel
   int i = 0;
   for (; i + 8 <= rd.w; i += 8) {
     C v[8];
@@ -1046,7 +1057,7 @@ __global__ __launch_bounds__(256) void spmm_t_reduce_kernel(SpmmTArgs<T> a) {
     s.x += v.x;
     s.y += v.y;
   }
-  a.u[bi.uoff * a.R + (int64_t)r * (P + 1) + k] = s;
+  a.u[bi.uoff * a.R + (int64_t)r * (P + 1) + k] = C{T(s.x), T(s.y)};
 }
 
 // fhat[r][m] = sum_j tail[m][j] f[r][j] for m < tail: one workgroup per (m, r)
@@ -1057,8 +1068,9 @@ __global__ __launch_bounds__(256) void tail_transposed_kernel(const T* __restric
   const int m = blockIdx.x, r = blockIdx.y;
   const T* __restrict__ col = tailmat + (int64_t)m * ldt;
   const T* __restrict__ f = F + (int64_t)r * N;
-  // eight loads of each in flight per thread (blockDim.x is 256)
-  T s = T(0);
+  // eight loads of each in flight per thread (blockDim.x is 256); sums in
+  // float64 for either precision, rounded once when stored
+  double s = 0.0;
   int64_t j = threadIdx.x;
   for (; j + 7 * 256 < N; j += 8 * 256) {
     T cv[8], fv[8];
@@ -1068,17 +1080,17 @@ __global__ __launch_bounds__(256) void tail_transposed_kernel(const T* __restric
       fv[u] = f[j + u * 256];
     }
 #pragma unroll
-    for (int u = 0; u < 8; ++u) s += cv[u] * fv[u];
+    for (int u = 0; u < 8; ++u) s += (double)cv[u] * fv[u];
   }
-  for (; j < N; j += 256) s += col[j] * f[j];
-  __shared__ T part[256];
+  for (; j < N; j += 256) s += (double)col[j] * f[j];
+  __shared__ double part[256];
   part[threadIdx.x] = s;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
     if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x == 0) Y[(int64_t)r * N + m] = part[0];
+  if (threadIdx.x == 0) Y[(int64_t)r * N + m] = T(part[0]);
 }
 
 }  // namespace

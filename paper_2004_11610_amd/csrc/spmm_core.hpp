@@ -91,23 +91,28 @@ struct EngF32 {
   static constexpr int SB = 2;
   __device__ static int row(int g, int i) { return 4 * g + i; }
   __device__ static Acc zero() { return Acc{0.f, 0.f, 0.f, 0.f}; }
+  // a step's eight products are summed from zero, then added to the running
+  // sum (one rounding of the running sum per step)
   __device__ static Acc step(const float2* a, const float2* z, Acc acc) {
+    Acc t = zero();
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[j].x, z[j].x, acc, 0, 0, 0);
-      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(-a[j].y, z[j].y, acc, 0, 0, 0);
+      t = __builtin_amdgcn_mfma_f32_16x16x4f32(a[j].x, z[j].x, t, 0, 0, 0);
+      t = __builtin_amdgcn_mfma_f32_16x16x4f32(-a[j].y, z[j].y, t, 0, 0, 0);
     }
-    return acc;
+    return acc + t;
   }
   __device__ static Acc step_real(const float* a, const float* x, Acc acc) {
+    Acc t = zero();
 #pragma unroll
-    for (int j = 0; j < 8; ++j) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[j], x[j], acc, 0, 0, 0);
-    return acc;
+    for (int j = 0; j < 8; ++j) t = __builtin_amdgcn_mfma_f32_16x16x4f32(a[j], x[j], t, 0, 0, 0);
+    return acc + t;
   }
 };
 
 // three bfloat16 pieces per operand, the six products of order <= 2 (small
-// ones first), float32 accumulation
+// ones first), float32 accumulation: a step's products are summed from zero,
+// then added to the running sum
 struct EngSplitBf16 {
   using T = float;
   using Acc = f32x4;
@@ -115,13 +120,13 @@ struct EngSplitBf16 {
   __device__ static int row(int g, int i) { return 4 * g + i; }
   __device__ static Acc zero() { return Acc{0.f, 0.f, 0.f, 0.f}; }
   __device__ static Acc mma6(const Split8& A, const Split8& B, Acc acc) {
-    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.get(2), B.get(0), acc, 0, 0, 0);
-    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.get(1), B.get(1), acc, 0, 0, 0);
-    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.get(0), B.get(2), acc, 0, 0, 0);
-    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.get(1), B.get(0), acc, 0, 0, 0);
-    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.get(0), B.get(1), acc, 0, 0, 0);
-    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.get(0), B.get(0), acc, 0, 0, 0);
-    return acc;
+    Acc t = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.get(2), B.get(0), zero(), 0, 0, 0);
+    t = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.get(1), B.get(1), t, 0, 0, 0);
+    t = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.get(0), B.get(2), t, 0, 0, 0);
+    t = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.get(1), B.get(0), t, 0, 0, 0);
+    t = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.get(0), B.get(1), t, 0, 0, 0);
+    t = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.get(0), B.get(0), t, 0, 0, 0);
+    return acc + t;
   }
   __device__ static Acc step(const float2* a, const float2* z, Acc acc) {
     f32x8 fa, fz;

@@ -55,14 +55,6 @@ def rel_rows(Y, Yref):
     return float(np.max(num / den))
 
 
-def reduced_tol(plan):
-    """Bar for the float32 and split-bf16 paths against float64 on one plan.
-    The half spectra carry float32 rounding that grows with the FFT depth
-    (about eps32 log2 L relative) and the product amplifies it by
-    kappa = rms(w) rms(1/w) (plan info); measured ratios error / (eps32 kappa
-    log2 L) are 0.14 .. 0.18, the bar takes 0.5, and never less than 1e-6."""
-    import numpy as np
-    info = plan.info()
-    L = max([b[0] for b in plan.blocks()] or [2])
-    return max(1e-6, 0.5 * np.finfo(np.float32).eps * info["kappa"] * np.log2(L))
-
+# Bar of the float32 and split-bf16 paths against float64 on the same plan:
+# relative 2-norm per right-hand side.
+REDUCED_TOL = 1e-6

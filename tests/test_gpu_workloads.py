@@ -18,7 +18,7 @@ import numpy as np
 import pytest
 
 import workloads
-from tests.helpers import reduced_tol, oracle_direct, rel_rows, say, to_dev, to_host
+from tests.helpers import REDUCED_TOL, oracle_direct, rel_rows, say, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
@@ -68,7 +68,7 @@ def test_batch_48_plans(spt):
         say("  %s mode %d F64 vs direct %.2e, split vs F64 %.2e" % (w["name"], p.info()["mode"],
                                                                     e, es))
         assert e <= 2e-6
-        assert es <= reduced_tol(p)
+        assert es <= REDUCED_TOL
     say("worst F64 vs direct %.2e" % worst)
     # the persistent one-launch batch computes the same
     for p in plans:
@@ -116,9 +116,9 @@ def test_laguerre_65536_r1024(spt):
     Y64 = to_host(p.execute(to_dev(Xh, torch.float64), prec=spt.F64))
     e64 = rel_rows(Y64[:, rows], ref)
     es = rel_rows(Ys, Y64)
-    say("  F64 vs direct %.2e, split vs F64 %.2e (bar %.2e)" % (e64, es, reduced_tol(p)))
+    say("  F64 vs direct %.2e, split vs F64 %.2e (bar %.2e)" % (e64, es, REDUCED_TOL))
     assert e64 <= (1e-9 if info["mode"] == spt.MODE_DIRECT else 5e-4)
-    assert es <= reduced_tol(p)
+    assert es <= REDUCED_TOL
     if info["mode"] != spt.MODE_DIRECT:
         # the transposed product of this nearly dense plan takes long segments
         # (expected: several stagings of 256 list entries each); it is the
