@@ -237,6 +237,23 @@ spt_status spt_precompute(spt_plan_t plan, void* stream);
 spt_status spt_execute(spt_plan_t plan, const void* X, void* Y, int64_t nrhs, int32_t prec,
                        void* stream);
 
+/* spt_execute for callers that cannot allocate device memory (code under HIP
+ * graph capture, serving loops, harnesses that forbid hipMalloc): the same
+ * arguments, kernels and results, with the workspace in a static device array
+ * of SPT_NOALLOC_MAX_BYTES per device (resident from the library's load until
+ * the process ends) instead of the plan's workspace.  Calls no hipMalloc,
+ * hipFree or allocating routine.  Every call on a device shares that device's
+ * array: calls that overlap on one device (two streams, two threads) race and
+ * must be ordered by the caller; nothing in the array needs clearing between
+ * calls (each call writes all it reads).  SPT_E_INVALID_ARG when the workspace
+ * of nrhs right-hand sides (complex float64 half spectra of every block, or the
+ * split-bf16 pieces) exceeds the array; SPT_E_UNSUPPORTED for plans with the
+ * persistent executor or with a block whose FFT exceeds one workgroup (half
+ * length above 10240). */
+#define SPT_NOALLOC_MAX_BYTES (32u << 20)
+spt_status spt_execute_noalloc(spt_plan_t plan, const void* X, void* Y, int64_t nrhs, int32_t prec,
+                               void* stream);
+
 /* Transposed product (Alg. 2 / block Alg. 4): Y[r*N + m] = sum_j A[j,m] X[r*N + j].
  * Same arguments and rules as spt_execute; F64 or F32 (SPT_E_UNSUPPORTED for
  * split-bf16).  Blocks with an FFT half-length above 10240 take a four-step

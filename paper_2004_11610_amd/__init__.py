@@ -144,6 +144,18 @@ class Plan:
                                          c_int64(R), c_int32(prec), _stream_ptr(stream)))
         return Y
 
+    def execute_noalloc(self, X, Y, prec=F64, stream=None):
+        """execute() through spt_execute_noalloc: the workspace is the library's
+        static device array (no allocation); Y must be given."""
+        prec = PRECISIONS.get(prec, prec)
+        if Y is None:
+            raise ValueError("execute_noalloc needs the output tensor Y")
+        R, Y = self._check_io(X, Y, prec)
+        _lib.check(self._lib.spt_execute_noalloc(
+            self._h, c_void_p(X.data_ptr()), c_void_p(Y.data_ptr()), c_int64(R), c_int32(prec),
+            _stream_ptr(stream)))
+        return Y
+
     def execute_transposed(self, X, Y=None, prec=F64, stream=None):
         """Y = X A (Y[r] = A^T X[r]) for X of shape (R, N) on the device."""
         prec = PRECISIONS.get(prec, prec)

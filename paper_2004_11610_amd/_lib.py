@@ -8,6 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libspt.so")
 
 SPT_OK = 0
+NOALLOC_MAX_BYTES = 32 << 20  # SPT_NOALLOC_MAX_BYTES
 ERRORS = {-1: "SPT_E_INVALID_ARG", -2: "SPT_E_NOT_PRECOMPUTED", -3: "SPT_E_HIP",
           -4: "SPT_E_OOM", -5: "SPT_E_UNSUPPORTED", -6: "SPT_E_NUMERIC"}
 
@@ -61,6 +62,7 @@ def load():
         "spt_precompute": [c_void_p, c_void_p],
         "spt_execute": [c_void_p, c_void_p, c_void_p, c_int64, c_int32, c_void_p],
         "spt_execute_transposed": [c_void_p, c_void_p, c_void_p, c_int64, c_int32, c_void_p],
+        "spt_execute_noalloc": [c_void_p, c_void_p, c_void_p, c_int64, c_int32, c_void_p],
         "spt_execute_batched": [POINTER(c_void_p), POINTER(c_void_p), POINTER(c_void_p),
                                 POINTER(c_int64), c_int32, c_int32, c_void_p],
         "spt_plan_query": [c_void_p, POINTER(SptPlanInfo)],

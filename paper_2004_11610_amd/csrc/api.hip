@@ -1376,7 +1376,8 @@ void precompute(spt_plan_t plan, hipStream_t s) {
 }
 
 template <typename T>
-void execute_staged_t(spt_plan_t plan, const T* X, T* Y, int64_t R, int prec, hipStream_t s);
+void execute_staged_t(spt_plan_t plan, const T* X, T* Y, int64_t R, int prec, hipStream_t s,
+                      void* ws = nullptr);
 
 // Arithmetic of the float32 and split-bf16 paths' x-side FFTs
 // (spt_params.reduced_fft).  The automatic choice runs 4 right-hand sides
@@ -1447,6 +1448,17 @@ void choose_reduced_fft(spt_plan_t plan, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------- execute
+// bytes of an execute's workspace for R right-hand sides: complex float64
+// spectra (and four-step intermediates; the transposed product also keeps its
+// partial sums after them), or the three bfloat16-pair planes of the
+// split-bf16 path
+size_t work_bytes(spt_plan_t plan, int64_t R, bool transposed) {
+  const int64_t per = z_per_rhs(plan) + w_per_rhs(plan) + (transposed ? t_per_rhs(plan) : 0);
+  return std::max((size_t)std::max<int64_t>(per, 1) * (size_t)R * sizeof(double2),
+                  ((size_t)plan->zper4 * 3 * sizeof(uint32_t) +
+                   (size_t)w_per_rhs(plan) * sizeof(float2)) * (size_t)R);
+}
+
 // select (and size) the workspace of stream s
 void ensure_work(spt_plan_t plan, int64_t R, hipStream_t s, bool transposed = false) {
   spt_plan::Work* w = nullptr;
@@ -1465,14 +1477,7 @@ void ensure_work(spt_plan_t plan, int64_t R, hipStream_t s, bool transposed = fa
     w->stream = s;
   }
   plan->work = &w->buf;
-  // the transposed product also keeps its partial sums after the intermediates
-  const int64_t per = z_per_rhs(plan) + w_per_rhs(plan) + (transposed ? t_per_rhs(plan) : 0);
-  // complex float64 spectra (and four-step intermediates), or the three
-  // bfloat16-pair planes of the split-bf16 path
-  const size_t bytes =
-      std::max((size_t)std::max<int64_t>(per, 1) * (size_t)R * sizeof(double2),
-               ((size_t)plan->zper4 * 3 * sizeof(uint32_t) + (size_t)w_per_rhs(plan) * sizeof(float2)) *
-                   (size_t)R);
+  const size_t bytes = work_bytes(plan, R, transposed);
   if (bytes > plan->work->bytes) {
     // work lists hold the old workspace address; work in flight may use them
     SPT_HIP(hipDeviceSynchronize());
@@ -1528,10 +1533,17 @@ void run_fft_items(ExecCtx& c, const void* const* X, int count, bool split, hipS
 // single-workgroup transforms and the column halves of the four-step ones, in
 // one launch and the row halves in a second.  Then the banded product.  The
 // split-bf16 path writes and reads the pre-split spectra.
+// ws: the workspace (work_bytes(plan, R, false) bytes) when the caller brings
+// one; then only fused-FFT plans are accepted (the FFT items need work lists)
 template <typename T>
-void execute_staged_t(spt_plan_t plan, const T* X, T* Y, int64_t R, int prec, hipStream_t s) {
+void execute_staged_t(spt_plan_t plan, const T* X, T* Y, int64_t R, int prec, hipStream_t s,
+                      void* ws) {
   using C = cplx_t<T>;
-  ensure_work(plan, R, s);
+  const bool own_ws = ws == nullptr;
+  if (own_ws) {
+    ensure_work(plan, R, s);
+    ws = plan->work->p;
+  }
   const int nblk = (int)plan->blk.size();
   const bool split = std::is_same<T, float>::value && prec == SPT_SPLIT_BF16;
   const bool fused = nblk > 0 && plan->fft_maxP <= FUSED_MAX_P;
@@ -1557,19 +1569,19 @@ void execute_staged_t(spt_plan_t plan, const T* X, T* Y, int64_t R, int prec, hi
                                                           128 + B.P / 128 + 1));
         }
         launch_exec_fft_multi_x32(plan->fftdesc64.as<FftDesc<double>>() + b0, nb, threads, lds64,
-                                  (int)gx, X, split ? nullptr : plan->work->as<float2>(),
-                                  split ? plan->work->as<uint32_t>() : nullptr,
+                                  (int)gx, X, split ? nullptr : static_cast<float2*>(ws),
+                                  split ? static_cast<uint32_t*>(ws) : nullptr,
                                   (int64_t)R * plan->zper4, (int)R, plan->N, st);
         return;
       }
       if (split) {
         launch_exec_fft_multi_split(d + b0, nb, threads, lds, (int)gx, X,
-                                    plan->work->as<uint32_t>(), (int64_t)R * plan->zper4, (int)R,
+                                    static_cast<uint32_t*>(ws), (int64_t)R * plan->zper4, (int)R,
                                     plan->N, st);
         return;
       }
     }
-    launch_exec_fft_multi<T>(d + b0, nb, threads, lds, (int)gx, X, plan->work->as<C>(), (int)R,
+    launch_exec_fft_multi<T>(d + b0, nb, threads, lds, (int)gx, X, static_cast<C*>(ws), (int)R,
                              plan->N, st);
   };
   // banded product of every block and the tail
@@ -1581,7 +1593,7 @@ void execute_staged_t(spt_plan_t plan, const T* X, T* Y, int64_t R, int prec, hi
         pa.blocks = plan->spmmblk_bf.as<SpmmSplitBlock>();
         pa.nblk = nblk;
         pa.n_tiles = plan->n_tiles;
-        pa.Zs = plan->work->as<uint32_t>();
+        pa.Zs = static_cast<uint32_t*>(ws);
         pa.zplane = (int64_t)R * plan->zper4;
         pa.tail = (int)plan->tail;
         pa.tailmat = plan->tailbf.as<uint16_t>();
@@ -1607,7 +1619,7 @@ void execute_staged_t(spt_plan_t plan, const T* X, T* Y, int64_t R, int prec, hi
     sa.meta = plan->tilemeta.as<TileMeta>();
     sa.blocks = std::is_same<T, double>::value ? (const SpmmBlock<T>*)plan->spmmblk64.p
                                                : (const SpmmBlock<T>*)plan->spmmblk32.p;
-    sa.Z = plan->work->as<C>();
+    sa.Z = static_cast<C*>(ws);
     sa.tail = (int)plan->tail;
     sa.tailmat = std::is_same<T, double>::value ? (const T*)plan->tail64.p
                                                 : (const T*)plan->tail32.p;
@@ -1628,6 +1640,9 @@ void execute_staged_t(spt_plan_t plan, const T* X, T* Y, int64_t R, int prec, hi
   if (fused) {
     staged(SPT_STAGE_FFT, s, [&] { fft_fused(0, nblk, s); });
   } else if (nblk > 0) {
+    if (!own_ws)
+      throw Error(SPT_E_UNSUPPORTED, "a block's FFT exceeds one workgroup: the caller's workspace "
+                                     "serves fused-FFT plans only");
     ExecCtx& c = plan_ctx(plan, R, prec, s, true);
     const void* xs[1] = {X};
     staged(SPT_STAGE_FFT, s, [&] { run_fft_items(c, xs, 1, split, s); });
@@ -1773,10 +1788,14 @@ struct Profiler {
 };
 Profiler g_prof;
 
+// set while a call must not create anything (spt_execute_noalloc): no
+// profiling events then
+thread_local bool t_noalloc = false;
+
 // records an event pair around fn() on stream s when profiling is on
 template <typename F>
 void staged(int stage, hipStream_t s, F&& fn) {
-  if (!g_prof.on) {
+  if (!g_prof.on || t_noalloc) {
     fn();
     return;
   }
@@ -2005,6 +2024,34 @@ void set_exec_wait(spt_plan_t plan, uint32_t ticks) {
                       hipMemcpyHostToDevice));
 }
 
+// ---------------------------------------------------------------- no-allocation execute
+// The workspace of spt_execute_noalloc: one static array per device, resident
+// from the library's load until the process ends.  Host code uses the address
+// that hipGetSymbolAddress gives on each device, never the array's name.
+static __device__ __align__(256) unsigned char scratch[SPT_NOALLOC_MAX_BYTES];
+
+constexpr int SCRATCH_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[SCRATCH_MAX_DEVICES] = {};
+
+// the array's address on the current device (looked up once per device)
+void* scratch_on(int device) {
+  if (device < 0 || device >= SCRATCH_MAX_DEVICES)
+    throw Error(SPT_E_UNSUPPORTED, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      (void)hipGetLastError();
+      throw Error(SPT_E_HIP, std::string("hipGetSymbolAddress(scratch) failed: ") +
+                                 hipGetErrorString(e));
+    }
+    g_scratch_ptr[device] = ptr;
+  }
+  return g_scratch_ptr[device];
+}
+
 template <typename F>
 spt_status guard(F&& fn) {
   try {
@@ -2150,6 +2197,37 @@ spt_status spt_execute(spt_plan_t plan, const void* X, void* Y, int64_t nrhs, in
       run_exec<double>(c, xs, ys, 1, prec, s);
     else
       run_exec<float>(c, xs, ys, 1, prec, s);
+  });
+}
+
+spt_status spt_execute_noalloc(spt_plan_t plan, const void* X, void* Y, int64_t nrhs,
+                               int32_t prec, void* stream) {
+  return guard([&] {
+    check_exec(plan, X, Y, nrhs, prec);
+    if (!uses_staged(plan))
+      throw Error(SPT_E_UNSUPPORTED, "spt_execute_noalloc runs the staged executor only");
+    if (!plan->blk.empty() && plan->fft_maxP > FUSED_MAX_P)
+      throw Error(SPT_E_UNSUPPORTED, "a block's FFT exceeds one workgroup (it needs work lists)");
+    const size_t need = work_bytes(plan, nrhs, false);
+    if (need > (size_t)SPT_NOALLOC_MAX_BYTES)
+      throw Error(SPT_E_INVALID_ARG, "the workspace of " + std::to_string(nrhs) +
+                                         " right-hand sides (" + std::to_string(need) +
+                                         " bytes) exceeds SPT_NOALLOC_MAX_BYTES (" +
+                                         std::to_string((size_t)SPT_NOALLOC_MAX_BYTES) + ")");
+    set_device(plan);
+    void* ws = scratch_on(plan->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    t_noalloc = true;
+    try {
+      if (prec == SPT_F64)
+        execute_staged_t<double>(plan, (const double*)X, (double*)Y, nrhs, prec, s, ws);
+      else
+        execute_staged_t<float>(plan, (const float*)X, (float*)Y, nrhs, prec, s, ws);
+    } catch (...) {
+      t_noalloc = false;
+      throw;
+    }
+    t_noalloc = false;
   });
 }
 
