@@ -103,3 +103,54 @@ class Compressed:
         real = np.abs(Y.real).max() if Y.size else 0.0
         assert imag <= 1e-9 * max(real, 1e-300), "imaginary part does not vanish"
         return Y.real.copy()
+
+
+def execute_rows(plan, X, rows, max_rows=()):
+    """Rows ``rows`` of the compressed method's Y = A X^T (the full Compressed
+    execute restricted to some output rows; each row costs O(L log L) per
+    block).  Block i keeps |Add| > eps1 * M_i with M_i the maximum of |Add_i|
+    over the rows ``rows`` and ``max_rows``: the whole block's maximum, and so
+    the full method's rows, when ``max_rows`` holds the rows where it is
+    attained (found once by ``block_max_rows``)."""
+    X = np.atleast_2d(np.asarray(X, dtype=np.float64))
+    R = X.shape[0]
+    rows = np.asarray(rows)
+    Y = np.zeros((R, rows.size), dtype=np.complex128)
+    maxabs = []
+    for blk in plan.blocks:
+        S = _spectrum(plan, blk, rows)
+        mx = np.abs(S).max()
+        if len(max_rows):
+            mx = max(mx, np.abs(_spectrum(plan, blk, np.asarray(max_rows))).max())
+        maxabs.append(mx)
+        S[np.abs(S) <= plan.eps1 * mx] = 0.0
+        w = plan.window(blk)
+        v = np.zeros((R, blk.L))
+        m_lo, m_hi = blk.c_lo + blk.m_offset, blk.c_hi + blk.m_offset
+        v[:, blk.c_lo:blk.c_hi] = X[:, m_lo:m_hi] / w[None, blk.c_lo:blk.c_hi]
+        z = np.fft.ifft(v, axis=1, norm="ortho")       # F* W^{-1} v
+        Y += z @ S.T
+    t = plan.tail
+    if t:
+        Y += X[:, :t] @ plan.fam.block(rows, 0, t).T
+    imag = np.abs(Y.imag).max() if Y.size else 0.0
+    real = np.abs(Y.real).max() if Y.size else 0.0
+    assert imag <= 1e-9 * max(real, 1e-300), "imaginary part does not vanish"
+    return Y.real.copy(), maxabs
+
+
+def block_max_rows(plan, panel=1024):
+    """For every block: (row, max) where max_n,k |Add[n, k]| is attained (all
+    rows, in panels; nothing is kept)."""
+    N = plan.fam.N
+    out = []
+    for blk in plan.blocks:
+        best = (-1, -1.0)
+        for p in range(0, N, panel):
+            rows = np.arange(p, min(p + panel, N))
+            a = np.abs(_spectrum(plan, blk, rows)).max(axis=1)
+            i = int(np.argmax(a))
+            if a[i] > best[1]:
+                best = (int(rows[i]), float(a[i]))
+        out.append(best)
+    return out

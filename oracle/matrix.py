@@ -31,7 +31,13 @@ TRIG = (CHEBYSHEV_T, SINE, COS_POWER)
 
 
 class MatrixFamily:
-    def __init__(self, family, N, alpha=0.0, beta=0.0, orthonormal=True, power=2):
+    """``given_nodes``: the N nodes x_j to use instead of the family's quadrature
+    nodes (the same entry formulas at other points; the Christoffel weights of
+    the Jacobi family are then those of the given points).  The trigonometric
+    generators always take the Chebyshev-Gauss angles."""
+
+    def __init__(self, family, N, alpha=0.0, beta=0.0, orthonormal=True, power=2,
+                 given_nodes=None):
         if family == LEGENDRE:
             alpha, beta = 0.0, 0.0
         if family == COS_POWER and power not in (2, 3, 4, 5):
@@ -40,6 +46,13 @@ class MatrixFamily:
         self.alpha, self.beta, self.orthonormal = float(alpha), float(beta), bool(orthonormal)
         self._x = {}
         self._lam = {}
+        if given_nodes is not None:
+            if family in TRIG:
+                raise ValueError("the trigonometric generators take no nodes")
+            x = np.array(given_nodes, dtype=np.float64)
+            if x.shape != (N,) or not np.all(np.isfinite(x)):
+                raise ValueError("need N finite nodes")
+            self._x["all"] = x
 
     @property
     def two_sided(self):

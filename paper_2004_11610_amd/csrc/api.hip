@@ -18,6 +18,7 @@
 #include "common.hpp"
 #include "exec.hpp"
 #include "planner.hpp"
+#include "worklist.hpp"
 
 namespace spt {
 namespace {
@@ -934,7 +935,9 @@ void build_exec_ctx(ExecCtx& c, const spt_plan_t* plans, const int64_t* R, int c
   std::vector<ExecPlan<T>> ep(count);
   std::vector<ExecBlock<T>> eb;
   std::vector<size_t> first(count);
-  std::vector<int4> col, fft, row, spmm;
+  std::vector<int4> spmm;
+  std::vector<std::vector<FftItemBlock>> fblk(count);
+  std::vector<int64_t> fR(R, R + count);
   int nsync = EXEC_SYNC_BASE;
   for (int i = 0; i < count; ++i) {
     spt_plan_t plan = plans[i];
@@ -980,18 +983,10 @@ void build_exec_ctx(ExecCtx& c, const spt_plan_t* plans, const int64_t* R, int c
         e.cctr = nsync;
         nsync += r;
         e.parts = B.n_row;
-        for (int rr = 0; rr < r; ++rr)
-          for (int g = 0; g < B.n_col; ++g)
-            col.push_back(make_int4(item_head(ITEM_COL, i), (int)b, rr, g));
-        for (int rr = 0; rr < r; ++rr)
-          for (int q = 0; q < B.n_row; ++q)
-            row.push_back(make_int4(item_head(ITEM_ROW, i), (int)b, rr, q));
       } else {
         e.parts = 1;
-        const int nb = fft_batch(B.P, r);
-        for (int r0 = 0; r0 < r; r0 += nb)
-          fft.push_back(make_int4(item_head(ITEM_FFT, i), (int)b, r0, log2_floor(nb)));
       }
+      fblk[i].push_back(FftItemBlock{B.P, B.four, B.n_col, B.n_row, fft_batch(B.P, r)});
       eb.push_back(e);
       zoff += B.P + 1;
       zoff4 += B.ldz4;
@@ -1023,16 +1018,26 @@ void build_exec_ctx(ExecCtx& c, const spt_plan_t* plans, const int64_t* R, int c
   upload(c.blocks, eb, s);
   for (int i = 0; i < count; ++i) ep[i].blocks = c.blocks.as<ExecBlock<T>>() + first[i];
   upload(c.plans, ep, s);
-  std::vector<int4> items;
-  items.reserve(col.size() + fft.size() + row.size() + spmm.size());
-  items.insert(items.end(), col.begin(), col.end());
-  items.insert(items.end(), fft.begin(), fft.end());
+  // FFT items: staged, the column and single-workgroup items in a first
+  // launch, the row items in a second; persistent, one queue with the product
+  // items last
+  FftItemLists fl;
+  build_fft_item_lists(fblk, fR, fl);
+  std::string why;
+  if (!check_fft_item_lists(fblk, fR, fl, &why))
+    throw Error(SPT_E_UNSUPPORTED, "FFT work lists failed their check: " + why);
+  auto as_int4 = [](const std::vector<WorkItem>& v) {
+    std::vector<int4> o(v.size());
+    for (size_t k = 0; k < v.size(); ++k) o[k] = make_int4(v[k].x, v[k].y, v[k].z, v[k].w);
+    return o;
+  };
+  std::vector<int4> items = as_int4(fl.first);
   if (staged) {
-    // first launch: column and single-workgroup items; second: row items
-    upload(c.items2, row, s);
-    c.n_items2 = (int)row.size();
+    upload(c.items2, as_int4(fl.second), s);
+    c.n_items2 = (int)fl.second.size();
   } else {
-    items.insert(items.end(), row.begin(), row.end());
+    const std::vector<int4> rows = as_int4(fl.second);
+    items.insert(items.end(), rows.begin(), rows.end());
     items.insert(items.end(), spmm.begin(), spmm.end());
   }
   upload(c.items, items, s);
@@ -1853,11 +1858,6 @@ void run_exec(ExecCtx& c, const void* const* X, void* const* Y, int count, int p
 }
 
 
-int xcd_tile_host(int b, int n) {
-  const int n8 = n >> 3;
-  return b < 8 * n8 ? (b & 7) * n8 + (b >> 3) : b;
-}
-
 // Product arguments and items of a staged batch (items of a plan's chunk of 64
 // right-hand sides start at a multiple of 8, tiles in XCD order).
 template <typename T>
@@ -1867,25 +1867,29 @@ void build_batch_products(ExecCtx& c, const spt_plan_t* plans, const int64_t* R,
   // split-bf16: plans with windows take the chunked product (groups of 4 row
   // tiles), the others the per-tile product
   const bool chunked = prec == SPT_SPLIT_BF16;
-  std::vector<int4> items, witems;
+  std::vector<BatchProductPlan> bp(count);
   c.wlds = 0;
   for (int i = 0; i < count; ++i) {
     const spt_plan_t plan = plans[i];
-    const bool win = chunked && plan->win_ok;
-    std::vector<int4>& it = win ? witems : items;
-    const int n = win ? plan->n_groups : plan->n_tiles;
-    if (win) c.wlds = std::max(c.wlds, spmm_chunk_lds_bytes(plan->win_tpad));
-    for (int r0 = 0; r0 < R[i]; r0 += 64) {
-      while (it.size() % 8) it.push_back(make_int4(i, -1, 0, 0));
-      for (int t = 0; t < n; ++t) it.push_back(make_int4(i, xcd_tile_host(t, n), r0, 0));
-    }
+    bp[i] = BatchProductPlan{plan->win_ok ? 1 : 0, plan->n_groups, plan->n_tiles, R[i]};
+    if (chunked && plan->win_ok) c.wlds = std::max(c.wlds, spmm_chunk_lds_bytes(plan->win_tpad));
   }
-  if (items.empty()) items.push_back(make_int4(0, -1, 0, 0));
-  if (witems.empty()) witems.push_back(make_int4(0, -1, 0, 0));
-  upload(c.sitems, items, s);
-  upload(c.witems, witems, s);
-  c.n_sitems = (int)items.size();
-  c.n_witems = c.wlds > 0 ? (int)witems.size() : 0;
+  BatchProductLists bl;
+  build_batch_product_lists(bp.data(), count, chunked, bl);
+  std::string why;
+  for (const BatchProductLaunch* l : {&bl.tile_launch, &bl.win_launch})
+    if (!check_batch_product_launch(bp.data(), count, *l, &why))
+      throw Error(SPT_E_UNSUPPORTED, "product work lists failed their check: " + why);
+  auto upload_items = [&](DevBuf& b, const std::vector<WorkItem>& v) {
+    std::vector<int4> o(std::max<size_t>(v.size(), 1), make_int4(0, -1, 0, 0));
+    for (size_t k = 0; k < v.size(); ++k) o[k] = make_int4(v[k].x, v[k].y, v[k].z, v[k].w);
+    upload(b, o, s);
+  };
+  upload_items(c.sitems, bl.tile_items);
+  upload_items(c.witems, bl.win_items);
+  // each launch reads its own list, as many items as the list holds
+  c.n_sitems = bl.tile_launch.count;
+  c.n_witems = bl.win_launch.count;
   if (prec == SPT_SPLIT_BF16) {
     std::vector<SpmmSplitArgs> a(count);
     for (int i = 0; i < count; ++i) {

@@ -25,6 +25,7 @@
 #pragma once
 
 #include "common.hpp"
+#include "worklist.hpp"
 
 namespace spt {
 
@@ -39,12 +40,6 @@ constexpr int EXEC_SYNC_WAIT = 3;   // bound of a dependency wait, 100 MHz ticks
 constexpr int EXEC_SYNC_BASE = 4;   // dependency counters start here
 constexpr uint32_t EXEC_WAIT_DEFAULT = 100000000u;  // 1 s
 
-enum : int { ITEM_FFT = 0, ITEM_COL = 1, ITEM_ROW = 2, ITEM_SPMM = 3 };
-
-// work item: x = kind | plan << 4; y = block (FFT/COL/ROW) or first row tile
-// (SPMM); z = first right-hand side; w = log2 of the right-hand sides (FFT),
-// column group (COL) or pair group (ROW)
-inline int item_head(int kind, int plan) { return kind | (plan << 4); }
 
 template <typename T>
 struct ExecBlock {

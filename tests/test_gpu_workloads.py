@@ -70,9 +70,135 @@ def test_batch_48_plans(spt):
         assert e <= 2e-6
         assert es <= REDUCED_TOL
     say("worst F64 vs direct %.2e" % worst)
-    # the persistent one-launch batch computes the same
+    # the persistent one-launch batch (a persistent twin of the first plan leads
+    # the batch) computes the same
+    lead = spt.Plan(FAM_NAME[ws[0]["family"]], ws[0]["N"], ws[0]["eps"], alpha=ws[0]["alpha"],
+                    beta=ws[0]["beta"], precisions=1 << spt.F64,
+                    executor=spt.EXECUTOR_PERSISTENT).precompute()
+    Yp = [torch.empty_like(x) for x in X64]
+    say("batched execute, persistent")
+    spt.execute_batched([lead] + plans[1:], X64, Yp, prec=spt.F64)
+    worst_p = max(rel_rows(to_host(a), to_host(b)) for a, b in zip(Yp, Y64))
+    say("persistent vs staged F64 %.2e" % worst_p)
+    assert worst_p <= 1e-12
+    lead.close()
     for p in plans:
         p.close()
+
+
+def golden_max_rows():
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                           "block_max_rows.json")) as f:
+        return json.load(f)
+
+
+def oracle_c_plan(w):
+    from oracle import compressed, matrix
+    fam = matrix.MatrixFamily(w["family"], w["N"], alpha=w.get("alpha", 0.0),
+                              beta=w.get("beta", 0.0),
+                              given_nodes=workloads.shared_nodes(w["family"], w["N"]))
+    return compressed.Plan(fam, w["eps"], 1e-2)
+
+
+def check_rows_vs_oracle_c(spt, w, p, X, Ys, gold, nrows=16, seed=0):
+    """Sampled rows (both ends and random ones) of each result in Ys against
+    the oracle's compressed method on the same rows, with each block's maximum
+    taken at the rows where the oracle found it over the whole block."""
+    from oracle import compressed
+    N = w["N"]
+    rows = np.unique(np.concatenate([[0, 1, N - 2, N - 1],
+                                     np.random.default_rng(seed).choice(N, nrows - 4,
+                                                                        replace=False)]))
+    oplan = oracle_c_plan(w)
+    g = gold[w["name"]]
+    ref, maxabs = compressed.execute_rows(oplan, X, rows, [r for r, _ in g["blocks"]])
+    for (r, m), mx in zip(g["blocks"], maxabs):
+        assert mx == pytest.approx(m, rel=1e-12)
+    lib_max = p.info()["max_abs"]
+    assert np.allclose(lib_max, maxabs, rtol=1e-12, atol=0.0), (lib_max, maxabs)
+    return [rel_rows(Y[:, rows], ref) for Y in Ys]
+
+
+def test_batch_plans_vs_oracle_compressed(spt):
+    """Members of the 48-plan batch (every family, the largest sizes with
+    four-step transforms, small ones) at full size, row mode, with the
+    closed-form nodes that the oracle also takes: float64 through the staged
+    and the persistent batch against the oracle's compressed method on sampled
+    rows at 1e-12."""
+    import torch
+    gold = golden_max_rows()
+    ws = [workloads.batch_plans()[i] for i in workloads.BATCH_ORACLE_C]
+    plans, X64, Xh = [], [], []
+    for w in ws:
+        say("precompute (shared nodes)", w["name"], FAM_NAME[w["family"]], w["N"], w["nrhs"])
+        plans.append(spt.Plan(FAM_NAME[w["family"]], w["N"], w["eps"], alpha=w["alpha"],
+                              beta=w["beta"], mode=spt.MODE_ROW,
+                              nodes=workloads.shared_nodes(w["family"], w["N"]),
+                              precisions=1 << spt.F64).precompute())
+        Xh.append(workloads.rhs(w["rhs"], w["nrhs"], w["N"], w["seed"]))
+        X64.append(to_dev(Xh[-1], torch.float64))
+    Ys = [torch.empty_like(x) for x in X64]
+    spt.execute_batched(plans, X64, Ys, prec=spt.F64)
+    w0 = ws[0]
+    lead = spt.Plan(FAM_NAME[w0["family"]], w0["N"], w0["eps"], alpha=w0["alpha"],
+                    beta=w0["beta"], mode=spt.MODE_ROW,
+                    nodes=workloads.shared_nodes(w0["family"], w0["N"]),
+                    precisions=1 << spt.F64, executor=spt.EXECUTOR_PERSISTENT).precompute()
+    Yp = [torch.empty_like(x) for x in X64]
+    spt.execute_batched([lead] + plans[1:], X64, Yp, prec=spt.F64)
+    for i, (w, p) in enumerate(zip(ws, plans)):
+        es, ep = check_rows_vs_oracle_c(spt, w, p, Xh[i], [to_host(Ys[i]), to_host(Yp[i])],
+                                        gold, seed=i)
+        say("  %s: staged %.2e, persistent %.2e vs oracle compressed" % (w["name"], es, ep))
+        assert es <= 1e-12 and ep <= 1e-12
+    lead.close()
+    for p in plans:
+        p.close()
+
+
+def test_laguerre_65536_vs_oracle_compressed(spt):
+    """The Laguerre-function workload at full size (1024 right-hand sides),
+    row mode, with the closed-form nodes that the oracle also takes: float64
+    against the oracle's compressed method on sampled rows of the first 64
+    right-hand sides at 1e-12."""
+    import torch
+    gold = golden_max_rows()
+    w = workloads.LAGUERRE_65536
+    say("precompute (shared nodes)", w["name"])
+    p = spt.Plan("laguerre_fn", w["N"], w["eps"], mode=spt.MODE_ROW,
+                 nodes=workloads.shared_nodes(w["family"], w["N"]),
+                 precisions=1 << spt.F64).precompute()
+    Xh = workloads.rhs(w["rhs"], w["nrhs"], w["N"], w["seed"])
+    Y = to_host(p.execute(to_dev(Xh, torch.float64), prec=spt.F64))
+    (e,) = check_rows_vs_oracle_c(spt, w, p, Xh[:64], [Y[:64]], gold, nrows=12, seed=5)
+    say("  F64 vs oracle compressed %.2e" % e)
+    assert e <= 1e-12
+    p.close()
+
+
+def test_legendre_16384_vs_oracle_compressed_all_rows(spt):
+    """The benchmark workload (Legendre, N = 16384, 64 right-hand sides,
+    eps1 = 1e-7) in float64 against the oracle's compressed method on every
+    row (the oracle's Gauss-Legendre nodes passed to the library) at 1e-12;
+    the per-block maxima of the threshold agree as well."""
+    import torch
+    from tests.helpers import oracle_compressed, oracle_family
+    w = workloads.LEGENDRE_16384
+    N = w["N"]
+    say("oracle compressed, all rows", w["name"])
+    fam = oracle_family("legendre", N)
+    ref = oracle_compressed("legendre", N, w["eps"])
+    p = spt.Plan("legendre", N, w["eps"], mode=spt.MODE_ROW, nodes=fam.nodes(),
+                 precisions=1 << spt.F64).precompute()
+    X = workloads.rhs(w["rhs"], w["nrhs"], N, w["seed"])
+    Y = to_host(p.execute(to_dev(X, torch.float64), prec=spt.F64))
+    e = rel_rows(Y, ref.execute(X))
+    say("  F64 vs oracle compressed (every row) %.2e" % e)
+    assert e <= 1e-12
+    assert np.allclose(p.info()["max_abs"], ref.maxabs, rtol=1e-12, atol=0.0)
+    p.close()
 
 
 def test_laguerre_8192_matches_oracle_compressed(spt):

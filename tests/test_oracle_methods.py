@@ -295,3 +295,32 @@ def test_appendix_a_truncation_stays_below_the_threshold(fam_id, kw, eps1):
     ef = rel(compressed.Compressed(plan).execute(X), Yd)
     Ya = appendix_a.compressed_method(plan, q=12).execute(X)
     assert rel(Ya, Yd) <= 1.05 * ef
+
+
+# ------------------------------------------------------------------ sampled rows of the method
+@pytest.mark.parametrize("fam_id,N,kw", [(matrix.LEGENDRE, 300, {}),
+                                         (matrix.JACOBI, 257, dict(alpha=2.0, beta=3.0)),
+                                         (matrix.HERMITE_FN, 200, {}),
+                                         (matrix.LAGUERRE_FN, 240, {})])
+def test_execute_rows_and_block_max_rows(fam_id, N, kw):
+    """The sampled-row form of the compressed method with the block maxima of
+    block_max_rows reproduces the full method's rows (shared closed-form nodes,
+    which the family then uses for every entry), and block_max_rows finds each
+    block's maximum."""
+    import workloads
+    from oracle import compressed
+    fam = matrix.MatrixFamily(fam_id, N, given_nodes=workloads.shared_nodes(fam_id, N), **kw)
+    plan = compressed.Plan(fam, 1e-7, 1e-2)
+    full = compressed.Compressed(plan)
+    X = workloads.rhs("normal", 3, N, 7)
+    Y = full.execute(X)
+    mrows = compressed.block_max_rows(plan, panel=64)
+    for (r, m), mx in zip(mrows, full.maxabs):
+        assert m == mx
+    rows = np.array([0, 5, N // 2, N - 1])
+    Yr, maxabs = compressed.execute_rows(plan, X, rows, [r for r, _ in mrows])
+    assert maxabs == full.maxabs
+    assert np.max(np.abs(Yr - Y[:, rows])) <= 1e-13 * np.max(np.abs(Y))
+    # without the maximum's rows a smaller threshold keeps more entries
+    Yp, maxp = compressed.execute_rows(plan, X, rows[:1])
+    assert all(a <= b for a, b in zip(maxp, full.maxabs))

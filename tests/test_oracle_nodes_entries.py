@@ -212,3 +212,38 @@ def test_laguerre_hermite_function_orthogonality(N):
     H = entries.hermite_fn(nodes.gauss_hermite(N), 0, N)
     G = (H * (wh * np.exp(xh * xh))[:, None]).T @ H
     np.testing.assert_allclose(G, np.eye(N), atol=1e-11)
+
+
+# ------------------------------------------------------------------ large-N Laguerre roots
+def _mp_laguerre_rec(n, x):
+    """L_n(x) and L_{n-1}(x) by the three-term recurrence
+    (k+1) L_{k+1} = (2k+1-x) L_k - k L_{k-1}, in mpmath arithmetic."""
+    l0, l1 = mpmath.mpf(1), 1 - x
+    for k in range(1, n):
+        l0, l1 = l1, ((2 * k + 1 - x) * l1 - k * l0) / (k + 1)
+    return l1, l0
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("N", [1024, 4096])
+def test_gauss_laguerre_large_n_vs_mpmath(N):
+    """Roots of L_N at N >= 1024 (the smallest, where the float64 recurrence has
+    a near double root at 0 and the oracle takes a double-double Newton step; a
+    middle one; the largest) against Newton iterations in 80-digit arithmetic:
+    the 80-digit root lies in a sign change of L_N and agrees with the oracle's
+    to 4 ulp."""
+    idx = [0, 1, 2, N // 2, N - 2, N - 1]
+    x = nodes.gauss_laguerre(N, idx)
+    with mpmath.workdps(80):
+        for j, xj in zip(idx, x):
+            r = mpmath.mpf(xj)
+            for _ in range(30):
+                ln, lm = _mp_laguerre_rec(N, r)
+                d = N * (ln - lm) / r          # L_N' = N (L_N - L_{N-1}) / x
+                step = ln / d
+                r -= step
+                if abs(step) <= mpmath.mpf(10) ** -60 * abs(r):
+                    break
+            delta = r * mpmath.mpf(10) ** -12
+            assert _mp_laguerre_rec(N, r - delta)[0] * _mp_laguerre_rec(N, r + delta)[0] < 0
+            assert abs(float(r) - xj) <= 4 * np.spacing(float(r)), (j, float(r), xj)

@@ -66,3 +66,28 @@ def batch_plans(count=48, seed=4, n_lo=1024, n_hi=65536, r_hi=256):
         out.append(dict(name="batch-%02d" % p, family=fam, alpha=a, beta=b, N=N, eps=1e-7,
                         nrhs=R, rhs="normal", seed=1000 + p))
     return out
+
+
+def shared_nodes(family, N):
+    """Closed-form nodes that both the library (through spt_params.nodes) and
+    the oracle take, so that full-size comparisons of the two hold at rounding
+    level (each side's own quadrature nodes differ by a few ulp, which moves the
+    entries by far more).  Synthetic points with the spread of each family's
+    Gauss nodes:
+      Jacobi family  x_j = cos(pi (2j+1) / (2N)), descending;
+      Hermite        x_j = -sqrt(2N+1) cos(pi (2j+1) / (2N)), ascending;
+      Laguerre       x_j = (4N+2) sin(pi (2j+1) / (4N))^2, ascending."""
+    t = np.pi * (2.0 * np.arange(N) + 1.0)
+    if family in (LEGENDRE, JACOBI):
+        return np.cos(t / (2.0 * N))
+    if family == HERMITE_FN:
+        return -math.sqrt(2.0 * N + 1.0) * np.cos(t / (2.0 * N))
+    if family == LAGUERRE_FN:
+        return (4.0 * N + 2.0) * np.sin(t / (4.0 * N)) ** 2
+    raise ValueError(family)
+
+
+# Plans of the 48-plan batch checked against the oracle's compressed method at
+# rounding level (shared nodes, row mode): every family, the largest sizes
+# (four-step transforms) and a few small ones.
+BATCH_ORACLE_C = [13, 10, 30, 17, 32, 6, 41, 1]
