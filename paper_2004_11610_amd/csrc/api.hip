@@ -112,7 +112,6 @@ struct DevBlock {
   FftPlan fftw;
   int half = 0, lbw = 0;
   DevBuf winv64, winv32, tw64, post64, post32, posttw;
-  DevBuf ptw64, ptw32;  // pass twiddles of the fused FFT (FftDesc::ptw)
   DevBuf k0, kw, off;   // per tile
   bool big = false;  // the transform does not fit one workgroup (four steps)
   // transposed product: the segments of row tiles per TCHUNK spectrum columns
@@ -370,25 +369,6 @@ void twiddles(int P, std::vector<long double>& twr, std::vector<long double>& tw
   }
 }
 
-// Pass twiddles of the fused FFT of plan fp (the FftDesc::ptw layout):
-// exp(2 pi i jm r / (Ns R)) for pass (R, Ns), r = 1 .. R-1, jm < Ns.
-void pass_twiddles(const FftPlan& fp, std::vector<long double>& re, std::vector<long double>& im) {
-  const long double pi = 3.141592653589793238462643383279502884L;
-  re.clear();
-  im.clear();
-  int64_t Ns = 1;
-  for (int p = 0; p < fp.npass; ++p) {
-    const int64_t R = fp.radix[p], n = Ns * R;
-    for (int64_t r = 1; r < R; ++r)
-      for (int64_t jm = 0; jm < Ns; ++jm) {
-        const long double a = 2.0L * pi * (long double)((jm * r) % n) / (long double)n;
-        re.push_back(cosl(a));
-        im.push_back(sinl(a));
-      }
-    Ns = n;
-  }
-}
-
 // two-level table of exp(i pi k / P), k <= P (the unpack twiddles):
 // lo[q] = exp(i pi q / P), q < 128; hi[q] = exp(i pi 128 q / P), q <= P / 128
 std::vector<double2> post_table(int P) {
@@ -501,12 +481,17 @@ int64_t build_block(spt_plan_t plan, DevBlock& B, hipStream_t s, size_t lds_max,
   const int L = B.g.L, P = L / 2;
   if (L % 2) throw Error(SPT_E_UNSUPPORTED, "odd block length " + std::to_string(L));
   B.P = P;
-  // rows whose transform does not fit one workgroup's LDS go by four steps
-  const bool big = P > FUSED_MAX_P || (size_t)P * sizeof(double2) > lds_max;
+  // rows whose transform does not fit one workgroup's LDS go by four steps:
+  // float64 points of the precomputation's row transforms and of the inverse
+  // transforms (P * 16 bytes), and the fused execute FFT's points of a
+  // transform or of a parity half with its two twiddle tables
+  const bool half = P >= FUSED_HALF_MIN_P && P % 2 == 0;
+  const bool big = P > FUSED_MAX_P || (size_t)P * sizeof(double2) > lds_max ||
+                   fused_lds_bytes<double>(half ? P / 2 : P, 128 + P / 128 + 1) > lds_max;
   B.big = big;
   if (!big) {
     B.fft = make_fft_plan(P);
-    B.half = P >= FUSED_HALF_MIN_P && P % 2 == 0 ? 1 : 0;
+    B.half = half ? 1 : 0;
     B.fftw = B.half ? make_fft_plan(P / 2) : B.fft;
   }
   exec_geometry(B);
@@ -534,14 +519,6 @@ int64_t build_block(spt_plan_t plan, DevBlock& B, hipStream_t s, size_t lds_max,
   upload(B.post64, to_vec2<double2, double>(por, poi), s);
   upload(B.post32, to_vec2<float2, float>(por, poi), s);
   upload(B.posttw, post_table(P), s);
-  if (!big) {
-    std::vector<long double> pr, pi_;
-    pass_twiddles(B.fftw, pr, pi_);
-    pr.push_back(1.0L);  // never empty
-    pi_.push_back(0.0L);
-    upload(B.ptw64, to_vec2<double2, double>(pr, pi_), s);
-    upload(B.ptw32, to_vec2<float2, float>(pr, pi_), s);
-  }
 
   const int64_t N = plan->N;
   const int64_t ntiles = plan->n_tiles;
@@ -1080,12 +1057,10 @@ std::vector<FftDesc<T>> fft_descs(spt_plan_t plan) {
     e.ldz4 = B.ldz4;
     e.tw2 = B.posttw.as<double2>();
     e.ntw = 128 + B.P / 128 + 1;
-    e.ptw = (const C*)(dbl ? B.ptw64.p : B.ptw32.p);
     // up to 4 right-hand sides per workgroup of a short block: 2^lb transforms
     // interleaved put 64 / 2^lb consecutive points of a row in a wave's
     // loads and stores (diagnostics: SPT_FFT_MAX_LB)
     e.half = B.half;
-    e.ntab = B.fftw.P - 1;
     e.lb = 0;
     while (!B.half && e.lb < fft_max_lb() && ((int64_t)B.fftw.P << (e.lb + 1)) <= plan->fft_wgP)
       ++e.lb;
@@ -1562,7 +1537,7 @@ void execute_staged_t(spt_plan_t plan, const T* X, T* Y, int64_t R, int prec, hi
     for (int b = b0; b < b0 + nb; ++b) {
       const DevBlock& B = *plan->blk[b];
       threads = std::max(threads, B.fftw.threads);
-      lds = std::max(lds, fused_lds_bytes<T>(B.fftw.P << B.lbw, B.fftw.P - 1, 128 + B.P / 128 + 1));
+      lds = std::max(lds, fused_lds_bytes<T>(B.fftw.P << B.lbw, 128 + B.P / 128 + 1));
       gx = std::max<int64_t>(gx, B.half ? 2 * R : (R + (1 << B.lbw) - 1) >> B.lbw);
     }
     if constexpr (std::is_same<T, float>::value) {
@@ -1570,8 +1545,7 @@ void execute_staged_t(spt_plan_t plan, const T* X, T* Y, int64_t R, int prec, hi
         size_t lds64 = 16;
         for (int b = b0; b < b0 + nb; ++b) {
           const DevBlock& B = *plan->blk[b];
-          lds64 = std::max(lds64, fused_lds_bytes<double>(B.fftw.P << B.lbw, B.fftw.P - 1,
-                                                          128 + B.P / 128 + 1));
+          lds64 = std::max(lds64, fused_lds_bytes<double>(B.fftw.P << B.lbw, 128 + B.P / 128 + 1));
         }
         launch_exec_fft_multi_x32(plan->fftdesc64.as<FftDesc<double>>() + b0, nb, threads, lds64,
                                   (int)gx, X, split ? nullptr : static_cast<float2*>(ws),

@@ -113,17 +113,12 @@ struct FftDesc {
   int ldz4;
   const double2* tw2;  // two-level table of exp(i pi k / P), k <= P
   int ntw;             // entries of tw and of tw2: 128 + P / 128 + 1
-  // pass twiddles of fp in the working precision: pass p (radix R, Ns points
-  // already combined) keeps exp(2 pi i jm r / (Ns R)) at ptw[off_p + (r-1) Ns
-  // + jm], r = 1 .. R-1, jm < Ns; off_p = sum of (R-1) Ns over earlier passes
-  const cplx_t<T>* ptw;
   // the fused launch gives each workgroup 2^lb right-hand sides of this block
   // (2^lb fp.P <= the launch's largest fp.P)
   int lb;
   // 1: the transform of P = L/2 points is split by the parity of its outputs
-  // into two halves of fp.P = P/2 points, one workgroup each (fp, ptw: P/2)
+  // into two halves of fp.P = P/2 points, one workgroup each (fp: P/2)
   int half;
-  int ntab;  // entries of ptw
 };
 
 // grid: gx x nblk workgroups of `threads`; lds: bytes of the largest
@@ -131,12 +126,12 @@ struct FftDesc {
 template <typename T>
 void launch_exec_fft_multi(const FftDesc<T>* descs, int nblk, int threads, size_t lds, int gx,
                            const T* X, cplx_t<T>* Z, int R, int64_t N, hipStream_t s);
-// LDS of a fused FFT workgroup of pts points whose block has a pass table of
-// ntab entries (float32) or a two-level table of ntw entries (float64)
+// LDS of a fused FFT workgroup of pts points whose block has two-level
+// twiddle tables of ntw entries (tw and tw2, float64)
 template <typename T>
-inline size_t fused_lds_bytes(int pts, int ntab, int ntw) {
+inline size_t fused_lds_bytes(int pts, int ntw) {
   const size_t data = ((size_t)pts * sizeof(cplx_t<T>) + 15) & ~(size_t)15;
-  return data + (sizeof(T) == 4 ? (size_t)ntab * sizeof(cplx_t<T>) : (size_t)ntw * 16);
+  return data + 2 * (size_t)ntw * sizeof(double2);
 }
 
 template <typename T>

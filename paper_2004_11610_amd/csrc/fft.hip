@@ -53,35 +53,35 @@ __global__ __launch_bounds__(FFT_MAX_THREADS) void exec_fft_kernel(ExecFftArgs<T
   for (int k = tid; k <= a.P; k += nt) z[k] = unpack<+1>(lds, a.P, k, a.post, a.scale);
 }
 
-// The pass twiddles of a block staged into LDS after its points (so that the
-// passes wait for no global memory): float32 the per-pass table (ntab = fp.P -
-// 1 entries), float64 the two-level table (ntw entries).  load() requests
-// them; store() writes them once they arrive, after the caller has requested
-// its points, so both share one wait.
+// The twiddles of a block staged into LDS after its points, so that the
+// passes and the unpacking wait for no global memory: the two-level float64
+// tables of exp(2 pi i q / P) (tw) and of exp(i pi k / P) (tw2), ntw entries
+// each (a few KB, which leaves LDS for other workgroups on the CU).  load()
+// requests them; store() writes them once they arrive, after the caller has
+// requested its points, so both share one wait.
 template <typename T, int EI>
 struct TabStage {
-  using C = cplx_t<T>;
-  using V = typename std::conditional<sizeof(T) == 4, C, double2>::type;
-  static constexpr int SLOTS = sizeof(T) == 4 ? EI : 2;
-  V v[SLOTS];
-  const V* src;
+  static constexpr int SLOTS = 2;
+  double2 v[2][SLOTS];
+  const double2* src[2];
   int n;
   __device__ __forceinline__ void load(const FftDesc<T>* d, int tid, int nt) {
-    if constexpr (sizeof(T) == 4) {
-      src = d->ptw;
-      n = d->ntab;
-    } else {
-      src = d->tw;
-      n = d->ntw;
-    }
+    src[0] = d->tw;
+    src[1] = d->tw2;
+    n = d->ntw;
 #pragma unroll
-    for (int e = 0; e < SLOTS; ++e) v[e] = gload(src + min(tid + e * nt, n - 1));
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int e = 0; e < SLOTS; ++e) v[t][e] = gload(src[t] + min(tid + e * nt, n - 1));
   }
-  __device__ __forceinline__ void store(V* dst, int tid, int nt) const {
+  __device__ __forceinline__ void store(double2* dst, int tid, int nt) const {
 #pragma unroll
-    for (int e = 0; e < SLOTS; ++e)
-      if (tid + e * nt < n) dst[tid + e * nt] = v[e];
-    for (int i = tid + SLOTS * nt; i < n; i += nt) dst[i] = gload(src + i);
+    for (int t = 0; t < 2; ++t) {
+#pragma unroll
+      for (int e = 0; e < SLOTS; ++e)
+        if (tid + e * nt < n) dst[t * n + tid + e * nt] = v[t][e];
+      for (int i = tid + SLOTS * nt; i < n; i += nt) dst[t * n + i] = gload(src[t] + i);
+    }
   }
 };
 
@@ -127,10 +127,9 @@ __device__ __forceinline__ cplx_t<T> point_pair(const TI* __restrict__ x, const 
 // SPLIT: the half spectra are written as three bfloat16 planes (the pieces of
 // the split-bf16 product, layout in common.hpp) instead of complex values.
 // BATCH == false: one transform (lb == 0), indexed without the interleaving.
-// EARLY: the unpack twiddles are requested with the points (registers permitting)
 // EI: points per thread, FFT_EPT or fewer (2^lb P <= EI nt): loops over the
 // thread's points stop there instead of clamping indexes past the end
-template <typename T, typename TI, bool SPLIT, bool BATCH, bool EARLY, int EI>
+template <typename T, typename TI, bool SPLIT, bool BATCH, int EI>
 __device__ __forceinline__ void fft_multi_body(const FftDesc<T>* __restrict__ d,
                                                const TI* __restrict__ X, cplx_t<TI>* __restrict__ Z,
                                                uint32_t* __restrict__ Zs, int64_t zplane, int R,
@@ -146,23 +145,9 @@ __device__ __forceinline__ void fft_multi_body(const FftDesc<T>* __restrict__ d,
   const int c_lo = d->c_lo, c_hi = d->c_hi, m_off = d->m_off;
   const T* __restrict__ winv = d->winv;
   const T scale = d->scale;
-  const C* __restrict__ post = d->post;
-  // The unpack twiddles of the thread's outputs (see below) and the pass
-  // twiddles are requested first, then the points, so that all of them arrive
-  // within one wait.
+  // The twiddle tables are requested first, then the points, so that all of
+  // them arrive within one wait.
   constexpr int GS = EI / 4 + 2;  // output groups per thread (SPLIT)
-  constexpr int NTW = SPLIT ? 4 * GS : EI + 1;
-  C tw[NTW];
-  auto load_tw = [&]() {
-#pragma unroll
-    for (int e = 0; e < NTW; ++e) {
-      if constexpr (SPLIT)
-        tw[e] = gload(post + min(4 * ((tid + (e / 4) * nt) >> lb) + (e % 4), P));
-      else
-        tw[e] = gload(post + min((tid + e * nt) >> lb, P));
-    }
-  };
-  if constexpr (EARLY) load_tw();
   TabStage<T, EI> ts;
   ts.load(d, tid, nt);
   // E1: the thread's points (float32: all at once; float64: in two rounds, for
@@ -170,7 +155,8 @@ __device__ __forceinline__ void fft_multi_body(const FftDesc<T>* __restrict__ d,
   // zero.  Loads are branch-free: indexes past the end are clamped.
   constexpr int ROUND = (sizeof(T) == 4 || EI <= FFT_EPT / 2) ? EI : FFT_EPT / 2;
   const int pts = P << lb;
-  auto* ltab = reinterpret_cast<typename TabStage<T, EI>::V*>(smem_raw + tab_offset<T>(pts));
+  double2* ltab = reinterpret_cast<double2*>(smem_raw + tab_offset<T>(pts));
+  const double2* ltab2 = ltab + d->ntw;  // exp(i pi k / P)
   auto input = [&](auto vtag) {
     constexpr bool VEC = decltype(vtag)::value;
 #pragma unroll
@@ -198,13 +184,8 @@ __device__ __forceinline__ void fft_multi_body(const FftDesc<T>* __restrict__ d,
   else
     input(std::false_type{});
   __syncthreads();
-  // E2: F*; float32 reads its pass twiddles from the block's table, float64
-  // forms them from the two-level table
-  if constexpr (sizeof(T) == 4)
-    run_fft_tab<+1, BATCH, EI>(lds, P, lb, d->fp.npass, d->fp.radix, ltab, tid, nt, true);
-  else
-    run_fft<+1, BATCH, EI>(lds, P, lb, d->fp.npass, d->fp.radix, ltab, 1, tid, nt, true);
-  if constexpr (!EARLY) load_tw();
+  // E2: F*, the pass twiddles formed from the two-level table
+  run_fft<+1, BATCH, EI>(lds, P, lb, d->fp.npass, d->fp.radix, ltab, 1, tid, nt, true);
   // unpack point k of transform t (see unpack_with)
   auto unpack_at = [&](int k, int t, C tw) {
     C ck = lds[((k == P ? 0 : k) << lb) + t];
@@ -224,7 +205,7 @@ __device__ __forceinline__ void fft_multi_body(const FftDesc<T>* __restrict__ d,
       const int u = tid + e * nt;
       const int k = u >> lb, t = u & tmask;
       if (u < n && t < cnt) {
-        const C z = unpack_at(k, t, tw[e]);
+        const C z = unpack_at(k, t, to_c<C>(twiddle(ltab2, k)));
         Z[(int64_t)R * d->zoff + (int64_t)(r0 + t) * d->ldz + k] = cplx_t<TI>{TI(z.x), TI(z.y)};
       }
     }
@@ -243,7 +224,7 @@ __device__ __forceinline__ void fft_multi_body(const FftDesc<T>* __restrict__ d,
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int k = 4 * q + j;
-        const C z = k <= P ? unpack_at(k, t, tw[4 * e + j]) : C{T(0), T(0)};
+        const C z = k <= P ? unpack_at(k, t, to_c<C>(twiddle(ltab2, k))) : C{T(0), T(0)};
         spmmcore::split2(spmmcore::f32x2{(float)z.x, (float)z.y}, pc[j]);
       }
       uint32_t* __restrict__ zs = Zs + (int64_t)R * d->zoff4 + (int64_t)(r0 + t) * d->ldz4;
@@ -261,7 +242,7 @@ __device__ __forceinline__ void fft_multi_body(const FftDesc<T>* __restrict__ d,
 // a transform of H points (one decimation-in-frequency step).  The unpack
 // pairs C_k with C_(P-k), of the same parity, so the half is complete: it
 // writes the half spectrum at every k of parity p (zeros past P).
-template <typename T, typename TI, bool SPLIT, bool EARLY, int EI>
+template <typename T, typename TI, bool SPLIT, int EI>
 __device__ __forceinline__ void fft_half_body(const FftDesc<T>* __restrict__ d,
                                               const TI* __restrict__ X, cplx_t<TI>* __restrict__ Z,
                                               uint32_t* __restrict__ Zs, int64_t zplane, int R,
@@ -275,17 +256,11 @@ __device__ __forceinline__ void fft_half_body(const FftDesc<T>* __restrict__ d,
   const T* __restrict__ winv = d->winv;
   const TI* __restrict__ x = X + (int64_t)r * N;
   const C* __restrict__ post = d->post;  // post[2n] = w^n
-  // the unpack twiddles of the thread's outputs k = 2 (tid + e nt) + par and
-  // the pass twiddles first, then the points: one wait for all of them
-  C tw[EI + 1];
-  auto load_tw = [&]() {
-#pragma unroll
-    for (int e = 0; e <= EI; ++e) tw[e] = gload(post + min(2 * (tid + e * nt) + par, P));
-  };
-  if constexpr (EARLY) load_tw();
+  // the twiddle tables first, then the points: one wait for all of them
   TabStage<T, EI> ts;
   ts.load(d, tid, nt);
-  auto* ltab = reinterpret_cast<typename TabStage<T, EI>::V*>(smem_raw + tab_offset<T>(H));
+  double2* ltab = reinterpret_cast<double2*>(smem_raw + tab_offset<T>(H));
+  const double2* ltab2 = ltab + d->ntw;  // exp(i pi k / P)
   constexpr int ROUND = (sizeof(T) == 4 || EI <= FFT_EPT / 2) ? EI : FFT_EPT / 2;
   auto input = [&](auto vtag) {
     constexpr bool VEC = decltype(vtag)::value;
@@ -312,15 +287,13 @@ __device__ __forceinline__ void fft_half_body(const FftDesc<T>* __restrict__ d,
   else
     input(std::false_type{});
   __syncthreads();
-  if constexpr (sizeof(T) == 4)
-    run_fft_tab<+1, false, EI>(lds, H, 0, d->fp.npass, d->fp.radix, ltab, tid, nt, true);
-  else  // the two-level table is of length P = 2H: index scale 2
-    run_fft<+1, false, EI>(lds, H, 0, d->fp.npass, d->fp.radix, ltab, 2, tid, nt, true);
-  if constexpr (!EARLY) load_tw();
+  // the two-level table is of length P = 2H: index scale 2
+  run_fft<+1, false, EI>(lds, H, 0, d->fp.npass, d->fp.radix, ltab, 2, tid, nt, true);
   // k = 2m + par: C_k at lds[m mod H], C_(P-k) at lds[(H - m) mod H] (par 0)
   // or lds[H - 1 - m] (par 1)
   const T scale = d->scale;
-  auto zval = [&](int m, C tw) {
+  auto zval = [&](int m) {
+    const C tw = to_c<C>(twiddle(ltab2, min(2 * m + par, P)));
     const int k = 2 * m + par;
     if (k > P) return C{T(0), T(0)};
     C ck = lds[m == H ? 0 : m];
@@ -339,7 +312,7 @@ __device__ __forceinline__ void fft_half_body(const FftDesc<T>* __restrict__ d,
   for (int e = 0; e <= EI; ++e) {
     const int m = tid + e * nt, k = 2 * m + par;
     if (k >= kend) break;
-    const C z = zval(m, tw[e]);
+    const C z = zval(m);
     if constexpr (!SPLIT) {
       Z[(int64_t)R * d->zoff + (int64_t)r * d->ldz + k] = cplx_t<TI>{TI(z.x), TI(z.y)};
     } else {
@@ -356,11 +329,13 @@ __device__ __forceinline__ void fft_half_body(const FftDesc<T>* __restrict__ d,
 // registers, 1024 leaves 128).  TI: type of X and of the complex spectra Z
 // (float with T = double: the float32 paths' transforms in float64
 // arithmetic, each spectrum value rounded once to float32).
+// Float32 arithmetic at 512 threads is held to 128 registers, so that two
+// workgroups share a CU (their memory waits and passes overlap).
 template <typename T, typename TI, bool SPLIT, int MAXT>
-__global__ __launch_bounds__(MAXT) void exec_fft_multi_kernel(
+__global__ __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(
+    sizeof(T) == 4 && MAXT <= 512 ? 4 : 1))) void exec_fft_multi_kernel(
     const FftDesc<T>* __restrict__ descs, const TI* __restrict__ X, cplx_t<TI>* __restrict__ Z,
     uint32_t* __restrict__ Zs, int64_t zplane, int R, int64_t N) {
-  constexpr bool EARLY = MAXT <= 512;
   // transforms of at most EI_SHORT points per thread take the variant whose
   // loops stop there
   constexpr int EI_SHORT = FFT_EPT / 2;
@@ -372,9 +347,9 @@ __global__ __launch_bounds__(MAXT) void exec_fft_multi_kernel(
     const int par = (int)blockIdx.x >= R ? 1 : 0;
     const int r = (int)blockIdx.x - par * R;
     if (d->fp.P <= EI_SHORT * (int)blockDim.x)
-      fft_half_body<T, TI, SPLIT, EARLY, EI_SHORT>(d, X, Z, Zs, zplane, R, N, r, par);
+      fft_half_body<T, TI, SPLIT, EI_SHORT>(d, X, Z, Zs, zplane, R, N, r, par);
     else
-      fft_half_body<T, TI, SPLIT, EARLY, FFT_EPT>(d, X, Z, Zs, zplane, R, N, r, par);
+      fft_half_body<T, TI, SPLIT, FFT_EPT>(d, X, Z, Zs, zplane, R, N, r, par);
     return;
   }
   const int lb = d->lb;
@@ -383,14 +358,14 @@ __global__ __launch_bounds__(MAXT) void exec_fft_multi_kernel(
   const bool short_pts = (d->fp.P << lb) <= EI_SHORT * (int)blockDim.x;
   if (lb == 0) {
     if (short_pts)
-      fft_multi_body<T, TI, SPLIT, false, EARLY, EI_SHORT>(d, X, Z, Zs, zplane, R, N, 0, r0);
+      fft_multi_body<T, TI, SPLIT, false, EI_SHORT>(d, X, Z, Zs, zplane, R, N, 0, r0);
     else
-      fft_multi_body<T, TI, SPLIT, false, EARLY, FFT_EPT>(d, X, Z, Zs, zplane, R, N, 0, r0);
+      fft_multi_body<T, TI, SPLIT, false, FFT_EPT>(d, X, Z, Zs, zplane, R, N, 0, r0);
   } else {
     if (short_pts)
-      fft_multi_body<T, TI, SPLIT, true, EARLY, EI_SHORT>(d, X, Z, Zs, zplane, R, N, lb, r0);
+      fft_multi_body<T, TI, SPLIT, true, EI_SHORT>(d, X, Z, Zs, zplane, R, N, lb, r0);
     else
-      fft_multi_body<T, TI, SPLIT, true, EARLY, FFT_EPT>(d, X, Z, Zs, zplane, R, N, lb, r0);
+      fft_multi_body<T, TI, SPLIT, true, FFT_EPT>(d, X, Z, Zs, zplane, R, N, lb, r0);
   }
 }
 

@@ -900,9 +900,9 @@ __global__ __launch_bounds__(256) void spmm_presplit_items_kernel(SpmmSplitBatch
 // workgroups) each stores into a slot of partial sums, and
 // spmm_t_reduce_kernel adds a chunk's slots in order (deterministic, no
 // atomics).  Thread: columns 2 cg, 2 cg + 1 and right-hand sides 4 rq ..
-// 4 rq + 3 of the chunk.  Sums are accumulated in float64 for either
-// precision (float32: products of float32 values are exact in float64, and
-// the sums are rounded to float32 once, where they are stored).
+// 4 rq + 3 of the chunk.  A tile's 16 rows are summed in the working
+// precision, the tiles' sums in float64 for either precision (rounded to the
+// working precision once, where they are stored).
 template <typename T>
 __global__ __launch_bounds__(256) void spmm_transposed_kernel(SpmmTArgs<T> a) {
   using C = cplx_t<T>;
@@ -982,19 +982,19 @@ __global__ __launch_bounds__(256) void spmm_transposed_kernel(SpmmTArgs<T> a) {
       for (int t = 0; t < TPR; ++t) {
         if (t >= cnt) break;
         // the tile's 16 rows summed first, then added (running sums stay short)
-        D part[4][2];
+        C part[4][2];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) part[j][0] = part[j][1] = D{0.0, 0.0};
+        for (int j = 0; j < 4; ++j) part[j][0] = part[j][1] = C{T(0), T(0)};
 #pragma unroll
         for (int q = 0; q < TILE_ROWS; ++q) {
           const C a0 = as[t][q][2 * cg], a1 = as[t][q][2 * cg + 1];
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
-            const double fv = fs[t][4 * rq + j][q];
-            part[j][0].x += (double)a0.x * fv;
-            part[j][0].y += (double)a0.y * fv;
-            part[j][1].x += (double)a1.x * fv;
-            part[j][1].y += (double)a1.y * fv;
+            const T fv = fs[t][4 * rq + j][q];
+            part[j][0].x += a0.x * fv;
+            part[j][0].y += a0.y * fv;
+            part[j][1].x += a1.x * fv;
+            part[j][1].y += a1.y * fv;
           }
         }
 #pragma unroll
