@@ -85,13 +85,15 @@ class Compressed:
         return [m.nnz for m in self.mats]
 
     def execute(self, X):
-        """Y = A X^T for X of shape (R, N) (one right-hand side per row)."""
-        X = np.atleast_2d(np.asarray(X, dtype=np.float64))
+        """Y = A X^T for X of shape (R, N) (one right-hand side per row); complex
+        families take and return complex X and Y."""
+        cplx = self.plan.fam.is_complex
+        X = np.atleast_2d(np.asarray(X, dtype=np.complex128 if cplx else np.float64))
         R, N = X.shape
         Y = np.zeros((R, N), dtype=np.complex128)
         for blk, S in zip(self.plan.blocks, self.mats):
             w = self.plan.window(blk)
-            v = np.zeros((R, blk.L))
+            v = np.zeros((R, blk.L), dtype=X.dtype)
             m_lo, m_hi = blk.c_lo + blk.m_offset, blk.c_hi + blk.m_offset
             v[:, blk.c_lo:blk.c_hi] = X[:, m_lo:m_hi] / w[None, blk.c_lo:blk.c_hi]
             z = np.fft.ifft(v, axis=1, norm="ortho")       # F* W^{-1} v
@@ -99,6 +101,8 @@ class Compressed:
         t = self.plan.tail
         if t:
             Y += X[:, :t] @ self.tail_matrix.T
+        if cplx:
+            return Y
         imag = np.abs(Y.imag).max() if Y.size else 0.0
         real = np.abs(Y.real).max() if Y.size else 0.0
         assert imag <= 1e-9 * max(real, 1e-300), "imaginary part does not vanish"

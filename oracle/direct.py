@@ -12,9 +12,10 @@ import numpy as np
 
 
 def matvec(fam, X, rows=None, panel=1024):
-    X = np.atleast_2d(np.asarray(X, dtype=np.float64))
+    cplx = getattr(fam, "is_complex", False)
+    X = np.atleast_2d(np.asarray(X, dtype=np.complex128 if cplx else np.float64))
     rows = np.arange(fam.N) if rows is None else np.asarray(rows)
-    Y = np.empty((X.shape[0], rows.size))
+    Y = np.empty((X.shape[0], rows.size), dtype=X.dtype)
     for p in range(0, rows.size, panel):
         A = fam.block(rows[p:p + panel], 0, fam.N)
         Y[:, p:p + panel] = X @ A.T
@@ -23,9 +24,10 @@ def matvec(fam, X, rows=None, panel=1024):
 
 def matvec_transposed(fam, F, cols=None, panel=1024):
     """fhat = A^T f: fhat[r, m] = sum_j A[j, m] F[r, j] for degrees m in ``cols``."""
-    F = np.atleast_2d(np.asarray(F, dtype=np.float64))
+    cplx = getattr(fam, "is_complex", False)
+    F = np.atleast_2d(np.asarray(F, dtype=np.complex128 if cplx else np.float64))
     cols = np.arange(fam.N) if cols is None else np.asarray(cols)
-    out = np.zeros((F.shape[0], cols.size))
+    out = np.zeros((F.shape[0], cols.size), dtype=F.dtype)
     lo, hi = int(cols.min()), int(cols.max()) + 1
     for p in range(0, fam.N, panel):
         rows = np.arange(p, min(p + panel, fam.N))

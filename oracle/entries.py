@@ -81,6 +81,39 @@ def cos_power(j, N, m0, m1, s):
     return chebyshev_t(j, N, m0, m1) ** int(s)
 
 
+def cexp(j, N, m0, m1):
+    """exp(i m theta_j) at the Chebyshev-Gauss angles: the complex generator of
+    sec. 2 (after Algorithm 2), cos + i sin at the exact angle of chebyshev_t."""
+    return chebyshev_t(j, N, m0, m1) + 1j * sine(j, N, m0, m1)
+
+
+# --------------------------------------------------------------------------- Laguerre, spectral domain
+
+def laguerre_spectral_k(j, T):
+    """k_j = 2 pi j / T, the wave numbers of the Fourier coefficients (sec. 4.1)."""
+    return 2.0 * np.pi * np.asarray(j, dtype=np.float64) / T
+
+
+def laguerre_spectral_phase(j, eta, T):
+    """phi_j with (-eta/2 - i k_j) / (eta/2 - i k_j) = exp(i phi_j): the ratio
+    has modulus one and equals -(eta/2 + i k)/(eta/2 - i k) = exp(i (pi + 2
+    atan(2k/eta))); phi_j = 2 atan(2 k_j / eta) - pi, in [-pi, 0)."""
+    return 2.0 * np.arctan(2.0 * laguerre_spectral_k(j, T) / eta) - np.pi
+
+
+def laguerre_spectral(j, eta, T, m0, m1, phi=None):
+    """C[j, m] = (-eta/2 - i k_j)^m / (eta/2 - i k_j)^(m+1)  (eq. main_formula2,
+    the matrix of eq. lag_matrix), evaluated as exp(i m phi_j) / (eta/2 - i k_j)
+    with the phase m phi_j a float64 product (rounded once).  phi: the row
+    phases to use (laguerre_spectral_phase by default)."""
+    j = np.asarray(j)
+    k = laguerre_spectral_k(j, T)
+    ph = laguerre_spectral_phase(j, eta, T) if phi is None else np.asarray(phi, dtype=np.float64)
+    m = np.arange(m0, m1, dtype=np.float64)
+    ang = np.outer(ph, m)
+    return np.exp(1j * ang) / (0.5 * eta - 1j * k)[:, None]
+
+
 # --------------------------------------------------------------------------- Jacobi
 
 def jacobi_coefficients(n, alpha, beta):

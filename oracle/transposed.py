@@ -15,17 +15,23 @@ import numpy as np
 
 
 def execute(comp, F):
-    """Fhat (R x N) with Fhat[r, m] = sum_j A[j, m] F[r, j]."""
-    F = np.atleast_2d(np.asarray(F, dtype=np.float64))
-    R, N = F.shape
+    """Fhat (R x N) with Fhat[r, m] = sum_j A[j, m] F[r, j] (the transpose, not
+    the conjugate transpose, for the complex families: eq. lag_matrix's
+    V = C^T F)."""
     plan = comp.plan
-    out = np.zeros((R, N))
+    cplx = plan.fam.is_complex
+    F = np.atleast_2d(np.asarray(F, dtype=np.complex128 if cplx else np.float64))
+    R, N = F.shape
+    out = np.zeros((R, N), dtype=F.dtype)
     for blk, S in zip(plan.blocks, comp.mats):
         w = plan.window(blk)
         u = (S.T @ F.T).T                                   # (R, L)
         g = np.fft.ifft(u, axis=1, norm="ortho")            # F* u
-        assert np.abs(g.imag).max() <= 1e-9 * max(np.abs(g.real).max(), 1e-300)
-        g = g.real / w[None, :]
+        if cplx:
+            g = g / w[None, :]
+        else:
+            assert np.abs(g.imag).max() <= 1e-9 * max(np.abs(g.real).max(), 1e-300)
+            g = g.real / w[None, :]
         m_lo, m_hi = blk.c_lo + blk.m_offset, blk.c_hi + blk.m_offset
         out[:, m_lo:m_hi] += g[:, blk.c_lo:blk.c_hi]
     t = plan.tail
