@@ -37,6 +37,20 @@
  *                    cosine one (sec. 2, after Algorithm 2).
  *   SPT_COS_POWER    A[j,m] = cos(m theta_j)^s, s = spt_params.power in 2..5
  *                    (eq. cosd2), at the Chebyshev-Gauss angles.
+ *   SPT_CEXP         A[j,m] = exp(i m theta_j) at the Chebyshev-Gauss angles: the
+ *                    complex generator of sec. 2 (after Algorithm 2).
+ *   SPT_LAGUERRE_SPECTRAL  A[j,m] = C[j,m] = (-eta/2 - i k_j)^m / (eta/2 - i k_j)^(m+1)
+ *                    (sec. 4.1, eqs. main_formula2 and lag_matrix), k_j = 2 pi j / T
+ *                    (spt_params.eta, .period): row j is exp(i m phi_j) /
+ *                    (eta/2 - i k_j) with phi_j = 2 atan(2 k_j / eta) - pi (the
+ *                    row phases; spt_params.nodes may give them instead); the
+ *                    Laguerre coefficients of the spectral method are
+ *                    V = C^T F (spt_execute_transposed).
+ *   The complex generators (SPT_CEXP, SPT_LAGUERRE_SPECTRAL) use Algorithm 1 with
+ *   extras on both sides and the full spectrum; X and Y are complex (interleaved
+ *   re, im), float64 for SPT_F64 and float32 for SPT_F32 (transforms in float64
+ *   arithmetic; SPT_SPLIT_BF16 unsupported); plans need L <= 10240 (one
+ *   workgroup's transform); staged executor, no batches.
  *   The trigonometric generators (SPT_CHEBYSHEV_T, SPT_SINE, SPT_COS_POWER)
  *   use Algorithm 1, extras on both sides (the generator continues to m < 0);
  *   the others use the block method (sec. 3): extras on the right only,
@@ -85,7 +99,10 @@ typedef enum {
   SPT_LAGUERRE_FN = 4,
   SPT_HERMITE_FN = 5,
   SPT_SINE = 6,
-  SPT_COS_POWER = 7
+  SPT_COS_POWER = 7,
+  SPT_CEXP = 8,              /* complex: exp(i m theta_j), Chebyshev-Gauss angles */
+  SPT_LAGUERRE_SPECTRAL = 9  /* complex: the matrix C of the spectral-domain
+                                Laguerre transform (sec. 4.1, eq. lag_matrix) */
 } spt_family;
 
 /* Arithmetic of the execute path.  The precomputation is always float64. */
@@ -150,6 +167,9 @@ typedef struct {
                              near each tone of the row.  The window's side
                              lobes make this an approximation: q = 12 moves an
                              entry by < 0.25 eps max|A_e W F|                     */
+  double eta;             /* SPT_LAGUERRE_SPECTRAL: the Laguerre scale eta > 0    */
+  double period;          /* SPT_LAGUERRE_SPECTRAL: the interval length T > 0 of
+                             the Fourier series (k_j = 2 pi j / T)               */
   int32_t reduced_fft;    /* arithmetic of the x-side FFTs (and of the transposed
                              product's single-workgroup inverse FFTs) of the
                              SPT_F32 and SPT_SPLIT_BF16 paths, staged executor:
@@ -202,6 +222,7 @@ typedef struct {
                                             more than 4x the half spectra's memory) */
   int64_t reduced_fft_f64;               /* 1: the F32 and SPLIT_BF16 paths' FFTs run
                                             in float64 arithmetic (spt_params.reduced_fft) */
+  int64_t is_complex;                    /* 1: complex matrix, data and spectra      */
   double reduced_fft_f32_err;            /* the measurement behind an automatic choice
                                             (spt_params.reduced_fft): relative error
                                             with float32 FFTs against the float64 path

@@ -13,13 +13,14 @@ from . import _lib
 from ._lib import SptError  # noqa: F401
 
 CHEBYSHEV_T, LEGENDRE, JACOBI, LAGUERRE_FN, HERMITE_FN, SINE, COS_POWER = 1, 2, 3, 4, 5, 6, 7
+CEXP, LAGUERRE_SPECTRAL = 8, 9  # complex generators
 F64, F32, SPLIT_BF16 = 0, 1, 2
 MODE_AUTO, MODE_ROW, MODE_DIRECT = 0, 1, 3
 FFT_AUTO, FFT_F32, FFT_F64 = 0, 1, 2
 EXECUTOR_AUTO, EXECUTOR_STAGED, EXECUTOR_PERSISTENT = 0, 1, 2
 FAMILIES = {"chebyshev_t": CHEBYSHEV_T, "legendre": LEGENDRE, "jacobi": JACOBI,
             "laguerre_fn": LAGUERRE_FN, "hermite_fn": HERMITE_FN, "sine": SINE,
-            "cos_power": COS_POWER}
+            "cos_power": COS_POWER, "cexp": CEXP, "laguerre_spectral": LAGUERRE_SPECTRAL}
 PRECISIONS = {"f64": F64, "f32": F32, "split_bf16": SPLIT_BF16}
 
 
@@ -32,8 +33,10 @@ def _stream_ptr(stream):
     return c_void_p(stream.cuda_stream)
 
 
-def _dtype_for(prec):
+def _dtype_for(prec, complex_=False):
     import torch
+    if complex_:
+        return torch.complex128 if prec == F64 else torch.complex64
     return torch.float64 if prec == F64 else torch.float32
 
 
@@ -46,7 +49,7 @@ class Plan:
     def __init__(self, family, N, eps, alpha=0.0, beta=0.0, eps2=0.0, mode=MODE_AUTO,
                  unweighted=False, precisions=0, min_block=0, exact_fft_len=False,
                  panel_rows=0, nodes=None, executor=EXECUTOR_AUTO, power=0, trig_conv_q=0,
-                 reduced_fft=0):
+                 reduced_fft=0, eta=0.0, period=0.0):
         self._lib = _lib.load()
         self._h = c_void_p()
         p = _lib.SptParams()
@@ -57,6 +60,7 @@ class Plan:
         p.power = int(power)
         p.trig_conv_q = int(trig_conv_q)
         p.reduced_fft = int(reduced_fft)
+        p.eta, p.period = float(eta), float(period)
         self._nodes_buf = None
         if nodes is not None:
             self._nodes_buf = (c_double * N)(*[float(v) for v in nodes])
@@ -65,6 +69,7 @@ class Plan:
         _lib.check(self._lib.spt_plan_create(byref(self._h), int(fam), byref(p), int(N),
                                              float(eps)))
         self.family, self.N, self.eps = fam, int(N), float(eps)
+        self.is_complex = fam in (CEXP, LAGUERRE_SPECTRAL)
 
     # ------------------------------------------------------------------ lifetime
     def close(self):
@@ -126,7 +131,7 @@ class Plan:
 
     def _check_io(self, X, Y, prec):
         import torch
-        dt = _dtype_for(prec)
+        dt = _dtype_for(prec, self.is_complex)
         if X.dtype != dt or not X.is_cuda or not X.is_contiguous() or X.shape[-1] != self.N:
             raise ValueError("X must be a contiguous CUDA %s tensor of shape (R, %d)" % (dt, self.N))
         R = X.numel() // self.N

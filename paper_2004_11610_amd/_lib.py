@@ -18,7 +18,8 @@ class SptParams(ctypes.Structure):
                 ("mode", c_int32), ("unweighted", c_int32), ("precisions", c_uint32),
                 ("min_block", c_int32), ("exact_fft_len", c_int32), ("executor", c_int32),
                 ("panel_rows", c_int64), ("nodes", POINTER(c_double)), ("power", c_int32),
-                ("trig_conv_q", c_int32), ("reduced_fft", c_int32)]
+                ("trig_conv_q", c_int32), ("eta", c_double), ("period", c_double),
+                ("reduced_fft", c_int32)]
 
 
 class SptPlanInfo(ctypes.Structure):
@@ -30,7 +31,7 @@ class SptPlanInfo(ctypes.Structure):
                 ("kappa", c_double), ("nnz_blk", c_int64 * 16), ("window_lds", c_int64),
                 ("window_cols", c_int64), ("window_chunked", c_int64),
                 ("transposed_segment", c_int64), ("reduced_fft_f64", c_int64),
-                ("reduced_fft_f32_err", c_double)]
+                ("is_complex", c_int64), ("reduced_fft_f32_err", c_double)]
 
 
 ALLOC_FN = ctypes.CFUNCTYPE(c_void_p, ctypes.c_size_t, c_void_p, c_void_p)

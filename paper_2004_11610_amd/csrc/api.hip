@@ -168,6 +168,19 @@ struct ExecCtx {
 
 bool is_jacobi(int f) { return f == SPT_LEGENDRE || f == SPT_JACOBI; }
 
+// A complex plan's one block (Algorithm 1): full-spectrum tile boxes, the
+// columns k0 .. k0 + kw - 1 of a box in 0 .. L + pad - 1 (past L - 1: the
+// spectrum's first columns again), the transposed product's chunk lists.
+struct CplxState {
+  int L = 0, pad = 0, m_off = 0, c_lo = 0, c_hi = 0, n_chunks = 0;
+  FftPlan fp;
+  DevBuf winv, tw, meta, val64, val32, tptr, tents;
+  std::vector<double> angles;  // row angles theta_j (SPT_CEXP) or phases phi_j
+  int64_t nnz = 0, stored = 0;
+  int max_band = 0;
+  double maxabs = 0.0, kappa = 0.0;
+};
+
 }  // namespace
 }  // namespace spt
 
@@ -223,6 +236,7 @@ struct spt_plan {
   int64_t serial = 0;  // changes with every precompute (keys of executor contexts)
   std::vector<std::unique_ptr<spt::ExecCtx>> ctx;  // executor contexts of spt_execute
   uint32_t exec_wait = spt::EXEC_WAIT_DEFAULT;      // persistent executor: wait bound, ticks
+  std::unique_ptr<spt::CplxState> cx;  // complex generators (is_complex_family)
   // the float32 and split-bf16 paths' x-side FFTs in float64 arithmetic
   // (spt_params.reduced_fft)
   bool reduced_fft64 = false;
@@ -1297,8 +1311,21 @@ void build_fft_descs(spt_plan_t plan, hipStream_t s) {
 
 void choose_reduced_fft(spt_plan_t plan, hipStream_t s);
 
+void precompute_complex(spt_plan_t plan, hipStream_t s);
+
 void precompute(spt_plan_t plan, hipStream_t s) {
   set_device(plan);
+  if (is_complex_family(plan->family)) {
+    plan->precomputed = false;
+    plan->serial = next_serial();
+    plan->prepared = plan->p.precisions ? plan->p.precisions : 3u;
+    plan->n_tiles = (int)tiles_of(plan->N);
+    plan->works.clear();
+    plan->work = nullptr;
+    precompute_complex(plan, s);
+    plan->precomputed = true;
+    return;
+  }
   const size_t lds_max = max_lds_bytes(plan->device);
   init_fft_kernels(lds_max);
   init_spmm_kernels(lds_max);
@@ -1433,6 +1460,9 @@ void choose_reduced_fft(spt_plan_t plan, hipStream_t s) {
 // partial sums after them), or the three bfloat16-pair planes of the
 // split-bf16 path
 size_t work_bytes(spt_plan_t plan, int64_t R, bool transposed) {
+  if (plan->cx)  // complex spectra (or transposed sums) of L + pad columns, float64
+    return (size_t)std::max<int64_t>(R, 1) * (size_t)(plan->cx->L + plan->cx->pad) *
+           sizeof(double2);
   const int64_t per = z_per_rhs(plan) + w_per_rhs(plan) + (transposed ? t_per_rhs(plan) : 0);
   return std::max((size_t)std::max<int64_t>(per, 1) * (size_t)R * sizeof(double2),
                   ((size_t)plan->zper4 * 3 * sizeof(uint32_t) +
@@ -1474,7 +1504,9 @@ void check_exec(spt_plan_t plan, const void* X, const void* Y, int64_t R, int pr
   if (prec < 0 || prec > 2) throw Error(SPT_E_INVALID_ARG, "unknown precision");
   if (!(plan->prepared & (1u << prec)))
     throw Error(SPT_E_UNSUPPORTED, "precision " + std::to_string(prec) + " was not prepared");
-  const size_t es = prec == SPT_F64 ? 8 : 4;
+  const size_t es = (prec == SPT_F64 ? 8 : 4) * (is_complex_family(plan->family) ? 2 : 1);
+  if (is_complex_family(plan->family) && prec == SPT_SPLIT_BF16)
+    throw Error(SPT_E_UNSUPPORTED, "complex plans execute in F64 or F32");
   const char* x0 = static_cast<const char*>(X);
   const char* y0 = static_cast<const char*>(Y);
   const size_t n = (size_t)R * plan->N * es;
@@ -1671,7 +1703,7 @@ void execute_transposed_t(spt_plan_t plan, const T* F, T* Y, int64_t R, hipStrea
   ta.F = F;
   ta.R = (int)R;
   ta.N = plan->N;
-  staged(SPT_STAGE_SPMM_T, s, [&] { launch_spmm_transposed<T>(ta, s); });
+  staged(SPT_STAGE_SPMM_T, s, [&] { launch_spmm_transposed<T>(ta, plan->reduced_fft64, s); });
   // the blocks that fit one workgroup in one launch (per block when four
   // steps are forced, a diagnostic)
   const bool multi = !inv_four_forced();
@@ -1743,6 +1775,223 @@ void execute_transposed_t(spt_plan_t plan, const T* F, T* Y, int64_t R, hipStrea
                                                                : (const T*)plan->tail32.p,
                                 (int)plan->tail, F, Y, (int)R, plan->N, s);
     });
+}
+
+// ---------------------------------------------------------------- complex generators
+template <typename F>
+void staged(int stage, hipStream_t s, F&& fn);
+
+// The compressed block of a complex plan: rows of A_e W by their closed forms
+// and their transforms F on the device in panels, then on the host the
+// threshold (eps1 times the block's maximum, Alg. 1 step 1.3), each row's kept
+// entries as one circular arc of the spectrum (a row is one tone), and the
+// tile boxes (union of their rows' arcs, unwrapped next to the first row's).
+void precompute_complex(spt_plan_t plan, hipStream_t s) {
+  if (plan->geom.size() != 1 || plan->tail != 0)
+    throw Error(SPT_E_UNSUPPORTED, "complex plans take Algorithm 1's single block");
+  auto cx = std::make_unique<CplxState>();
+  const BlockGeom g = plan->geom[0];
+  const int L = g.L;
+  const int64_t N = plan->N;
+  if (L > FUSED_MAX_P)
+    throw Error(SPT_E_UNSUPPORTED, "complex plans need L <= " + std::to_string(FUSED_MAX_P) +
+                                       " (one workgroup's transform); L = " + std::to_string(L));
+  cx->L = L;
+  cx->m_off = g.m_off;
+  cx->c_lo = g.c_lo;
+  cx->c_hi = g.c_hi;
+  cx->fp = make_fft_plan(L);
+  // window, its reciprocal, kappa
+  std::vector<double> w(L), winv(L);
+  double sw = 0.0, swi = 0.0;
+  for (int c = 0; c < L; ++c) {
+    w[c] = kaiser((double)c, (double)(L - 1), plan->zeta);
+    winv[c] = 1.0 / w[c];
+    sw += w[c] * w[c];
+    if (c >= g.c_lo && c < g.c_hi) swi += winv[c] * winv[c];
+  }
+  cx->kappa = std::sqrt(sw / L) * std::sqrt(swi / (g.c_hi - g.c_lo));
+  DevBuf dw;
+  upload(dw, w, s);
+  upload(cx->winv, winv, s);
+  std::vector<long double> twr, twi, por, poi;
+  twiddles(L, twr, twi, por, poi);
+  upload(cx->tw, to_vec2<double2, double>(twr, twi), s);
+  // row angles; for the Laguerre matrix C the phases phi_j and the factors
+  // 1 / (eta/2 - i k_j), k_j = 2 pi j / T
+  const long double pi = 3.141592653589793238462643383279502884L;
+  cx->angles.resize(N);
+  std::vector<double2> rowf;
+  if (plan->family == SPT_CEXP) {
+    for (int64_t j = 0; j < N; ++j)
+      cx->angles[j] = (double)(pi * (long double)(2 * j + 1) / (long double)(2 * N));
+  } else {
+    const double eta = plan->p.eta, T = plan->p.period;
+    rowf.resize(N);
+    for (int64_t j = 0; j < N; ++j) {
+      const double k = 2.0 * (double)pi * (double)j / T;
+      cx->angles[j] = plan->user_nodes.empty() ? 2.0 * std::atan(2.0 * k / eta) - (double)pi
+                                               : plan->user_nodes[j];
+      const double a = 0.5 * eta, d = a * a + k * k;
+      rowf[j] = double2{a / d, k / d};
+    }
+  }
+  DevBuf dphi, drowf;
+  if (!rowf.empty()) {
+    upload(dphi, cx->angles, s);
+    upload(drowf, rowf, s);
+  }
+  // spectra of all rows, panel by panel, to the host
+  const int64_t panel = std::max<int64_t>(1, std::min<int64_t>(N, (int64_t)(256 << 20) / (16 * L)));
+  DevBuf rows;
+  rows.alloc((size_t)panel * L * sizeof(double2), s);
+  std::vector<double2> S((size_t)N * L);
+  for (int64_t r0 = 0; r0 < N; r0 += panel) {
+    const int nr = (int)std::min<int64_t>(panel, N - r0);
+    CplxRowsArgs ra{rows.as<double2>(), dw.as<double>(), dphi.as<double>(), drowf.as<double2>(),
+                    N, r0, L, g.m_off, plan->family};
+    launch_cplx_rows(ra, nr, s);
+    launch_cplx_row_fft(rows.as<double2>(), nr, L, cx->fp, cx->tw.as<double2>(), s);
+    SPT_HIP(hipMemcpyAsync(S.data() + (size_t)r0 * L, rows.p, (size_t)nr * L * sizeof(double2),
+                           hipMemcpyDeviceToHost, s));
+  }
+  SPT_HIP(hipStreamSynchronize(s));
+  double mx2 = 0.0;
+  for (const double2& v : S) mx2 = std::max(mx2, v.x * v.x + v.y * v.y);
+  if (!std::isfinite(mx2))
+    throw Error(SPT_E_NUMERIC, "non-finite entries in the compressed complex block");
+  cx->maxabs = std::sqrt(mx2);
+  const double thr = plan->eps1 * cx->maxabs, thr2 = thr * thr;
+  auto kept = [&](int64_t n, int k) {
+    const double2 v = S[(size_t)n * L + k];
+    return v.x * v.x + v.y * v.y > thr2;
+  };
+  // each row's kept entries: the arc that leaves out the longest circular run
+  // of dropped columns; lo in [0, L), len columns (len 0: none kept)
+  std::vector<int> lo(N, 0), len(N, 0);
+  for (int64_t n = 0; n < N; ++n) {
+    std::vector<int> ks;
+    for (int k = 0; k < L; ++k)
+      if (kept(n, k)) ks.push_back(k);
+    if (ks.empty()) continue;
+    int gap = -1, at = 0;
+    for (size_t i = 0; i < ks.size(); ++i) {
+      const int nxt = i + 1 < ks.size() ? ks[i + 1] : ks[0] + L;
+      if (nxt - ks[i] > gap) {
+        gap = nxt - ks[i];
+        at = (int)((i + 1) % ks.size());
+      }
+    }
+    lo[n] = ks[at];
+    len[n] = L - gap + 1;
+    cx->nnz += (int64_t)ks.size();
+    cx->max_band = std::max(cx->max_band, len[n]);
+  }
+  // tile boxes
+  const int nt = plan->n_tiles;
+  std::vector<TileMeta> meta(nt);
+  std::vector<int64_t> k0s(nt, 0), kws(nt, 0);
+  int64_t off = 0;
+  for (int t = 0; t < nt; ++t) {
+    int64_t b0 = 0, b1 = -1;
+    bool first = true;
+    for (int q = 0; q < TILE_ROWS; ++q) {
+      const int64_t n = (int64_t)t * TILE_ROWS + q;
+      if (n >= N || len[n] == 0) continue;
+      int64_t a0 = lo[n], a1 = lo[n] + len[n] - 1;
+      if (first) {
+        b0 = a0;
+        b1 = a1;
+        first = false;
+        continue;
+      }
+      // unwrap next to the box so far (the rows of a tile are neighbouring tones)
+      const int64_t mid = (b0 + b1) / 2;
+      while (a0 - mid > L / 2) { a0 -= L; a1 -= L; }
+      while (mid - a0 > L / 2) { a0 += L; a1 += L; }
+      b0 = std::min(b0, a0);
+      b1 = std::max(b1, a1);
+    }
+    if (first) continue;  // nothing kept in the tile
+    int64_t kw = b1 - b0 + 1;
+    if (kw >= L) {
+      b0 = 0;
+      kw = L;
+    }
+    b0 = ((b0 % L) + L) % L;
+    k0s[t] = b0;
+    kws[t] = kw;
+    cx->pad = std::max<int>(cx->pad, (int)std::max<int64_t>(0, b0 + kw - L));
+    meta[t] = TileMeta{(int)b0, (int)kw, off};
+    off += kw * TILE_ROWS;
+  }
+  cx->stored = off;
+  std::vector<double2> v64((size_t)std::max<int64_t>(off, 1), double2{0.0, 0.0});
+  for (int t = 0; t < nt; ++t)
+    for (int64_t kk = 0; kk < kws[t]; ++kk)
+      for (int q = 0; q < TILE_ROWS; ++q) {
+        const int64_t n = (int64_t)t * TILE_ROWS + q;
+        if (n >= N) continue;
+        const int k = (int)((k0s[t] + kk) % L);
+        if (kept(n, k)) v64[(size_t)(meta[t].off + kk * TILE_ROWS + q)] = S[(size_t)n * L + k];
+      }
+  S.clear();
+  S.shrink_to_fit();
+  upload(cx->meta, meta, s);
+  if (plan->prepared & (1u << SPT_F64)) upload(cx->val64, v64, s);
+  if (plan->prepared & (1u << SPT_F32)) {
+    std::vector<float2> v32(v64.size());
+    for (size_t i = 0; i < v64.size(); ++i) v32[i] = float2{(float)v64[i].x, (float)v64[i].y};
+    upload(cx->val32, v32, s);
+  }
+  // the transposed product's lists: the tiles whose boxes meet each 32 columns
+  // of 0 .. L + pad - 1
+  const int ldu = L + cx->pad;
+  cx->n_chunks = (ldu + 31) / 32;
+  std::vector<int32_t> tptr(cx->n_chunks + 1, 0), tents;
+  for (int c = 0; c < cx->n_chunks; ++c) {
+    for (int t = 0; t < nt; ++t)
+      if (kws[t] > 0 && k0s[t] < 32 * (c + 1) && k0s[t] + kws[t] > 32 * c) tents.push_back(t);
+    tptr[c + 1] = (int32_t)tents.size();
+  }
+  if (tents.empty()) tents.push_back(0);
+  upload(cx->tptr, tptr, s);
+  upload(cx->tents, tents, s);
+  plan->cx = std::move(cx);
+}
+
+template <typename T>
+void execute_complex(spt_plan_t plan, const void* X, void* Y, int64_t R, hipStream_t s) {
+  using C = cplx_t<T>;
+  const CplxState& cx = *plan->cx;
+  ensure_work(plan, R, s);
+  const int ldz = cx.L + cx.pad;
+  CplxExecArgs<T> ea{static_cast<const C*>(X), plan->work->as<C>(), cx.winv.as<double>(),
+                     cx.tw.as<double2>(), plan->N, cx.L, ldz, cx.m_off, cx.c_lo, cx.c_hi,
+                     1.0 / std::sqrt((double)cx.L)};
+  staged(SPT_STAGE_FFT, s, [&] { launch_cplx_exec_fft<T>(ea, cx.fp, (int)R, s); });
+  CplxSpmmArgs<T> pa{cx.meta.as<TileMeta>(),
+                     std::is_same<T, double>::value ? (const C*)cx.val64.p : (const C*)cx.val32.p,
+                     plan->work->as<C>(), static_cast<C*>(Y), plan->N, (int)R, ldz};
+  staged(SPT_STAGE_SPMM, s, [&] { launch_cplx_spmm<T>(pa, plan->n_tiles, s); });
+}
+
+template <typename T>
+void execute_complex_transposed(spt_plan_t plan, const void* F, void* Y, int64_t R,
+                                hipStream_t s) {
+  using C = cplx_t<T>;
+  const CplxState& cx = *plan->cx;
+  ensure_work(plan, R, s, true);
+  const int ldu = cx.L + cx.pad;
+  CplxSpmmTArgs<T> ta{cx.meta.as<TileMeta>(),
+                      std::is_same<T, double>::value ? (const C*)cx.val64.p : (const C*)cx.val32.p,
+                      cx.tptr.as<int32_t>(), cx.tents.as<int32_t>(), static_cast<const C*>(F),
+                      plan->work->as<C>(), plan->N, (int)R, ldu};
+  staged(SPT_STAGE_SPMM_T, s, [&] { launch_cplx_spmm_t<T>(ta, cx.n_chunks, s); });
+  CplxInvArgs<T> ia{plan->work->as<C>(), static_cast<C*>(Y), cx.winv.as<double>(),
+                    cx.tw.as<double2>(), plan->N, cx.L, ldu, cx.m_off, cx.c_lo, cx.c_hi,
+                    1.0 / std::sqrt((double)cx.L)};
+  staged(SPT_STAGE_INV_FFT, s, [&] { launch_cplx_inv_fft<T>(ia, cx.fp, (int)R, s); });
 }
 
 // ---------------------------------------------------------------- stage timing
@@ -2064,7 +2313,7 @@ spt_status spt_plan_create(spt_plan_t* out, int32_t family, const spt_params* p,
   return guard([&] {
     if (!out) throw Error(SPT_E_INVALID_ARG, "out is NULL");
     *out = nullptr;
-    if (family < SPT_CHEBYSHEV_T || family > SPT_COS_POWER)
+    if (family < SPT_CHEBYSHEV_T || family > SPT_LAGUERRE_SPECTRAL)
       throw Error(SPT_E_INVALID_ARG, "unknown family " + std::to_string(family));
     if (N < 2 || N > (int64_t)1 << 24) throw Error(SPT_E_INVALID_ARG, "N out of range");
     spt_params prm{};
@@ -2087,6 +2336,14 @@ spt_status spt_plan_create(spt_plan_t* out, int32_t family, const spt_params* p,
     if (prm.executor < SPT_EXECUTOR_AUTO || prm.executor > SPT_EXECUTOR_PERSISTENT)
       throw Error(SPT_E_INVALID_ARG, "unknown executor");
     if (prm.min_block < 0 || prm.panel_rows < 0) throw Error(SPT_E_INVALID_ARG, "negative size");
+    if (family == SPT_LAGUERRE_SPECTRAL && !(prm.eta > 0.0 && prm.period > 0.0))
+      throw Error(SPT_E_INVALID_ARG, "the Laguerre spectral matrix needs eta > 0 and period > 0");
+    if (is_complex_family(family) && prm.mode == SPT_MODE_DIRECT)
+      throw Error(SPT_E_UNSUPPORTED, "complex plans run the compressed method only");
+    if (is_complex_family(family) && (prm.precisions & (1u << SPT_SPLIT_BF16)))
+      throw Error(SPT_E_UNSUPPORTED, "complex plans execute in F64 or F32");
+    if (family == SPT_CEXP && prm.nodes)
+      throw Error(SPT_E_INVALID_ARG, "the exp(i m theta) generator takes the Chebyshev-Gauss angles");
     if (prm.reduced_fft < 0 || prm.reduced_fft > 2)
       throw Error(SPT_E_INVALID_ARG, "reduced_fft must be 0 (automatic), 1 or 2");
     auto plan = std::make_unique<spt_plan>();
@@ -2108,7 +2365,7 @@ spt_status spt_plan_create(spt_plan_t* out, int32_t family, const spt_params* p,
     if (prm.mode == SPT_MODE_DIRECT) {
       plan->geom.clear();
       plan->tail = N;
-    } else if (is_trig(family)) {
+    } else if (is_trig(family) || is_complex_family(family)) {
       partition_two_sided(N, plan->zeta, eps2, round_fft, plan->geom, plan->tail);
     } else {
       partition_one_sided(N, plan->zeta, eps2, min_block, round_fft, plan->geom, plan->tail);
@@ -2129,10 +2386,11 @@ spt_status spt_plan_blocks(spt_plan_t plan, int32_t* L, int32_t* m_offset, int32
                            int32_t* c_hi, int32_t cap, int32_t* n_blocks) {
   return guard([&] {
     check_plan(plan);
-    const int n = plan->precomputed ? (int)plan->blk.size() : (int)plan->geom.size();
+    const bool built = plan->precomputed && !plan->cx;  // complex plans keep geom
+    const int n = built ? (int)plan->blk.size() : (int)plan->geom.size();
     if (n_blocks) *n_blocks = n;
     for (int i = 0; i < n && i < cap; ++i) {
-      const BlockGeom& g = plan->precomputed ? plan->blk[i]->g : plan->geom[i];
+      const BlockGeom& g = built ? plan->blk[i]->g : plan->geom[i];
       if (L) L[i] = g.L;
       if (m_offset) m_offset[i] = g.m_off;
       if (c_lo) c_lo[i] = g.c_lo;
@@ -2149,6 +2407,7 @@ spt_status spt_precompute(spt_plan_t plan, void* stream) {
     } catch (...) {
       plan->precomputed = false;
       plan->blk.clear();
+      plan->cx.reset();
       throw;
     }
   });
@@ -2160,6 +2419,13 @@ spt_status spt_execute(spt_plan_t plan, const void* X, void* Y, int64_t nrhs, in
     check_exec(plan, X, Y, nrhs, prec);
     set_device(plan);
     hipStream_t s = static_cast<hipStream_t>(stream);
+    if (plan->cx) {
+      if (prec == SPT_F64)
+        execute_complex<double>(plan, X, Y, nrhs, s);
+      else
+        execute_complex<float>(plan, X, Y, nrhs, s);
+      return;
+    }
     if (uses_staged(plan)) {
       if (prec == SPT_F64)
         execute_staged_t<double>(plan, (const double*)X, (double*)Y, nrhs, prec, s);
@@ -2182,8 +2448,9 @@ spt_status spt_execute_noalloc(spt_plan_t plan, const void* X, void* Y, int64_t 
                                int32_t prec, void* stream) {
   return guard([&] {
     check_exec(plan, X, Y, nrhs, prec);
-    if (!uses_staged(plan))
-      throw Error(SPT_E_UNSUPPORTED, "spt_execute_noalloc runs the staged executor only");
+    if (!uses_staged(plan) || plan->cx)
+      throw Error(SPT_E_UNSUPPORTED,
+                  "spt_execute_noalloc runs the staged executor of real plans only");
     if (!plan->blk.empty() && plan->fft_maxP > FUSED_MAX_P)
       throw Error(SPT_E_UNSUPPORTED, "a block's FFT exceeds one workgroup (it needs work lists)");
     const size_t need = work_bytes(plan, nrhs, false);
@@ -2217,6 +2484,13 @@ spt_status spt_execute_transposed(spt_plan_t plan, const void* X, void* Y, int64
       throw Error(SPT_E_UNSUPPORTED, "the transposed product runs in F64 or F32");
     set_device(plan);
     hipStream_t s = static_cast<hipStream_t>(stream);
+    if (plan->cx) {
+      if (prec == SPT_F64)
+        execute_complex_transposed<double>(plan, X, Y, nrhs, s);
+      else
+        execute_complex_transposed<float>(plan, X, Y, nrhs, s);
+      return;
+    }
     if (prec == SPT_F64)
       execute_transposed_t<double>(plan, (const double*)X, (double*)Y, nrhs, s);
     else
@@ -2237,6 +2511,7 @@ spt_status spt_execute_batched(const spt_plan_t* plans, const void* const* X, vo
       for (int j = 0; j < i; ++j)
         if (plans[j] == plans[i])
           throw Error(SPT_E_INVALID_ARG, "a plan appears twice in one batch");
+      if (plans[i]->cx) throw Error(SPT_E_UNSUPPORTED, "complex plans do not run in batches");
     }
     set_device(plans[0]);
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -2318,7 +2593,9 @@ spt_status spt_plan_query(spt_plan_t plan, spt_plan_info* info) {
     info->zeta = plan->zeta;
     info->tail = (int32_t)plan->tail;
     info->precomputed = plan->precomputed;
-    info->n_blocks = plan->precomputed ? (int)plan->blk.size() : (int)plan->geom.size();
+    info->is_complex = is_complex_family(plan->family) ? 1 : 0;
+    info->n_blocks = plan->precomputed && !plan->cx ? (int)plan->blk.size()
+                                                    : (int)plan->geom.size();
     if (plan->precomputed) {
       int64_t ldt = (int64_t)plan->n_tiles * TILE_ROWS;
       int64_t tiles_bytes = 0;
@@ -2340,6 +2617,18 @@ spt_status spt_plan_query(spt_plan_t plan, spt_plan_info* info) {
         info->window_chunked = plan->win_chunked ? 1 : 0;
       }
       info->transposed_segment = plan->tseglen;
+      if (plan->cx) {
+        const CplxState& cx = *plan->cx;
+        info->nnz = cx.nnz;
+        info->stored = cx.stored;
+        info->max_band = cx.max_band;
+        info->max_abs[0] = cx.maxabs;
+        info->nnz_blk[0] = cx.nnz;
+        info->kappa = cx.kappa;
+        const int64_t tb = (int64_t)plan->n_tiles * 16;
+        info->matrix_bytes_f64 = cx.stored * 16 + tb;
+        info->matrix_bytes_f32 = cx.stored * 8 + tb;
+      }
       info->reduced_fft_f64 = plan->reduced_fft64 ? 1 : 0;
       info->reduced_fft_f32_err = plan->reduced_fft32_err;
     }
@@ -2351,6 +2640,10 @@ spt_status spt_plan_nodes(spt_plan_t plan, double* out) {
     check_plan(plan);
     if (!out) throw Error(SPT_E_INVALID_ARG, "out is NULL");
     if (!plan->precomputed) throw Error(SPT_E_NOT_PRECOMPUTED, "plan is not precomputed");
+    if (plan->cx) {
+      std::copy(plan->cx->angles.begin(), plan->cx->angles.end(), out);
+      return;
+    }
     set_device(plan);
     SPT_HIP(hipMemcpy(out, plan->nodes.p, plan->N * sizeof(double), hipMemcpyDeviceToHost));
   });
@@ -2361,6 +2654,7 @@ spt_status spt_plan_compressed_rows(spt_plan_t plan, int32_t blk, int64_t row0, 
   return guard([&] {
     check_plan(plan);
     if (!plan->precomputed) throw Error(SPT_E_NOT_PRECOMPUTED, "plan is not precomputed");
+    if (plan->cx) throw Error(SPT_E_UNSUPPORTED, "complex plans: rows are not exported");
     if (blk < 0 || blk >= (int)plan->blk.size()) throw Error(SPT_E_INVALID_ARG, "bad block");
     if (!out || row0 < 0 || nrows < 0 || row0 + nrows > plan->N)
       throw Error(SPT_E_INVALID_ARG, "bad row range");

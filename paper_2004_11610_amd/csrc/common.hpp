@@ -371,8 +371,10 @@ struct SpmmTArgs {
   int R;
   int64_t N;
 };
+// products64: a tile's rows summed in float64 as well (float32 plans with
+// float64 spectra-side arithmetic)
 template <typename T>
-void launch_spmm_transposed(const SpmmTArgs<T>& a, hipStream_t s);
+void launch_spmm_transposed(const SpmmTArgs<T>& a, bool products64, hipStream_t s);
 
 // tail of the transposed product: fhat[:, m] += sum_j A[j, m] f_j, m < tail
 template <typename T>
@@ -385,6 +387,75 @@ void launch_tail_transposed(const T* tailmat, int tail, const T* F, T* Y, int R,
 __host__ __device__ inline bool is_trig(int family) {
   return family == SPT_CHEBYSHEV_T || family == SPT_SINE || family == SPT_COS_POWER;
 }
+// the complex generators (Algorithm 1, complex data, full spectrum; cplx.hip)
+__host__ __device__ inline bool is_complex_family(int family) {
+  return family == SPT_CEXP || family == SPT_LAGUERRE_SPECTRAL;
+}
+
+// ---------------------------------------------------------------- complex generators (cplx.hip)
+// rows row0 .. of A_e W (degrees m = c + m_off, c < L), complex float64, row
+// stride L: exp(i m theta_j) at the exact angle (SPT_CEXP), or exp(i m phi_j)
+// rowf_j (SPT_LAGUERRE_SPECTRAL, rowf_j = 1 / (eta/2 - i k_j))
+struct CplxRowsArgs {
+  double2* out;
+  const double* w;      // window, L entries
+  const double* phi;    // row phases (SPT_LAGUERRE_SPECTRAL)
+  const double2* rowf;  // row factors (SPT_LAGUERRE_SPECTRAL)
+  int64_t N, row0;
+  int L, m_off, family;
+};
+void launch_cplx_rows(const CplxRowsArgs& a, int nrows, hipStream_t s);
+// F (unitary, SIGN -1) of nrows rows of L points in place (L <= 10240)
+void launch_cplx_row_fft(double2* rows, int nrows, int L, const FftPlan& fp, const double2* tw,
+                         hipStream_t s);
+template <typename TI>
+struct CplxExecArgs {
+  const cplx_t<TI>* X;  // R x N complex
+  cplx_t<TI>* Z;        // R x ldz spectra (ldz = L + pad)
+  const double* winv;   // 1 / w_c, c < L
+  const double2* tw;    // two-level table of exp(2 pi i q / L)
+  int64_t N;
+  int L, ldz, m_off, c_lo, c_hi;
+  double scale;         // 1 / sqrt(L)
+};
+template <typename TI>
+void launch_cplx_exec_fft(const CplxExecArgs<TI>& a, const FftPlan& fp, int R, hipStream_t s);
+template <typename T>
+struct CplxSpmmArgs {
+  const TileMeta* meta;  // per tile: box columns k0 .. k0 + kw - 1 (k0 < L), values at off
+  const cplx_t<T>* val;  // val[off + kk * 16 + q]
+  const cplx_t<T>* Z;
+  cplx_t<T>* Y;
+  int64_t N;
+  int R, ldz;
+};
+template <typename T>
+void launch_cplx_spmm(const CplxSpmmArgs<T>& a, int n_tiles, hipStream_t s);
+template <typename T>
+struct CplxSpmmTArgs {
+  const TileMeta* meta;
+  const cplx_t<T>* val;
+  const int32_t* tptr;   // tiles of the 32-column chunk c: tents[tptr[c] .. tptr[c + 1])
+  const int32_t* tents;
+  const cplx_t<T>* F;    // R x N
+  cplx_t<T>* U;          // R x ldu (ldu = L + pad)
+  int64_t N;
+  int R, ldu;
+};
+template <typename T>
+void launch_cplx_spmm_t(const CplxSpmmTArgs<T>& a, int n_chunks, hipStream_t s);
+template <typename TI>
+struct CplxInvArgs {
+  const cplx_t<TI>* U;
+  cplx_t<TI>* Y;
+  const double* winv;
+  const double2* tw;
+  int64_t N;
+  int L, ldu, m_off, c_lo, c_hi;
+  double scale;
+};
+template <typename TI>
+void launch_cplx_inv_fft(const CplxInvArgs<TI>& a, const FftPlan& fp, int R, hipStream_t s);
 
 struct FamilyArgs {
   int family;

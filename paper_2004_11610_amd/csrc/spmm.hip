@@ -900,13 +900,17 @@ __global__ __launch_bounds__(256) void spmm_presplit_items_kernel(SpmmSplitBatch
 // workgroups) each stores into a slot of partial sums, and
 // spmm_t_reduce_kernel adds a chunk's slots in order (deterministic, no
 // atomics).  Thread: columns 2 cg, 2 cg + 1 and right-hand sides 4 rq ..
-// 4 rq + 3 of the chunk.  A tile's 16 rows are summed in the working
-// precision, the tiles' sums in float64 for either precision (rounded to the
-// working precision once, where they are stored).
-template <typename T>
+// 4 rq + 3 of the chunk.  The tiles' sums are added in float64 for either
+// precision (rounded to the working precision once, where they are stored);
+// a tile's 16 rows are summed in the working precision, or in float64 (PD:
+// float32 plans whose spectra-side arithmetic runs in float64,
+// spt_params.reduced_fft).
+template <typename T, bool PD>
 __global__ __launch_bounds__(256) void spmm_transposed_kernel(SpmmTArgs<T> a) {
   using C = cplx_t<T>;
   using D = double2;
+  using PT = typename std::conditional<PD, double, T>::type;  // a tile's sums
+  using PC = cplx_t<PT>;
   static_assert(TCHUNK == 32, "thread layout: 16 column pairs x 16 groups of 4 right-hand sides");
   constexpr int FPT = 64 * TILE_ROWS / 256;      // f values per thread and tile
   constexpr int APT = TILE_ROWS * TCHUNK / 256;  // box values per thread and tile
@@ -982,19 +986,19 @@ __global__ __launch_bounds__(256) void spmm_transposed_kernel(SpmmTArgs<T> a) {
       for (int t = 0; t < TPR; ++t) {
         if (t >= cnt) break;
         // the tile's 16 rows summed first, then added (running sums stay short)
-        C part[4][2];
+        PC part[4][2];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) part[j][0] = part[j][1] = C{T(0), T(0)};
+        for (int j = 0; j < 4; ++j) part[j][0] = part[j][1] = PC{PT(0), PT(0)};
 #pragma unroll
         for (int q = 0; q < TILE_ROWS; ++q) {
           const C a0 = as[t][q][2 * cg], a1 = as[t][q][2 * cg + 1];
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
-            const T fv = fs[t][4 * rq + j][q];
-            part[j][0].x += a0.x * fv;
-            part[j][0].y += a0.y * fv;
-            part[j][1].x += a1.x * fv;
-            part[j][1].y += a1.y * fv;
+            const PT fv = fs[t][4 * rq + j][q];
+            part[j][0].x += PT(a0.x) * fv;
+            part[j][0].y += PT(a0.y) * fv;
+            part[j][1].x += PT(a1.x) * fv;
+            part[j][1].y += PT(a1.y) * fv;
           }
         }
 #pragma unroll
@@ -1185,11 +1189,15 @@ void launch_spmm_split_bf16(const SpmmArgs<float>& a, hipStream_t s) {
 }
 
 template <typename T>
-void launch_spmm_transposed(const SpmmTArgs<T>& a, hipStream_t s) {
+void launch_spmm_transposed(const SpmmTArgs<T>& a, bool products64, hipStream_t s) {
   if (a.R > 65535 * 8) throw Error(SPT_E_INVALID_ARG, "too many right-hand sides");
   if (a.n_segs <= 0) return;
-  hipLaunchKernelGGL(spmm_transposed_kernel<T>, dim3(a.n_segs, (a.R + 63) / 64), dim3(256), 0, s,
-                     a);
+  if (products64 && !std::is_same<T, double>::value)
+    hipLaunchKernelGGL((spmm_transposed_kernel<T, true>), dim3(a.n_segs, (a.R + 63) / 64),
+                       dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL((spmm_transposed_kernel<T, false>), dim3(a.n_segs, (a.R + 63) / 64),
+                       dim3(256), 0, s, a);
   SPT_HIP(hipGetLastError());
   if (a.n_red <= 0) return;
   hipLaunchKernelGGL(spmm_t_reduce_kernel<T>, dim3(a.n_red, (a.R + 7) / 8), dim3(256), 0, s, a);
@@ -1208,8 +1216,8 @@ void launch_tail_transposed(const T* tailmat, int tail, const T* F, T* Y, int R,
 
 template void launch_spmm<double>(const SpmmArgs<double>&, hipStream_t);
 template void launch_spmm<float>(const SpmmArgs<float>&, hipStream_t);
-template void launch_spmm_transposed<double>(const SpmmTArgs<double>&, hipStream_t);
-template void launch_spmm_transposed<float>(const SpmmTArgs<float>&, hipStream_t);
+template void launch_spmm_transposed<double>(const SpmmTArgs<double>&, bool, hipStream_t);
+template void launch_spmm_transposed<float>(const SpmmTArgs<float>&, bool, hipStream_t);
 template void launch_tail_transposed<double>(const double*, int, const double*, double*, int,
                                              int64_t, hipStream_t);
 template void launch_tail_transposed<float>(const float*, int, const float*, float*, int,

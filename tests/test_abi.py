@@ -37,7 +37,8 @@ def test_library_exports_every_declared_symbol():
 FAM_IDS = {"chebyshev_t": matrix.CHEBYSHEV_T, "legendre": matrix.LEGENDRE,
            "jacobi": matrix.JACOBI, "laguerre_fn": matrix.LAGUERRE_FN,
            "hermite_fn": matrix.HERMITE_FN, "sine": matrix.SINE,
-           "cos_power": matrix.COS_POWER}
+           "cos_power": matrix.COS_POWER, "cexp": matrix.CEXP,
+           "laguerre_spectral": matrix.LAGUERRE_SPECTRAL}
 
 PLAN_CASES = [("legendre", 256, 1e-12, {}), ("legendre", 4096, 1e-12, {}),
               ("legendre", 16384, 1e-7, {}), ("chebyshev_t", 4096, 1e-12, {}),
@@ -46,7 +47,9 @@ PLAN_CASES = [("legendre", 256, 1e-12, {}), ("legendre", 4096, 1e-12, {}),
               ("legendre", 16384, 1e-10, dict(eps2=1e-4, min_block=20)),
               ("legendre", 777, 1e-9, dict(exact_fft_len=True, eps2=1e-3)),
               ("legendre", 40, 1e-7, {}), ("legendre", 33, 1e-7, {}),
-              ("sine", 2000, 1e-8, {}), ("cos_power", 1500, 1e-7, dict(power=3))]
+              ("sine", 2000, 1e-8, {}), ("cos_power", 1500, 1e-7, dict(power=3)),
+              ("cexp", 3000, 1e-12, {}), ("laguerre_spectral", 501, 1e-10,
+                                          dict(eta=2500.0, period=4.0))]
 
 
 @pytest.mark.parametrize("fam,N,eps,kw", PLAN_CASES)
@@ -77,7 +80,10 @@ def test_direct_mode_plan():
 
 
 @pytest.mark.parametrize("args", [
-    dict(family=0, N=64, eps=1e-7), dict(family=8, N=64, eps=1e-7),
+    dict(family=0, N=64, eps=1e-7), dict(family=10, N=64, eps=1e-7),
+    dict(family="laguerre_spectral", N=64, eps=1e-7),
+    dict(family="laguerre_spectral", N=64, eps=1e-7, eta=10.0),
+    dict(family="cexp", N=64, eps=1e-7, nodes=np.linspace(0.1, 0.9, 64)),
     dict(family="cos_power", N=64, eps=1e-7), dict(family="cos_power", N=64, eps=1e-7, power=6),
     dict(family="legendre", N=64, eps=1e-7, trig_conv_q=12),
     dict(family="chebyshev_t", N=64, eps=1e-7, trig_conv_q=65),
@@ -183,3 +189,13 @@ def test_set_allocator_arguments():
     lib = _lib.load()
     assert lib.spt_set_allocator(_lib.ALLOC_FN(lambda n, s, c: 0), _lib.FREE_FN(), None) == -1
     assert lib.spt_set_allocator(_lib.ALLOC_FN(), _lib.FREE_FN(), None) == 0
+
+
+@pytest.mark.parametrize("args,code", [
+    (dict(family="cexp", N=64, eps=1e-7, mode=3), -5),
+    (dict(family="cexp", N=64, eps=1e-7, precisions=1 << 2), -5),
+])
+def test_complex_plan_refusals(args, code):
+    with pytest.raises(spt.SptError) as e:
+        spt.Plan(**args)
+    assert e.value.code == code
