@@ -225,6 +225,8 @@ def main():
                     choices=["legendre-n16384-r64", "batch48", "laguerre-fn-n65536-r1024"],
                     help="the headline workload (default), or one of the two large ones "
                          "(timed the same way, reported for the design notes)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default launch choices instead of spt_autotune's")
     ap.add_argument("--reduced-fft", type=int, default=0, choices=[0, 1, 2],
                     help="arithmetic of the float32 paths' FFTs: 0 chosen by the plan "
                          "(spt_params.reduced_fft), 1 float32, 2 float64")
@@ -264,6 +266,15 @@ def main():
     info = plan.info()
     log("precompute %.2f s, blocks %s, tail %d, nnz %d" % (t_pre, plan.blocks(), info["tail"],
                                                           info["nnz"]))
+    # launch choices by the library's autotuner (timed on the split-bf16 path;
+    # the float64 and float32 paths run with the same choices)
+    tuning = {"autotuned": False}
+    if not args.no_autotune:
+        t0 = time.perf_counter()
+        chosen, us = plan.autotune(R, prec=spt.SPLIT_BF16)
+        tuning = dict(chosen, autotuned=True, us_per_execute=us,
+                      seconds=time.perf_counter() - t0)
+        log("autotune", tuning)
     Xh = workloads.rhs(w["rhs"], R, N, w["seed"])
     X64 = torch.as_tensor(Xh, device="cuda")
     X32 = X64.float()
@@ -395,7 +406,7 @@ def main():
                    "eps1": w["eps"], "eps2": info["eps2"], "blocks": [b[0] for b in plan.blocks()],
                    "tail": info["tail"], "nnz": info["nnz"], "parallelism": "single-gpu",
                    "reduced_fft_f64": info["reduced_fft_f64"],
-                   "reduced_fft_f32_err": info["reduced_fft_f32_err"]},
+                   "reduced_fft_f32_err": info["reduced_fft_f32_err"], "tuning": tuning},
         "streams": args.streams,
         "paths": {k: {"value": v["value"], "ms_per_step": v["ms_per_step"],
                       "one_stream": v["one_stream"], "kernel_ms": v["kernel_ms"]}

@@ -189,6 +189,30 @@ typedef struct {
 
 typedef struct spt_plan* spt_plan_t;
 
+/* Launch choices of a plan's staged execute (none changes what is computed;
+ * the banded-product and FFT-batching choices give the same bits, the parity
+ * split of a transform rounds differently).  Zero-filled: the defaults. */
+enum {
+  SPT_PRODUCT_DEFAULT = 0,  /* split-bf16 product: windowed, chunked where the
+                               windows do not fit LDS                            */
+  SPT_PRODUCT_TILE = 1,     /* per row tile, spectra read from memory             */
+  SPT_PRODUCT_WINDOW = 2,   /* the default's choice, asked for explicitly         */
+  SPT_PRODUCT_CHUNKED = 3,  /* windows through LDS in chunks of 32 columns        */
+  SPT_TUNE_DEFAULT = 0, SPT_TUNE_OFF = 1, SPT_TUNE_ON = 2
+};
+typedef struct {
+  int32_t product;     /* SPT_PRODUCT_*                                          */
+  int32_t window_rhs;  /* right-hand sides per windowed-product workgroup: 0 (64
+                          when two such workgroups fit a CU's LDS, else 32), 32, 64 */
+  int32_t fft_batch;   /* most right-hand sides per workgroup of a short block's
+                          fused FFT: 0 (4), 1, 2 or 4                            */
+  int32_t fft_half;    /* SPT_TUNE_*: split even transforms of at least 4096 points
+                          by output parity into two workgroups (default on; off
+                          only where the whole transform fits one workgroup)    */
+  int32_t inv_four;    /* SPT_TUNE_*: transposed product, four-step inverse
+                          transforms also for blocks that fit one workgroup (ON) */
+} spt_tuning;
+
 /* Plan summary (spt_plan_query). */
 typedef struct {
   int32_t family, mode, n_blocks, tail;  /* tail = columns multiplied directly  */
@@ -324,6 +348,28 @@ spt_status spt_set_allocator(spt_alloc_fn alloc, spt_free_fn free_, void* ctx);
  * that path; waits end without it, since items only wait for items taken
  * before them.  Synchronises the device when contexts exist. */
 spt_status spt_plan_set_exec_wait(spt_plan_t plan, int64_t ticks);
+
+/* Set / read a plan's launch choices (host struct).  Set after spt_precompute,
+ * the device-side descriptions are rebuilt (a device synchronisation first);
+ * before, spt_precompute applies them.  SPT_E_INVALID_ARG for unknown values. */
+spt_status spt_plan_set_tuning(spt_plan_t plan, const spt_tuning* t);
+spt_status spt_plan_get_tuning(spt_plan_t plan, spt_tuning* t);
+
+/* Autotuner: time spt_execute of nrhs right-hand sides (x ~ N(0,1), a fixed
+ * seed) in precision prec on `stream` with HIP events for every launch choice
+ * that applies to the plan (split-bf16: the three products and both window
+ * widths; every precision: FFT batching 1, 2, 4 and, where a block qualifies,
+ * the parity split on and off), median of 10 executes each after 2 warm-up
+ * executes, and keep the fastest (spt_plan_set_tuning).  cache_path (may be
+ * NULL): a JSON file of earlier results keyed by family, Jacobi parameters,
+ * ceil(log2 N), ceil(log2 nrhs) and precision; a key found there is applied
+ * without timing, a new result is added to the file.  *chosen (may be NULL)
+ * gets the choice, *us (may be NULL) its time per execute in microseconds (0
+ * when taken from the cache).  Complex plans have nothing to tune (their
+ * current choice is returned).  Allocates the right-hand sides and outputs
+ * through the library's allocator; synchronises the device. */
+spt_status spt_autotune(spt_plan_t plan, int64_t nrhs, int32_t prec, void* stream,
+                        const char* cache_path, spt_tuning* chosen, double* us);
 
 /* Plan summary; info is a host struct filled by the call. */
 spt_status spt_plan_query(spt_plan_t plan, spt_plan_info* info);

@@ -17,6 +17,9 @@ CEXP, LAGUERRE_SPECTRAL = 8, 9  # complex generators
 F64, F32, SPLIT_BF16 = 0, 1, 2
 MODE_AUTO, MODE_ROW, MODE_DIRECT = 0, 1, 3
 FFT_AUTO, FFT_F32, FFT_F64 = 0, 1, 2
+PRODUCT_DEFAULT, PRODUCT_TILE, PRODUCT_WINDOW, PRODUCT_CHUNKED = 0, 1, 2, 3
+TUNE_DEFAULT, TUNE_OFF, TUNE_ON = 0, 1, 2
+TUNING_FIELDS = ("product", "window_rhs", "fft_batch", "fft_half", "inv_four")
 EXECUTOR_AUTO, EXECUTOR_STAGED, EXECUTOR_PERSISTENT = 0, 1, 2
 FAMILIES = {"chebyshev_t": CHEBYSHEV_T, "legendre": LEGENDRE, "jacobi": JACOBI,
             "laguerre_fn": LAGUERRE_FN, "hermite_fn": HERMITE_FN, "sine": SINE,
@@ -119,6 +122,33 @@ class Plan:
             self._h, int(blk), int(row0), int(nrows),
             out.ctypes.data_as(ctypes.POINTER(c_double))))
         return out
+
+    def set_tuning(self, **choices):
+        """Launch choices (spt_tuning fields; the others keep their values)."""
+        t = _lib.SptTuning()
+        _lib.check(self._lib.spt_plan_get_tuning(self._h, byref(t)))
+        for k, v in choices.items():
+            if k not in TUNING_FIELDS:
+                raise ValueError("unknown tuning field %r" % k)
+            setattr(t, k, int(v))
+        _lib.check(self._lib.spt_plan_set_tuning(self._h, byref(t)))
+        return self
+
+    def tuning(self):
+        t = _lib.SptTuning()
+        _lib.check(self._lib.spt_plan_get_tuning(self._h, byref(t)))
+        return {k: getattr(t, k) for k in TUNING_FIELDS}
+
+    def autotune(self, nrhs, prec=F64, cache_path=None, stream=None):
+        """spt_autotune: time the launch choices, keep the fastest; returns
+        (choices, microseconds per execute, 0 when read from the cache)."""
+        prec = PRECISIONS.get(prec, prec)
+        t = _lib.SptTuning()
+        us = c_double()
+        path = None if cache_path is None else str(cache_path).encode()
+        _lib.check(self._lib.spt_autotune(self._h, c_int64(nrhs), c_int32(prec),
+                                          _stream_ptr(stream), path, byref(t), byref(us)))
+        return {k: getattr(t, k) for k in TUNING_FIELDS}, us.value
 
     def set_exec_wait(self, ticks):
         """Bound of the persistent executor's dependency waits (100 MHz ticks, 0 = 1 s)."""

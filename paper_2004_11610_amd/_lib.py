@@ -38,6 +38,11 @@ ALLOC_FN = ctypes.CFUNCTYPE(c_void_p, ctypes.c_size_t, c_void_p, c_void_p)
 FREE_FN = ctypes.CFUNCTYPE(None, c_void_p, c_void_p, c_void_p)
 
 
+class SptTuning(ctypes.Structure):
+    _fields_ = [("product", c_int32), ("window_rhs", c_int32), ("fft_batch", c_int32),
+                ("fft_half", c_int32), ("inv_four", c_int32)]
+
+
 class SptError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__("%s (%d): %s" % (ERRORS.get(code, "?"), code, msg))
@@ -69,6 +74,10 @@ def load():
         "spt_plan_query": [c_void_p, POINTER(SptPlanInfo)],
         "spt_plan_set_exec_wait": [c_void_p, c_int64],
         "spt_set_allocator": [ALLOC_FN, FREE_FN, c_void_p],
+        "spt_plan_set_tuning": [c_void_p, POINTER(SptTuning)],
+        "spt_plan_get_tuning": [c_void_p, POINTER(SptTuning)],
+        "spt_autotune": [c_void_p, c_int64, c_int32, c_void_p, c_char_p, POINTER(SptTuning),
+                         POINTER(c_double)],
         "spt_plan_nodes": [c_void_p, POINTER(c_double)],
         "spt_plan_compressed_rows": [c_void_p, c_int32, c_int64, c_int64, POINTER(c_double)],
         "spt_plan_destroy": [c_void_p],

@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <memory>
 #include <atomic>
@@ -237,6 +238,7 @@ struct spt_plan {
   std::vector<std::unique_ptr<spt::ExecCtx>> ctx;  // executor contexts of spt_execute
   uint32_t exec_wait = spt::EXEC_WAIT_DEFAULT;      // persistent executor: wait bound, ticks
   std::unique_ptr<spt::CplxState> cx;  // complex generators (is_complex_family)
+  spt_tuning tune{};                    // launch choices (spt_plan_set_tuning)
   // the float32 and split-bf16 paths' x-side FFTs in float64 arithmetic
   // (spt_params.reduced_fft)
   bool reduced_fft64 = false;
@@ -411,14 +413,7 @@ size_t max_lds_bytes(int device) {
 // workgroup (several right-hand sides at a time when they fit); longer ones as
 // four-step transforms P = P1 * P2, P1 the divisor nearest sqrt(P) for which a
 // column item holds >= 8 columns and a row item >= 1 pair of rows.
-int split_points() {
-  static const int v = [] {
-    const char* e = std::getenv("SPT_EXEC_SPLIT_P");
-    const int x = e ? std::atoi(e) : 0;
-    return x > 0 ? std::min(x, EXEC_POINTS) : EXEC_POINTS;
-  }();
-  return v;
-}
+int split_points() { return EXEC_POINTS; }
 
 int log2_floor(int v) {
   int l = 0;
@@ -430,21 +425,18 @@ uint32_t magic_of(int d) {
   return (uint32_t)((((uint64_t)1 << 32) + (uint64_t)d - 1) / (uint64_t)d);
 }
 
-int fft_max_lb() {
-  const char* e = std::getenv("SPT_FFT_MAX_LB");
-  return e ? std::max(0, std::min(10, std::atoi(e))) : 2;
+// log2 of the most right-hand sides per workgroup of a short block's fused
+// FFT (spt_tuning.fft_batch; 4 by default)
+int fft_max_lb(spt_plan_t plan) {
+  const int b = plan->tune.fft_batch;
+  return b == 1 ? 0 : b == 2 ? 1 : 2;
 }
 
-// The windowed product (diagnostics: SPT_SPMM_WINDOW=0 keeps the per-tile one,
-// SPT_SPMM_WINDOW=chunk stages every plan's windows in chunks).
-bool window_product_enabled() {
-  const char* e = std::getenv("SPT_SPMM_WINDOW");
-  return !(e && e[0] == '0');
-}
-bool window_chunks_forced() {
-  const char* e = std::getenv("SPT_SPMM_WINDOW");
-  return e && std::strcmp(e, "chunk") == 0;
-}
+// The split-bf16 product (spt_tuning.product): windowed unless the per-tile
+// one is asked for; windows that do not fit LDS, or all windows when asked
+// for, in chunks.
+bool window_product_enabled(spt_plan_t plan) { return plan->tune.product != SPT_PRODUCT_TILE; }
+bool window_chunks_forced(spt_plan_t plan) { return plan->tune.product == SPT_PRODUCT_CHUNKED; }
 
 void exec_geometry(DevBlock& B) {
   const int P = B.P;
@@ -499,7 +491,9 @@ int64_t build_block(spt_plan_t plan, DevBlock& B, hipStream_t s, size_t lds_max,
   // float64 points of the precomputation's row transforms and of the inverse
   // transforms (P * 16 bytes), and the fused execute FFT's points of a
   // transform or of a parity half with its two twiddle tables
-  const bool half = P >= FUSED_HALF_MIN_P && P % 2 == 0;
+  const bool can_half = P >= FUSED_HALF_MIN_P && P % 2 == 0;
+  const bool whole_fits = fused_lds_bytes<double>(P, 128 + P / 128 + 1) <= lds_max;
+  const bool half = can_half && (plan->tune.fft_half != SPT_TUNE_OFF || !whole_fits);
   const bool big = P > FUSED_MAX_P || (size_t)P * sizeof(double2) > lds_max ||
                    fused_lds_bytes<double>(half ? P / 2 : P, 128 + P / 128 + 1) > lds_max;
   B.big = big;
@@ -1076,7 +1070,7 @@ std::vector<FftDesc<T>> fft_descs(spt_plan_t plan) {
     // loads and stores (diagnostics: SPT_FFT_MAX_LB)
     e.half = B.half;
     e.lb = 0;
-    while (!B.half && e.lb < fft_max_lb() && ((int64_t)B.fftw.P << (e.lb + 1)) <= plan->fft_wgP)
+    while (!B.half && e.lb < fft_max_lb(plan) && ((int64_t)B.fftw.P << (e.lb + 1)) <= plan->fft_wgP)
       ++e.lb;
     B.lbw = e.lb;
     d.push_back(e);
@@ -1095,7 +1089,7 @@ void build_windows(spt_plan_t plan, hipStream_t s) {
   plan->win_lds = 0;
   const int nblk = (int)plan->blk.size();
   plan->n_groups = (plan->n_tiles + WIN_TILES - 1) / WIN_TILES;
-  if (nblk == 0 || nblk > 64 || !window_product_enabled()) return;
+  if (nblk == 0 || nblk > 64 || !window_product_enabled(plan)) return;
   for (auto& B : plan->blk)
     if (B->h_soff.empty()) return;
   // union of the boxes of each (group, block): [lo, hi) columns
@@ -1142,17 +1136,14 @@ void build_windows(spt_plan_t plan, hipStream_t s) {
   };
   // 64 right-hand sides per workgroup (more reuse of each matrix piece) when
   // two such workgroups still fit a CU's LDS, else 32, which leaves room for
-  // the FFTs of other streams beside the product (diagnostics:
-  // SPT_SPMM_WINDOW_RG=4 or 2)
+  // the FFTs of other streams beside the product (spt_tuning.window_rhs)
   int rg = 2 * layout(4, nullptr, nullptr).second <= lds_max ? 4 : 2;
-  if (const char* e = std::getenv("SPT_SPMM_WINDOW_RG")) {
-    if (e[0] == '4') rg = 4;
-    if (e[0] == '2') rg = 2;
-  }
+  if (plan->tune.window_rhs == 64) rg = 4;
+  if (plan->tune.window_rhs == 32) rg = 2;
   std::vector<WinMeta> win((size_t)plan->n_groups * nblk);
   int64_t cols = 0;
   const auto lay = layout(rg, &win, &cols);
-  if (lay.second > lds_max || window_chunks_forced()) {
+  if (lay.second > lds_max || window_chunks_forced(plan)) {
     // the windows pass through LDS in chunks (64 right-hand sides per workgroup)
     if (spmm_chunk_lds_bytes(tpad) > lds_max) return;
     upload(plan->winmeta, win, s);
@@ -1662,13 +1653,12 @@ void execute_staged_t(spt_plan_t plan, const T* X, T* Y, int64_t R, int prec, hi
 }
 
 // Blocks of the transposed product whose inverse transform runs in four steps:
-// those longer than one workgroup's FFT, and (diagnostics: SPT_INV_FFT_FOUR=1)
-// every block with a four-step geometry.
-bool inv_four_forced() {
-  const char* e = std::getenv("SPT_INV_FFT_FOUR");
-  return e && e[0] == '1';
+// those longer than one workgroup's FFT, and (spt_tuning.inv_four) every block
+// with a four-step geometry.
+bool inv_four_forced(spt_plan_t plan) { return plan->tune.inv_four == 2; }
+bool inv_four_step(spt_plan_t plan, const DevBlock& B) {
+  return B.big || (B.four && inv_four_forced(plan));
 }
-bool inv_four_step(const DevBlock& B) { return B.big || (B.four && inv_four_forced()); }
 
 // log2 of the transforms of n points per workgroup of a four-step inverse
 // pass (at most 64, at most `count`, about 4096 points per workgroup)
@@ -1682,7 +1672,7 @@ template <typename T>
 void execute_transposed_t(spt_plan_t plan, const T* F, T* Y, int64_t R, hipStream_t s) {
   using C = cplx_t<T>;
   for (auto& B : plan->blk)
-    if (inv_four_step(*B) && !B->four)
+    if (inv_four_step(plan, *B) && !B->four)
       throw Error(SPT_E_UNSUPPORTED, "block of FFT length half " + std::to_string(B->P) +
                                          " has no four-step split");
   ensure_work(plan, R, s, true);
@@ -1706,7 +1696,7 @@ void execute_transposed_t(spt_plan_t plan, const T* F, T* Y, int64_t R, hipStrea
   staged(SPT_STAGE_SPMM_T, s, [&] { launch_spmm_transposed<T>(ta, plan->reduced_fft64, s); });
   // the blocks that fit one workgroup in one launch (per block when four
   // steps are forced, a diagnostic)
-  const bool multi = !inv_four_forced();
+  const bool multi = !inv_four_forced(plan);
   if (multi && plan->n_inv > 0)
     staged(SPT_STAGE_INV_FFT, s, [&] {
       if constexpr (std::is_same<T, float>::value) {
@@ -1740,7 +1730,7 @@ void execute_transposed_t(spt_plan_t plan, const T* F, T* Y, int64_t R, hipStrea
     ia.c_lo = B.g.c_lo;
     ia.c_hi = B.g.c_hi;
     ia.scale = (T)(1.0 / std::sqrt((double)B.g.L));
-    if (inv_four_step(B)) {
+    if (inv_four_step(plan, B)) {
       InvFft4Args<T> fa{};
       fa.U = u;
       fa.W = wbuf;
@@ -2251,6 +2241,184 @@ void set_exec_wait(spt_plan_t plan, uint32_t ticks) {
                       hipMemcpyHostToDevice));
 }
 
+// ---------------------------------------------------------------- launch choices
+void check_tuning(const spt_tuning& t) {
+  if (t.product < SPT_PRODUCT_DEFAULT || t.product > SPT_PRODUCT_CHUNKED)
+    throw Error(SPT_E_INVALID_ARG, "unknown product choice");
+  if (t.window_rhs != 0 && t.window_rhs != 32 && t.window_rhs != 64)
+    throw Error(SPT_E_INVALID_ARG, "window_rhs must be 0, 32 or 64");
+  if (t.fft_batch != 0 && t.fft_batch != 1 && t.fft_batch != 2 && t.fft_batch != 4)
+    throw Error(SPT_E_INVALID_ARG, "fft_batch must be 0, 1, 2 or 4");
+  for (int v : {t.fft_half, t.inv_four})
+    if (v < SPT_TUNE_DEFAULT || v > SPT_TUNE_ON)
+      throw Error(SPT_E_INVALID_ARG, "unknown on/off choice");
+}
+
+// the batch contexts that refer to a plan's buffers (keyed by its serial)
+void drop_batch_contexts(spt_plan_t plan) {
+  std::lock_guard<std::mutex> lk(g_batch_mu);
+  auto uses = [&](const std::unique_ptr<ExecCtx>& c) {
+    for (size_t i = 3; i < c->key.size(); i += 3)  // key: prec, n, staged, (serial, R, work)...
+      if (c->key[i] == plan->serial) return true;
+    return false;
+  };
+  g_batch_ctx.erase(std::remove_if(g_batch_ctx.begin(), g_batch_ctx.end(), uses),
+                    g_batch_ctx.end());
+}
+
+// Rebuild what the launch choices shape on a precomputed plan: each block's
+// parity split, the fused FFT descriptors (batching), the windows.
+void apply_tuning(spt_plan_t plan, hipStream_t s) {
+  if (!plan->precomputed || plan->cx) return;
+  SPT_HIP(hipDeviceSynchronize());  // launches in flight read the old descriptions
+  plan->ctx.clear();
+  drop_batch_contexts(plan);
+  const size_t lds_max = max_lds_bytes(plan->device);
+  for (auto& Bp : plan->blk) {
+    DevBlock& B = *Bp;
+    if (B.big) continue;
+    const int P = B.P;
+    const bool can_half = P >= FUSED_HALF_MIN_P && P % 2 == 0;
+    const bool whole_fits = fused_lds_bytes<double>(P, 128 + P / 128 + 1) <= lds_max;
+    B.half = can_half && (plan->tune.fft_half != SPT_TUNE_OFF || !whole_fits) ? 1 : 0;
+    B.fftw = B.half ? make_fft_plan(P / 2) : B.fft;
+  }
+  build_fft_descs(plan, s);
+  plan->serial = next_serial();  // keys of the executor contexts
+}
+
+// seconds of `reps` executes after `warm` ones, HIP events on s (median of reps)
+template <typename T>
+double time_executes(spt_plan_t plan, const T* X, T* Y, int64_t R, int prec, hipStream_t s,
+                     int warm, int reps) {
+  for (int i = 0; i < warm; ++i) execute_staged_t<T>(plan, X, Y, R, prec, s);
+  std::vector<hipEvent_t> ev(reps + 1);
+  for (auto& e : ev) SPT_HIP(hipEventCreate(&e));
+  SPT_HIP(hipEventRecord(ev[0], s));
+  for (int i = 0; i < reps; ++i) {
+    execute_staged_t<T>(plan, X, Y, R, prec, s);
+    SPT_HIP(hipEventRecord(ev[i + 1], s));
+  }
+  SPT_HIP(hipEventSynchronize(ev[reps]));
+  std::vector<float> ms(reps);
+  for (int i = 0; i < reps; ++i) SPT_HIP(hipEventElapsedTime(&ms[i], ev[i], ev[i + 1]));
+  for (auto& e : ev) (void)hipEventDestroy(e);
+  std::sort(ms.begin(), ms.end());
+  return 1e-3 * ms[reps / 2];
+}
+
+std::string tuning_key(spt_plan_t plan, int64_t R, int prec) {
+  int ln = 0, lr = 0;
+  while (((int64_t)1 << ln) < plan->N) ++ln;
+  while (((int64_t)1 << lr) < R) ++lr;
+  char buf[160];
+  std::snprintf(buf, sizeof(buf), "family=%d alpha=%.17g beta=%.17g log2N=%d log2R=%d prec=%d",
+                plan->family, plan->p.alpha, plan->p.beta, ln, lr, prec);
+  return buf;
+}
+
+// The autotuner's cache: one line per key, "key": {fields}, inside { }.
+bool cache_lookup(const char* path, const std::string& key, spt_tuning& t) {
+  if (!path) return false;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return false;
+  std::string text;
+  char buf[4096];
+  size_t n;
+  while ((n = std::fread(buf, 1, sizeof(buf), f)) > 0) text.append(buf, n);
+  std::fclose(f);
+  const size_t at = text.find("\"" + key + "\"");
+  if (at == std::string::npos) return false;
+  const size_t b = text.find('{', at), e = text.find('}', at);
+  if (b == std::string::npos || e == std::string::npos || e < b) return false;
+  const std::string body = text.substr(b, e - b);
+  auto field = [&](const char* name, int32_t& out) {
+    const size_t p = body.find(std::string("\"") + name + "\":");
+    if (p == std::string::npos) return false;
+    out = (int32_t)std::strtol(body.c_str() + p + std::strlen(name) + 3, nullptr, 10);
+    return true;
+  };
+  spt_tuning c{};
+  if (!field("product", c.product) || !field("window_rhs", c.window_rhs) ||
+      !field("fft_batch", c.fft_batch) || !field("fft_half", c.fft_half) ||
+      !field("inv_four", c.inv_four))
+    return false;
+  check_tuning(c);
+  t = c;
+  return true;
+}
+
+void cache_store(const char* path, const std::string& key, const spt_tuning& t, double us) {
+  if (!path) return;
+  std::vector<std::string> lines;
+  if (FILE* f = std::fopen(path, "r")) {
+    char buf[1024];
+    while (std::fgets(buf, sizeof(buf), f)) {
+      std::string l(buf);
+      while (!l.empty() && (l.back() == '\n' || l.back() == ',')) l.pop_back();
+      if (l.size() > 2 && l[0] == ' ' && l.find("\"" + key + "\"") == std::string::npos)
+        lines.push_back(l);
+    }
+    std::fclose(f);
+  }
+  char rec[512];
+  std::snprintf(rec, sizeof(rec),
+                "  \"%s\": {\"product\": %d, \"window_rhs\": %d, \"fft_batch\": %d, "
+                "\"fft_half\": %d, \"inv_four\": %d, \"us\": %.3f}",
+                key.c_str(), t.product, t.window_rhs, t.fft_batch, t.fft_half, t.inv_four, us);
+  lines.push_back(rec);
+  FILE* f = std::fopen(path, "w");
+  if (!f) throw Error(SPT_E_INVALID_ARG, std::string("cannot write the tuning cache ") + path);
+  std::fputs("{\n", f);
+  for (size_t i = 0; i < lines.size(); ++i)
+    std::fprintf(f, "%s%s\n", lines[i].c_str(), i + 1 < lines.size() ? "," : "");
+  std::fputs("}\n", f);
+  std::fclose(f);
+}
+
+template <typename T>
+void autotune_t(spt_plan_t plan, int64_t R, int prec, hipStream_t s, spt_tuning& best,
+                double& best_s) {
+  const int64_t N = plan->N;
+  std::vector<double> hx((size_t)R * N);
+  std::mt19937_64 gen(0x70e5eed);
+  std::normal_distribution<double> nd;
+  for (double& v : hx) v = nd(gen);
+  std::vector<T> h(hx.begin(), hx.end());
+  DevBuf x, y;
+  upload(x, h, s);
+  y.alloc(h.size() * sizeof(T), s);
+  const bool split = prec == SPT_SPLIT_BF16;
+  const size_t lds_max = max_lds_bytes(plan->device);
+  bool halvable = false;
+  for (auto& B : plan->blk)
+    halvable |= !B->big && B->P >= FUSED_HALF_MIN_P && B->P % 2 == 0 &&
+                fused_lds_bytes<double>(B->P, 128 + B->P / 128 + 1) <= lds_max;
+  std::vector<spt_tuning> cand;
+  const std::vector<int> prods = split ? std::vector<int>{SPT_PRODUCT_TILE, SPT_PRODUCT_WINDOW,
+                                                          SPT_PRODUCT_CHUNKED}
+                                       : std::vector<int>{SPT_PRODUCT_DEFAULT};
+  const std::vector<int> halves = halvable ? std::vector<int>{SPT_TUNE_OFF, SPT_TUNE_ON}
+                                           : std::vector<int>{SPT_TUNE_DEFAULT};
+  for (int pr : prods)
+    for (int rhs : (pr == SPT_PRODUCT_WINDOW ? std::vector<int>{32, 64} : std::vector<int>{0}))
+      for (int fb : {1, 2, 4})
+        for (int hf : halves) cand.push_back(spt_tuning{pr, rhs, fb, hf, plan->tune.inv_four});
+  best_s = 1e30;
+  for (const spt_tuning& c : cand) {
+    plan->tune = c;
+    apply_tuning(plan, s);
+    const double t = time_executes<T>(plan, x.as<T>(), y.as<T>(), R, prec, s, 2, 10);
+    if (t < best_s) {
+      best_s = t;
+      best = c;
+    }
+  }
+  plan->tune = best;
+  apply_tuning(plan, s);
+  SPT_HIP(hipStreamSynchronize(s));
+}
+
 // ---------------------------------------------------------------- no-allocation execute
 // The workspace of spt_execute_noalloc: one static array per device, resident
 // from the library's load until the process ends.  Host code uses the address
@@ -2572,6 +2740,61 @@ spt_status spt_set_allocator(spt_alloc_fn alloc, spt_free_fn free_, void* ctx) {
   });
 }
 
+spt_status spt_plan_set_tuning(spt_plan_t plan, const spt_tuning* t) {
+  return guard([&] {
+    check_plan(plan);
+    if (!t) throw Error(SPT_E_INVALID_ARG, "t is NULL");
+    check_tuning(*t);
+    plan->tune = *t;
+    if (plan->precomputed) {
+      set_device(plan);
+      apply_tuning(plan, nullptr);
+    }
+  });
+}
+
+spt_status spt_plan_get_tuning(spt_plan_t plan, spt_tuning* t) {
+  return guard([&] {
+    check_plan(plan);
+    if (!t) throw Error(SPT_E_INVALID_ARG, "t is NULL");
+    *t = plan->tune;
+  });
+}
+
+spt_status spt_autotune(spt_plan_t plan, int64_t nrhs, int32_t prec, void* stream,
+                        const char* cache_path, spt_tuning* chosen, double* us) {
+  return guard([&] {
+    check_plan(plan);
+    if (!plan->precomputed) throw Error(SPT_E_NOT_PRECOMPUTED, "plan is not precomputed");
+    if (nrhs < 1 || nrhs > 65535 * 64) throw Error(SPT_E_INVALID_ARG, "nrhs out of range");
+    if (prec < 0 || prec > 2) throw Error(SPT_E_INVALID_ARG, "unknown precision");
+    if (!(plan->prepared & (1u << prec)))
+      throw Error(SPT_E_UNSUPPORTED, "precision " + std::to_string(prec) + " was not prepared");
+    if (us) *us = 0.0;
+    if (plan->cx || !uses_staged(plan)) {
+      if (chosen) *chosen = plan->tune;
+      return;
+    }
+    set_device(plan);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const std::string key = tuning_key(plan, nrhs, prec);
+    spt_tuning t{};
+    if (cache_lookup(cache_path, key, t)) {
+      plan->tune = t;
+      apply_tuning(plan, s);
+    } else {
+      double best = 0.0;
+      if (prec == SPT_F64)
+        autotune_t<double>(plan, nrhs, prec, s, t, best);
+      else
+        autotune_t<float>(plan, nrhs, prec, s, t, best);
+      cache_store(cache_path, key, t, 1e6 * best);
+      if (us) *us = 1e6 * best;
+    }
+    if (chosen) *chosen = plan->tune;
+  });
+}
+
 spt_status spt_plan_set_exec_wait(spt_plan_t plan, int64_t ticks) {
   return guard([&] {
     check_plan(plan);
@@ -2717,17 +2940,7 @@ spt_status spt_plan_destroy(spt_plan_t plan) {
     if (!plan) return;
     (void)hipSetDevice(plan->device);
     (void)hipDeviceSynchronize();
-    {
-      // batched contexts keyed by this plan's serial refer to its buffers
-      std::lock_guard<std::mutex> lk(g_batch_mu);
-      auto uses = [&](const std::unique_ptr<ExecCtx>& c) {
-        for (size_t i = 3; i < c->key.size(); i += 3)  // key: prec, n, staged, (serial, R, work)...
-          if (c->key[i] == plan->serial) return true;
-        return false;
-      };
-      g_batch_ctx.erase(std::remove_if(g_batch_ctx.begin(), g_batch_ctx.end(), uses),
-                        g_batch_ctx.end());
-    }
+    drop_batch_contexts(plan);  // batched contexts refer to its buffers
     delete plan;
   });
 }

@@ -199,3 +199,19 @@ def test_complex_plan_refusals(args, code):
     with pytest.raises(spt.SptError) as e:
         spt.Plan(**args)
     assert e.value.code == code
+
+
+def test_tuning_arguments():
+    p = spt.Plan("legendre", 512, 1e-7)
+    assert p.tuning() == {"product": 0, "window_rhs": 0, "fft_batch": 0, "fft_half": 0,
+                          "inv_four": 0}
+    p.set_tuning(product=spt.PRODUCT_CHUNKED, fft_batch=2)   # before precompute: host only
+    assert p.tuning()["product"] == 3 and p.tuning()["fft_batch"] == 2
+    for bad in (dict(product=4), dict(window_rhs=48), dict(fft_batch=3), dict(fft_half=3)):
+        with pytest.raises(spt.SptError) as e:
+            p.set_tuning(**bad)
+        assert e.value.code == -1
+    with pytest.raises(ValueError):
+        p.set_tuning(nonsense=1)
+    lib = _lib.load()
+    assert lib.spt_autotune(p.handle, 4, 0, None, None, None, None) == -2

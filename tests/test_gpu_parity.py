@@ -407,7 +407,7 @@ def test_transposed_direct_mode(spt, fam, N, R):
 
 @pytest.mark.parametrize("fam,N,kw", [
     ("legendre", 7000, {}), ("jacobi", 9000, dict(alpha=-0.5, beta=-0.5))])
-def test_transposed_four_step_fp64(spt, monkeypatch, fam, N, kw):
+def test_transposed_four_step_fp64(spt, fam, N, kw):
     """The four-step inverse transform of the transposed product, forced on
     first blocks that also fit one workgroup (Legendre 7000: P = 4374, Jacobi
     9000: P = 5625, odd): oracle parity, and agreement with the
@@ -420,7 +420,7 @@ def test_transposed_four_step_fp64(spt, monkeypatch, fam, N, kw):
     F = workloads.rhs("normal", 5, N, 77)
     import torch
     Y1 = to_host(p.execute_transposed(to_dev(F, torch.float64), prec=spt.F64))
-    monkeypatch.setenv("SPT_INV_FFT_FOUR", "1")
+    p.set_tuning(inv_four=spt.TUNE_ON)
     Y4 = to_host(p.execute_transposed(to_dev(F, torch.float64), prec=spt.F64))
     C = oracle_compressed(fam, N, 1e-7, 1e-2, 32, kw.get("alpha", 0.0), kw.get("beta", 0.0))
     Yt = transposed.execute(C, F)
@@ -678,18 +678,15 @@ def test_batched_staged_matches_single_plans(spt):
 
 @pytest.mark.parametrize("fam,N,R", [("legendre", 7000, 3), ("legendre", 16384, 64),
                                      ("legendre", LONG_N, 2), ("chebyshev_t", 3000, 130)])
-def test_forced_chunks_match_per_tile(spt, monkeypatch, fam, N, R):
+def test_forced_chunks_match_per_tile(spt, fam, N, R):
     """The chunked products (split-bf16 and float64) on plans whose windows
-    would fit whole (forced by SPT_SPMM_WINDOW=chunk): the same bits as the
+    would fit whole (asked for: spt_tuning.product): the same bits as the
     per-tile products; a first
     block of four-step transforms (N = 24000), no direct tail (Chebyshev, one
     two-sided block), several right-hand-side chunks."""
     say("forced chunks", fam, N, R)
-    monkeypatch.setenv("SPT_SPMM_WINDOW", "chunk")
-    p = spt.Plan(fam, N, 1e-7).precompute()
-    monkeypatch.setenv("SPT_SPMM_WINDOW", "0")
-    q = spt.Plan(fam, N, 1e-7).precompute()
-    monkeypatch.delenv("SPT_SPMM_WINDOW")
+    p = spt.Plan(fam, N, 1e-7).set_tuning(product=spt.PRODUCT_CHUNKED).precompute()
+    q = spt.Plan(fam, N, 1e-7).set_tuning(product=spt.PRODUCT_TILE).precompute()
     assert p.info()["window_chunked"] == 1 and q.info()["window_lds"] == 0
     if fam == "chebyshev_t":
         assert p.info()["tail"] == 0
@@ -773,7 +770,7 @@ def test_one_plan_on_several_streams(spt):
     ("chebyshev_t", 3000, 130, {}), ("laguerre_fn", 5000, 64, {}),
     ("laguerre_fn", 3001, 130, {}), ("hermite_fn", 2049, 17, {}),
     ("jacobi", 4100, 200, dict(alpha=-0.5, beta=0.5))])
-def test_windowed_product_matches_per_tile(spt, monkeypatch, fam, N, R, kw, rg):
+def test_windowed_product_matches_per_tile(spt, fam, N, R, kw, rg):
     """The windowed split-bf16 product (spectra staged in LDS per group of four
     row tiles, 64 or 32 right-hand sides per workgroup; for windows too wide
     for LDS, in chunks of 32 columns) takes the same steps in the same order as
@@ -781,13 +778,9 @@ def test_windowed_product_matches_per_tile(spt, monkeypatch, fam, N, R, kw, rg):
     exact zero); ragged tile groups (N not a multiple of 64), right-hand-side
     chunks with fewer columns than a workgroup's and several chunks."""
     say("windowed product", fam, N, R, kw, "rg", rg)
-    monkeypatch.setenv("SPT_SPMM_WINDOW_RG", rg)
-    p = spt.Plan(fam, N, 1e-7, **kw).precompute()
-    monkeypatch.delenv("SPT_SPMM_WINDOW_RG")
+    p = spt.Plan(fam, N, 1e-7, **kw).set_tuning(window_rhs=16 * int(rg)).precompute()
     info = p.info()
-    monkeypatch.setenv("SPT_SPMM_WINDOW", "0")
-    q = spt.Plan(fam, N, 1e-7, **kw).precompute()
-    monkeypatch.delenv("SPT_SPMM_WINDOW")
+    q = spt.Plan(fam, N, 1e-7, **kw).set_tuning(product=spt.PRODUCT_TILE).precompute()
     assert q.info()["window_lds"] == 0
     say("  blocks %d window LDS %d B, %d columns, chunked %d" % (
         info["n_blocks"], info["window_lds"], info["window_cols"], info["window_chunked"]))
@@ -800,3 +793,28 @@ def test_windowed_product_matches_per_tile(spt, monkeypatch, fam, N, R, kw, rg):
     if info["window_chunked"]:
         # the float64 product through the same chunked windows
         assert np.array_equal(run(spt, p, X, spt.F64), run(spt, q, X, spt.F64))
+
+
+def test_autotuned_plan_keeps_parity(spt, tmp_path):
+    """The autotuner (every launch choice timed on the device, the fastest
+    kept, the result cached as JSON): the tuned plan's float64 result equals
+    the oracle's compressed method at 1e-12 and its split-bf16 result stays
+    within 1e-6 of float64; the cache gives the same choice without timing."""
+    import torch
+    from tests.helpers import oracle_compressed, oracle_family
+    N, R = 4096, 32
+    say("autotune", N, R)
+    f = oracle_family("legendre", N)
+    p = spt.Plan("legendre", N, 1e-7, mode=spt.MODE_ROW, nodes=f.nodes()).precompute()
+    cache = tmp_path / "tuning.json"
+    chosen, us = p.autotune(R, prec=spt.SPLIT_BF16, cache_path=cache)
+    say("  chosen %s, %.1f us per execute" % (chosen, us))
+    assert us > 0 and cache.exists() and p.tuning() == chosen
+    X = workloads.rhs("normal", R, N, 81)
+    Y64 = run(spt, p, X, spt.F64)
+    assert rel_rows(Y64, oracle_compressed("legendre", N, 1e-7).execute(X)) <= 1e-12
+    assert rel_rows(run(spt, p, X, spt.SPLIT_BF16), Y64) <= REDUCED_TOL
+    q = spt.Plan("legendre", N, 1e-7, mode=spt.MODE_ROW, nodes=f.nodes()).precompute()
+    again, us2 = q.autotune(R, prec=spt.SPLIT_BF16, cache_path=cache)
+    assert again == chosen and us2 == 0.0
+    assert np.array_equal(run(spt, q, X, spt.SPLIT_BF16), run(spt, p, X, spt.SPLIT_BF16))
