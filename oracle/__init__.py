@@ -21,6 +21,8 @@ transposed  Algorithm 2 / block Algorithm 4 (product with the transpose): sparse
             discard the extras.
 appendix_a  Appendix A: compressed rows of the trigonometric generators from the
             closed-form row spectra convolved with 2q+1 window coefficients.
+two_d       The two-dimensional compression of sec. 4.2 (eq. comp_2d) as a
+            density measure, beside the row and column compressions.
 
 Pins (what ties this oracle to something other than itself) live in
 ``tests/test_oracle_*.py``.  Parity unpinned: the compression ratios of the
@@ -28,4 +30,4 @@ Laguerre and Hermite function families at their Gauss nodes (the paper gives
 them only for an equispaced grid, and only as figures).
 """
 
-from . import params, nodes, entries, direct, compressed, transposed, appendix_a  # noqa: F401
+from . import params, nodes, entries, direct, compressed, transposed, appendix_a, two_d  # noqa: F401
