@@ -227,6 +227,9 @@ def main():
                          "(timed the same way, reported for the design notes)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default launch choices instead of spt_autotune's")
+    ap.add_argument("--tuning", default="",
+                    help="launch choices to use instead of the autotuner's, e.g. "
+                         "product=2,window_rhs=32,fft_batch=4 (spt_tuning fields)")
     ap.add_argument("--reduced-fft", type=int, default=0, choices=[0, 1, 2],
                     help="arithmetic of the float32 paths' FFTs: 0 chosen by the plan "
                          "(spt_params.reduced_fft), 1 float32, 2 float64")
@@ -269,7 +272,10 @@ def main():
     # launch choices by the library's autotuner (timed on the split-bf16 path;
     # the float64 and float32 paths run with the same choices)
     tuning = {"autotuned": False}
-    if not args.no_autotune:
+    if args.tuning:
+        plan.set_tuning(**{k: int(v) for k, v in (kv.split("=") for kv in args.tuning.split(","))})
+        tuning = dict(plan.tuning(), autotuned=False)
+    elif not args.no_autotune:
         t0 = time.perf_counter()
         chosen, us = plan.autotune(R, prec=spt.SPLIT_BF16)
         tuning = dict(chosen, autotuned=True, us_per_execute=us,
