@@ -324,3 +324,46 @@ def test_execute_rows_and_block_max_rows(fam_id, N, kw):
     # without the maximum's rows a smaller threshold keeps more entries
     Yp, maxp = compressed.execute_rows(plan, X, rows[:1])
     assert all(a <= b for a, b in zip(maxp, full.maxabs))
+
+
+class _ScaledRows:
+    """A family whose rows ``rows`` are multiplied by ``c`` (everything else
+    delegated): scaling a row scales that row of Add = A_e W F, since the
+    window and the DFT act along the columns."""
+
+    def __init__(self, fam, rows, c):
+        self._fam, self._rows, self._c = fam, np.asarray(rows), c
+
+    def __getattr__(self, name):
+        return getattr(self._fam, name)
+
+    def block(self, rows, m0, m1):
+        B = self._fam.block(rows, m0, m1)
+        B[np.isin(np.asarray(rows), self._rows)] *= self._c
+        return B
+
+
+def _kept_per_row(fam, eps1):
+    C = compressed.Compressed(compressed.Plan(fam, eps1))
+    return [np.diff(m.indptr) for m in C.mats]
+
+
+@pytest.mark.parametrize("fam_id,kw", [(matrix.LEGENDRE, {}), (matrix.LAGUERRE_FN, {})])
+def test_threshold_is_relative_to_the_whole_block(fam_id, kw):
+    # Alg. 1 step 1.3: an entry is dropped when it is below eps1 times the largest
+    # entry of the (block's) matrix, one threshold for all rows.  So the kept
+    # pattern is invariant under scaling the whole matrix, while scaling one row
+    # up by 1e4 raises the threshold of every other row of each block and drops
+    # entries there (a per-row threshold would leave the other rows unchanged).
+    N, eps1, j0 = 256, 1e-7, 100
+    fam = matrix.MatrixFamily(fam_id, N, **kw)
+    base = _kept_per_row(fam, eps1)
+    every = _kept_per_row(_ScaledRows(fam, np.arange(N), 8.0), eps1)
+    for a, b in zip(base, every):
+        np.testing.assert_array_equal(a, b)
+    one = _kept_per_row(_ScaledRows(fam, [j0], 1e4), eps1)
+    others = np.arange(N) != j0
+    for a, b in zip(base, one):
+        assert b[j0] >= a[j0]
+        assert b[others].sum() < a[others].sum()
+        assert np.all(b[others] <= a[others])
