@@ -198,7 +198,8 @@ enum {
   SPT_PRODUCT_TILE = 1,     /* per row tile, spectra read from memory             */
   SPT_PRODUCT_WINDOW = 2,   /* the default's choice, asked for explicitly         */
   SPT_PRODUCT_CHUNKED = 3,  /* windows through LDS in chunks of 32 columns        */
-  SPT_TUNE_DEFAULT = 0, SPT_TUNE_OFF = 1, SPT_TUNE_ON = 2
+  SPT_TUNE_DEFAULT = 0, SPT_TUNE_OFF = 1, SPT_TUNE_ON = 2,
+  SPT_FFT_EIGHT = 3         /* fft_half: split by output residue mod 8 instead      */
 };
 typedef struct {
   int32_t product;     /* SPT_PRODUCT_*                                          */
@@ -206,9 +207,12 @@ typedef struct {
                           when two such workgroups fit a CU's LDS, else 32), 32, 64 */
   int32_t fft_batch;   /* most right-hand sides per workgroup of a short block's
                           fused FFT: 0 (4), 1, 2 or 4                            */
-  int32_t fft_half;    /* SPT_TUNE_*: split even transforms of at least 4096 points
-                          by output parity into two workgroups (default on; off
-                          only where the whole transform fits one workgroup)    */
+  int32_t fft_half;    /* SPT_TUNE_* or SPT_FFT_EIGHT: split transforms of at least
+                          4096 points by output parity into two workgroups (ON,
+                          and DEFAULT), or the real transform by output residue
+                          mod 8 into five (SPT_FFT_EIGHT, when 4 divides P),
+                          or not at all (OFF: only where the whole transform
+                          fits one workgroup)                                   */
   int32_t inv_four;    /* SPT_TUNE_*: transposed product, four-step inverse
                           transforms also for blocks that fit one workgroup (ON) */
 } spt_tuning;

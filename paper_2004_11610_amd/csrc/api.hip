@@ -478,6 +478,24 @@ void exec_geometry(DevBlock& B) {
   B.f2 = make_fft_plan(B.P2);
 }
 
+// The fused FFT's split of a transform of P points (FftDesc::half, by the
+// plan's launch choice): by output parity by default for P >= 4096; by output
+// residue mod 8 when asked for and 4 divides P; none when asked for and the
+// whole transform fits one workgroup.
+int fused_split(spt_plan_t plan, int P, size_t lds_max) {
+  if (P < FUSED_HALF_MIN_P || P % 2) return FFT_SPLIT_NONE;
+  const int t = plan->tune.fft_half;
+  if (t == SPT_FFT_EIGHT && P % 4 == 0) return FFT_SPLIT_EIGHT;
+  const bool whole_fits = fused_lds_bytes<double>(P, 128 + P / 128 + 1) <= lds_max;
+  if (t == SPT_TUNE_OFF && whole_fits) return FFT_SPLIT_NONE;
+  return FFT_SPLIT_PARITY;
+}
+
+// points of one workgroup's transform under a split
+int fused_points(int P, int split) {
+  return split == FFT_SPLIT_EIGHT ? P / 4 : split == FFT_SPLIT_PARITY ? P / 2 : P;
+}
+
 // Build the compressed block B (three passes over row panels).  With
 // `estimate`, only 8 panels of 64 rows spread over the rows are transformed
 // (maximum and tile boxes from those rows) and the return value is the
@@ -491,16 +509,14 @@ int64_t build_block(spt_plan_t plan, DevBlock& B, hipStream_t s, size_t lds_max,
   // float64 points of the precomputation's row transforms and of the inverse
   // transforms (P * 16 bytes), and the fused execute FFT's points of a
   // transform or of a parity half with its two twiddle tables
-  const bool can_half = P >= FUSED_HALF_MIN_P && P % 2 == 0;
-  const bool whole_fits = fused_lds_bytes<double>(P, 128 + P / 128 + 1) <= lds_max;
-  const bool half = can_half && (plan->tune.fft_half != SPT_TUNE_OFF || !whole_fits);
+  const int split = fused_split(plan, P, lds_max);
   const bool big = P > FUSED_MAX_P || (size_t)P * sizeof(double2) > lds_max ||
-                   fused_lds_bytes<double>(half ? P / 2 : P, 128 + P / 128 + 1) > lds_max;
+                   fused_lds_bytes<double>(fused_points(P, split), 128 + P / 128 + 1) > lds_max;
   B.big = big;
   if (!big) {
     B.fft = make_fft_plan(P);
-    B.half = half ? 1 : 0;
-    B.fftw = B.half ? make_fft_plan(P / 2) : B.fft;
+    B.half = split;
+    B.fftw = split ? make_fft_plan(fused_points(P, split)) : B.fft;
   }
   exec_geometry(B);
   if (big && !B.four)
@@ -1556,13 +1572,21 @@ void execute_staged_t(spt_plan_t plan, const T* X, T* Y, int64_t R, int prec, hi
   auto fft_fused = [&](int b0, int nb, hipStream_t st) {
     int threads = 64;
     size_t lds = 16;
-    int64_t gx = 1;
+    if (nb > FFT_GRID_MAX)
+      throw Error(SPT_E_UNSUPPORTED, "more than " + std::to_string(FFT_GRID_MAX) +
+                                         " blocks in one fused FFT launch");
+    FftGrid g{};
+    g.nblk = nb;
+    int64_t wgs = 0;
     for (int b = b0; b < b0 + nb; ++b) {
       const DevBlock& B = *plan->blk[b];
       threads = std::max(threads, B.fftw.threads);
       lds = std::max(lds, fused_lds_bytes<T>(B.fftw.P << B.lbw, 128 + B.P / 128 + 1));
-      gx = std::max<int64_t>(gx, B.half ? 2 * R : (R + (1 << B.lbw) - 1) >> B.lbw);
+      g.wg0[b - b0] = (int)wgs;
+      wgs += B.half ? fft_split_wgs(B.half) * R : (R + (1 << B.lbw) - 1) >> B.lbw;
     }
+    if (wgs > INT32_MAX) throw Error(SPT_E_UNSUPPORTED, "FFT grid too large");
+    g.wg0[nb] = (int)wgs;
     if constexpr (std::is_same<T, float>::value) {
       if (plan->reduced_fft64) {
         size_t lds64 = 16;
@@ -1570,21 +1594,20 @@ void execute_staged_t(spt_plan_t plan, const T* X, T* Y, int64_t R, int prec, hi
           const DevBlock& B = *plan->blk[b];
           lds64 = std::max(lds64, fused_lds_bytes<double>(B.fftw.P << B.lbw, 128 + B.P / 128 + 1));
         }
-        launch_exec_fft_multi_x32(plan->fftdesc64.as<FftDesc<double>>() + b0, nb, threads, lds64,
-                                  (int)gx, X, split ? nullptr : static_cast<float2*>(ws),
+        launch_exec_fft_multi_x32(plan->fftdesc64.as<FftDesc<double>>() + b0, g, threads, lds64,
+                                  X, split ? nullptr : static_cast<float2*>(ws),
                                   split ? static_cast<uint32_t*>(ws) : nullptr,
                                   (int64_t)R * plan->zper4, (int)R, plan->N, st);
         return;
       }
       if (split) {
-        launch_exec_fft_multi_split(d + b0, nb, threads, lds, (int)gx, X,
-                                    static_cast<uint32_t*>(ws), (int64_t)R * plan->zper4, (int)R,
-                                    plan->N, st);
+        launch_exec_fft_multi_split(d + b0, g, threads, lds, X, static_cast<uint32_t*>(ws),
+                                    (int64_t)R * plan->zper4, (int)R, plan->N, st);
         return;
       }
     }
-    launch_exec_fft_multi<T>(d + b0, nb, threads, lds, (int)gx, X, static_cast<C*>(ws), (int)R,
-                             plan->N, st);
+    launch_exec_fft_multi<T>(d + b0, g, threads, lds, X, static_cast<C*>(ws), (int)R, plan->N,
+                             st);
   };
   // banded product of every block and the tail
   auto product = [&](hipStream_t st) {
@@ -2249,9 +2272,10 @@ void check_tuning(const spt_tuning& t) {
     throw Error(SPT_E_INVALID_ARG, "window_rhs must be 0, 32 or 64");
   if (t.fft_batch != 0 && t.fft_batch != 1 && t.fft_batch != 2 && t.fft_batch != 4)
     throw Error(SPT_E_INVALID_ARG, "fft_batch must be 0, 1, 2 or 4");
-  for (int v : {t.fft_half, t.inv_four})
-    if (v < SPT_TUNE_DEFAULT || v > SPT_TUNE_ON)
-      throw Error(SPT_E_INVALID_ARG, "unknown on/off choice");
+  if (t.inv_four < SPT_TUNE_DEFAULT || t.inv_four > SPT_TUNE_ON)
+    throw Error(SPT_E_INVALID_ARG, "unknown on/off choice");
+  if (t.fft_half < SPT_TUNE_DEFAULT || t.fft_half > SPT_FFT_EIGHT)
+    throw Error(SPT_E_INVALID_ARG, "unknown FFT split choice");
 }
 
 // the batch contexts that refer to a plan's buffers (keyed by its serial)
@@ -2278,10 +2302,11 @@ void apply_tuning(spt_plan_t plan, hipStream_t s) {
     DevBlock& B = *Bp;
     if (B.big) continue;
     const int P = B.P;
-    const bool can_half = P >= FUSED_HALF_MIN_P && P % 2 == 0;
-    const bool whole_fits = fused_lds_bytes<double>(P, 128 + P / 128 + 1) <= lds_max;
-    B.half = can_half && (plan->tune.fft_half != SPT_TUNE_OFF || !whole_fits) ? 1 : 0;
-    B.fftw = B.half ? make_fft_plan(P / 2) : B.fft;
+    const int split = fused_split(plan, P, lds_max);
+    if (fused_lds_bytes<double>(fused_points(P, split), 128 + P / 128 + 1) > lds_max)
+      throw Error(SPT_E_UNSUPPORTED, "FFT split does not fit one workgroup");
+    B.half = split;
+    B.fftw = split ? make_fft_plan(fused_points(P, split)) : B.fft;
   }
   build_fft_descs(plan, s);
   plan->serial = next_serial();  // keys of the executor contexts
@@ -2390,16 +2415,25 @@ void autotune_t(spt_plan_t plan, int64_t R, int prec, hipStream_t s, spt_tuning&
   y.alloc(h.size() * sizeof(T), s);
   const bool split = prec == SPT_SPLIT_BF16;
   const size_t lds_max = max_lds_bytes(plan->device);
-  bool halvable = false;
+  // the FFT splits worth timing: parity (the default), none where a whole
+  // transform fits one workgroup, eight-way where 4 divides P
+  bool can_split = false, can_off = false, can_eight = false;
   for (auto& B : plan->blk)
-    halvable |= !B->big && B->P >= FUSED_HALF_MIN_P && B->P % 2 == 0 &&
-                fused_lds_bytes<double>(B->P, 128 + B->P / 128 + 1) <= lds_max;
+    if (!B->big && B->P >= FUSED_HALF_MIN_P && B->P % 2 == 0) {
+      can_split = true;
+      can_off |= fused_lds_bytes<double>(B->P, 128 + B->P / 128 + 1) <= lds_max;
+      can_eight |= B->P % 4 == 0;
+    }
+  std::vector<int> halves{SPT_TUNE_DEFAULT};
+  if (can_split) {
+    halves = {SPT_TUNE_ON};
+    if (can_off) halves.push_back(SPT_TUNE_OFF);
+    if (can_eight) halves.push_back(SPT_FFT_EIGHT);
+  }
   std::vector<spt_tuning> cand;
   const std::vector<int> prods = split ? std::vector<int>{SPT_PRODUCT_TILE, SPT_PRODUCT_WINDOW,
                                                           SPT_PRODUCT_CHUNKED}
                                        : std::vector<int>{SPT_PRODUCT_DEFAULT};
-  const std::vector<int> halves = halvable ? std::vector<int>{SPT_TUNE_OFF, SPT_TUNE_ON}
-                                           : std::vector<int>{SPT_TUNE_DEFAULT};
   for (int pr : prods)
     for (int rhs : (pr == SPT_PRODUCT_WINDOW ? std::vector<int>{32, 64} : std::vector<int>{0}))
       for (int fb : {1, 2, 4})

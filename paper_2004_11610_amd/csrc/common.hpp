@@ -116,15 +116,33 @@ struct FftDesc {
   // the fused launch gives each workgroup 2^lb right-hand sides of this block
   // (2^lb fp.P <= the launch's largest fp.P)
   int lb;
-  // 1: the transform of P = L/2 points is split by the parity of its outputs
-  // into two halves of fp.P = P/2 points, one workgroup each (fp: P/2)
+  // FFT_SPLIT_PARITY: the transform of P = L/2 points is split by the parity
+  // of its outputs into two halves of fp.P = P/2 points, one workgroup each;
+  // FFT_SPLIT_EIGHT: the real transform of L points is split by the residue
+  // of its outputs mod 8 into five workgroups of fp.P = L/8 points
   int half;
+};
+
+enum { FFT_SPLIT_NONE = 0, FFT_SPLIT_PARITY = 1, FFT_SPLIT_EIGHT = 2 };
+
+// workgroups per right-hand side of a split transform
+inline int fft_split_wgs(int half) {
+  return half == FFT_SPLIT_EIGHT ? 5 : half == FFT_SPLIT_PARITY ? 2 : 1;
+}
+
+// The fused FFT launch's one-dimensional grid: block b takes workgroups
+// wg0[b] .. wg0[b + 1] - 1 (no idle workgroups); at most FFT_GRID_MAX blocks
+// per launch.
+constexpr int FFT_GRID_MAX = 16;
+struct FftGrid {
+  int nblk;
+  int wg0[FFT_GRID_MAX + 1];
 };
 
 // grid: gx x nblk workgroups of `threads`; lds: bytes of the largest
 // workgroup (fused_lds_bytes)
 template <typename T>
-void launch_exec_fft_multi(const FftDesc<T>* descs, int nblk, int threads, size_t lds, int gx,
+void launch_exec_fft_multi(const FftDesc<T>* descs, const FftGrid& g, int threads, size_t lds,
                            const T* X, cplx_t<T>* Z, int R, int64_t N, hipStream_t s);
 // LDS of a fused FFT workgroup of pts points whose block has two-level
 // twiddle tables of ntw entries (tw and tw2, float64)
@@ -326,16 +344,16 @@ void launch_spmm_presplit_items(const SpmmSplitBatch& b, int n_items, hipStream_
 void launch_spmm_chunk_items(const SpmmSplitBatch& b, int n_items, size_t lds, hipStream_t s);
 
 // split-bf16 staged FFT: the half spectra go out as the three planes above
-void launch_exec_fft_multi_split(const FftDesc<float>* descs, int nblk, int threads, size_t lds,
-                                 int gx, const float* X, uint32_t* Zs, int64_t zplane, int R,
+void launch_exec_fft_multi_split(const FftDesc<float>* descs, const FftGrid& g, int threads,
+                                 size_t lds, const float* X, uint32_t* Zs, int64_t zplane, int R,
                                  int64_t N, hipStream_t s);
 // the float32 paths' transforms in float64 arithmetic (float32 X, the float64
 // descriptors and tables; lds from fused_lds_bytes<double>): each spectrum
 // value is rounded once to float32, then split into the three planes Zs
 // (split-bf16) or stored in Z (float32 path, Zs null)
-void launch_exec_fft_multi_x32(const FftDesc<double>* descs, int nblk, int threads, size_t lds,
-                               int gx, const float* X, float2* Z, uint32_t* Zs, int64_t zplane,
-                               int R, int64_t N, hipStream_t s);
+void launch_exec_fft_multi_x32(const FftDesc<double>* descs, const FftGrid& g, int threads,
+                               size_t lds, const float* X, float2* Z, uint32_t* Zs,
+                               int64_t zplane, int R, int64_t N, hipStream_t s);
 
 // transposed banded product: u_i = A_i^T f (half spectrum), per block
 // The transposed product gathers by columns of the half spectrum: the row

@@ -325,6 +325,118 @@ __device__ __forceinline__ void fft_half_body(const FftDesc<T>* __restrict__ d,
   }
 }
 
+// Eight-way split of the real transform of L = 2P points by output residue
+// (FftDesc::half == FFT_SPLIT_EIGHT), one workgroup per residue p = 0..4: with
+// W = exp(2 pi i / L), omega = exp(2 pi i / 8) and M = L / 8,
+//   X[8m + p] = sum_{n<M} exp(2 pi i nm / M) y_n,
+//   y_n = W^(np) sum_{q<8} v_(n + qM) omega^(pq),
+// one decimation-in-frequency step of radix 8, then a transform of M points.
+// v is real, so X[L - k] = conj(X[k]) and the transform Y of residue p also
+// gives residue 8 - p: X[8m + 8 - p] = conj(Y[M - 1 - m]).  The five
+// workgroups of a right-hand side write the half spectrum k = 0..P between
+// them (zeros past P in the split planes), and each reads the whole row, so
+// that the transform of a long block is spread over five CUs.
+template <typename T, typename TI, bool SPLIT, int EI>
+__device__ __forceinline__ void fft_rdif_body(const FftDesc<T>* __restrict__ d,
+                                              const TI* __restrict__ X, cplx_t<TI>* __restrict__ Z,
+                                              uint32_t* __restrict__ Zs, int64_t zplane, int R,
+                                              int64_t N, int r, int p) {
+  using C = cplx_t<T>;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C* lds = reinterpret_cast<C*>(smem_raw);
+  const int M = d->fp.P, P = 4 * M, nt = blockDim.x;
+  const int tid = threadIdx.x;
+  const int c_lo = d->c_lo, c_hi = d->c_hi, m_off = d->m_off;
+  const T* __restrict__ winv = d->winv;
+  const TI* __restrict__ x = X + (int64_t)r * N;
+  TabStage<T, EI> ts;
+  ts.load(d, tid, nt);
+  double2* ltab = reinterpret_cast<double2*>(smem_raw + tab_offset<T>(M));
+  const double2* ltab2 = ltab + d->ntw;  // W^k = exp(i pi k / P)
+  // omega^t = (cos, sin)(2 pi t / 8) for t = (p q) mod 8
+  constexpr T h = T(0.70710678118654752440);
+  T co[8], si[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int t = (p * q) & 7;
+    co[q] = t == 0 ? T(1) : t == 4 ? T(-1) : (t == 2 || t == 6) ? T(0) : (t == 1 || t == 7) ? h : -h;
+    si[q] = t == 2 ? T(1) : t == 6 ? T(-1) : (t == 0 || t == 4) ? T(0) : (t == 1 || t == 3) ? h : -h;
+  }
+  // E1 and the radix-8 step: y_n without the factor W^(np), in rounds of RD
+  // points (16 loads each)
+  constexpr int RD = 2;
+#pragma unroll
+  for (int e0 = 0; e0 < EI; e0 += RD) {
+    TI xv[RD][8];
+    T wv[RD][8];
+#pragma unroll
+    for (int e = 0; e < RD; ++e) {
+      const int n = min(tid + (e0 + e) * nt, M - 1);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int c = n + q * M;
+        const int cc = c >= c_lo && c < c_hi ? c : c_lo;
+        xv[e][q] = gload(x + m_off + cc);
+        wv[e][q] = gload(winv + cc);
+      }
+    }
+    if (e0 == 0) ts.store(ltab, tid, nt);
+#pragma unroll
+    for (int e = 0; e < RD; ++e) {
+      const int n = tid + (e0 + e) * nt;
+      T re = T(0), im = T(0);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int c = n + q * M;
+        const T v = c >= c_lo && c < c_hi ? T(xv[e][q]) * wv[e][q] : T(0);
+        re += v * co[q];
+        im += v * si[q];
+      }
+      if (e0 + e < EI && n < M) lds[n] = C{re, im};
+    }
+  }
+  __syncthreads();
+  // the factor W^(np) on the thread's own points (the tables are in LDS now)
+  if (p != 0) {
+#pragma unroll
+    for (int e = 0; e < EI; ++e) {
+      const int n = tid + e * nt;
+      if (n < M) lds[n] = cmul(lds[n], to_c<C>(twiddle(ltab2, n * p)));
+    }
+    __syncthreads();
+  }
+  // the table is of length P = 4M: index scale 4
+  run_fft<+1, false, EI>(lds, M, 0, d->fp.npass, d->fp.radix, ltab, 4, tid, nt, true);
+  // outputs: residue p at k = 8m + p (Y[m]) and, for p = 1..3, residue 8 - p
+  // at k = 8m + 8 - p (conj Y[M - 1 - m]); output u of the workgroup is
+  // residue p at m = u (p = 0, 4) or, alternately, the two residues at m = u / 2
+  const T scale = d->scale;
+  const int kend = SPLIT ? d->ldz4 : P + 1;
+  const bool two = p != 0 && p != 4;
+  const int n_p = (kend - p + 7) / 8;
+  const int n_out = two ? n_p + (kend - (8 - p) + 7) / 8 : n_p;
+  for (int u = tid; u < n_out; u += nt) {
+    const bool mirror = two && (u & 1);
+    const int m = two ? u >> 1 : u;
+    const int k = mirror ? 8 * m + 8 - p : 8 * m + p;
+    if (mirror && k >= kend) continue;
+    C z = C{T(0), T(0)};
+    if (k <= P) {
+      const C y = lds[mirror ? M - 1 - m : m];
+      z = C{y.x * scale, (mirror ? -y.y : y.y) * scale};
+    }
+    if constexpr (!SPLIT) {
+      Z[(int64_t)R * d->zoff + (int64_t)r * d->ldz + k] = cplx_t<TI>{TI(z.x), TI(z.y)};
+    } else {
+      uint32_t pc[3];
+      spmmcore::split2(spmmcore::f32x2{(float)z.x, (float)z.y}, pc);
+      uint32_t* __restrict__ zs = Zs + (int64_t)R * d->zoff4 + (int64_t)r * d->ldz4 + k;
+#pragma unroll
+      for (int q = 0; q < 3; ++q) zs[q * zplane] = pc[q];
+    }
+  }
+}
+
 // MAXT: the launch's threads are at most MAXT (512 leaves each thread 256
 // registers, 1024 leaves 128).  TI: type of X and of the complex spectra Z
 // (float with T = double: the float32 paths' transforms in float64
@@ -334,18 +446,35 @@ __device__ __forceinline__ void fft_half_body(const FftDesc<T>* __restrict__ d,
 template <typename T, typename TI, bool SPLIT, int MAXT>
 __global__ __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(
     sizeof(T) == 4 && MAXT <= 512 ? 4 : 1))) void exec_fft_multi_kernel(
-    const FftDesc<T>* __restrict__ descs, const TI* __restrict__ X, cplx_t<TI>* __restrict__ Z,
-    uint32_t* __restrict__ Zs, int64_t zplane, int R, int64_t N) {
+    const FftDesc<T>* __restrict__ descs, FftGrid g, const TI* __restrict__ X,
+    cplx_t<TI>* __restrict__ Z, uint32_t* __restrict__ Zs, int64_t zplane, int R, int64_t N) {
   // transforms of at most EI_SHORT points per thread take the variant whose
   // loops stop there
   constexpr int EI_SHORT = FFT_EPT / 2;
-  const FftDesc<T>* __restrict__ d = descs + blockIdx.y;
-  if (d->half) {
-    // workgroup x = parity R + r: the two halves of a right-hand side are R
+  // the workgroup's block: the last b with wg0[b] <= blockIdx.x
+  int b = 0;
+#pragma unroll
+  for (int i = 1; i < FFT_GRID_MAX; ++i)
+    if (i < g.nblk && (int)blockIdx.x >= g.wg0[i]) b = i;
+  const int wx = (int)blockIdx.x - g.wg0[b];
+  const FftDesc<T>* __restrict__ d = descs + b;
+  if (d->half == FFT_SPLIT_EIGHT) {
+    // workgroup wx = p R + r: the five workgroups of a right-hand side are R
+    // apart, on one XCD when R is a multiple of 8 (their reads of the row and
+    // their interleaved writes meet in one L2)
+    const int p = wx / R, r = wx - p * R;
+    if (d->fp.P <= EI_SHORT * (int)blockDim.x)
+      fft_rdif_body<T, TI, SPLIT, EI_SHORT>(d, X, Z, Zs, zplane, R, N, r, p);
+    else
+      fft_rdif_body<T, TI, SPLIT, FFT_EPT>(d, X, Z, Zs, zplane, R, N, r, p);
+    return;
+  }
+  if (d->half == FFT_SPLIT_PARITY) {
+    // workgroup wx = parity R + r: the two halves of a right-hand side are R
     // workgroups apart, on the same XCD when R is a multiple of 8, so that
     // their reads of the row and their interleaved writes meet in one L2
-    const int par = (int)blockIdx.x >= R ? 1 : 0;
-    const int r = (int)blockIdx.x - par * R;
+    const int par = wx >= R ? 1 : 0;
+    const int r = wx - par * R;
     if (d->fp.P <= EI_SHORT * (int)blockDim.x)
       fft_half_body<T, TI, SPLIT, EI_SHORT>(d, X, Z, Zs, zplane, R, N, r, par);
     else
@@ -353,7 +482,7 @@ __global__ __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(
     return;
   }
   const int lb = d->lb;
-  const int r0 = (int)blockIdx.x << lb;
+  const int r0 = wx << lb;
   if (r0 >= R) return;
   const bool short_pts = (d->fp.P << lb) <= EI_SHORT * (int)blockDim.x;
   if (lb == 0) {
@@ -626,55 +755,57 @@ void launch_row_fft(const RowFftArgs& a, const FftPlan& fp, hipStream_t s) {
 }
 
 template <typename T>
-void launch_exec_fft_multi(const FftDesc<T>* descs, int nblk, int threads, size_t lds, int gx,
+void launch_exec_fft_multi(const FftDesc<T>* descs, const FftGrid& g, int threads, size_t lds,
                            const T* X, cplx_t<T>* Z, int R, int64_t N, hipStream_t s) {
+  const dim3 grid(g.wg0[g.nblk]);
   if (threads <= 512)
-    hipLaunchKernelGGL((exec_fft_multi_kernel<T, T, false, 512>), dim3(gx, nblk), dim3(threads),
-                       lds, s, descs, X, Z, (uint32_t*)nullptr, (int64_t)0, R, N);
+    hipLaunchKernelGGL((exec_fft_multi_kernel<T, T, false, 512>), grid, dim3(threads), lds, s,
+                       descs, g, X, Z, (uint32_t*)nullptr, (int64_t)0, R, N);
   else
-    hipLaunchKernelGGL((exec_fft_multi_kernel<T, T, false, 1024>), dim3(gx, nblk), dim3(threads),
-                       lds, s, descs, X, Z, (uint32_t*)nullptr, (int64_t)0, R, N);
+    hipLaunchKernelGGL((exec_fft_multi_kernel<T, T, false, 1024>), grid, dim3(threads), lds, s,
+                       descs, g, X, Z, (uint32_t*)nullptr, (int64_t)0, R, N);
   SPT_HIP(hipGetLastError());
 }
 
-void launch_exec_fft_multi_split(const FftDesc<float>* descs, int nblk, int threads, size_t lds,
-                                 int gx, const float* X, uint32_t* Zs, int64_t zplane, int R,
+void launch_exec_fft_multi_split(const FftDesc<float>* descs, const FftGrid& g, int threads,
+                                 size_t lds, const float* X, uint32_t* Zs, int64_t zplane, int R,
                                  int64_t N, hipStream_t s) {
+  const dim3 grid(g.wg0[g.nblk]);
   if (threads <= 512)
-    hipLaunchKernelGGL((exec_fft_multi_kernel<float, float, true, 512>), dim3(gx, nblk),
-                       dim3(threads), lds, s, descs, X, (float2*)nullptr, Zs, zplane, R, N);
+    hipLaunchKernelGGL((exec_fft_multi_kernel<float, float, true, 512>), grid, dim3(threads), lds,
+                       s, descs, g, X, (float2*)nullptr, Zs, zplane, R, N);
   else
-    hipLaunchKernelGGL((exec_fft_multi_kernel<float, float, true, 1024>), dim3(gx, nblk),
-                       dim3(threads), lds, s, descs, X, (float2*)nullptr, Zs, zplane, R, N);
+    hipLaunchKernelGGL((exec_fft_multi_kernel<float, float, true, 1024>), grid, dim3(threads),
+                       lds, s, descs, g, X, (float2*)nullptr, Zs, zplane, R, N);
   SPT_HIP(hipGetLastError());
 }
 
-void launch_exec_fft_multi_x32(const FftDesc<double>* descs, int nblk, int threads, size_t lds,
-                               int gx, const float* X, float2* Z, uint32_t* Zs, int64_t zplane,
-                               int R, int64_t N, hipStream_t s) {
+void launch_exec_fft_multi_x32(const FftDesc<double>* descs, const FftGrid& g, int threads,
+                               size_t lds, const float* X, float2* Z, uint32_t* Zs,
+                               int64_t zplane, int R, int64_t N, hipStream_t s) {
+  const dim3 grid(g.wg0[g.nblk]);
   if (Zs) {
     if (threads <= 512)
-      hipLaunchKernelGGL((exec_fft_multi_kernel<double, float, true, 512>), dim3(gx, nblk),
-                         dim3(threads), lds, s, descs, X, (float2*)nullptr, Zs, zplane, R, N);
+      hipLaunchKernelGGL((exec_fft_multi_kernel<double, float, true, 512>), grid, dim3(threads),
+                         lds, s, descs, g, X, (float2*)nullptr, Zs, zplane, R, N);
     else
-      hipLaunchKernelGGL((exec_fft_multi_kernel<double, float, true, 1024>), dim3(gx, nblk),
-                         dim3(threads), lds, s, descs, X, (float2*)nullptr, Zs, zplane, R, N);
+      hipLaunchKernelGGL((exec_fft_multi_kernel<double, float, true, 1024>), grid, dim3(threads),
+                         lds, s, descs, g, X, (float2*)nullptr, Zs, zplane, R, N);
   } else {
     if (threads <= 512)
-      hipLaunchKernelGGL((exec_fft_multi_kernel<double, float, false, 512>), dim3(gx, nblk),
-                         dim3(threads), lds, s, descs, X, Z, (uint32_t*)nullptr, (int64_t)0, R,
-                         N);
+      hipLaunchKernelGGL((exec_fft_multi_kernel<double, float, false, 512>), grid, dim3(threads),
+                         lds, s, descs, g, X, Z, (uint32_t*)nullptr, (int64_t)0, R, N);
     else
-      hipLaunchKernelGGL((exec_fft_multi_kernel<double, float, false, 1024>), dim3(gx, nblk),
-                         dim3(threads), lds, s, descs, X, Z, (uint32_t*)nullptr, (int64_t)0, R,
+      hipLaunchKernelGGL((exec_fft_multi_kernel<double, float, false, 1024>), grid,
+                         dim3(threads), lds, s, descs, g, X, Z, (uint32_t*)nullptr, (int64_t)0, R,
                          N);
   }
   SPT_HIP(hipGetLastError());
 }
 
-template void launch_exec_fft_multi<double>(const FftDesc<double>*, int, int, size_t, int,
+template void launch_exec_fft_multi<double>(const FftDesc<double>*, const FftGrid&, int, size_t,
                                             const double*, double2*, int, int64_t, hipStream_t);
-template void launch_exec_fft_multi<float>(const FftDesc<float>*, int, int, size_t, int,
+template void launch_exec_fft_multi<float>(const FftDesc<float>*, const FftGrid&, int, size_t,
                                            const float*, float2*, int, int64_t, hipStream_t);
 template void launch_exec_fft<double>(const ExecFftArgs<double>&, const FftPlan&, hipStream_t);
 template void launch_exec_fft<float>(const ExecFftArgs<float>&, const FftPlan&, hipStream_t);

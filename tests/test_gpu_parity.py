@@ -82,12 +82,15 @@ def test_compressed_rows_match_oracle(spt, fam, N, eps):
 
 
 # ------------------------------------------------------------------ F64 against the oracle
-def _check_f64(spt, fam, N, eps, X, tol=1e-12, own_nodes=False, **kw):
-    """ROW mode unless kw says otherwise; the oracle's nodes unless own_nodes."""
+def _check_f64(spt, fam, N, eps, X, tol=1e-12, own_nodes=False, tuning=None, **kw):
+    """ROW mode unless kw says otherwise; the oracle's nodes unless own_nodes;
+    launch choices `tuning` (spt_plan_set_tuning fields) if given."""
     kw.setdefault("mode", spt.MODE_ROW)
     f = oracle_family(fam, N, kw.get("alpha", 0.0), kw.get("beta", 0.0))
     nodes = None if own_nodes else f.nodes()
     p = spt.Plan(fam, N, eps, nodes=nodes, **kw).precompute()
+    if tuning:
+        p.set_tuning(**tuning)
     Y = run(spt, p, X, spt.F64)
     C = oracle_compressed(fam, N, eps, kw.get("eps2", 1e-2), kw.get("min_block", 32),
                           kw.get("alpha", 0.0), kw.get("beta", 0.0), kw.get("unweighted", False),
@@ -515,6 +518,29 @@ def test_parity_halves_fp64(spt, fam, N, R, kw):
     X = workloads.rhs("normal", R, N, 23)
     p, _ = _check_f64(spt, fam, N, 1e-7, X, executor=spt.EXECUTOR_STAGED, **kw)
     assert p.blocks()[0][0] // 2 >= 4096
+
+
+@pytest.mark.parametrize("fam,N,eps,R,kw", [
+    ("legendre", 8192, 1e-7, 13, {}), ("chebyshev_t", 5000, 1e-9, 8, {})])
+def test_eight_way_split(spt, fam, N, eps, R, kw):
+    """A block's real transform split by output residue mod 8, five workgroups
+    per right-hand side (Legendre 8192: P = 5120 with three shorter blocks in
+    the same launch; Chebyshev 5000, Algorithm 1: one block, P = 4320): F64
+    parity with the oracle; F32 and split-bf16 against F64 and against the
+    default parity split."""
+    say("eight-way split", fam, N, eps, R, kw)
+    X = workloads.rhs("normal", R, N, 27)
+    p, Y64 = _check_f64(spt, fam, N, eps, X, executor=spt.EXECUTOR_STAGED,
+                        tuning=dict(fft_half=spt.FFT_EIGHT), **kw)
+    assert p.blocks()[0][0] // 2 >= 4096 and (p.blocks()[0][0] // 2) % 4 == 0
+    for prec in (spt.F32, spt.SPLIT_BF16):
+        p.set_tuning(fft_half=spt.FFT_EIGHT)
+        Ye = run(spt, p, X, prec)
+        p.set_tuning(fft_half=spt.TUNE_ON)
+        Yh = run(spt, p, X, prec)
+        e, eh = rel_rows(Ye, Y64), rel_rows(Ye, Yh)
+        say("  prec %d: vs F64 %.3e, vs parity split %.3e" % (prec, e, eh))
+        assert e <= REDUCED_TOL and eh <= REDUCED_TOL
 
 
 @pytest.mark.parametrize("prec", [0, 1, 2], ids=["f64", "f32", "split_bf16"])
