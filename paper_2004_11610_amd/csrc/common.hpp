@@ -65,6 +65,37 @@ __device__ __forceinline__ double2 gload(const double2* p) {
   return double2{v.x, v.y};
 }
 
+// A raw buffer over `bytes` bytes at p (gfx9 buffer resource, 32-bit
+// elements): a load whose offset is at or past the end, a negative offset
+// included (it wraps past the end), returns zeros.  Offsets are in bytes and
+// all go in the lane's offset register, which is what the range check sees.
+typedef __amdgpu_buffer_rsrc_t buf_t;
+__device__ __forceinline__ buf_t buf_rsrc(const void* p, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ float buf_f32(buf_t r, int off) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+__device__ __forceinline__ float2 buf_f32x2(buf_t r, int off) {
+  typedef float v2 __attribute__((ext_vector_type(2)));
+  const v2 v = __builtin_bit_cast(v2, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+  return float2{v.x, v.y};
+}
+__device__ __forceinline__ double buf_f64(buf_t r, int off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+__device__ __forceinline__ double2 buf_f64x2(buf_t r, int off) {
+  typedef double v2 __attribute__((ext_vector_type(2)));
+  const v2 v = __builtin_bit_cast(v2, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+  return double2{v.x, v.y};
+}
+// typed forms: buf_ld<float>, buf_ld<float2>, buf_ld<double>, buf_ld<double2>
+template <typename V> __device__ __forceinline__ V buf_ld(buf_t r, int off);
+template <> __device__ __forceinline__ float buf_ld<float>(buf_t r, int off) { return buf_f32(r, off); }
+template <> __device__ __forceinline__ float2 buf_ld<float2>(buf_t r, int off) { return buf_f32x2(r, off); }
+template <> __device__ __forceinline__ double buf_ld<double>(buf_t r, int off) { return buf_f64(r, off); }
+template <> __device__ __forceinline__ double2 buf_ld<double2>(buf_t r, int off) { return buf_f64x2(r, off); }
+
 template <typename T> struct cplx;
 template <> struct cplx<double> { using type = double2; };
 template <> struct cplx<float> { using type = float2; };

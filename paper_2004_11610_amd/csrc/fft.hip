@@ -116,6 +116,35 @@ __device__ __forceinline__ cplx_t<T> point_pair(const TI* __restrict__ x, const 
   }
 }
 
+// The retained columns [c_lo, c_hi) of one row of X and of the window
+// reciprocals as raw buffers: a load outside them returns zeros, so that
+// v_c = x_(c + m_off) / w_c needs neither an index clamp nor a select, and
+// every address is one 32-bit offset.
+template <typename T, typename TI>
+struct RowSrc {
+  buf_t xr, wr;
+  int c_lo;
+  __device__ __forceinline__ RowSrc(const TI* x, const T* winv, int c_lo_, int c_hi, int m_off)
+      : c_lo(c_lo_) {
+    const uint32_t n = c_hi > c_lo_ ? (uint32_t)(c_hi - c_lo_) : 0u;
+    xr = buf_rsrc(x + m_off + c_lo_, n * (uint32_t)sizeof(TI));
+    wr = buf_rsrc(winv + c_lo_, n * (uint32_t)sizeof(T));
+  }
+  // v_c
+  __device__ __forceinline__ T one(int c) const {
+    const int o = c - c_lo;
+    return T(buf_ld<TI>(xr, o * (int)sizeof(TI))) * buf_ld<T>(wr, o * (int)sizeof(T));
+  }
+  // (v_c, v_(c+1)) for an even c, when m_off, c_lo and c_hi are even (a pair
+  // lies wholly inside or outside the retained columns)
+  __device__ __forceinline__ cplx_t<T> pair(int c) const {
+    const int o = c - c_lo;
+    const cplx_t<TI> xv = buf_ld<cplx_t<TI>>(xr, o * (int)sizeof(TI));
+    const cplx_t<T> wv = buf_ld<cplx_t<T>>(wr, o * (int)sizeof(T));
+    return cplx_t<T>{T(xv.x) * wv.x, T(xv.y) * wv.y};
+  }
+};
+
 // Every block of a plan and every right-hand side in one grid: workgroup
 // (x, y) takes block y (blocks sorted by decreasing length) and either one
 // parity half of right-hand side x mod R (FftDesc::half), or the right-hand
@@ -165,6 +194,12 @@ __device__ __forceinline__ void fft_multi_body(const FftDesc<T>* __restrict__ d,
 #pragma unroll
       for (int e = 0; e < ROUND; ++e) {
         const int u = tid + (h + e) * nt;
+        if constexpr (VEC && !BATCH) {
+          // one row: points past the transform read past c_hi (zeros)
+          const RowSrc<T, TI> src(X + (int64_t)r0 * N, winv, c_lo, c_hi, m_off);
+          v[e] = src.pair(2 * u);
+          continue;
+        }
         const int uu = min(u, pts - 1);
         const int j = uu >> lb, t = uu & tmask;
         const TI* __restrict__ x = X + (int64_t)(r0 + (BATCH ? min(t, cnt - 1) : 0)) * N;
@@ -264,11 +299,22 @@ __device__ __forceinline__ void fft_half_body(const FftDesc<T>* __restrict__ d,
   constexpr int ROUND = (sizeof(T) == 4 || EI <= FFT_EPT / 2) ? EI : FFT_EPT / 2;
   auto input = [&](auto vtag) {
     constexpr bool VEC = decltype(vtag)::value;
+    // VEC: buffer loads, zeros outside the retained columns and past the end
+    // of post (points n >= H are not stored)
+    const RowSrc<T, TI> src(x, winv, c_lo, c_hi, m_off);
+    const buf_t postr = buf_rsrc(post, (uint32_t)(P + 1) * (uint32_t)sizeof(C));
 #pragma unroll
     for (int h = 0; h < EI; h += ROUND) {
       C y[ROUND];
 #pragma unroll
       for (int e = 0; e < ROUND; ++e) {
+        if constexpr (VEC) {
+          const int n = tid + (h + e) * nt;
+          const C a = src.pair(2 * n);
+          const C b = src.pair(2 * n + P);
+          y[e] = par ? cmul(csub(a, b), buf_ld<C>(postr, 2 * n * (int)sizeof(C))) : cadd(a, b);
+          continue;
+        }
         const int n = min(tid + (h + e) * nt, H - 1);
         const C a = point_pair<VEC>(x, winv, 2 * n, c_lo, c_hi, m_off);
         const C b = point_pair<VEC>(x, winv, 2 * n + P, c_lo, c_hi, m_off);
@@ -365,20 +411,15 @@ __device__ __forceinline__ void fft_rdif_body(const FftDesc<T>* __restrict__ d,
   // E1 and the radix-8 step: y_n without the factor W^(np), in rounds of RD
   // points (16 loads each)
   constexpr int RD = 2;
+  const RowSrc<T, TI> src(x, winv, c_lo, c_hi, m_off);  // zeros outside [c_lo, c_hi)
 #pragma unroll
   for (int e0 = 0; e0 < EI; e0 += RD) {
-    TI xv[RD][8];
-    T wv[RD][8];
+    T v[RD][8];
 #pragma unroll
     for (int e = 0; e < RD; ++e) {
-      const int n = min(tid + (e0 + e) * nt, M - 1);
+      const int n = tid + (e0 + e) * nt;
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int c = n + q * M;
-        const int cc = c >= c_lo && c < c_hi ? c : c_lo;
-        xv[e][q] = gload(x + m_off + cc);
-        wv[e][q] = gload(winv + cc);
-      }
+      for (int q = 0; q < 8; ++q) v[e][q] = src.one(n + q * M);
     }
     if (e0 == 0) ts.store(ltab, tid, nt);
 #pragma unroll
@@ -387,10 +428,8 @@ __device__ __forceinline__ void fft_rdif_body(const FftDesc<T>* __restrict__ d,
       T re = T(0), im = T(0);
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
-        const int c = n + q * M;
-        const T v = c >= c_lo && c < c_hi ? T(xv[e][q]) * wv[e][q] : T(0);
-        re += v * co[q];
-        im += v * si[q];
+        re += v[e][q] * co[q];
+        im += v[e][q] * si[q];
       }
       if (e0 + e < EI && n < M) lds[n] = C{re, im};
     }
