@@ -198,6 +198,8 @@ enum {
   SPT_PRODUCT_TILE = 1,     /* per row tile, spectra read from memory             */
   SPT_PRODUCT_WINDOW = 2,   /* the default's choice, asked for explicitly         */
   SPT_PRODUCT_CHUNKED = 3,  /* windows through LDS in chunks of 32 columns        */
+  SPT_PRODUCT_WINDOW_2W = 4,  /* windowed over 64 right-hand sides, two waves per row
+                                 tile (32 right-hand sides each, 8 waves)         */
   SPT_TUNE_DEFAULT = 0, SPT_TUNE_OFF = 1, SPT_TUNE_ON = 2,
   SPT_FFT_EIGHT = 3         /* fft_half: split by output residue mod 8 instead      */
 };

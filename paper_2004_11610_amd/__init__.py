@@ -17,7 +17,7 @@ CEXP, LAGUERRE_SPECTRAL = 8, 9  # complex generators
 F64, F32, SPLIT_BF16 = 0, 1, 2
 MODE_AUTO, MODE_ROW, MODE_DIRECT = 0, 1, 3
 FFT_AUTO, FFT_F32, FFT_F64 = 0, 1, 2
-PRODUCT_DEFAULT, PRODUCT_TILE, PRODUCT_WINDOW, PRODUCT_CHUNKED = 0, 1, 2, 3
+PRODUCT_DEFAULT, PRODUCT_TILE, PRODUCT_WINDOW, PRODUCT_CHUNKED, PRODUCT_WINDOW_2W = 0, 1, 2, 3, 4
 TUNE_DEFAULT, TUNE_OFF, TUNE_ON, FFT_EIGHT = 0, 1, 2, 3
 TUNING_FIELDS = ("product", "window_rhs", "fft_batch", "fft_half", "inv_four")
 EXECUTOR_AUTO, EXECUTOR_STAGED, EXECUTOR_PERSISTENT = 0, 1, 2

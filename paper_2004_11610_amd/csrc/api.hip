@@ -229,6 +229,7 @@ struct spt_plan {
   size_t win_lds = 0;
   int64_t win_cols = 0;
   int win_rg = 4;                  // groups of 16 right-hand sides per workgroup
+  int win_waves = 1;               // waves per row tile of the windowed product
   int win_xlds = 0, win_tpad = 0;  // x of the direct tail in LDS (16-byte units), its pitch
   bool win_ok = false;
   bool win_chunked = false;  // the windows pass through LDS in chunks (too wide to fit)
@@ -1156,6 +1157,11 @@ void build_windows(spt_plan_t plan, hipStream_t s) {
   int rg = 2 * layout(4, nullptr, nullptr).second <= lds_max ? 4 : 2;
   if (plan->tune.window_rhs == 64) rg = 4;
   if (plan->tune.window_rhs == 32) rg = 2;
+  plan->win_waves = 1;
+  if (plan->tune.product == SPT_PRODUCT_WINDOW_2W) {
+    rg = 4;
+    plan->win_waves = 2;
+  }
   std::vector<WinMeta> win((size_t)plan->n_groups * nblk);
   int64_t cols = 0;
   const auto lay = layout(rg, &win, &cols);
@@ -1632,7 +1638,8 @@ void execute_staged_t(spt_plan_t plan, const T* X, T* Y, int64_t R, int prec, hi
           launch_spmm_chunk(pa, plan->winmeta.as<WinMeta>(), plan->n_groups, plan->win_tpad, st);
         else if (plan->win_ok && 12.0 * (double)R * (double)plan->zper4 < 4294967296.0)
           launch_spmm_window(pa, plan->winmeta.as<WinMeta>(), plan->n_groups, plan->win_rg,
-                             plan->win_xlds, plan->win_tpad, plan->win_lds, st);
+                             plan->win_waves, plan->win_xlds, plan->win_tpad, plan->win_lds,
+                             st);
         else
           launch_spmm_presplit(pa, st);
         return;
@@ -2266,7 +2273,7 @@ void set_exec_wait(spt_plan_t plan, uint32_t ticks) {
 
 // ---------------------------------------------------------------- launch choices
 void check_tuning(const spt_tuning& t) {
-  if (t.product < SPT_PRODUCT_DEFAULT || t.product > SPT_PRODUCT_CHUNKED)
+  if (t.product < SPT_PRODUCT_DEFAULT || t.product > SPT_PRODUCT_WINDOW_2W)
     throw Error(SPT_E_INVALID_ARG, "unknown product choice");
   if (t.window_rhs != 0 && t.window_rhs != 32 && t.window_rhs != 64)
     throw Error(SPT_E_INVALID_ARG, "window_rhs must be 0, 32 or 64");
@@ -2432,7 +2439,8 @@ void autotune_t(spt_plan_t plan, int64_t R, int prec, hipStream_t s, spt_tuning&
   }
   std::vector<spt_tuning> cand;
   const std::vector<int> prods = split ? std::vector<int>{SPT_PRODUCT_TILE, SPT_PRODUCT_WINDOW,
-                                                          SPT_PRODUCT_CHUNKED}
+                                                          SPT_PRODUCT_CHUNKED,
+                                                          SPT_PRODUCT_WINDOW_2W}
                                        : std::vector<int>{SPT_PRODUCT_DEFAULT};
   for (int pr : prods)
     for (int rhs : (pr == SPT_PRODUCT_WINDOW ? std::vector<int>{32, 64} : std::vector<int>{0}))

@@ -346,8 +346,9 @@ void launch_spmm_chunk_f64(const SpmmArgs<double>& a, const WinMeta* win, int n_
                            hipStream_t s);
 void launch_spmm_chunk(const SpmmSplitArgs& a, const WinMeta* win, int n_groups, int tpad,
                        hipStream_t s);
+// waves: per row tile (2: 8-wave workgroups over 64 right-hand sides, rg 4)
 void launch_spmm_window(const SpmmSplitArgs& a, const WinMeta* win, int n_groups, int rg,
-                        int xlds, int tpad, size_t lds_bytes, hipStream_t s);
+                        int waves, int xlds, int tpad, size_t lds_bytes, hipStream_t s);
 void init_spmm_kernels(size_t max_lds);
 
 // Products of several plans in one launch: items (plan, row tile or -1, first

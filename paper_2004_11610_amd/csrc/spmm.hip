@@ -267,21 +267,26 @@ __device__ __forceinline__ void mma6xg(const bf16x8* A, const bf16x8 (*B)[3], f3
   for (int q = 0; q < RG; ++q) acc[q] += t[q];
 }
 
-// RG: groups of 16 right-hand sides per workgroup (4 or 2); the windows hold
-// 3 * 16 RG rows.
-template <int RG>
-__global__ __launch_bounds__(256) void spmm_window_kernel(SpmmSplitArgs args,
-                                                          const WinMeta* __restrict__ win,
-                                                          int n_groups, int xlds, int tpad) {
+// RG: groups of 16 right-hand sides per wave (4 or 2); WS: waves per row tile
+// (1, or 2 sharing the tile's matrix pieces, each with its own RG groups of
+// right-hand sides: 8 waves); the windows hold 3 * 16 RG WS rows.
+template <int RG, int WS>
+__global__ __launch_bounds__(256 * WS) void spmm_window_kernel(SpmmSplitArgs args,
+                                                               const WinMeta* __restrict__ win,
+                                                               int n_groups, int xlds, int tpad) {
   extern __shared__ __align__(16) uint4 zl[];
   const int grp = xcd_tile(blockIdx.x, n_groups);
-  constexpr int NR = 16 * RG;  // right-hand sides of the workgroup
+  constexpr int NR = 16 * RG * WS;  // right-hand sides of the workgroup
+  constexpr int NW = WIN_TILES * WS;  // waves
   const int r0 = blockIdx.y * NR;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   const int m = lane & 15, g = lane >> 4;
   const int nblk = args.nblk;
-  const int tile = grp * WIN_TILES + wave;
+  // wave: row tile wave % WIN_TILES, right-hand sides rw .. rw + 16 RG - 1 of
+  // the workgroup's
+  const int rw = (wave / WIN_TILES) * 16 * RG;
+  const int tile = grp * WIN_TILES + wave % WIN_TILES;
   const bool has_tile = tile < args.n_tiles;  // wave-uniform
   const bf16x8 zero8 = bf16x8{};
 
@@ -333,7 +338,7 @@ __global__ __launch_bounds__(256) void spmm_window_kernel(SpmmSplitArgs args,
     // byte offsets from the window's first column fit 32 bits (checked on the host)
     const char* __restrict__ zw = reinterpret_cast<const char*>(
         args.Zs + (int64_t)args.R * lane_i64(zoff_l, bw) + lane_i32(wk0_l, bw));
-    for (int c = wave; c * 64 < units; c += 4) {
+    for (int c = wave; c * 64 < units; c += NW) {
       const uint32_t u = (uint32_t)(c * 64 + lane);
       const uint32_t q = __umulhi(u, magic);
       const uint32_t cg = min(u - q * (uint32_t)pitch, (uint32_t)w4 - 1u);
@@ -347,7 +352,7 @@ __global__ __launch_bounds__(256) void spmm_window_kernel(SpmmSplitArgs args,
   // xl + i * tpad (tpad = 32 * tail steps + 4 floats, NR * tpad a multiple of
   // 64); columns past the tail repeat its last one and are never used
   float* __restrict__ xl = reinterpret_cast<float*>(zl + xlds);
-  for (int c = wave; c * 64 < NR * tpad; c += 4) {
+  for (int c = wave; c * 64 < NR * tpad; c += NW) {
     const int u = c * 64 + lane;
     const int i = u / tpad, mm = u - i * tpad;
     const float* src = args.X + (int64_t)min(r0 + i, args.R - 1) * args.N + min(mm, args.tail - 1);
@@ -413,7 +418,7 @@ __global__ __launch_bounds__(256) void spmm_window_kernel(SpmmSplitArgs args,
         for (int q = 0; q < RG; ++q)
 #pragma unroll
           for (int p = 0; p < 3; ++p)
-            Z[q][p] = __builtin_bit_cast(bf16x8, zr[(p * NR + 16 * q) * pitch]);
+            Z[q][p] = __builtin_bit_cast(bf16x8, zr[(p * NR + rw + 16 * q) * pitch]);
         mma6xg<RG>(A[i], Z, acc);
       }
     }
@@ -427,7 +432,8 @@ __global__ __launch_bounds__(256) void spmm_window_kernel(SpmmSplitArgs args,
     bf16x8 B[RG][3];
 #pragma unroll
     for (int q = 0; q < RG; ++q) {
-      const float4* xq = reinterpret_cast<const float4*>(xl + (16 * q + m) * tpad + 32 * st + 8 * g);
+      const float4* xq =
+          reinterpret_cast<const float4*>(xl + (rw + 16 * q + m) * tpad + 32 * st + 8 * g);
       const float4 lo = xq[0], hi = xq[1];
       const float v[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
       f32x8 xv;
@@ -440,10 +446,10 @@ __global__ __launch_bounds__(256) void spmm_window_kernel(SpmmSplitArgs args,
     mma6xg<RG>(TA, B, acc);
   }
 
-  // 5. y: lane (m, g) holds rows 4g .. 4g+3 of right-hand side r0 + 16 q + m
+  // 5. y: lane (m, g) holds rows 4g .. 4g+3 of right-hand side r0 + rw + 16 q + m
 #pragma unroll
   for (int q = 0; q < RG; ++q) {
-    const int rhs = r0 + 16 * q + m;
+    const int rhs = r0 + rw + 16 * q + m;
     if (rhs < args.R) {
       float* __restrict__ y = args.Y + (int64_t)rhs * args.N + n0;
 #pragma unroll
@@ -1152,12 +1158,15 @@ void launch_spmm_chunk(const SpmmSplitArgs& a, const WinMeta* win, int n_groups,
 }
 
 void launch_spmm_window(const SpmmSplitArgs& a, const WinMeta* win, int n_groups, int rg,
-                        int xlds, int tpad, size_t lds_bytes, hipStream_t s) {
-  if (rg == 4)
-    hipLaunchKernelGGL(spmm_window_kernel<4>, dim3(n_groups, (a.R + 63) / 64), dim3(256),
+                        int waves, int xlds, int tpad, size_t lds_bytes, hipStream_t s) {
+  if (rg == 4 && waves == 2)
+    hipLaunchKernelGGL((spmm_window_kernel<2, 2>), dim3(n_groups, (a.R + 63) / 64), dim3(512),
+                       lds_bytes, s, a, win, n_groups, xlds, tpad);
+  else if (rg == 4)
+    hipLaunchKernelGGL((spmm_window_kernel<4, 1>), dim3(n_groups, (a.R + 63) / 64), dim3(256),
                        lds_bytes, s, a, win, n_groups, xlds, tpad);
   else
-    hipLaunchKernelGGL(spmm_window_kernel<2>, dim3(n_groups, (a.R + 31) / 32), dim3(256),
+    hipLaunchKernelGGL((spmm_window_kernel<2, 1>), dim3(n_groups, (a.R + 31) / 32), dim3(256),
                        lds_bytes, s, a, win, n_groups, xlds, tpad);
   SPT_HIP(hipGetLastError());
 }
@@ -1169,9 +1178,11 @@ void init_spmm_kernels(size_t max_lds) {
   SPT_HIP(hipGetDevice(&dev));
   for (int d : done)
     if (d == dev) return;
-  SPT_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(spmm_window_kernel<4>),
+  SPT_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(spmm_window_kernel<4, 1>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_lds));
-  SPT_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(spmm_window_kernel<2>),
+  SPT_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(spmm_window_kernel<2, 1>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_lds));
+  SPT_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(spmm_window_kernel<2, 2>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_lds));
   SPT_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(spmm_chunk_kernel),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_lds));

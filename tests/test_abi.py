@@ -207,7 +207,7 @@ def test_tuning_arguments():
                           "inv_four": 0}
     p.set_tuning(product=spt.PRODUCT_CHUNKED, fft_batch=2)   # before precompute: host only
     assert p.tuning()["product"] == 3 and p.tuning()["fft_batch"] == 2
-    for bad in (dict(product=4), dict(window_rhs=48), dict(fft_batch=3), dict(fft_half=4)):
+    for bad in (dict(product=5), dict(window_rhs=48), dict(fft_batch=3), dict(fft_half=4)):
         with pytest.raises(spt.SptError) as e:
             p.set_tuning(**bad)
         assert e.value.code == -1

@@ -790,7 +790,7 @@ def test_one_plan_on_several_streams(spt):
 
 
 
-@pytest.mark.parametrize("rg", ["4", "2"])
+@pytest.mark.parametrize("rg", ["4", "2", "2w"])
 @pytest.mark.parametrize("fam,N,R,kw", [
     ("legendre", 16384, 64, {}), ("legendre", 1000, 1, {}), ("legendre", 1000, 70, {}),
     ("chebyshev_t", 3000, 130, {}), ("laguerre_fn", 5000, 64, {}),
@@ -802,9 +802,12 @@ def test_windowed_product_matches_per_tile(spt, fam, N, R, kw, rg):
     for LDS, in chunks of 32 columns) takes the same steps in the same order as
     the per-tile product, so both give the same bits (up to the sign of an
     exact zero); ragged tile groups (N not a multiple of 64), right-hand-side
-    chunks with fewer columns than a workgroup's and several chunks."""
+    chunks with fewer columns than a workgroup's and several chunks.  rg "2w":
+    windows of 64 right-hand sides with two waves per row tile."""
     say("windowed product", fam, N, R, kw, "rg", rg)
-    p = spt.Plan(fam, N, 1e-7, **kw).set_tuning(window_rhs=16 * int(rg)).precompute()
+    tune = (dict(product=spt.PRODUCT_WINDOW_2W) if rg == "2w"
+            else dict(window_rhs=16 * int(rg)))
+    p = spt.Plan(fam, N, 1e-7, **kw).set_tuning(**tune).precompute()
     info = p.info()
     q = spt.Plan(fam, N, 1e-7, **kw).set_tuning(product=spt.PRODUCT_TILE).precompute()
     assert q.info()["window_lds"] == 0
