@@ -81,6 +81,11 @@ __device__ __forceinline__ float2 buf_f32x2(buf_t r, int off) {
   const v2 v = __builtin_bit_cast(v2, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
   return float2{v.x, v.y};
 }
+__device__ __forceinline__ float4 buf_f32x4(buf_t r, int off) {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  const v4 v = __builtin_bit_cast(v4, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+  return float4{v.x, v.y, v.z, v.w};
+}
 __device__ __forceinline__ double buf_f64(buf_t r, int off) {
   return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
 }

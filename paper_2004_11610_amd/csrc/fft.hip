@@ -143,6 +143,14 @@ struct RowSrc {
     const cplx_t<T> wv = buf_ld<cplx_t<T>>(wr, o * (int)sizeof(T));
     return cplx_t<T>{T(xv.x) * wv.x, T(xv.y) * wv.y};
   }
+  // float32: (v_c, v_(c+1)) and (v_(c+2), v_(c+3)) for c a multiple of 4,
+  // when m_off, c_lo and c_hi are too (16-byte loads)
+  __device__ __forceinline__ void quad(int c, float2& lo, float2& hi) const {
+    const int o = (c - c_lo) * 4;
+    const float4 xv = buf_f32x4(xr, o), wv = buf_f32x4(wr, o);
+    lo = float2{xv.x * wv.x, xv.y * wv.y};
+    hi = float2{xv.z * wv.z, xv.w * wv.w};
+  }
 };
 
 // Every block of a plan and every right-hand side in one grid: workgroup
@@ -328,7 +336,47 @@ __device__ __forceinline__ void fft_half_body(const FftDesc<T>* __restrict__ d,
       }
     }
   };
-  if (((m_off | (int)N | c_lo | c_hi) & 1) == 0)
+  // float32 with columns aligned to 4: two points per thread and load (16
+  // bytes of x and of 1/w from each half of the row), in two rounds
+  auto input_quads = [&]() {
+    if constexpr (sizeof(T) == 4 && sizeof(TI) == 4) {
+      constexpr int EH = (EI + 1) / 2;  // pairs of points per thread
+      constexpr int RQ = (EH + 1) / 2;
+      const RowSrc<T, TI> src(x, winv, c_lo, c_hi, m_off);
+      const buf_t postr = buf_rsrc(post, (uint32_t)(P + 1) * (uint32_t)sizeof(C));
+#pragma unroll
+      for (int h = 0; h < EH; h += RQ) {
+        C y[RQ][2];
+#pragma unroll
+        for (int e = 0; e < RQ; ++e) {
+          const int j = tid + (h + e) * nt;  // points 2j and 2j + 1
+          C a0, a1, b0, b1;
+          src.quad(4 * j, a0, a1);
+          src.quad(4 * j + P, b0, b1);
+          if (par) {
+            const C w0 = buf_ld<C>(postr, 4 * j * (int)sizeof(C));
+            const C w1 = buf_ld<C>(postr, (4 * j + 2) * (int)sizeof(C));
+            y[e][0] = cmul(csub(a0, b0), w0);
+            y[e][1] = cmul(csub(a1, b1), w1);
+          } else {
+            y[e][0] = cadd(a0, b0);
+            y[e][1] = cadd(a1, b1);
+          }
+        }
+        if (h == 0) ts.store(ltab, tid, nt);
+#pragma unroll
+        for (int e = 0; e < RQ; ++e) {
+          const int j = tid + (h + e) * nt;
+          if (h + e < EH && 2 * j < H)
+            *reinterpret_cast<float4*>(lds + 2 * j) =
+                float4{y[e][0].x, y[e][0].y, y[e][1].x, y[e][1].y};
+        }
+      }
+    }
+  };
+  if (sizeof(T) == 4 && sizeof(TI) == 4 && ((m_off | (int)N | c_lo | c_hi) & 3) == 0)
+    input_quads();
+  else if (((m_off | (int)N | c_lo | c_hi) & 1) == 0)
     input(std::true_type{});
   else
     input(std::false_type{});
