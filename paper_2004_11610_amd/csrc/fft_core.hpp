@@ -9,8 +9,7 @@
 // float64 tables of 128 + Pt/128 entries for the block's length Pt (w^q =
 // lo[q % 128] hi[q / 128]; a sub-transform of length P < Pt uses index
 // q * (Pt / P)); a butterfly forms w^jm once and its powers in float64, for
-// every precision.  stockham_pass_tab reads every w^(jm r) from a per-pass
-// table in the working precision instead.  SIGN -1 uses the conjugates.
+// every precision.  SIGN -1 uses the conjugates.
 #pragma once
 
 #include "common.hpp"
@@ -205,83 +204,6 @@ __device__ __forceinline__ void run_fft(C* lds, int P, int lb, int npass, const 
       case 5: stockham_pass<SIGN, 5, BATCH, EPT>(lds, P, lb, Ns, tw, tmul, tid, nt, active); break;
       default: stockham_pass<SIGN, 3, BATCH, EPT>(lds, P, lb, Ns, tw, tmul, tid, nt, active); break;
     }
-    Ns *= R;
-  }
-}
-
-// The same pass over 2^lb interleaved transforms (point j of transform t at
-// lds[(j << lb) + t]), with the twiddles w^(jm r) (r = 1 .. R-1) read from the
-// pass's table tab[(r-1) Ns + jm] in the working precision (a copy in LDS).
-// float32: the table reads go out with the point reads, before the barrier;
-// float64 would read them after it (registers).
-template <int SIGN, int R, bool BATCH, int EPT, typename C>
-__device__ __forceinline__ void stockham_pass_tab(C* lds, int P, int lb_, int Ns,
-                                                  const C* __restrict__ tab, int tid, int nt,
-                                                  bool active) {
-  constexpr int MAXB = (EPT + R - 1) / R;
-  const int lb = BATCH ? lb_ : 0;
-  constexpr bool EARLY = sizeof(C) == 8;
-  const int nb = P / R;
-  const int nbt = nb << lb;
-  const int tmask = (1 << lb) - 1;
-  C v[MAXB][R];
-  C w[MAXB][R - 1];
-#pragma unroll
-  for (int b = 0; b < MAXB; ++b) {
-    const int u = tid + b * nt;
-    if (active && u < nbt) {
-      const int j = u >> lb, t = u & tmask;
-#pragma unroll
-      for (int r = 0; r < R; ++r) v[b][r] = lds[((j + r * nb) << lb) + t];
-      if (EARLY && Ns > 1) {
-        const int jm = j % Ns;
-#pragma unroll
-        for (int r = 1; r < R; ++r) w[b][r - 1] = tab[(r - 1) * Ns + jm];
-      }
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int b = 0; b < MAXB; ++b) {
-    const int u = tid + b * nt;
-    if (active && u < nbt) {
-      const int j = u >> lb, t = u & tmask;
-      const int jm = j % Ns;
-      if (Ns > 1) {
-#pragma unroll
-        for (int r = 1; r < R; ++r) {
-          C tw = EARLY ? w[b][r - 1] : tab[(r - 1) * Ns + jm];
-          if (SIGN < 0) tw.y = -tw.y;
-          v[b][r] = cmul(v[b][r], tw);
-        }
-      }
-      Dft<SIGN, R, C>::run(v[b]);
-      const int base = (j - jm) * R + jm;
-#pragma unroll
-      for (int r = 0; r < R; ++r) lds[((base + r * Ns) << lb) + t] = v[b][r];
-    }
-  }
-  __syncthreads();
-}
-
-// all passes of 2^lb interleaved transforms with table twiddles (tab: the
-// FftDesc layout); requires 2^lb * P <= EPT * nt; BATCH == false: one
-// transform (lb is 0)
-template <int SIGN, bool BATCH, int EPT = FFT_EPT, typename C>
-__device__ __forceinline__ void run_fft_tab(C* lds, int P, int lb, int npass, const int* radix,
-                                            const C* __restrict__ tab, int tid, int nt,
-                                            bool active) {
-  int Ns = 1;
-  for (int p = 0; p < npass; ++p) {
-    const int R = radix[p];
-    switch (R) {
-      case 8: stockham_pass_tab<SIGN, 8, BATCH, EPT>(lds, P, lb, Ns, tab, tid, nt, active); break;
-      case 4: stockham_pass_tab<SIGN, 4, BATCH, EPT>(lds, P, lb, Ns, tab, tid, nt, active); break;
-      case 2: stockham_pass_tab<SIGN, 2, BATCH, EPT>(lds, P, lb, Ns, tab, tid, nt, active); break;
-      case 5: stockham_pass_tab<SIGN, 5, BATCH, EPT>(lds, P, lb, Ns, tab, tid, nt, active); break;
-      default: stockham_pass_tab<SIGN, 3, BATCH, EPT>(lds, P, lb, Ns, tab, tid, nt, active); break;
-    }
-    tab += (R - 1) * Ns;
     Ns *= R;
   }
 }
