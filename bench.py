@@ -410,7 +410,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": w["name"], "family": "legendre", "N": N, "nrhs": R,
                    "eps1": w["eps"], "eps2": info["eps2"], "blocks": [b[0] for b in plan.blocks()],
-                   "tail": info["tail"], "nnz": info["nnz"], "parallelism": "single-gpu",
+                   "tail": info["tail"], "nnz": info["nnz"], "stored": info["stored"],
+                   "parallelism": "single-gpu",
                    "reduced_fft_f64": info["reduced_fft_f64"],
                    "reduced_fft_f32_err": info["reduced_fft_f32_err"], "tuning": tuning},
         "streams": args.streams,
