@@ -1670,7 +1670,11 @@ void execute_staged_t(spt_plan_t plan, const T* X, T* Y, int64_t R, int prec, hi
   };
 
   if (fused) {
-    staged(SPT_STAGE_FFT, s, [&] { fft_fused(0, nblk, s); });
+    // one launch per FFT_GRID_MAX blocks (a plan has more only for eps2 near 1)
+    staged(SPT_STAGE_FFT, s, [&] {
+      for (int b0 = 0; b0 < nblk; b0 += FFT_GRID_MAX)
+        fft_fused(b0, std::min(FFT_GRID_MAX, nblk - b0), s);
+    });
   } else if (nblk > 0) {
     if (!own_ws)
       throw Error(SPT_E_UNSUPPORTED, "a block's FFT exceeds one workgroup: the caller's workspace "
