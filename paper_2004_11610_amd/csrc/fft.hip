@@ -222,7 +222,9 @@ __device__ __forceinline__ void fft_multi_body(const FftDesc<T>* __restrict__ d,
       }
     }
   };
-  if (((m_off | (int)N | c_lo | c_hi) & 1) == 0)
+  // pairs: columns and the base of X aligned to two elements
+  const int xa = (int)((uintptr_t)X / sizeof(TI));
+  if (((m_off | (int)N | c_lo | c_hi | xa) & 1) == 0)
     input(std::true_type{});
   else
     input(std::false_type{});
@@ -374,9 +376,11 @@ __device__ __forceinline__ void fft_half_body(const FftDesc<T>* __restrict__ d,
       }
     }
   };
-  if (sizeof(T) == 4 && sizeof(TI) == 4 && ((m_off | (int)N | c_lo | c_hi) & 3) == 0)
+  // quads and pairs: columns and the base of X aligned to four and two elements
+  const int xa = (int)((uintptr_t)X / sizeof(TI));
+  if (sizeof(T) == 4 && sizeof(TI) == 4 && ((m_off | (int)N | c_lo | c_hi | xa) & 3) == 0)
     input_quads();
-  else if (((m_off | (int)N | c_lo | c_hi) & 1) == 0)
+  else if (((m_off | (int)N | c_lo | c_hi | xa) & 1) == 0)
     input(std::true_type{});
   else
     input(std::false_type{});

@@ -847,3 +847,26 @@ def test_autotuned_plan_keeps_parity(spt, tmp_path):
     again, us2 = q.autotune(R, prec=spt.SPLIT_BF16, cache_path=cache)
     assert again == chosen and us2 == 0.0
     assert np.array_equal(run(spt, q, X, spt.SPLIT_BF16), run(spt, p, X, spt.SPLIT_BF16))
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2], ids=["f64", "f32", "split_bf16"])
+def test_unaligned_input_matches_aligned(spt, prec):
+    """X starting one element past an aligned address (a view into a larger
+    buffer) takes the FFT's scalar loads instead of the paired or 16-byte ones:
+    the same spectra, so the same result up to the product's summation (the
+    same bits here)."""
+    import torch
+    dt = torch.float64 if prec == spt.F64 else torch.float32
+    N, R = 16384, 8
+    say("unaligned X, prec", prec)
+    p = spt.Plan("legendre", N, 1e-7).precompute()
+    Xh = workloads.rhs("normal", R, N, 99)
+    buf = torch.zeros(R * N + 1, dtype=dt, device="cuda")
+    buf[1:].copy_(to_dev(Xh, dt).reshape(-1))
+    Xu = buf[1:].view(R, N)
+    assert Xu.data_ptr() % 8 != 0 or dt == torch.float64
+    ya = to_host(p.execute(to_dev(Xh, dt), prec=prec))
+    yu = to_host(p.execute(Xu, prec=prec))
+    e = rel_rows(yu, ya)
+    say("  rel %.3e" % e)
+    assert e <= (1e-14 if prec == spt.F64 else 1e-7)
