@@ -164,12 +164,17 @@ __device__ __forceinline__ void stockham_pass(C* lds, int P, int lb, int Ns,
   }
   __syncthreads();
   const int stride = P / (Ns * R) * tmul;
+  // j mod Ns by a multiply-high: with m = ceil(2^32 / Ns), umulhi(j, m) =
+  // floor(j / Ns) exactly while j Ns < 2^32 (j and Ns are below P, and a
+  // workgroup's transform has P < 2^16 points); Ns = 1 (m would be 2^32) is
+  // the first pass, whose jm is 0
+  const uint32_t mag = Ns > 1 ? 0xFFFFFFFFu / (uint32_t)Ns + 1u : 0u;
 #pragma unroll
   for (int b = 0; b < MAXB; ++b) {
     const int u = tid + b * nt;
     if (active && u < nbt) {
       const int j = BATCH ? u >> lb : u, t = u & tmask;
-      const int jm = j % Ns;
+      const int jm = Ns > 1 ? j - (int)__umulhi((uint32_t)j, mag) * Ns : 0;
       if (Ns > 1) {
         // w^(jm r) = (w^jm)^r, powers in float64
         double2 t1 = twiddle(tw, jm * stride);
