@@ -18,6 +18,7 @@
 // unpack twiddles exp(+i pi k/P) (k <= P) are a table in the working
 // precision.  SIGN -1 uses the conjugates.
 
+#include <algorithm>
 #include <type_traits>
 
 #include "fft_core.hpp"
@@ -812,6 +813,14 @@ FftPlan make_fft_plan(int P) {
   while (n % 5 == 0) { rad.push_back(5); n /= 5; }
   if (n != 1) throw Error(SPT_E_UNSUPPORTED, "FFT length half " + std::to_string(P) +
                                                  " is not 2^a 3^b 5^c");
+  // a lone radix 2 and a radix 5 become one radix-10 pass (one LDS round trip
+  // fewer)
+  const auto two = std::find(rad.begin(), rad.end(), 2);
+  const auto five = std::find(rad.begin(), rad.end(), 5);
+  if (two != rad.end() && five != rad.end()) {
+    *five = 10;
+    rad.erase(two);
+  }
   if ((int)rad.size() > MAX_PASSES) throw Error(SPT_E_UNSUPPORTED, "too many FFT passes");
   fp.npass = (int)rad.size();
   for (int i = 0; i < fp.npass; ++i) fp.radix[i] = rad[i];

@@ -117,6 +117,31 @@ struct Dft<SIGN, 5, C> {
   }
 };
 
+// radix 10 as two radix-5 DFTs of the even and odd points and one radix-2
+// step: X_k = E_k + w^k O_k, X_(k+5) = E_k - w^k O_k, w = exp(SIGN 2 pi i / 10)
+template <int SIGN, typename C>
+struct Dft<SIGN, 10, C> {
+  __device__ __forceinline__ static void run(C* v) {
+    using T = decltype(v[0].x);
+    const T c[5] = {T(1), T(0.80901699437494742410), T(0.30901699437494742410),
+                    T(-0.30901699437494742410), T(-0.80901699437494742410)};
+    const T sn[5] = {T(0), T(0.58778525229247312917), T(0.95105651629515357212),
+                     T(0.95105651629515357212), T(0.58778525229247312917)};
+    C e[5] = {v[0], v[2], v[4], v[6], v[8]};
+    C o[5] = {v[1], v[3], v[5], v[7], v[9]};
+    Dft<SIGN, 5, C>::run(e);
+    Dft<SIGN, 5, C>::run(o);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      const C t = k == 0 ? o[0]
+                         : C{o[k].x * c[k] - SIGN * o[k].y * sn[k],
+                             o[k].y * c[k] + SIGN * o[k].x * sn[k]};
+      v[k] = cadd(e[k], t);
+      v[k + 5] = csub(e[k], t);
+    }
+  }
+};
+
 // two-level twiddle table of a length P: tw[i] = exp(2 pi i i / P) for
 // i < TW_LO, tw[TW_LO + i] = exp(2 pi i TW_LO i / P) for i <= P / TW_LO
 constexpr int TW_LO_BITS = 7;
@@ -203,6 +228,7 @@ __device__ __forceinline__ void run_fft(C* lds, int P, int lb, int npass, const 
   for (int p = 0; p < npass; ++p) {
     const int R = radix[p];
     switch (R) {
+      case 10: stockham_pass<SIGN, 10, BATCH, EPT>(lds, P, lb, Ns, tw, tmul, tid, nt, active); break;
       case 8: stockham_pass<SIGN, 8, BATCH, EPT>(lds, P, lb, Ns, tw, tmul, tid, nt, active); break;
       case 4: stockham_pass<SIGN, 4, BATCH, EPT>(lds, P, lb, Ns, tw, tmul, tid, nt, active); break;
       case 2: stockham_pass<SIGN, 2, BATCH, EPT>(lds, P, lb, Ns, tw, tmul, tid, nt, active); break;
