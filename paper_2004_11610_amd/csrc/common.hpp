@@ -175,8 +175,8 @@ struct FftGrid {
   int wg0[FFT_GRID_MAX + 1];
 };
 
-// grid: gx x nblk workgroups of `threads`; lds: bytes of the largest
-// workgroup (fused_lds_bytes)
+// grid: the g.wg0[g.nblk] workgroups of `threads` that g assigns to the
+// blocks; lds: bytes of the largest workgroup (fused_lds_bytes)
 template <typename T>
 void launch_exec_fft_multi(const FftDesc<T>* descs, const FftGrid& g, int threads, size_t lds,
                            const T* X, cplx_t<T>* Z, int R, int64_t N, hipStream_t s);

@@ -154,13 +154,13 @@ struct RowSrc {
   }
 };
 
-// Every block of a plan and every right-hand side in one grid: workgroup
-// (x, y) takes block y (blocks sorted by decreasing length) and either one
-// parity half of right-hand side x mod R (FftDesc::half), or the right-hand
-// sides r0 = x 2^lb .. r0 + 2^lb - 1 (lb = FftDesc::lb), their
+// Every block of a plan and every right-hand side in one grid (FftGrid: block
+// b, sorted by decreasing length, owns workgroups wg0[b] .. wg0[b+1] - 1);
+// workgroup x of a block takes either a part of a split transform of one
+// right-hand side (FftDesc::half: one parity half, or one residue mod 8), or
+// the right-hand sides r0 = x 2^lb .. r0 + 2^lb - 1 (lb = FftDesc::lb), their
 // transforms interleaved in LDS (point j of transform t at lds[(j << lb) + t])
-// so that a short block fills the workgroup as a long one does; workgroups
-// past a block's right-hand sides return at once.
+// so that a short block fills the workgroup as a long one does.
 
 // SPLIT: the half spectra are written as three bfloat16 planes (the pieces of
 // the split-bf16 product, layout in common.hpp) instead of complex values.
