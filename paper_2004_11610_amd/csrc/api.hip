@@ -517,7 +517,7 @@ int64_t build_block(spt_plan_t plan, DevBlock& B, hipStream_t s, size_t lds_max,
   if (!big) {
     B.fft = make_fft_plan(P);
     B.half = split;
-    B.fftw = split ? make_fft_plan(fused_points(P, split)) : B.fft;
+    B.fftw = make_fft_plan(fused_points(P, split), true);
   }
   exec_geometry(B);
   if (big && !B.four)
@@ -2112,14 +2112,21 @@ void build_batch_products(ExecCtx& c, const spt_plan_t* plans, const int64_t* R,
                           int prec, hipStream_t s) {
   const bool dbl = std::is_same<T, double>::value;
   // split-bf16: plans with windows take the chunked product (groups of 4 row
-  // tiles), the others the per-tile product
-  const bool chunked = prec == SPT_SPLIT_BF16;
+  // tiles), the others the per-tile product; float64: plans whose windows are
+  // too wide for LDS take the chunked float64 product (as a single execute
+  // does), the others the per-tile one
+  const bool chunked = prec == SPT_SPLIT_BF16 || prec == SPT_F64;
+  auto windowed = [&](const spt_plan_t plan) {
+    return prec == SPT_SPLIT_BF16 ? plan->win_ok
+                                  : prec == SPT_F64 && plan->win_ok && plan->win_chunked;
+  };
   std::vector<BatchProductPlan> bp(count);
   c.wlds = 0;
   for (int i = 0; i < count; ++i) {
     const spt_plan_t plan = plans[i];
-    bp[i] = BatchProductPlan{plan->win_ok ? 1 : 0, plan->n_groups, plan->n_tiles, R[i]};
-    if (chunked && plan->win_ok) c.wlds = std::max(c.wlds, spmm_chunk_lds_bytes(plan->win_tpad));
+    bp[i] = BatchProductPlan{windowed(plan) ? 1 : 0, plan->n_groups, plan->n_tiles, R[i]};
+    if (prec == SPT_SPLIT_BF16 && plan->win_ok)
+      c.wlds = std::max(c.wlds, spmm_chunk_lds_bytes(plan->win_tpad));
   }
   BatchProductLists bl;
   build_batch_product_lists(bp.data(), count, chunked, bl);
@@ -2173,6 +2180,7 @@ void build_batch_products(ExecCtx& c, const spt_plan_t* plans, const int64_t* R,
     a[i].tailmat = dbl ? (const T*)plan->tail64.p : (const T*)plan->tail32.p;
     a[i].R = (int)R[i];
     a[i].N = plan->N;
+    a[i].win = windowed(plan) ? plan->winmeta.as<WinMeta>() : nullptr;
   }
   upload(c.sargs, a, s);
 }
@@ -2200,11 +2208,16 @@ void run_batch_staged(ExecCtx& c, const void* const* X, void* const* Y, int coun
     }
     SpmmBatch<T> b{};
     b.plans = c.sargs.as<SpmmArgs<T>>();
-    b.items = c.sitems.as<int4>();
     for (int i = 0; i < count; ++i) {
       b.X[i] = static_cast<const T*>(X[i]);
       b.Y[i] = static_cast<T*>(Y[i]);
     }
+    // each launch reads its own item list (n items each)
+    if constexpr (std::is_same<T, double>::value) {
+      b.items = c.witems.as<int4>();
+      launch_spmm_chunk_f64_items(b, c.n_witems, s);
+    }
+    b.items = c.sitems.as<int4>();
     launch_spmm_items<T>(b, c.n_sitems, s);
   });
 }
@@ -2317,7 +2330,7 @@ void apply_tuning(spt_plan_t plan, hipStream_t s) {
     if (fused_lds_bytes<double>(fused_points(P, split), 128 + P / 128 + 1) > lds_max)
       throw Error(SPT_E_UNSUPPORTED, "FFT split does not fit one workgroup");
     B.half = split;
-    B.fftw = split ? make_fft_plan(fused_points(P, split)) : B.fft;
+    B.fftw = make_fft_plan(fused_points(P, split), true);
   }
   build_fft_descs(plan, s);
   plan->serial = next_serial();  // keys of the executor contexts

@@ -114,7 +114,9 @@ struct FftPlan {
   int threads = 64;
 };
 
-FftPlan make_fft_plan(int P);
+// radix10: the plan may merge a radix 2 and a radix 5 into one radix-10 pass,
+// which only the fused FFT kernels take (run_fft<..., R10 = true>)
+FftPlan make_fft_plan(int P, bool radix10 = false);
 
 // ---------------------------------------------------------------- kernel launch API
 // (implemented in the .hip files; all take device pointers and a stream)
@@ -278,6 +280,8 @@ struct SpmmArgs {
   T* Y;
   int R;
   int64_t N;
+  const struct WinMeta* win;  // batches: the windows of a plan the chunked float64
+                              // product takes (n_groups x nblk), else null
 };
 
 template <typename T>
@@ -375,6 +379,9 @@ struct SpmmSplitBatch {
 };
 template <typename T>
 void launch_spmm_items(const SpmmBatch<T>& b, int n_items, hipStream_t s);
+// items {plan, tile group, first right-hand side, 0} of the chunked float64
+// product (group < 0: padding); the plans' SpmmArgs carry their windows
+void launch_spmm_chunk_f64_items(const SpmmBatch<double>& b, int n_items, hipStream_t s);
 void launch_spmm_presplit_items(const SpmmSplitBatch& b, int n_items, hipStream_t s);
 // items {plan, tile group, first right-hand side, 0} of the chunked product
 // (group < 0: padding); lds: the largest spmm_chunk_lds_bytes of the plans

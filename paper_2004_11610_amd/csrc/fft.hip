@@ -231,7 +231,7 @@ __device__ __forceinline__ void fft_multi_body(const FftDesc<T>* __restrict__ d,
     input(std::false_type{});
   __syncthreads();
   // E2: F*, the pass twiddles formed from the two-level table
-  run_fft<+1, BATCH, EI>(lds, P, lb, d->fp.npass, d->fp.radix, ltab, 1, tid, nt, true);
+  run_fft<+1, BATCH, EI, true>(lds, P, lb, d->fp.npass, d->fp.radix, ltab, 1, tid, nt, true);
   // unpack point k of transform t (see unpack_with)
   auto unpack_at = [&](int k, int t, C tw) {
     C ck = lds[((k == P ? 0 : k) << lb) + t];
@@ -387,7 +387,7 @@ __device__ __forceinline__ void fft_half_body(const FftDesc<T>* __restrict__ d,
     input(std::false_type{});
   __syncthreads();
   // the two-level table is of length P = 2H: index scale 2
-  run_fft<+1, false, EI>(lds, H, 0, d->fp.npass, d->fp.radix, ltab, 2, tid, nt, true);
+  run_fft<+1, false, EI, true>(lds, H, 0, d->fp.npass, d->fp.radix, ltab, 2, tid, nt, true);
   // k = 2m + par: C_k at lds[m mod H], C_(P-k) at lds[(H - m) mod H] (par 0)
   // or lds[H - 1 - m] (par 1)
   const T scale = d->scale;
@@ -498,7 +498,7 @@ __device__ __forceinline__ void fft_rdif_body(const FftDesc<T>* __restrict__ d,
     __syncthreads();
   }
   // the table is of length P = 4M: index scale 4
-  run_fft<+1, false, EI>(lds, M, 0, d->fp.npass, d->fp.radix, ltab, 4, tid, nt, true);
+  run_fft<+1, false, EI, true>(lds, M, 0, d->fp.npass, d->fp.radix, ltab, 4, tid, nt, true);
   // outputs: residue p at k = 8m + p (Y[m]) and, for p = 1..3, residue 8 - p
   // at k = 8m + 8 - p (conj Y[M - 1 - m]); output u of the workgroup is
   // residue p at m = u (p = 0, 4) or, alternately, the two residues at m = u / 2
@@ -800,7 +800,7 @@ void init_fft_kernels(size_t max_lds) {
   done.push_back(dev);
 }
 
-FftPlan make_fft_plan(int P) {
+FftPlan make_fft_plan(int P, bool radix10) {
   FftPlan fp;
   fp.P = P;
   int n = P;
@@ -814,10 +814,10 @@ FftPlan make_fft_plan(int P) {
   if (n != 1) throw Error(SPT_E_UNSUPPORTED, "FFT length half " + std::to_string(P) +
                                                  " is not 2^a 3^b 5^c");
   // a lone radix 2 and a radix 5 become one radix-10 pass (one LDS round trip
-  // fewer)
+  // fewer) for the kernels that take radix 10 (the fused FFT)
   const auto two = std::find(rad.begin(), rad.end(), 2);
   const auto five = std::find(rad.begin(), rad.end(), 5);
-  if (two != rad.end() && five != rad.end()) {
+  if (radix10 && two != rad.end() && five != rad.end()) {
     *five = 10;
     rad.erase(two);
   }

@@ -220,15 +220,21 @@ __device__ __forceinline__ void stockham_pass(C* lds, int P, int lb, int Ns,
   __syncthreads();
 }
 
-// all passes; threads with active == false only take part in the barriers
-template <int SIGN, bool BATCH, int EPT = FFT_EPT, typename C>
+// all passes; threads with active == false only take part in the barriers.
+// R10: the plan may hold radix-10 passes (make_fft_plan(P, true)); the other
+// kernels leave them out, which keeps their registers down.
+template <int SIGN, bool BATCH, int EPT = FFT_EPT, bool R10 = false, typename C>
 __device__ __forceinline__ void run_fft(C* lds, int P, int lb, int npass, const int* radix,
                         const double2* __restrict__ tw, int tmul, int tid, int nt, bool active) {
   int Ns = 1;
   for (int p = 0; p < npass; ++p) {
     const int R = radix[p];
+    if (R10 && R == 10) {
+      stockham_pass<SIGN, R10 ? 10 : 2, BATCH, EPT>(lds, P, lb, Ns, tw, tmul, tid, nt, active);
+      Ns *= R;
+      continue;
+    }
     switch (R) {
-      case 10: stockham_pass<SIGN, 10, BATCH, EPT>(lds, P, lb, Ns, tw, tmul, tid, nt, active); break;
       case 8: stockham_pass<SIGN, 8, BATCH, EPT>(lds, P, lb, Ns, tw, tmul, tid, nt, active); break;
       case 4: stockham_pass<SIGN, 4, BATCH, EPT>(lds, P, lb, Ns, tw, tmul, tid, nt, active); break;
       case 2: stockham_pass<SIGN, 2, BATCH, EPT>(lds, P, lb, Ns, tw, tmul, tid, nt, active); break;

@@ -674,15 +674,14 @@ constexpr int CKF_PITCH = CKF_COLS + 1;         // odd row pitch (16-byte units)
 constexpr int CKF_UNITS = CK_NR * CKF_PITCH;    // units of one buffer
 static_assert(CKF_UNITS % 64 == 0, "chunk buffer layout");
 
-__global__ __launch_bounds__(256) void spmm_chunk_f64_kernel(SpmmArgs<double> args,
-                                                             const WinMeta* __restrict__ win,
-                                                             int n_groups) {
+// tile group grp, right-hand sides r0 .. r0 + CK_NR - 1 of one plan
+__device__ __forceinline__ void chunk_group_f64(const SpmmArgs<double>& args,
+                                                const WinMeta* __restrict__ win, int grp,
+                                                int r0) {
   using E = EngF64;
   using C = double2;
   constexpr int NR = CK_NR, RG = NR / 16;
   extern __shared__ __align__(16) C zc[];
-  const int grp = xcd_tile(blockIdx.x, n_groups);
-  const int r0 = blockIdx.y * NR;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   const int m = lane & 15, g = lane >> 4;
@@ -842,6 +841,22 @@ __global__ __launch_bounds__(256) void spmm_chunk_f64_kernel(SpmmArgs<double> ar
       }
     }
   }
+}
+
+__global__ __launch_bounds__(256) void spmm_chunk_f64_kernel(SpmmArgs<double> args,
+                                                             const WinMeta* __restrict__ win,
+                                                             int n_groups) {
+  chunk_group_f64(args, win, xcd_tile(blockIdx.x, n_groups), blockIdx.y * CK_NR);
+}
+
+// Several plans in one launch: workgroup b takes item b = (plan, group, r0)
+__global__ __launch_bounds__(256) void spmm_chunk_f64_items_kernel(SpmmBatch<double> b) {
+  const int4 it = b.items[blockIdx.x];
+  if (it.y < 0) return;
+  SpmmArgs<double> a = b.plans[it.x];
+  a.X = b.X[it.x];
+  a.Y = b.Y[it.x];
+  chunk_group_f64(a, a.win, it.y, it.z);
 }
 
 __global__ __launch_bounds__(256) void spmm_chunk_kernel(SpmmSplitArgs args,
@@ -1139,6 +1154,13 @@ void launch_spmm_chunk_items(const SpmmSplitBatch& b, int n_items, size_t lds, h
   SPT_HIP(hipGetLastError());
 }
 
+void launch_spmm_chunk_f64_items(const SpmmBatch<double>& b, int n_items, hipStream_t s) {
+  if (n_items <= 0) return;
+  hipLaunchKernelGGL(spmm_chunk_f64_items_kernel, dim3(n_items), dim3(256),
+                     (size_t)2 * CKF_UNITS * sizeof(double2), s, b);
+  SPT_HIP(hipGetLastError());
+}
+
 void launch_spmm_chunk_f64(const SpmmArgs<double>& a, const WinMeta* win, int n_groups,
                            hipStream_t s) {
   hipLaunchKernelGGL(spmm_chunk_f64_kernel, dim3(n_groups, (a.R + CK_NR - 1) / CK_NR), dim3(256),
@@ -1189,6 +1211,8 @@ void init_spmm_kernels(size_t max_lds) {
   SPT_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(spmm_chunk_items_kernel),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_lds));
   SPT_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(spmm_chunk_f64_kernel),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_lds));
+  SPT_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(spmm_chunk_f64_items_kernel),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_lds));
   done.push_back(dev);
 }
