@@ -171,14 +171,16 @@ typedef struct {
   double period;          /* SPT_LAGUERRE_SPECTRAL: the interval length T > 0 of
                              the Fourier series (k_j = 2 pi j / T)               */
   int32_t reduced_fft;    /* arithmetic of the x-side FFTs (and of the transposed
-                             product's single-workgroup inverse FFTs) of the
-                             SPT_F32 and SPT_SPLIT_BF16 paths, staged executor:
+                             product's inverse FFTs) of the SPT_F32 and
+                             SPT_SPLIT_BF16 paths, staged executor:
                              0 -> chosen at spt_precompute from 4 seeded N(0,1)
                              right-hand sides through the split-bf16 path (the
                              float32 path if only that is prepared) with float32
                              FFTs: kept when within 7e-7 of the float64 path
-                             (relative 2-norm), or, without a float64 path,
-                             within 5e-7 of the same path with float64 FFTs;
+                             (relative 2-norm), the transposed float32 product
+                             too when F32 and F64 are prepared, or, without a
+                             float64 path, within 5e-7 of the same path with
+                             float64 FFTs;
                              1 -> float32; 2 -> float64 (float32 in and out,
                              each spectrum value rounded once to float32).  The
                              spectra's rounding is amplified by kappa

@@ -1323,6 +1323,9 @@ void build_fft_descs(spt_plan_t plan, hipStream_t s) {
 }
 
 void choose_reduced_fft(spt_plan_t plan, hipStream_t s);
+bool inv_four_step(spt_plan_t plan, const DevBlock& B);
+template <typename T>
+void execute_transposed_t(spt_plan_t plan, const T* F, T* Y, int64_t R, hipStream_t s);
 
 void precompute_complex(spt_plan_t plan, hipStream_t s);
 
@@ -1451,17 +1454,38 @@ void choose_reduced_fft(spt_plan_t plan, hipStream_t s) {
   }
   SPT_HIP(hipMemcpyAsync(h32.data(), y32.p, n * sizeof(float), hipMemcpyDeviceToHost, s));
   SPT_HIP(hipStreamSynchronize(s));
-  double worst = 0.0;
-  for (int r = 0; r < R; ++r) {
-    double num = 0.0, den = 0.0;
-    for (int64_t j = 0; j < N; ++j) {
-      const double a = h32[(size_t)r * N + j], b = href[(size_t)r * N + j];
-      num += (a - b) * (a - b);
-      den += b * b;
+  // worst relative 2-norm error over the right-hand sides
+  auto worst_err = [&] {
+    double w = 0.0;
+    for (int r = 0; r < R; ++r) {
+      double num = 0.0, den = 0.0;
+      for (int64_t j = 0; j < N; ++j) {
+        const double a = h32[(size_t)r * N + j], b = href[(size_t)r * N + j];
+        num += (a - b) * (a - b);
+        den += b * b;
+      }
+      if (!(den > 0.0) || !std::isfinite(num))
+        throw Error(SPT_E_NUMERIC, "non-finite or zero result while choosing the FFT arithmetic");
+      w = std::max(w, std::sqrt(num / den));
     }
-    if (!(den > 0.0) || !std::isfinite(num))
-      throw Error(SPT_E_NUMERIC, "non-finite or zero result while choosing the FFT arithmetic");
-    worst = std::max(worst, std::sqrt(num / den));
+    return w;
+  };
+  double worst = worst_err();
+  // the transposed product (float32 against float64) on the same inputs: its
+  // inverse transforms take the same choice, and its error can exceed the
+  // forward product's on long blocks
+  bool tr = f32 && f64;
+  for (auto& B : plan->blk)
+    if (inv_four_step(plan, *B) && !B->four) tr = false;
+  if (tr) {
+    execute_transposed_t<float>(plan, x.as<float>(), y32.as<float>(), R, s);
+    DevBuf x64;
+    upload(x64, hx, s);
+    execute_transposed_t<double>(plan, x64.as<double>(), yref.as<double>(), R, s);
+    SPT_HIP(hipMemcpyAsync(href.data(), yref.p, n * sizeof(double), hipMemcpyDeviceToHost, s));
+    SPT_HIP(hipMemcpyAsync(h32.data(), y32.p, n * sizeof(float), hipMemcpyDeviceToHost, s));
+    SPT_HIP(hipStreamSynchronize(s));
+    worst = std::max(worst, worst_err());
   }
   plan->reduced_fft32_err = worst;
   plan->reduced_fft64 = worst > (f64 ? REDUCED_TOTAL_BUDGET : REDUCED_FFT32_BUDGET);
@@ -1712,9 +1736,16 @@ void execute_transposed_t(spt_plan_t plan, const T* F, T* Y, int64_t R, hipStrea
   ensure_work(plan, R, s, true);
   int64_t per = 0;
   for (auto& B : plan->blk) per += B->P + 1;
-  // four-step intermediates after the half spectra (w_per_rhs)
+  // four-step intermediates after the half spectra (w_per_rhs); the float32
+  // path's float64 intermediates (reduced_fft64) behind everything it uses,
+  // 16-byte aligned: the workspace holds (z + w + t) R float64 complex values
+  // and the float32 path uses half of that, and z > w
   C* wbuf = plan->work->as<C>() + per * R;
   C* u = plan->work->as<C>();
+  const size_t used32 = (size_t)(z_per_rhs(plan) + w_per_rhs(plan) + t_per_rhs(plan)) * R *
+                        sizeof(float2);
+  double2* wbuf64 = reinterpret_cast<double2*>(static_cast<char*>(plan->work->p) +
+                                               ((used32 + 15) & ~(size_t)15));
   SpmmTArgs<T> ta{};
   ta.segs = plan->tseg.as<int4>();
   ta.ents = plan->tent.as<TChunkEnt>();
@@ -1786,7 +1817,39 @@ void execute_transposed_t(spt_plan_t plan, const T* F, T* Y, int64_t R, hipStrea
       fa.f1 = B.f1;
       fa.f2 = B.f2;
       fa.scale = ia.scale;
-      staged(SPT_STAGE_INV_FFT, s, [&] { launch_inv_fft4<T>(fa, s); });
+      bool done = false;
+      if constexpr (std::is_same<T, float>::value) {
+        if (plan->reduced_fft64) {
+          // float64 arithmetic on float32 data (as the single-workgroup inverse
+          // transforms): the intermediate in float64, in the second half of
+          // the workspace, which is sized for float64 spectra
+          InvFft4Args<double, float> fx{};
+          fx.U = fa.U;
+          fx.W = wbuf64;
+          fx.Y = fa.Y;
+          fx.winv = B.winv64.as<double>();
+          fx.tw = fa.tw;
+          fx.post = B.post64.as<double2>();
+          fx.N = fa.N;
+          fx.R = fa.R;
+          fx.P = fa.P;
+          fx.P1 = fa.P1;
+          fx.P2 = fa.P2;
+          fx.ldu = fa.ldu;
+          fx.m_off = fa.m_off;
+          fx.c_lo = fa.c_lo;
+          fx.c_hi = fa.c_hi;
+          fx.lb1 = fa.lb1;
+          fx.lb2 = fa.lb2;
+          fx.f1 = fa.f1;
+          fx.f2 = fa.f2;
+          fx.scale = 1.0 / std::sqrt((double)B.g.L);
+          staged(SPT_STAGE_INV_FFT, s, [&] { launch_inv_fft4<double, float>(fx, s); });
+          wbuf64 += (size_t)R * B.P;
+          done = true;
+        }
+      }
+      if (!done) staged(SPT_STAGE_INV_FFT, s, [&] { launch_inv_fft4<T>(fa, s); });
       wbuf += (size_t)R * B.P;
     } else if (!multi) {
       staged(SPT_STAGE_INV_FFT, s, [&] { launch_inv_fft<T>(ia, B.fft, s); });

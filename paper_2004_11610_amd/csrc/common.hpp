@@ -227,11 +227,13 @@ void launch_inv_fft_multi(const InvFftDesc<T>* descs, int nblk, int threads, siz
 void launch_inv_fft_multi_x32(const InvFftDesc<double>* descs, int nblk, int threads, size_t lds,
                               const float2* U, float* Y, int R, int64_t N, hipStream_t s);
 
-template <typename T>
+// T: arithmetic, tables and intermediate; TI: type of U and Y (float with T =
+// double: the float32 path's transform in float64 arithmetic)
+template <typename T, typename TI = T>
 struct InvFft4Args {      // transposed execute of a block with P = P1 P2 (four steps)
-  const cplx_t<T>* U;     // R x ldu half spectrum
+  const cplx_t<TI>* U;    // R x ldu half spectrum
   cplx_t<T>* W;           // R x P intermediate, W[j2 P1 + k1]
-  T* Y;                   // R x N output, written at degrees c + m_off, c in [c_lo, c_hi)
+  TI* Y;                  // R x N output, written at degrees c + m_off, c in [c_lo, c_hi)
   const T* winv;
   const double2* tw;      // two-level table of the length P
   const cplx_t<T>* post;
@@ -242,8 +244,8 @@ struct InvFft4Args {      // transposed execute of a block with P = P1 P2 (four 
   T scale;
 };
 
-template <typename T>
-void launch_inv_fft4(const InvFft4Args<T>& a, hipStream_t s);
+template <typename T, typename TI = T>
+void launch_inv_fft4(const InvFft4Args<T, TI>& a, hipStream_t s);
 
 struct RowFftArgs {      // precompute: forward F of windowed rows, float64
   const double* rows;    // nrows x L

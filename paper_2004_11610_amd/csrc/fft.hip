@@ -671,8 +671,8 @@ __global__ __launch_bounds__(FFT_MAX_THREADS) void inv_fft_multi_kernel(
 // P1-point transforms over k1, then g_2j + i g_(2j+1) = c_j is divided by the
 // window on the retained columns (eq. Fe2).  Workgroup b takes right-hand side
 // b / groups and group b % groups.
-template <typename T>
-__global__ __launch_bounds__(FFT_MAX_THREADS) void inv_fft4_col_kernel(InvFft4Args<T> a) {
+template <typename T, typename TI>
+__global__ __launch_bounds__(FFT_MAX_THREADS) void inv_fft4_col_kernel(InvFft4Args<T, TI> a) {
   using C = cplx_t<T>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C* lds = reinterpret_cast<C*>(smem_raw);
@@ -681,15 +681,15 @@ __global__ __launch_bounds__(FFT_MAX_THREADS) void inv_fft4_col_kernel(InvFft4Ar
   const int groups = (a.P1 + tmask) >> lb;
   const int r = (int)blockIdx.x / groups;
   const int k1_0 = ((int)blockIdx.x - r * groups) << lb;
-  const C* __restrict__ u = a.U + (int64_t)r * a.ldu;
+  const cplx_t<TI>* __restrict__ u = a.U + (int64_t)r * a.ldu;
   const int pts = a.P2 << lb;
   for (int i = tid; i < pts; i += nt) {
     const int k2 = i >> lb, k1 = k1_0 + (i & tmask);
     C v = C{T(0), T(0)};
     if (k1 < a.P1) {
       const int k = k1 + a.P1 * k2;
-      const C uk = u[k];
-      C um = u[a.P - k];
+      const C uk = C{T(u[k].x), T(u[k].y)};
+      C um = C{T(u[a.P - k].x), T(u[a.P - k].y)};
       um.y = -um.y;  // conj U_(P-k)
       const C ge = cadd(uk, um);
       const C go = cmul(csub(uk, um), a.post[k]);
@@ -707,8 +707,8 @@ __global__ __launch_bounds__(FFT_MAX_THREADS) void inv_fft4_col_kernel(InvFft4Ar
   }
 }
 
-template <typename T>
-__global__ __launch_bounds__(FFT_MAX_THREADS) void inv_fft4_row_kernel(InvFft4Args<T> a) {
+template <typename T, typename TI>
+__global__ __launch_bounds__(FFT_MAX_THREADS) void inv_fft4_row_kernel(InvFft4Args<T, TI> a) {
   using C = cplx_t<T>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C* lds = reinterpret_cast<C*>(smem_raw);
@@ -728,15 +728,15 @@ __global__ __launch_bounds__(FFT_MAX_THREADS) void inv_fft4_row_kernel(InvFft4Ar
   __syncthreads();
   // w_P1 = w_P^P2
   run_fft<+1, true>(lds, a.P1, lb, a.f1.npass, a.f1.radix, a.tw, a.P2, tid, nt, true);
-  T* __restrict__ y = a.Y + (int64_t)r * a.N;
+  TI* __restrict__ y = a.Y + (int64_t)r * a.N;
   for (int i = tid; i < pts; i += nt) {
     const int j1 = i >> lb, t = i & tmask;
     if (t >= ncol) continue;
     const int j = j2_0 + t + a.P2 * j1;
     const C c = lds[i];
     const int c0 = 2 * j, c1 = 2 * j + 1;
-    if (c0 >= a.c_lo && c0 < a.c_hi) y[c0 + a.m_off] = c.x * a.scale * a.winv[c0];
-    if (c1 >= a.c_lo && c1 < a.c_hi) y[c1 + a.m_off] = c.y * a.scale * a.winv[c1];
+    if (c0 >= a.c_lo && c0 < a.c_hi) y[c0 + a.m_off] = TI(c.x * a.scale * a.winv[c0]);
+    if (c1 >= a.c_lo && c1 < a.c_hi) y[c1 + a.m_off] = TI(c.y * a.scale * a.winv[c1]);
   }
 }
 
@@ -782,10 +782,12 @@ void init_fft_kernels(size_t max_lds) {
   set_lds(inv_fft_multi_kernel<double>, max_lds);
   set_lds(inv_fft_multi_kernel<double, float>, max_lds);
   set_lds(inv_fft_multi_kernel<float>, max_lds);
-  set_lds(inv_fft4_col_kernel<double>, max_lds);
-  set_lds(inv_fft4_col_kernel<float>, max_lds);
-  set_lds(inv_fft4_row_kernel<double>, max_lds);
-  set_lds(inv_fft4_row_kernel<float>, max_lds);
+  set_lds(inv_fft4_col_kernel<double, double>, max_lds);
+  set_lds(inv_fft4_col_kernel<float, float>, max_lds);
+  set_lds(inv_fft4_col_kernel<double, float>, max_lds);
+  set_lds(inv_fft4_row_kernel<double, double>, max_lds);
+  set_lds(inv_fft4_row_kernel<float, float>, max_lds);
+  set_lds(inv_fft4_row_kernel<double, float>, max_lds);
   set_lds(row_fft_kernel, max_lds);
   set_lds(exec_fft_multi_kernel<double, double, false, 512>, max_lds);
   set_lds(exec_fft_multi_kernel<float, float, false, 512>, max_lds);
@@ -919,18 +921,18 @@ static int batch_threads(int pts) {
   return t < 64 ? 64 : t;
 }
 
-template <typename T>
-void launch_inv_fft4(const InvFft4Args<T>& a, hipStream_t s) {
+template <typename T, typename TI>
+void launch_inv_fft4(const InvFft4Args<T, TI>& a, hipStream_t s) {
   const int p1 = a.P2 << a.lb1, p2 = a.P1 << a.lb2;
   if (p1 > FFT_EPT * FFT_MAX_THREADS || p2 > FFT_EPT * FFT_MAX_THREADS)
     throw Error(SPT_E_INVALID_ARG, "four-step inverse transform groups exceed one workgroup");
   const int64_t g1 = (int64_t)a.R * ((a.P1 + (1 << a.lb1) - 1) >> a.lb1);
   const int64_t g2 = (int64_t)a.R * ((a.P2 + (1 << a.lb2) - 1) >> a.lb2);
   if (g1 > INT32_MAX || g2 > INT32_MAX) throw Error(SPT_E_INVALID_ARG, "too many right-hand sides");
-  hipLaunchKernelGGL(inv_fft4_col_kernel<T>, dim3((unsigned)g1), dim3(batch_threads(p1)),
+  hipLaunchKernelGGL((inv_fft4_col_kernel<T, TI>), dim3((unsigned)g1), dim3(batch_threads(p1)),
                      sizeof(cplx_t<T>) * (size_t)p1, s, a);
   SPT_HIP(hipGetLastError());
-  hipLaunchKernelGGL(inv_fft4_row_kernel<T>, dim3((unsigned)g2), dim3(batch_threads(p2)),
+  hipLaunchKernelGGL((inv_fft4_row_kernel<T, TI>), dim3((unsigned)g2), dim3(batch_threads(p2)),
                      sizeof(cplx_t<T>) * (size_t)p2, s, a);
   SPT_HIP(hipGetLastError());
 }
@@ -956,7 +958,8 @@ template void launch_inv_fft_multi<double>(const InvFftDesc<double>*, int, int, 
                                            const double2*, double*, int, int64_t, hipStream_t);
 template void launch_inv_fft_multi<float>(const InvFftDesc<float>*, int, int, size_t,
                                           const float2*, float*, int, int64_t, hipStream_t);
-template void launch_inv_fft4<double>(const InvFft4Args<double>&, hipStream_t);
-template void launch_inv_fft4<float>(const InvFft4Args<float>&, hipStream_t);
+template void launch_inv_fft4<double, double>(const InvFft4Args<double, double>&, hipStream_t);
+template void launch_inv_fft4<float, float>(const InvFft4Args<float, float>&, hipStream_t);
+template void launch_inv_fft4<double, float>(const InvFft4Args<double, float>&, hipStream_t);
 
 }  // namespace spt

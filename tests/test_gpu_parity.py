@@ -870,3 +870,23 @@ def test_unaligned_input_matches_aligned(spt, prec):
     e = rel_rows(yu, ya)
     say("  rel %.3e" % e)
     assert e <= (1e-14 if prec == spt.F64 else 1e-7)
+
+
+@pytest.mark.parametrize("fam,N,kw", [("sine", 16384, {}), ("chebyshev_t", 16384, {}),
+                                      ("cos_power", 16384, dict(power=3)),
+                                      ("legendre", LONG_N, {})])
+def test_transposed_reduced_long_blocks(spt, fam, N, kw):
+    """The float32 transposed product on plans whose inverse transforms take
+    four steps (P > 10240): within 1e-6 of float64, the float32 path running
+    those transforms in float64 arithmetic where the plan chose that
+    (spt_params.reduced_fft)."""
+    import torch
+    say("transposed float32, long blocks", fam, N, kw)
+    p = spt.Plan(fam, N, 1e-7, **kw).precompute()
+    assert max(L for L, _, _, _ in p.blocks()) // 2 > 10240
+    X = workloads.rhs("normal", 8, N, 113)
+    y64 = to_host(p.execute_transposed(to_dev(X, torch.float64), prec=spt.F64))
+    y32 = to_host(p.execute_transposed(to_dev(X, torch.float32), prec=spt.F32))
+    e = rel_rows(y32, y64)
+    say("  rel %.3e (float64 FFTs %d)" % (e, p.info()["reduced_fft_f64"]))
+    assert e <= REDUCED_TOL
