@@ -209,6 +209,72 @@ def large_workload(args, spt, workloads):
     return out
 
 
+def generators_workload(args, spt, workloads):
+    """The other generators the method takes (sec. 2, eq. cosd2, sec. 4.1) and
+    the Appendix A precompute, at the benchmark's 64 right-hand sides: one
+    stream, executes back to back; per path the RHS-transforms/s, the stage
+    times (HIP events) and the relative error against float64."""
+    import numpy as np
+    import torch
+    R = 64
+    cases = [("sine-n16384", "sine", 16384, {}),
+             ("cos3-n16384", "cos_power", 16384, dict(power=3)),
+             ("chebyshev-n16384-appendix-a", "chebyshev_t", 16384, dict(trig_conv_q=12)),
+             ("cexp-n4096", "cexp", 4096, {}),
+             ("laguerre-spectral-n4096", "laguerre_spectral", 4096,
+              dict(eta=100.0, period=4.0))]
+    out = {"metric": "RHS-transforms/s", "workload": "generators", "nrhs": R, "eps1": 1e-7,
+           "plans": {}}
+    steps = max(10, min(args.steps, 100))
+    for name, fam, N, kw in cases:
+        cplx = fam in ("cexp", "laguerre_spectral")
+        t0 = time.perf_counter()
+        p = spt.Plan(fam, N, 1e-7, **kw).precompute()
+        torch.cuda.synchronize()
+        res = {"N": N, "precompute_s": time.perf_counter() - t0, "blocks": [b[0] for b in p.blocks()],
+               "nnz": p.info()["nnz"], "paths": {}}
+        if fam == "chebyshev_t":
+            t0 = time.perf_counter()
+            q = spt.Plan(fam, N, 1e-7).precompute()
+            torch.cuda.synchronize()
+            res["precompute_row_ffts_s"] = time.perf_counter() - t0
+            q.close()
+        g = np.random.default_rng(77)
+        Xh = g.standard_normal((R, N)) + (1j * g.standard_normal((R, N)) if cplx else 0.0)
+        precs = [("f64", spt.F64), ("f32", spt.F32)] + ([] if cplx else [("split_bf16", spt.SPLIT_BF16)])
+        ref = {}
+        for tr in (False, True):
+            for pname, prec in precs:
+                if tr and prec == spt.SPLIT_BF16:
+                    continue
+                dt = (torch.complex128 if prec == spt.F64 else torch.complex64) if cplx else \
+                     (torch.float64 if prec == spt.F64 else torch.float32)
+                X = torch.as_tensor(Xh).to(device="cuda", dtype=dt)
+                f = p.execute_transposed if tr else p.execute
+                Y = f(X, prec=prec)
+                run = lambda: f(X, Y, prec=prec)
+                t = timed_steps(run, steps, 5)
+                spt.profile_begin()
+                for _ in range(steps):
+                    run()
+                torch.cuda.synchronize()
+                st = spt.profile_end()
+                key = ("transposed_" if tr else "") + pname
+                y = Y.cpu().numpy().astype(np.complex128 if cplx else np.float64)
+                if prec == spt.F64:
+                    ref[tr] = y
+                err = float(np.max(np.linalg.norm(y - ref[tr], axis=1) /
+                                   np.linalg.norm(ref[tr], axis=1)))
+                res["paths"][key] = {"value": R * steps / t, "ms_per_execute": 1e3 * t / steps,
+                                     "kernel_ms": {k: v[0] / max(v[1], 1) for k, v in st.items()
+                                                   if v[1]},
+                                     "rel_err_vs_f64": err}
+                log(name, key, res["paths"][key])
+        out["plans"][name] = res
+        p.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -222,9 +288,11 @@ def main():
                     help="streams the timed steps are dealt to in turn (independent "
                          "batches in flight at once; 1 = strictly one after another)")
     ap.add_argument("--workload", default="legendre-n16384-r64",
-                    choices=["legendre-n16384-r64", "batch48", "laguerre-fn-n65536-r1024"],
-                    help="the headline workload (default), or one of the two large ones "
-                         "(timed the same way, reported for the design notes)")
+                    choices=["legendre-n16384-r64", "batch48", "laguerre-fn-n65536-r1024",
+                             "generators"],
+                    help="the headline workload (default), one of the two large ones "
+                         "(timed the same way), or the other generators and the Appendix A "
+                         "precompute (reported for the design notes)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default launch choices instead of spt_autotune's")
     ap.add_argument("--tuning", default="",
@@ -256,6 +324,9 @@ def main():
         return
     import paper_2004_11610_amd as spt
     import workloads
+    if args.workload == "generators":
+        print(json.dumps(generators_workload(args, spt, workloads)), flush=True)
+        return
     if args.workload != "legendre-n16384-r64":
         print(json.dumps(large_workload(args, spt, workloads)), flush=True)
         return
