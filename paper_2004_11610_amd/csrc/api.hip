@@ -1084,10 +1084,12 @@ std::vector<FftDesc<T>> fft_descs(spt_plan_t plan) {
     e.ntw = 128 + B.P / 128 + 1;
     // up to 4 right-hand sides per workgroup of a short block: 2^lb transforms
     // interleaved put 64 / 2^lb consecutive points of a row in a wave's
-    // loads and stores (diagnostics: SPT_FFT_MAX_LB)
+    // loads and stores.  A batched workgroup stays below the launch's largest
+    // transform: its interleaved passes take longer than a single transform
+    // of the same points, and it would become the launch's last workgroup.
     e.half = B.half;
     e.lb = 0;
-    while (!B.half && e.lb < fft_max_lb(plan) && ((int64_t)B.fftw.P << (e.lb + 1)) <= plan->fft_wgP)
+    while (!B.half && e.lb < fft_max_lb(plan) && ((int64_t)B.fftw.P << (e.lb + 1)) < plan->fft_wgP)
       ++e.lb;
     B.lbw = e.lb;
     d.push_back(e);

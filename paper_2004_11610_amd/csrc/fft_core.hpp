@@ -220,14 +220,119 @@ __device__ __forceinline__ void stockham_pass(C* lds, int P, int lb, int Ns,
   __syncthreads();
 }
 
+// v from lane (lane ^ S) of the same group of 8 lanes: S = 1 and 2 by DPP
+// quad permutations, S = 4 by a bit-mode LDS swizzle (xor 4 within 32 lanes;
+// no LDS memory).  Every lane of a group must be active.
+template <int S>
+__device__ __forceinline__ int xor_lane_i(int v) {
+  static_assert(S == 1 || S == 2 || S == 4, "lane partner");
+  if constexpr (S == 1) return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false);  // [1,0,3,2]
+  if constexpr (S == 2) return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false);  // [2,3,0,1]
+  return __builtin_amdgcn_ds_swizzle(v, (S << 10) | 0x1F);  // and 0x1f, or 0, xor S
+}
+template <int S>
+__device__ __forceinline__ float xor_lane(float v) {
+  return __builtin_bit_cast(float, xor_lane_i<S>(__builtin_bit_cast(int, v)));
+}
+template <int S>
+__device__ __forceinline__ double xor_lane(double v) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = (unsigned)xor_lane_i<S>((int)(unsigned)u);
+  const unsigned hi = (unsigned)xor_lane_i<S>((int)(unsigned)(u >> 32));
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+// 8 x 8 transpose over a group of 8 lanes: lane c ends with element c of every
+// lane's eight.  Stage S exchanges, between lanes c and c ^ S, the elements
+// whose index differs from the lane in bit S; after the three stages element
+// i of lane c has moved to element c of lane i.
+template <int S, typename C>
+__device__ __forceinline__ void transpose8_stage(C* v, int c) {
+  using T = decltype(v[0].x);
+  const bool hi = (c & S) != 0;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    if (i & S) continue;
+    const T sx = hi ? v[i].x : v[i | S].x, sy = hi ? v[i].y : v[i | S].y;
+    const T rx = xor_lane<S>(sx), ry = xor_lane<S>(sy);
+    if (hi) {
+      v[i].x = rx;
+      v[i].y = ry;
+    } else {
+      v[i | S].x = rx;
+      v[i | S].y = ry;
+    }
+  }
+}
+
+// The first two passes (radix 8, then radix 8 with Ns = 8) of one transform
+// of length P in LDS, with one LDS round trip instead of two.  The second
+// pass's butterfly 8g + c takes element c of the first pass's butterflies
+// g + r M (r < 8, M = P / 64); lane c of an 8-lane group g holds butterfly
+// g + c M, so after the first DFT the group exchanges its 64 values in
+// registers (transpose8) and runs the second pass's twiddles and DFT.
+// Requires P % 64 == 0 and P / 8 <= ceil(EPT / 8) nt, and nt a multiple of 8
+// (groups are then all active or all idle).
+template <int SIGN, int EPT, typename C>
+__device__ __forceinline__ void stockham_pass88(C* lds, int P, const double2* __restrict__ tw,
+                                                int tmul, int tid, int nt, bool active) {
+  constexpr int MAXB = (EPT + 7) / 8;
+  const int nb = P / 8, M = P / 64;
+  C v[MAXB][8];
+#pragma unroll
+  for (int b = 0; b < MAXB; ++b) {
+    const int u = tid + b * nt;
+    if (active && u < nb) {
+      const int j = (u >> 3) + (u & 7) * M;
+#pragma unroll
+      for (int r = 0; r < 8; ++r) v[b][r] = lds[j + r * nb];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < MAXB; ++b) {
+    const int u = tid + b * nt;
+    if (active && u < nb) {
+      const int g = u >> 3, c = u & 7;
+      Dft<SIGN, 8, C>::run(v[b]);
+      transpose8_stage<1>(v[b], c);
+      transpose8_stage<2>(v[b], c);
+      transpose8_stage<4>(v[b], c);
+      if (c > 0) {
+        // w^(c r) with w = exp(SIGN 2 pi i M / P), powers in float64
+        double2 t1 = twiddle(tw, c * M * tmul);
+        if (SIGN < 0) t1.y = -t1.y;
+        double2 w = t1;
+#pragma unroll
+        for (int r = 1; r < 8; ++r) {
+          v[b][r] = cmul(v[b][r], to_c<C>(w));
+          if (r + 1 < 8) w = cmul(w, t1);
+        }
+      }
+      Dft<SIGN, 8, C>::run(v[b]);
+#pragma unroll
+      for (int r = 0; r < 8; ++r) lds[64 * g + c + 8 * r] = v[b][r];
+    }
+  }
+  __syncthreads();
+}
+
 // all passes; threads with active == false only take part in the barriers.
 // R10: the plan may hold radix-10 passes (make_fft_plan(P, true)); the other
-// kernels leave them out, which keeps their registers down.
+// kernels leave them out, which keeps their registers down.  Those kernels
+// (single transforms) also take two leading radix-8 passes together
+// (stockham_pass88).
 template <int SIGN, bool BATCH, int EPT = FFT_EPT, bool R10 = false, typename C>
 __device__ __forceinline__ void run_fft(C* lds, int P, int lb, int npass, const int* radix,
                         const double2* __restrict__ tw, int tmul, int tid, int nt, bool active) {
   int Ns = 1;
-  for (int p = 0; p < npass; ++p) {
+  int p0 = 0;
+  if (R10 && !BATCH && npass >= 2 && radix[0] == 8 && radix[1] == 8) {
+    stockham_pass88<SIGN, EPT>(lds, P, tw, tmul, tid, nt, active);
+    Ns = 64;
+    p0 = 2;
+  }
+  for (int p = p0; p < npass; ++p) {
     const int R = radix[p];
     if (R10 && R == 10) {
       stockham_pass<SIGN, R10 ? 10 : 2, BATCH, EPT>(lds, P, lb, Ns, tw, tmul, tid, nt, active);
