@@ -371,15 +371,17 @@ def main():
         Ys = [Y] + [torch.empty_like(Y) for _ in range(args.streams - 1)]
         state = {"i": 0}
 
+        # each execute names its stream (no stream context per step: entering
+        # one costs the host more than a step's launches)
         def step():
             j = state["i"] % args.streams
             state["i"] += 1
-            with torch.cuda.stream(streams[j]):
-                run(X, Ys[j], prec=prec)
+            run(X, Ys[j], prec=prec, stream=streams[j])
 
         torch.cuda.synchronize()
         t = timed_steps(step, args.steps, args.warmup)
-        t1 = timed_steps(lambda: run(X, Y, prec=prec), args.steps, args.warmup)
+        s0 = torch.cuda.current_stream()
+        t1 = timed_steps(lambda: run(X, Y, prec=prec, stream=s0), args.steps, args.warmup)
         r = {"ms_per_step": 1e3 * t / args.steps, "value": R * args.steps / t,
              "streams": args.streams,
              "one_stream": {"ms_per_step": 1e3 * t1 / args.steps, "value": R * args.steps / t1}}
