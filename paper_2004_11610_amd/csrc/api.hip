@@ -115,6 +115,10 @@ struct DevBlock {
   DevBuf winv64, winv32, tw64, post64, post32, posttw;
   DevBuf k0, kw, off;   // per tile
   bool big = false;  // the transform does not fit one workgroup (four steps)
+  // the computation stage's forward FFT is fused (one workgroup per transform
+  // or split part; every block of a plan with !big, and split blocks up to
+  // FUSED_FWD_MAX_P)
+  bool fwd = false;
   // transposed product: the segments of row tiles per TCHUNK spectrum columns
   std::vector<int32_t> h_tptr;  // chunk c's tiles are h_tent[h_tptr[c] .. h_tptr[c + 1])
   std::vector<TChunkEnt> h_tent;
@@ -235,6 +239,7 @@ struct spt_plan {
   bool win_chunked = false;  // the windows pass through LDS in chunks (too wide to fit)
   int fft_threads = 64, fft_maxP = 1;
   int fft_wgP = 1;  // most points of one workgroup of the fused FFT
+  bool fwd_fused = false;  // every block's forward FFT is fused (DevBlock::fwd)
   int64_t serial = 0;  // changes with every precompute (keys of executor contexts)
   std::vector<std::unique_ptr<spt::ExecCtx>> ctx;  // executor contexts of spt_execute
   uint32_t exec_wait = spt::EXEC_WAIT_DEFAULT;      // persistent executor: wait bound, ticks
@@ -511,11 +516,12 @@ int64_t build_block(spt_plan_t plan, DevBlock& B, hipStream_t s, size_t lds_max,
   // transforms (P * 16 bytes), and the fused execute FFT's points of a
   // transform or of a parity half with its two twiddle tables
   const int split = fused_split(plan, P, lds_max);
-  const bool big = P > FUSED_MAX_P || (size_t)P * sizeof(double2) > lds_max ||
-                   fused_lds_bytes<double>(fused_points(P, split), 128 + P / 128 + 1) > lds_max;
+  const bool fits = fused_lds_bytes<double>(fused_points(P, split), 128 + P / 128 + 1) <= lds_max;
+  const bool big = P > FUSED_MAX_P || (size_t)P * sizeof(double2) > lds_max || !fits;
   B.big = big;
-  if (!big) {
-    B.fft = make_fft_plan(P);
+  B.fwd = fits && (!big || (P <= FUSED_FWD_MAX_P && split != FFT_SPLIT_NONE));
+  if (!big) B.fft = make_fft_plan(P);
+  if (B.fwd) {
     B.half = split;
     B.fftw = make_fft_plan(fused_points(P, split), true);
   }
@@ -1193,7 +1199,9 @@ void build_fft_descs(spt_plan_t plan, hipStream_t s) {
   plan->fft_maxP = 1;
   for (auto& B : plan->blk) exec_geometry(*B);
   plan->fft_wgP = 1;
+  plan->fwd_fused = true;
   for (auto& B : plan->blk) {
+    plan->fwd_fused = plan->fwd_fused && B->fwd;
     plan->fft_threads = std::max(plan->fft_threads, B->fftw.threads);
     plan->fft_maxP = std::max(plan->fft_maxP, B->P);
     plan->fft_wgP = std::max(plan->fft_wgP, B->fftw.P);
@@ -1597,7 +1605,7 @@ void execute_staged_t(spt_plan_t plan, const T* X, T* Y, int64_t R, int prec, hi
   }
   const int nblk = (int)plan->blk.size();
   const bool split = std::is_same<T, float>::value && prec == SPT_SPLIT_BF16;
-  const bool fused = nblk > 0 && plan->fft_maxP <= FUSED_MAX_P;
+  const bool fused = nblk > 0 && plan->fwd_fused;
   const FftDesc<T>* d = std::is_same<T, double>::value ? (const FftDesc<T>*)plan->fftdesc64.p
                                                        : (const FftDesc<T>*)plan->fftdesc32.p;
   // fused FFT launch of blocks b0 .. b0 + nb - 1 on stream st
@@ -2389,7 +2397,7 @@ void apply_tuning(spt_plan_t plan, hipStream_t s) {
   const size_t lds_max = max_lds_bytes(plan->device);
   for (auto& Bp : plan->blk) {
     DevBlock& B = *Bp;
-    if (B.big) continue;
+    if (!B.fwd) continue;
     const int P = B.P;
     const int split = fused_split(plan, P, lds_max);
     if (fused_lds_bytes<double>(fused_points(P, split), 128 + P / 128 + 1) > lds_max)
@@ -2508,7 +2516,7 @@ void autotune_t(spt_plan_t plan, int64_t R, int prec, hipStream_t s, spt_tuning&
   // transform fits one workgroup, eight-way where 4 divides P
   bool can_split = false, can_off = false, can_eight = false;
   for (auto& B : plan->blk)
-    if (!B->big && B->P >= FUSED_HALF_MIN_P && B->P % 2 == 0) {
+    if (B->fwd && B->P >= FUSED_HALF_MIN_P && B->P % 2 == 0) {
       can_split = true;
       can_off |= fused_lds_bytes<double>(B->P, 128 + B->P / 128 + 1) <= lds_max;
       can_eight |= B->P % 4 == 0;
@@ -2743,7 +2751,7 @@ spt_status spt_execute_noalloc(spt_plan_t plan, const void* X, void* Y, int64_t 
     if (!uses_staged(plan) || plan->cx)
       throw Error(SPT_E_UNSUPPORTED,
                   "spt_execute_noalloc runs the staged executor of real plans only");
-    if (!plan->blk.empty() && plan->fft_maxP > FUSED_MAX_P)
+    if (!plan->blk.empty() && !plan->fwd_fused)
       throw Error(SPT_E_UNSUPPORTED, "a block's FFT exceeds one workgroup (it needs work lists)");
     const size_t need = work_bytes(plan, nrhs, false);
     if (need > (size_t)SPT_NOALLOC_MAX_BYTES)

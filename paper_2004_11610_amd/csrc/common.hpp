@@ -29,6 +29,10 @@ constexpr int FUSED_MAX_P = 10240;
 // the fused FFT splits transforms of an even number of points, at least
 // this many, into two workgroups (by the parity of the outputs)
 constexpr int FUSED_HALF_MIN_P = 4096;
+// longest FFT half-length of the fused computation-stage FFT when it is split
+// (parity halves or the eight-way split): a float64 parity half of 8192
+// points and its tables fill 136 KiB of LDS.  Longer blocks go by four steps.
+constexpr int FUSED_FWD_MAX_P = 16384;
 // AUTO mode compares built blocks with the dense matrix up to this N, and an
 // estimate from sampled rows above it
 constexpr int64_t AUTO_EXACT_N = 8192;

@@ -624,7 +624,9 @@ def test_nonfinite_precompute_is_numeric_error(spt):
 
 
 # ------------------------------------------------------------------ long blocks
-LONG_N = 24000  # first block L = 30000: P = 15000 > 10240, four-step transforms
+# first block L = 30000: P = 15000 > 10240, four-step precompute and inverse
+# transforms; the staged forward FFT in parity halves of 7500 points
+LONG_N = 24000
 
 
 def test_long_block_precompute_sampled_rows(spt):
@@ -660,8 +662,10 @@ def test_long_block_precompute_sampled_rows(spt):
 
 @pytest.mark.parametrize("executor", ["staged", "persistent"])
 def test_long_block_execute(spt, executor):
-    """Execute with a four-step first block: F64 against sampled rows of the
-    direct product, F32 and split-bf16 against F64."""
+    """Execute with a first block longer than one workgroup's whole transform
+    (P = 15000: parity halves in the staged executor's fused FFT, four-step
+    items in the persistent one): F64 against sampled rows of the direct
+    product, F32 and split-bf16 against F64."""
     say("long block execute", executor)
     ex = spt.EXECUTOR_STAGED if executor == "staged" else spt.EXECUTOR_PERSISTENT
     fam = oracle_family("legendre", LONG_N)
@@ -724,15 +728,17 @@ def test_forced_chunks_match_per_tile(spt, fam, N, R):
 def test_batch_of_windowed_plans_matches_single(spt):
     """A staged split-bf16 batch whose plans all have windows runs only the
     chunked product's items (the per-tile item list holds one padding entry);
-    a plan whose FFTs are four-step items in both paths (P = 15000) gives the
-    same bits batched, alone or beside another plan, as executed singly; with
+    a plan whose FFTs are four-step items in both paths (Legendre 30000, first
+    block P = 18750, longer than the fused FFT's split parts) gives the same
+    bits batched, alone or beside another plan, as executed singly; with
     a plan without windows in the batch, both product launches run."""
     import torch
     say("batch of windowed plans")
-    big = spt.Plan("legendre", LONG_N, 1e-7).precompute()
+    big = spt.Plan("legendre", 30000, 1e-7).precompute()
     small = spt.Plan("legendre", 1000, 1e-7).precompute()
+    assert big.blocks()[0][0] // 2 > 16384
     assert big.info()["window_lds"] > 0 and small.info()["window_lds"] > 0
-    Xb = to_dev(workloads.rhs("normal", 2, LONG_N, 75), torch.float32)
+    Xb = to_dev(workloads.rhs("normal", 2, 30000, 75), torch.float32)
     Xs = to_dev(workloads.rhs("normal", 5, 1000, 70), torch.float32)
     ref = to_host(big.execute(Xb, prec=spt.SPLIT_BF16))
     for plans, Xl in (([big], [Xb]), ([small, big], [Xs, Xb])):
@@ -890,3 +896,28 @@ def test_transposed_reduced_long_blocks(spt, fam, N, kw):
     e = rel_rows(y32, y64)
     say("  rel %.3e (float64 FFTs %d)" % (e, p.info()["reduced_fft_f64"]))
     assert e <= REDUCED_TOL
+
+
+@pytest.mark.parametrize("fam,N,R,kw", [("sine", 16384, 5, {}), ("legendre", 26000, 3, {}),
+                                        ("legendre", LONG_N, 2, dict(fft_half=3))])
+def test_fused_split_beyond_one_workgroup(spt, fam, N, R, kw):
+    """First blocks longer than one workgroup's whole transform (10240 < P <=
+    16384): the staged executor's forward FFT runs fused as parity halves (or
+    the eight-way split), the persistent executor's as four-step items; both
+    float64 results agree to 1e-12 and the float32 and split-bf16 paths stay
+    within 1e-6 of float64."""
+    say("fused split beyond one workgroup", fam, N, R, kw)
+    tune = {k: v for k, v in kw.items() if k == "fft_half"}
+    p = spt.Plan(fam, N, 1e-7).set_tuning(**tune).precompute()
+    q = spt.Plan(fam, N, 1e-7, executor=spt.EXECUTOR_PERSISTENT).precompute()
+    P = p.blocks()[0][0] // 2
+    assert 10240 < P <= 16384
+    X = workloads.rhs("normal", R, N, 131)
+    y = run(spt, p, X, spt.F64)
+    e = rel_rows(y, run(spt, q, X, spt.F64))
+    say("  P %d staged vs persistent F64 %.3e" % (P, e))
+    assert e <= 1e-12
+    for prec in (spt.F32, spt.SPLIT_BF16):
+        e = rel_rows(run(spt, p, X, prec), y)
+        say("  prec", prec, "rel vs F64 %.3e" % e)
+        assert e <= REDUCED_TOL

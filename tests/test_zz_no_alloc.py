@@ -68,7 +68,8 @@ def test_noalloc_refusals(spt):
     q = spt.Plan("legendre", 2048, 1e-7, executor=spt.EXECUTOR_PERSISTENT).precompute()
     x = torch.zeros((2, 2048), dtype=torch.float64, device="cuda")
     assert noalloc(spt, q, x, torch.empty_like(x), spt.F64) == -5
-    big = spt.Plan("legendre", 24000, 1e-7, precisions=1 << spt.F64).precompute()
-    xb = torch.zeros((1, 24000), dtype=torch.float64, device="cuda")
+    # first block L = 37500 (P = 18750): its forward FFT runs as work-list items
+    big = spt.Plan("legendre", 30000, 1e-7, precisions=1 << spt.F64).precompute()
+    xb = torch.zeros((1, 30000), dtype=torch.float64, device="cuda")
     assert noalloc(spt, big, xb, torch.empty_like(xb), spt.F64) == -5
     assert info["N"] == 16384
