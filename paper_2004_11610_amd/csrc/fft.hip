@@ -530,7 +530,8 @@ __device__ __forceinline__ void fft_rdif_body(const FftDesc<T>* __restrict__ d,
 }
 
 // MAXT: the launch's threads are at most MAXT (512 leaves each thread 256
-// registers, 1024 leaves 128).  TI: type of X and of the complex spectra Z
+// registers, 768 leaves 168, 1024 leaves 128; float64 arithmetic takes 768
+// where it fits, as it spills under 128).  TI: type of X and of the complex spectra Z
 // (float with T = double: the float32 paths' transforms in float64
 // arithmetic, each spectrum value rounded once to float32).
 // Float32 arithmetic at 512 threads is held to 128 registers, so that two
@@ -794,6 +795,9 @@ void init_fft_kernels(size_t max_lds) {
   set_lds(exec_fft_multi_kernel<float, float, true, 512>, max_lds);
   set_lds(exec_fft_multi_kernel<double, float, true, 512>, max_lds);
   set_lds(exec_fft_multi_kernel<double, float, false, 512>, max_lds);
+  set_lds(exec_fft_multi_kernel<double, double, false, 768>, max_lds);
+  set_lds(exec_fft_multi_kernel<double, float, true, 768>, max_lds);
+  set_lds(exec_fft_multi_kernel<double, float, false, 768>, max_lds);
   set_lds(exec_fft_multi_kernel<double, double, false, 1024>, max_lds);
   set_lds(exec_fft_multi_kernel<float, float, false, 1024>, max_lds);
   set_lds(exec_fft_multi_kernel<float, float, true, 1024>, max_lds);
@@ -860,8 +864,13 @@ template <typename T>
 void launch_exec_fft_multi(const FftDesc<T>* descs, const FftGrid& g, int threads, size_t lds,
                            const T* X, cplx_t<T>* Z, int R, int64_t N, hipStream_t s) {
   const dim3 grid(g.wg0[g.nblk]);
+  // float64 between 512 and 768 threads: the 768-thread build (no spills)
+  constexpr int MID = std::is_same<T, double>::value ? 768 : 1024;
   if (threads <= 512)
     hipLaunchKernelGGL((exec_fft_multi_kernel<T, T, false, 512>), grid, dim3(threads), lds, s,
+                       descs, g, X, Z, (uint32_t*)nullptr, (int64_t)0, R, N);
+  else if (threads <= MID)
+    hipLaunchKernelGGL((exec_fft_multi_kernel<T, T, false, MID>), grid, dim3(threads), lds, s,
                        descs, g, X, Z, (uint32_t*)nullptr, (int64_t)0, R, N);
   else
     hipLaunchKernelGGL((exec_fft_multi_kernel<T, T, false, 1024>), grid, dim3(threads), lds, s,
@@ -890,12 +899,18 @@ void launch_exec_fft_multi_x32(const FftDesc<double>* descs, const FftGrid& g, i
     if (threads <= 512)
       hipLaunchKernelGGL((exec_fft_multi_kernel<double, float, true, 512>), grid, dim3(threads),
                          lds, s, descs, g, X, (float2*)nullptr, Zs, zplane, R, N);
+    else if (threads <= 768)
+      hipLaunchKernelGGL((exec_fft_multi_kernel<double, float, true, 768>), grid, dim3(threads),
+                         lds, s, descs, g, X, (float2*)nullptr, Zs, zplane, R, N);
     else
       hipLaunchKernelGGL((exec_fft_multi_kernel<double, float, true, 1024>), grid, dim3(threads),
                          lds, s, descs, g, X, (float2*)nullptr, Zs, zplane, R, N);
   } else {
     if (threads <= 512)
       hipLaunchKernelGGL((exec_fft_multi_kernel<double, float, false, 512>), grid, dim3(threads),
+                         lds, s, descs, g, X, Z, (uint32_t*)nullptr, (int64_t)0, R, N);
+    else if (threads <= 768)
+      hipLaunchKernelGGL((exec_fft_multi_kernel<double, float, false, 768>), grid, dim3(threads),
                          lds, s, descs, g, X, Z, (uint32_t*)nullptr, (int64_t)0, R, N);
     else
       hipLaunchKernelGGL((exec_fft_multi_kernel<double, float, false, 1024>), grid,
