@@ -514,7 +514,9 @@ int64_t build_block(spt_plan_t plan, DevBlock& B, hipStream_t s, size_t lds_max,
   // rows whose transform does not fit one workgroup's LDS go by four steps:
   // float64 points of the precomputation's row transforms and of the inverse
   // transforms (P * 16 bytes), and the fused execute FFT's points of a
-  // transform or of a parity half with its two twiddle tables
+  // transform or of a parity half with its two twiddle tables.  The forward
+  // FFT of a four-step block stays fused while its split parts fit
+  // (P <= FUSED_FWD_MAX_P).
   const int split = fused_split(plan, P, lds_max);
   const bool fits = fused_lds_bytes<double>(fused_points(P, split), 128 + P / 128 + 1) <= lds_max;
   const bool big = P > FUSED_MAX_P || (size_t)P * sizeof(double2) > lds_max || !fits;

@@ -1,6 +1,7 @@
 // Device building blocks of the FFTs (shared by the FFT kernels and the
-// persistent executor): complex helpers, in-register DFTs of radix 2, 3, 4, 5
-// and 8, a batched LDS Stockham radix pass, and the unpacking of a packed real
+// persistent executor): complex helpers, in-register DFTs of radix 2, 3, 4, 5,
+// 8 and 10, a batched LDS Stockham radix pass, two leading radix-8 passes
+// joined by an exchange of lane shuffles, and the unpacking of a packed real
 // transform into its half spectrum.
 //
 // Conventions: F of eq. (1) has the kernel exp(-2 pi i jk/L)/sqrt(L) (SIGN -1,
