@@ -365,10 +365,12 @@ spt_status spt_plan_get_tuning(spt_plan_t plan, spt_tuning* t);
 
 /* Autotuner: time spt_execute of nrhs right-hand sides (x ~ N(0,1), a fixed
  * seed) in precision prec on `stream` with HIP events for every launch choice
- * that applies to the plan (split-bf16: the three products and both window
+ * that applies to the plan (split-bf16: the four products and both window
  * widths; every precision: FFT batching 1, 2, 4 and, where a block qualifies,
- * the parity split on and off), median of 10 executes each after 2 warm-up
- * executes, and keep the fastest (spt_plan_set_tuning).  cache_path (may be
+ * the parity split on and off and the eight-way split): two sweeps over the
+ * choices, each the median of 20 executes after 3 warm-up executes, the
+ * smaller of a choice's two medians kept, and keep the fastest
+ * (spt_plan_set_tuning).  cache_path (may be
  * NULL): a JSON file of earlier results keyed by family, Jacobi parameters,
  * ceil(log2 N), ceil(log2 nrhs) and precision; a key found there is applied
  * without timing, a new result is added to the file.  *chosen (may be NULL)
