@@ -232,7 +232,7 @@ def generators_workload(args, spt, workloads):
         p = spt.Plan(fam, N, 1e-7, **kw).precompute()
         torch.cuda.synchronize()
         res = {"N": N, "precompute_s": time.perf_counter() - t0, "blocks": [b[0] for b in p.blocks()],
-               "nnz": p.info()["nnz"], "paths": {}}
+               "nnz": p.info()["nnz"], "stored": p.info()["stored"], "paths": {}}
         if fam == "chebyshev_t":
             t0 = time.perf_counter()
             q = spt.Plan(fam, N, 1e-7).precompute()

@@ -183,6 +183,7 @@ struct CplxState {
   std::vector<double> angles;  // row angles theta_j (SPT_CEXP) or phases phi_j
   int64_t nnz = 0, stored = 0;
   int max_band = 0;
+  int max_kw = 0;  // widest tile box (columns)
   double maxabs = 0.0, kappa = 0.0;
 };
 
@@ -2023,6 +2024,7 @@ void precompute_complex(spt_plan_t plan, hipStream_t s) {
     cx->pad = std::max<int>(cx->pad, (int)std::max<int64_t>(0, b0 + kw - L));
     meta[t] = TileMeta{(int)b0, (int)kw, off};
     off += kw * TILE_ROWS;
+    cx->max_kw = std::max<int>(cx->max_kw, (int)kw);
   }
   cx->stored = off;
   std::vector<double2> v64((size_t)std::max<int64_t>(off, 1), double2{0.0, 0.0});
@@ -2072,7 +2074,7 @@ void execute_complex(spt_plan_t plan, const void* X, void* Y, int64_t R, hipStre
   CplxSpmmArgs<T> pa{cx.meta.as<TileMeta>(),
                      std::is_same<T, double>::value ? (const C*)cx.val64.p : (const C*)cx.val32.p,
                      plan->work->as<C>(), static_cast<C*>(Y), plan->N, (int)R, ldz};
-  staged(SPT_STAGE_SPMM, s, [&] { launch_cplx_spmm<T>(pa, plan->n_tiles, s); });
+  staged(SPT_STAGE_SPMM, s, [&] { launch_cplx_spmm<T>(pa, plan->n_tiles, cx.max_kw, s); });
 }
 
 template <typename T>

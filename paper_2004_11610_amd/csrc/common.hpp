@@ -498,7 +498,7 @@ struct CplxSpmmArgs {
   int R, ldz;
 };
 template <typename T>
-void launch_cplx_spmm(const CplxSpmmArgs<T>& a, int n_tiles, hipStream_t s);
+void launch_cplx_spmm(const CplxSpmmArgs<T>& a, int n_tiles, int max_kw, hipStream_t s);
 template <typename T>
 struct CplxSpmmTArgs {
   const TileMeta* meta;

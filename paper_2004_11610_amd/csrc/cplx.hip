@@ -94,26 +94,67 @@ __global__ __launch_bounds__(1024) void cplx_exec_fft_kernel(CplxExecArgs<TI> a,
 }
 
 // y[r][n] = sum over the tile box of A[n][k] z[r][k]: workgroup = tile x 16
-// right-hand sides, thread = (row q, right-hand side)
-template <typename T>
-__global__ __launch_bounds__(256) void cplx_spmm_kernel(CplxSpmmArgs<T> a) {
+// right-hand sides x KQ parts of the box's columns, thread = (row q,
+// right-hand side, part).  The parts' sums meet in LDS and are added in a
+// fixed order.  The widest boxes (the low frequencies of the Laguerre
+// spectral matrix, near a thousand columns) set the launch's length: a
+// thread's columns are a chain of memory round trips, so plans with wide
+// boxes take KQ = 4, the others 1.
+template <typename T, int KQ>
+__global__ __launch_bounds__(256 * KQ) void cplx_spmm_kernel(CplxSpmmArgs<T> a) {
   using C = cplx_t<T>;
+  __shared__ double2 part[KQ > 1 ? KQ - 1 : 1][256];
   const int tile = blockIdx.x;
-  const int q = threadIdx.x & 15, rl = threadIdx.x >> 4;
+  const int t = threadIdx.x & 255, ks = threadIdx.x >> 8;
+  const int q = t & 15, rl = t >> 4;
   const int r = blockIdx.y * 16 + rl;
   const int64_t n = (int64_t)tile * TILE_ROWS + q;
-  if (r >= a.R || n >= a.N) return;
+  const bool live = r < a.R && n < a.N;
   const TileMeta tm = a.meta[tile];
-  const C* __restrict__ val = a.val + tm.off + q;
-  const C* __restrict__ z = a.Z + (int64_t)r * a.ldz + tm.k0;
-  double2 acc = double2{0.0, 0.0};
-  for (int kk = 0; kk < tm.kw; ++kk) {
-    const C av = val[(int64_t)kk * TILE_ROWS];
-    const C zv = z[kk];
-    acc.x += (double)av.x * zv.x - (double)av.y * zv.y;
-    acc.y += (double)av.x * zv.y + (double)av.y * zv.x;
+  const int kq = (tm.kw + KQ - 1) / KQ;
+  const int k1 = min(tm.kw, (ks + 1) * kq);
+  // eight columns per step, their loads issued together, into four partial
+  // sums added in a fixed order
+  constexpr int U = 8;
+  double2 acc[4] = {};
+  if (live) {
+    const C* __restrict__ val = a.val + tm.off + q;
+    const C* __restrict__ z = a.Z + (int64_t)r * a.ldz + tm.k0;
+    int kk = ks * kq;
+    for (; kk + U <= k1; kk += U) {
+      C av[U], zv[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        av[u] = val[(int64_t)(kk + u) * TILE_ROWS];
+        zv[u] = z[kk + u];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        acc[u & 3].x += (double)av[u].x * zv[u].x - (double)av[u].y * zv[u].y;
+        acc[u & 3].y += (double)av[u].x * zv[u].y + (double)av[u].y * zv[u].x;
+      }
+    }
+    for (; kk < k1; ++kk) {
+      const C av = val[(int64_t)kk * TILE_ROWS];
+      const C zv = z[kk];
+      acc[0].x += (double)av.x * zv.x - (double)av.y * zv.y;
+      acc[0].y += (double)av.x * zv.y + (double)av.y * zv.x;
+    }
   }
-  a.Y[(int64_t)r * a.N + n] = C{(T)acc.x, (T)acc.y};
+  double2 sum = double2{(acc[0].x + acc[1].x) + (acc[2].x + acc[3].x),
+                        (acc[0].y + acc[1].y) + (acc[2].y + acc[3].y)};
+  if (KQ > 1) {
+    if (ks > 0) part[ks - 1][t] = sum;
+    __syncthreads();
+  }
+  if (ks == 0 && live) {
+#pragma unroll
+    for (int i = 0; i < KQ - 1; ++i) {
+      sum.x += part[i][t].x;
+      sum.y += part[i][t].y;
+    }
+    a.Y[(int64_t)r * a.N + n] = C{(T)sum.x, (T)sum.y};
+  }
 }
 
 // u[r][k'] = sum_n A[n][k'] f[r][n] for the columns k' < L + pad of the tile
@@ -128,7 +169,9 @@ __global__ __launch_bounds__(256) void cplx_spmm_t_kernel(CplxSpmmTArgs<T> a) {
   const int k = c * 32 + col;
   if (r >= a.R || k >= a.ldu) return;
   const C* __restrict__ f = a.F + (int64_t)r * a.N;
-  double2 acc = double2{0.0, 0.0};
+  // a tile's 16 rows in two groups of eight, each group's loads issued
+  // together, into four partial sums added in a fixed order at the end
+  double2 acc[4] = {};
   for (int e = a.tptr[c]; e < a.tptr[c + 1]; ++e) {
     const int tile = a.tents[e];
     const TileMeta tm = a.meta[tile];
@@ -136,15 +179,33 @@ __global__ __launch_bounds__(256) void cplx_spmm_t_kernel(CplxSpmmTArgs<T> a) {
     if (kk < 0 || kk >= tm.kw) continue;
     const C* __restrict__ val = a.val + tm.off + (int64_t)kk * TILE_ROWS;
     const int64_t n0 = (int64_t)tile * TILE_ROWS;
-    for (int q = 0; q < TILE_ROWS; ++q) {
-      if (n0 + q >= a.N) break;
-      const C av = val[q];
-      const C fv = f[n0 + q];
-      acc.x += (double)av.x * fv.x - (double)av.y * fv.y;
-      acc.y += (double)av.x * fv.y + (double)av.y * fv.x;
+    if (n0 + TILE_ROWS <= a.N) {
+#pragma unroll
+      for (int h = 0; h < TILE_ROWS; h += 8) {
+        C av[8], fv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          av[u] = val[h + u];
+          fv[u] = f[n0 + h + u];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          acc[u & 3].x += (double)av[u].x * fv[u].x - (double)av[u].y * fv[u].y;
+          acc[u & 3].y += (double)av[u].x * fv[u].y + (double)av[u].y * fv[u].x;
+        }
+      }
+    } else {
+      for (int q = 0; q < TILE_ROWS && n0 + q < a.N; ++q) {
+        const C av = val[q];
+        const C fv = f[n0 + q];
+        acc[0].x += (double)av.x * fv.x - (double)av.y * fv.y;
+        acc[0].y += (double)av.x * fv.y + (double)av.y * fv.x;
+      }
     }
   }
-  a.U[(int64_t)r * a.ldu + k] = C{(T)acc.x, (T)acc.y};
+  const double sx = (acc[0].x + acc[1].x) + (acc[2].x + acc[3].x);
+  const double sy = (acc[0].y + acc[1].y) + (acc[2].y + acc[3].y);
+  a.U[(int64_t)r * a.ldu + k] = C{(T)sx, (T)sy};
 }
 
 // y_m = (F* u)_c / w_c on the retained columns, m = c + m_off; u[k] takes the
@@ -210,8 +271,12 @@ void launch_cplx_exec_fft(const CplxExecArgs<TI>& a, const FftPlan& fp, int R, h
 }
 
 template <typename T>
-void launch_cplx_spmm(const CplxSpmmArgs<T>& a, int n_tiles, hipStream_t s) {
-  hipLaunchKernelGGL(cplx_spmm_kernel<T>, dim3(n_tiles, (a.R + 15) / 16), dim3(256), 0, s, a);
+void launch_cplx_spmm(const CplxSpmmArgs<T>& a, int n_tiles, int max_kw, hipStream_t s) {
+  const dim3 grid(n_tiles, (a.R + 15) / 16);
+  if (max_kw > 128)
+    hipLaunchKernelGGL((cplx_spmm_kernel<T, 4>), grid, dim3(1024), 0, s, a);
+  else
+    hipLaunchKernelGGL((cplx_spmm_kernel<T, 1>), grid, dim3(256), 0, s, a);
   SPT_HIP(hipGetLastError());
 }
 
@@ -233,8 +298,8 @@ template void launch_cplx_exec_fft<double>(const CplxExecArgs<double>&, const Ff
                                            hipStream_t);
 template void launch_cplx_exec_fft<float>(const CplxExecArgs<float>&, const FftPlan&, int,
                                           hipStream_t);
-template void launch_cplx_spmm<double>(const CplxSpmmArgs<double>&, int, hipStream_t);
-template void launch_cplx_spmm<float>(const CplxSpmmArgs<float>&, int, hipStream_t);
+template void launch_cplx_spmm<double>(const CplxSpmmArgs<double>&, int, int, hipStream_t);
+template void launch_cplx_spmm<float>(const CplxSpmmArgs<float>&, int, int, hipStream_t);
 template void launch_cplx_spmm_t<double>(const CplxSpmmTArgs<double>&, int, hipStream_t);
 template void launch_cplx_spmm_t<float>(const CplxSpmmTArgs<float>&, int, hipStream_t);
 template void launch_cplx_inv_fft<double>(const CplxInvArgs<double>&, const FftPlan&, int,
