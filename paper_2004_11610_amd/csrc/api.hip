@@ -183,7 +183,8 @@ struct CplxState {
   std::vector<double> angles;  // row angles theta_j (SPT_CEXP) or phases phi_j
   int64_t nnz = 0, stored = 0;
   int max_band = 0;
-  int max_kw = 0;  // widest tile box (columns)
+  int max_kw = 0;    // widest tile box (columns)
+  int max_list = 0;  // longest tile list of a transposed chunk
   double maxabs = 0.0, kappa = 0.0;
 };
 
@@ -2054,6 +2055,7 @@ void precompute_complex(spt_plan_t plan, hipStream_t s) {
     for (int t = 0; t < nt; ++t)
       if (kws[t] > 0 && k0s[t] < 32 * (c + 1) && k0s[t] + kws[t] > 32 * c) tents.push_back(t);
     tptr[c + 1] = (int32_t)tents.size();
+    cx->max_list = std::max(cx->max_list, tptr[c + 1] - tptr[c]);
   }
   if (tents.empty()) tents.push_back(0);
   upload(cx->tptr, tptr, s);
@@ -2088,7 +2090,7 @@ void execute_complex_transposed(spt_plan_t plan, const void* F, void* Y, int64_t
                       std::is_same<T, double>::value ? (const C*)cx.val64.p : (const C*)cx.val32.p,
                       cx.tptr.as<int32_t>(), cx.tents.as<int32_t>(), static_cast<const C*>(F),
                       plan->work->as<C>(), plan->N, (int)R, ldu};
-  staged(SPT_STAGE_SPMM_T, s, [&] { launch_cplx_spmm_t<T>(ta, cx.n_chunks, s); });
+  staged(SPT_STAGE_SPMM_T, s, [&] { launch_cplx_spmm_t<T>(ta, cx.n_chunks, cx.max_list, s); });
   CplxInvArgs<T> ia{plan->work->as<C>(), static_cast<C*>(Y), cx.winv.as<double>(),
                     cx.tw.as<double2>(), plan->N, cx.L, ldu, cx.m_off, cx.c_lo, cx.c_hi,
                     1.0 / std::sqrt((double)cx.L)};

@@ -511,7 +511,7 @@ struct CplxSpmmTArgs {
   int R, ldu;
 };
 template <typename T>
-void launch_cplx_spmm_t(const CplxSpmmTArgs<T>& a, int n_chunks, hipStream_t s);
+void launch_cplx_spmm_t(const CplxSpmmTArgs<T>& a, int n_chunks, int max_list, hipStream_t s);
 template <typename TI>
 struct CplxInvArgs {
   const cplx_t<TI>* U;

@@ -158,54 +158,76 @@ __global__ __launch_bounds__(256 * KQ) void cplx_spmm_kernel(CplxSpmmArgs<T> a) 
 }
 
 // u[r][k'] = sum_n A[n][k'] f[r][n] for the columns k' < L + pad of the tile
-// boxes: workgroup = 32 columns x 8 right-hand sides, over the tiles whose
-// boxes meet the 32 columns (list ents[tptr[c] .. tptr[c + 1]))
-template <typename T>
-__global__ __launch_bounds__(256) void cplx_spmm_t_kernel(CplxSpmmTArgs<T> a) {
+// boxes: workgroup = 32 columns x 8 right-hand sides x KQ parts of the tile
+// list, over the tiles whose boxes meet the 32 columns (list ents[tptr[c] ..
+// tptr[c + 1])).  Where many rows' tones share a few columns (the high
+// frequencies of the Laguerre spectral matrix) the lists run to hundreds of
+// tiles, a chain per thread: plans with such lists take KQ = 4 parts, whose
+// sums meet in LDS and are added in a fixed order.
+template <typename T, int KQ>
+__global__ __launch_bounds__(256 * KQ) void cplx_spmm_t_kernel(CplxSpmmTArgs<T> a) {
   using C = cplx_t<T>;
+  __shared__ double2 part[KQ > 1 ? KQ - 1 : 1][256];
   const int c = blockIdx.x;
-  const int col = threadIdx.x & 31, rl = threadIdx.x >> 5;
+  const int t = threadIdx.x & 255, ks = threadIdx.x >> 8;
+  const int col = t & 31, rl = t >> 5;
   const int r = blockIdx.y * 8 + rl;
   const int k = c * 32 + col;
-  if (r >= a.R || k >= a.ldu) return;
-  const C* __restrict__ f = a.F + (int64_t)r * a.N;
+  const bool live = r < a.R && k < a.ldu;
   // a tile's 16 rows in two groups of eight, each group's loads issued
   // together, into four partial sums added in a fixed order at the end
   double2 acc[4] = {};
-  for (int e = a.tptr[c]; e < a.tptr[c + 1]; ++e) {
-    const int tile = a.tents[e];
-    const TileMeta tm = a.meta[tile];
-    const int kk = k - tm.k0;
-    if (kk < 0 || kk >= tm.kw) continue;
-    const C* __restrict__ val = a.val + tm.off + (int64_t)kk * TILE_ROWS;
-    const int64_t n0 = (int64_t)tile * TILE_ROWS;
-    if (n0 + TILE_ROWS <= a.N) {
+  if (live) {
+    const C* __restrict__ f = a.F + (int64_t)r * a.N;
+    const int e0 = a.tptr[c], n_e = a.tptr[c + 1] - e0;
+    const int per = (n_e + KQ - 1) / KQ;
+    const int e1 = e0 + min(n_e, (ks + 1) * per);
+    for (int e = e0 + ks * per; e < e1; ++e) {
+      const int tile = a.tents[e];
+      const TileMeta tm = a.meta[tile];
+      const int kk = k - tm.k0;
+      if (kk < 0 || kk >= tm.kw) continue;
+      const C* __restrict__ val = a.val + tm.off + (int64_t)kk * TILE_ROWS;
+      const int64_t n0 = (int64_t)tile * TILE_ROWS;
+      if (n0 + TILE_ROWS <= a.N) {
 #pragma unroll
-      for (int h = 0; h < TILE_ROWS; h += 8) {
-        C av[8], fv[8];
+        for (int h = 0; h < TILE_ROWS; h += 8) {
+          C av[8], fv[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          av[u] = val[h + u];
-          fv[u] = f[n0 + h + u];
+          for (int u = 0; u < 8; ++u) {
+            av[u] = val[h + u];
+            fv[u] = f[n0 + h + u];
+          }
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            acc[u & 3].x += (double)av[u].x * fv[u].x - (double)av[u].y * fv[u].y;
+            acc[u & 3].y += (double)av[u].x * fv[u].y + (double)av[u].y * fv[u].x;
+          }
         }
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          acc[u & 3].x += (double)av[u].x * fv[u].x - (double)av[u].y * fv[u].y;
-          acc[u & 3].y += (double)av[u].x * fv[u].y + (double)av[u].y * fv[u].x;
+      } else {
+        for (int q = 0; q < TILE_ROWS && n0 + q < a.N; ++q) {
+          const C av = val[q];
+          const C fv = f[n0 + q];
+          acc[0].x += (double)av.x * fv.x - (double)av.y * fv.y;
+          acc[0].y += (double)av.x * fv.y + (double)av.y * fv.x;
         }
-      }
-    } else {
-      for (int q = 0; q < TILE_ROWS && n0 + q < a.N; ++q) {
-        const C av = val[q];
-        const C fv = f[n0 + q];
-        acc[0].x += (double)av.x * fv.x - (double)av.y * fv.y;
-        acc[0].y += (double)av.x * fv.y + (double)av.y * fv.x;
       }
     }
   }
-  const double sx = (acc[0].x + acc[1].x) + (acc[2].x + acc[3].x);
-  const double sy = (acc[0].y + acc[1].y) + (acc[2].y + acc[3].y);
-  a.U[(int64_t)r * a.ldu + k] = C{(T)sx, (T)sy};
+  double2 sum = double2{(acc[0].x + acc[1].x) + (acc[2].x + acc[3].x),
+                        (acc[0].y + acc[1].y) + (acc[2].y + acc[3].y)};
+  if (KQ > 1) {
+    if (ks > 0) part[ks - 1][t] = sum;
+    __syncthreads();
+  }
+  if (ks == 0 && live) {
+#pragma unroll
+    for (int i = 0; i < KQ - 1; ++i) {
+      sum.x += part[i][t].x;
+      sum.y += part[i][t].y;
+    }
+    a.U[(int64_t)r * a.ldu + k] = C{(T)sum.x, (T)sum.y};
+  }
 }
 
 // y_m = (F* u)_c / w_c on the retained columns, m = c + m_off; u[k] takes the
@@ -281,8 +303,12 @@ void launch_cplx_spmm(const CplxSpmmArgs<T>& a, int n_tiles, int max_kw, hipStre
 }
 
 template <typename T>
-void launch_cplx_spmm_t(const CplxSpmmTArgs<T>& a, int n_chunks, hipStream_t s) {
-  hipLaunchKernelGGL(cplx_spmm_t_kernel<T>, dim3(n_chunks, (a.R + 7) / 8), dim3(256), 0, s, a);
+void launch_cplx_spmm_t(const CplxSpmmTArgs<T>& a, int n_chunks, int max_list, hipStream_t s) {
+  const dim3 grid(n_chunks, (a.R + 7) / 8);
+  if (max_list > 32)
+    hipLaunchKernelGGL((cplx_spmm_t_kernel<T, 4>), grid, dim3(1024), 0, s, a);
+  else
+    hipLaunchKernelGGL((cplx_spmm_t_kernel<T, 1>), grid, dim3(256), 0, s, a);
   SPT_HIP(hipGetLastError());
 }
 
@@ -300,8 +326,8 @@ template void launch_cplx_exec_fft<float>(const CplxExecArgs<float>&, const FftP
                                           hipStream_t);
 template void launch_cplx_spmm<double>(const CplxSpmmArgs<double>&, int, int, hipStream_t);
 template void launch_cplx_spmm<float>(const CplxSpmmArgs<float>&, int, int, hipStream_t);
-template void launch_cplx_spmm_t<double>(const CplxSpmmTArgs<double>&, int, hipStream_t);
-template void launch_cplx_spmm_t<float>(const CplxSpmmTArgs<float>&, int, hipStream_t);
+template void launch_cplx_spmm_t<double>(const CplxSpmmTArgs<double>&, int, int, hipStream_t);
+template void launch_cplx_spmm_t<float>(const CplxSpmmTArgs<float>&, int, int, hipStream_t);
 template void launch_cplx_inv_fft<double>(const CplxInvArgs<double>&, const FftPlan&, int,
                                           hipStream_t);
 template void launch_cplx_inv_fft<float>(const CplxInvArgs<float>&, const FftPlan&, int,
