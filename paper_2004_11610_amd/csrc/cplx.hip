@@ -182,9 +182,18 @@ __global__ __launch_bounds__(256 * KQ) void cplx_spmm_t_kernel(CplxSpmmTArgs<T> 
     const int e0 = a.tptr[c], n_e = a.tptr[c + 1] - e0;
     const int per = (n_e + KQ - 1) / KQ;
     const int e1 = e0 + min(n_e, (ks + 1) * per);
-    for (int e = e0 + ks * per; e < e1; ++e) {
-      const int tile = a.tents[e];
-      const TileMeta tm = a.meta[tile];
+    int e = e0 + ks * per;
+    // the list is read ahead (the tile two entries on, the box of the next),
+    // so that an entry waits for one memory round trip instead of three
+    int tile_a = e < e1 ? a.tents[e] : 0;          // entry e
+    int tile_b = e + 1 < e1 ? a.tents[e + 1] : 0;  // entry e + 1
+    TileMeta meta_a = e < e1 ? a.meta[tile_a] : TileMeta{};
+    for (; e < e1; ++e) {
+      const int tile = tile_a;
+      const TileMeta tm = meta_a;
+      if (e + 1 < e1) meta_a = a.meta[tile_b];
+      tile_a = tile_b;
+      if (e + 2 < e1) tile_b = a.tents[e + 2];
       const int kk = k - tm.k0;
       if (kk < 0 || kk >= tm.kw) continue;
       const C* __restrict__ val = a.val + tm.off + (int64_t)kk * TILE_ROWS;
