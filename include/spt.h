@@ -301,8 +301,9 @@ spt_status spt_execute(spt_plan_t plan, const void* X, void* Y, int64_t nrhs, in
  * calls (each call writes all it reads).  SPT_E_INVALID_ARG when the workspace
  * of nrhs right-hand sides (complex float64 half spectra of every block, or the
  * split-bf16 pieces) exceeds the array; SPT_E_UNSUPPORTED for plans with the
- * persistent executor or with a block whose FFT exceeds one workgroup (half
- * length above 10240). */
+ * persistent executor or with a block whose forward FFT does not run fused
+ * (half length above 16384, or above 10240 and odd: such blocks go by work
+ * lists). */
 #define SPT_NOALLOC_MAX_BYTES (32u << 20)
 spt_status spt_execute_noalloc(spt_plan_t plan, const void* X, void* Y, int64_t nrhs, int32_t prec,
                                void* stream);
