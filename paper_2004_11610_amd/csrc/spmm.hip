@@ -276,6 +276,10 @@ __global__ __launch_bounds__(256 * WS) void spmm_window_kernel(SpmmSplitArgs arg
                                                                int n_groups, int xlds, int tpad) {
   extern __shared__ __align__(16) uint4 zl[];
   const int grp = xcd_tile(blockIdx.x, n_groups);
+  // the metadata, window and matrix loads at raised wave priority, so that
+  // beside other streams' FFT workgroups (long runs of vector work) they are
+  // issued first; back to normal for the matrix-core steps
+  __builtin_amdgcn_s_setprio(3);
   constexpr int NR = 16 * RG * WS;  // right-hand sides of the workgroup
   constexpr int NW = WIN_TILES * WS;  // waves
   const int r0 = blockIdx.y * NR;
@@ -395,6 +399,7 @@ __global__ __launch_bounds__(256 * WS) void spmm_window_kernel(SpmmSplitArgs arg
   if (tsteps > 0) load_tail(0);
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
+  __builtin_amdgcn_s_setprio(0);
   if (!has_tile) return;
 
   // 3. every block's steps: matrix pieces from memory, spectra from LDS
