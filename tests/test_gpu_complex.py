@@ -19,6 +19,7 @@ pytestmark = pytest.mark.gpu
 
 CASES = [("cexp", 256, 1e-12, {}), ("cexp", 1000, 1e-10, {}), ("cexp", 3000, 1e-7, {}),
          ("laguerre_spectral", 501, 1e-10, dict(eta=2500.0, period=4.0)),
+         ("laguerre_spectral", 1200, 1e-7, dict(eta=100.0, period=4.0)),
          ("laguerre_spectral", 2048, 1e-7, dict(eta=100.0, period=4.0)),
          ("laguerre_spectral", 40, 1e-12, dict(eta=1.0, period=30.0))]
 FAM = {"cexp": matrix.CEXP, "laguerre_spectral": matrix.LAGUERRE_SPECTRAL}
