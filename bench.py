@@ -7,8 +7,10 @@ eps2 = 1e-2, float64 precomputation.  One step = one spt_execute of all 64
 right-hand sides (extend + window + FFT of every block, banded product of every
 block and the direct tail): two launches, the FFTs of every block, then the
 banded products.  The timed steps are dealt in turn to --streams streams
-(default 4), each with its own output buffer, so that independent batches
-are in flight together as in serving; the one-stream rate (each step after the
+(default 3; four measured the same for the split path and about 10% slower
+for float64, with the runtime's four hardware queues per process), each with
+its own output buffer, so that independent batches are in flight together as
+in serving; the one-stream rate (each step after the
 previous one) is reported beside it.  The headline value is the split-bf16 path (float32 FFT,
 three-piece bfloat16 matrix-core product accumulated in float32); the float64
 and float32 paths are timed beside it on the same plan, the split path's error
@@ -284,7 +286,7 @@ def main():
     ap.add_argument("--no-cpu-compressed", action="store_true",
                     help="skip the oracle's compressed method in the CPU baseline (its "
                          "precomputation takes about a minute)")
-    ap.add_argument("--streams", type=int, default=4,
+    ap.add_argument("--streams", type=int, default=3,
                     help="streams the timed steps are dealt to in turn (independent "
                          "batches in flight at once; 1 = strictly one after another)")
     ap.add_argument("--workload", default="legendre-n16384-r64",
